@@ -1,0 +1,425 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: exact
+polynomial moments, closed forms, brute-force integration, the mirror-doubled
+domain of the paper's own validation (Section "Results", Test-1), the direct
+LU solve and the monotonicity Proposition.  No GPU is used.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import quadrature, solve
+from oracle.core import Grid, Problem
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# ---------------------------------------------------------------- quadrature (Section 2, M_q = 14 / 4)
+
+@pytest.mark.parametrize("degree,npts", [(2, 4), (5, 14)])
+def test_tet_rule_integrates_cartesian_monomials(degree, npts):
+    p, w = quadrature.tet_rule(degree)
+    assert len(w) == npts and np.all(w > 0) and np.all(p > 0)
+    xyz = p[:, 1:]                       # reference tet with vertices 0, e1, e2, e3
+    worst_exact, fails_above = 0.0, False
+    for a, b, c in itertools.product(range(degree + 2), repeat=3):
+        if a + b + c > degree + 1:
+            continue
+        exact = math.factorial(a) * math.factorial(b) * math.factorial(c) / math.factorial(a + b + c + 3)
+        val = np.sum(w * xyz[:, 0] ** a * xyz[:, 1] ** b * xyz[:, 2] ** c) / 6.0
+        if a + b + c <= degree:
+            worst_exact = max(worst_exact, abs(val - exact) / exact)
+        elif abs(val - exact) > 1e-9 * exact:
+            fails_above = True
+    assert worst_exact < 1e-13
+    assert fails_above, "rule should not be exact one degree higher"
+
+
+@pytest.mark.parametrize("degree,npts", [(2, 3), (5, 7)])
+def test_triangle_rule_integrates_cartesian_monomials(degree, npts):
+    p, w = quadrature.tri_rule(degree)
+    assert len(w) == npts and np.all(w > 0) and np.all(p > 0)
+    xy = p[:, 1:]
+    for a, b in itertools.product(range(degree + 1), repeat=2):
+        if a + b > degree:
+            continue
+        exact = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+        val = np.sum(w * xy[:, 0] ** a * xy[:, 1] ** b) / 2.0
+        assert abs(val - exact) < 5e-14 * exact
+
+
+# ---------------------------------------------------------------- P1 kappa on the Kuhn grid
+
+def _grid_problem(n, lo=(0, 0, 0), hi=(1, 1, 1), kappa=None, **kw):
+    g = Grid(tuple(n), tuple(float(v) for v in lo), tuple(float(v) for v in hi))
+    if kappa is None:
+        kappa = np.ones(g.N)
+    elif callable(kappa):
+        kappa = kappa(g.positions())
+    return Problem(g, kappa, **kw)
+
+
+def test_p1_kappa_reproduces_linear_fields():
+    rng = np.random.default_rng(0)
+    c0, c = 0.7, np.array([0.3, -0.2, 0.45])
+    P = _grid_problem((6, 5, 7), hi=(2, 1, 1.5), kappa=lambda X: c0 + X @ c)
+    x = rng.uniform([0, 0, 0], [2, 1, 1.5], size=(500, 3))
+    x[:10, 0] = 2.0                            # points on the box boundary
+    assert np.max(np.abs(P.kappa_at(x) - (c0 + x @ c))) < 1e-14
+
+
+def test_p1_kappa_is_continuous_and_interpolates():
+    rng = np.random.default_rng(1)
+    P = _grid_problem((5, 5, 5), kappa=lambda X: rng.uniform(0.1, 2.0, len(X)))
+    pos = P.grid.positions()
+    assert np.max(np.abs(P.kappa_at(pos) - P.kappa)) < 1e-15
+    # across a Kuhn diagonal plane (x = y inside a cell) the interpolant is continuous
+    base = rng.uniform(0.05, 0.95, size=(200, 3)) * 0.25
+    base[:, 1] = base[:, 0]
+    eps = np.array([1e-9, -1e-9, 0.0])
+    jump = P.kappa_at(base + eps) - P.kappa_at(base - eps)
+    assert np.max(np.abs(jump)) < 1e-7
+
+
+# ---------------------------------------------------------------- optical depth (eq. gen1)
+
+def test_tau_constant_and_linear_kappa():
+    rng = np.random.default_rng(2)
+    p = rng.uniform(0, 1, size=(300, 3))
+    q = rng.uniform(0, 1, size=(300, 3))
+    P = _grid_problem((9, 9, 9), kappa=np.full(729, 1.7))
+    L = np.linalg.norm(q - p, axis=1)
+    assert np.max(np.abs(P.tau(p, q) - 1.7 * L)) < 1e-13
+    c0, c = 0.5, np.array([0.2, 0.9, -0.3])
+    P = _grid_problem((9, 9, 9), kappa=lambda X: c0 + X @ c)
+    expect = L * (2 * c0 + (p + q) @ c) / 2
+    assert np.max(np.abs(P.tau(p, q) - expect)) < 1e-13
+
+
+def test_tau_matches_fine_sampling_of_p1_kappa():
+    rng = np.random.default_rng(3)
+    P = _grid_problem((7, 6, 5), hi=(1.2, 1, 0.8), kappa=lambda X: rng.uniform(0.0, 3.0, len(X)))
+    for _ in range(4):
+        p = rng.uniform(0, 1, 3) * [1.2, 1, 0.8]
+        q = rng.uniform(0, 1, 3) * [1.2, 1, 0.8]
+        m = 1 << 17
+        t = (np.arange(m) + 0.5) / m
+        pts = p[None, :] + t[:, None] * (q - p)[None, :]
+        ref = np.linalg.norm(q - p) * np.mean(P.kappa_at(pts))
+        assert abs(P.tau(p, q)[0] - ref) < 1e-8 * max(ref, 1.0)
+
+
+def _doubled(P: Problem):
+    """The mirror-doubled domain of a problem whose wall is the x = lo face."""
+    g = P.grid
+    n0 = g.n[0]
+    L = g.hi[0] - g.lo[0]
+    gd = Grid((2 * n0 - 1, g.n[1], g.n[2]), (g.lo[0] - L, g.lo[1], g.lo[2]), g.hi)
+    idx = gd.index(np.arange(gd.N))
+    src = idx.copy()
+    src[:, 0] = np.abs(idx[:, 0] - (n0 - 1))
+    emit = 0
+    for f in range(6):
+        if (P.emit_faces >> f) & 1:
+            assert f // 2 != 0, "the doubled check keeps emitting faces off the wall axis"
+            emit |= 1 << f
+    Pd = Problem(gd, P.kappa[g.vid(src)], emit_faces=emit, flip_axis=0, flip_cells=n0 - 1)
+    return Pd
+
+
+def test_mirror_tau_equals_straight_tau_in_doubled_domain():
+    rng = np.random.default_rng(4)
+    P = _grid_problem((6, 5, 5), kappa=lambda X: rng.uniform(0.1, 2.0, len(X)),
+                      wall_axis=0, wall_side=0, R=1.0, emit_faces=4)
+    Pd = _doubled(P)
+    x = rng.uniform(0, 1, size=(200, 3))
+    y = rng.uniform(0, 1, size=(200, 3))
+    ym = y * [-1, 1, 1]
+    tb = P.tau(x, y, mirrored=True)
+    td = Pd.tau(x, ym)
+    assert np.max(np.abs(tb - td)) < 1e-13 * np.max(td)
+    # and the mirrored kappa field reproduces the original on the mirrored half
+    assert np.max(np.abs(Pd.kappa_at(ym) - P.kappa_at(y))) < 1e-14
+
+
+def test_reflective_operator_equals_doubled_domain_for_R1():
+    """Section "Results": reflection on a plane is equivalent to extending the domain
+    by symmetry.  With R = 1 the reflective G and S equal the doubled-domain matrices
+    folded onto the original vertices, entry by entry."""
+    rng = np.random.default_rng(5)
+    P = _grid_problem((5, 4, 4), kappa=lambda X: rng.uniform(0.2, 1.5, len(X)),
+                      wall_axis=0, wall_side=0, R=1.0, emit_faces=4 | 32)
+    Pd = _doubled(P)
+    g, gd = P.grid, Pd.grid
+    n0 = g.n[0]
+    ids = np.arange(g.N)
+    idx = g.index(ids)
+    dir_ids = gd.vid(idx + [n0 - 1, 0, 0])
+    mir_ids = gd.vid(idx * [-1, 1, 1] + [n0 - 1, 0, 0])
+    GR = P.dense_G()
+    Gd = Pd.volume_block(dir_ids, np.concatenate([dir_ids, mir_ids]))
+    fold = Gd[:, :g.N] + np.where(idx[:, 0] > 0, 1.0, 0.0)[None, :] * Gd[:, g.N:]
+    assert np.max(np.abs(GR - fold)) < 1e-13 * np.max(np.abs(GR))
+    em = P.emitting
+    eidx = g.index(em)
+    SR = P.dense_S()
+    e_dir = gd.vid(eidx + [n0 - 1, 0, 0])
+    e_mir = gd.vid(eidx * [-1, 1, 1] + [n0 - 1, 0, 0])
+    Sd = Pd.surface_block(dir_ids, np.concatenate([e_dir, e_mir]))
+    foldS = Sd[:, :len(em)] + np.where(eidx[:, 0] > 0, 1.0, 0.0)[None, :] * Sd[:, len(em):]
+    assert np.max(np.abs(SR - foldS)) < 1e-13 * np.max(np.abs(SR))
+    # R = 0 is a different operator (the check has teeth)
+    P0 = _grid_problem((5, 4, 4), kappa=P.kappa, emit_faces=4 | 32)
+    assert np.max(np.abs(P0.dense_G() - fold)) > 1e-3 * np.max(np.abs(GR))
+
+
+def test_operator_is_affine_in_R():
+    rng = np.random.default_rng(6)
+    kap = rng.uniform(0.2, 1.5, 80)
+    mats = [_grid_problem((5, 4, 4), kappa=kap, wall_axis=2, wall_side=1, R=r, emit_faces=1).dense_G()
+            for r in (0.0, 0.5, 1.0)]
+    assert np.max(np.abs(mats[1] - 0.5 * (mats[0] + mats[2]))) < 1e-15 * 1e2
+
+
+# ---------------------------------------------------------------- volume entries vs brute force
+
+def _tets_around(g: Grid, j_idx):
+    out = []
+    for o in itertools.product((0, 1), repeat=3):
+        c = np.array(j_idx) - o
+        if np.any(c < 0) or np.any(c > np.array(g.n) - 2):
+            continue
+        for perm in itertools.permutations(range(3)):
+            v = [c.copy()]
+            for a in perm:
+                nxt = v[-1].copy()
+                nxt[a] += 1
+                v.append(nxt)
+            if any(np.array_equal(vv, j_idx) for vv in v):
+                out.append(np.array(v))
+    return out
+
+
+def _refine(tet):
+    """Split a tetrahedron (4x3) into 8 by its edge midpoints."""
+    a, b, c, d = tet
+    ab, ac, ad, bc, bd, cd = (a + b) / 2, (a + c) / 2, (a + d) / 2, (b + c) / 2, (b + d) / 2, (c + d) / 2
+    return [np.array(t) for t in ([a, ab, ac, ad], [ab, b, bc, bd], [ac, bc, c, cd], [ad, bd, cd, d],
+                                  [ab, ac, ad, bd], [ab, ac, bc, bd], [ac, ad, bd, cd], [ac, bc, bd, cd])]
+
+
+def _brute_g(P: Problem, i, j, levels=2):
+    """(1/4pi) int kappa(y) w^j(y) / |x_i - y|^2 dy by refined degree-5 quadrature,
+    barycentrics recomputed from the geometry."""
+    g = P.grid
+    h = np.array(g.h)
+    xi = g.positions()[i]
+    jidx = g.index(j)
+    bp, bw = quadrature.tet_rule(5)
+    total = 0.0
+    for tet_idx in _tets_around(g, jidx):
+        verts = np.asarray(g.lo) + tet_idx * h
+        kv = P.kappa[g.vid(tet_idx)]
+        loc = [k for k in range(4) if np.array_equal(tet_idx[k], jidx)][0]
+        Minv = np.linalg.inv((verts[1:] - verts[0]).T)
+        subs = [verts]
+        for _ in range(levels):
+            subs = [s for t in subs for s in _refine(t)]
+        for s in subs:
+            vol = abs(np.linalg.det(s[1:] - s[0])) / 6
+            y = bp @ s
+            lam123 = (Minv @ (y - verts[0]).T).T
+            lam = np.column_stack([1 - lam123.sum(1), lam123])
+            ky = lam @ kv
+            r2 = np.sum((xi - y) ** 2, axis=1)
+            total += vol * np.sum(bw * ky * lam[:, loc] / r2)
+    return total / (4 * np.pi)
+
+
+def test_volume_quadrature_matches_brute_force_far():
+    rng = np.random.default_rng(7)
+    P14 = _grid_problem((9, 8, 7), hi=(1, 0.9, 0.8), kappa=lambda X: rng.uniform(0.2, 2.0, len(X)),
+                        near_cheb=100)
+    P4 = Problem(P14.grid, P14.kappa, near_cheb=-1)
+    g = P14.grid
+    pairs = [((0, 0, 0), (5, 4, 4)), ((8, 7, 6), (3, 3, 2)), ((1, 7, 0), (6, 2, 5)), ((4, 0, 3), (4, 6, 3))]
+    for a, b in pairs:
+        i, j = int(g.vid(a)), int(g.vid(b))
+        ref = _brute_g(P14, i, j)
+        tau = P14.tau(g.positions()[i], g.positions()[j])[0]
+        e14 = P14.volume_pairs([i], [j])[0] * np.exp(tau)
+        e4 = P4.volume_pairs([i], [j])[0] * np.exp(tau)
+        assert abs(e14 - ref) < 2e-5 * ref, (a, b, e14, ref)
+        assert abs(e4 - ref) < 2e-2 * ref, (a, b, e4, ref)
+
+
+def _box_centre_closed_form(kappa, L=1.0, n=96):
+    """(1/4pi) int_{S^2} (1 - exp(-kappa rho)) dw at the centre of a cube of side L,
+    written as 1 - (1/4pi) sum over faces of int exp(-kappa r) d / r^3 dGamma."""
+    x, wq = np.polynomial.legendre.leggauss(n)
+    u = 0.5 * L * x
+    wu = 0.5 * L * wq
+    U, V = np.meshgrid(u, u, indexing="ij")
+    W = np.outer(wu, wu)
+    d = 0.5 * L
+    r = np.sqrt(U ** 2 + V ** 2 + d ** 2)
+    face = np.sum(W * np.exp(-kappa * r) * d / r ** 3)
+    return 1.0 - 6.0 * face / (4 * np.pi)
+
+
+def test_row_sum_converges_to_closed_form_at_box_centre():
+    """Lemma 1 with constant kappa: sum_j G^{ij} -> (1/4pi) int (1 - e^{-kappa rho}) dw,
+    at O(h) (the paper reports O(h) errors, Section "Results")."""
+    ref = _box_centre_closed_form(1.0)
+    errs = []
+    for n in (5, 9, 17):
+        P = _grid_problem((n, n, n))
+        c = int(P.grid.vid([n // 2] * 3))
+        errs.append(abs(P.volume_block([c], np.arange(P.grid.N)).sum() - ref) / ref)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.02
+    assert 1.5 < errs[1] / errs[2] < 3.0          # first order
+
+
+def test_closure_of_volume_plus_boundary_operators():
+    """Along any ray, absorbed plus transmitted fractions sum to one:
+    sum_j G^{ij} + sum_l S^{il} -> 1 when every face emits (variable kappa)."""
+    devs = []
+    for n in (5, 9, 17):
+        P = _grid_problem((n, n, n), kappa=lambda X: 0.5 + 0.4 * np.sin(2 * np.pi * X[:, 0])
+                          * np.cos(2 * np.pi * X[:, 1]) * X[:, 2], emit_faces=63)
+        i = int(P.grid.vid([n // 4, n // 2, (3 * n) // 4]))
+        tot = P.volume_block([i], np.arange(P.grid.N)).sum() + P.surface_block([i], P.emitting).sum()
+        devs.append(abs(1.0 - tot))
+    assert devs[0] > devs[1] > devs[2] and devs[2] < 0.02
+
+
+def _rect_solid_angle(x, y, z):
+    """Solid angle of [0,1]^2 in the plane X=0 seen from (x,y,z), x > 0: sum of the
+    four corner sub-rectangles, each arctan(ab / (d sqrt(a^2+b^2+d^2)))."""
+    d = x
+    tot = 0.0
+    for a, sa in ((y, 1), (1 - y, 1)):
+        for b in (z, 1 - z):
+            tot += sa * np.arctan(a * b / (d * np.sqrt(a * a + b * b + d * d)))
+    return tot
+
+
+def test_surface_source_kappa0_equals_solid_angle():
+    """kappa -> 0: S^E = Q Omega(x) / (4 pi) for an isotropic black wall (eq. SE1)."""
+    errs = []
+    for n in (5, 9, 17):
+        P = _grid_problem((n, n, n), kappa=np.zeros(n ** 3), emit_faces=1)
+        g = P.grid
+        pts = [(n // 2, n // 2, n // 2), (n - 1, 0, n // 4), (n // 4, n // 2, n - 1)]
+        ids = g.vid(np.array(pts))
+        SE = P.surface_block(ids, P.emitting).sum(axis=1)
+        ref = np.array([_rect_solid_angle(*g.positions()[i]) / (4 * np.pi) for i in ids])
+        errs.append(np.max(np.abs(SE - ref) / ref))
+    assert errs[2] < errs[0] and errs[2] < 5e-3
+    # a vertex inside the emitting face sees half the sphere
+    P = _grid_problem((5, 5, 5), kappa=np.zeros(125), emit_faces=1)
+    wall = int(P.grid.vid([0, 2, 2]))
+    assert abs(P.surface_block([wall], P.emitting).sum() - 0.5) < 1e-15
+
+
+# ---------------------------------------------------------------- Planck, bands, temperature
+
+def test_band_sum_of_planck_recovers_stefan_boltzmann():
+    """eq. grey: int_0^inf B_nu(T) dnu = sigma T^4 with sigma = pi^4/15."""
+    nu = np.linspace(1e-4, 60, 20001)
+    w = solve.band_weights(nu)
+    for T in (0.5, 1.0, 2.0):
+        assert abs(np.sum(w * solve.planck(nu, T)) - solve.SIGMA * T ** 4) < 1e-6 * solve.SIGMA * T ** 4
+
+
+def test_bisection_matches_single_band_closed_form():
+    nu = np.array([2.0])
+    J = np.array([[0.1, 1.0, 7.0, 40.0]])
+    T = solve.temperature_bisect(J, np.ones_like(J), nu)
+    closed = nu[0] / np.log1p(nu[0] ** 3 / J[0])
+    assert np.max(np.abs(T - closed) / closed) < 1e-14
+
+
+# ---------------------------------------------------------------- fixed point (Algorithm, Proposition)
+
+@pytest.fixture(scope="module")
+def config1_like():
+    P = _grid_problem((7, 7, 7), emit_faces=1)
+    G = P.dense_G()
+    S = P.dense_S()
+    Q = solve.SIGMA * np.ones(len(P.emitting))
+    return P, G, S @ Q
+
+
+def test_fixed_point_limit_equals_direct_solve(config1_like):
+    P, G, SE = config1_like
+    res = solve.fixed_point([G], SE[None], grey=True, tol=1e-14)
+    Jstar = solve.direct_grey(G, SE)
+    assert np.max(np.abs(res.J[0] - Jstar)) < 1e-12 * np.max(Jstar)
+
+
+def test_fixed_point_is_monotone(config1_like):
+    """Proposition (Section "Fixed Point Iterations"): increasing from T^0 = 0,
+    decreasing from T^0 above the solution."""
+    P, G, SE = config1_like
+    up = solve.fixed_point([G], SE[None], grey=True, tol=1e-12, keep_history=True)
+    Ts = np.array(up.T_history)
+    assert np.all(np.diff(Ts, axis=0) >= -1e-15)
+    assert np.all(np.diff(np.array(up.J_history)[:, 0], axis=0) >= -1e-15)
+    down = solve.fixed_point([G], SE[None], grey=True, tol=1e-12, T0=np.full(P.grid.N, 2.0),
+                             keep_history=True)
+    Td = np.array(down.T_history)
+    assert np.all(np.diff(Td, axis=0) <= 1e-15)
+    assert np.max(np.abs(down.T - up.T)) < 1e-10
+
+
+def test_grey_solution_is_linear_in_the_source(config1_like):
+    P, G, SE = config1_like
+    a = solve.fixed_point([G], SE[None], grey=True, tol=1e-14)
+    b = solve.fixed_point([G], 3.0 * SE[None], grey=True, tol=1e-14)
+    assert np.max(np.abs(b.J - 3.0 * a.J)) < 1e-12 * np.max(b.J)
+
+
+def test_y_z_symmetry_with_wall_at_x0():
+    """The Kuhn split is invariant under axis permutations: with the x = 0 wall
+    emitting and constant kappa, J(x,y,z) = J(x,z,y)."""
+    P = _grid_problem((6, 5, 5), hi=(1.6, 1, 1), kappa=np.full(150, 0.8), emit_faces=1)
+    G, S = P.dense_G(), P.dense_S()
+    res = solve.fixed_point([G], (S @ np.full(len(P.emitting), solve.SIGMA))[None], grey=True, tol=1e-13)
+    J = res.J[0].reshape(P.grid.n)
+    assert np.max(np.abs(J - J.transpose(0, 2, 1))) < 1e-13 * np.max(J)
+    # the x direction is not symmetric (the wall is at x = 0): the check has teeth
+    assert np.max(np.abs(J - J[::-1, :, :])) > 1e-3 * np.max(J)
+
+
+def test_isothermal_enclosure_tends_to_wall_temperature():
+    """All walls at T_w: the continuum solution is T = T_w everywhere; the discrete
+    one approaches it as h -> 0."""
+    devs = []
+    for n in (4, 7, 13):
+        P = _grid_problem((n, n, n), kappa=lambda X: 0.3 + X[:, 0], emit_faces=63)
+        G, S = P.dense_G(), P.dense_S()
+        SE = S @ np.full(len(P.emitting), solve.SIGMA * 1.5 ** 4)
+        res = solve.fixed_point([G], SE[None], grey=True, tol=1e-12)
+        devs.append(np.sqrt(np.mean((res.T / 1.5 - 1) ** 2)))
+    assert devs[0] > devs[1] > devs[2] and devs[2] < 0.03
+    assert 1.6 < devs[1] / devs[2] < 2.4           # first order in h
+
+
+def test_multiband_fixed_point_approaches_grey_with_fine_bands():
+    """With kappa independent of nu, the band sum of Planck is sigma T^4 and the
+    band fixed point tends to the grey one (Section "An Academic Test")."""
+    P = _grid_problem((4, 4, 4), kappa=np.full(64, 0.7), emit_faces=1)
+    G, S = P.dense_G(), P.dense_S()
+    grey = solve.fixed_point([G], (S @ np.full(len(P.emitting), solve.SIGMA))[None], grey=True, tol=1e-13)
+    nu = np.linspace(1e-3, 40, 4001)
+    B = len(nu)
+    Q = solve.planck(nu, 1.0)
+    SE = (S.sum(axis=1)[None, :] * Q[:, None])
+    w = solve.band_weights(nu)
+    res = solve.fixed_point([G] * B, SE, grey=False, nu=nu, w=w, kappa_v=np.full((B, 64), 0.7), tol=1e-12)
+    assert np.max(np.abs(res.T - grey.T) / grey.T) < 1e-5
