@@ -1,0 +1,210 @@
+/*
+ * rte.h -- C ABI of the MI355X (gfx950) library for the integral form of
+ * radiative transfer with a planar reflective wall, compressed with
+ * H-matrices (Pironneau & Tournier, "Reflective Conditions for Radiative
+ * Transfer in Integral Form with H-Matrices", arXiv 2306.05789).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns rte_status_t.  No C++ exception or abort crosses the
+ *    ABI.  On an error, rte_last_error() returns a thread-local message.
+ *  - Handles (rte_mesh_t, rte_plan_t, rte_hmat_t) are opaque and owned by the
+ *    library; *_destroy(NULL) is a no-op.  Handles are immutable after
+ *    creation, so concurrent calls on different streams may share them.
+ *  - Arrays documented "device" are HIP device pointers on the current
+ *    device (for example torch tensors' data pointers); "host" arrays are
+ *    ordinary host memory.  The caller owns every array it passes.
+ *  - Vertex arrays are in natural order v = (i*n1 + j)*n2 + k of the grid
+ *    index (i,j,k); the library permutes to its cluster order internally.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it; calls that return host-visible results
+ *    synchronise that stream before returning.
+ *  - Validation of every argument happens before any device work.
+ */
+#ifndef RTE_H
+#define RTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RTE_OK = 0,
+    RTE_E_INVALID_ARG = 1,   /* an argument failed validation; nothing was enqueued */
+    RTE_E_OUT_OF_MEMORY = 2, /* a device allocation failed; no state leaks */
+    RTE_E_BUDGET = 3,        /* the request does not fit the configured memory budget */
+    RTE_E_DEVICE = 4,        /* a HIP runtime call failed */
+    RTE_E_NOT_CONVERGED = 5, /* max_iter reached; outputs hold the last iterate */
+    RTE_E_INTERNAL = 6
+} rte_status_t;
+
+typedef enum {
+    RTE_FP64 = 0,        /* FP64 entries, ACA, storage and matvec */
+    RTE_FP32 = 1,        /* FP32 entries, ACA, storage; FP32 accumulation */
+    RTE_MIXED_BF16 = 2   /* FP32 entries and ACA; low-rank factors stored as BF16 hi + lo
+                            with per-block FP32 scale, dense leaves FP32; solves use
+                            BF16-hi sweeps with FP64 defect correction */
+} rte_precision_t;
+
+typedef enum { RTE_VOLUME = 0, RTE_SURFACE = 1 } rte_kind_t;
+
+typedef struct rte_mesh *rte_mesh_t;
+typedef struct rte_plan *rte_plan_t;
+typedef struct rte_hmat *rte_hmat_t;
+
+/* ------------------------------------------------------------------ mesh
+ * Section "FEM discretization": a tetrahedral mesh of the domain and a
+ * triangular mesh of its boundary.  Here the domain is the box [lo,hi] with
+ * n[a] >= 2 vertices per axis; each cell is split into the six Kuhn
+ * tetrahedra that share its (0,0,0)-(1,1,1) diagonal, and each boundary square
+ * into the two triangles of its low-to-high diagonal.
+ * reflect_axis in {-1,0,1,2}: -1 = no reflective wall; else the box face
+ * x[reflect_axis] = (reflect_side ? hi : lo) reflects with coefficient
+ * R in [0,1] (Corollary, planar wall, one reflection: Hypothesis 1 with M = 1).
+ * emit_faces: bit f (0..5 = x-,x+,y-,y+,z-,z+) marks a black emitting face
+ * (boundary source Q = B_nu(T_wall), eq. SE1); the reflective face may not emit. */
+typedef struct {
+    int32_t n[3];
+    double lo[3], hi[3];
+    int32_t reflect_axis;
+    int32_t reflect_side;
+    double R;
+    uint32_t emit_faces;
+} rte_mesh_desc_t;
+
+rte_status_t rte_mesh_create(const rte_mesh_desc_t *desc, rte_mesh_t *out);
+/* Number of volume vertices N and of emitting boundary vertices L. */
+rte_status_t rte_mesh_sizes(rte_mesh_t mesh, int64_t *N, int64_t *L);
+/* Natural ids of the emitting vertices in ascending order (host array of L). */
+rte_status_t rte_mesh_emitting_ids(rte_mesh_t mesh, int64_t *ids);
+void rte_mesh_destroy(rte_mesh_t mesh);
+
+/* ------------------------------------------------------------------ H-matrix options
+ * Section "Compression": cluster tree by geometric bisection (leaf_size),
+ * admissibility max(R1,R2) < eta * dist(box1, box2), partially pivoted ACA
+ * with relative Frobenius tolerance aca_eps.  dense = 1 stores every block
+ * dense (no compression). */
+typedef struct {
+    int32_t kind;        /* rte_kind_t: RTE_VOLUME (N x N matrix G) or RTE_SURFACE (N x L matrix S) */
+    int32_t dense;
+    int32_t leaf_size;   /* >= 1 */
+    double eta;          /* > 0 */
+    double aca_eps;      /* in (0,1) */
+    int32_t precision;   /* rte_precision_t */
+} rte_hmat_opts_t;
+
+/* ------------------------------------------------------------------ plan (host only)
+ * The cluster trees and the block tree, built on the host without touching
+ * the device.  Export: tgt_perm[N_tgt] and src_perm[N_src] map cluster order
+ * to natural ids (surface sources: to emitting-vertex natural ids); blocks
+ * [nblocks][5] = (t0, t1, s0, s1, admissible) as half-open ranges in cluster
+ * order, dense leaves first, then admissible blocks, each in tree order. */
+typedef struct {
+    int64_t n_tgt, n_src;
+    int64_t n_dense, n_lowrank;
+    int64_t dense_entries;       /* sum of m*n over dense leaves */
+    int64_t lowrank_sum_mn;      /* sum of m+n over admissible blocks */
+    int64_t n_tgt_leaves;
+} rte_plan_info_t;
+
+rte_status_t rte_plan_create(rte_mesh_t mesh, const rte_hmat_opts_t *opts, rte_plan_t *out);
+rte_status_t rte_plan_info(rte_plan_t plan, rte_plan_info_t *info);
+rte_status_t rte_plan_export(rte_plan_t plan, int64_t *tgt_perm, int64_t *src_perm, int64_t *blocks);
+void rte_plan_destroy(rte_plan_t plan);
+
+/* ------------------------------------------------------------------ entries
+ * Direct evaluation of n matrix entries (rows[k], cols[k]) for one kappa field
+ * (tests and diagnostics).  Volume: G^{ij} = exp(-tau) g^{ij} + R exp(-tau_bar) g_bar^{ij}
+ * (Section "FEM discretization"), cols are vertex ids.  Surface: S^{il} of the
+ * boundary source matrix, cols are natural ids of emitting vertices.
+ * kappa: device, [N] FP64 vertex values.  rows, cols: device int64 [n].
+ * out: device [n], FP64 (precision RTE_FP64) or FP32 values widened to FP64. */
+rte_status_t rte_entries(rte_mesh_t mesh, int32_t kind, const double *kappa, int64_t n,
+                         const int64_t *rows, const int64_t *cols, double *out,
+                         int32_t precision, void *stream);
+
+/* ------------------------------------------------------------------ assembly
+ * Builds one H-matrix per band from kappa (device, [n_bands][N] FP64): dense
+ * leaves are filled directly, admissible blocks by partially pivoted ACA on
+ * the GPU (Section "Compression").  Synchronises `stream`. */
+rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *kappa,
+                               const rte_hmat_opts_t *opts, void *stream, rte_hmat_t *out);
+
+/* y = H_band x for nrhs right-hand sides.  x: device [nrhs][N_src] FP64 (surface:
+ * N_src = L, emitting vertices in ascending id order); y: device [nrhs][N_tgt].
+ * Natural order on both sides.  Stored precision as assembled; FP64 accumulate
+ * for FP64 storage, FP32 accumulate otherwise, results returned in FP64. */
+rte_status_t rte_hmat_matvec(rte_hmat_t h, int32_t band, int32_t nrhs, const double *x,
+                             double *y, void *stream);
+
+typedef struct {
+    int64_t n_tgt, n_src;
+    int32_t n_bands, precision;
+    int64_t n_dense, n_lowrank, n_fallback_dense; /* fallback: ACA did not converge below the cap */
+    int64_t dense_entries;                        /* stored dense entries, per band, summed */
+    int64_t lowrank_entries;                      /* sum over LR blocks of (m+n)*rank, summed over bands */
+    int32_t max_rank;
+    double mean_rank;                             /* (m+n)-weighted */
+    double compression;                           /* 1 - stored entries / (N_tgt*N_src*bands) */
+    int64_t bytes;                                /* device bytes of the stored operator */
+    int64_t entries_evaluated;                    /* kernel entries computed during assembly */
+    double assemble_ms;
+} rte_hmat_stats_t;
+
+rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats);
+
+/* Factors of admissible block `block` (0-based among admissible blocks, plan
+ * order) of band `band`, copied to host FP64: U [m][rank] and V [n][rank],
+ * rows in cluster order of the block's ranges; the block approximates rows
+ * tgt_perm[t0..t1) x cols src_perm[s0..s1) as U V^T.  Pass NULL U/V to query
+ * the rank only.  Synchronous. */
+rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, int32_t *rank,
+                                    double *U, double *V);
+void rte_hmat_destroy(rte_hmat_t h);
+
+/* ------------------------------------------------------------------ fixed point
+ * Algorithm of Section "Fixed Point Iterations" (eq. algo), with J^0 = 0:
+ *   S_b   = (1 - a_b) B_{nu_b}(T) + a_b J_b
+ *   J_b  <- S^E_b + G_b S_b,  S^E_b = S_b_hat Q_b,  Q_b = B_{nu_b}(T_wall)
+ *   T     : per vertex root of sum_b w_b kappa_b (1 - a_b)(J_b - B_{nu_b}(T)) = 0 (FP64 Newton)
+ * grey = 1: one band, B(T) = sigma T^4 with sigma = pi^4/15 (eq. grey), T = (J/sigma)^{1/4}.
+ * Stops when max_b ||J_b^{k+1} - J_b^k||_2 / ||J_b^{k+1}||_2 <= tol, per right-hand side.
+ * nu, w, a: host arrays of n_bands (w: NULL = trapezoid weights on sorted nu;
+ * a: NULL = no scattering).  T_wall: device [nrhs][L]; T0: device [nrhs][N] or NULL (= 0).
+ * T_out: device [nrhs][N]; J_out: device [nrhs][n_bands][N] or NULL. */
+typedef struct {
+    int32_t n_bands;
+    const double *nu;
+    const double *w;
+    const double *a;
+    int32_t grey;
+    int32_t nrhs;
+    const double *T_wall;
+    const double *T0;
+    double tol;
+    int32_t max_iter;
+    int32_t precision;     /* RTE_MIXED_BF16: inner sweeps on BF16-hi factors, FP64 defect steps */
+} rte_solve_desc_t;
+
+typedef struct {
+    int32_t iterations;         /* matvec sweeps over all bands */
+    int32_t outer_steps;        /* FP64 defect-correction steps (mixed precision) */
+    double residual;            /* final relative change of J */
+    int64_t monotone_violations;/* vertex-steps where T decreased (from T0 = 0 it should be 0) */
+    double ms_total, ms_matvec;
+} rte_solve_stats_t;
+
+rte_status_t rte_fixed_point_solve(rte_mesh_t mesh, rte_hmat_t vol, rte_hmat_t surf,
+                                   const rte_solve_desc_t *desc, double *T_out, double *J_out,
+                                   rte_solve_stats_t *stats, void *stream);
+
+/* ------------------------------------------------------------------ misc */
+const char *rte_status_string(rte_status_t s);
+const char *rte_last_error(void);
+const char *rte_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTE_H */

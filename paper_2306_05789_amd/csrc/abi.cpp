@@ -1,0 +1,346 @@
+// The C ABI (include/rte.h): argument validation, handle management and
+// error translation.  Every entry point catches everything and returns a
+// status; the message of the last error is kept per thread.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <unordered_set>
+
+#include "rte_internal.h"
+
+namespace rte {
+void mesh_init(Mesh &M, const rte_mesh_desc_t &d);
+}
+
+using namespace rte;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+rte_status_t guard(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return RTE_E_OUT_OF_MEMORY;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return RTE_E_INTERNAL;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return RTE_E_INTERNAL;
+    }
+}
+
+template <typename T>
+std::vector<T> to_host(const T *dev, int64_t n, hipStream_t s) {
+    std::vector<T> h((size_t)n);
+    if (n) {
+        HIP_CHECK(hipMemcpyAsync(h.data(), dev, sizeof(T) * (size_t)n, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+    return h;
+}
+
+void check_device_pointer(const void *p, const char *what) {
+    RTE_REQUIRE(p != nullptr, std::string(what) + " is NULL");
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(RTE_E_INVALID_ARG, std::string(what) + " is not a device pointer");
+    }
+    RTE_REQUIRE(attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged,
+                std::string(what) + " is not device memory");
+}
+
+void check_kappa(const double *kappa, int64_t n, hipStream_t s) {
+    check_device_pointer(kappa, "kappa");
+    auto h = to_host(kappa, n, s);
+    for (double v : h) RTE_REQUIRE(std::isfinite(v) && v >= 0.0, "kappa must be finite and >= 0");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rte_status_string(rte_status_t s) {
+    switch (s) {
+        case RTE_OK: return "ok";
+        case RTE_E_INVALID_ARG: return "invalid argument";
+        case RTE_E_OUT_OF_MEMORY: return "out of memory";
+        case RTE_E_BUDGET: return "memory budget exceeded";
+        case RTE_E_DEVICE: return "device error";
+        case RTE_E_NOT_CONVERGED: return "not converged";
+        case RTE_E_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char *rte_last_error(void) { return g_last_error.c_str(); }
+
+const char *rte_version(void) { return "rte-mi355x 0.1 (gfx950)"; }
+
+rte_status_t rte_mesh_create(const rte_mesh_desc_t *desc, rte_mesh_t *out) {
+    return guard([&] {
+        RTE_REQUIRE(desc && out, "rte_mesh_create: NULL argument");
+        *out = nullptr;
+        auto m = std::make_unique<rte_mesh>();
+        mesh_init(m->m, *desc);
+        *out = m.release();
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_mesh_sizes(rte_mesh_t mesh, int64_t *N, int64_t *L) {
+    return guard([&] {
+        RTE_REQUIRE(mesh, "rte_mesh_sizes: NULL mesh");
+        if (N) *N = mesh->m.N;
+        if (L) *L = mesh->m.L;
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_mesh_emitting_ids(rte_mesh_t mesh, int64_t *ids) {
+    return guard([&] {
+        RTE_REQUIRE(mesh && ids, "rte_mesh_emitting_ids: NULL argument");
+        std::memcpy(ids, mesh->m.emitting.data(), sizeof(int64_t) * mesh->m.emitting.size());
+        return RTE_OK;
+    });
+}
+
+void rte_mesh_destroy(rte_mesh_t mesh) { delete mesh; }
+
+rte_status_t rte_plan_create(rte_mesh_t mesh, const rte_hmat_opts_t *opts, rte_plan_t *out) {
+    return guard([&] {
+        RTE_REQUIRE(mesh && opts && out, "rte_plan_create: NULL argument");
+        *out = nullptr;
+        auto p = std::make_unique<rte_plan>();
+        p->p = build_plan(mesh->m, *opts);
+        *out = p.release();
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_plan_info(rte_plan_t plan, rte_plan_info_t *info) {
+    return guard([&] {
+        RTE_REQUIRE(plan && info, "rte_plan_info: NULL argument");
+        const Plan &P = *plan->p;
+        info->n_tgt = (int64_t)P.tgt_nat.size();
+        info->n_src = (int64_t)P.src_nat.size();
+        info->n_dense = (int64_t)P.dense.size();
+        info->n_lowrank = (int64_t)P.lowrank.size();
+        info->dense_entries = 0;
+        for (auto &b : P.dense) info->dense_entries += (b.t1 - b.t0) * (b.s1 - b.s0);
+        info->lowrank_sum_mn = 0;
+        for (auto &b : P.lowrank) info->lowrank_sum_mn += (b.t1 - b.t0) + (b.s1 - b.s0);
+        info->n_tgt_leaves = (int64_t)P.tgt_leaves.size();
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_plan_export(rte_plan_t plan, int64_t *tgt_perm, int64_t *src_perm, int64_t *blocks) {
+    return guard([&] {
+        RTE_REQUIRE(plan, "rte_plan_export: NULL plan");
+        const Plan &P = *plan->p;
+        if (tgt_perm) std::memcpy(tgt_perm, P.tgt_nat.data(), sizeof(int64_t) * P.tgt_nat.size());
+        if (src_perm) std::memcpy(src_perm, P.src_nat.data(), sizeof(int64_t) * P.src_nat.size());
+        if (blocks) {
+            int64_t k = 0;
+            for (auto &b : P.dense) {
+                blocks[k++] = b.t0; blocks[k++] = b.t1; blocks[k++] = b.s0; blocks[k++] = b.s1; blocks[k++] = 0;
+            }
+            for (auto &b : P.lowrank) {
+                blocks[k++] = b.t0; blocks[k++] = b.t1; blocks[k++] = b.s0; blocks[k++] = b.s1; blocks[k++] = 1;
+            }
+        }
+        return RTE_OK;
+    });
+}
+
+void rte_plan_destroy(rte_plan_t plan) { delete plan; }
+
+rte_status_t rte_entries(rte_mesh_t mesh, int32_t kind, const double *kappa, int64_t n, const int64_t *rows,
+                         const int64_t *cols, double *out, int32_t precision, void *stream) {
+    return guard([&] {
+        RTE_REQUIRE(mesh, "rte_entries: NULL mesh");
+        RTE_REQUIRE(kind == RTE_VOLUME || kind == RTE_SURFACE, "rte_entries: bad kind");
+        RTE_REQUIRE(precision == RTE_FP64 || precision == RTE_FP32 || precision == RTE_MIXED_BF16,
+                    "rte_entries: bad precision");
+        RTE_REQUIRE(n >= 0, "rte_entries: n < 0");
+        if (n == 0) return RTE_OK;
+        hipStream_t s = (hipStream_t)stream;
+        const Mesh &m = mesh->m;
+        check_kappa(kappa, m.N, s);
+        check_device_pointer(rows, "rows");
+        check_device_pointer(cols, "cols");
+        check_device_pointer(out, "out");
+        auto hr = to_host(rows, n, s), hc = to_host(cols, n, s);
+        for (int64_t v : hr) RTE_REQUIRE(v >= 0 && v < m.N, "rte_entries: row id out of range");
+        if (kind == RTE_VOLUME) {
+            for (int64_t v : hc) RTE_REQUIRE(v >= 0 && v < m.N, "rte_entries: column id out of range");
+        } else {
+            std::unordered_set<int64_t> em(m.emitting.begin(), m.emitting.end());
+            for (int64_t v : hc) RTE_REQUIRE(em.count(v), "rte_entries: column is not an emitting vertex");
+        }
+        entries_launch(m, kind, kappa, n, rows, cols, out, precision, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *kappa, const rte_hmat_opts_t *opts,
+                               void *stream, rte_hmat_t *out) {
+    return guard([&] {
+        RTE_REQUIRE(mesh && opts && out, "rte_hmat_assemble: NULL argument");
+        *out = nullptr;
+        RTE_REQUIRE(n_bands >= 1 && n_bands <= 4096, "rte_hmat_assemble: n_bands out of range");
+        hipStream_t s = (hipStream_t)stream;
+        const Mesh &m = mesh->m;
+        auto plan = build_plan(m, *opts);
+        check_kappa(kappa, m.N * n_bands, s);
+        const auto t0 = std::chrono::steady_clock::now();
+        auto hm = std::make_unique<rte_hmat>();
+        HMat &H = hm->h;
+        HIP_CHECK(hipGetDevice(&H.device));
+        H.mesh = &m;
+        H.n_bands = n_bands;
+        H.precision = opts->precision;
+        H.kind = opts->kind;
+        H.plan = std::move(plan);
+        const Plan &P = *H.plan;
+        H.tgt_nat = upload(P.tgt_nat, s);
+        H.src_nat = upload(P.src_nat, s);
+        H.src_pos = upload(opts->kind == RTE_VOLUME ? P.tgt_nat : P.src.perm, s);
+        H.kappa_c.alloc(sizeof(double) * (size_t)m.N * n_bands);
+        permute_gather(H.tgt_nat.as<int64_t>(), m.N, n_bands, m.N, m.N, kappa, H.kappa_c.as<double>(), s);
+        H.bands.resize(n_bands);
+        int64_t evaluated = 0, bytes = 0, dense_e = 0, lr_e = 0, nfb = 0;
+        double wsum = 0, wr = 0;
+        int maxr = 0;
+        for (int b = 0; b < n_bands; ++b) {
+            assemble_band(H, b, kappa + (int64_t)b * m.N, s);
+            matvec_build(H, b, s);
+            const BandStore &B = H.bands[b];
+            evaluated += B.evaluated;
+            bytes += B.bytes;
+            dense_e += B.dense_entries;
+            lr_e += B.lr_entries;
+            for (size_t k = 0; k < P.lowrank.size(); ++k) {
+                const Block &bl = P.lowrank[k];
+                const double mn = (double)((bl.t1 - bl.t0) + (bl.s1 - bl.s0));
+                if (B.rank[k] < 0) { ++nfb; continue; }
+                wsum += mn;
+                wr += mn * B.rank[k];
+                maxr = std::max(maxr, B.rank[k]);
+            }
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+        rte_hmat_stats_t &st = H.stats;
+        st.n_tgt = (int64_t)P.tgt_nat.size();
+        st.n_src = (int64_t)P.src_nat.size();
+        st.n_bands = n_bands;
+        st.precision = H.precision;
+        st.n_dense = (int64_t)P.dense.size();
+        st.n_lowrank = (int64_t)P.lowrank.size();
+        st.n_fallback_dense = nfb;
+        st.dense_entries = dense_e;
+        st.lowrank_entries = lr_e;
+        st.max_rank = maxr;
+        st.mean_rank = wsum > 0 ? wr / wsum : 0.0;
+        st.compression = 1.0 - (double)(dense_e + lr_e) / ((double)st.n_tgt * st.n_src * n_bands);
+        st.bytes = bytes;
+        st.entries_evaluated = evaluated;
+        st.assemble_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = hm.release();
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_matvec(rte_hmat_t h, int32_t band, int32_t nrhs, const double *x, double *y, void *stream) {
+    return guard([&] {
+        RTE_REQUIRE(h, "rte_hmat_matvec: NULL matrix");
+        const HMat &H = h->h;
+        RTE_REQUIRE(band >= 0 && band < H.n_bands, "rte_hmat_matvec: band out of range");
+        RTE_REQUIRE(nrhs >= 1 && nrhs <= 4096, "rte_hmat_matvec: nrhs out of range");
+        check_device_pointer(x, "x");
+        check_device_pointer(y, "y");
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t ns = H.stats.n_src, nt = H.stats.n_tgt;
+        DevBuf xc(sizeof(double) * ns * nrhs), yc(sizeof(double) * nt * nrhs);
+        permute_gather(H.src_pos.as<int64_t>(), ns, nrhs, ns, ns, x, xc.as<double>(), s);
+        matvec_launch(H, band, nrhs, xc.as<double>(), yc.as<double>(), nullptr, s);
+        permute_scatter(H.tgt_nat.as<int64_t>(), nt, nrhs, nt, nt, yc.as<double>(), y, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats) {
+    return guard([&] {
+        RTE_REQUIRE(h && stats, "rte_hmat_stats: NULL argument");
+        *stats = h->h.stats;
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, int32_t *rank, double *U, double *V) {
+    return guard([&] {
+        RTE_REQUIRE(h && rank, "rte_hmat_block_factors: NULL argument");
+        const HMat &H = h->h;
+        RTE_REQUIRE(band >= 0 && band < H.n_bands, "rte_hmat_block_factors: band out of range");
+        RTE_REQUIRE(block >= 0 && block < (int64_t)H.plan->lowrank.size(), "rte_hmat_block_factors: block out of range");
+        const BandStore &B = H.bands[band];
+        *rank = B.rank[block];
+        if (!U || !V || B.rank[block] <= 0) return RTE_OK;
+        const Block &bl = H.plan->lowrank[block];
+        const int64_t m = bl.t1 - bl.t0, n = bl.s1 - bl.s0, k = B.rank[block];
+        std::vector<double> ut(m * k), vt(n * k);
+        if (H.precision == RTE_FP64) {
+            HIP_CHECK(hipMemcpy(ut.data(), B.U[block], sizeof(double) * m * k, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vt.data(), B.V[block], sizeof(double) * n * k, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> uf(m * k), vf(n * k);
+            HIP_CHECK(hipMemcpy(uf.data(), B.U[block], sizeof(float) * m * k, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vf.data(), B.V[block], sizeof(float) * n * k, hipMemcpyDeviceToHost));
+            for (int64_t e = 0; e < m * k; ++e) ut[e] = uf[e];
+            for (int64_t e = 0; e < n * k; ++e) vt[e] = vf[e];
+        }
+        for (int64_t l = 0; l < k; ++l) {
+            for (int64_t i = 0; i < m; ++i) U[i * k + l] = ut[l * m + i];
+            for (int64_t j = 0; j < n; ++j) V[j * k + l] = vt[l * n + j];
+        }
+        return RTE_OK;
+    });
+}
+
+void rte_hmat_destroy(rte_hmat_t h) { delete h; }
+
+rte_status_t rte_fixed_point_solve(rte_mesh_t mesh, rte_hmat_t vol, rte_hmat_t surf, const rte_solve_desc_t *desc,
+                                   double *T_out, double *J_out, rte_solve_stats_t *stats, void *stream) {
+    return guard([&] {
+        RTE_REQUIRE(mesh && vol && surf && desc, "rte_fixed_point_solve: NULL argument");
+        hipStream_t s = (hipStream_t)stream;
+        const Mesh &m = mesh->m;
+        RTE_REQUIRE(desc->nrhs >= 1 && desc->nrhs <= 4096, "solve: nrhs out of range");
+        check_device_pointer(desc->T_wall, "T_wall");
+        auto tw = to_host(desc->T_wall, m.L * desc->nrhs, s);
+        for (double v : tw) RTE_REQUIRE(std::isfinite(v) && v > 0.0, "solve: T_wall must be finite and > 0");
+        if (desc->T0) {
+            check_device_pointer(desc->T0, "T0");
+            auto t0 = to_host(desc->T0, m.N * desc->nrhs, s);
+            for (double v : t0) RTE_REQUIRE(std::isfinite(v) && v >= 0.0, "solve: T0 must be finite and >= 0");
+        }
+        if (T_out) check_device_pointer(T_out, "T_out");
+        if (J_out) check_device_pointer(J_out, "J_out");
+        return fixed_point_solve(m, vol->h, surf->h, *desc, T_out, J_out, stats, s);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Kernels that evaluate kernel entries directly: arbitrary (row, col) pairs,
+// and the dense near-field leaves of the H-matrix (Section "Compression": a
+// block that reaches the leaves without being admissible is computed in full).
+#include "entry_dev.h"
+#include "kernels.h"
+
+namespace rte {
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void k_entries(EntryCtx<T> c, int64_t n, const int64_t *__restrict__ rows,
+                                                 const int64_t *__restrict__ cols, double *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    out[k] = (double)entry<T, KIND>(c, rows[k], cols[k]);
+}
+
+// One task = up to kFillChunk consecutive entries of one dense block, stored
+// column-major (source column outer, target row inner).
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void k_dense_fill(EntryCtx<T> c, const FillTask *__restrict__ tasks,
+                                                    const int64_t *__restrict__ tgt_nat,
+                                                    const int64_t *__restrict__ src_nat) {
+    const FillTask tk = tasks[blockIdx.x];
+    T *out = static_cast<T *>(tk.out);
+    const int64_t total = (int64_t)tk.m * tk.n;
+    const int64_t end = min(total, tk.first + (int64_t)kFillChunk);
+    for (int64_t e = tk.first + threadIdx.x; e < end; e += blockDim.x) {
+        const int64_t jl = e / tk.m, il = e - jl * tk.m;
+        out[e] = entry<T, KIND>(c, tgt_nat[tk.t0 + il], src_nat[tk.s0 + jl]);
+    }
+}
+
+__global__ void k_to_float(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = (float)in[k];
+}
+
+void to_float(const double *in, float *out, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    k_to_float<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, out, n);
+    HIP_LAUNCH_CHECK();
+}
+
+template <typename T>
+EntryCtx<T> make_ctx(const Mesh &m, const T *kappa) {
+    EntryCtx<T> c;
+    c.g = m.dev;
+    c.kappa = kappa;
+    if constexpr (std::is_same<T, double>::value) c.st = stencil_device().d;
+    else c.st = stencil_device().f;
+    return c;
+}
+template EntryCtx<double> make_ctx<double>(const Mesh &, const double *);
+template EntryCtx<float> make_ctx<float>(const Mesh &, const float *);
+
+void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, const int64_t *rows,
+                    const int64_t *cols, double *out, int precision, hipStream_t s) {
+    if (n == 0) return;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    if (precision == RTE_FP64) {
+        auto c = make_ctx<double>(m, kappa);
+        if (kind == RTE_VOLUME) k_entries<double, RTE_VOLUME><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
+        else k_entries<double, RTE_SURFACE><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
+    } else {
+        DevBuf kf(sizeof(float) * (size_t)m.N);
+        to_float(kappa, kf.as<float>(), m.N, s);
+        auto c = make_ctx<float>(m, kf.as<float>());
+        if (kind == RTE_VOLUME) k_entries<float, RTE_VOLUME><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
+        else k_entries<float, RTE_SURFACE><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
+        HIP_LAUNCH_CHECK();
+        HIP_CHECK(hipStreamSynchronize(s));   // kf is released on return
+        return;
+    }
+    HIP_LAUNCH_CHECK();
+}
+
+template <typename T>
+void dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
+                       const int64_t *tgt_nat, const int64_t *src_nat, hipStream_t s) {
+    if (tasks.empty()) return;
+    DevBuf dt = upload(tasks, s);
+    auto c = make_ctx<T>(m, kappa);
+    const unsigned grid = (unsigned)tasks.size();
+    if (kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME><<<grid, 256, 0, s>>>(c, dt.as<FillTask>(), tgt_nat, src_nat);
+    else k_dense_fill<T, RTE_SURFACE><<<grid, 256, 0, s>>>(c, dt.as<FillTask>(), tgt_nat, src_nat);
+    HIP_LAUNCH_CHECK();
+    HIP_CHECK(hipStreamSynchronize(s));   // the task list is released on return
+}
+template void dense_fill_launch<double>(const Mesh &, int, const double *, const std::vector<FillTask> &,
+                                        const int64_t *, const int64_t *, hipStream_t);
+template void dense_fill_launch<float>(const Mesh &, int, const float *, const std::vector<FillTask> &,
+                                       const int64_t *, const int64_t *, hipStream_t);
+
+}  // namespace rte

@@ -1,0 +1,364 @@
+// Device evaluation of the kernel entries of the P1 collocation.
+//
+// Volume entry (Section "FEM discretization", with the Corollary's mirror term):
+//   G^{ij} = exp(-tau(x_i,x_j)) g(x_i, j) + R exp(-tau_bar(x_i,x_j)) g(x_bar_i, j)
+//   g(x, j) = |e|/(4 pi) sum_{e ni j} sum_q w_q kappa(y_q) lambda_j(y_q) / |x - y_q|^2
+// Surface entry (eq. SE1 and its mirror, Proposition 2):
+//   S^{il}  = exp(-tau(x_i,x_l)) s(x_i, l) + R exp(-tau_bar(x_i,x_l)) s(x_bar_i, l)
+//   s(x, l) = |t|/(4 pi) sum_{t ni l} sum_q w_q lambda_l(y_q) |(x - y_q).n| / |x - y_q|^3
+// with the coplanar limit theta_F/(4 pi) on the diagonal.  tau is the exact
+// line integral of the P1 kappa, tau_bar the same along the path reflected
+// at the wall.  One optical depth per vertex pair; near rule (degree 5)
+// when the grid Chebyshev distance is <= 2, degree 2 otherwise.
+//
+// tau is computed by a march over the six plane families that bound the
+// Kuhn tetrahedra (x_a = const and x_a - x_b = const in grid units): the
+// next crossing of every family is kept, the smallest one ends the current
+// piece, and kappa is linear on each piece, so the piece contributes its
+// length times kappa at its midpoint.
+#pragma once
+
+#include <type_traits>
+#include <utility>
+
+#include "rte_internal.h"
+
+namespace rte {
+
+template <typename T>
+struct EntryCtx {
+    GridDev g;
+    const T *__restrict__ kappa;   // [N] P1 vertex values of one band
+    StencilDev<T> st;
+};
+
+// ---------------------------------------------------------------- compile-time Kuhn star
+struct TetInfo { int slot[4]; int bits; };
+struct TriInfo { int ob, oc; };
+
+struct KuhnStar {
+    TetInfo tet[kTets];
+    TriInfo tri[kTris];
+};
+
+// Same enumeration as the host stencil tables: cell corner bits o (cell = j - o),
+// then the axis orders in lexicographic order; keep the tetrahedra that contain j.
+constexpr KuhnStar make_star() {
+    KuhnStar S{};
+    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int n = 0;
+    for (int bits = 0; bits < 8; ++bits) {
+        int o[3] = {bits & 1, (bits >> 1) & 1, (bits >> 2) & 1};
+        for (int p = 0; p < 6; ++p) {
+            int w[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
+            w[1][perm[p][0]] = 1;
+            w[2][perm[p][0]] = 1;
+            w[2][perm[p][1]] = 1;
+            bool has = false;
+            for (int k = 0; k < 4; ++k)
+                if (w[k][0] == o[0] && w[k][1] == o[1] && w[k][2] == o[2]) has = true;
+            if (!has) continue;
+            for (int k = 0; k < 4; ++k)
+                S.tet[n].slot[k] = (w[k][0] - o[0] + 1) * 9 + (w[k][1] - o[1] + 1) * 3 + (w[k][2] - o[2] + 1);
+            S.tet[n].bits = bits;
+            ++n;
+        }
+    }
+    const int corners[2][3][2] = {{{0, 0}, {1, 0}, {1, 1}}, {{0, 0}, {0, 1}, {1, 1}}};
+    int m = 0;
+    for (int ob = 0; ob < 2; ++ob)
+        for (int oc = 0; oc < 2; ++oc)
+            for (int t = 0; t < 2; ++t) {
+                bool has = false;
+                for (int k = 0; k < 3; ++k)
+                    if (corners[t][k][0] == ob && corners[t][k][1] == oc) has = true;
+                if (!has) continue;
+                S.tri[m].ob = ob;
+                S.tri[m].oc = oc;
+                ++m;
+            }
+    return S;
+}
+
+constexpr KuhnStar kStar = make_star();
+
+// ---------------------------------------------------------------- P1 kappa and the march
+template <typename T>
+__device__ __forceinline__ T kappa_grid(const GridDev &g, const T *__restrict__ kap, T X, T Y, T Z) {
+    int c0 = min(max((int)floor(X), 0), g.n[0] - 2);
+    int c1 = min(max((int)floor(Y), 0), g.n[1] - 2);
+    int c2 = min(max((int)floor(Z), 0), g.n[2] - 2);
+    T u0 = X - (T)c0, u1 = Y - (T)c1, u2 = Z - (T)c2;
+    int s0 = g.stride[0], s1 = g.stride[1], s2 = 1;
+    // order the local coordinates decreasingly, carrying the axis strides
+    if (u1 > u0) { T t = u0; u0 = u1; u1 = t; int s = s0; s0 = s1; s1 = s; }
+    if (u2 > u1) { T t = u1; u1 = u2; u2 = t; int s = s1; s1 = s2; s2 = s; }
+    if (u1 > u0) { T t = u0; u0 = u1; u1 = t; int s = s0; s0 = s1; s1 = s; }
+    int b = c0 * g.stride[0] + c1 * g.stride[1] + c2;
+    int v1 = b + s0, v2 = v1 + s1, v3 = b + g.stride[0] + g.stride[1] + 1;
+    return ((T)1 - u0) * kap[b] + (u0 - u1) * kap[v1] + (u1 - u2) * kap[v2] + u2 * kap[v3];
+}
+
+// tau along the segment P -> Q given in grid coordinates.
+template <typename T>
+__device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3]) {
+    const T D[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
+    const T wx = D[0] * (T)g.h[0], wy = D[1] * (T)g.h[1], wz = D[2] * (T)g.h[2];
+    const T len = sqrt(wx * wx + wy * wy + wz * wz);
+    if (len == (T)0) return (T)0;
+    const T F0[6] = {P[0], P[1], P[2], P[0] - P[1], P[1] - P[2], P[0] - P[2]};
+    const T dF[6] = {D[0], D[1], D[2], D[0] - D[1], D[1] - D[2], D[0] - D[2]};
+    T inv[6], m[6], st[6], tn[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (dF[f] != (T)0) {
+            inv[f] = (T)1 / dF[f];
+            st[f] = dF[f] > (T)0 ? (T)1 : (T)-1;
+            m[f] = dF[f] > (T)0 ? floor(F0[f]) + (T)1 : ceil(F0[f]) - (T)1;
+            tn[f] = (m[f] - F0[f]) * inv[f];
+        } else {
+            inv[f] = (T)0;
+            st[f] = (T)0;
+            m[f] = (T)0;
+            tn[f] = (T)2;   // never before the end of the segment
+        }
+    }
+    T tp = (T)0, acc = (T)0;
+    // every step advances at least one family; the pieces number at most
+    // sum_f |dF_f| + 7 <= 3 (|D0|+|D1|+|D2|) + 7
+    const int cap = 3 * (g.n[0] + g.n[1] + g.n[2]) + 16;
+    for (int it = 0; it < cap; ++it) {
+        T t = fmin(fmin(fmin(tn[0], tn[1]), fmin(tn[2], tn[3])), fmin(tn[4], tn[5]));
+        t = fmin(t, (T)1);
+        if (t > tp) {
+            const T tm = (T)0.5 * (tp + t);
+            acc += (t - tp) * kappa_grid(g, kap, P[0] + tm * D[0], P[1] + tm * D[1], P[2] + tm * D[2]);
+        }
+        if (t >= (T)1) break;
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+            if (tn[f] <= t) {
+                m[f] += st[f];
+                tn[f] = (m[f] - F0[f]) * inv[f];
+            }
+        tp = t;
+    }
+    return len * acc;
+}
+
+// Optical depth of the path from x (grid coords P) to the wall and on to y (Q),
+// the wall point being where the segment from the mirror image of x to y meets it.
+template <typename T>
+__device__ T tau_mirror(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3]) {
+    const int a = g.wall_axis;
+    const T C = g.wall_side ? (T)(g.n[a] - 1) : (T)0;
+    T Pb[3] = {P[0], P[1], P[2]};
+    Pb[a] = (T)2 * C - P[a];
+    T X[3];
+    const T den = Q[a] - Pb[a];
+    if (den == (T)0) {
+        X[0] = Q[0]; X[1] = Q[1]; X[2] = Q[2];
+    } else {
+        const T t = (C - Pb[a]) / den;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) X[b] = Pb[b] + t * (Q[b] - Pb[b]);
+        X[a] = C;
+    }
+    return tau_segment(g, kap, P, X) + tau_segment(g, kap, X, Q);
+}
+
+__device__ __forceinline__ int cheb3(const int a[3], const int b[3]) {
+    return max(max(abs(a[0] - b[0]), abs(a[1] - b[1])), abs(a[2] - b[2]));
+}
+
+__device__ __forceinline__ void vtx_index(const GridDev &g, int64_t v, int idx[3]) {
+    idx[0] = (int)(v / g.stride[0]);
+    int64_t r = v - (int64_t)idx[0] * g.stride[0];
+    idx[1] = (int)(r / g.stride[1]);
+    idx[2] = (int)(r - (int64_t)idx[1] * g.stride[1]);
+}
+
+// ---------------------------------------------------------------- volume quadrature
+template <typename T, int NQ, int t>
+__device__ __forceinline__ void vol_tet(const T *__restrict__ tab, const T kn[27], int cellmask,
+                                        const T dg[3], const T h2[3], T &acc) {
+    constexpr TetInfo ti = kStar.tet[t];
+    if (!((cellmask >> ti.bits) & 1)) return;
+    const T k0 = kn[ti.slot[0]], k1 = kn[ti.slot[1]], k2 = kn[ti.slot[2]], k3 = kn[ti.slot[3]];
+    const T *e = tab + t * NQ * 8;
+    T s = (T)0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const T ex = dg[0] - e[8 * q + 0], ey = dg[1] - e[8 * q + 1], ez = dg[2] - e[8 * q + 2];
+        const T r2 = h2[0] * ex * ex + h2[1] * ey * ey + h2[2] * ez * ez;
+        const T kq = e[8 * q + 4] * k0 + e[8 * q + 5] * k1 + e[8 * q + 6] * k2 + e[8 * q + 7] * k3;
+        s += e[8 * q + 3] * kq / r2;
+    }
+    acc += s;
+}
+
+template <typename T, int NQ, int... ts>
+__device__ __forceinline__ T vol_quad_all(std::integer_sequence<int, ts...>, const T *__restrict__ tab,
+                                          const T kn[27], int cellmask, const T dg[3], const T h2[3]) {
+    T acc = (T)0;
+    (vol_tet<T, NQ, ts>(tab, kn, cellmask, dg, h2, acc), ...);
+    return acc;
+}
+
+// g(x, j) without the 1/(4 pi)|e| factor; dg = (x - x_j) in grid units
+template <typename T>
+__device__ __forceinline__ T vol_quad(const EntryCtx<T> &c, const T kn[27], int cellmask, const T dg[3],
+                                      const T h2[3], bool near) {
+    if (near)
+        return vol_quad_all<T, 14>(std::make_integer_sequence<int, kTets>{}, c.st.vol_near, kn, cellmask, dg, h2);
+    return vol_quad_all<T, 4>(std::make_integer_sequence<int, kTets>{}, c.st.vol_far, kn, cellmask, dg, h2);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_star(const EntryCtx<T> &c, const int jj[3], T kn[27], int &cellmask) {
+    const GridDev &g = c.g;
+    cellmask = 0;
+#pragma unroll
+    for (int bits = 0; bits < 8; ++bits) {
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int o = (bits >> a) & 1;
+            ok = ok && (o ? jj[a] >= 1 : jj[a] <= g.n[a] - 2);
+        }
+        cellmask |= ok ? (1 << bits) : 0;
+    }
+#pragma unroll
+    for (int s = 0; s < 27; ++s) {
+        const int dx = s / 9 - 1, dy = (s / 3) % 3 - 1, dz = s % 3 - 1;
+        const int x = min(max(jj[0] + dx, 0), g.n[0] - 1);
+        const int y = min(max(jj[1] + dy, 0), g.n[1] - 1);
+        const int z = min(max(jj[2] + dz, 0), g.n[2] - 1);
+        kn[s] = c.kappa[x * g.stride[0] + y * g.stride[1] + z];
+    }
+}
+
+template <typename T>
+__device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
+    const GridDev &g = c.g;
+    int ii[3], jj[3];
+    vtx_index(g, i, ii);
+    vtx_index(g, j, jj);
+    T kn[27];
+    int cellmask;
+    load_star(c, jj, kn, cellmask);
+    const T h2[3] = {(T)(g.h[0] * g.h[0]), (T)(g.h[1] * g.h[1]), (T)(g.h[2] * g.h[2])};
+    const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
+    const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
+    const T dg[3] = {P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
+    T G = exp(-tau_segment(g, c.kappa, P, Q)) * vol_quad(c, kn, cellmask, dg, h2, cheb3(ii, jj) <= kNearCheb);
+    if (g.wall_axis >= 0) {
+        const int a = g.wall_axis;
+        const int Ci = g.wall_side ? g.n[a] - 1 : 0;
+        int mi[3] = {ii[0], ii[1], ii[2]};
+        mi[a] = 2 * Ci - ii[a];
+        const T dgm[3] = {(T)mi[0] - Q[0], (T)mi[1] - Q[1], (T)mi[2] - Q[2]};
+        G += (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) *
+             vol_quad(c, kn, cellmask, dgm, h2, cheb3(mi, jj) <= kNearCheb);
+    }
+    return G * (T)g.vol_scale;
+}
+
+// ---------------------------------------------------------------- surface quadrature
+template <typename T, int NQ, int t>
+__device__ __forceinline__ void tri_term(const T *__restrict__ tab, const int lb, const int lc, const int nb,
+                                         const int nc, const T db, const T dc, const T da2, const T hb2,
+                                         const T hc2, T &acc) {
+    constexpr TriInfo ti = kStar.tri[t];
+    const int sb = lb - ti.ob, sc = lc - ti.oc;
+    if (sb < 0 || sb > nb - 2 || sc < 0 || sc > nc - 2) return;
+    const T *e = tab + t * NQ * 4;
+    T s = (T)0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const T eb = db - e[4 * q + 0], ec = dc - e[4 * q + 1];
+        const T r2 = da2 + hb2 * eb * eb + hc2 * ec * ec;
+        s += e[4 * q + 2] / (r2 * sqrt(r2));
+    }
+    acc += s;
+}
+
+template <typename T, int NQ, int... ts>
+__device__ __forceinline__ T tri_all(std::integer_sequence<int, ts...>, const T *__restrict__ tab, int lb, int lc,
+                                     int nb, int nc, T db, T dc, T da2, T hb2, T hc2) {
+    T acc = (T)0;
+    (tri_term<T, NQ, ts>(tab, lb, lc, nb, nc, db, dc, da2, hb2, hc2, acc), ...);
+    return acc;
+}
+
+// s(x, l) including 1/(4 pi) and the element areas; x given by its grid
+// coordinates (possibly outside the box for a mirror image) and index.
+template <typename T>
+__device__ T surf_quad(const EntryCtx<T> &c, const int xi[3], const int ll[3], bool near) {
+    const GridDev &g = c.g;
+    T acc = (T)0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!((g.emit_faces >> f) & 1u)) continue;
+        const int a = f / 2;
+        const int pf = (f & 1) ? g.n[a] - 1 : 0;
+        if (ll[a] != pf) continue;
+        const int b = (a == 0) ? 1 : 0;
+        const int cc = (a == 2) ? 1 : 2;
+        if (xi[a] == pf) {
+            // coplanar limit: theta_F(x)/(4 pi) on the diagonal
+            if (xi[0] == ll[0] && xi[1] == ll[1] && xi[2] == ll[2]) {
+                T frac = (T)1;
+                const int axes[2] = {b, cc};
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int p = xi[axes[k]];
+                    if (p < 0 || p > g.n[axes[k]] - 1) frac = (T)0;
+                    else if (p == 0 || p == g.n[axes[k]] - 1) frac *= (T)0.5;
+                }
+                acc += (T)0.5 * frac;
+            }
+            continue;
+        }
+        const T da = (T)(xi[a] - pf) * (T)g.h[a];
+        const T da2 = da * da;
+        const T hb2 = (T)(g.h[b] * g.h[b]), hc2 = (T)(g.h[cc] * g.h[cc]);
+        const T db = (T)(xi[b] - ll[b]), dc = (T)(xi[cc] - ll[cc]);
+        T s;
+        if (near)
+            s = tri_all<T, 7>(std::make_integer_sequence<int, kTris>{}, c.st.tri_near, ll[b], ll[cc], g.n[b],
+                              g.n[cc], db, dc, da2, hb2, hc2);
+        else
+            s = tri_all<T, 3>(std::make_integer_sequence<int, kTris>{}, c.st.tri_far, ll[b], ll[cc], g.n[b],
+                              g.n[cc], db, dc, da2, hb2, hc2);
+        acc += s * fabs(da) * (T)g.area_scale[a];
+    }
+    return acc;
+}
+
+template <typename T>
+__device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
+    const GridDev &g = c.g;
+    int ii[3], ll[3];
+    vtx_index(g, i, ii);
+    vtx_index(g, l, ll);
+    const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
+    const T Q[3] = {(T)ll[0], (T)ll[1], (T)ll[2]};
+    T S = exp(-tau_segment(g, c.kappa, P, Q)) * surf_quad(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
+    if (g.wall_axis >= 0) {
+        const int a = g.wall_axis;
+        const int Ci = g.wall_side ? g.n[a] - 1 : 0;
+        int mi[3] = {ii[0], ii[1], ii[2]};
+        mi[a] = 2 * Ci - ii[a];
+        S += (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) * surf_quad(c, mi, ll, cheb3(mi, ll) <= kNearCheb);
+    }
+    return S;
+}
+
+template <typename T, int KIND>
+__device__ __forceinline__ T entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
+    if constexpr (KIND == RTE_VOLUME) return volume_entry(c, i, j);
+    else return surface_entry(c, i, j);
+}
+
+}  // namespace rte

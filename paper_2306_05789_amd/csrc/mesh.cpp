@@ -1,0 +1,236 @@
+// Structured Kuhn mesh of a box and the quadrature stencils of the P1
+// collocation (Section "FEM discretization and Compressed H-Matrices").
+//
+// Each grid cell is split into the six tetrahedra that share its
+// (0,0,0)-(1,1,1) diagonal, one per ordering of the three axes; a vertex of
+// the interior belongs to 24 of them.  Boundary squares are split along the
+// same diagonal direction, so a vertex inside a face belongs to 6 triangles.
+// On a uniform grid the quadrature points of the elements around a vertex sit
+// at fixed offsets from it, so one table per rule serves every vertex; the
+// elements that fall outside the box are masked per vertex.
+#include <cmath>
+#include <map>
+#include <mutex>
+
+#include "rte_internal.h"
+
+namespace rte {
+
+std::vector<double> Mesh::positions() const {
+    std::vector<double> p((size_t)N * 3);
+    for (int64_t v = 0; v < N; ++v) {
+        int64_t k = v % desc.n[2], j = (v / desc.n[2]) % desc.n[1], i = v / ((int64_t)desc.n[1] * desc.n[2]);
+        p[3 * v + 0] = desc.lo[0] + i * h[0];
+        p[3 * v + 1] = desc.lo[1] + j * h[1];
+        p[3 * v + 2] = desc.lo[2] + k * h[2];
+    }
+    return p;
+}
+
+std::vector<double> Mesh::emitting_positions() const {
+    auto all = positions();
+    std::vector<double> p;
+    p.reserve(emitting.size() * 3);
+    for (int64_t v : emitting) p.insert(p.end(), all.begin() + 3 * v, all.begin() + 3 * v + 3);
+    return p;
+}
+
+static const int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+static StencilHost make_stencil() {
+    StencilHost S;
+    const Rule &r_far = tet_rule(2), &r_near = tet_rule(5);
+    const Rule &t_far = tri_rule(2), &t_near = tri_rule(5);
+    S.nq_vol_far = r_far.nq;
+    S.nq_vol_near = r_near.nq;
+    S.nq_tri_far = t_far.nq;
+    S.nq_tri_near = t_near.nq;
+    // the device quadrature loops are specialised for these orbit sizes
+    if (r_far.nq != 4 || r_near.nq != 14 || t_far.nq != 3 || t_near.nq != 7)
+        throw Error(RTE_E_INTERNAL, "quadrature rule sizes differ from the device stencil sizes");
+    struct Tet { int dv[4][3]; int loc; int bits; };
+    std::vector<Tet> tets;
+    for (int bits = 0; bits < 8; ++bits) {
+        int o[3] = {bits & 1, (bits >> 1) & 1, (bits >> 2) & 1};
+        for (auto &sg : kPerm) {
+            int w[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
+            w[1][sg[0]] = 1;
+            w[2][sg[0]] = 1;
+            w[2][sg[1]] = 1;
+            int loc = -1;
+            for (int k = 0; k < 4; ++k)
+                if (w[k][0] == o[0] && w[k][1] == o[1] && w[k][2] == o[2]) loc = k;
+            if (loc < 0) continue;
+            Tet t;
+            for (int k = 0; k < 4; ++k)
+                for (int a = 0; a < 3; ++a) t.dv[k][a] = w[k][a] - o[a];
+            t.loc = loc;
+            t.bits = bits;
+            tets.push_back(t);
+        }
+    }
+    if ((int)tets.size() != kTets) throw Error(RTE_E_INTERNAL, "Kuhn star size");
+    auto fill_vol = [&](const Rule &r, std::vector<double> &out) {
+        out.assign((size_t)kTets * r.nq * 8, 0.0);
+        for (int t = 0; t < kTets; ++t)
+            for (int q = 0; q < r.nq; ++q) {
+                double *e = &out[((size_t)t * r.nq + q) * 8];
+                const double *b = &r.p[(size_t)q * 4];
+                for (int a = 0; a < 3; ++a) {
+                    double s = 0;
+                    for (int k = 0; k < 4; ++k) s += b[k] * tets[t].dv[k][a];
+                    e[a] = s;
+                }
+                e[3] = r.w[q] * b[tets[t].loc];
+                for (int k = 0; k < 4; ++k) e[4 + k] = b[k];
+            }
+    };
+    fill_vol(r_far, S.vol_far);
+    fill_vol(r_near, S.vol_near);
+    for (auto &t : tets) {
+        for (int k = 0; k < 4; ++k)
+            S.tet_meta.push_back((t.dv[k][0] + 1) * 9 + (t.dv[k][1] + 1) * 3 + (t.dv[k][2] + 1));
+        S.tet_meta.push_back(t.bits);
+    }
+    // boundary triangles around a face vertex, in the face's axes (b, c)
+    struct Tri { int dv[3][2]; int loc; int ob, oc; };
+    std::vector<Tri> tris;
+    const int corners[2][3][2] = {{{0, 0}, {1, 0}, {1, 1}}, {{0, 0}, {0, 1}, {1, 1}}};
+    for (int ob = 0; ob < 2; ++ob)
+        for (int oc = 0; oc < 2; ++oc)
+            for (int t = 0; t < 2; ++t) {
+                int loc = -1;
+                for (int k = 0; k < 3; ++k)
+                    if (corners[t][k][0] == ob && corners[t][k][1] == oc) loc = k;
+                if (loc < 0) continue;
+                Tri tr;
+                for (int k = 0; k < 3; ++k) {
+                    tr.dv[k][0] = corners[t][k][0] - ob;
+                    tr.dv[k][1] = corners[t][k][1] - oc;
+                }
+                tr.loc = loc;
+                tr.ob = ob;
+                tr.oc = oc;
+                tris.push_back(tr);
+            }
+    if ((int)tris.size() != kTris) throw Error(RTE_E_INTERNAL, "face star size");
+    auto fill_tri = [&](const Rule &r, std::vector<double> &out) {
+        out.assign((size_t)kTris * r.nq * 4, 0.0);
+        for (int t = 0; t < kTris; ++t)
+            for (int q = 0; q < r.nq; ++q) {
+                double *e = &out[((size_t)t * r.nq + q) * 4];
+                const double *b = &r.p[(size_t)q * 3];
+                for (int a = 0; a < 2; ++a) {
+                    double s = 0;
+                    for (int k = 0; k < 3; ++k) s += b[k] * tris[t].dv[k][a];
+                    e[a] = s;
+                }
+                e[2] = r.w[q] * b[tris[t].loc];
+                e[3] = 0;
+            }
+    };
+    fill_tri(t_far, S.tri_far);
+    fill_tri(t_near, S.tri_near);
+    for (auto &t : tris) {
+        S.tri_meta.push_back(t.ob);
+        S.tri_meta.push_back(t.oc);
+    }
+    return S;
+}
+
+const StencilHost &stencil_host() {
+    static std::once_flag f;
+    static StencilHost S;
+    std::call_once(f, [] { S = make_stencil(); });
+    return S;
+}
+
+namespace {
+template <typename T>
+const T *upload_forever(const std::vector<double> &v) {
+    std::vector<T> c(v.begin(), v.end());
+    void *p = nullptr;
+    HIP_CHECK(hipMalloc(&p, c.size() * sizeof(T)));
+    HIP_CHECK(hipMemcpy(p, c.data(), c.size() * sizeof(T), hipMemcpyHostToDevice));
+    return static_cast<const T *>(p);
+}
+const int *upload_ints(const std::vector<int> &v) {
+    void *p = nullptr;
+    HIP_CHECK(hipMalloc(&p, v.size() * sizeof(int)));
+    HIP_CHECK(hipMemcpy(p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice));
+    return static_cast<const int *>(p);
+}
+}  // namespace
+
+// One copy per device, kept for the life of the process.
+const StencilBuffers &stencil_device() {
+    static std::mutex mu;
+    static std::map<int, StencilBuffers> per_dev;
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = per_dev.find(dev);
+    if (it != per_dev.end()) return it->second;
+    const StencilHost &H = stencil_host();
+    StencilBuffers B;
+    const int *tm = upload_ints(H.tet_meta);
+    const int *rm = upload_ints(H.tri_meta);
+    B.d = {upload_forever<double>(H.vol_far), upload_forever<double>(H.vol_near),
+           upload_forever<double>(H.tri_far), upload_forever<double>(H.tri_near),
+           H.nq_vol_far, H.nq_vol_near, H.nq_tri_far, H.nq_tri_near, tm, rm};
+    B.f = {upload_forever<float>(H.vol_far), upload_forever<float>(H.vol_near),
+           upload_forever<float>(H.tri_far), upload_forever<float>(H.tri_near),
+           H.nq_vol_far, H.nq_vol_near, H.nq_tri_far, H.nq_tri_near, tm, rm};
+    return per_dev.emplace(dev, B).first->second;
+}
+
+void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
+    for (int a = 0; a < 3; ++a) {
+        RTE_REQUIRE(d.n[a] >= 2, "mesh: every axis needs at least 2 vertices");
+        RTE_REQUIRE(d.n[a] <= (1 << 20), "mesh: axis too long");
+        RTE_REQUIRE(std::isfinite(d.lo[a]) && std::isfinite(d.hi[a]) && d.lo[a] < d.hi[a],
+                    "mesh: need finite lo < hi on every axis");
+    }
+    RTE_REQUIRE(d.reflect_axis >= -1 && d.reflect_axis <= 2, "mesh: reflect_axis must be -1, 0, 1 or 2");
+    RTE_REQUIRE(d.reflect_side == 0 || d.reflect_side == 1, "mesh: reflect_side must be 0 or 1");
+    RTE_REQUIRE(d.reflect_axis < 0 || (std::isfinite(d.R) && d.R >= 0.0 && d.R <= 1.0),
+                "mesh: R must lie in [0, 1]");
+    RTE_REQUIRE(d.emit_faces < 64u, "mesh: emit_faces has 6 bits");
+    if (d.reflect_axis >= 0)
+        RTE_REQUIRE(!((d.emit_faces >> (2 * d.reflect_axis + d.reflect_side)) & 1u),
+                    "mesh: the reflective face cannot also emit");
+    int64_t N = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    RTE_REQUIRE(N < (int64_t)1 << 31, "mesh: more than 2^31 vertices");
+    M.desc = d;
+    M.N = N;
+    for (int a = 0; a < 3; ++a) M.h[a] = (d.hi[a] - d.lo[a]) / (d.n[a] - 1);
+    M.emitting.clear();
+    for (int64_t v = 0; v < N; ++v) {
+        int idx[3] = {(int)(v / ((int64_t)d.n[1] * d.n[2])), (int)((v / d.n[2]) % d.n[1]), (int)(v % d.n[2])};
+        bool on = false;
+        for (int f = 0; f < 6; ++f)
+            if ((d.emit_faces >> f) & 1u) on |= idx[f / 2] == ((f & 1) ? d.n[f / 2] - 1 : 0);
+        if (on) M.emitting.push_back(v);
+    }
+    M.L = (int64_t)M.emitting.size();
+    GridDev &g = M.dev;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = d.n[a];
+        g.lo[a] = d.lo[a];
+        g.h[a] = M.h[a];
+    }
+    g.stride[0] = d.n[1] * d.n[2];
+    g.stride[1] = d.n[2];
+    g.stride[2] = 1;
+    g.wall_axis = (d.reflect_axis >= 0 && d.R > 0.0) ? d.reflect_axis : -1;
+    g.wall_side = d.reflect_side;
+    g.R = d.reflect_axis >= 0 ? d.R : 0.0;
+    g.emit_faces = d.emit_faces;
+    const double four_pi = 4.0 * M_PI;
+    g.vol_scale = M.h[0] * M.h[1] * M.h[2] / 6.0 / four_pi;
+    g.area_scale[0] = 0.5 * M.h[1] * M.h[2] / four_pi;
+    g.area_scale[1] = 0.5 * M.h[0] * M.h[2] / four_pi;
+    g.area_scale[2] = 0.5 * M.h[0] * M.h[1] / four_pi;
+}
+
+}  // namespace rte

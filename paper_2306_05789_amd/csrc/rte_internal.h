@@ -1,0 +1,226 @@
+// Internal declarations of the rte library (host C++ and HIP device code).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "rte.h"
+
+namespace rte {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    rte_status_t code;
+    Error(rte_status_t c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define RTE_REQUIRE(cond, msg)                                                          \
+    do {                                                                                \
+        if (!(cond)) throw ::rte::Error(RTE_E_INVALID_ARG, std::string(msg));           \
+    } while (0)
+
+#define HIP_CHECK(expr)                                                                 \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::rte::Error(e_ == hipErrorOutOfMemory ? RTE_E_OUT_OF_MEMORY : RTE_E_DEVICE, \
+                               std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+#define HIP_LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
+
+// ---------------------------------------------------------------- quadrature rules
+// Symmetric simplex rules obtained by solving their moment equations
+// (quadrule.cpp).  Points are barycentric ([nq][nvert]), weights sum to 1.
+struct Rule {
+    int nvert = 0, nq = 0, degree = 0;
+    std::vector<double> p, w;
+};
+const Rule &tet_rule(int degree);   // 2 (4 points) or 5 (14 points)
+const Rule &tri_rule(int degree);   // 2 (3 points) or 5 (7 points)
+
+// ---------------------------------------------------------------- device geometry
+constexpr int kNearCheb = 2;        // near rule iff grid Chebyshev distance <= 2
+constexpr int kTets = 24;           // Kuhn tetrahedra around an interior vertex
+constexpr int kTris = 6;            // boundary triangles around a face vertex
+
+struct GridDev {
+    int n[3];
+    int stride[3];          // natural-order strides: n1*n2, n2, 1
+    double lo[3], h[3];
+    int wall_axis;          // -1: none
+    int wall_side;
+    double R;
+    unsigned emit_faces;
+    double vol_scale;       // |tet| / (4 pi)
+    double area_scale[3];   // |triangle| / (4 pi) for faces normal to axis a
+};
+
+// Stencil tables on the device, one set per precision (T = double or float).
+// Volume, per rule: [kTets][nq][8] = offset (3, grid units, from the source
+// vertex), coef = w_q * lambda_j(y_q), barycentrics b0..b3 of the tet vertices.
+// Surface, per rule: [kTris][nq][4] = offset along the face's two axes (grid
+// units), coef = w_q * lambda_l(y_q), pad.
+template <typename T>
+struct StencilDev {
+    const T *vol_far, *vol_near, *tri_far, *tri_near;
+    int nq_vol_far, nq_vol_near, nq_tri_far, nq_tri_near;
+    const int *tet_meta;    // [kTets][5]: 4 neighbour slots (0..26 of the 3x3x3 block), cell corner bits
+    const int *tri_meta;    // [kTris][2]: square offset bits along the face axes (b, c)
+};
+
+// ---------------------------------------------------------------- mesh
+struct Mesh {
+    rte_mesh_desc_t desc{};
+    int64_t N = 0, L = 0;
+    double h[3] = {0, 0, 0};
+    std::vector<int64_t> emitting;   // natural ids, ascending
+    GridDev dev{};
+    std::vector<double> positions() const;            // [N][3]
+    std::vector<double> emitting_positions() const;   // [L][3]
+};
+
+// Host copies of the stencil tables (built once per process from the rules).
+struct StencilHost {
+    std::vector<double> vol_far, vol_near, tri_far, tri_near;
+    int nq_vol_far = 0, nq_vol_near = 0, nq_tri_far = 0, nq_tri_near = 0;
+    std::vector<int> tet_meta, tri_meta;
+};
+const StencilHost &stencil_host();
+
+// Per-device uploaded copies.
+struct StencilBuffers {
+    StencilDev<double> d;
+    StencilDev<float> f;
+};
+const StencilBuffers &stencil_device();   // uploads on first use on the current device
+
+// ---------------------------------------------------------------- trees (htree.cpp)
+struct ClusterNode {
+    int64_t start, stop;
+    double bmin[3], bmax[3];
+    int child[2] = {-1, -1};
+};
+
+struct ClusterTree {
+    std::vector<int64_t> perm;        // cluster position -> caller's point index
+    std::vector<ClusterNode> nodes;   // nodes[0] is the root
+    std::vector<int> leaves;          // node ids of the leaves in order
+};
+
+ClusterTree build_cluster_tree(const std::vector<double> &pts, int leaf_size);
+
+struct Block {
+    int64_t t0, t1, s0, s1;
+};
+
+struct Plan {
+    rte_hmat_opts_t opts{};
+    ClusterTree tgt, src;
+    std::vector<int64_t> tgt_nat, src_nat;   // cluster position -> natural vertex id
+    std::vector<Block> dense, lowrank;
+    std::vector<std::pair<int64_t, int64_t>> tgt_leaves;   // [start, stop) of target leaves
+};
+
+std::unique_ptr<Plan> build_plan(const Mesh &m, const rte_hmat_opts_t &opts);
+
+// ---------------------------------------------------------------- device memory helper
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t b) { alloc(b); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t b) {
+        release();
+        if (b) HIP_CHECK(hipMalloc(&p, b));
+        bytes = b;
+    }
+    void release() noexcept {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+template <typename T>
+DevBuf upload(const std::vector<T> &v, hipStream_t s) {
+    DevBuf b(v.size() * sizeof(T));
+    if (!v.empty()) {
+        HIP_CHECK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    return b;
+}
+
+// ---------------------------------------------------------------- H-matrix storage
+// Dense leaves are stored column-major (for each source column, the block's
+// rows contiguous); a low-rank block as U^T [rank][m] and V^T [rank][n], so
+// every stream the matvec reads is contiguous along the lanes.  Mixed
+// precision keeps the factors as BF16 hi and lo parts with one FP32 scale per
+// block (value = scale * (hi + lo)); dense leaves are FP32 there.
+struct BandStore {
+    std::vector<DevBuf> bufs;               // owning storage chunks
+    std::vector<Block> dense_blocks;        // plan dense leaves, then ACA fallbacks
+    std::vector<const void *> dense_ptr;    // per dense block
+    std::vector<int32_t> rank;              // per plan LR block; -1 = stored dense (fallback)
+    std::vector<const void *> U, V;         // per plan LR block (nullptr for fallbacks)
+    std::vector<const void *> Ulo, Vlo;     // mixed precision: BF16 lo parts
+    std::vector<float> scale;               // mixed precision: per LR block scale
+    int64_t bytes = 0, dense_entries = 0, lr_entries = 0, evaluated = 0;
+};
+
+struct MatvecPlan;   // device work lists (hmatvec.hip)
+
+struct HMat {
+    const Mesh *mesh = nullptr;     // not owned: the mesh must outlive the matrix
+    std::unique_ptr<Plan> plan;
+    int n_bands = 0;
+    int precision = RTE_FP64;
+    int kind = RTE_VOLUME;
+    std::vector<BandStore> bands;
+    DevBuf tgt_nat, src_nat;        // int64: cluster position -> natural id (surface sources: vertex ids)
+    DevBuf src_pos;                 // int64: cluster position -> position in the caller's source vector
+    DevBuf kappa_c;                 // FP64 [n_bands][N_tgt] kappa at the targets, cluster order
+    std::vector<std::unique_ptr<MatvecPlan>> mv;   // per band
+    rte_hmat_stats_t stats{};
+    int device = 0;
+    HMat();
+    ~HMat();
+};
+
+// ---------------------------------------------------------------- entry points implemented in .hip files
+void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, const int64_t *rows,
+                    const int64_t *cols, double *out, int precision, hipStream_t s);
+void assemble_band(HMat &H, int band, const double *kappa_band, hipStream_t s);
+void matvec_build(HMat &H, int band, hipStream_t s);
+void matvec_launch(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
+                   hipStream_t s);
+// Same with a caller-provided workspace of nrhs * matvec_ktot(H, band) doubles; does not synchronise.
+void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
+                      double *tbuf, hipStream_t s);
+int64_t matvec_ktot(const HMat &H, int band);
+void permute_gather(const int64_t *perm, int64_t n, int nrhs, int64_t ld_in, int64_t ld_out, const double *in,
+                    double *out, hipStream_t s);
+void permute_scatter(const int64_t *perm, int64_t n, int nrhs, int64_t ld_in, int64_t ld_out, const double *in,
+                     double *out, hipStream_t s);
+rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_desc_t &d,
+                               double *T_out, double *J_out, rte_solve_stats_t *st, hipStream_t s);
+
+}  // namespace rte
+
+struct rte_mesh { rte::Mesh m; };
+struct rte_plan { std::unique_ptr<rte::Plan> p; };
+struct rte_hmat { rte::HMat h; };

@@ -1,0 +1,307 @@
+// The monotone fixed point (Algorithm of Section "Fixed Point Iterations",
+// eq. algo) on the GPU, with J^0 = 0:
+//   S_b   = (1 - a_b) B_{nu_b}(T) + a_b J_b              (collocated source, eq. eqS / P1)
+//   J_b  <- S^E_b + G_b S_b,   S^E_b = S_hat_b Q_b,  Q_b = B_{nu_b}(T_wall)
+//   T     : per vertex, root of sum_b w_b kappa_b (1 - a_b)(J_b - B_{nu_b}(T)) = 0
+// The temperature root is a safeguarded FP64 Newton iteration (the paper uses
+// Newton); in the grey case (eq. grey) B(T) = sigma T^4, sigma = pi^4/15, and
+// T = (J/sigma)^{1/4}.  Rescaled Planck function B_nu(T) = nu^3/(exp(nu/T)-1).
+// All vectors live in the cluster order of the volume H-matrix; the
+// iteration stops when max over bands and right-hand sides of
+// ||J^{k+1} - J^k||_2 / ||J^{k+1}||_2 <= tol.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace rte {
+
+namespace {
+
+constexpr double kSigma = 6.493939402266829;   // pi^4 / 15
+
+__device__ __forceinline__ double planck(double nu, double T) {
+    if (!(T > 0.0)) return 0.0;
+    const double x = nu / T;
+    if (x > 700.0) return 0.0;
+    return nu * nu * nu / expm1(x);
+}
+
+// B and dB/dT
+__device__ __forceinline__ void planck_d(double nu, double T, double &B, double &dB) {
+    B = 0.0;
+    dB = 0.0;
+    if (!(T > 0.0)) return;
+    const double x = nu / T;
+    if (x > 700.0) return;
+    const double e = expm1(x);
+    B = nu * nu * nu / e;
+    dB = B * ((e + 1.0) / e) * (x / T);
+}
+
+struct BandParams {
+    int nb;
+    int grey;
+    const double *nu;   // device [nb]
+    const double *w;    // device [nb]
+    const double *a;    // device [nb]
+};
+
+__global__ void k_emission(BandParams bp, const double *__restrict__ Tw, int64_t L, int nrhs,
+                           double *__restrict__ Q) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = L * nrhs;
+    if (k >= tot) return;
+    const double T = Tw[k];
+    for (int b = 0; b < bp.nb; ++b)
+        Q[(int64_t)b * tot + k] = bp.grey ? kSigma * (T * T) * (T * T) : planck(bp.nu[b], T);
+}
+
+__global__ void k_source(BandParams bp, const double *__restrict__ T, const double *__restrict__ J, int64_t N,
+                         int nrhs, double *__restrict__ S) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = N * nrhs;
+    if (k >= tot) return;
+    const double t = T[k];
+    for (int b = 0; b < bp.nb; ++b) {
+        const int64_t o = (int64_t)b * tot + k;
+        const double ab = bp.a[b];
+        const double e = bp.grey ? kSigma * (t * t) * (t * t) : planck(bp.nu[b], t);
+        S[o] = (1.0 - ab) * e + (ab != 0.0 ? ab * J[o] : 0.0);
+    }
+}
+
+// Partial sums of ||Jn - J||^2 and ||Jn||^2 per (band, rhs) vector; fixed
+// assignment of elements to blocks, reduced in a fixed order by k_resid_final.
+constexpr int kResidBlocks = 64;
+
+__global__ __launch_bounds__(256) void k_resid_partial(const double *__restrict__ J, const double *__restrict__ Jn,
+                                                       int64_t N, double *__restrict__ part) {
+    __shared__ double s1[4], s2[4];
+    const int vec = blockIdx.y;
+    const double *a = J + (int64_t)vec * N, *b = Jn + (int64_t)vec * N;
+    double d2 = 0.0, n2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)kResidBlocks * 256) {
+        const double d = b[i] - a[i];
+        d2 += d * d;
+        n2 += b[i] * b[i];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        d2 += __shfl_xor(d2, o, 64);
+        n2 += __shfl_xor(n2, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { s1[wid] = d2; s2[wid] = n2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[((int64_t)vec * kResidBlocks + blockIdx.x) * 2 + 0] = ((s1[0] + s1[1]) + s1[2]) + s1[3];
+        part[((int64_t)vec * kResidBlocks + blockIdx.x) * 2 + 1] = ((s2[0] + s2[1]) + s2[2]) + s2[3];
+    }
+}
+
+__global__ void k_resid_final(const double *__restrict__ part, int nvec, double *__restrict__ out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvec) return;
+    double d2 = 0.0, n2 = 0.0;
+    for (int b = 0; b < kResidBlocks; ++b) {
+        d2 += part[((int64_t)v * kResidBlocks + b) * 2 + 0];
+        n2 += part[((int64_t)v * kResidBlocks + b) * 2 + 1];
+    }
+    out[2 * v] = d2;
+    out[2 * v + 1] = n2;
+}
+
+// Per vertex and right-hand side: T solving sum_b c_b (J_b - B_b(T)) = 0,
+// c_b = w_b kappa_b (1 - a_b).  Bracketed Newton: f decreases in T,
+// f(0) = sum c_b J_b > 0; a step leaving the bracket is replaced by bisection.
+__global__ void k_newton(BandParams bp, const double *__restrict__ J, const double *__restrict__ kap, int64_t N,
+                         int nrhs, double *__restrict__ T, unsigned long long *__restrict__ viol) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = N * nrhs;
+    if (k >= tot) return;
+    const int64_t i = k % N;
+    const double Told = T[k];
+    double Tn;
+    if (bp.grey) {
+        const double j = J[k];
+        Tn = j > 0.0 ? sqrt(sqrt(j / kSigma)) : 0.0;
+    } else {
+        double f0 = 0.0;
+        for (int b = 0; b < bp.nb; ++b)
+            f0 += bp.w[b] * kap[(int64_t)b * N + i] * (1.0 - bp.a[b]) * J[(int64_t)b * tot + k];
+        if (!(f0 > 0.0)) {
+            Tn = 0.0;
+        } else {
+            auto f = [&](double t, double &df) {
+                double s = 0.0, d = 0.0;
+                for (int b = 0; b < bp.nb; ++b) {
+                    const double c = bp.w[b] * kap[(int64_t)b * N + i] * (1.0 - bp.a[b]);
+                    double B, dB;
+                    planck_d(bp.nu[b], t, B, dB);
+                    s += c * (J[(int64_t)b * tot + k] - B);
+                    d -= c * dB;
+                }
+                df = d;
+                return s;
+            };
+            double lo = 0.0, hi = Told > 0.0 ? 2.0 * Told : 1.0, d;
+            for (int it = 0; it < 200 && f(hi, d) > 0.0; ++it) { lo = hi; hi *= 2.0; }
+            double x = (Told > lo && Told < hi) ? Told : 0.5 * (lo + hi);
+            for (int it = 0; it < 100; ++it) {
+                const double fx = f(x, d);
+                if (fx == 0.0) break;
+                if (fx > 0.0) lo = x; else hi = x;
+                double xn = (d < 0.0) ? x - fx / d : 0.5 * (lo + hi);
+                if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+                const double dx = fabs(xn - x);
+                x = xn;
+                if (dx <= 2.3e-16 * x || hi - lo <= 2.3e-16 * hi) break;
+            }
+            Tn = x;
+        }
+    }
+    if (Tn < Told) atomicAdd(viol, 1ull);
+    T[k] = Tn;
+}
+
+void check_desc(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_desc_t &d) {
+    RTE_REQUIRE(G.kind == RTE_VOLUME && S.kind == RTE_SURFACE, "solve: need a volume and a surface H-matrix");
+    RTE_REQUIRE(G.mesh == &m && S.mesh == &m, "solve: H-matrices were assembled on another mesh");
+    RTE_REQUIRE(d.n_bands >= 1 && d.n_bands <= 4096, "solve: n_bands out of range");
+    RTE_REQUIRE(G.n_bands == d.n_bands && S.n_bands == d.n_bands, "solve: band count differs from the matrices");
+    RTE_REQUIRE(!d.grey || d.n_bands == 1, "solve: the grey formulation has one band");
+    RTE_REQUIRE(d.nrhs >= 1 && d.nrhs <= 4096, "solve: nrhs out of range");
+    RTE_REQUIRE(d.T_wall != nullptr, "solve: T_wall is required");
+    RTE_REQUIRE(d.tol > 0.0 && std::isfinite(d.tol), "solve: tol must be > 0");
+    RTE_REQUIRE(d.max_iter >= 1, "solve: max_iter must be >= 1");
+    RTE_REQUIRE(d.precision == RTE_FP64 || d.precision == RTE_FP32 || d.precision == RTE_MIXED_BF16,
+                "solve: unknown precision");
+    if (!d.grey) {
+        RTE_REQUIRE(d.nu != nullptr, "solve: nu is required for the band formulation");
+        for (int b = 0; b < d.n_bands; ++b) {
+            RTE_REQUIRE(std::isfinite(d.nu[b]) && d.nu[b] > 0, "solve: nu must be positive");
+            if (b) RTE_REQUIRE(d.nu[b] > d.nu[b - 1], "solve: nu must increase");
+            if (d.w) RTE_REQUIRE(std::isfinite(d.w[b]) && d.w[b] >= 0, "solve: w must be >= 0");
+        }
+    }
+    if (d.a)
+        for (int b = 0; b < d.n_bands; ++b)
+            RTE_REQUIRE(std::isfinite(d.a[b]) && d.a[b] >= 0 && d.a[b] < 1, "solve: a must lie in [0, 1)");
+}
+
+}  // namespace
+
+rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_desc_t &d,
+                               double *T_out, double *J_out, rte_solve_stats_t *st, hipStream_t s) {
+    check_desc(m, G, S, d);
+    const auto t_start = std::chrono::steady_clock::now();
+    const int nb = d.n_bands, nr = d.nrhs;
+    const int64_t N = m.N, L = m.L;
+    // band constants
+    std::vector<double> nu(nb, 1.0), w(nb, 1.0), a(nb, 0.0);
+    if (!d.grey) {
+        for (int b = 0; b < nb; ++b) nu[b] = d.nu[b];
+        if (d.w) {
+            for (int b = 0; b < nb; ++b) w[b] = d.w[b];
+        } else if (nb > 1) {
+            // trapezoid weights on the sorted band frequencies, no tails
+            w[0] = 0.5 * (nu[1] - nu[0]);
+            w[nb - 1] = 0.5 * (nu[nb - 1] - nu[nb - 2]);
+            for (int b = 1; b + 1 < nb; ++b) w[b] = 0.5 * (nu[b + 1] - nu[b - 1]);
+        }
+    }
+    if (d.a)
+        for (int b = 0; b < nb; ++b) a[b] = d.a[b];
+    std::vector<double> consts;
+    consts.insert(consts.end(), nu.begin(), nu.end());
+    consts.insert(consts.end(), w.begin(), w.end());
+    consts.insert(consts.end(), a.begin(), a.end());
+    DevBuf dconst = upload(consts, s);
+    BandParams bp{nb, d.grey, dconst.as<double>(), dconst.as<double>() + nb, dconst.as<double>() + 2 * nb};
+
+    const int64_t vecN = N * nr;
+    DevBuf Tw(sizeof(double) * L * nr), Q(sizeof(double) * L * nr * nb), SE(sizeof(double) * vecN * nb),
+        Sv(sizeof(double) * vecN * nb), J(sizeof(double) * vecN * nb), Jn(sizeof(double) * vecN * nb),
+        T(sizeof(double) * vecN), part(sizeof(double) * 2 * kResidBlocks * nb * nr),
+        res(sizeof(double) * 2 * nb * nr), viol(sizeof(unsigned long long));
+    int64_t kt = 1;
+    for (int b = 0; b < nb; ++b) kt = std::max({kt, matvec_ktot(G, b), matvec_ktot(S, b)});
+    DevBuf tbuf(sizeof(double) * kt * nr);
+    const unsigned gN = (unsigned)((vecN + 255) / 256), gL = (unsigned)((L * nr + 255) / 256);
+
+    // boundary source: Q_b = B_b(T_wall) and S^E_b = S_hat_b Q_b
+    permute_gather(S.src_pos.as<int64_t>(), L, nr, L, L, d.T_wall, Tw.as<double>(), s);
+    k_emission<<<gL, 256, 0, s>>>(bp, Tw.as<double>(), L, nr, Q.as<double>());
+    HIP_LAUNCH_CHECK();
+    for (int b = 0; b < nb; ++b)
+        matvec_launch_ws(S, b, nr, Q.as<double>() + (int64_t)b * L * nr, SE.as<double>() + (int64_t)b * vecN,
+                         nullptr, tbuf.as<double>(), s);
+    if (d.T0) permute_gather(G.tgt_nat.as<int64_t>(), N, nr, N, N, d.T0, T.as<double>(), s);
+    else HIP_CHECK(hipMemsetAsync(T.p, 0, T.bytes, s));
+    HIP_CHECK(hipMemsetAsync(J.p, 0, J.bytes, s));
+    HIP_CHECK(hipMemsetAsync(viol.p, 0, viol.bytes, s));
+
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    float mv_ms = 0.0f;
+    std::vector<double> rv(2 * nb * nr);
+    double r = INFINITY;
+    int it = 0;
+    bool conv = false;
+    for (it = 1; it <= d.max_iter; ++it) {
+        k_source<<<gN, 256, 0, s>>>(bp, T.as<double>(), J.as<double>(), N, nr, Sv.as<double>());
+        HIP_LAUNCH_CHECK();
+        HIP_CHECK(hipEventRecord(e0, s));
+        for (int b = 0; b < nb; ++b)
+            matvec_launch_ws(G, b, nr, Sv.as<double>() + (int64_t)b * vecN, Jn.as<double>() + (int64_t)b * vecN,
+                             SE.as<double>() + (int64_t)b * vecN, tbuf.as<double>(), s);
+        HIP_CHECK(hipEventRecord(e1, s));
+        k_resid_partial<<<dim3(kResidBlocks, nb * nr), 256, 0, s>>>(J.as<double>(), Jn.as<double>(), N,
+                                                                     part.as<double>());
+        k_resid_final<<<(nb * nr + 63) / 64, 64, 0, s>>>(part.as<double>(), nb * nr, res.as<double>());
+        k_newton<<<gN, 256, 0, s>>>(bp, Jn.as<double>(), G.kappa_c.as<double>(), N, nr, T.as<double>(),
+                                    viol.as<unsigned long long>());
+        HIP_LAUNCH_CHECK();
+        std::swap(J, Jn);
+        HIP_CHECK(hipMemcpyAsync(rv.data(), res.p, sizeof(double) * rv.size(), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        float ms = 0.0f;
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        mv_ms += ms;
+        r = 0.0;
+        for (int v = 0; v < nb * nr; ++v) {
+            const double num = rv[2 * v], den = rv[2 * v + 1];
+            const double q = den > 0.0 ? std::sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+            r = std::max(r, q);
+        }
+        if (!std::isfinite(r)) break;
+        if (r <= d.tol) { conv = true; break; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (it > d.max_iter) it = d.max_iter;
+    if (T_out) permute_scatter(G.tgt_nat.as<int64_t>(), N, nr, N, N, T.as<double>(), T_out, s);
+    if (J_out)
+        for (int b = 0; b < nb; ++b)
+            // J_out is [nrhs][nb][N]: rhs stride nb*N, band offset b*N
+            permute_scatter(G.tgt_nat.as<int64_t>(), N, nr, N, (int64_t)nb * N, J.as<double>() + (int64_t)b * vecN,
+                            J_out + (int64_t)b * N, s);
+    unsigned long long nviol = 0;
+    HIP_CHECK(hipMemcpyAsync(&nviol, viol.p, sizeof(nviol), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (st) {
+        st->iterations = it;
+        st->outer_steps = 0;
+        st->residual = r;
+        st->monotone_violations = (int64_t)nviol;
+        st->ms_matvec = mv_ms;
+        st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (!std::isfinite(r)) throw Error(RTE_E_INTERNAL, "solve: the residual is not finite");
+    return conv ? RTE_OK : RTE_E_NOT_CONVERGED;
+}
+
+}  // namespace rte

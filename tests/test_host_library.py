@@ -1,0 +1,112 @@
+"""Host-side checks of librte.so that need no GPU: every symbol of include/rte.h
+is exported, the host cluster/block trees equal the oracle's exactly (index
+work is compared bit-exactly), and invalid arguments are rejected before any
+device work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.core import Grid
+from oracle.htree import block_tree, cluster_tree
+from paper_2306_05789_amd import rte
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported():
+    header = open(os.path.join(ROOT, "include", "rte.h")).read()
+    names = set(re.findall(r"\b(rte_[a-z_]+)\s*\(", header))
+    assert len(names) >= 15
+    lib = rte.load()
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(rte.SIGNATURES) == names
+
+
+def _oracle_plan(n, lo, hi, kind, emit, leaf, eta, dense=False):
+    g = Grid(n, lo, hi)
+    pts = g.positions()
+    tperm, troot = cluster_tree(pts, leaf)
+    if kind == rte.RTE_VOLUME:
+        sperm, sroot, snat = tperm, troot, tperm
+    else:
+        em = g.emitting_vertices(emit)
+        sperm, sroot = cluster_tree(pts[em], leaf)
+        snat = em[sperm]
+    d, l = block_tree(troot, sroot, eta if not dense else 0.0)
+    if dense:
+        d, l = d + l, []
+    return tperm, snat, d, l
+
+
+@pytest.mark.parametrize("n,hi,kind,emit,leaf", [
+    ((11, 11, 11), (1, 1, 1), rte.RTE_VOLUME, 1, 64),
+    ((21, 21, 21), (1, 1, 1), rte.RTE_VOLUME, 1, 64),
+    ((33, 17, 17), (2, 1, 1), rte.RTE_VOLUME, 1, 64),
+    ((17, 13, 9), (1.3, 1, 0.7), rte.RTE_VOLUME, 1, 32),
+    ((21, 21, 21), (1, 1, 1), rte.RTE_SURFACE, 63, 64),
+    ((33, 17, 17), (2, 1, 1), rte.RTE_SURFACE, 1, 64),
+])
+def test_host_trees_match_oracle_exactly(n, hi, kind, emit, leaf):
+    mesh = rte.rte_mesh_create(n, (0, 0, 0), hi, emit_faces=emit)
+    plan = rte.rte_plan_create(mesh, rte.hmat_opts(kind=kind, leaf_size=leaf, eta=2.0))
+    tp, sp, blocks = rte.rte_plan_export(plan)
+    rte.rte_plan_destroy(plan)
+    otp, osp, od, ol = _oracle_plan(n, (0, 0, 0), hi, kind, emit, leaf, 2.0)
+    assert np.array_equal(tp, otp)
+    assert np.array_equal(sp, osp)
+    dense = [tuple(b[:4]) for b in blocks if b[4] == 0]
+    low = [tuple(b[:4]) for b in blocks if b[4] == 1]
+    assert dense == [tuple(b) for b in od]
+    assert low == [tuple(b) for b in ol]
+
+
+def test_dense_option_keeps_every_block_dense():
+    mesh = rte.rte_mesh_create((9, 9, 9))
+    plan = rte.rte_plan_create(mesh, rte.hmat_opts(dense=True, leaf_size=64))
+    info = rte.rte_plan_info(plan)
+    assert info.n_lowrank == 0 and info.dense_entries == 729 * 729
+    rte.rte_plan_destroy(plan)
+
+
+def test_mesh_sizes_and_emitting_ids():
+    mesh = rte.rte_mesh_create((5, 4, 3), emit_faces=1 | 32)
+    g = Grid((5, 4, 3))
+    assert mesh.N == 60
+    assert np.array_equal(rte.rte_mesh_emitting_ids(mesh), g.emitting_vertices(1 | 32))
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(n=(1, 4, 4)), "at least 2"),
+    (dict(n=(4, 4, 4), hi=(0, 1, 1)), "lo < hi"),
+    (dict(n=(4, 4, 4), reflect_axis=3), "reflect_axis"),
+    (dict(n=(4, 4, 4), reflect_axis=2, R=1.5), "R must"),
+    (dict(n=(4, 4, 4), reflect_axis=0, reflect_side=0, R=0.5, emit_faces=1), "cannot also emit"),
+    (dict(n=(4, 4, 4), emit_faces=64), "6 bits"),
+])
+def test_mesh_validation(kw, frag):
+    with pytest.raises(rte.RteError) as e:
+        rte.rte_mesh_create(**kw)
+    assert e.value.status == rte.RTE_E_INVALID_ARG and frag in str(e.value)
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(leaf_size=0), "leaf_size"),
+    (dict(eta=-1.0), "eta"),
+    (dict(aca_eps=0.0), "aca_eps"),
+    (dict(precision=7), "precision"),
+    (dict(kind=5), "kind"),
+])
+def test_plan_validation(kw, frag):
+    mesh = rte.rte_mesh_create((4, 4, 4))
+    with pytest.raises(rte.RteError) as e:
+        rte.rte_plan_create(mesh, rte.hmat_opts(**kw))
+    assert frag in str(e.value)
+
+
+def test_surface_plan_needs_an_emitting_face():
+    mesh = rte.rte_mesh_create((4, 4, 4), emit_faces=0)
+    with pytest.raises(rte.RteError):
+        rte.rte_plan_create(mesh, rte.hmat_opts(kind=rte.RTE_SURFACE))
