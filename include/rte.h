@@ -149,7 +149,12 @@ typedef struct {
     double compression;                           /* 1 - stored entries / (N_tgt*N_src*bands) */
     int64_t bytes;                                /* device bytes of the stored operator */
     int64_t entries_evaluated;                    /* kernel entries computed during assembly */
-    double assemble_ms;
+    double assemble_ms;                           /* host wall time of the assembly call */
+    double aca_kernel_ms;                         /* HIP-event time of the ACA launches, summed */
+    int32_t aca_launches;
+    double fill_kernel_ms;                        /* HIP-event time of the dense-fill launches, summed */
+    int32_t fill_launches;
+    int64_t aca_entries;                          /* entries evaluated inside the ACA launches */
 } rte_hmat_stats_t;
 
 rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats);
@@ -157,10 +162,11 @@ rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats);
 /* Factors of admissible block `block` (0-based among admissible blocks, plan
  * order) of band `band`, copied to host FP64: U [m][rank] and V [n][rank],
  * rows in cluster order of the block's ranges; the block approximates rows
- * tgt_perm[t0..t1) x cols src_perm[s0..s1) as U V^T.  Pass NULL U/V to query
- * the rank only.  Synchronous. */
-rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, int32_t *rank,
-                                    double *U, double *V);
+ * tgt_perm[t0..t1) x cols src_perm[s0..s1) as U V^T.  rank, m and n are always
+ * written (rank -1: the block is stored dense); pass NULL U/V to query them,
+ * then buffers of m*rank and n*rank doubles.  Synchronous. */
+rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, int32_t *rank, int64_t *m,
+                                    int64_t *n, double *U, double *V);
 void rte_hmat_destroy(rte_hmat_t h);
 
 /* ------------------------------------------------------------------ fixed point

@@ -221,7 +221,9 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
         H.kappa_c.alloc(sizeof(double) * (size_t)m.N * n_bands);
         permute_gather(H.tgt_nat.as<int64_t>(), m.N, n_bands, m.N, m.N, kappa, H.kappa_c.as<double>(), s);
         H.bands.resize(n_bands);
-        int64_t evaluated = 0, bytes = 0, dense_e = 0, lr_e = 0, nfb = 0;
+        int64_t evaluated = 0, bytes = 0, dense_e = 0, lr_e = 0, nfb = 0, aca_e = 0;
+        double aca_ms = 0, fill_ms = 0;
+        int aca_l = 0, fill_l = 0;
         double wsum = 0, wr = 0;
         int maxr = 0;
         for (int b = 0; b < n_bands; ++b) {
@@ -229,6 +231,11 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
             matvec_build(H, b, s);
             const BandStore &B = H.bands[b];
             evaluated += B.evaluated;
+            aca_e += B.aca_entries;
+            aca_ms += B.aca_ms;
+            fill_ms += B.fill_ms;
+            aca_l += B.aca_launches;
+            fill_l += B.fill_launches;
             bytes += B.bytes;
             dense_e += B.dense_entries;
             lr_e += B.lr_entries;
@@ -257,6 +264,11 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
         st.compression = 1.0 - (double)(dense_e + lr_e) / ((double)st.n_tgt * st.n_src * n_bands);
         st.bytes = bytes;
         st.entries_evaluated = evaluated;
+        st.aca_entries = aca_e;
+        st.aca_kernel_ms = aca_ms;
+        st.aca_launches = aca_l;
+        st.fill_kernel_ms = fill_ms;
+        st.fill_launches = fill_l;
         st.assemble_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         *out = hm.release();
         return RTE_OK;
@@ -290,17 +302,20 @@ rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats) {
     });
 }
 
-rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, int32_t *rank, double *U, double *V) {
+rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, int32_t *rank, int64_t *mo,
+                                    int64_t *no, double *U, double *V) {
     return guard([&] {
-        RTE_REQUIRE(h && rank, "rte_hmat_block_factors: NULL argument");
+        RTE_REQUIRE(h && rank && mo && no, "rte_hmat_block_factors: NULL argument");
         const HMat &H = h->h;
         RTE_REQUIRE(band >= 0 && band < H.n_bands, "rte_hmat_block_factors: band out of range");
         RTE_REQUIRE(block >= 0 && block < (int64_t)H.plan->lowrank.size(), "rte_hmat_block_factors: block out of range");
         const BandStore &B = H.bands[band];
-        *rank = B.rank[block];
-        if (!U || !V || B.rank[block] <= 0) return RTE_OK;
         const Block &bl = H.plan->lowrank[block];
         const int64_t m = bl.t1 - bl.t0, n = bl.s1 - bl.s0, k = B.rank[block];
+        *rank = B.rank[block];
+        *mo = m;
+        *no = n;
+        if (!U || !V || k <= 0) return RTE_OK;
         std::vector<double> ut(m * k), vt(n * k);
         if (H.precision == RTE_FP64) {
             HIP_CHECK(hipMemcpy(ut.data(), B.U[block], sizeof(double) * m * k, hipMemcpyDeviceToHost));

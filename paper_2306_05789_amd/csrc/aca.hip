@@ -203,7 +203,8 @@ void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Bl
         for (int64_t f = 0; f < (int64_t)m * n; f += kFillChunk) tasks.push_back({p, b.t0, b.s0, m, n, f});
         off += (int64_t)m * n;
     }
-    dense_fill_launch<T>(*H.mesh, H.kind, kap, tasks, H.tgt_nat.as<int64_t>(), H.src_nat.as<int64_t>(), s);
+    B.fill_ms += dense_fill_launch<T>(*H.mesh, H.kind, kap, tasks, H.tgt_nat.as<int64_t>(), H.src_nat.as<int64_t>(), s);
+    B.fill_launches += 1;
     B.dense_entries += total;
     B.evaluated += total;
     B.bytes += (int64_t)buf.bytes;
@@ -253,6 +254,8 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
         }
         DevBuf Us(sizeof(T) * (size_t)uo), Vs(sizeof(T) * (size_t)vo), dr(sizeof(int) * tasks.size());
         DevBuf dt = upload(tasks, s);
+        EventTimer tm(s);
+        tm.start();
         if (H.kind == RTE_VOLUME)
             k_aca<T, RTE_VOLUME><<<(unsigned)tasks.size(), 256, 0, s>>>(c, dt.as<AcaTask>(), H.tgt_nat.as<int64_t>(),
                                                                     H.src_nat.as<int64_t>(), Us.as<T>(), Vs.as<T>(),
@@ -262,6 +265,9 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
                                                                      H.src_nat.as<int64_t>(), Us.as<T>(), Vs.as<T>(),
                                                                      dr.as<int>(), eps);
         HIP_LAUNCH_CHECK();
+        tm.stop();
+        B.aca_ms += tm.ms();
+        B.aca_launches += 1;
         std::vector<int> rk(tasks.size());
         HIP_CHECK(hipMemcpyAsync(rk.data(), dr.p, sizeof(int) * rk.size(), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
@@ -269,7 +275,9 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
         for (size_t t = 0; t < tasks.size(); ++t) {
             if (rk[t] > 0) total += (int64_t)rk[t] * (tasks[t].m + tasks[t].n);
             // entries evaluated: one row and one column per rank step (zero rows aside)
-            B.evaluated += (int64_t)std::max(rk[t], tasks[t].kcap * (rk[t] < 0)) * (tasks[t].m + tasks[t].n);
+            const int64_t ev = (int64_t)std::max(rk[t], tasks[t].kcap * (rk[t] < 0)) * (tasks[t].m + tasks[t].n);
+            B.evaluated += ev;
+            B.aca_entries += ev;
         }
         DevBuf out(sizeof(T) * (size_t)total);
         std::vector<CompactTask> ct;

@@ -75,20 +75,25 @@ void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, con
 }
 
 template <typename T>
-void dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
-                       const int64_t *tgt_nat, const int64_t *src_nat, hipStream_t s) {
-    if (tasks.empty()) return;
+double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
+                         const int64_t *tgt_nat, const int64_t *src_nat, hipStream_t s) {
+    if (tasks.empty()) return 0.0;
     DevBuf dt = upload(tasks, s);
     auto c = make_ctx<T>(m, kappa);
     const unsigned grid = (unsigned)tasks.size();
+    EventTimer tm(s);
+    tm.start();
     if (kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME><<<grid, 256, 0, s>>>(c, dt.as<FillTask>(), tgt_nat, src_nat);
     else k_dense_fill<T, RTE_SURFACE><<<grid, 256, 0, s>>>(c, dt.as<FillTask>(), tgt_nat, src_nat);
     HIP_LAUNCH_CHECK();
+    tm.stop();
+    const double ms = tm.ms();
     HIP_CHECK(hipStreamSynchronize(s));   // the task list is released on return
+    return ms;
 }
-template void dense_fill_launch<double>(const Mesh &, int, const double *, const std::vector<FillTask> &,
-                                        const int64_t *, const int64_t *, hipStream_t);
-template void dense_fill_launch<float>(const Mesh &, int, const float *, const std::vector<FillTask> &,
-                                       const int64_t *, const int64_t *, hipStream_t);
+template double dense_fill_launch<double>(const Mesh &, int, const double *, const std::vector<FillTask> &,
+                                          const int64_t *, const int64_t *, hipStream_t);
+template double dense_fill_launch<float>(const Mesh &, int, const float *, const std::vector<FillTask> &,
+                                         const int64_t *, const int64_t *, hipStream_t);
 
 }  // namespace rte

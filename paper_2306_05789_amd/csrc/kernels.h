@@ -24,11 +24,34 @@ struct AcaTask {
     int64_t uoff, voff;   // scratch offsets (elements) of U^T [kcap][m] and V^T [kcap][n]
 };
 
+// Times the device work enqueued on `s` between start() and stop() with HIP events.
+struct EventTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit EventTimer(hipStream_t st) : s(st) {
+        HIP_CHECK(hipEventCreate(&a));
+        HIP_CHECK(hipEventCreate(&b));
+    }
+    ~EventTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    void start() { HIP_CHECK(hipEventRecord(a, s)); }
+    void stop() { HIP_CHECK(hipEventRecord(b, s)); }
+    double ms() {   // after stop(); synchronises on the stop event
+        HIP_CHECK(hipEventSynchronize(b));
+        float v = 0.0f;
+        HIP_CHECK(hipEventElapsedTime(&v, a, b));
+        return (double)v;
+    }
+};
+
 template <typename T> struct EntryCtx;
 template <typename T> EntryCtx<T> make_ctx(const Mesh &m, const T *kappa);
 void to_float(const double *in, float *out, int64_t n, hipStream_t s);
+// returns the HIP-event time of the fill launch in ms
 template <typename T>
-void dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
-                       const int64_t *tgt_nat, const int64_t *src_nat, hipStream_t s);
+double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
+                         const int64_t *tgt_nat, const int64_t *src_nat, hipStream_t s);
 
 }  // namespace rte

@@ -179,7 +179,9 @@ struct BandStore {
     std::vector<const void *> U, V;         // per plan LR block (nullptr for fallbacks)
     std::vector<const void *> Ulo, Vlo;     // mixed precision: BF16 lo parts
     std::vector<float> scale;               // mixed precision: per LR block scale
-    int64_t bytes = 0, dense_entries = 0, lr_entries = 0, evaluated = 0;
+    int64_t bytes = 0, dense_entries = 0, lr_entries = 0, evaluated = 0, aca_entries = 0;
+    double aca_ms = 0.0, fill_ms = 0.0;   // HIP-event kernel times
+    int aca_launches = 0, fill_launches = 0;
 };
 
 struct MatvecPlan;   // device work lists (hmatvec.hip)

@@ -47,7 +47,9 @@ class HmatStats(C.Structure):
                 ("n_dense", C.c_int64), ("n_lowrank", C.c_int64), ("n_fallback_dense", C.c_int64),
                 ("dense_entries", C.c_int64), ("lowrank_entries", C.c_int64), ("max_rank", C.c_int32),
                 ("mean_rank", C.c_double), ("compression", C.c_double), ("bytes", C.c_int64),
-                ("entries_evaluated", C.c_int64), ("assemble_ms", C.c_double)]
+                ("entries_evaluated", C.c_int64), ("assemble_ms", C.c_double),
+                ("aca_kernel_ms", C.c_double), ("aca_launches", C.c_int32),
+                ("fill_kernel_ms", C.c_double), ("fill_launches", C.c_int32), ("aca_entries", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,7 +87,7 @@ SIGNATURES = {
     "rte_hmat_matvec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_hmat_stats": (C.c_int, [C.c_void_p, C.POINTER(HmatStats)]),
     "rte_hmat_block_factors": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
-                                         C.c_void_p, C.c_void_p]),
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
     "rte_hmat_destroy": (None, [C.c_void_p]),
     "rte_fixed_point_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveDesc),
                                         C.c_void_p, C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),
@@ -245,15 +247,18 @@ def rte_hmat_stats(hmat: HMat) -> dict:
     return st.as_dict()
 
 
-def rte_hmat_block_factors(hmat: HMat, band: int, block: int, m: int, n: int):
+def rte_hmat_block_factors(hmat: HMat, band: int, block: int, factors: bool = True):
+    """(rank, U [m,rank], V [n,rank]) of an admissible block; U, V are None when
+    factors is False or the block is stored dense (rank -1)."""
     import numpy as np
-    k = C.c_int32()
-    _check(load().rte_hmat_block_factors(hmat.handle, int(band), int(block), C.byref(k), None, None))
-    if k.value <= 0:
+    k, m, n = C.c_int32(), C.c_int64(), C.c_int64()
+    _check(load().rte_hmat_block_factors(hmat.handle, int(band), int(block), C.byref(k), C.byref(m), C.byref(n),
+                                         None, None))
+    if not factors or k.value <= 0:
         return k.value, None, None
-    U = np.empty((m, k.value))
-    V = np.empty((n, k.value))
-    _check(_lib.rte_hmat_block_factors(hmat.handle, int(band), int(block), C.byref(k),
+    U = np.empty((m.value, k.value))
+    V = np.empty((n.value, k.value))
+    _check(_lib.rte_hmat_block_factors(hmat.handle, int(band), int(block), C.byref(k), C.byref(m), C.byref(n),
                                        U.ctypes.data_as(C.c_void_p), V.ctypes.data_as(C.c_void_p)))
     return k.value, U, V
 
