@@ -150,8 +150,10 @@ typedef struct {
     int64_t bytes;                                /* device bytes of the stored operator */
     int64_t entries_evaluated;                    /* kernel entries computed during assembly */
     double assemble_ms;                           /* host wall time of the assembly call */
-    double aca_kernel_ms;                         /* HIP-event time of the ACA launches, summed */
-    int32_t aca_launches;
+    double aca_kernel_ms;                         /* HIP-event time of the whole ACA (all rank steps) */
+    int32_t aca_launches;                         /* ACA batches */
+    double aca_entry_ms;                          /* HIP-event time of the ACA row/column entry launches */
+    int32_t aca_entry_launches;
     double fill_kernel_ms;                        /* HIP-event time of the dense-fill launches, summed */
     int32_t fill_launches;
     int64_t aca_entries;                          /* entries evaluated inside the ACA launches */

@@ -222,8 +222,8 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
         permute_gather(H.tgt_nat.as<int64_t>(), m.N, n_bands, m.N, m.N, kappa, H.kappa_c.as<double>(), s);
         H.bands.resize(n_bands);
         int64_t evaluated = 0, bytes = 0, dense_e = 0, lr_e = 0, nfb = 0, aca_e = 0;
-        double aca_ms = 0, fill_ms = 0;
-        int aca_l = 0, fill_l = 0;
+        double aca_ms = 0, fill_ms = 0, aca_entry_ms = 0;
+        int aca_l = 0, fill_l = 0, aca_entry_l = 0;
         double wsum = 0, wr = 0;
         int maxr = 0;
         for (int b = 0; b < n_bands; ++b) {
@@ -233,6 +233,8 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
             evaluated += B.evaluated;
             aca_e += B.aca_entries;
             aca_ms += B.aca_ms;
+            aca_entry_ms += B.aca_entry_ms;
+            aca_entry_l += B.aca_entry_launches;
             fill_ms += B.fill_ms;
             aca_l += B.aca_launches;
             fill_l += B.fill_launches;
@@ -267,6 +269,8 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
         st.aca_entries = aca_e;
         st.aca_kernel_ms = aca_ms;
         st.aca_launches = aca_l;
+        st.aca_entry_ms = aca_entry_ms;
+        st.aca_entry_launches = aca_entry_l;
         st.fill_kernel_ms = fill_ms;
         st.fill_launches = fill_l;
         st.assemble_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -329,7 +333,7 @@ rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, i
         }
         for (int64_t l = 0; l < k; ++l) {
             for (int64_t i = 0; i < m; ++i) U[i * k + l] = ut[l * m + i];
-            for (int64_t j = 0; j < n; ++j) V[j * k + l] = vt[l * n + j];
+            for (int64_t j = 0; j < n; ++j) V[j * k + l] = vt[j * k + l];   // stored row-major [n][k]
         }
         return RTE_OK;
     });

@@ -3,8 +3,8 @@
 // and r columns of a block are computed, r being the rank reached for the
 // relative Frobenius tolerance eps).
 //
-// One admissible block per workgroup of 256 lanes.  Rank step k:
-//   1. residual row  r_j = A(i*, j) - sum_l U_l(i*) V_l(j)       (entries in parallel)
+// Rank step k of a block A (m x n), with U_l, V_l the previous factors:
+//   1. residual row  r_j = A(i*, j) - sum_l U_l(i*) V_l(j)
 //   2. pivot j* = argmax |r_j| (ties: lowest j), v_k = r / r_{j*}
 //   3. residual column u_k(i) = A(i, j*) - sum_l V_l(j*) U_l(i)
 //   4. ||S_k||^2 += ||u_k||^2 ||v_k||^2 + 2 sum_l (u_l.u_k)(v_l.v_k)
@@ -12,8 +12,14 @@
 // The first row is local row 0.  A zero residual row is marked used and the
 // lowest unused row is taken instead.  A block that reaches
 // k = floor(m n / (m + n)) without converging is stored dense.
-// Reductions go through wavefront shuffles and one LDS stage in a fixed
-// order, so results are bitwise reproducible.
+//
+// GPU organisation: all admissible blocks of a band advance together, one
+// rank step at a time.  Steps 1 and 3 are flat launches with one lane per
+// matrix entry over every active block (a lane finds its block by binary
+// search in a prefix array), so the expensive entry evaluations keep every
+// lane busy whatever the block sizes; steps 2, 4 and 5 run one workgroup per
+// active block.  Reductions use wavefront shuffles and one LDS stage in a
+// fixed order, so results are bitwise reproducible.
 #include <algorithm>
 #include <climits>
 #include <numeric>
@@ -24,6 +30,31 @@
 namespace rte {
 
 namespace {
+
+enum : int { kActive = 0, kConverged = 1, kFailed = 2 };
+
+template <typename T>
+struct AcaState {
+    const AcaTask *task;
+    int nb;
+    int *k, *istar, *jstar, *status, *havepiv;
+    T *pivot, *normS2;
+    unsigned *used;             // row bitmaps
+    const int64_t *ubase;       // first bitmap word of each block
+    int64_t *rowoff, *coloff;   // [nb + 1] prefix sums of the active widths
+    int64_t *chunkoff;          // [nb + 1] prefix sums of the update chunks of the pivoted blocks
+    int *act, *act2;            // active block lists (row phase, column phase)
+    int64_t *tot;               // [0] row entries, [1] active blocks, [2] column entries, [3] pivoted blocks,
+                                // [4] update chunks
+    T *Us, *Vs;                 // U^T [kcap][m] and V^T [kcap][n] per block
+    T *part;                    // per chunk: [2][kAcaMaxRank + 1] partial dot products
+    T *pmax;                    // per chunk: |u| max and its signed value
+    int *pidx;                  // per chunk: row of the max
+};
+
+// elements of the concatenated (u_k, v_k) range of a block handled by one update chunk
+constexpr int kChunk = 1024;
+constexpr int kPartStride = 2 * (kAcaMaxRank + 1);
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -45,142 +76,306 @@ __device__ __forceinline__ void wave_argmax(T &a, int &idx, T &sv) {
 }
 
 template <typename T>
-__device__ __forceinline__ void combine4(const T *va, const int *vi, const T *vs, T &a, int &idx, T &sv) {
-    a = va[0]; idx = vi[0]; sv = vs[0];
+__device__ __forceinline__ void block_argmax(T &a, int &idx, T &sv, T *sa, int *si, T *ss) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    wave_argmax(a, idx, sv);
+    if (lane == 0) { sa[wid] = a; si[wid] = idx; ss[wid] = sv; }
+    __syncthreads();
+    a = sa[0]; idx = si[0]; sv = ss[0];
 #pragma unroll
     for (int w = 1; w < 4; ++w)
-        if (va[w] > a || (va[w] == a && vi[w] < idx)) { a = va[w]; idx = vi[w]; sv = vs[w]; }
+        if (sa[w] > a || (sa[w] == a && si[w] < idx)) { a = sa[w]; idx = si[w]; sv = ss[w]; }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool is_used(const unsigned *bits, int r) { return (bits[r >> 5] >> (r & 31)) & 1u; }
+
+// the block whose range [off[b], off[b+1]) holds e (zero-width blocks are skipped)
+__device__ __forceinline__ int find_block(const int64_t *off, int nb, int64_t e) {
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
 }  // namespace
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_aca_init(AcaState<T> st) {
+    const int b = blockIdx.x;
+    if (threadIdx.x == 0) {
+        st.k[b] = 0;
+        st.istar[b] = 0;
+        st.jstar[b] = 0;
+        st.status[b] = kActive;
+        st.havepiv[b] = 0;
+        st.normS2[b] = (T)0;
+        st.pivot[b] = (T)0;
+    }
+    const int words = (st.task[b].m + 31) / 32;
+    for (int w = threadIdx.x; w < words; w += blockDim.x) st.used[st.ubase[b] + w] = 0u;
+}
+
+// Prefix sums of the widths of the blocks taking part in a phase, and the
+// list of those blocks.  One workgroup of 1024 lanes.
+template <typename T, bool COLS>
+__global__ __launch_bounds__(1024) void k_aca_scan(AcaState<T> st) {
+    __shared__ int64_t sw[1024], sq[1024];
+    __shared__ int sc[1024];
+    const int nb = st.nb, tid = threadIdx.x;
+    const int per = (nb + 1023) / 1024;
+    const int b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
+    int64_t w = 0, q = 0;
+    int c = 0;
+    for (int b = b0; b < b1; ++b) {
+        const bool on = COLS ? (st.status[b] == kActive && st.havepiv[b]) : (st.status[b] == kActive);
+        if (on) {
+            w += COLS ? st.task[b].m : st.task[b].n;
+            q += (st.task[b].m + st.task[b].n + kChunk - 1) / kChunk;
+            ++c;
+        }
+    }
+    sw[tid] = w;
+    sq[tid] = q;
+    sc[tid] = c;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive scan
+        const int64_t a = tid >= o ? sw[tid - o] : 0;
+        const int64_t aq = tid >= o ? sq[tid - o] : 0;
+        const int ac = tid >= o ? sc[tid - o] : 0;
+        __syncthreads();
+        sw[tid] += a;
+        sq[tid] += aq;
+        sc[tid] += ac;
+        __syncthreads();
+    }
+    int64_t off = sw[tid] - w, qoff = sq[tid] - q;
+    int cnt = sc[tid] - c;
+    int64_t *offs = COLS ? st.coloff : st.rowoff;
+    int *list = COLS ? st.act2 : st.act;
+    for (int b = b0; b < b1; ++b) {
+        offs[b] = off;
+        if (COLS) st.chunkoff[b] = qoff;
+        const bool on = COLS ? (st.status[b] == kActive && st.havepiv[b]) : (st.status[b] == kActive);
+        if (on) {
+            off += COLS ? st.task[b].m : st.task[b].n;
+            qoff += (st.task[b].m + st.task[b].n + kChunk - 1) / kChunk;
+            list[cnt++] = b;
+        }
+    }
+    if (tid == 1023) {
+        offs[nb] = sw[1023];
+        st.tot[COLS ? 2 : 0] = sw[1023];
+        st.tot[COLS ? 3 : 1] = sc[1023];
+        if (COLS) {
+            st.chunkoff[nb] = sq[1023];
+            st.tot[4] = sq[1023];
+        }
+    }
+}
+
+// Step 1: residual rows of every active block, one lane per entry.
 template <typename T, int KIND>
-__global__ __launch_bounds__(256) void k_aca(EntryCtx<T> c, const AcaTask *__restrict__ tasks,
-                                             const int64_t *__restrict__ tgt_nat,
-                                             const int64_t *__restrict__ src_nat, T *__restrict__ Us,
-                                             T *__restrict__ Vs, int *__restrict__ ranks, T eps) {
-    __shared__ unsigned used[kAcaMaxRows / 32];
+__global__ __launch_bounds__(256) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
+                                                  const int64_t *__restrict__ tgt_nat,
+                                                  const int64_t *__restrict__ src_nat) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int b = find_block(st.rowoff, st.nb, e);
+    const AcaTask tk = st.task[b];
+    const int j = (int)(e - st.rowoff[b]);
+    const int k = st.k[b], is = st.istar[b];
+    const T *U = st.Us + tk.uoff;
+    T *V = st.Vs + tk.voff;
+    T a = entry<T, KIND>(c, tgt_nat[tk.t0 + is], src_nat[tk.s0 + j]);
+    for (int l = 0; l < k; ++l) a -= U[(int64_t)l * tk.m + is] * V[(int64_t)l * tk.n + j];
+    V[(int64_t)k * tk.n + j] = a;
+}
+
+// Step 2: pivot column of each active block, or the next row after a zero row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_aca_pivot(AcaState<T> st) {
+    __shared__ T sa[4], ss[4];
+    __shared__ int si[4];
+    const int b = st.act[blockIdx.x];
+    const AcaTask tk = st.task[b];
+    const int k = st.k[b];
+    const T *V = st.Vs + tk.voff + (int64_t)k * tk.n;
+    unsigned *bits = st.used + st.ubase[b];
+    T best = (T)-1, sv = (T)0;
+    int bj = INT_MAX;
+    for (int j = threadIdx.x; j < tk.n; j += 256) {
+        const T v = V[j], av = fabs(v);
+        if (av > best) { best = av; bj = j; sv = v; }
+    }
+    block_argmax(best, bj, sv, sa, si, ss);
+    if (threadIdx.x == 0) {
+        const int is = st.istar[b];
+        bits[is >> 5] |= 1u << (is & 31);
+    }
+    if (best > (T)0) {
+        if (threadIdx.x == 0) {
+            st.jstar[b] = bj;
+            st.pivot[b] = sv;
+            st.havepiv[b] = 1;
+        }
+        return;
+    }
+    // zero residual row: the lowest unused row is next
+    __syncthreads();   // the bit of i* is visible
+    int cand = INT_MAX;
+    for (int r = threadIdx.x; r < tk.m; r += 256)
+        if (!is_used(bits, r)) { cand = r; break; }
+    T key = cand == INT_MAX ? (T)-1 : (T)1, dv = (T)0;
+    block_argmax(key, cand, dv, sa, si, ss);
+    if (threadIdx.x == 0) {
+        st.havepiv[b] = 0;
+        if (key < (T)0) st.status[b] = kConverged;   // every row used: the residual is zero
+        else st.istar[b] = cand;
+    }
+}
+
+// Step 3: residual columns of the pivoted blocks, one lane per entry.
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
+                                                  const int64_t *__restrict__ tgt_nat,
+                                                  const int64_t *__restrict__ src_nat) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int b = find_block(st.coloff, st.nb, e);
+    const AcaTask tk = st.task[b];
+    const int i = (int)(e - st.coloff[b]);
+    const int k = st.k[b], js = st.jstar[b];
+    T *U = st.Us + tk.uoff;
+    const T *V = st.Vs + tk.voff;
+    T a = entry<T, KIND>(c, tgt_nat[tk.t0 + i], src_nat[tk.s0 + js]);
+    // V_l(j*) for l < k is already scaled; V_k is scaled in step 4
+    for (int l = 0; l < k; ++l) a -= V[(int64_t)l * tk.n + js] * U[(int64_t)l * tk.m + i];
+    U[(int64_t)k * tk.m + i] = a;
+}
+
+// Steps 4-5, first part: scale v_k and form the partial dot products
+// (u_l.u_k), (v_l.v_k), l <= k, and the partial argmax of |u_k| over unused
+// rows, on one chunk of the concatenated (u_k, v_k) range of a block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
     __shared__ T red_u[4][kAcaMaxRank + 1];
     __shared__ T red_v[4][kAcaMaxRank + 1];
-    __shared__ T ra[4], rs[4], ca[4], cs[4];
-    __shared__ int ri[4], ci[4];
-    __shared__ int s_ctrl[2];
-
-    const AcaTask tk = tasks[blockIdx.x];
+    __shared__ T sa[4], ss[4];
+    __shared__ int si[4];
+    const int64_t c = blockIdx.x;
+    const int b = find_block(st.chunkoff, st.nb, c);
+    const AcaTask tk = st.task[b];
+    const int k = st.k[b], m = tk.m, n = tk.n;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    T *U = Us + tk.uoff;
-    T *V = Vs + tk.voff;
-    const int m = tk.m, n = tk.n;
-    for (int w = tid; w < (m + 31) / 32; w += 256) used[w] = 0u;
-    __syncthreads();
-
-    int k = 0, istar = 0;
-    bool conv = false;
-    T normS2 = (T)0;   // meaningful in thread 0 only
-    const int max_iter = tk.kcap + m + 1;
-    for (int iter = 0; iter < max_iter; ++iter) {
-        if (tid == 0) used[istar >> 5] |= 1u << (istar & 31);
-        // 1. residual row i*
-        const int64_t gi = tgt_nat[tk.t0 + istar];
-        T best = (T)-1, bsv = (T)0;
-        int bj = INT_MAX;
-        for (int j = tid; j < n; j += 256) {
-            T a = entry<T, KIND>(c, gi, src_nat[tk.s0 + j]);
-            for (int l = 0; l < k; ++l) a -= U[(int64_t)l * m + istar] * V[(int64_t)l * n + j];
-            V[(int64_t)k * n + j] = a;
-            const T av = fabs(a);
-            if (av > best) { best = av; bj = j; bsv = a; }
+    const int e0 = (int)(c - st.chunkoff[b]) * kChunk;
+    const int e1 = min(e0 + kChunk, m + n);
+    const T *U = st.Us + tk.uoff;
+    T *V = st.Vs + tk.voff;
+    const unsigned *bits = st.used + st.ubase[b];
+    const T inv = (T)1 / st.pivot[b];
+    T bu = (T)-1, busv = (T)0;
+    int bi = INT_MAX;
+    for (int e = e0 + tid; e < e1; e += 256) {
+        if (e < m) {
+            const T u = U[(int64_t)k * m + e];
+            if (!is_used(bits, e) && fabs(u) > bu) { bu = fabs(u); bi = e; busv = u; }
+        } else {
+            V[(int64_t)k * n + (e - m)] *= inv;   // read back below by this lane only
         }
-        // 2. pivot column
-        wave_argmax(best, bj, bsv);
-        if (lane == 0) { ra[wid] = best; ri[wid] = bj; rs[wid] = bsv; }
-        __syncthreads();
-        combine4(ra, ri, rs, best, bj, bsv);
-        if (!(best > (T)0)) {
-            // zero residual row: continue from the lowest unused row
-            if (tid == 0) {
-                int cand = -1;
-                for (int r = 0; r < m && cand < 0; ++r)
-                    if (!((used[r >> 5] >> (r & 31)) & 1u)) cand = r;
-                s_ctrl[1] = cand;
-            }
-            __syncthreads();
-            const int cand = s_ctrl[1];
-            __syncthreads();
-            if (cand < 0) { conv = true; break; }
-            istar = cand;
-            continue;
-        }
-        const T inv = (T)1 / bsv;
-        T nv2 = (T)0;
-        for (int j = tid; j < n; j += 256) {
-            const T v = V[(int64_t)k * n + j] * inv;
-            V[(int64_t)k * n + j] = v;
-            nv2 += v * v;
-        }
-        __syncthreads();   // V_k(j*) and earlier V_l(j*) are read by every lane below
-        // 3. residual column j*
-        const int64_t gj = src_nat[tk.s0 + bj];
-        T bu = (T)-1, busv = (T)0, nu2 = (T)0;
-        int bi = INT_MAX;
-        for (int i = tid; i < m; i += 256) {
-            T a = entry<T, KIND>(c, tgt_nat[tk.t0 + i], gj);
-            for (int l = 0; l < k; ++l) a -= V[(int64_t)l * n + bj] * U[(int64_t)l * m + i];
-            U[(int64_t)k * m + i] = a;
-            nu2 += a * a;
-            const T av = fabs(a);
-            if (!((used[i >> 5] >> (i & 31)) & 1u) && av > bu) { bu = av; bi = i; busv = a; }
-        }
-        // 4. Frobenius norm update (each lane reads only the elements it wrote)
-        for (int l = 0; l < k; ++l) {
-            T pu = (T)0, pv = (T)0;
-            for (int i = tid; i < m; i += 256) pu += U[(int64_t)l * m + i] * U[(int64_t)k * m + i];
-            for (int j = tid; j < n; j += 256) pv += V[(int64_t)l * n + j] * V[(int64_t)k * n + j];
-            pu = wave_sum(pu);
-            pv = wave_sum(pv);
-            if (lane == 0) { red_u[wid][l] = pu; red_v[wid][l] = pv; }
-        }
-        nu2 = wave_sum(nu2);
-        nv2 = wave_sum(nv2);
-        if (lane == 0) { red_u[wid][k] = nu2; red_v[wid][k] = nv2; }
-        wave_argmax(bu, bi, busv);
-        if (lane == 0) { ca[wid] = bu; ci[wid] = bi; cs[wid] = busv; }
-        __syncthreads();
-        if (tid == 0) {
-            T cross = (T)0;
-            for (int l = 0; l < k; ++l)
-                cross += (red_u[0][l] + red_u[1][l] + red_u[2][l] + red_u[3][l]) *
-                         (red_v[0][l] + red_v[1][l] + red_v[2][l] + red_v[3][l]);
-            const T u2 = red_u[0][k] + red_u[1][k] + red_u[2][k] + red_u[3][k];
-            const T v2 = red_v[0][k] + red_v[1][k] + red_v[2][k] + red_v[3][k];
-            normS2 += u2 * v2 + (T)2 * cross;
-            s_ctrl[0] = (sqrt(u2 * v2) <= eps * sqrt(fabs(normS2))) ? 1 : 0;
-        }
-        combine4(ca, ci, cs, bu, bi, busv);
-        __syncthreads();
-        const int stop = s_ctrl[0];
-        ++k;
-        if (stop) { conv = true; break; }
-        if (k >= tk.kcap) break;
-        if (bi == INT_MAX) { conv = true; break; }   // every row used: the residual is zero
-        istar = bi;
     }
-    if (tid == 0) ranks[blockIdx.x] = conv ? k : -1;
+    for (int l = 0; l <= k; ++l) {
+        T pu = (T)0, pv = (T)0;
+        for (int e = e0 + tid; e < e1; e += 256) {
+            if (e < m) pu += U[(int64_t)l * m + e] * U[(int64_t)k * m + e];
+            else pv += V[(int64_t)l * n + (e - m)] * V[(int64_t)k * n + (e - m)];
+        }
+        pu = wave_sum(pu);
+        pv = wave_sum(pv);
+        if (lane == 0) { red_u[wid][l] = pu; red_v[wid][l] = pv; }
+    }
+    block_argmax(bu, bi, busv, sa, si, ss);   // includes the barrier for red_u / red_v
+    T *part = st.part + c * kPartStride;
+    for (int l = tid; l <= k; l += 256) {
+        part[l] = ((red_u[0][l] + red_u[1][l]) + red_u[2][l]) + red_u[3][l];
+        part[kAcaMaxRank + 1 + l] = ((red_v[0][l] + red_v[1][l]) + red_v[2][l]) + red_v[3][l];
+    }
+    if (tid == 0) {
+        st.pmax[2 * c] = bu;
+        st.pmax[2 * c + 1] = busv;
+        st.pidx[c] = bi;
+    }
+}
+
+// Steps 4-5, second part: add the chunk partials in order, update ||S_k||,
+// test convergence and pick the next row.  One wavefront per pivoted block.
+template <typename T>
+__global__ __launch_bounds__(64) void k_aca_finish(AcaState<T> st, T eps) {
+    const int b = st.act2[blockIdx.x];
+    const AcaTask tk = st.task[b];
+    const int k = st.k[b], lane = threadIdx.x;
+    const int64_t c0 = st.chunkoff[b], c1 = st.chunkoff[b + 1];
+    T cross = (T)0, u2 = (T)0, v2 = (T)0;
+    for (int l = lane; l <= k; l += 64) {
+        T su = (T)0, sv = (T)0;
+        for (int64_t c = c0; c < c1; ++c) {
+            su += st.part[c * kPartStride + l];
+            sv += st.part[c * kPartStride + kAcaMaxRank + 1 + l];
+        }
+        if (l < k) cross += su * sv;
+        else { u2 = su; v2 = sv; }
+    }
+    cross = wave_sum(cross);
+    u2 = wave_sum(u2);
+    v2 = wave_sum(v2);
+    if (lane != 0) return;
+    T bu = (T)-1, busv = (T)0;
+    int bi = INT_MAX;
+    for (int64_t c = c0; c < c1; ++c) {
+        const T a = st.pmax[2 * c];
+        const int i = st.pidx[c];
+        if (a > bu || (a == bu && i < bi)) { bu = a; bi = i; busv = st.pmax[2 * c + 1]; }
+    }
+    (void)busv;
+    const T s2 = st.normS2[b] + u2 * v2 + (T)2 * cross;
+    st.normS2[b] = s2;
+    const bool stop = sqrt(u2 * v2) <= eps * sqrt(fabs(s2));
+    const int kn = k + 1;
+    st.k[b] = kn;
+    st.havepiv[b] = 0;
+    if (stop) st.status[b] = kConverged;
+    else if (kn >= tk.kcap) st.status[b] = kFailed;
+    else if (bi == INT_MAX) st.status[b] = kConverged;   // every row used
+    else st.istar[b] = bi;
+}
+
+__global__ void k_aca_ranks(const int *__restrict__ k, const int *__restrict__ status, int nb, int *__restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) out[b] = status[b] == kConverged ? k[b] : -1;
 }
 
 struct CompactTask {
     const void *su, *sv;
     void *du, *dv;
-    int64_t nu, nv;   // elements to copy
+    int32_t m, n, k, pad;
 };
 
+// Final layout of a low-rank block: U^T [k][m] as produced, and V row-major
+// [n][k] (the k coefficients of one source point contiguous) for the matvec.
 template <typename T>
 __global__ __launch_bounds__(256) void k_compact(const CompactTask *__restrict__ tasks) {
     const CompactTask t = tasks[blockIdx.x];
     const T *su = static_cast<const T *>(t.su), *sv = static_cast<const T *>(t.sv);
     T *du = static_cast<T *>(t.du), *dv = static_cast<T *>(t.dv);
-    for (int64_t e = threadIdx.x; e < t.nu; e += blockDim.x) du[e] = su[e];
-    for (int64_t e = threadIdx.x; e < t.nv; e += blockDim.x) dv[e] = sv[e];
+    const int64_t nu = (int64_t)t.k * t.m, nv = (int64_t)t.k * t.n;
+    for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) du[e] = su[e];
+    for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
+        const int64_t j = e / t.k, l = e - j * t.k;
+        dv[e] = sv[l * t.n + j];
+    }
 }
 
 // ---------------------------------------------------------------- host side
@@ -212,6 +407,147 @@ void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Bl
 }
 
 template <typename T>
+void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &tasks, const std::vector<size_t> &ids,
+               int64_t uo, int64_t vo, std::vector<Block> &fallback, hipStream_t s) {
+    const Plan &P = *H.plan;
+    const int nb = (int)tasks.size();
+    std::vector<int64_t> ubase(nb);
+    int64_t words = 0;
+    for (int b = 0; b < nb; ++b) {
+        ubase[b] = words;
+        words += (tasks[b].m + 31) / 32;
+    }
+    DevBuf Us(sizeof(T) * (size_t)uo), Vs(sizeof(T) * (size_t)vo);
+    DevBuf dt = upload(tasks, s), dub = upload(ubase, s);
+    int64_t max_chunks = 0;
+    for (auto &t : tasks) max_chunks += (t.m + t.n + kChunk - 1) / kChunk;
+    DevBuf ints(sizeof(int) * (size_t)nb * 7), reals(sizeof(T) * (size_t)nb * 2),
+        used(sizeof(unsigned) * (size_t)words), offs(sizeof(int64_t) * (size_t)(nb + 1) * 3),
+        tot(sizeof(int64_t) * 5), part(sizeof(T) * (size_t)max_chunks * kPartStride),
+        pmax(sizeof(T) * (size_t)max_chunks * 2), pidx(sizeof(int) * (size_t)max_chunks);
+    AcaState<T> st;
+    st.task = dt.as<AcaTask>();
+    st.nb = nb;
+    int *ip = ints.as<int>();
+    st.k = ip;
+    st.istar = ip + nb;
+    st.jstar = ip + 2 * nb;
+    st.status = ip + 3 * nb;
+    st.havepiv = ip + 4 * nb;
+    st.act = ip + 5 * nb;
+    st.act2 = ip + 6 * nb;
+    st.pivot = reals.as<T>();
+    st.normS2 = reals.as<T>() + nb;
+    st.used = used.as<unsigned>();
+    st.ubase = dub.as<int64_t>();
+    st.rowoff = offs.as<int64_t>();
+    st.coloff = offs.as<int64_t>() + nb + 1;
+    st.chunkoff = offs.as<int64_t>() + 2 * (nb + 1);
+    st.tot = tot.as<int64_t>();
+    st.part = part.as<T>();
+    st.pmax = pmax.as<T>();
+    st.pidx = pidx.as<int>();
+    st.Us = Us.as<T>();
+    st.Vs = Vs.as<T>();
+    auto c = make_ctx<T>(*H.mesh, kap);
+    const T eps = (T)P.opts.aca_eps;
+    const int64_t *tn = H.tgt_nat.as<int64_t>(), *sn = H.src_nat.as<int64_t>();
+    // every step raises a rank or consumes a zero row, so this bounds the steps
+    int max_steps = 0;
+    for (auto &t : tasks) max_steps = std::max(max_steps, t.kcap + t.m);
+
+    EventTimer ent(s), whole(s);
+    double entry_ms = 0.0;
+    int64_t entries = 0;
+    int launches = 0;
+    whole.start();
+    k_aca_init<T><<<nb, 256, 0, s>>>(st);
+    HIP_LAUNCH_CHECK();
+    int64_t ht[5];
+    for (int step = 0; step <= max_steps; ++step) {
+        k_aca_scan<T, false><<<1, 1024, 0, s>>>(st);
+        HIP_LAUNCH_CHECK();
+        HIP_CHECK(hipMemcpyAsync(ht, st.tot, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (ht[1] == 0) break;
+        const int64_t nrow = ht[0];
+        ent.start();
+        if (H.kind == RTE_VOLUME)
+            k_aca_rows<T, RTE_VOLUME><<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn);
+        else
+            k_aca_rows<T, RTE_SURFACE><<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn);
+        HIP_LAUNCH_CHECK();
+        ent.stop();
+        entries += nrow;
+        k_aca_pivot<T><<<(unsigned)ht[1], 256, 0, s>>>(st);
+        k_aca_scan<T, true><<<1, 1024, 0, s>>>(st);
+        HIP_LAUNCH_CHECK();
+        HIP_CHECK(hipMemcpyAsync(ht + 2, st.tot + 2, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        entry_ms += ent.ms();
+        ++launches;
+        if (ht[3] == 0) continue;
+        const int64_t ncol = ht[2];
+        ent.start();
+        if (H.kind == RTE_VOLUME)
+            k_aca_cols<T, RTE_VOLUME><<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn);
+        else
+            k_aca_cols<T, RTE_SURFACE><<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn);
+        HIP_LAUNCH_CHECK();
+        ent.stop();
+        entries += ncol;
+        k_aca_dots<T><<<(unsigned)ht[4], 256, 0, s>>>(st);
+        k_aca_finish<T><<<(unsigned)ht[3], 64, 0, s>>>(st, eps);
+        HIP_LAUNCH_CHECK();
+        entry_ms += ent.ms();
+        ++launches;
+    }
+    whole.stop();
+    B.aca_ms += whole.ms();
+    B.aca_entry_ms += entry_ms;
+    B.aca_entry_launches += launches;
+    B.aca_launches += 1;
+    B.aca_entries += entries;
+    B.evaluated += entries;
+
+    DevBuf dr(sizeof(int) * (size_t)nb);
+    k_aca_ranks<<<(nb + 255) / 256, 256, 0, s>>>(st.k, st.status, nb, dr.as<int>());
+    HIP_LAUNCH_CHECK();
+    std::vector<int> rk(nb);
+    HIP_CHECK(hipMemcpyAsync(rk.data(), dr.p, sizeof(int) * rk.size(), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    int64_t total = 0;
+    for (int t = 0; t < nb; ++t)
+        if (rk[t] > 0) total += (int64_t)rk[t] * (tasks[t].m + tasks[t].n);
+    DevBuf out(sizeof(T) * (size_t)total);
+    std::vector<CompactTask> ct;
+    int64_t off = 0;
+    for (int t = 0; t < nb; ++t) {
+        const size_t b = ids[t];
+        if (rk[t] <= 0) {
+            fallback.push_back(P.lowrank[b]);
+            continue;
+        }
+        const int64_t nu = (int64_t)rk[t] * tasks[t].m, nv = (int64_t)rk[t] * tasks[t].n;
+        T *du = out.as<T>() + off, *dv = du + nu;
+        ct.push_back({Us.as<T>() + tasks[t].uoff, Vs.as<T>() + tasks[t].voff, du, dv, tasks[t].m, tasks[t].n, rk[t], 0});
+        B.rank[b] = rk[t];
+        B.U[b] = du;
+        B.V[b] = dv;
+        B.lr_entries += nu + nv;
+        off += nu + nv;
+    }
+    if (!ct.empty()) {
+        DevBuf dct = upload(ct, s);
+        k_compact<T><<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>());
+        HIP_LAUNCH_CHECK();
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+    B.bytes += (int64_t)out.bytes;
+    B.bufs.push_back(std::move(out));
+}
+
+template <typename T>
 void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
     const Plan &P = *H.plan;
     const size_t nlr = P.lowrank.size();
@@ -219,93 +555,31 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
     B.U.assign(nlr, nullptr);
     B.V.assign(nlr, nullptr);
     std::vector<Block> fallback;
-    std::vector<size_t> order;
+    const size_t scratch_limit = (size_t)8 << 30;   // bytes of U/V scratch per batch
+    std::vector<AcaTask> tasks;
+    std::vector<size_t> ids;
+    int64_t uo = 0, vo = 0;
     for (size_t b = 0; b < nlr; ++b) {
         const Block &bl = P.lowrank[b];
-        const int64_t m = bl.t1 - bl.t0, n = bl.s1 - bl.s0;
-        const int64_t kcap = std::min<int64_t>(m * n / (m + n), kAcaMaxRank);
-        if (kcap < 1 || m > kAcaMaxRows) fallback.push_back(bl);
-        else order.push_back(b);
+        const int32_t m = (int32_t)(bl.t1 - bl.t0), n = (int32_t)(bl.s1 - bl.s0);
+        const int32_t kcap = (int32_t)std::min<int64_t>((int64_t)m * n / (m + n), kAcaMaxRank);
+        if (kcap < 1) {
+            fallback.push_back(bl);
+            continue;
+        }
+        const int64_t need = (int64_t)kcap * (m + n);
+        if (!tasks.empty() && (size_t)(uo + vo + need) * sizeof(T) > scratch_limit) {
+            aca_batch<T>(H, B, kap, tasks, ids, uo, vo, fallback, s);
+            tasks.clear();
+            ids.clear();
+            uo = vo = 0;
+        }
+        tasks.push_back({bl.t0, bl.s0, m, n, kcap, 0, uo, vo});
+        ids.push_back(b);
+        uo += (int64_t)kcap * m;
+        vo += (int64_t)kcap * n;
     }
-    // large blocks first: they take longest
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-        const Block &x = P.lowrank[a], &y = P.lowrank[b];
-        return (x.t1 - x.t0) + (x.s1 - x.s0) > (y.t1 - y.t0) + (y.s1 - y.s0);
-    });
-    const T eps = (T)P.opts.aca_eps;
-    const size_t scratch_limit = (size_t)6 << 30;   // bytes of U/V scratch per batch
-    auto c = make_ctx<T>(*H.mesh, kap);
-    size_t pos = 0;
-    while (pos < order.size()) {
-        std::vector<AcaTask> tasks;
-        std::vector<size_t> ids;
-        int64_t uo = 0, vo = 0;
-        while (pos < order.size()) {
-            const Block &bl = P.lowrank[order[pos]];
-            const int32_t m = (int32_t)(bl.t1 - bl.t0), n = (int32_t)(bl.s1 - bl.s0);
-            const int32_t kcap = (int32_t)std::min<int64_t>((int64_t)m * n / (m + n), kAcaMaxRank);
-            const int64_t need = (int64_t)kcap * (m + n);
-            if (!tasks.empty() && (size_t)(uo + vo + need) * sizeof(T) > scratch_limit) break;
-            tasks.push_back({bl.t0, bl.s0, m, n, kcap, 0, uo, vo});
-            ids.push_back(order[pos]);
-            uo += (int64_t)kcap * m;
-            vo += (int64_t)kcap * n;
-            ++pos;
-        }
-        DevBuf Us(sizeof(T) * (size_t)uo), Vs(sizeof(T) * (size_t)vo), dr(sizeof(int) * tasks.size());
-        DevBuf dt = upload(tasks, s);
-        EventTimer tm(s);
-        tm.start();
-        if (H.kind == RTE_VOLUME)
-            k_aca<T, RTE_VOLUME><<<(unsigned)tasks.size(), 256, 0, s>>>(c, dt.as<AcaTask>(), H.tgt_nat.as<int64_t>(),
-                                                                    H.src_nat.as<int64_t>(), Us.as<T>(), Vs.as<T>(),
-                                                                    dr.as<int>(), eps);
-        else
-            k_aca<T, RTE_SURFACE><<<(unsigned)tasks.size(), 256, 0, s>>>(c, dt.as<AcaTask>(), H.tgt_nat.as<int64_t>(),
-                                                                     H.src_nat.as<int64_t>(), Us.as<T>(), Vs.as<T>(),
-                                                                     dr.as<int>(), eps);
-        HIP_LAUNCH_CHECK();
-        tm.stop();
-        B.aca_ms += tm.ms();
-        B.aca_launches += 1;
-        std::vector<int> rk(tasks.size());
-        HIP_CHECK(hipMemcpyAsync(rk.data(), dr.p, sizeof(int) * rk.size(), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        int64_t total = 0;
-        for (size_t t = 0; t < tasks.size(); ++t) {
-            if (rk[t] > 0) total += (int64_t)rk[t] * (tasks[t].m + tasks[t].n);
-            // entries evaluated: one row and one column per rank step (zero rows aside)
-            const int64_t ev = (int64_t)std::max(rk[t], tasks[t].kcap * (rk[t] < 0)) * (tasks[t].m + tasks[t].n);
-            B.evaluated += ev;
-            B.aca_entries += ev;
-        }
-        DevBuf out(sizeof(T) * (size_t)total);
-        std::vector<CompactTask> ct;
-        int64_t off = 0;
-        for (size_t t = 0; t < tasks.size(); ++t) {
-            const size_t b = ids[t];
-            if (rk[t] < 0) {
-                fallback.push_back(P.lowrank[b]);
-                continue;
-            }
-            const int64_t nu = (int64_t)rk[t] * tasks[t].m, nv = (int64_t)rk[t] * tasks[t].n;
-            T *du = out.as<T>() + off, *dv = du + nu;
-            ct.push_back({Us.as<T>() + tasks[t].uoff, Vs.as<T>() + tasks[t].voff, du, dv, nu, nv});
-            B.rank[b] = rk[t];
-            B.U[b] = du;
-            B.V[b] = dv;
-            B.lr_entries += nu + nv;
-            off += nu + nv;
-        }
-        if (!ct.empty()) {
-            DevBuf dct = upload(ct, s);
-            k_compact<T><<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>());
-            HIP_LAUNCH_CHECK();
-            HIP_CHECK(hipStreamSynchronize(s));
-        }
-        B.bytes += (int64_t)out.bytes;
-        B.bufs.push_back(std::move(out));
-    }
+    if (!tasks.empty()) aca_batch<T>(H, B, kap, tasks, ids, uo, vo, fallback, s);
     fill_dense_blocks<T>(H, B, kap, fallback, s);
 }
 

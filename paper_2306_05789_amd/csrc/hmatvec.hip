@@ -2,9 +2,12 @@
 // "Compression": after compression the fixed point only needs matrix-vector
 // products, O(N ln N) each).
 //
-// Phase A: t_b = V_b^T x[s-range of b] for every low-rank block b (one
-//          wavefront per block, lanes along the source points, V^T rows
-//          contiguous).
+// Phase A: t_b = V_b^T x[s-range of b] for every low-rank block b.  V is
+//          row-major [n][k]; a wavefront takes a chunk of source rows, lane
+//          l accumulates t_l and 64/kpad rows are read per step, so loads
+//          are contiguous and no per-l reduction is needed.  Blocks larger
+//          than one chunk write partial sums that a second pass adds in a
+//          fixed order.
 // Phase B: one workgroup per target leaf owns its rows: it sums the dense
 //          leaves of its block row and the row slices of every low-rank block
 //          that covers it, y = y0 + sum_seg D x or U t.  Each of the 4
@@ -18,10 +21,17 @@
 namespace rte {
 
 struct VtTask {
-    const void *V;      // V^T [k][n]
-    int64_t s0;         // first source (cluster order)
-    int64_t toff;       // offset of t_b in the t buffer
-    int32_t n, k;
+    const void *V;      // first row of the chunk in V [n][k]
+    int64_t s0;         // source (cluster order) of the chunk's first row
+    int64_t out;        // offset of the result (t buffer, or partial buffer if partial)
+    int32_t nj, k;      // rows in the chunk, rank
+    int32_t partial, pad;
+};
+
+struct VtReduce {
+    int64_t part;       // first partial (elements) in the partial buffer
+    int64_t toff;       // offset of t_b
+    int32_t chunks, k;
 };
 
 struct Seg {
@@ -36,8 +46,8 @@ struct LeafWork {
 };
 
 struct MatvecPlan {
-    DevBuf vt, seg, leaf;
-    int64_t n_vt = 0, n_leaf = 0, ktot = 0;
+    DevBuf vt, seg, leaf, red;
+    int64_t n_vt = 0, n_leaf = 0, ktot = 0, n_red = 0, n_red_threads = 0, npart = 0;
     int64_t n_src = 0, n_tgt = 0;
     int max_rows = 0;
 };
@@ -54,30 +64,67 @@ __device__ __forceinline__ double wsum(double v) {
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_phase_a(const VtTask *__restrict__ tasks, int64_t ntask,
                                                  const double *__restrict__ x, int64_t ldx, double *__restrict__ t,
-                                                 int64_t ldt, int r0, int nr) {
+                                                 int64_t ldt, double *__restrict__ part, int64_t ldp, int r0, int nr) {
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= ntask) return;
     const VtTask tk = tasks[w];
     const T *V = static_cast<const T *>(tk.V);
-    for (int l = 0; l < tk.k; ++l) {
+    double *dst = tk.partial ? part : t;
+    const int64_t ldd = tk.partial ? ldp : ldt;
+    for (int l0 = 0; l0 < tk.k; l0 += 64) {
+        const int kk = min(64, tk.k - l0);
+        int kp = 1;
+        while (kp < kk) kp <<= 1;
+        const int G = 64 / kp;
+        const int g = lane / kp, l = lane - g * kp;
+        const bool live = l < kk;
         double acc[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-        const T *row = V + (int64_t)l * tk.n;
-        for (int j = lane; j < tk.n; j += 64) {
-            const double v = (double)row[j];
+        int jj = g;
+        for (; jj + 3 * G < tk.nj; jj += 4 * G) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = live ? (double)V[(int64_t)(jj + u * G) * tk.k + l0 + l] : 0.0;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (r < nr) {
+                    const double *xr = x + (int64_t)(r0 + r) * ldx + tk.s0 + jj;
+                    acc[r] += v[0] * xr[0] + v[1] * xr[G] + v[2] * xr[2 * G] + v[3] * xr[3 * G];
+                }
+            }
+        }
+        for (; jj < tk.nj; jj += G) {
+            const double v = live ? (double)V[(int64_t)jj * tk.k + l0 + l] : 0.0;
 #pragma unroll
             for (int r = 0; r < NR; ++r)
-                if (r < nr) acc[r] += v * x[(int64_t)(r0 + r) * ldx + tk.s0 + j];
+                if (r < nr) acc[r] += v * x[(int64_t)(r0 + r) * ldx + tk.s0 + jj];
         }
+        // add the G row groups (lanes l, l + kp, ...) in a fixed order
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (r < nr) {
-                const double s = wsum<T>(acc[r]);
-                if (lane == 0) t[(int64_t)(r0 + r) * ldt + tk.toff + l] = s;
+                double a = acc[r];
+                for (int o = kp; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
+                if (g == 0 && live) dst[(int64_t)(r0 + r) * ldd + tk.out + l0 + l] = a;
             }
         }
+    }
+}
+
+__global__ void k_phase_a_reduce(const VtReduce *__restrict__ red, int64_t nred, const double *__restrict__ part,
+                                 int64_t ldp, double *__restrict__ t, int64_t ldt, int r0, int nr) {
+    // one thread per (reduce item, l); items are laid out with a prefix of k
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t item = blockIdx.y;
+    if (item >= nred) return;
+    const VtReduce rd = red[item];
+    if (w >= rd.k) return;
+    for (int r = 0; r < nr; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < rd.chunks; ++c) s += part[(int64_t)(r0 + r) * ldp + rd.part + (int64_t)c * rd.k + w];
+        t[(int64_t)(r0 + r) * ldt + rd.toff + w] = s;
     }
 }
 
@@ -163,14 +210,22 @@ __global__ void k_scatter(const int64_t *__restrict__ perm, int64_t n, int nrhs,
 template <typename T, typename A>
 void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double *y0, double *y, double *tb,
                   hipStream_t s) {
+    double *part = tb + mp.ktot * (int64_t)nrhs;   // the workspace holds t, then the partials
+    const int64_t ldp = std::max<int64_t>(mp.npart, 1);
     for (int r0 = 0; r0 < nrhs; r0 += 16) {
         const int nr = std::min(16, nrhs - r0);
         if (mp.n_vt) {
             const unsigned ga = (unsigned)((mp.n_vt + 3) / 4);
-            if (nr == 1) k_phase_a<T, 1><<<ga, 256, 0, s>>>(mp.vt.as<VtTask>(), mp.n_vt, x, mp.n_src, tb, mp.ktot, r0, nr);
-            else if (nr <= 4) k_phase_a<T, 4><<<ga, 256, 0, s>>>(mp.vt.as<VtTask>(), mp.n_vt, x, mp.n_src, tb, mp.ktot, r0, nr);
-            else k_phase_a<T, 16><<<ga, 256, 0, s>>>(mp.vt.as<VtTask>(), mp.n_vt, x, mp.n_src, tb, mp.ktot, r0, nr);
+            const VtTask *vt = mp.vt.as<VtTask>();
+            if (nr == 1) k_phase_a<T, 1><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
+            else if (nr <= 4) k_phase_a<T, 4><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
+            else k_phase_a<T, 16><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
             HIP_LAUNCH_CHECK();
+            if (mp.n_red) {
+                dim3 grid((unsigned)((mp.n_red_threads + 63) / 64), (unsigned)mp.n_red);
+                k_phase_a_reduce<<<grid, 64, 0, s>>>(mp.red.as<VtReduce>(), mp.n_red, part, ldp, tb, mp.ktot, r0, nr);
+                HIP_LAUNCH_CHECK();
+            }
         }
         const unsigned gb = (unsigned)mp.n_leaf;
         if (nr == 1)
@@ -198,21 +253,44 @@ void matvec_build(HMat &H, int band, hipStream_t s) {
     mp->n_src = (int64_t)P.src_nat.size();
     mp->n_tgt = (int64_t)P.tgt_nat.size();
     std::vector<VtTask> vt;
+    std::vector<VtReduce> red;
     std::vector<int64_t> toff(P.lowrank.size(), -1);
-    int64_t ktot = 0;
+    int64_t ktot = 0, npart = 0, maxk = 0;
+    // about this many bytes of V per wavefront task
+    const int64_t chunk_bytes = 48 * 1024;
+    const int64_t esz = H.precision == RTE_FP64 ? 8 : 4;
     for (size_t b = 0; b < P.lowrank.size(); ++b) {
         if (B.rank[b] <= 0) continue;
         const Block &bl = P.lowrank[b];
+        const int32_t k = B.rank[b];
+        const int64_t n = bl.s1 - bl.s0;
         toff[b] = ktot;
-        vt.push_back({B.V[b], bl.s0, ktot, (int32_t)(bl.s1 - bl.s0), B.rank[b]});
-        ktot += B.rank[b];
+        const int64_t rows = std::max<int64_t>(64, chunk_bytes / (k * esz));
+        const int64_t chunks = (n + rows - 1) / rows;
+        const char *V = static_cast<const char *>(B.V[b]);
+        if (chunks == 1) {
+            vt.push_back({V, bl.s0, ktot, (int32_t)n, k, 0, 0});
+        } else {
+            red.push_back({npart, ktot, (int32_t)chunks, k});
+            for (int64_t c = 0; c < chunks; ++c) {
+                const int64_t j0 = c * rows, nj = std::min(rows, n - j0);
+                vt.push_back({V + j0 * k * esz, bl.s0 + j0, npart + c * k, (int32_t)nj, k, 1, 0});
+            }
+            npart += chunks * k;
+        }
+        maxk = std::max<int64_t>(maxk, k);
+        ktot += k;
     }
-    // wide blocks first so that long wavefronts start early
+    // large tasks first so that long wavefronts start early
     std::stable_sort(vt.begin(), vt.end(), [](const VtTask &a, const VtTask &b) {
-        return (int64_t)a.n * a.k > (int64_t)b.n * b.k;
+        return (int64_t)a.nj * a.k > (int64_t)b.nj * b.k;
     });
     mp->ktot = std::max<int64_t>(ktot, 1);
+    mp->npart = npart;
     mp->n_vt = (int64_t)vt.size();
+    mp->n_red = (int64_t)red.size();
+    mp->n_red_threads = maxk;
+    mp->red = upload(red, s);
     const auto &leaves = P.tgt_leaves;
     std::vector<int64_t> starts;
     for (auto &lf : leaves) starts.push_back(lf.first);
@@ -257,7 +335,8 @@ void matvec_build(HMat &H, int band, hipStream_t s) {
     H.mv[band] = std::move(mp);
 }
 
-int64_t matvec_ktot(const HMat &H, int band) { return H.mv[band]->ktot; }
+// workspace doubles per right-hand side: t, then the partial sums of chunked blocks
+int64_t matvec_ktot(const HMat &H, int band) { return H.mv[band]->ktot + H.mv[band]->npart; }
 
 void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                       double *tbuf, hipStream_t s) {
@@ -268,7 +347,7 @@ void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, doub
 
 void matvec_launch(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                    hipStream_t s) {
-    DevBuf tb(sizeof(double) * (size_t)H.mv[band]->ktot * nrhs);
+    DevBuf tb(sizeof(double) * (size_t)matvec_ktot(H, band) * nrhs);
     matvec_launch_ws(H, band, nrhs, x_c, y_c, y0_c, tb.as<double>(), s);
     HIP_CHECK(hipStreamSynchronize(s));
 }

@@ -7,7 +7,6 @@ namespace rte {
 
 constexpr int kFillChunk = 4096;   // entries of a dense block per fill task
 constexpr int kAcaMaxRank = 192;   // rank cap of one ACA block before dense fallback
-constexpr int kAcaMaxRows = 32768; // LDS bitmap of used pivot rows
 
 struct FillTask {
     void *out;        // first element of the block's column-major storage

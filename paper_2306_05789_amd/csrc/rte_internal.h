@@ -167,8 +167,8 @@ DevBuf upload(const std::vector<T> &v, hipStream_t s) {
 
 // ---------------------------------------------------------------- H-matrix storage
 // Dense leaves are stored column-major (for each source column, the block's
-// rows contiguous); a low-rank block as U^T [rank][m] and V^T [rank][n], so
-// every stream the matvec reads is contiguous along the lanes.  Mixed
+// rows contiguous); a low-rank block as U^T [rank][m] and V row-major
+// [n][rank], so every stream the matvec reads is contiguous along the lanes.  Mixed
 // precision keeps the factors as BF16 hi and lo parts with one FP32 scale per
 // block (value = scale * (hi + lo)); dense leaves are FP32 there.
 struct BandStore {
@@ -180,8 +180,8 @@ struct BandStore {
     std::vector<const void *> Ulo, Vlo;     // mixed precision: BF16 lo parts
     std::vector<float> scale;               // mixed precision: per LR block scale
     int64_t bytes = 0, dense_entries = 0, lr_entries = 0, evaluated = 0, aca_entries = 0;
-    double aca_ms = 0.0, fill_ms = 0.0;   // HIP-event kernel times
-    int aca_launches = 0, fill_launches = 0;
+    double aca_ms = 0.0, fill_ms = 0.0, aca_entry_ms = 0.0;   // HIP-event kernel times
+    int aca_launches = 0, fill_launches = 0, aca_entry_launches = 0;
 };
 
 struct MatvecPlan;   // device work lists (hmatvec.hip)

@@ -49,6 +49,7 @@ class HmatStats(C.Structure):
                 ("mean_rank", C.c_double), ("compression", C.c_double), ("bytes", C.c_int64),
                 ("entries_evaluated", C.c_int64), ("assemble_ms", C.c_double),
                 ("aca_kernel_ms", C.c_double), ("aca_launches", C.c_int32),
+                ("aca_entry_ms", C.c_double), ("aca_entry_launches", C.c_int32),
                 ("fill_kernel_ms", C.c_double), ("fill_launches", C.c_int32), ("aca_entries", C.c_int64)]
 
     def as_dict(self):
