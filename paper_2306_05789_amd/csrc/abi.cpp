@@ -324,12 +324,27 @@ rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, i
         if (H.precision == RTE_FP64) {
             HIP_CHECK(hipMemcpy(ut.data(), B.U[block], sizeof(double) * m * k, hipMemcpyDeviceToHost));
             HIP_CHECK(hipMemcpy(vt.data(), B.V[block], sizeof(double) * n * k, hipMemcpyDeviceToHost));
-        } else {
+        } else if (H.precision == RTE_FP32) {
             std::vector<float> uf(m * k), vf(n * k);
             HIP_CHECK(hipMemcpy(uf.data(), B.U[block], sizeof(float) * m * k, hipMemcpyDeviceToHost));
             HIP_CHECK(hipMemcpy(vf.data(), B.V[block], sizeof(float) * n * k, hipMemcpyDeviceToHost));
             for (int64_t e = 0; e < m * k; ++e) ut[e] = uf[e];
             for (int64_t e = 0; e < n * k; ++e) vt[e] = vf[e];
+        } else {
+            // BF16 hi + lo: the factor value is hi + lo
+            std::vector<uint16_t> uh(m * k), ul(m * k), vh(n * k), vl(n * k);
+            HIP_CHECK(hipMemcpy(uh.data(), B.U[block], 2 * m * k, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(ul.data(), B.Ulo[block], 2 * m * k, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vh.data(), B.V[block], 2 * n * k, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vl.data(), B.Vlo[block], 2 * n * k, hipMemcpyDeviceToHost));
+            auto wid = [](uint16_t h) {
+                uint32_t u = (uint32_t)h << 16;
+                float f;
+                std::memcpy(&f, &u, 4);
+                return (double)f;
+            };
+            for (int64_t e = 0; e < m * k; ++e) ut[e] = wid(uh[e]) + wid(ul[e]);
+            for (int64_t e = 0; e < n * k; ++e) vt[e] = wid(vh[e]) + wid(vl[e]);
         }
         for (int64_t l = 0; l < k; ++l) {
             for (int64_t i = 0; i < m; ++i) U[i * k + l] = ut[l * m + i];

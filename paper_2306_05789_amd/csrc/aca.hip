@@ -360,6 +360,7 @@ __global__ void k_aca_ranks(const int *__restrict__ k, const int *__restrict__ s
 struct CompactTask {
     const void *su, *sv;
     void *du, *dv;
+    void *dul, *dvl;      // BF16 lo parts (mixed precision)
     int32_t m, n, k, pad;
 };
 
@@ -375,6 +376,29 @@ __global__ __launch_bounds__(256) void k_compact(const CompactTask *__restrict__
     for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
         const int64_t j = e / t.k, l = e - j * t.k;
         dv[e] = sv[l * t.n + j];
+    }
+}
+
+// Mixed precision: each factor element x (FP32) is stored as hi = bf16(x) and
+// lo = bf16(x - hi), in the same layouts; BF16 keeps FP32's exponent range.
+__global__ __launch_bounds__(256) void k_compact_bf16(const CompactTask *__restrict__ tasks) {
+    const CompactTask t = tasks[blockIdx.x];
+    const float *su = static_cast<const float *>(t.su), *sv = static_cast<const float *>(t.sv);
+    uint16_t *uh = static_cast<uint16_t *>(t.du), *vh = static_cast<uint16_t *>(t.dv);
+    uint16_t *ul = static_cast<uint16_t *>(t.dul), *vl = static_cast<uint16_t *>(t.dvl);
+    const int64_t nu = (int64_t)t.k * t.m, nv = (int64_t)t.k * t.n;
+    for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) {
+        const float x = su[e];
+        const uint16_t h = f2bf(x);
+        uh[e] = h;
+        ul[e] = f2bf(x - bf2f(h));
+    }
+    for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
+        const int64_t j = e / t.k, l = e - j * t.k;
+        const float x = sv[l * t.n + j];
+        const uint16_t h = f2bf(x);
+        vh[e] = h;
+        vl[e] = f2bf(x - bf2f(h));
     }
 }
 
@@ -519,7 +543,9 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     int64_t total = 0;
     for (int t = 0; t < nb; ++t)
         if (rk[t] > 0) total += (int64_t)rk[t] * (tasks[t].m + tasks[t].n);
-    DevBuf out(sizeof(T) * (size_t)total);
+    const bool split = H.precision == RTE_MIXED_BF16;
+    const size_t esz = split ? sizeof(uint16_t) : sizeof(T);
+    DevBuf out(esz * (size_t)total), outlo(split ? esz * (size_t)total : 0);
     std::vector<CompactTask> ct;
     int64_t off = 0;
     for (int t = 0; t < nb; ++t) {
@@ -529,22 +555,31 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
             continue;
         }
         const int64_t nu = (int64_t)rk[t] * tasks[t].m, nv = (int64_t)rk[t] * tasks[t].n;
-        T *du = out.as<T>() + off, *dv = du + nu;
-        ct.push_back({Us.as<T>() + tasks[t].uoff, Vs.as<T>() + tasks[t].voff, du, dv, tasks[t].m, tasks[t].n, rk[t], 0});
+        char *du = static_cast<char *>(out.p) + off * esz, *dv = du + nu * esz;
+        char *dul = split ? static_cast<char *>(outlo.p) + off * esz : nullptr;
+        char *dvl = split ? dul + nu * esz : nullptr;
+        ct.push_back({Us.as<T>() + tasks[t].uoff, Vs.as<T>() + tasks[t].voff, du, dv, dul, dvl, tasks[t].m,
+                      tasks[t].n, rk[t], 0});
         B.rank[b] = rk[t];
         B.U[b] = du;
         B.V[b] = dv;
+        if (split) {
+            B.Ulo[b] = dul;
+            B.Vlo[b] = dvl;
+        }
         B.lr_entries += nu + nv;
         off += nu + nv;
     }
     if (!ct.empty()) {
         DevBuf dct = upload(ct, s);
-        k_compact<T><<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>());
+        if (split) k_compact_bf16<<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>());
+        else k_compact<T><<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>());
         HIP_LAUNCH_CHECK();
         HIP_CHECK(hipStreamSynchronize(s));
     }
-    B.bytes += (int64_t)out.bytes;
+    B.bytes += (int64_t)(out.bytes + outlo.bytes);
     B.bufs.push_back(std::move(out));
+    if (split) B.bufs.push_back(std::move(outlo));
 }
 
 template <typename T>
@@ -554,6 +589,8 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
     B.rank.assign(nlr, -1);
     B.U.assign(nlr, nullptr);
     B.V.assign(nlr, nullptr);
+    B.Ulo.assign(nlr, nullptr);
+    B.Vlo.assign(nlr, nullptr);
     std::vector<Block> fallback;
     const size_t scratch_limit = (size_t)8 << 30;   // bytes of U/V scratch per batch
     std::vector<AcaTask> tasks;

@@ -22,6 +22,7 @@ namespace rte {
 
 struct VtTask {
     const void *V;      // first row of the chunk in V [n][k]
+    const void *Vlo;    // same position in the BF16 lo part (mixed precision)
     int64_t s0;         // source (cluster order) of the chunk's first row
     int64_t out;        // offset of the result (t buffer, or partial buffer if partial)
     int32_t nj, k;      // rows in the chunk, rank
@@ -36,6 +37,7 @@ struct VtReduce {
 
 struct Seg {
     const void *data;   // column-major [K][ld] (dense: x columns; low rank: U^T rows)
+    const void *lo;     // BF16 lo part of U^T (mixed precision low rank)
     int64_t coef_off;   // offset into x (dense: s0) or t (low rank: toff)
     int32_t ld, row_off, K, is_lr;
 };
@@ -54,14 +56,28 @@ struct MatvecPlan {
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ double wsum(double v) {
+// factor storage: FP64, FP32, or BF16 (hi part, plus the lo part in MODE_ACC)
+enum : int { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
+
+template <int ST, int MODE, typename A>
+__device__ __forceinline__ A load_factor(const void *p, const void *lo, int64_t i) {
+    if constexpr (ST == ST_F64) return (A) static_cast<const double *>(p)[i];
+    else if constexpr (ST == ST_F32) return (A) static_cast<const float *>(p)[i];
+    else {
+        A v = (A)bf2f(static_cast<const uint16_t *>(p)[i]);
+        if constexpr (MODE == kMatvecAccurate) v += (A)bf2f(static_cast<const uint16_t *>(lo)[i]);
+        return v;
+    }
+}
+
+template <typename A>
+__device__ __forceinline__ A wsum(A v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-template <typename T, int NR>
+template <int ST, int MODE, typename A, int NR>
 __global__ __launch_bounds__(256) void k_phase_a(const VtTask *__restrict__ tasks, int64_t ntask,
                                                  const double *__restrict__ x, int64_t ldx, double *__restrict__ t,
                                                  int64_t ldt, double *__restrict__ part, int64_t ldp, int r0, int nr) {
@@ -69,7 +85,6 @@ __global__ __launch_bounds__(256) void k_phase_a(const VtTask *__restrict__ task
     const int lane = threadIdx.x & 63;
     if (w >= ntask) return;
     const VtTask tk = tasks[w];
-    const T *V = static_cast<const T *>(tk.V);
     double *dst = tk.partial ? part : t;
     const int64_t ldd = tk.partial ? ldp : ldt;
     for (int l0 = 0; l0 < tk.k; l0 += 64) {
@@ -79,35 +94,36 @@ __global__ __launch_bounds__(256) void k_phase_a(const VtTask *__restrict__ task
         const int G = 64 / kp;
         const int g = lane / kp, l = lane - g * kp;
         const bool live = l < kk;
-        double acc[NR];
+        A acc[NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+        for (int r = 0; r < NR; ++r) acc[r] = (A)0;
         int jj = g;
         for (; jj + 3 * G < tk.nj; jj += 4 * G) {
-            double v[4];
+            A v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = live ? (double)V[(int64_t)(jj + u * G) * tk.k + l0 + l] : 0.0;
+            for (int u = 0; u < 4; ++u)
+                v[u] = live ? load_factor<ST, MODE, A>(tk.V, tk.Vlo, (int64_t)(jj + u * G) * tk.k + l0 + l) : (A)0;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (r < nr) {
                     const double *xr = x + (int64_t)(r0 + r) * ldx + tk.s0 + jj;
-                    acc[r] += v[0] * xr[0] + v[1] * xr[G] + v[2] * xr[2 * G] + v[3] * xr[3 * G];
+                    acc[r] += v[0] * (A)xr[0] + v[1] * (A)xr[G] + v[2] * (A)xr[2 * G] + v[3] * (A)xr[3 * G];
                 }
             }
         }
         for (; jj < tk.nj; jj += G) {
-            const double v = live ? (double)V[(int64_t)jj * tk.k + l0 + l] : 0.0;
+            const A v = live ? load_factor<ST, MODE, A>(tk.V, tk.Vlo, (int64_t)jj * tk.k + l0 + l) : (A)0;
 #pragma unroll
             for (int r = 0; r < NR; ++r)
-                if (r < nr) acc[r] += v * x[(int64_t)(r0 + r) * ldx + tk.s0 + jj];
+                if (r < nr) acc[r] += v * (A)x[(int64_t)(r0 + r) * ldx + tk.s0 + jj];
         }
         // add the G row groups (lanes l, l + kp, ...) in a fixed order
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (r < nr) {
-                double a = acc[r];
+                A a = acc[r];
                 for (int o = kp; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
-                if (g == 0 && live) dst[(int64_t)(r0 + r) * ldd + tk.out + l0 + l] = a;
+                if (g == 0 && live) dst[(int64_t)(r0 + r) * ldd + tk.out + l0 + l] = (double)a;
             }
         }
     }
@@ -115,7 +131,6 @@ __global__ __launch_bounds__(256) void k_phase_a(const VtTask *__restrict__ task
 
 __global__ void k_phase_a_reduce(const VtReduce *__restrict__ red, int64_t nred, const double *__restrict__ part,
                                  int64_t ldp, double *__restrict__ t, int64_t ldt, int r0, int nr) {
-    // one thread per (reduce item, l); items are laid out with a prefix of k
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t item = blockIdx.y;
     if (item >= nred) return;
@@ -128,12 +143,13 @@ __global__ void k_phase_a_reduce(const VtReduce *__restrict__ red, int64_t nred,
     }
 }
 
-template <typename T, typename A, int NR>
+template <int ST, int MODE, typename A, int NR>
 __global__ __launch_bounds__(256) void k_phase_b(const LeafWork *__restrict__ leaves, const Seg *__restrict__ segs,
                                                  const double *__restrict__ x, int64_t ldx,
                                                  const double *__restrict__ t, int64_t ldt,
                                                  const double *__restrict__ y0, double *__restrict__ y, int64_t ldy,
                                                  int r0, int nr) {
+    constexpr int SD = ST == ST_F64 ? ST_F64 : ST_F32;   // dense leaves: FP64, else FP32
     __shared__ A part[4][NR][64];
     const LeafWork lw = leaves[blockIdx.x];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -145,18 +161,21 @@ __global__ __launch_bounds__(256) void k_phase_b(const LeafWork *__restrict__ le
         for (int r = 0; r < NR; ++r) acc[r] = (A)0;
         for (int s = lw.seg0 + wid; s < lw.seg1; s += 4) {
             const Seg sg = segs[s];
-            const T *D = static_cast<const T *>(sg.data) + sg.row_off + row;
+            const int64_t base = sg.row_off + row;
             const double *cb = sg.is_lr ? t : x;
             const int64_t ldc = sg.is_lr ? ldt : ldx;
             const double *cf = cb + sg.coef_off;
+            auto ld = [&](int64_t i) -> A {
+                return sg.is_lr ? load_factor<ST, MODE, A>(sg.data, sg.lo, i) : load_factor<SD, 0, A>(sg.data, nullptr, i);
+            };
             int l = 0;
             for (; l + 4 <= sg.K; l += 4) {
                 A d0 = (A)0, d1 = (A)0, d2 = (A)0, d3 = (A)0;
                 if (live) {
-                    d0 = (A)D[(int64_t)(l + 0) * sg.ld];
-                    d1 = (A)D[(int64_t)(l + 1) * sg.ld];
-                    d2 = (A)D[(int64_t)(l + 2) * sg.ld];
-                    d3 = (A)D[(int64_t)(l + 3) * sg.ld];
+                    d0 = ld(base + (int64_t)(l + 0) * sg.ld);
+                    d1 = ld(base + (int64_t)(l + 1) * sg.ld);
+                    d2 = ld(base + (int64_t)(l + 2) * sg.ld);
+                    d3 = ld(base + (int64_t)(l + 3) * sg.ld);
                 }
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
@@ -167,7 +186,7 @@ __global__ __launch_bounds__(256) void k_phase_b(const LeafWork *__restrict__ le
                 }
             }
             for (; l < sg.K; ++l) {
-                const A d = live ? (A)D[(int64_t)l * sg.ld] : (A)0;
+                const A d = live ? ld(base + (int64_t)l * sg.ld) : (A)0;
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
                     if (r < nr) acc[r] += d * (A)cf[(int64_t)(r0 + r) * ldc + l];
@@ -207,7 +226,7 @@ __global__ void k_scatter(const int64_t *__restrict__ perm, int64_t n, int nrhs,
     out[r * ld_out + perm[p]] = in[r * ld_in + p];
 }
 
-template <typename T, typename A>
+template <int ST, int MODE, typename A>
 void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double *y0, double *y, double *tb,
                   hipStream_t s) {
     double *part = tb + mp.ktot * (int64_t)nrhs;   // the workspace holds t, then the partials
@@ -217,9 +236,12 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
         if (mp.n_vt) {
             const unsigned ga = (unsigned)((mp.n_vt + 3) / 4);
             const VtTask *vt = mp.vt.as<VtTask>();
-            if (nr == 1) k_phase_a<T, 1><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
-            else if (nr <= 4) k_phase_a<T, 4><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
-            else k_phase_a<T, 16><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
+            if (nr == 1)
+                k_phase_a<ST, MODE, A, 1><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
+            else if (nr <= 4)
+                k_phase_a<ST, MODE, A, 4><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
+            else
+                k_phase_a<ST, MODE, A, 16><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
             HIP_LAUNCH_CHECK();
             if (mp.n_red) {
                 dim3 grid((unsigned)((mp.n_red_threads + 63) / 64), (unsigned)mp.n_red);
@@ -228,15 +250,14 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
             }
         }
         const unsigned gb = (unsigned)mp.n_leaf;
+        const LeafWork *lw = mp.leaf.as<LeafWork>();
+        const Seg *sg = mp.seg.as<Seg>();
         if (nr == 1)
-            k_phase_b<T, A, 1><<<gb, 256, 0, s>>>(mp.leaf.as<LeafWork>(), mp.seg.as<Seg>(), x, mp.n_src, tb, mp.ktot,
-                                                  y0, y, mp.n_tgt, r0, nr);
+            k_phase_b<ST, MODE, A, 1><<<gb, 256, 0, s>>>(lw, sg, x, mp.n_src, tb, mp.ktot, y0, y, mp.n_tgt, r0, nr);
         else if (nr <= 4)
-            k_phase_b<T, A, 4><<<gb, 256, 0, s>>>(mp.leaf.as<LeafWork>(), mp.seg.as<Seg>(), x, mp.n_src, tb, mp.ktot,
-                                                  y0, y, mp.n_tgt, r0, nr);
+            k_phase_b<ST, MODE, A, 4><<<gb, 256, 0, s>>>(lw, sg, x, mp.n_src, tb, mp.ktot, y0, y, mp.n_tgt, r0, nr);
         else
-            k_phase_b<T, A, 16><<<gb, 256, 0, s>>>(mp.leaf.as<LeafWork>(), mp.seg.as<Seg>(), x, mp.n_src, tb,
-                                                   mp.ktot, y0, y, mp.n_tgt, r0, nr);
+            k_phase_b<ST, MODE, A, 16><<<gb, 256, 0, s>>>(lw, sg, x, mp.n_src, tb, mp.ktot, y0, y, mp.n_tgt, r0, nr);
         HIP_LAUNCH_CHECK();
     }
 }
@@ -258,7 +279,7 @@ void matvec_build(HMat &H, int band, hipStream_t s) {
     int64_t ktot = 0, npart = 0, maxk = 0;
     // about this many bytes of V per wavefront task
     const int64_t chunk_bytes = 48 * 1024;
-    const int64_t esz = H.precision == RTE_FP64 ? 8 : 4;
+    const int64_t esz = H.precision == RTE_FP64 ? 8 : H.precision == RTE_FP32 ? 4 : 2;
     for (size_t b = 0; b < P.lowrank.size(); ++b) {
         if (B.rank[b] <= 0) continue;
         const Block &bl = P.lowrank[b];
@@ -268,13 +289,15 @@ void matvec_build(HMat &H, int band, hipStream_t s) {
         const int64_t rows = std::max<int64_t>(64, chunk_bytes / (k * esz));
         const int64_t chunks = (n + rows - 1) / rows;
         const char *V = static_cast<const char *>(B.V[b]);
+        const char *Vl = static_cast<const char *>(B.Vlo.empty() ? nullptr : B.Vlo[b]);
         if (chunks == 1) {
-            vt.push_back({V, bl.s0, ktot, (int32_t)n, k, 0, 0});
+            vt.push_back({V, Vl, bl.s0, ktot, (int32_t)n, k, 0, 0});
         } else {
             red.push_back({npart, ktot, (int32_t)chunks, k});
             for (int64_t c = 0; c < chunks; ++c) {
                 const int64_t j0 = c * rows, nj = std::min(rows, n - j0);
-                vt.push_back({V + j0 * k * esz, bl.s0 + j0, npart + c * k, (int32_t)nj, k, 1, 0});
+                vt.push_back({V + j0 * k * esz, Vl ? Vl + j0 * k * esz : nullptr, bl.s0 + j0, npart + c * k,
+                              (int32_t)nj, k, 1, 0});
             }
             npart += chunks * k;
         }
@@ -302,7 +325,7 @@ void matvec_build(HMat &H, int band, hipStream_t s) {
         const Block &bl = B.dense_blocks[d];
         const int32_t m = (int32_t)(bl.t1 - bl.t0);
         for (int64_t li = leaf_of(bl.t0); li < (int64_t)leaves.size() && leaves[li].first < bl.t1; ++li) {
-            per[li].push_back({B.dense_ptr[d], bl.s0, m, (int32_t)(leaves[li].first - bl.t0),
+            per[li].push_back({B.dense_ptr[d], nullptr, bl.s0, m, (int32_t)(leaves[li].first - bl.t0),
                                (int32_t)(bl.s1 - bl.s0), 0});
         }
     }
@@ -312,7 +335,8 @@ void matvec_build(HMat &H, int band, hipStream_t s) {
         const Block &bl = P.lowrank[b];
         const int32_t m = (int32_t)(bl.t1 - bl.t0);
         for (int64_t li = leaf_of(bl.t0); li < (int64_t)leaves.size() && leaves[li].first < bl.t1; ++li)
-            per[li].push_back({B.U[b], toff[b], m, (int32_t)(leaves[li].first - bl.t0), B.rank[b], 1});
+            per[li].push_back({B.U[b], B.Ulo.empty() ? nullptr : B.Ulo[b], toff[b], m,
+                               (int32_t)(leaves[li].first - bl.t0), B.rank[b], 1});
     }
     std::vector<Seg> segs;
     std::vector<LeafWork> lw;
@@ -339,16 +363,18 @@ void matvec_build(HMat &H, int band, hipStream_t s) {
 int64_t matvec_ktot(const HMat &H, int band) { return H.mv[band]->ktot + H.mv[band]->npart; }
 
 void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
-                      double *tbuf, hipStream_t s) {
+                      double *tbuf, hipStream_t s, int mode) {
     const MatvecPlan &mp = *H.mv[band];
-    if (H.precision == RTE_FP64) launch_typed<double, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
-    else launch_typed<float, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    if (H.precision == RTE_FP64) launch_typed<ST_F64, 0, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    else if (H.precision == RTE_FP32) launch_typed<ST_F32, 0, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    else if (mode == kMatvecAccurate) launch_typed<ST_BF16, kMatvecAccurate, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    else launch_typed<ST_BF16, kMatvecLow, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
 }
 
 void matvec_launch(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
-                   hipStream_t s) {
+                   hipStream_t s, int mode) {
     DevBuf tb(sizeof(double) * (size_t)matvec_ktot(H, band) * nrhs);
-    matvec_launch_ws(H, band, nrhs, x_c, y_c, y0_c, tb.as<double>(), s);
+    matvec_launch_ws(H, band, nrhs, x_c, y_c, y0_c, tb.as<double>(), s, mode);
     HIP_CHECK(hipStreamSynchronize(s));
 }
 

@@ -6,6 +6,17 @@
 namespace rte {
 
 constexpr int kFillChunk = 4096;   // entries of a dense block per fill task
+
+// bfloat16 as the upper half of an IEEE binary32: round to nearest even on
+// the way in (finite inputs), exact widening on the way out.
+__host__ __device__ __forceinline__ uint16_t f2bf(float x) {
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__host__ __device__ __forceinline__ float bf2f(uint16_t h) {
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
 constexpr int kAcaMaxRank = 192;   // rank cap of one ACA block before dense fallback
 
 struct FillTask {

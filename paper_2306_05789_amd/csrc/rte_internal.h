@@ -208,11 +208,16 @@ void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, con
                     const int64_t *cols, double *out, int precision, hipStream_t s);
 void assemble_band(HMat &H, int band, const double *kappa_band, hipStream_t s);
 void matvec_build(HMat &H, int band, hipStream_t s);
+// Operator applied by a matvec on mixed-precision storage: the BF16-hi
+// factors with FP32 accumulation (inner sweeps), or hi + lo with FP64
+// accumulation (defect steps and external calls).  Other storages ignore it.
+constexpr int kMatvecLow = 0;
+constexpr int kMatvecAccurate = 1;
 void matvec_launch(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
-                   hipStream_t s);
+                   hipStream_t s, int mode = kMatvecAccurate);
 // Same with a caller-provided workspace of nrhs * matvec_ktot(H, band) doubles; does not synchronise.
 void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
-                      double *tbuf, hipStream_t s);
+                      double *tbuf, hipStream_t s, int mode = kMatvecAccurate);
 int64_t matvec_ktot(const HMat &H, int band);
 void permute_gather(const int64_t *perm, int64_t n, int nrhs, int64_t ld_in, int64_t ld_out, const double *in,
                     double *out, hipStream_t s);

@@ -166,6 +166,11 @@ __global__ void k_newton(BandParams bp, const double *__restrict__ J, const doub
     T[k] = Tn;
 }
 
+__global__ void k_sub(const double *__restrict__ a, const double *__restrict__ b, int64_t n, double *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = a[k] - b[k];
+}
+
 void check_desc(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_desc_t &d) {
     RTE_REQUIRE(G.kind == RTE_VOLUME && S.kind == RTE_SURFACE, "solve: need a volume and a surface H-matrix");
     RTE_REQUIRE(G.mesh == &m && S.mesh == &m, "solve: H-matrices were assembled on another mesh");
@@ -178,6 +183,8 @@ void check_desc(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_des
     RTE_REQUIRE(d.max_iter >= 1, "solve: max_iter must be >= 1");
     RTE_REQUIRE(d.precision == RTE_FP64 || d.precision == RTE_FP32 || d.precision == RTE_MIXED_BF16,
                 "solve: unknown precision");
+    RTE_REQUIRE(d.precision != RTE_MIXED_BF16 || G.precision == RTE_MIXED_BF16,
+                "solve: the mixed-precision iteration needs a volume matrix assembled with RTE_MIXED_BF16");
     if (!d.grey) {
         RTE_REQUIRE(d.nu != nullptr, "solve: nu is required for the band formulation");
         for (int b = 0; b < d.n_bands; ++b) {
@@ -248,41 +255,82 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
     HIP_CHECK(hipEventCreate(&e1));
     float mv_ms = 0.0f;
     std::vector<double> rv(2 * nb * nr);
-    double r = INFINITY;
-    int it = 0;
-    bool conv = false;
-    for (it = 1; it <= d.max_iter; ++it) {
+    const bool mixed = d.precision == RTE_MIXED_BF16;
+    DevBuf D0(mixed ? sizeof(double) * vecN * nb : 0), Jlo(mixed ? sizeof(double) * vecN * nb : 0);
+
+    // one sweep: S = S(T, J); Jn = y0 + G S over all bands; residual(J, Jn); T = T(Jn); J <- Jn
+    auto sweep = [&](int mode, const double *y0, bool newton) -> double {
         k_source<<<gN, 256, 0, s>>>(bp, T.as<double>(), J.as<double>(), N, nr, Sv.as<double>());
         HIP_LAUNCH_CHECK();
         HIP_CHECK(hipEventRecord(e0, s));
         for (int b = 0; b < nb; ++b)
             matvec_launch_ws(G, b, nr, Sv.as<double>() + (int64_t)b * vecN, Jn.as<double>() + (int64_t)b * vecN,
-                             SE.as<double>() + (int64_t)b * vecN, tbuf.as<double>(), s);
+                             y0 + (int64_t)b * vecN, tbuf.as<double>(), s, mode);
         HIP_CHECK(hipEventRecord(e1, s));
         k_resid_partial<<<dim3(kResidBlocks, nb * nr), 256, 0, s>>>(J.as<double>(), Jn.as<double>(), N,
                                                                      part.as<double>());
         k_resid_final<<<(nb * nr + 63) / 64, 64, 0, s>>>(part.as<double>(), nb * nr, res.as<double>());
-        k_newton<<<gN, 256, 0, s>>>(bp, Jn.as<double>(), G.kappa_c.as<double>(), N, nr, T.as<double>(),
-                                    viol.as<unsigned long long>());
+        if (newton)
+            k_newton<<<gN, 256, 0, s>>>(bp, Jn.as<double>(), G.kappa_c.as<double>(), N, nr, T.as<double>(),
+                                        viol.as<unsigned long long>());
         HIP_LAUNCH_CHECK();
-        std::swap(J, Jn);
         HIP_CHECK(hipMemcpyAsync(rv.data(), res.p, sizeof(double) * rv.size(), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         float ms = 0.0f;
         HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
         mv_ms += ms;
-        r = 0.0;
+        double q = 0.0;
         for (int v = 0; v < nb * nr; ++v) {
             const double num = rv[2 * v], den = rv[2 * v + 1];
-            const double q = den > 0.0 ? std::sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
-            r = std::max(r, q);
+            q = std::max(q, den > 0.0 ? std::sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0));
         }
-        if (!std::isfinite(r)) break;
-        if (r <= d.tol) { conv = true; break; }
+        return q;
+    };
+
+    double r = INFINITY;
+    int it = 0, outer = 0;
+    bool conv = false;
+    if (!mixed) {
+        while (it < d.max_iter) {
+            r = sweep(kMatvecAccurate, SE.as<double>(), true);
+            ++it;
+            std::swap(J, Jn);
+            if (!std::isfinite(r)) break;
+            if (r <= d.tol) { conv = true; break; }
+        }
+    } else {
+        // FP64 defect correction around sweeps on the BF16-hi operator G_lo:
+        //   outer: J <- S^E + G S(T) with the hi+lo operator (FP64 accumulation); its
+        //          relative change is the residual that decides convergence;
+        //          D0 = J - G_lo S(T) = S^E + (G - G_lo) S(T) is frozen;
+        //   inner: J <- D0 + G_lo S(T(J)) until the change is well below the outer one.
+        while (it < d.max_iter) {
+            r = sweep(kMatvecAccurate, SE.as<double>(), false);
+            ++it;
+            ++outer;
+            if (!std::isfinite(r)) break;
+            // G_lo S with the same S (Sv still holds it)
+            for (int b = 0; b < nb; ++b)
+                matvec_launch_ws(G, b, nr, Sv.as<double>() + (int64_t)b * vecN, Jlo.as<double>() + (int64_t)b * vecN,
+                                 nullptr, tbuf.as<double>(), s, kMatvecLow);
+            k_sub<<<(unsigned)((vecN * nb + 255) / 256), 256, 0, s>>>(Jn.as<double>(), Jlo.as<double>(), vecN * nb,
+                                                                      D0.as<double>());
+            k_newton<<<gN, 256, 0, s>>>(bp, Jn.as<double>(), G.kappa_c.as<double>(), N, nr, T.as<double>(),
+                                        viol.as<unsigned long long>());
+            HIP_LAUNCH_CHECK();
+            std::swap(J, Jn);
+            if (r <= d.tol) { conv = true; break; }
+            const double inner_tol = std::max(0.05 * r, 0.25 * d.tol);
+            for (int k = 0; k < 200 && it < d.max_iter; ++k) {
+                const double ri = sweep(kMatvecLow, D0.as<double>(), true);
+                ++it;
+                std::swap(J, Jn);
+                if (!std::isfinite(ri) || ri <= inner_tol) break;
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (it > d.max_iter) it = d.max_iter;
     if (T_out) permute_scatter(G.tgt_nat.as<int64_t>(), N, nr, N, N, T.as<double>(), T_out, s);
     if (J_out)
         for (int b = 0; b < nb; ++b)
@@ -294,7 +342,7 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
     HIP_CHECK(hipStreamSynchronize(s));
     if (st) {
         st->iterations = it;
-        st->outer_steps = 0;
+        st->outer_steps = outer;
         st->residual = r;
         st->monotone_violations = (int64_t)nviol;
         st->ms_matvec = mv_ms;
