@@ -218,6 +218,13 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
         H.tgt_nat = upload(P.tgt_nat, s);
         H.src_nat = upload(P.src_nat, s);
         H.src_pos = upload(opts->kind == RTE_VOLUME ? P.tgt_nat : P.src.perm, s);
+        // leaf slices are padded to 8 rows for BF16 storage (16-byte loads), else 4
+        const int64_t unit = H.precision == RTE_MIXED_BF16 ? 8 : 4;
+        H.leaf_prp_h.assign(1, 0);
+        for (auto &lf : P.tgt_leaves)
+            H.leaf_prp_h.push_back(H.leaf_prp_h.back() + (lf.second - lf.first + unit - 1) / unit * unit);
+        H.leaf_start = upload(P.leaf_start, s);
+        H.leaf_prp = upload(H.leaf_prp_h, s);
         H.kappa_c.alloc(sizeof(double) * (size_t)m.N * n_bands);
         permute_gather(H.tgt_nat.as<int64_t>(), m.N, n_bands, m.N, m.N, kappa, H.kappa_c.as<double>(), s);
         H.bands.resize(n_bands);
@@ -250,6 +257,7 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
                 maxr = std::max(maxr, B.rank[k]);
             }
         }
+        matvec_build_all(H, s);
         HIP_CHECK(hipStreamSynchronize(s));
         rte_hmat_stats_t &st = H.stats;
         st.n_tgt = (int64_t)P.tgt_nat.size();
@@ -320,36 +328,46 @@ rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, i
         *mo = m;
         *no = n;
         if (!U || !V || k <= 0) return RTE_OK;
-        std::vector<double> ut(m * k), vt(n * k);
+        // U: k * (padded rows of the block's target leaves); V row-major [n][kp]
+        const int64_t kp = (k + 3) & ~(int64_t)3;
+        const int64_t mu = k * (H.leaf_prp_h[H.plan->leaf_of(bl.t1 - 1) + 1] - H.leaf_prp_h[H.plan->leaf_of(bl.t0)]);
+        std::vector<double> ut(mu), vt(n * kp);
         if (H.precision == RTE_FP64) {
-            HIP_CHECK(hipMemcpy(ut.data(), B.U[block], sizeof(double) * m * k, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vt.data(), B.V[block], sizeof(double) * n * k, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(ut.data(), B.U[block], sizeof(double) * mu, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vt.data(), B.V[block], sizeof(double) * n * kp, hipMemcpyDeviceToHost));
         } else if (H.precision == RTE_FP32) {
-            std::vector<float> uf(m * k), vf(n * k);
-            HIP_CHECK(hipMemcpy(uf.data(), B.U[block], sizeof(float) * m * k, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vf.data(), B.V[block], sizeof(float) * n * k, hipMemcpyDeviceToHost));
-            for (int64_t e = 0; e < m * k; ++e) ut[e] = uf[e];
-            for (int64_t e = 0; e < n * k; ++e) vt[e] = vf[e];
+            std::vector<float> uf(mu), vf(n * kp);
+            HIP_CHECK(hipMemcpy(uf.data(), B.U[block], sizeof(float) * mu, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vf.data(), B.V[block], sizeof(float) * n * kp, hipMemcpyDeviceToHost));
+            for (int64_t e = 0; e < mu; ++e) ut[e] = uf[e];
+            for (int64_t e = 0; e < n * kp; ++e) vt[e] = vf[e];
         } else {
             // BF16 hi + lo: the factor value is hi + lo
-            std::vector<uint16_t> uh(m * k), ul(m * k), vh(n * k), vl(n * k);
-            HIP_CHECK(hipMemcpy(uh.data(), B.U[block], 2 * m * k, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(ul.data(), B.Ulo[block], 2 * m * k, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vh.data(), B.V[block], 2 * n * k, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vl.data(), B.Vlo[block], 2 * n * k, hipMemcpyDeviceToHost));
+            std::vector<uint16_t> uh(mu), ul(mu), vh(n * kp), vl(n * kp);
+            HIP_CHECK(hipMemcpy(uh.data(), B.U[block], 2 * mu, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(ul.data(), B.Ulo[block], 2 * mu, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vh.data(), B.V[block], 2 * n * kp, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vl.data(), B.Vlo[block], 2 * n * kp, hipMemcpyDeviceToHost));
             auto wid = [](uint16_t h) {
                 uint32_t u = (uint32_t)h << 16;
                 float f;
                 std::memcpy(&f, &u, 4);
                 return (double)f;
             };
-            for (int64_t e = 0; e < m * k; ++e) ut[e] = wid(uh[e]) + wid(ul[e]);
-            for (int64_t e = 0; e < n * k; ++e) vt[e] = wid(vh[e]) + wid(vl[e]);
+            for (int64_t e = 0; e < mu; ++e) ut[e] = wid(uh[e]) + wid(ul[e]);
+            for (int64_t e = 0; e < n * kp; ++e) vt[e] = wid(vh[e]) + wid(vl[e]);
         }
-        for (int64_t l = 0; l < k; ++l) {
-            for (int64_t i = 0; i < m; ++i) U[i * k + l] = ut[l * m + i];
-            for (int64_t j = 0; j < n; ++j) V[j * k + l] = vt[j * k + l];   // stored row-major [n][k]
+        // U: target-leaf slices, each column-major [k][rp]
+        const Plan &P = *H.plan;
+        const int li0 = P.leaf_of(bl.t0);
+        for (int64_t i = 0; i < m; ++i) {
+            const int li = P.leaf_of(bl.t0 + i);
+            const int64_t rp = H.leaf_prp_h[li + 1] - H.leaf_prp_h[li];
+            const int64_t base = k * (H.leaf_prp_h[li] - H.leaf_prp_h[li0]) + (bl.t0 + i - P.leaf_start[li]);
+            for (int64_t l = 0; l < k; ++l) U[i * k + l] = ut[base + l * rp];
         }
+        for (int64_t l = 0; l < k; ++l)
+            for (int64_t j = 0; j < n; ++j) V[j * k + l] = vt[j * kp + l];
         return RTE_OK;
     });
 }

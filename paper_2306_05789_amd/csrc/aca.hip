@@ -361,41 +361,52 @@ struct CompactTask {
     const void *su, *sv;
     void *du, *dv;
     void *dul, *dvl;      // BF16 lo parts (mixed precision)
-    int32_t m, n, k, pad;
+    int64_t t0;           // first target row of the block
+    int32_t m, n, k, li0; // li0: target leaf of t0
 };
 
-// Final layout of a low-rank block: U^T [k][m] as produced, and V row-major
-// [n][k] (the k coefficients of one source point contiguous) for the matvec.
+// Final layout of a low-rank block: U in target-leaf slices, each column-major
+// [k][rp] (the matvec's phase B reads 4 consecutive rows of one column per
+// lane), and V row-major [n][kp], kp = pad4(k) (phase A reads 4 consecutive
+// coefficients of one source per lane).  Padding stays zero (the output is
+// cleared beforehand).
 template <typename T>
-__global__ __launch_bounds__(256) void k_compact(const CompactTask *__restrict__ tasks) {
+__global__ __launch_bounds__(256) void k_compact(const CompactTask *__restrict__ tasks, SliceMap sm) {
     const CompactTask t = tasks[blockIdx.x];
     const T *su = static_cast<const T *>(t.su), *sv = static_cast<const T *>(t.sv);
     T *du = static_cast<T *>(t.du), *dv = static_cast<T *>(t.dv);
-    const int64_t nu = (int64_t)t.k * t.m, nv = (int64_t)t.k * t.n;
-    for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) du[e] = su[e];
+    const int kp = (int)pad4(t.k);
+    const int64_t nu = (int64_t)t.k * t.m, nv = (int64_t)kp * t.n;
+    for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) {
+        const int64_t l = e / t.m, i = e - l * t.m;
+        du[slice_offset(sm, t.li0, t.t0 + i, t.k, l)] = su[e];
+    }
     for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
-        const int64_t j = e / t.k, l = e - j * t.k;
-        dv[e] = sv[l * t.n + j];
+        const int64_t j = e / kp, l = e - j * kp;
+        dv[e] = l < t.k ? sv[l * t.n + j] : (T)0;
     }
 }
 
 // Mixed precision: each factor element x (FP32) is stored as hi = bf16(x) and
 // lo = bf16(x - hi), in the same layouts; BF16 keeps FP32's exponent range.
-__global__ __launch_bounds__(256) void k_compact_bf16(const CompactTask *__restrict__ tasks) {
+__global__ __launch_bounds__(256) void k_compact_bf16(const CompactTask *__restrict__ tasks, SliceMap sm) {
     const CompactTask t = tasks[blockIdx.x];
     const float *su = static_cast<const float *>(t.su), *sv = static_cast<const float *>(t.sv);
     uint16_t *uh = static_cast<uint16_t *>(t.du), *vh = static_cast<uint16_t *>(t.dv);
     uint16_t *ul = static_cast<uint16_t *>(t.dul), *vl = static_cast<uint16_t *>(t.dvl);
-    const int64_t nu = (int64_t)t.k * t.m, nv = (int64_t)t.k * t.n;
+    const int kp = (int)pad4(t.k);
+    const int64_t nu = (int64_t)t.k * t.m, nv = (int64_t)kp * t.n;
     for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) {
+        const int64_t l = e / t.m, i = e - l * t.m;
+        const int64_t o = slice_offset(sm, t.li0, t.t0 + i, t.k, l);
         const float x = su[e];
         const uint16_t h = f2bf(x);
-        uh[e] = h;
-        ul[e] = f2bf(x - bf2f(h));
+        uh[o] = h;
+        ul[o] = f2bf(x - bf2f(h));
     }
     for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
-        const int64_t j = e / t.k, l = e - j * t.k;
-        const float x = sv[l * t.n + j];
+        const int64_t j = e / kp, l = e - j * kp;
+        const float x = l < t.k ? sv[l * t.n + j] : 0.0f;
         const uint16_t h = f2bf(x);
         vh[e] = h;
         vl[e] = f2bf(x - bf2f(h));
@@ -406,28 +417,52 @@ __global__ __launch_bounds__(256) void k_compact_bf16(const CompactTask *__restr
 
 namespace {
 
+SliceMap slice_map(const HMat &H) {
+    return {H.leaf_start.as<int64_t>(), H.leaf_prp.as<int64_t>(), (int)H.plan->tgt_leaves.size()};
+}
+
+int64_t round8(int64_t e) { return (e + 7) & ~(int64_t)7; }
+
+// padded rows of the target leaves covered by rows [t0, t1)
+int64_t padded_rows(const HMat &H, int64_t t0, int64_t t1) {
+    const Plan &P = *H.plan;
+    return H.leaf_prp_h[P.leaf_of(t1 - 1) + 1] - H.leaf_prp_h[P.leaf_of(t0)];
+}
+
 template <typename T>
 void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Block> &blocks, hipStream_t s) {
     if (blocks.empty()) return;
-    int64_t total = 0;
-    for (auto &b : blocks) total += (b.t1 - b.t0) * (b.s1 - b.s0);
-    DevBuf buf(sizeof(T) * (size_t)total);
+    const Plan &P = *H.plan;
+    const bool split = H.precision == RTE_MIXED_BF16;
+    const size_t esz = split ? sizeof(uint16_t) : sizeof(T);
+    int64_t total = 0, stored = 0;
+    for (auto &b : blocks) {
+        total += (b.t1 - b.t0) * (b.s1 - b.s0);
+        stored += padded_rows(H, b.t0, b.t1) * (b.s1 - b.s0);
+    }
+    DevBuf buf(esz * (size_t)stored), lo(split ? esz * (size_t)stored : 0);
+    HIP_CHECK(hipMemsetAsync(buf.p, 0, buf.bytes, s));   // the row padding stays zero
+    if (split) HIP_CHECK(hipMemsetAsync(lo.p, 0, lo.bytes, s));
     std::vector<FillTask> tasks;
     int64_t off = 0;
     for (auto &b : blocks) {
-        const int m = (int)(b.t1 - b.t0), n = (int)(b.s1 - b.s0);
-        T *p = buf.as<T>() + off;
+        const int m = (int)(b.t1 - b.t0), n = (int)(b.s1 - b.s0), li0 = P.leaf_of(b.t0);
+        char *p = static_cast<char *>(buf.p) + off * esz;
+        char *pl = split ? static_cast<char *>(lo.p) + off * esz : nullptr;
         B.dense_blocks.push_back(b);
         B.dense_ptr.push_back(p);
-        for (int64_t f = 0; f < (int64_t)m * n; f += kFillChunk) tasks.push_back({p, b.t0, b.s0, m, n, f});
-        off += (int64_t)m * n;
+        B.dense_lo.push_back(pl);
+        for (int64_t f = 0; f < (int64_t)m * n; f += kFillChunk) tasks.push_back({p, pl, b.t0, b.s0, m, n, li0, 0, f});
+        off += padded_rows(H, b.t0, b.t1) * n;
     }
-    B.fill_ms += dense_fill_launch<T>(*H.mesh, H.kind, kap, tasks, H.tgt_nat.as<int64_t>(), H.src_nat.as<int64_t>(), s);
+    B.fill_ms += dense_fill_launch<T>(*H.mesh, H.kind, kap, tasks, H.tgt_nat.as<int64_t>(), H.src_nat.as<int64_t>(),
+                                      slice_map(H), split, s);
     B.fill_launches += 1;
     B.dense_entries += total;
     B.evaluated += total;
-    B.bytes += (int64_t)buf.bytes;
+    B.bytes += (int64_t)(buf.bytes + lo.bytes);
     B.bufs.push_back(std::move(buf));
+    if (split) B.bufs.push_back(std::move(lo));
 }
 
 template <typename T>
@@ -542,10 +577,13 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     HIP_CHECK(hipStreamSynchronize(s));
     int64_t total = 0;
     for (int t = 0; t < nb; ++t)
-        if (rk[t] > 0) total += (int64_t)rk[t] * (tasks[t].m + tasks[t].n);
+        if (rk[t] > 0)
+            total += round8((int64_t)rk[t] * padded_rows(H, tasks[t].t0, tasks[t].t0 + tasks[t].m) + pad4(rk[t]) * tasks[t].n);
     const bool split = H.precision == RTE_MIXED_BF16;
     const size_t esz = split ? sizeof(uint16_t) : sizeof(T);
     DevBuf out(esz * (size_t)total), outlo(split ? esz * (size_t)total : 0);
+    HIP_CHECK(hipMemsetAsync(out.p, 0, out.bytes, s));   // slice and row padding stays zero
+    if (split) HIP_CHECK(hipMemsetAsync(outlo.p, 0, outlo.bytes, s));
     std::vector<CompactTask> ct;
     int64_t off = 0;
     for (int t = 0; t < nb; ++t) {
@@ -554,12 +592,13 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
             fallback.push_back(P.lowrank[b]);
             continue;
         }
-        const int64_t nu = (int64_t)rk[t] * tasks[t].m, nv = (int64_t)rk[t] * tasks[t].n;
+        const int64_t nu = (int64_t)rk[t] * padded_rows(H, tasks[t].t0, tasks[t].t0 + tasks[t].m),
+                      nv = pad4(rk[t]) * tasks[t].n;
         char *du = static_cast<char *>(out.p) + off * esz, *dv = du + nu * esz;
         char *dul = split ? static_cast<char *>(outlo.p) + off * esz : nullptr;
         char *dvl = split ? dul + nu * esz : nullptr;
-        ct.push_back({Us.as<T>() + tasks[t].uoff, Vs.as<T>() + tasks[t].voff, du, dv, dul, dvl, tasks[t].m,
-                      tasks[t].n, rk[t], 0});
+        ct.push_back({Us.as<T>() + tasks[t].uoff, Vs.as<T>() + tasks[t].voff, du, dv, dul, dvl, tasks[t].t0,
+                      tasks[t].m, tasks[t].n, rk[t], P.leaf_of(tasks[t].t0)});
         B.rank[b] = rk[t];
         B.U[b] = du;
         B.V[b] = dv;
@@ -567,13 +606,13 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
             B.Ulo[b] = dul;
             B.Vlo[b] = dvl;
         }
-        B.lr_entries += nu + nv;
-        off += nu + nv;
+        B.lr_entries += (int64_t)rk[t] * (tasks[t].m + tasks[t].n);
+        off += round8(nu + nv);   // every block starts 16-byte aligned for BF16, 32-byte for FP64
     }
     if (!ct.empty()) {
         DevBuf dct = upload(ct, s);
-        if (split) k_compact_bf16<<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>());
-        else k_compact<T><<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>());
+        if (split) k_compact_bf16<<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>(), slice_map(H));
+        else k_compact<T><<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>(), slice_map(H));
         HIP_LAUNCH_CHECK();
         HIP_CHECK(hipStreamSynchronize(s));
     }

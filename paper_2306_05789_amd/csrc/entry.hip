@@ -14,19 +14,27 @@ __global__ __launch_bounds__(256) void k_entries(EntryCtx<T> c, int64_t n, const
     out[k] = (double)entry<T, KIND>(c, rows[k], cols[k]);
 }
 
-// One task = up to kFillChunk consecutive entries of one dense block, stored
-// column-major (source column outer, target row inner).
-template <typename T, int KIND>
+// One task = up to kFillChunk consecutive entries (column-major) of one
+// dense block: the lanes of a wavefront march rays from a cluster of targets
+// to one source and write contiguous rows of the leaf-sliced storage.
+template <typename T, int KIND, bool SPLIT>
 __global__ __launch_bounds__(256) void k_dense_fill(EntryCtx<T> c, const FillTask *__restrict__ tasks,
                                                     const int64_t *__restrict__ tgt_nat,
-                                                    const int64_t *__restrict__ src_nat) {
+                                                    const int64_t *__restrict__ src_nat, SliceMap sm) {
     const FillTask tk = tasks[blockIdx.x];
-    T *out = static_cast<T *>(tk.out);
     const int64_t total = (int64_t)tk.m * tk.n;
     const int64_t end = min(total, tk.first + (int64_t)kFillChunk);
     for (int64_t e = tk.first + threadIdx.x; e < end; e += blockDim.x) {
         const int64_t jl = e / tk.m, il = e - jl * tk.m;
-        out[e] = entry<T, KIND>(c, tgt_nat[tk.t0 + il], src_nat[tk.s0 + jl]);
+        const T v = entry<T, KIND>(c, tgt_nat[tk.t0 + il], src_nat[tk.s0 + jl]);
+        const int64_t o = slice_offset(sm, tk.li0, tk.t0 + il, tk.n, jl);
+        if constexpr (SPLIT) {
+            const uint16_t h = f2bf((float)v);
+            static_cast<uint16_t *>(tk.out)[o] = h;
+            static_cast<uint16_t *>(tk.outlo)[o] = f2bf((float)v - bf2f(h));
+        } else {
+            static_cast<T *>(tk.out)[o] = v;
+        }
     }
 }
 
@@ -76,15 +84,21 @@ void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, con
 
 template <typename T>
 double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
-                         const int64_t *tgt_nat, const int64_t *src_nat, hipStream_t s) {
+                         const int64_t *tgt_nat, const int64_t *src_nat, SliceMap sm, bool split, hipStream_t s) {
     if (tasks.empty()) return 0.0;
     DevBuf dt = upload(tasks, s);
     auto c = make_ctx<T>(m, kappa);
     const unsigned grid = (unsigned)tasks.size();
+    const FillTask *d = dt.as<FillTask>();
     EventTimer tm(s);
     tm.start();
-    if (kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME><<<grid, 256, 0, s>>>(c, dt.as<FillTask>(), tgt_nat, src_nat);
-    else k_dense_fill<T, RTE_SURFACE><<<grid, 256, 0, s>>>(c, dt.as<FillTask>(), tgt_nat, src_nat);
+    if (split) {
+        if (kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, true><<<grid, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+        else k_dense_fill<T, RTE_SURFACE, true><<<grid, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+    } else {
+        if (kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, false><<<grid, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+        else k_dense_fill<T, RTE_SURFACE, false><<<grid, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+    }
     HIP_LAUNCH_CHECK();
     tm.stop();
     const double ms = tm.ms();
@@ -92,8 +106,8 @@ double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vec
     return ms;
 }
 template double dense_fill_launch<double>(const Mesh &, int, const double *, const std::vector<FillTask> &,
-                                          const int64_t *, const int64_t *, hipStream_t);
+                                          const int64_t *, const int64_t *, SliceMap, bool, hipStream_t);
 template double dense_fill_launch<float>(const Mesh &, int, const float *, const std::vector<FillTask> &,
-                                         const int64_t *, const int64_t *, hipStream_t);
+                                         const int64_t *, const int64_t *, SliceMap, bool, hipStream_t);
 
 }  // namespace rte

@@ -2,18 +2,23 @@
 // "Compression": after compression the fixed point only needs matrix-vector
 // products, O(N ln N) each).
 //
-// Phase A: t_b = V_b^T x[s-range of b] for every low-rank block b.  V is
-//          row-major [n][k]; a wavefront takes a chunk of source rows, lane
-//          l accumulates t_l and 64/kpad rows are read per step, so loads
-//          are contiguous and no per-l reduction is needed.  Blocks larger
-//          than one chunk write partial sums that a second pass adds in a
-//          fixed order.
-// Phase B: one workgroup per target leaf owns its rows: it sums the dense
-//          leaves of its block row and the row slices of every low-rank block
-//          that covers it, y = y0 + sum_seg D x or U t.  Each of the 4
-//          wavefronts takes every 4th segment; lanes are rows, so every load
-//          of D or U^T is contiguous; the 4 partial sums are added in a fixed
-//          order.  No atomics: results are bitwise reproducible.
+// Storage: every block row-major with rows padded to a multiple of 4.
+// Phase A: t_b = V_b^T x[s-range of b] for every low-rank block b.  A
+//          wavefront takes a chunk of source rows of V [n][kp]; a lane owns 4
+//          consecutive coefficients l..l+3 (one vector load per row) and the
+//          wavefront covers 64/LQ rows per step, so no per-l reduction is
+//          needed.  Blocks larger than one chunk write partial sums that a
+//          second pass adds in a fixed order.
+// Phase B: one workgroup per (band, target leaf) owns its rows: it sums the
+//          dense blocks of its block row and the leaf slices of every
+//          low-rank block that covers it, y = y0 + sum_seg D x or U t.  Each
+//          of the W wavefronts takes every W-th segment.  A segment slice is
+//          column-major [K][rp]; 16 lanes read 4 consecutive rows each of one
+//          column (contiguous) and the 4 lane groups take columns l, l+1,
+//          l+2, l+3, so lane use depends on the leaf size, not on the rank.
+//          Partial sums are added over the lane groups by a butterfly and over
+//          the W wavefronts in a fixed order.  No atomics: results are
+//          bitwise reproducible.
 #include <algorithm>
 
 #include "kernels.h"
@@ -21,12 +26,12 @@
 namespace rte {
 
 struct VtTask {
-    const void *V;      // first row of the chunk in V [n][k]
+    const void *V;      // first row of the chunk in V [n][kp]
     const void *Vlo;    // same position in the BF16 lo part (mixed precision)
     int64_t s0;         // source (cluster order) of the chunk's first row
     int64_t out;        // offset of the result (t buffer, or partial buffer if partial)
-    int32_t nj, k;      // rows in the chunk, rank
-    int32_t partial, pad;
+    int32_t nj, k;      // rows in the chunk, rank (row length kp = pad4(k))
+    int32_t partial, band;
 };
 
 struct VtReduce {
@@ -36,15 +41,15 @@ struct VtReduce {
 };
 
 struct Seg {
-    const void *data;   // column-major [K][ld] (dense: x columns; low rank: U^T rows)
-    const void *lo;     // BF16 lo part of U^T (mixed precision low rank)
+    const void *data;   // leaf slice, column-major [K][ld]: dense block columns or U of a low-rank block
+    const void *lo;     // BF16 lo part (mixed precision)
     int64_t coef_off;   // offset into x (dense: s0) or t (low rank: toff)
-    int32_t ld, row_off, K, is_lr;
+    int32_t ld, pad, K, is_lr;   // ld = pad4(leaf rows); K columns (dense: n, low rank: rank)
 };
 
 struct LeafWork {
     int64_t r0;         // first row (cluster order)
-    int32_t rows, seg0, seg1, pad;
+    int32_t rows, seg0, seg1, band;
 };
 
 struct MatvecPlan {
@@ -59,71 +64,97 @@ namespace {
 // factor storage: FP64, FP32, or BF16 (hi part, plus the lo part in MODE_ACC)
 enum : int { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
 
+// 4 consecutive elements starting at element i (i a multiple of 4, rows aligned)
 template <int ST, int MODE, typename A>
-__device__ __forceinline__ A load_factor(const void *p, const void *lo, int64_t i) {
-    if constexpr (ST == ST_F64) return (A) static_cast<const double *>(p)[i];
-    else if constexpr (ST == ST_F32) return (A) static_cast<const float *>(p)[i];
-    else {
-        A v = (A)bf2f(static_cast<const uint16_t *>(p)[i]);
-        if constexpr (MODE == kMatvecAccurate) v += (A)bf2f(static_cast<const uint16_t *>(lo)[i]);
-        return v;
+__device__ __forceinline__ void load4(const void *p, const void *lo, int64_t i, A v[4]) {
+    if constexpr (ST == ST_F64) {
+        const double2 *q = reinterpret_cast<const double2 *>(static_cast<const double *>(p) + i);
+        const double2 a = q[0], b = q[1];
+        v[0] = (A)a.x; v[1] = (A)a.y; v[2] = (A)b.x; v[3] = (A)b.y;
+    } else if constexpr (ST == ST_F32) {
+        const float4 a = *reinterpret_cast<const float4 *>(static_cast<const float *>(p) + i);
+        v[0] = (A)a.x; v[1] = (A)a.y; v[2] = (A)a.z; v[3] = (A)a.w;
+    } else {
+        const uint2 h = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(p) + i);
+        v[0] = (A)bf2f((uint16_t)(h.x & 0xFFFFu));
+        v[1] = (A)bf2f((uint16_t)(h.x >> 16));
+        v[2] = (A)bf2f((uint16_t)(h.y & 0xFFFFu));
+        v[3] = (A)bf2f((uint16_t)(h.y >> 16));
+        if constexpr (MODE == kMatvecAccurate) {
+            const uint2 l = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(lo) + i);
+            v[0] += (A)bf2f((uint16_t)(l.x & 0xFFFFu));
+            v[1] += (A)bf2f((uint16_t)(l.x >> 16));
+            v[2] += (A)bf2f((uint16_t)(l.y & 0xFFFFu));
+            v[3] += (A)bf2f((uint16_t)(l.y >> 16));
+        }
     }
-}
-
-template <typename A>
-__device__ __forceinline__ A wsum(A v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
 }
 
 template <int ST, int MODE, typename A, int NR>
 __global__ __launch_bounds__(256) void k_phase_a(const VtTask *__restrict__ tasks, int64_t ntask,
-                                                 const double *__restrict__ x, int64_t ldx, double *__restrict__ t,
-                                                 int64_t ldt, double *__restrict__ part, int64_t ldp, int r0, int nr) {
+                                                 const double *__restrict__ x, int64_t ldx, int64_t xbs,
+                                                 double *__restrict__ t, int64_t ldt, double *__restrict__ part,
+                                                 int64_t ldp, int r0, int nr) {
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= ntask) return;
     const VtTask tk = tasks[w];
     double *dst = tk.partial ? part : t;
     const int64_t ldd = tk.partial ? ldp : ldt;
-    for (int l0 = 0; l0 < tk.k; l0 += 64) {
-        const int kk = min(64, tk.k - l0);
-        int kp = 1;
-        while (kp < kk) kp <<= 1;
-        const int G = 64 / kp;
-        const int g = lane / kp, l = lane - g * kp;
-        const bool live = l < kk;
-        A acc[NR];
+    const int kp = (int)pad4(tk.k);
+    x += (int64_t)tk.band * xbs;
+    for (int l0 = 0; l0 < kp; l0 += 64) {
+        const int quads = min(64, kp - l0) / 4;   // vector loads per row in this slice
+        int LQ = 1;
+        while (LQ < quads) LQ <<= 1;
+        const int G = 64 / LQ;                     // rows per step
+        const int g = lane / LQ, q = lane - g * LQ;
+        const bool live = q < quads;
+        const int l = l0 + 4 * q;
+        A acc[NR][4];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] = (A)0;
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[r][u] = (A)0;
         int jj = g;
-        for (; jj + 3 * G < tk.nj; jj += 4 * G) {
-            A v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                v[u] = live ? load_factor<ST, MODE, A>(tk.V, tk.Vlo, (int64_t)(jj + u * G) * tk.k + l0 + l) : (A)0;
+        for (; jj + G < tk.nj; jj += 2 * G) {
+            A v0[4] = {(A)0, (A)0, (A)0, (A)0}, v1[4] = {(A)0, (A)0, (A)0, (A)0};
+            if (live) {
+                load4<ST, MODE, A>(tk.V, tk.Vlo, (int64_t)jj * kp + l, v0);
+                load4<ST, MODE, A>(tk.V, tk.Vlo, (int64_t)(jj + G) * kp + l, v1);
+            }
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (r < nr) {
                     const double *xr = x + (int64_t)(r0 + r) * ldx + tk.s0 + jj;
-                    acc[r] += v[0] * (A)xr[0] + v[1] * (A)xr[G] + v[2] * (A)xr[2 * G] + v[3] * (A)xr[3 * G];
+                    const A x0 = (A)xr[0], x1 = (A)xr[G];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[r][u] += v0[u] * x0 + v1[u] * x1;
                 }
             }
         }
-        for (; jj < tk.nj; jj += G) {
-            const A v = live ? load_factor<ST, MODE, A>(tk.V, tk.Vlo, (int64_t)jj * tk.k + l0 + l) : (A)0;
+        if (jj < tk.nj) {
+            A v0[4] = {(A)0, (A)0, (A)0, (A)0};
+            if (live) load4<ST, MODE, A>(tk.V, tk.Vlo, (int64_t)jj * kp + l, v0);
 #pragma unroll
-            for (int r = 0; r < NR; ++r)
-                if (r < nr) acc[r] += v * (A)x[(int64_t)(r0 + r) * ldx + tk.s0 + jj];
+            for (int r = 0; r < NR; ++r) {
+                if (r < nr) {
+                    const A x0 = (A)x[(int64_t)(r0 + r) * ldx + tk.s0 + jj];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[r][u] += v0[u] * x0;
+                }
+            }
         }
-        // add the G row groups (lanes l, l + kp, ...) in a fixed order
+        // add the G row groups (lanes q, q + LQ, ...) in a fixed order
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (r < nr) {
-                A a = acc[r];
-                for (int o = kp; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
-                if (g == 0 && live) dst[(int64_t)(r0 + r) * ldd + tk.out + l0 + l] = (double)a;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    A a = acc[r][u];
+                    for (int o = LQ; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
+                    if (g == 0 && live && l + u < tk.k) dst[(int64_t)(r0 + r) * ldd + tk.out + l + u] = (double)a;
+                }
             }
         }
     }
@@ -143,66 +174,130 @@ __global__ void k_phase_a_reduce(const VtReduce *__restrict__ red, int64_t nred,
     }
 }
 
-template <int ST, int MODE, typename A, int NR>
-__global__ __launch_bounds__(256) void k_phase_b(const LeafWork *__restrict__ leaves, const Seg *__restrict__ segs,
-                                                 const double *__restrict__ x, int64_t ldx,
-                                                 const double *__restrict__ t, int64_t ldt,
-                                                 const double *__restrict__ y0, double *__restrict__ y, int64_t ldy,
-                                                 int r0, int nr) {
-    constexpr int SD = ST == ST_F64 ? ST_F64 : ST_F32;   // dense leaves: FP64, else FP32
-    __shared__ A part[4][NR][64];
+// RPL rows per lane: a lane reads RPL consecutive rows of one column per load
+// (16 or 32 bytes); 64/RPL lanes cover a 64-row tile and RPL column groups
+// run side by side.
+template <int ST, int MODE, typename A, int RPL>
+__device__ __forceinline__ void load_rows(const void *p, const void *lo, int64_t i, A v[RPL]) {
+    if constexpr (RPL == 4) {
+        load4<ST, MODE, A>(p, lo, i, v);
+    } else {
+        static_assert(ST == ST_BF16 && RPL == 8, "8 rows per lane is used for BF16 storage");
+        const uint4 h = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(p) + i);
+        const uint32_t w[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[2 * k] = (A)bf2f((uint16_t)(w[k] & 0xFFFFu));
+            v[2 * k + 1] = (A)bf2f((uint16_t)(w[k] >> 16));
+        }
+        if constexpr (MODE == kMatvecAccurate) {
+            const uint4 l = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(lo) + i);
+            const uint32_t z[4] = {l.x, l.y, l.z, l.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[2 * k] += (A)bf2f((uint16_t)(z[k] & 0xFFFFu));
+                v[2 * k + 1] += (A)bf2f((uint16_t)(z[k] >> 16));
+            }
+        }
+    }
+}
+
+template <int ST> constexpr int rows_per_lane() { return ST == ST_BF16 ? 8 : 4; }
+
+template <int ST, int MODE, typename A, int NR, int W>
+__global__ __launch_bounds__(64 * W) void k_phase_b(const LeafWork *__restrict__ leaves, const Seg *__restrict__ segs,
+                                                    const double *__restrict__ x, int64_t ldx, int64_t xbs,
+                                                    const double *__restrict__ t, int64_t ldt,
+                                                    const double *__restrict__ y0, double *__restrict__ y,
+                                                    int64_t ldy, int64_t ybs, int r0, int nr) {
+    constexpr int RPL = rows_per_lane<ST>();
+    constexpr int LPC = 64 / RPL;   // lanes per column (a 64-row tile)
+    constexpr int CG = RPL;         // column groups
+    __shared__ A part[W][NR][64];
     const LeafWork lw = leaves[blockIdx.x];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int rq = lane % LPC, cg = lane / LPC;
+    x += (int64_t)lw.band * xbs;
+    y += (int64_t)lw.band * ybs;
+    if (y0) y0 += (int64_t)lw.band * ybs;
     for (int rb = 0; rb < lw.rows; rb += 64) {
-        const int row = rb + lane;
-        const bool live = row < lw.rows;
-        A acc[NR];
+        const bool rlive = rb + RPL * rq < lw.rows;
+        const int64_t cb = rb + RPL * rq;   // first row of this lane within a column
+        A acc[RPL][NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] = (A)0;
-        for (int s = lw.seg0 + wid; s < lw.seg1; s += 4) {
-            const Seg sg = segs[s];
-            const int64_t base = sg.row_off + row;
-            const double *cb = sg.is_lr ? t : x;
-            const int64_t ldc = sg.is_lr ? ldt : ldx;
-            const double *cf = cb + sg.coef_off;
-            auto ld = [&](int64_t i) -> A {
-                return sg.is_lr ? load_factor<ST, MODE, A>(sg.data, sg.lo, i) : load_factor<SD, 0, A>(sg.data, nullptr, i);
-            };
-            int l = 0;
-            for (; l + 4 <= sg.K; l += 4) {
-                A d0 = (A)0, d1 = (A)0, d2 = (A)0, d3 = (A)0;
-                if (live) {
-                    d0 = ld(base + (int64_t)(l + 0) * sg.ld);
-                    d1 = ld(base + (int64_t)(l + 1) * sg.ld);
-                    d2 = ld(base + (int64_t)(l + 2) * sg.ld);
-                    d3 = ld(base + (int64_t)(l + 3) * sg.ld);
+        for (int u = 0; u < RPL; ++u)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[u][r] = (A)0;
+        int s = lw.seg0 + wid;
+        Seg sg;
+        if (s < lw.seg1) sg = segs[s];
+        for (; s < lw.seg1; s += W) {
+            // the next descriptor is fetched while this segment streams
+            const Seg cur = sg;
+            if (s + W < lw.seg1) sg = segs[s + W];
+            const double *cf = (cur.is_lr ? t : x) + cur.coef_off;
+            const int64_t ldc = cur.is_lr ? ldt : ldx;
+            int l = cg;
+            for (; l + CG < cur.K; l += 2 * CG) {
+                A d0[RPL], d1[RPL];
+#pragma unroll
+                for (int u = 0; u < RPL; ++u) d0[u] = d1[u] = (A)0;
+                if (rlive) {
+                    load_rows<ST, MODE, A, RPL>(cur.data, cur.lo, (int64_t)l * cur.ld + cb, d0);
+                    load_rows<ST, MODE, A, RPL>(cur.data, cur.lo, (int64_t)(l + CG) * cur.ld + cb, d1);
                 }
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     if (r < nr) {
-                        const double *c = cf + (int64_t)(r0 + r) * ldc + l;
-                        acc[r] += d0 * (A)c[0] + d1 * (A)c[1] + d2 * (A)c[2] + d3 * (A)c[3];
+                        const A c0 = (A)cf[(int64_t)(r0 + r) * ldc + l], c1 = (A)cf[(int64_t)(r0 + r) * ldc + l + CG];
+#pragma unroll
+                        for (int u = 0; u < RPL; ++u) acc[u][r] += d0[u] * c0 + d1[u] * c1;
                     }
                 }
             }
-            for (; l < sg.K; ++l) {
-                const A d = live ? ld(base + (int64_t)l * sg.ld) : (A)0;
+            if (l < cur.K) {
+                A d0[RPL];
 #pragma unroll
-                for (int r = 0; r < NR; ++r)
-                    if (r < nr) acc[r] += d * (A)cf[(int64_t)(r0 + r) * ldc + l];
+                for (int u = 0; u < RPL; ++u) d0[u] = (A)0;
+                if (rlive) load_rows<ST, MODE, A, RPL>(cur.data, cur.lo, (int64_t)l * cur.ld + cb, d0);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if (r < nr) {
+                        const A c0 = (A)cf[(int64_t)(r0 + r) * ldc + l];
+#pragma unroll
+                        for (int u = 0; u < RPL; ++u) acc[u][r] += d0[u] * c0;
+                    }
+                }
             }
         }
+        // sum over the column groups (same order on every lane)
 #pragma unroll
-        for (int r = 0; r < NR; ++r) part[wid][r][lane] = acc[r];
+        for (int u = 0; u < RPL; ++u)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                A a = acc[u][r];
+#pragma unroll
+                for (int o = LPC; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
+                acc[u][r] = a;
+            }
+        if (cg == 0) {
+#pragma unroll
+            for (int u = 0; u < RPL; ++u)
+#pragma unroll
+                for (int r = 0; r < NR; ++r) part[wid][r][RPL * rq + u] = acc[u][r];
+        }
         __syncthreads();
-        if (wid == 0 && live) {
+        const int row = rb + lane;
+        if (wid == 0 && row < lw.rows) {
             const int64_t gr = lw.r0 + row;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (r < nr) {
                     double v = y0 ? y0[(int64_t)(r0 + r) * ldy + gr] : 0.0;
-                    v += (double)(((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane]);
-                    y[(int64_t)(r0 + r) * ldy + gr] = v;
+                    A sum = part[0][r][lane];
+#pragma unroll
+                    for (int w = 1; w < W; ++w) sum += part[w][r][lane];
+                    y[(int64_t)(r0 + r) * ldy + gr] = v + (double)sum;
                 }
             }
         }
@@ -231,17 +326,18 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
                   hipStream_t s) {
     double *part = tb + mp.ktot * (int64_t)nrhs;   // the workspace holds t, then the partials
     const int64_t ldp = std::max<int64_t>(mp.npart, 1);
+    const int64_t xbs = (int64_t)nrhs * mp.n_src, ybs = (int64_t)nrhs * mp.n_tgt;
     for (int r0 = 0; r0 < nrhs; r0 += 16) {
         const int nr = std::min(16, nrhs - r0);
         if (mp.n_vt) {
             const unsigned ga = (unsigned)((mp.n_vt + 3) / 4);
             const VtTask *vt = mp.vt.as<VtTask>();
             if (nr == 1)
-                k_phase_a<ST, MODE, A, 1><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
+                k_phase_a<ST, MODE, A, 1><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, xbs, tb, mp.ktot, part, ldp, r0, nr);
             else if (nr <= 4)
-                k_phase_a<ST, MODE, A, 4><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
+                k_phase_a<ST, MODE, A, 4><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, xbs, tb, mp.ktot, part, ldp, r0, nr);
             else
-                k_phase_a<ST, MODE, A, 16><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, tb, mp.ktot, part, ldp, r0, nr);
+                k_phase_a<ST, MODE, A, 16><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, xbs, tb, mp.ktot, part, ldp, r0, nr);
             HIP_LAUNCH_CHECK();
             if (mp.n_red) {
                 dim3 grid((unsigned)((mp.n_red_threads + 63) / 64), (unsigned)mp.n_red);
@@ -253,11 +349,14 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
         const LeafWork *lw = mp.leaf.as<LeafWork>();
         const Seg *sg = mp.seg.as<Seg>();
         if (nr == 1)
-            k_phase_b<ST, MODE, A, 1><<<gb, 256, 0, s>>>(lw, sg, x, mp.n_src, tb, mp.ktot, y0, y, mp.n_tgt, r0, nr);
+            k_phase_b<ST, MODE, A, 1, 8><<<gb, 512, 0, s>>>(lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt,
+                                                          ybs, r0, nr);
         else if (nr <= 4)
-            k_phase_b<ST, MODE, A, 4><<<gb, 256, 0, s>>>(lw, sg, x, mp.n_src, tb, mp.ktot, y0, y, mp.n_tgt, r0, nr);
+            k_phase_b<ST, MODE, A, 4, 8><<<gb, 512, 0, s>>>(lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt,
+                                                          ybs, r0, nr);
         else
-            k_phase_b<ST, MODE, A, 16><<<gb, 256, 0, s>>>(lw, sg, x, mp.n_src, tb, mp.ktot, y0, y, mp.n_tgt, r0, nr);
+            k_phase_b<ST, MODE, A, 16, 4><<<gb, 256, 0, s>>>(lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt,
+                                                           ybs, r0, nr);
         HIP_LAUNCH_CHECK();
     }
 }
@@ -267,42 +366,89 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
 HMat::HMat() = default;
 HMat::~HMat() = default;
 
-void matvec_build(HMat &H, int band, hipStream_t s) {
+namespace {
+
+// Work lists of y = H x for the bands in `bands`, all in one launch per phase:
+// band b's vectors sit at x + b' * nrhs * N_src (b' its position in the list),
+// and its t coefficients follow those of the previous bands.
+std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &bands, hipStream_t s) {
     const Plan &P = *H.plan;
-    const BandStore &B = H.bands[band];
     auto mp = std::make_unique<MatvecPlan>();
     mp->n_src = (int64_t)P.src_nat.size();
     mp->n_tgt = (int64_t)P.tgt_nat.size();
     std::vector<VtTask> vt;
     std::vector<VtReduce> red;
-    std::vector<int64_t> toff(P.lowrank.size(), -1);
     int64_t ktot = 0, npart = 0, maxk = 0;
     // about this many bytes of V per wavefront task
     const int64_t chunk_bytes = 48 * 1024;
     const int64_t esz = H.precision == RTE_FP64 ? 8 : H.precision == RTE_FP32 ? 4 : 2;
-    for (size_t b = 0; b < P.lowrank.size(); ++b) {
-        if (B.rank[b] <= 0) continue;
-        const Block &bl = P.lowrank[b];
-        const int32_t k = B.rank[b];
-        const int64_t n = bl.s1 - bl.s0;
-        toff[b] = ktot;
-        const int64_t rows = std::max<int64_t>(64, chunk_bytes / (k * esz));
-        const int64_t chunks = (n + rows - 1) / rows;
-        const char *V = static_cast<const char *>(B.V[b]);
-        const char *Vl = static_cast<const char *>(B.Vlo.empty() ? nullptr : B.Vlo[b]);
-        if (chunks == 1) {
-            vt.push_back({V, Vl, bl.s0, ktot, (int32_t)n, k, 0, 0});
-        } else {
-            red.push_back({npart, ktot, (int32_t)chunks, k});
-            for (int64_t c = 0; c < chunks; ++c) {
-                const int64_t j0 = c * rows, nj = std::min(rows, n - j0);
-                vt.push_back({V + j0 * k * esz, Vl ? Vl + j0 * k * esz : nullptr, bl.s0 + j0, npart + c * k,
-                              (int32_t)nj, k, 1, 0});
+    const auto &leaves = P.tgt_leaves;
+    std::vector<int64_t> starts;
+    for (auto &lf : leaves) starts.push_back(lf.first);
+    auto leaf_of = [&](int64_t row) {
+        return (int64_t)(std::upper_bound(starts.begin(), starts.end(), row) - starts.begin()) - 1;
+    };
+    std::vector<Seg> segs;
+    std::vector<LeafWork> lw;
+    for (int bi = 0; bi < (int)bands.size(); ++bi) {
+        const BandStore &B = H.bands[bands[bi]];
+        std::vector<int64_t> toff(P.lowrank.size(), -1);
+        for (size_t b = 0; b < P.lowrank.size(); ++b) {
+            if (B.rank[b] <= 0) continue;
+            const Block &bl = P.lowrank[b];
+            const int32_t k = B.rank[b];
+            const int64_t n = bl.s1 - bl.s0;
+            toff[b] = ktot;
+            const int64_t rows = std::max<int64_t>(64, chunk_bytes / (pad4(k) * esz));
+            const int64_t chunks = (n + rows - 1) / rows;
+            const char *V = static_cast<const char *>(B.V[b]);
+            const char *Vl = static_cast<const char *>(B.Vlo.empty() ? nullptr : B.Vlo[b]);
+            if (chunks == 1) {
+                vt.push_back({V, Vl, bl.s0, ktot, (int32_t)n, k, 0, bi});
+            } else {
+                red.push_back({npart, ktot, (int32_t)chunks, k});
+                for (int64_t c = 0; c < chunks; ++c) {
+                    const int64_t j0 = c * rows, nj = std::min(rows, n - j0);
+                    vt.push_back({V + j0 * pad4(k) * esz, Vl ? Vl + j0 * pad4(k) * esz : nullptr, bl.s0 + j0,
+                                  npart + c * k, (int32_t)nj, k, 1, bi});
+                }
+                npart += chunks * k;
             }
-            npart += chunks * k;
+            maxk = std::max<int64_t>(maxk, k);
+            ktot += k;
         }
-        maxk = std::max<int64_t>(maxk, k);
-        ktot += k;
+        std::vector<std::vector<Seg>> per(leaves.size());
+        // one segment per (block, target leaf slice); slice li of a block with K
+        // columns starts K * (prp[li] - prp[li0]) elements after the block
+        auto slices = [&](const Block &bl, const void *hi, const void *lo, int64_t K, int64_t coef, int is_lr) {
+            const int64_t li0 = leaf_of(bl.t0);
+            for (int64_t li = li0; li < (int64_t)leaves.size() && leaves[li].first < bl.t1; ++li) {
+                const int64_t off = K * (H.leaf_prp_h[li] - H.leaf_prp_h[li0]) * esz;
+                const int32_t rp = (int32_t)(H.leaf_prp_h[li + 1] - H.leaf_prp_h[li]);
+                per[li].push_back({static_cast<const char *>(hi) + off,
+                                   lo ? static_cast<const char *>(lo) + off : nullptr, coef, rp, 0, (int32_t)K,
+                                   is_lr});
+            }
+        };
+        for (size_t d = 0; d < B.dense_blocks.size(); ++d) {
+            const Block &bl = B.dense_blocks[d];
+            slices(bl, B.dense_ptr[d], B.dense_lo[d], bl.s1 - bl.s0, bl.s0, 0);
+        }
+        for (size_t b = 0; b < P.lowrank.size(); ++b) {
+            if (B.rank[b] <= 0) continue;
+            slices(P.lowrank[b], B.U[b], B.Ulo.empty() ? nullptr : B.Ulo[b], B.rank[b], toff[b], 1);
+        }
+        for (size_t li = 0; li < leaves.size(); ++li) {
+            LeafWork w{};
+            w.r0 = leaves[li].first;
+            w.rows = (int32_t)(leaves[li].second - leaves[li].first);
+            w.seg0 = (int32_t)segs.size();
+            segs.insert(segs.end(), per[li].begin(), per[li].end());
+            w.seg1 = (int32_t)segs.size();
+            w.band = bi;
+            lw.push_back(w);
+            mp->max_rows = std::max(mp->max_rows, w.rows);
+        }
     }
     // large tasks first so that long wavefronts start early
     std::stable_sort(vt.begin(), vt.end(), [](const VtTask &a, const VtTask &b) {
@@ -314,49 +460,44 @@ void matvec_build(HMat &H, int band, hipStream_t s) {
     mp->n_red = (int64_t)red.size();
     mp->n_red_threads = maxk;
     mp->red = upload(red, s);
-    const auto &leaves = P.tgt_leaves;
-    std::vector<int64_t> starts;
-    for (auto &lf : leaves) starts.push_back(lf.first);
-    auto leaf_of = [&](int64_t row) {
-        return (int64_t)(std::upper_bound(starts.begin(), starts.end(), row) - starts.begin()) - 1;
-    };
-    std::vector<std::vector<Seg>> per(leaves.size());
-    for (size_t d = 0; d < B.dense_blocks.size(); ++d) {
-        const Block &bl = B.dense_blocks[d];
-        const int32_t m = (int32_t)(bl.t1 - bl.t0);
-        for (int64_t li = leaf_of(bl.t0); li < (int64_t)leaves.size() && leaves[li].first < bl.t1; ++li) {
-            per[li].push_back({B.dense_ptr[d], nullptr, bl.s0, m, (int32_t)(leaves[li].first - bl.t0),
-                               (int32_t)(bl.s1 - bl.s0), 0});
-        }
-    }
-    // a dense block spanning several leaves is read once per leaf as a column slice
-    for (size_t b = 0; b < P.lowrank.size(); ++b) {
-        if (B.rank[b] <= 0) continue;
-        const Block &bl = P.lowrank[b];
-        const int32_t m = (int32_t)(bl.t1 - bl.t0);
-        for (int64_t li = leaf_of(bl.t0); li < (int64_t)leaves.size() && leaves[li].first < bl.t1; ++li)
-            per[li].push_back({B.U[b], B.Ulo.empty() ? nullptr : B.Ulo[b], toff[b], m,
-                               (int32_t)(leaves[li].first - bl.t0), B.rank[b], 1});
-    }
-    std::vector<Seg> segs;
-    std::vector<LeafWork> lw;
-    for (size_t li = 0; li < leaves.size(); ++li) {
-        LeafWork w{};
-        w.r0 = leaves[li].first;
-        w.rows = (int32_t)(leaves[li].second - leaves[li].first);
-        w.seg0 = (int32_t)segs.size();
-        segs.insert(segs.end(), per[li].begin(), per[li].end());
-        w.seg1 = (int32_t)segs.size();
-        lw.push_back(w);
-        mp->max_rows = std::max(mp->max_rows, w.rows);
-    }
     mp->n_leaf = (int64_t)lw.size();
     mp->vt = upload(vt, s);
     mp->seg = upload(segs, s);
     mp->leaf = upload(lw, s);
     HIP_CHECK(hipStreamSynchronize(s));
+    return mp;
+}
+
+void launch_plan(const HMat &H, const MatvecPlan &mp, int nrhs, const double *x_c, double *y_c, const double *y0_c,
+                 double *tbuf, hipStream_t s, int mode) {
+    if (H.precision == RTE_FP64) launch_typed<ST_F64, 0, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    else if (H.precision == RTE_FP32) launch_typed<ST_F32, 0, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    else if (mode == kMatvecAccurate) launch_typed<ST_BF16, kMatvecAccurate, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    else launch_typed<ST_BF16, kMatvecLow, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+}
+
+}  // namespace
+
+void matvec_build(HMat &H, int band, hipStream_t s) {
     if ((int)H.mv.size() <= band) H.mv.resize(band + 1);
-    H.mv[band] = std::move(mp);
+    H.mv[band] = build_plan(H, {band}, s);
+}
+
+void matvec_build_all(HMat &H, hipStream_t s) {
+    if (H.n_bands == 1) return;   // the band-0 plan serves
+    std::vector<int> all(H.n_bands);
+    for (int b = 0; b < H.n_bands; ++b) all[b] = b;
+    H.mv_all = build_plan(H, all, s);
+}
+
+int64_t matvec_ktot_all(const HMat &H) {
+    const MatvecPlan &mp = H.mv_all ? *H.mv_all : *H.mv[0];
+    return mp.ktot + mp.npart;
+}
+
+void matvec_launch_all(const HMat &H, int nrhs, const double *x_c, double *y_c, const double *y0_c, double *tbuf,
+                       hipStream_t s, int mode) {
+    launch_plan(H, H.mv_all ? *H.mv_all : *H.mv[0], nrhs, x_c, y_c, y0_c, tbuf, s, mode);
 }
 
 // workspace doubles per right-hand side: t, then the partial sums of chunked blocks
@@ -364,11 +505,7 @@ int64_t matvec_ktot(const HMat &H, int band) { return H.mv[band]->ktot + H.mv[ba
 
 void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                       double *tbuf, hipStream_t s, int mode) {
-    const MatvecPlan &mp = *H.mv[band];
-    if (H.precision == RTE_FP64) launch_typed<ST_F64, 0, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
-    else if (H.precision == RTE_FP32) launch_typed<ST_F32, 0, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
-    else if (mode == kMatvecAccurate) launch_typed<ST_BF16, kMatvecAccurate, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
-    else launch_typed<ST_BF16, kMatvecLow, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    launch_plan(H, *H.mv[band], nrhs, x_c, y_c, y0_c, tbuf, s, mode);
 }
 
 void matvec_launch(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,

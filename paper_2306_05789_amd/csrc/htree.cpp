@@ -114,6 +114,11 @@ struct BlockBuilder {
 
 }  // namespace
 
+int Plan::leaf_of(int64_t row) const {
+    // leaf_start is increasing; the last entry is N_tgt
+    return (int)(std::upper_bound(leaf_start.begin(), leaf_start.end() - 1, row) - leaf_start.begin()) - 1;
+}
+
 ClusterTree build_cluster_tree(const std::vector<double> &pts, int leaf_size) {
     ClusterTree T;
     int64_t n = (int64_t)pts.size() / 3;
@@ -149,6 +154,11 @@ std::unique_ptr<Plan> build_plan(const Mesh &m, const rte_hmat_opts_t &o) {
     BlockBuilder bb{P->tgt, P->src, o.eta, !o.dense, *P};
     bb.rec(0, 0);
     for (int id : P->tgt.leaves) P->tgt_leaves.push_back({P->tgt.nodes[id].start, P->tgt.nodes[id].stop});
+    P->leaf_start.push_back(0);
+    for (auto &lf : P->tgt_leaves) {
+        P->leaf_start.back() = lf.first;
+        P->leaf_start.push_back(lf.second);
+    }
     return P;
 }
 

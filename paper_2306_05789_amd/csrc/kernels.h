@@ -19,11 +19,37 @@ __host__ __device__ __forceinline__ float bf2f(uint16_t h) {
 }
 constexpr int kAcaMaxRank = 192;   // rank cap of one ACA block before dense fallback
 
+// Stored blocks are row-major with the row length padded to a multiple of 4
+// elements (zeros), so the matvec reads 4-element vectors per lane.
+__host__ __device__ constexpr int64_t pad4(int64_t k) { return (k + 3) & ~(int64_t)3; }
+
+// Target-leaf tables of a plan on the device: where a row of a block lands in
+// its leaf-sliced storage (see the storage notes in rte_internal.h).
+struct SliceMap {
+    const int64_t *start;   // [n_leaves + 1]
+    const int64_t *prp;     // [n_leaves + 1]
+    int nleaf;
+};
+
+// element offset of (row `grow`, column `col`) in a block with K columns whose
+// first target leaf is li0
+__device__ __forceinline__ int64_t slice_offset(const SliceMap &sm, int li0, int64_t grow, int64_t K, int64_t col) {
+    int lo = li0, hi = sm.nleaf;   // start[lo] <= grow < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sm.start[mid] <= grow) lo = mid;
+        else hi = mid;
+    }
+    const int64_t rp = sm.prp[lo + 1] - sm.prp[lo];
+    return K * (sm.prp[lo] - sm.prp[li0]) + col * rp + (grow - sm.start[lo]);
+}
+
 struct FillTask {
-    void *out;        // first element of the block's column-major storage
+    void *out;        // first element of the block (leaf-sliced, K = n columns)
+    void *outlo;      // BF16 lo part (mixed precision), else null
     int64_t t0, s0;   // block ranges start, in cluster order
-    int32_t m, n;
-    int64_t first;    // first entry of this task
+    int32_t m, n, li0, pad;
+    int64_t first;    // first entry (column-major over m x n) of this task
 };
 
 struct AcaTask {
@@ -59,9 +85,9 @@ struct EventTimer {
 template <typename T> struct EntryCtx;
 template <typename T> EntryCtx<T> make_ctx(const Mesh &m, const T *kappa);
 void to_float(const double *in, float *out, int64_t n, hipStream_t s);
-// returns the HIP-event time of the fill launch in ms
+// returns the HIP-event time of the fill launch in ms; split: write BF16 hi/lo
 template <typename T>
 double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
-                         const int64_t *tgt_nat, const int64_t *src_nat, hipStream_t s);
+                         const int64_t *tgt_nat, const int64_t *src_nat, SliceMap sm, bool split, hipStream_t s);
 
 }  // namespace rte

@@ -125,6 +125,8 @@ struct Plan {
     std::vector<int64_t> tgt_nat, src_nat;   // cluster position -> natural vertex id
     std::vector<Block> dense, lowrank;
     std::vector<std::pair<int64_t, int64_t>> tgt_leaves;   // [start, stop) of target leaves
+    std::vector<int64_t> leaf_start;   // [n_leaves + 1] first row of each target leaf, then N_tgt
+    int leaf_of(int64_t row) const;    // target leaf holding a row (cluster order)
 };
 
 std::unique_ptr<Plan> build_plan(const Mesh &m, const rte_hmat_opts_t &opts);
@@ -166,19 +168,24 @@ DevBuf upload(const std::vector<T> &v, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- H-matrix storage
-// Dense leaves are stored column-major (for each source column, the block's
-// rows contiguous); a low-rank block as U^T [rank][m] and V row-major
-// [n][rank], so every stream the matvec reads is contiguous along the lanes.  Mixed
-// precision keeps the factors as BF16 hi and lo parts with one FP32 scale per
-// block (value = scale * (hi + lo)); dense leaves are FP32 there.
+// Storage of a block whose target range covers target leaves li0..li1-1:
+//  - the row side (a dense block's columns, or U of a low-rank block with K =
+//    rank columns) is split into one slice per target leaf; slice s is
+//    column-major [K][rp_s], rp_s = leaf rows rounded up to the row unit
+//    (8 for BF16 storage, else 4), and the slices follow each other (slice s
+//    starts K * (prp[li0 + s] - prp[li0]) elements in);
+//  - V of a low-rank block is row-major [n][pad4(rank)].
+// Padding is zero.  Mixed precision stores every element x as BF16 hi =
+// bf16(x) and lo = bf16(x - hi) in two arrays of the same layout (BF16
+// keeps FP32's exponent range, so no scale is needed).
 struct BandStore {
     std::vector<DevBuf> bufs;               // owning storage chunks
     std::vector<Block> dense_blocks;        // plan dense leaves, then ACA fallbacks
     std::vector<const void *> dense_ptr;    // per dense block
+    std::vector<const void *> dense_lo;     // per dense block: BF16 lo part (mixed precision)
     std::vector<int32_t> rank;              // per plan LR block; -1 = stored dense (fallback)
     std::vector<const void *> U, V;         // per plan LR block (nullptr for fallbacks)
     std::vector<const void *> Ulo, Vlo;     // mixed precision: BF16 lo parts
-    std::vector<float> scale;               // mixed precision: per LR block scale
     int64_t bytes = 0, dense_entries = 0, lr_entries = 0, evaluated = 0, aca_entries = 0;
     double aca_ms = 0.0, fill_ms = 0.0, aca_entry_ms = 0.0;   // HIP-event kernel times
     int aca_launches = 0, fill_launches = 0, aca_entry_launches = 0;
@@ -196,7 +203,10 @@ struct HMat {
     DevBuf tgt_nat, src_nat;        // int64: cluster position -> natural id (surface sources: vertex ids)
     DevBuf src_pos;                 // int64: cluster position -> position in the caller's source vector
     DevBuf kappa_c;                 // FP64 [n_bands][N_tgt] kappa at the targets, cluster order
+    std::vector<int64_t> leaf_prp_h;   // [n_leaves + 1] prefix sums of the padded leaf rows
+    DevBuf leaf_start, leaf_prp;       // device copies of the target-leaf tables
     std::vector<std::unique_ptr<MatvecPlan>> mv;   // per band
+    std::unique_ptr<MatvecPlan> mv_all;            // all bands in one launch (multi-band matrices)
     rte_hmat_stats_t stats{};
     int device = 0;
     HMat();
@@ -219,6 +229,12 @@ void matvec_launch(const HMat &H, int band, int nrhs, const double *x_c, double 
 void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                       double *tbuf, hipStream_t s, int mode = kMatvecAccurate);
 int64_t matvec_ktot(const HMat &H, int band);
+// All bands at once: x, y, y0 are [n_bands][nrhs][N] (band-major); workspace
+// nrhs * matvec_ktot_all(H) doubles.  Does not synchronise.
+void matvec_build_all(HMat &H, hipStream_t s);
+int64_t matvec_ktot_all(const HMat &H);
+void matvec_launch_all(const HMat &H, int nrhs, const double *x_c, double *y_c, const double *y0_c, double *tbuf,
+                       hipStream_t s, int mode = kMatvecAccurate);
 void permute_gather(const int64_t *perm, int64_t n, int nrhs, int64_t ld_in, int64_t ld_out, const double *in,
                     double *out, hipStream_t s);
 void permute_scatter(const int64_t *perm, int64_t n, int nrhs, int64_t ld_in, int64_t ld_out, const double *in,
