@@ -218,13 +218,38 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
         H.tgt_nat = upload(P.tgt_nat, s);
         H.src_nat = upload(P.src_nat, s);
         H.src_pos = upload(opts->kind == RTE_VOLUME ? P.tgt_nat : P.src.perm, s);
-        // leaf slices are padded to 8 rows for BF16 storage (16-byte loads), else 4
-        const int64_t unit = H.precision == RTE_MIXED_BF16 ? 8 : 4;
+        // FP64 / FP32 slices are column-major with rows padded to 4 (vector
+        // loads along the rows); BF16 slices are K-grouped (8 columns of a row
+        // contiguous) with unpadded rows and sources counted in stored
+        // coordinates in which every source leaf is rounded up to 8
+        const bool kgrouped = H.precision == RTE_MIXED_BF16;
+        H.kgroup = kgrouped ? 8 : 1;
+        const int64_t unit = kgrouped ? 1 : 4;
         H.leaf_prp_h.assign(1, 0);
         for (auto &lf : P.tgt_leaves)
             H.leaf_prp_h.push_back(H.leaf_prp_h.back() + (lf.second - lf.first + unit - 1) / unit * unit);
         H.leaf_start = upload(P.leaf_start, s);
         H.leaf_prp = upload(H.leaf_prp_h, s);
+        {
+            const int64_t ns = (int64_t)P.src_nat.size();
+            H.src_p_h.assign(ns + 1, 0);
+            std::vector<int64_t> pmap;
+            int64_t pos = 0;
+            for (int id : P.src.leaves) {
+                const ClusterNode &nd = P.src.nodes[id];
+                for (int64_t j = nd.start; j < nd.stop; ++j) {
+                    H.src_p_h[j] = pos + (j - nd.start);
+                    pmap.push_back(j);
+                }
+                const int64_t w = kgrouped ? ((nd.stop - nd.start + 7) & ~(int64_t)7) : nd.stop - nd.start;
+                for (int64_t e = nd.stop - nd.start; e < w; ++e) pmap.push_back(-1);
+                pos += w;
+            }
+            H.src_p_h[ns] = pos;
+            H.n_src_p = pos;
+            H.src_p = upload(H.src_p_h, s);
+            H.src_pmap = upload(pmap, s);
+        }
         H.kappa_c.alloc(sizeof(double) * (size_t)m.N * n_bands);
         permute_gather(H.tgt_nat.as<int64_t>(), m.N, n_bands, m.N, m.N, kappa, H.kappa_c.as<double>(), s);
         H.bands.resize(n_bands);
@@ -328,26 +353,28 @@ rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, i
         *mo = m;
         *no = n;
         if (!U || !V || k <= 0) return RTE_OK;
-        // U: k * (padded rows of the block's target leaves); V row-major [n][kp]
-        const int64_t kp = (k + 3) & ~(int64_t)3;
-        const int64_t mu = k * (H.leaf_prp_h[H.plan->leaf_of(bl.t1 - 1) + 1] - H.leaf_prp_h[H.plan->leaf_of(bl.t0)]);
-        std::vector<double> ut(mu), vt(n * kp);
+        const Plan &P = *H.plan;
+        const int64_t g = H.kgroup, kgp = (k + g - 1) / g * g;
+        const int li0 = P.leaf_of(bl.t0);
+        const int64_t mu = kgp * (H.leaf_prp_h[P.leaf_of(bl.t1 - 1) + 1] - H.leaf_prp_h[li0]);
+        const int64_t nv = g > 1 ? H.pwidth(bl.s0, bl.s1) * k : n * ((k + 3) & ~(int64_t)3);
+        std::vector<double> ut(mu), vt(nv);
         if (H.precision == RTE_FP64) {
             HIP_CHECK(hipMemcpy(ut.data(), B.U[block], sizeof(double) * mu, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vt.data(), B.V[block], sizeof(double) * n * kp, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vt.data(), B.V[block], sizeof(double) * nv, hipMemcpyDeviceToHost));
         } else if (H.precision == RTE_FP32) {
-            std::vector<float> uf(mu), vf(n * kp);
+            std::vector<float> uf(mu), vf(nv);
             HIP_CHECK(hipMemcpy(uf.data(), B.U[block], sizeof(float) * mu, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vf.data(), B.V[block], sizeof(float) * n * kp, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vf.data(), B.V[block], sizeof(float) * nv, hipMemcpyDeviceToHost));
             for (int64_t e = 0; e < mu; ++e) ut[e] = uf[e];
-            for (int64_t e = 0; e < n * kp; ++e) vt[e] = vf[e];
+            for (int64_t e = 0; e < nv; ++e) vt[e] = vf[e];
         } else {
             // BF16 hi + lo: the factor value is hi + lo
-            std::vector<uint16_t> uh(mu), ul(mu), vh(n * kp), vl(n * kp);
+            std::vector<uint16_t> uh(mu), ul(mu), vh(nv), vl(nv);
             HIP_CHECK(hipMemcpy(uh.data(), B.U[block], 2 * mu, hipMemcpyDeviceToHost));
             HIP_CHECK(hipMemcpy(ul.data(), B.Ulo[block], 2 * mu, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vh.data(), B.V[block], 2 * n * kp, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vl.data(), B.Vlo[block], 2 * n * kp, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vh.data(), B.V[block], 2 * nv, hipMemcpyDeviceToHost));
+            HIP_CHECK(hipMemcpy(vl.data(), B.Vlo[block], 2 * nv, hipMemcpyDeviceToHost));
             auto wid = [](uint16_t h) {
                 uint32_t u = (uint32_t)h << 16;
                 float f;
@@ -355,19 +382,22 @@ rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, i
                 return (double)f;
             };
             for (int64_t e = 0; e < mu; ++e) ut[e] = wid(uh[e]) + wid(ul[e]);
-            for (int64_t e = 0; e < n * kp; ++e) vt[e] = wid(vh[e]) + wid(vl[e]);
+            for (int64_t e = 0; e < nv; ++e) vt[e] = wid(vh[e]) + wid(vl[e]);
         }
-        // U: target-leaf slices, each column-major [k][rp]
-        const Plan &P = *H.plan;
-        const int li0 = P.leaf_of(bl.t0);
+        // U: target-leaf slices; element (row r of slice, column l) at
+        // ((l / g) * rp + r) * g + l % g
         for (int64_t i = 0; i < m; ++i) {
             const int li = P.leaf_of(bl.t0 + i);
             const int64_t rp = H.leaf_prp_h[li + 1] - H.leaf_prp_h[li];
-            const int64_t base = k * (H.leaf_prp_h[li] - H.leaf_prp_h[li0]) + (bl.t0 + i - P.leaf_start[li]);
-            for (int64_t l = 0; l < k; ++l) U[i * k + l] = ut[base + l * rp];
+            const int64_t base = kgp * (H.leaf_prp_h[li] - H.leaf_prp_h[li0]), r = bl.t0 + i - P.leaf_start[li];
+            for (int64_t l = 0; l < k; ++l) U[i * k + l] = ut[base + ((l / g) * rp + r) * g + l % g];
         }
-        for (int64_t l = 0; l < k; ++l)
-            for (int64_t j = 0; j < n; ++j) V[j * k + l] = vt[j * kp + l];
+        // V: [n][pad4(k)], or [nP/8][k][8] over stored source coordinates
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t jp = H.src_p_h[bl.s0 + j] - H.src_p_h[bl.s0];
+            for (int64_t l = 0; l < k; ++l)
+                V[j * k + l] = g > 1 ? vt[((jp / 8) * k + l) * 8 + jp % 8] : vt[j * ((k + 3) & ~(int64_t)3) + l];
+        }
         return RTE_OK;
     });
 }

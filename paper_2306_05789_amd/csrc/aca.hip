@@ -361,55 +361,81 @@ struct CompactTask {
     const void *su, *sv;
     void *du, *dv;
     void *dul, *dvl;      // BF16 lo parts (mixed precision)
-    int64_t t0;           // first target row of the block
+    int64_t t0, s0;       // first target row and first source of the block
     int32_t m, n, k, li0; // li0: target leaf of t0
 };
 
-// Final layout of a low-rank block: U in target-leaf slices, each column-major
-// [k][rp] (the matvec's phase B reads 4 consecutive rows of one column per
-// lane), and V row-major [n][kp], kp = pad4(k) (phase A reads 4 consecutive
-// coefficients of one source per lane).  Padding stays zero (the output is
-// cleared beforehand).
+// Final layout of a low-rank block (FP64 / FP32 storage): U in target-leaf
+// slices, each column-major [k][rp], and V row-major [n][kp], kp = pad4(k).
+// A thread owns a row of U (one slice lookup, then its k columns: reads of
+// the U^T rows and writes of the slice columns are contiguous across
+// threads) and 4 consecutive coefficients of a row of V (vector stores).
+// Padding stays zero (the output is cleared beforehand).
 template <typename T>
 __global__ __launch_bounds__(256) void k_compact(const CompactTask *__restrict__ tasks, SliceMap sm) {
     const CompactTask t = tasks[blockIdx.x];
     const T *su = static_cast<const T *>(t.su), *sv = static_cast<const T *>(t.sv);
     T *du = static_cast<T *>(t.du), *dv = static_cast<T *>(t.dv);
-    const int kp = (int)pad4(t.k);
-    const int64_t nu = (int64_t)t.k * t.m, nv = (int64_t)kp * t.n;
-    for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) {
-        const int64_t l = e / t.m, i = e - l * t.m;
-        du[slice_offset(sm, t.li0, t.t0 + i, t.k, l)] = su[e];
+    for (int64_t i = threadIdx.x; i < t.m; i += blockDim.x) {
+        const SliceRow sr = slice_row(sm, t.li0, t.t0 + i, t.k);
+        for (int l = 0; l < t.k; ++l) du[sr.base + l * sr.rp + sr.r] = su[(int64_t)l * t.m + i];
     }
+    const int q4 = (int)(pad4(t.k) / 4);
+    const int64_t nv = (int64_t)q4 * t.n;
     for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
-        const int64_t j = e / kp, l = e - j * kp;
-        dv[e] = l < t.k ? sv[l * t.n + j] : (T)0;
+        const int64_t j = e / q4;
+        const int l0 = 4 * (int)(e - j * q4);
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = l0 + u < t.k ? sv[(int64_t)(l0 + u) * t.n + j] : (T)0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dv[j * 4 * q4 + l0 + u] = v[u];
     }
 }
 
-// Mixed precision: each factor element x (FP32) is stored as hi = bf16(x) and
-// lo = bf16(x - hi), in the same layouts; BF16 keeps FP32's exponent range.
-__global__ __launch_bounds__(256) void k_compact_bf16(const CompactTask *__restrict__ tasks, SliceMap sm) {
+// Mixed precision (K-grouped BF16 storage): each factor element x (FP32) is
+// stored as hi = bf16(x) and lo = bf16(x - hi).  U: slice rows of 8
+// consecutive rank columns ([k8/8][r][8]); V: [nP/8][k][8] over the stored
+// source coordinates (src_p), whose padding stays zero.  A thread writes one
+// 16-byte group of 8 elements of each array.
+__global__ __launch_bounds__(256) void k_compact_bf16(const CompactTask *__restrict__ tasks, SliceMap sm,
+                                                      const int64_t *__restrict__ pmap) {
     const CompactTask t = tasks[blockIdx.x];
     const float *su = static_cast<const float *>(t.su), *sv = static_cast<const float *>(t.sv);
     uint16_t *uh = static_cast<uint16_t *>(t.du), *vh = static_cast<uint16_t *>(t.dv);
     uint16_t *ul = static_cast<uint16_t *>(t.dul), *vl = static_cast<uint16_t *>(t.dvl);
-    const int kp = (int)pad4(t.k);
-    const int64_t nu = (int64_t)t.k * t.m, nv = (int64_t)kp * t.n;
+    auto put8 = [](uint16_t *hi, uint16_t *lo, int64_t o, const float x[8]) {
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint16_t h0 = f2bf(x[2 * e]), h1 = f2bf(x[2 * e + 1]);
+            h[e] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+            l[e] = (uint32_t)f2bf(x[2 * e] - bf2f(h0)) | ((uint32_t)f2bf(x[2 * e + 1] - bf2f(h1)) << 16);
+        }
+        *reinterpret_cast<uint4 *>(hi + o) = make_uint4(h[0], h[1], h[2], h[3]);
+        *reinterpret_cast<uint4 *>(lo + o) = make_uint4(l[0], l[1], l[2], l[3]);
+    };
+    const int kg = (t.k + 7) / 8;
+    const int64_t nu = (int64_t)kg * t.m;
     for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) {
-        const int64_t l = e / t.m, i = e - l * t.m;
-        const int64_t o = slice_offset(sm, t.li0, t.t0 + i, t.k, l);
-        const float x = su[e];
-        const uint16_t h = f2bf(x);
-        uh[o] = h;
-        ul[o] = f2bf(x - bf2f(h));
+        const int64_t lg = e / t.m, i = e - lg * t.m;
+        const SliceRow sr = slice_row(sm, t.li0, t.t0 + i, t.k);
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = 8 * lg + u < t.k ? su[(8 * lg + u) * t.m + i] : 0.0f;
+        put8(uh, ul, sr.base + (lg * sr.rp + sr.r) * 8, x);
     }
+    const int64_t p0 = sm.src_p[t.s0], np = sm.src_p[t.s0 + t.n] - p0;
+    const int64_t nv = (np / 8) * t.k;
     for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
-        const int64_t j = e / kp, l = e - j * kp;
-        const float x = l < t.k ? sv[l * t.n + j] : 0.0f;
-        const uint16_t h = f2bf(x);
-        vh[e] = h;
-        vl[e] = f2bf(x - bf2f(h));
+        const int64_t jg = e / t.k, l = e - jg * t.k;
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t j = pmap[p0 + 8 * jg + u];
+            x[u] = j >= 0 ? sv[l * t.n + (j - t.s0)] : 0.0f;
+        }
+        put8(vh, vl, (jg * t.k + l) * 8, x);
     }
 }
 
@@ -418,7 +444,8 @@ __global__ __launch_bounds__(256) void k_compact_bf16(const CompactTask *__restr
 namespace {
 
 SliceMap slice_map(const HMat &H) {
-    return {H.leaf_start.as<int64_t>(), H.leaf_prp.as<int64_t>(), (int)H.plan->tgt_leaves.size()};
+    return {H.leaf_start.as<int64_t>(), H.leaf_prp.as<int64_t>(), H.src_p.as<int64_t>(),
+            (int)H.plan->tgt_leaves.size(), H.kgroup};
 }
 
 int64_t round8(int64_t e) { return (e + 7) & ~(int64_t)7; }
@@ -427,6 +454,15 @@ int64_t round8(int64_t e) { return (e + 7) & ~(int64_t)7; }
 int64_t padded_rows(const HMat &H, int64_t t0, int64_t t1) {
     const Plan &P = *H.plan;
     return H.leaf_prp_h[P.leaf_of(t1 - 1) + 1] - H.leaf_prp_h[P.leaf_of(t0)];
+}
+
+// stored elements of the row side (K columns over rows [t0, t1)) and of V
+int64_t stored_u(const HMat &H, int64_t t0, int64_t t1, int64_t K) {
+    const int64_t g = H.kgroup;
+    return (K + g - 1) / g * g * padded_rows(H, t0, t1);
+}
+int64_t stored_v(const HMat &H, int64_t s0, int64_t s1, int64_t k) {
+    return H.kgroup > 1 ? H.pwidth(s0, s1) * k : (s1 - s0) * pad4(k);
 }
 
 template <typename T>
@@ -438,7 +474,7 @@ void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Bl
     int64_t total = 0, stored = 0;
     for (auto &b : blocks) {
         total += (b.t1 - b.t0) * (b.s1 - b.s0);
-        stored += padded_rows(H, b.t0, b.t1) * (b.s1 - b.s0);
+        stored += round8(stored_u(H, b.t0, b.t1, H.pwidth(b.s0, b.s1)));
     }
     DevBuf buf(esz * (size_t)stored), lo(split ? esz * (size_t)stored : 0);
     HIP_CHECK(hipMemsetAsync(buf.p, 0, buf.bytes, s));   // the row padding stays zero
@@ -452,8 +488,9 @@ void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Bl
         B.dense_blocks.push_back(b);
         B.dense_ptr.push_back(p);
         B.dense_lo.push_back(pl);
-        for (int64_t f = 0; f < (int64_t)m * n; f += kFillChunk) tasks.push_back({p, pl, b.t0, b.s0, m, n, li0, 0, f});
-        off += padded_rows(H, b.t0, b.t1) * n;
+        const int32_t kw = (int32_t)H.pwidth(b.s0, b.s1);
+        for (int64_t f = 0; f < (int64_t)m * n; f += kFillChunk) tasks.push_back({p, pl, b.t0, b.s0, m, n, li0, kw, f});
+        off += round8(stored_u(H, b.t0, b.t1, kw));
     }
     B.fill_ms += dense_fill_launch<T>(*H.mesh, H.kind, kap, tasks, H.tgt_nat.as<int64_t>(), H.src_nat.as<int64_t>(),
                                       slice_map(H), split, s);
@@ -578,7 +615,8 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     int64_t total = 0;
     for (int t = 0; t < nb; ++t)
         if (rk[t] > 0)
-            total += round8((int64_t)rk[t] * padded_rows(H, tasks[t].t0, tasks[t].t0 + tasks[t].m) + pad4(rk[t]) * tasks[t].n);
+            total += round8(stored_u(H, tasks[t].t0, tasks[t].t0 + tasks[t].m, rk[t])) +
+                     round8(stored_v(H, tasks[t].s0, tasks[t].s0 + tasks[t].n, rk[t]));
     const bool split = H.precision == RTE_MIXED_BF16;
     const size_t esz = split ? sizeof(uint16_t) : sizeof(T);
     DevBuf out(esz * (size_t)total), outlo(split ? esz * (size_t)total : 0);
@@ -592,13 +630,13 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
             fallback.push_back(P.lowrank[b]);
             continue;
         }
-        const int64_t nu = (int64_t)rk[t] * padded_rows(H, tasks[t].t0, tasks[t].t0 + tasks[t].m),
-                      nv = pad4(rk[t]) * tasks[t].n;
+        const int64_t nu = round8(stored_u(H, tasks[t].t0, tasks[t].t0 + tasks[t].m, rk[t])),
+                      nv = round8(stored_v(H, tasks[t].s0, tasks[t].s0 + tasks[t].n, rk[t]));
         char *du = static_cast<char *>(out.p) + off * esz, *dv = du + nu * esz;
         char *dul = split ? static_cast<char *>(outlo.p) + off * esz : nullptr;
         char *dvl = split ? dul + nu * esz : nullptr;
         ct.push_back({Us.as<T>() + tasks[t].uoff, Vs.as<T>() + tasks[t].voff, du, dv, dul, dvl, tasks[t].t0,
-                      tasks[t].m, tasks[t].n, rk[t], P.leaf_of(tasks[t].t0)});
+                      tasks[t].s0, tasks[t].m, tasks[t].n, rk[t], P.leaf_of(tasks[t].t0)});
         B.rank[b] = rk[t];
         B.U[b] = du;
         B.V[b] = dv;
@@ -607,11 +645,13 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
             B.Vlo[b] = dvl;
         }
         B.lr_entries += (int64_t)rk[t] * (tasks[t].m + tasks[t].n);
-        off += round8(nu + nv);   // every block starts 16-byte aligned for BF16, 32-byte for FP64
+        off += nu + nv;   // U and V each start 16-byte aligned for BF16, 32-byte for FP64
     }
     if (!ct.empty()) {
         DevBuf dct = upload(ct, s);
-        if (split) k_compact_bf16<<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>(), slice_map(H));
+        if (split)
+            k_compact_bf16<<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>(), slice_map(H),
+                                                              H.src_pmap.as<int64_t>());
         else k_compact<T><<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>(), slice_map(H));
         HIP_LAUNCH_CHECK();
         HIP_CHECK(hipStreamSynchronize(s));

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_dense_fill(EntryCtx<T> c, const FillTas
     for (int64_t e = tk.first + threadIdx.x; e < end; e += blockDim.x) {
         const int64_t jl = e / tk.m, il = e - jl * tk.m;
         const T v = entry<T, KIND>(c, tgt_nat[tk.t0 + il], src_nat[tk.s0 + jl]);
-        const int64_t o = slice_offset(sm, tk.li0, tk.t0 + il, tk.n, jl);
+        const int64_t o = slice_offset(sm, tk.li0, tk.t0 + il, tk.kw, sm.src_p[tk.s0 + jl] - sm.src_p[tk.s0]);
         if constexpr (SPLIT) {
             const uint16_t h = f2bf((float)v);
             static_cast<uint16_t *>(tk.out)[o] = h;

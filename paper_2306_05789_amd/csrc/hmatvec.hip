@@ -19,7 +19,17 @@
 //          Partial sums are added over the lane groups by a butterfly and over
 //          the W wavefronts in a fixed order.  No atomics: results are
 //          bitwise reproducible.
+// BF16 storage runs both phases on the matrix cores
+// (v_mfma_f32_16x16x32_bf16, 16 right-hand sides per instruction): the
+// vectors are first staged as BF16 splits x = hi + mid (+ lo) in the stored
+// source coordinates, phase A multiplies 16-rank tiles of V^T by them, a
+// fixed-order pass adds the chunk partials and splits t the same way, and
+// phase B multiplies 16-row tiles of the K-grouped slices by 32-column steps
+// of x or t.  The low operator (inner sweeps) takes hi factors times hi + mid
+// with FP32 accumulation; the accurate operator takes hi + lo factors times
+// hi + mid + lo and adds every 32-column step's FP32 result into FP64.
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -52,41 +62,47 @@ struct LeafWork {
     int32_t rows, seg0, seg1, band;
 };
 
+// BF16 (matrix-core) phase A task: 64 ranks of one chunk of a low-rank block
+struct MfVt {
+    const uint16_t *V, *Vlo;   // first 8-row group of the chunk in V [nP/8][k][8]
+    int64_t xoff;              // stored source coordinate of the chunk's first row
+    int64_t out;               // partial-sum offset of the chunk (rank l at out + l)
+    int32_t ng, k, band, kt0;  // 8-row groups in the chunk, rank, band, first rank of the task
+};
+
+// BF16 t staging: sum a block's chunk partials, split into hi, mid, lo
+struct MfRed {
+    int64_t part, toff;        // first partial; offset of t (a multiple of 8, pad8(k) entries)
+    int32_t chunks, k;
+};
+
 struct MatvecPlan {
     DevBuf vt, seg, leaf, red;
     int64_t n_vt = 0, n_leaf = 0, ktot = 0, n_red = 0, n_red_threads = 0, npart = 0;
     int64_t n_src = 0, n_tgt = 0;
     int max_rows = 0;
+    // matrix-core path (BF16 storage)
+    bool mf = false;
+    int nb = 1;                // bands in this plan
+    int64_t np = 0;            // stored source coordinates per vector
+    const int64_t *pmap_p = nullptr;   // H.src_pmap: stored coordinate -> source or -1
 };
 
 namespace {
 
-// factor storage: FP64, FP32, or BF16 (hi part, plus the lo part in MODE_ACC)
-enum : int { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
+// factor storage of the vector-ALU path: FP64 or FP32
+enum : int { ST_F64 = 0, ST_F32 = 1 };
 
 // 4 consecutive elements starting at element i (i a multiple of 4, rows aligned)
 template <int ST, int MODE, typename A>
-__device__ __forceinline__ void load4(const void *p, const void *lo, int64_t i, A v[4]) {
+__device__ __forceinline__ void load4(const void *p, const void *, int64_t i, A v[4]) {
     if constexpr (ST == ST_F64) {
         const double2 *q = reinterpret_cast<const double2 *>(static_cast<const double *>(p) + i);
         const double2 a = q[0], b = q[1];
         v[0] = (A)a.x; v[1] = (A)a.y; v[2] = (A)b.x; v[3] = (A)b.y;
-    } else if constexpr (ST == ST_F32) {
+    } else {
         const float4 a = *reinterpret_cast<const float4 *>(static_cast<const float *>(p) + i);
         v[0] = (A)a.x; v[1] = (A)a.y; v[2] = (A)a.z; v[3] = (A)a.w;
-    } else {
-        const uint2 h = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(p) + i);
-        v[0] = (A)bf2f((uint16_t)(h.x & 0xFFFFu));
-        v[1] = (A)bf2f((uint16_t)(h.x >> 16));
-        v[2] = (A)bf2f((uint16_t)(h.y & 0xFFFFu));
-        v[3] = (A)bf2f((uint16_t)(h.y >> 16));
-        if constexpr (MODE == kMatvecAccurate) {
-            const uint2 l = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(lo) + i);
-            v[0] += (A)bf2f((uint16_t)(l.x & 0xFFFFu));
-            v[1] += (A)bf2f((uint16_t)(l.x >> 16));
-            v[2] += (A)bf2f((uint16_t)(l.y & 0xFFFFu));
-            v[3] += (A)bf2f((uint16_t)(l.y >> 16));
-        }
     }
 }
 
@@ -160,49 +176,29 @@ __global__ __launch_bounds__(256) void k_phase_a(const VtTask *__restrict__ task
     }
 }
 
-__global__ void k_phase_a_reduce(const VtReduce *__restrict__ red, int64_t nred, const double *__restrict__ part,
-                                 int64_t ldp, double *__restrict__ t, int64_t ldt, int r0, int nr) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t item = blockIdx.y;
+__global__ __launch_bounds__(256) void k_phase_a_reduce(const VtReduce *__restrict__ red, int64_t nred,
+                                                        const double *__restrict__ part, int64_t ldp,
+                                                        double *__restrict__ t, int64_t ldt, int r0, int nr) {
+    const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (item >= nred) return;
     const VtReduce rd = red[item];
-    if (w >= rd.k) return;
-    for (int r = 0; r < nr; ++r) {
-        double s = 0.0;
-        for (int c = 0; c < rd.chunks; ++c) s += part[(int64_t)(r0 + r) * ldp + rd.part + (int64_t)c * rd.k + w];
-        t[(int64_t)(r0 + r) * ldt + rd.toff + w] = s;
-    }
+    for (int w = threadIdx.x & 63; w < rd.k; w += 64)
+        for (int r = 0; r < nr; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < rd.chunks; ++c) s += part[(int64_t)(r0 + r) * ldp + rd.part + (int64_t)c * rd.k + w];
+            t[(int64_t)(r0 + r) * ldt + rd.toff + w] = s;
+        }
 }
 
-// RPL rows per lane: a lane reads RPL consecutive rows of one column per load
-// (16 or 32 bytes); 64/RPL lanes cover a 64-row tile and RPL column groups
-// run side by side.
+// a lane reads RPL = 4 consecutive rows of one column per load (16 or 32
+// bytes); 16 lanes cover a 64-row tile and 4 column groups run side by side
 template <int ST, int MODE, typename A, int RPL>
 __device__ __forceinline__ void load_rows(const void *p, const void *lo, int64_t i, A v[RPL]) {
-    if constexpr (RPL == 4) {
-        load4<ST, MODE, A>(p, lo, i, v);
-    } else {
-        static_assert(ST == ST_BF16 && RPL == 8, "8 rows per lane is used for BF16 storage");
-        const uint4 h = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(p) + i);
-        const uint32_t w[4] = {h.x, h.y, h.z, h.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            v[2 * k] = (A)bf2f((uint16_t)(w[k] & 0xFFFFu));
-            v[2 * k + 1] = (A)bf2f((uint16_t)(w[k] >> 16));
-        }
-        if constexpr (MODE == kMatvecAccurate) {
-            const uint4 l = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(lo) + i);
-            const uint32_t z[4] = {l.x, l.y, l.z, l.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                v[2 * k] += (A)bf2f((uint16_t)(z[k] & 0xFFFFu));
-                v[2 * k + 1] += (A)bf2f((uint16_t)(z[k] >> 16));
-            }
-        }
-    }
+    static_assert(RPL == 4, "4 rows per lane");
+    load4<ST, MODE, A>(p, lo, i, v);
 }
 
-template <int ST> constexpr int rows_per_lane() { return ST == ST_BF16 ? 8 : 4; }
+template <int ST> constexpr int rows_per_lane() { return 4; }
 
 template <int ST, int MODE, typename A, int NR, int W>
 __global__ __launch_bounds__(64 * W) void k_phase_b(const LeafWork *__restrict__ leaves, const Seg *__restrict__ segs,
@@ -305,6 +301,227 @@ __global__ __launch_bounds__(64 * W) void k_phase_b(const LeafWork *__restrict__
     }
 }
 
+// ---------------------------------------------------------------- matrix-core path (BF16 storage)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u)); }
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// v = hi + mid + lo with each part a BF16 (hi + mid carries 16 significant
+// bits, all three 24)
+__device__ __forceinline__ void split3(double v, uint16_t &h, uint16_t &m, uint16_t &l) {
+    h = f2bf((float)v);
+    const double r1 = v - (double)bf2f(h);
+    m = f2bf((float)r1);
+    const double r2 = r1 - (double)bf2f(m);
+    l = f2bf((float)r2);
+}
+
+// x [nvec][n_src] (FP64, cluster order) -> xs [3][nvec][np] in stored
+// coordinates; the padding coordinates get zeros
+__global__ void k_mf_xstage(const int64_t *__restrict__ pmap, int64_t np, int64_t nvec, const double *__restrict__ x,
+                            int64_t n_src, uint16_t *__restrict__ xs, int64_t xsplit) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nvec * np) return;
+    const int64_t v = k / np, p = k - v * np;
+    const int64_t j = pmap[p];
+    uint16_t h = 0, m = 0, l = 0;
+    if (j >= 0) split3(x[v * n_src + j], h, m, l);
+    xs[k] = h;
+    xs[xsplit + k] = m;
+    xs[2 * xsplit + k] = l;
+}
+
+// Phase A: one wavefront per task; lane (c = lane % 16, q = lane / 16) feeds
+// rank row c of each 16-rank tile and right-hand side c of the x operand,
+// over rows 8q..8q+7 of each 32-row step.  Result lane layout: rank 4q + v
+// of the tile, right-hand side c.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_mf_phase_a(const MfVt *__restrict__ tasks, int64_t ntask,
+                                                    const uint16_t *__restrict__ xs, int64_t xsplit, int64_t ldx,
+                                                    int64_t xbs, double *__restrict__ part, int64_t ldp, int r0,
+                                                    int nr) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= ntask) return;
+    const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4;
+    const MfVt tk = tasks[w];
+    const bool rl = c < nr;
+    const uint16_t *xb = xs + (int64_t)tk.band * xbs + (int64_t)(r0 + (rl ? c : 0)) * ldx + tk.xoff;
+    const int nt = min(4, (tk.k - tk.kt0 + 15) / 16);
+    f32x4 acc[4];
+    double a64[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
+    for (int g0 = 0; g0 < tk.ng; g0 += 4) {
+        const int g = g0 + q;
+        const bool live = g < tk.ng;
+        bf16x8 bh = zero8(), bm = zero8(), bl = zero8();
+        if (live && rl) {
+            bh = ld8(xb + 8 * g);
+            bm = ld8(xb + xsplit + 8 * g);
+            if constexpr (MODE == kMatvecAccurate) bl = ld8(xb + 2 * xsplit + 8 * g);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t < nt) {
+                const int rk = tk.kt0 + 16 * t + c;
+                const bool ok = live && rk < tk.k;
+                const int64_t o = ((int64_t)g * tk.k + rk) * 8;
+                const bf16x8 a = ok ? ld8(tk.V + o) : zero8();
+                if constexpr (MODE == kMatvecLow) {
+                    acc[t] = mfma(a, bh, acc[t]);
+                    acc[t] = mfma(a, bm, acc[t]);
+                } else {
+                    const bf16x8 al = ok ? ld8(tk.Vlo + o) : zero8();
+                    f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                    z = mfma(a, bh, z);
+                    z = mfma(a, bm, z);
+                    z = mfma(a, bl, z);
+                    z = mfma(al, bh, z);
+                    z = mfma(al, bm, z);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) a64[t][v] += (double)z[v];
+                }
+            }
+        }
+    }
+    if (!rl) return;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t < nt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rk = tk.kt0 + 16 * t + 4 * q + v;
+                if (rk < tk.k)
+                    part[(int64_t)(r0 + c) * ldp + tk.out + rk] = MODE == kMatvecLow ? (double)acc[t][v] : a64[t][v];
+            }
+        }
+    }
+}
+
+// t_b = sum of the chunk partials (fixed order), split into hi, mid, lo;
+// one wavefront per block, entries k..pad8(k)-1 are zeros
+__global__ __launch_bounds__(256) void k_mf_tstage(const MfRed *__restrict__ red, int64_t nred,
+                                                   const double *__restrict__ part, int64_t ldp,
+                                                   uint16_t *__restrict__ ts, int64_t tsplit, int64_t ldt, int r0,
+                                                   int nr) {
+    const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= nred) return;
+    const MfRed rd = red[item];
+    const int k8 = (int)pad8(rd.k);
+    for (int l = threadIdx.x & 63; l < k8; l += 64)
+        for (int r = 0; r < nr; ++r) {
+            double sum = 0.0;
+            if (l < rd.k)
+                for (int c = 0; c < rd.chunks; ++c) sum += part[(int64_t)(r0 + r) * ldp + rd.part + (int64_t)c * rd.k + l];
+            uint16_t h, m, lo;
+            split3(sum, h, m, lo);
+            const int64_t o = (int64_t)(r0 + r) * ldt + rd.toff + l;
+            ts[o] = h;
+            ts[tsplit + o] = m;
+            ts[2 * tsplit + o] = lo;
+        }
+}
+
+// Phase B: one workgroup per (band, target leaf), W wavefronts over its
+// segments.  Lane (c, q) feeds row c of each 16-row tile and right-hand side
+// c of the coefficient operand, over columns 8q..8q+7 of each 32-column step.
+// Result lane layout: row 4q + v of the tile, right-hand side c; the W
+// wavefront sums are added in a fixed order through LDS.
+template <int MODE, int W>
+__global__ __launch_bounds__(64 * W) void k_mf_phase_b(const LeafWork *__restrict__ leaves,
+                                                       const Seg *__restrict__ segs, const uint16_t *__restrict__ xs,
+                                                       int64_t xsplit, int64_t ldx, int64_t xbs,
+                                                       const uint16_t *__restrict__ ts, int64_t tsplit, int64_t ldt,
+                                                       const double *__restrict__ y0, double *__restrict__ y,
+                                                       int64_t ldy, int64_t ybs, int r0, int nr) {
+    using PT = typename std::conditional<MODE == kMatvecAccurate, double, float>::type;
+    __shared__ PT part[W][64][17];
+    const LeafWork lw = leaves[blockIdx.x];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, c = lane & 15, q = lane >> 4;
+    const bool rl = c < nr;
+    const int rc = r0 + (rl ? c : 0);
+    const uint16_t *xb = xs + (int64_t)lw.band * xbs + (int64_t)rc * ldx;
+    const uint16_t *tb = ts + (int64_t)rc * ldt;
+    y += (int64_t)lw.band * ybs;
+    if (y0) y0 += (int64_t)lw.band * ybs;
+    for (int rb = 0; rb < lw.rows; rb += 64) {
+        const int nrt = min(4, (lw.rows - rb + 15) / 16);
+        f32x4 acc[4];
+        double a64[4][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
+        for (int s = lw.seg0 + wid; s < lw.seg1; s += W) {
+            const Seg sg = segs[s];
+            const uint16_t *src = (sg.is_lr ? tb : xb) + sg.coef_off;
+            const int64_t sst = sg.is_lr ? tsplit : xsplit;
+            const uint16_t *A = static_cast<const uint16_t *>(sg.data), *Al = static_cast<const uint16_t *>(sg.lo);
+            const int kg = (sg.K + 7) / 8;
+            for (int g0 = 0; g0 < kg; g0 += 4) {
+                const int g = g0 + q;
+                const bool live = g < kg;
+                bf16x8 bh = zero8(), bm = zero8(), bl = zero8();
+                if (live && rl) {
+                    bh = ld8(src + 8 * g);
+                    bm = ld8(src + sst + 8 * g);
+                    if constexpr (MODE == kMatvecAccurate) bl = ld8(src + 2 * sst + 8 * g);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (t < nrt) {
+                        const int row = rb + 16 * t + c;
+                        const bool ok = live && row < lw.rows;
+                        const int64_t o = ((int64_t)g * sg.ld + row) * 8;
+                        const bf16x8 a = ok ? ld8(A + o) : zero8();
+                        if constexpr (MODE == kMatvecLow) {
+                            acc[t] = mfma(a, bh, acc[t]);
+                            acc[t] = mfma(a, bm, acc[t]);
+                        } else {
+                            const bf16x8 al = ok ? ld8(Al + o) : zero8();
+                            f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                            z = mfma(a, bh, z);
+                            z = mfma(a, bm, z);
+                            z = mfma(a, bl, z);
+                            z = mfma(al, bh, z);
+                            z = mfma(al, bm, z);
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) a64[t][v] += (double)z[v];
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                part[wid][16 * t + 4 * q + v][c] = MODE == kMatvecLow ? (PT)acc[t][v] : (PT)a64[t][v];
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 16 * 64; idx += 64 * W) {
+            const int r = idx >> 6, row = idx & 63;
+            if (r < nr && rb + row < lw.rows) {
+                PT sum = part[0][row][r];
+#pragma unroll
+                for (int w = 1; w < W; ++w) sum += part[w][row][r];
+                const int64_t gr = lw.r0 + rb + row;
+                const double v0 = y0 ? y0[(int64_t)(r0 + r) * ldy + gr] : 0.0;
+                y[(int64_t)(r0 + r) * ldy + gr] = v0 + (double)sum;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_gather(const int64_t *__restrict__ perm, int64_t n, int nrhs, int64_t ld_in, int64_t ld_out,
                          const double *__restrict__ in, double *__restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -340,8 +557,8 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
                 k_phase_a<ST, MODE, A, 16><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, xbs, tb, mp.ktot, part, ldp, r0, nr);
             HIP_LAUNCH_CHECK();
             if (mp.n_red) {
-                dim3 grid((unsigned)((mp.n_red_threads + 63) / 64), (unsigned)mp.n_red);
-                k_phase_a_reduce<<<grid, 64, 0, s>>>(mp.red.as<VtReduce>(), mp.n_red, part, ldp, tb, mp.ktot, r0, nr);
+                k_phase_a_reduce<<<(unsigned)((mp.n_red + 3) / 4), 256, 0, s>>>(mp.red.as<VtReduce>(), mp.n_red, part,
+                                                                               ldp, tb, mp.ktot, r0, nr);
                 HIP_LAUNCH_CHECK();
             }
         }
@@ -359,6 +576,46 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
                                                            ybs, r0, nr);
         HIP_LAUNCH_CHECK();
     }
+}
+
+// BF16 storage on the matrix cores.  Workspace (per call): phase A partials
+// [nrhs][npart] FP64, then the staged x [3][nb * nrhs][np] and t [3][nrhs][ktot]
+// BF16 splits.
+template <int MODE>
+void launch_mf(const MatvecPlan &mp, int nrhs, const double *x, const double *y0, double *y, double *tb,
+               hipStream_t s) {
+    const int64_t ldp = std::max<int64_t>(mp.npart, 1);
+    double *part = tb;
+    uint16_t *xs = reinterpret_cast<uint16_t *>(tb + ((ldp * nrhs + 1) & ~(int64_t)1));   // 16-byte aligned
+    const int64_t nvec = (int64_t)mp.nb * nrhs, xsplit = nvec * mp.np;
+    uint16_t *ts = xs + 3 * xsplit;
+    const int64_t tsplit = (int64_t)nrhs * mp.ktot;
+    const int64_t xbs = (int64_t)nrhs * mp.np, ybs = (int64_t)nrhs * mp.n_tgt;
+    if (xsplit) {
+        k_mf_xstage<<<(unsigned)((xsplit + 255) / 256), 256, 0, s>>>(mp.pmap_p, mp.np, nvec, x, mp.n_src, xs, xsplit);
+        HIP_LAUNCH_CHECK();
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += 16) {
+        const int nr = std::min(16, nrhs - r0);
+        if (mp.n_vt) {
+            k_mf_phase_a<MODE><<<(unsigned)((mp.n_vt + 3) / 4), 256, 0, s>>>(mp.vt.as<MfVt>(), mp.n_vt, xs, xsplit,
+                                                                          mp.np, xbs, part, ldp, r0, nr);
+            HIP_LAUNCH_CHECK();
+            k_mf_tstage<<<(unsigned)((mp.n_red + 3) / 4), 256, 0, s>>>(mp.red.as<MfRed>(), mp.n_red, part, ldp, ts,
+                                                                      tsplit, mp.ktot, r0, nr);
+            HIP_LAUNCH_CHECK();
+        }
+        k_mf_phase_b<MODE, 4><<<(unsigned)mp.n_leaf, 256, 0, s>>>(mp.leaf.as<LeafWork>(), mp.seg.as<Seg>(), xs, xsplit,
+                                                                mp.np, xbs, ts, tsplit, mp.ktot, y0, y, mp.n_tgt,
+                                                                ybs, r0, nr);
+        HIP_LAUNCH_CHECK();
+    }
+}
+
+// workspace doubles per right-hand side
+int64_t ws_words(const MatvecPlan &mp) {
+    if (!mp.mf) return mp.ktot + mp.npart;
+    return std::max<int64_t>(mp.npart, 1) + (6 * (int64_t)mp.nb * mp.np + 6 * mp.ktot + 15) / 8 + 2;
 }
 
 }  // namespace
@@ -390,10 +647,34 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     };
     std::vector<Seg> segs;
     std::vector<LeafWork> lw;
+    const bool mf = H.precision == RTE_MIXED_BF16;
+    std::vector<MfVt> mvt;
+    std::vector<MfRed> mred;
+    const int64_t g = H.kgroup;
     for (int bi = 0; bi < (int)bands.size(); ++bi) {
         const BandStore &B = H.bands[bands[bi]];
         std::vector<int64_t> toff(P.lowrank.size(), -1);
-        for (size_t b = 0; b < P.lowrank.size(); ++b) {
+        for (size_t b = 0; b < P.lowrank.size() && mf; ++b) {
+            if (B.rank[b] <= 0) continue;
+            const Block &bl = P.lowrank[b];
+            const int32_t k = B.rank[b];
+            const int64_t wp = H.pwidth(bl.s0, bl.s1);
+            toff[b] = ktot;
+            const int64_t rows = std::max<int64_t>(32, chunk_bytes / (2 * k) / 32 * 32);
+            const int64_t chunks = (wp + rows - 1) / rows;
+            mred.push_back({npart, ktot, (int32_t)chunks, k});
+            const uint16_t *V = static_cast<const uint16_t *>(B.V[b]), *Vl = static_cast<const uint16_t *>(B.Vlo[b]);
+            for (int64_t c = 0; c < chunks; ++c) {
+                const int64_t nj = std::min(rows, wp - c * rows);
+                for (int32_t kt0 = 0; kt0 < k; kt0 += 64)
+                    mvt.push_back({V + c * rows * k, Vl + c * rows * k, H.src_p_h[bl.s0] + c * rows, npart + c * k,
+                                   (int32_t)(nj / 8), k, bi, kt0});
+            }
+            npart += chunks * k;
+            maxk = std::max<int64_t>(maxk, k);
+            ktot += pad8(k);
+        }
+        for (size_t b = 0; b < P.lowrank.size() && !mf; ++b) {
             if (B.rank[b] <= 0) continue;
             const Block &bl = P.lowrank[b];
             const int32_t k = B.rank[b];
@@ -422,8 +703,9 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
         // columns starts K * (prp[li] - prp[li0]) elements after the block
         auto slices = [&](const Block &bl, const void *hi, const void *lo, int64_t K, int64_t coef, int is_lr) {
             const int64_t li0 = leaf_of(bl.t0);
+            const int64_t Kp = (K + g - 1) / g * g;
             for (int64_t li = li0; li < (int64_t)leaves.size() && leaves[li].first < bl.t1; ++li) {
-                const int64_t off = K * (H.leaf_prp_h[li] - H.leaf_prp_h[li0]) * esz;
+                const int64_t off = Kp * (H.leaf_prp_h[li] - H.leaf_prp_h[li0]) * esz;
                 const int32_t rp = (int32_t)(H.leaf_prp_h[li + 1] - H.leaf_prp_h[li]);
                 per[li].push_back({static_cast<const char *>(hi) + off,
                                    lo ? static_cast<const char *>(lo) + off : nullptr, coef, rp, 0, (int32_t)K,
@@ -432,7 +714,7 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
         };
         for (size_t d = 0; d < B.dense_blocks.size(); ++d) {
             const Block &bl = B.dense_blocks[d];
-            slices(bl, B.dense_ptr[d], B.dense_lo[d], bl.s1 - bl.s0, bl.s0, 0);
+            slices(bl, B.dense_ptr[d], B.dense_lo[d], H.pwidth(bl.s0, bl.s1), H.src_p_h[bl.s0], 0);
         }
         for (size_t b = 0; b < P.lowrank.size(); ++b) {
             if (B.rank[b] <= 0) continue;
@@ -454,14 +736,28 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     std::stable_sort(vt.begin(), vt.end(), [](const VtTask &a, const VtTask &b) {
         return (int64_t)a.nj * a.k > (int64_t)b.nj * b.k;
     });
-    mp->ktot = std::max<int64_t>(ktot, 1);
+    std::stable_sort(mvt.begin(), mvt.end(), [](const MfVt &a, const MfVt &b) {
+        return (int64_t)a.ng * std::min(64, a.k - a.kt0) > (int64_t)b.ng * std::min(64, b.k - b.kt0);
+    });
+    mp->ktot = std::max<int64_t>(ktot, mf ? 8 : 1);
     mp->npart = npart;
-    mp->n_vt = (int64_t)vt.size();
-    mp->n_red = (int64_t)red.size();
     mp->n_red_threads = maxk;
-    mp->red = upload(red, s);
     mp->n_leaf = (int64_t)lw.size();
-    mp->vt = upload(vt, s);
+    mp->mf = mf;
+    mp->nb = (int)bands.size();
+    mp->np = H.n_src_p;
+    mp->pmap_p = H.src_pmap.as<int64_t>();
+    if (mf) {
+        mp->n_vt = (int64_t)mvt.size();
+        mp->n_red = (int64_t)mred.size();
+        mp->vt = upload(mvt, s);
+        mp->red = upload(mred, s);
+    } else {
+        mp->n_vt = (int64_t)vt.size();
+        mp->n_red = (int64_t)red.size();
+        mp->vt = upload(vt, s);
+        mp->red = upload(red, s);
+    }
     mp->seg = upload(segs, s);
     mp->leaf = upload(lw, s);
     HIP_CHECK(hipStreamSynchronize(s));
@@ -472,8 +768,8 @@ void launch_plan(const HMat &H, const MatvecPlan &mp, int nrhs, const double *x_
                  double *tbuf, hipStream_t s, int mode) {
     if (H.precision == RTE_FP64) launch_typed<ST_F64, 0, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
     else if (H.precision == RTE_FP32) launch_typed<ST_F32, 0, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
-    else if (mode == kMatvecAccurate) launch_typed<ST_BF16, kMatvecAccurate, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
-    else launch_typed<ST_BF16, kMatvecLow, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    else if (mode == kMatvecAccurate) launch_mf<kMatvecAccurate>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    else launch_mf<kMatvecLow>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
 }
 
 }  // namespace
@@ -490,10 +786,7 @@ void matvec_build_all(HMat &H, hipStream_t s) {
     H.mv_all = build_plan(H, all, s);
 }
 
-int64_t matvec_ktot_all(const HMat &H) {
-    const MatvecPlan &mp = H.mv_all ? *H.mv_all : *H.mv[0];
-    return mp.ktot + mp.npart;
-}
+int64_t matvec_ktot_all(const HMat &H) { return ws_words(H.mv_all ? *H.mv_all : *H.mv[0]); }
 
 void matvec_launch_all(const HMat &H, int nrhs, const double *x_c, double *y_c, const double *y0_c, double *tbuf,
                        hipStream_t s, int mode) {
@@ -501,7 +794,7 @@ void matvec_launch_all(const HMat &H, int nrhs, const double *x_c, double *y_c, 
 }
 
 // workspace doubles per right-hand side: t, then the partial sums of chunked blocks
-int64_t matvec_ktot(const HMat &H, int band) { return H.mv[band]->ktot + H.mv[band]->npart; }
+int64_t matvec_ktot(const HMat &H, int band) { return ws_words(*H.mv[band]); }
 
 void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                       double *tbuf, hipStream_t s, int mode) {

@@ -19,36 +19,49 @@ __host__ __device__ __forceinline__ float bf2f(uint16_t h) {
 }
 constexpr int kAcaMaxRank = 192;   // rank cap of one ACA block before dense fallback
 
-// Stored blocks are row-major with the row length padded to a multiple of 4
-// elements (zeros), so the matvec reads 4-element vectors per lane.
 __host__ __device__ constexpr int64_t pad4(int64_t k) { return (k + 3) & ~(int64_t)3; }
+__host__ __device__ constexpr int64_t pad8(int64_t k) { return (k + 7) & ~(int64_t)7; }
 
-// Target-leaf tables of a plan on the device: where a row of a block lands in
-// its leaf-sliced storage (see the storage notes in rte_internal.h).
+// Target-leaf tables of a plan on the device: where an element of a block
+// lands in its leaf-sliced storage (see the storage notes in rte_internal.h).
 struct SliceMap {
     const int64_t *start;   // [n_leaves + 1]
     const int64_t *prp;     // [n_leaves + 1]
+    const int64_t *src_p;   // [N_src + 1] source (cluster order) -> stored column coordinate
     int nleaf;
+    int g;                  // columns per group: 1 (column-major slices) or 8 (K-grouped)
 };
 
-// element offset of (row `grow`, column `col`) in a block with K columns whose
-// first target leaf is li0
-__device__ __forceinline__ int64_t slice_offset(const SliceMap &sm, int li0, int64_t grow, int64_t K, int64_t col) {
+// Where row `grow` of a block of stored width K (first target leaf li0) sits:
+// element (grow, col) is at base + ((col / g) * rp + r) * g + col % g.
+struct SliceRow {
+    int64_t base, rp, r;
+};
+__device__ __forceinline__ SliceRow slice_row(const SliceMap &sm, int li0, int64_t grow, int64_t K) {
     int lo = li0, hi = sm.nleaf;   // start[lo] <= grow < start[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (sm.start[mid] <= grow) lo = mid;
         else hi = mid;
     }
-    const int64_t rp = sm.prp[lo + 1] - sm.prp[lo];
-    return K * (sm.prp[lo] - sm.prp[li0]) + col * rp + (grow - sm.start[lo]);
+    const int64_t g = sm.g, Kp = (K + g - 1) / g * g;
+    return {Kp * (sm.prp[lo] - sm.prp[li0]), sm.prp[lo + 1] - sm.prp[lo], grow - sm.start[lo]};
+}
+
+// element offset of (row `grow`, stored column `col`) in a block of stored
+// width K whose first target leaf is li0
+__device__ __forceinline__ int64_t slice_offset(const SliceMap &sm, int li0, int64_t grow, int64_t K, int64_t col) {
+    const SliceRow sr = slice_row(sm, li0, grow, K);
+    const int64_t g = sm.g;
+    return sr.base + ((col / g) * sr.rp + sr.r) * g + col % g;
 }
 
 struct FillTask {
     void *out;        // first element of the block (leaf-sliced, K = n columns)
     void *outlo;      // BF16 lo part (mixed precision), else null
     int64_t t0, s0;   // block ranges start, in cluster order
-    int32_t m, n, li0, pad;
+    int32_t m, n, li0;
+    int32_t kw;       // stored width (columns) of the block
     int64_t first;    // first entry (column-major over m x n) of this task
 };
 

@@ -170,11 +170,19 @@ DevBuf upload(const std::vector<T> &v, hipStream_t s) {
 // ---------------------------------------------------------------- H-matrix storage
 // Storage of a block whose target range covers target leaves li0..li1-1:
 //  - the row side (a dense block's columns, or U of a low-rank block with K =
-//    rank columns) is split into one slice per target leaf; slice s is
-//    column-major [K][rp_s], rp_s = leaf rows rounded up to the row unit
-//    (8 for BF16 storage, else 4), and the slices follow each other (slice s
-//    starts K * (prp[li0 + s] - prp[li0]) elements in);
-//  - V of a low-rank block is row-major [n][pad4(rank)].
+//    rank columns) is split into one slice per target leaf, and the slices
+//    follow each other;
+//  - FP64 and FP32 storage: slice s is column-major [K][rp_s], rp_s = leaf
+//    rows rounded up to 4, and starts K * (prp[li0 + s] - prp[li0]) elements
+//    in; V of a low-rank block is row-major [n][pad4(rank)];
+//  - BF16 storage is K-grouped for the matrix cores: slice s is [K8/8][r_s][8]
+//    (8 consecutive columns of one row are contiguous; K8 = K rounded up to 8,
+//    rows not padded), and V is [n8/8][rank][8] (8 consecutive sources of one
+//    rank index contiguous).  Sources are counted in stored coordinates in
+//    which every source leaf is rounded up to 8 (src_p maps a source to its
+//    stored coordinate), so a dense block has pwidth(s0, s1) >= n columns and
+//    V has pwidth rows; the vectors a matvec multiplies are staged in the same
+//    coordinates.
 // Padding is zero.  Mixed precision stores every element x as BF16 hi =
 // bf16(x) and lo = bf16(x - hi) in two arrays of the same layout (BF16
 // keeps FP32's exponent range, so no scale is needed).
@@ -205,6 +213,12 @@ struct HMat {
     DevBuf kappa_c;                 // FP64 [n_bands][N_tgt] kappa at the targets, cluster order
     std::vector<int64_t> leaf_prp_h;   // [n_leaves + 1] prefix sums of the padded leaf rows
     DevBuf leaf_start, leaf_prp;       // device copies of the target-leaf tables
+    int kgroup = 1;                    // columns per group in the slices: 1, or 8 (BF16, K-grouped)
+    std::vector<int64_t> src_p_h;      // [N_src + 1] cluster source -> stored coordinate; [N_src] = n_src_p
+    DevBuf src_p, src_pmap;            // device src_p; src_pmap [n_src_p]: stored coordinate -> source or -1
+    int64_t n_src_p = 0;
+    // stored width of the source range [s0, s1) (a union of source leaves)
+    int64_t pwidth(int64_t s0, int64_t s1) const { return src_p_h[s1] - src_p_h[s0]; }
     std::vector<std::unique_ptr<MatvecPlan>> mv;   // per band
     std::unique_ptr<MatvecPlan> mv_all;            // all bands in one launch (multi-band matrices)
     rte_hmat_stats_t stats{};
