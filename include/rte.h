@@ -138,6 +138,19 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
 rte_status_t rte_hmat_matvec(rte_hmat_t h, int32_t band, int32_t nrhs, const double *x,
                              double *y, void *stream);
 
+/* Operator of a matvec on RTE_MIXED_BF16 storage (the other storages have one):
+ * RTE_OP_ACCURATE multiplies by the hi + lo factors and adds the FP32
+ * matrix-core steps in FP64 (the operator of the defect steps); RTE_OP_LOW
+ * multiplies by the BF16 hi factors with FP32 accumulation (inner sweeps). */
+typedef enum { RTE_OP_ACCURATE = 0, RTE_OP_LOW = 1 } rte_operator_t;
+
+/* y_b = H_b x_b for every band b and nrhs right-hand sides, each phase one
+ * launch over all bands and right-hand sides (Section "Compression").
+ * x: device [n_bands][nrhs][N_src] FP64, y: device [n_bands][nrhs][N_tgt],
+ * natural order on both sides.  op: an rte_operator_t.  Synchronises `stream`. */
+rte_status_t rte_hmat_matvec_batched(rte_hmat_t h, int32_t nrhs, const double *x, double *y, int32_t op,
+                                     void *stream);
+
 typedef struct {
     int64_t n_tgt, n_src;
     int32_t n_bands, precision;
@@ -193,14 +206,20 @@ typedef struct {
     double tol;
     int32_t max_iter;
     int32_t precision;     /* RTE_MIXED_BF16: inner sweeps on BF16-hi factors, FP64 defect steps */
+    int32_t launch;        /* RTE_LAUNCH_STREAM: kernels enqueued one by one; RTE_LAUNCH_GRAPH: each
+                              distinct sweep captured once in a hipGraph and replayed (same kernels,
+                              same results; fewer launch round trips for small meshes) */
 } rte_solve_desc_t;
+
+enum { RTE_LAUNCH_STREAM = 0, RTE_LAUNCH_GRAPH = 1 };
 
 typedef struct {
     int32_t iterations;         /* matvec sweeps over all bands */
     int32_t outer_steps;        /* FP64 defect-correction steps (mixed precision) */
     double residual;            /* final relative change of J */
     int64_t monotone_violations;/* vertex-steps where T decreased (from T0 = 0 it should be 0) */
-    double ms_total, ms_matvec;
+    double ms_total, ms_matvec; /* ms_matvec: HIP-event time of the matvecs (graph launch: of the whole sweeps) */
+    int32_t graphs;             /* sweep graphs captured (RTE_LAUNCH_GRAPH) */
 } rte_solve_stats_t;
 
 rte_status_t rte_fixed_point_solve(rte_mesh_t mesh, rte_hmat_t vol, rte_hmat_t surf,

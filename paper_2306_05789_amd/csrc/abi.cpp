@@ -331,6 +331,28 @@ rte_status_t rte_hmat_matvec(rte_hmat_t h, int32_t band, int32_t nrhs, const dou
     });
 }
 
+rte_status_t rte_hmat_matvec_batched(rte_hmat_t h, int32_t nrhs, const double *x, double *y, int32_t op,
+                                     void *stream) {
+    return guard([&] {
+        RTE_REQUIRE(h, "rte_hmat_matvec_batched: NULL matrix");
+        const HMat &H = h->h;
+        RTE_REQUIRE(nrhs >= 1 && nrhs <= 4096, "rte_hmat_matvec_batched: nrhs out of range");
+        RTE_REQUIRE(op == RTE_OP_ACCURATE || op == RTE_OP_LOW, "rte_hmat_matvec_batched: unknown operator");
+        check_device_pointer(x, "x");
+        check_device_pointer(y, "y");
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t ns = H.stats.n_src, nt = H.stats.n_tgt, nv = (int64_t)nrhs * H.n_bands;
+        DevBuf xc(sizeof(double) * ns * nv), yc(sizeof(double) * nt * nv),
+            ws(sizeof(double) * (size_t)matvec_ws_all(H, nrhs));
+        permute_gather(H.src_pos.as<int64_t>(), ns, (int)nv, ns, ns, x, xc.as<double>(), s);
+        matvec_launch_all(H, nrhs, xc.as<double>(), yc.as<double>(), nullptr, ws.as<double>(), s,
+                          op == RTE_OP_LOW ? kMatvecLow : kMatvecAccurate);
+        permute_scatter(H.tgt_nat.as<int64_t>(), nt, (int)nv, nt, nt, yc.as<double>(), y, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        return RTE_OK;
+    });
+}
+
 rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats) {
     return guard([&] {
         RTE_REQUIRE(h && stats, "rte_hmat_stats: NULL argument");

@@ -66,8 +66,9 @@ struct LeafWork {
 struct MfVt {
     const uint16_t *V, *Vlo;   // first 8-row group of the chunk in V [nP/8][k][8]
     int64_t xoff;              // stored source coordinate of the chunk's first row
-    int64_t out;               // partial-sum offset of the chunk (rank l at out + l)
+    int64_t out;               // direct: offset of t_b in the t splits; else partial-sum offset of the chunk
     int32_t ng, k, band, kt0;  // 8-row groups in the chunk, rank, band, first rank of the task
+    int32_t direct;            // 1: the block is one chunk, its t splits are written here
 };
 
 // BF16 t staging: sum a block's chunk partials, split into hi, mid, lo
@@ -305,12 +306,21 @@ __global__ __launch_bounds__(64 * W) void k_phase_b(const LeafWork *__restrict__
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
-    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
-}
-__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u)); }
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Operands are read with buffer loads relative to a per-segment (per-task)
+// resource: an offset at or beyond the resource's size returns zeros, so
+// masked lanes and ragged tails need no branch and every step issues the
+// same loads (which lets the compiler keep the next step's loads in flight).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kOOB = 0x7FFFFFF0;   // beyond every resource
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ bf16x8 bload(rsrc_t r, int off) {
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
 // v = hi + mid + lo with each part a BF16 (hi + mid carries 16 significant
@@ -323,134 +333,274 @@ __device__ __forceinline__ void split3(double v, uint16_t &h, uint16_t &m, uint1
     l = f2bf((float)r2);
 }
 
-// x [nvec][n_src] (FP64, cluster order) -> xs [3][nvec][np] in stored
-// coordinates; the padding coordinates get zeros
-__global__ void k_mf_xstage(const int64_t *__restrict__ pmap, int64_t np, int64_t nvec, const double *__restrict__ x,
-                            int64_t n_src, uint16_t *__restrict__ xs, int64_t xsplit) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nvec * np) return;
-    const int64_t v = k / np, p = k - v * np;
+// Staged operands of one group of up to 16 right-hand sides: for a
+// coefficient group G (8 consecutive stored coordinates or ranks) the 16
+// right-hand sides follow each other, 8 BF16 each: element (G, r, e) at
+// (G * 16 + r) * 8 + e, so the 16 lanes of a step read 256 contiguous bytes.
+// x: [3 splits][band][np / 8][16][8]; t: [3 splits][ktot / 8][16][8].
+// Right-hand sides beyond the group's count are zeros.
+__global__ void k_mf_xstage(const int64_t *__restrict__ pmap, int64_t np, int nb, int nrhs, int r0, int nr,
+                            const double *__restrict__ x, int64_t n_src, uint16_t *__restrict__ xs, int64_t xsplit) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (band, G, r, e)
+    if (k >= (int64_t)nb * np * 16) return;
+    const int e = (int)(k & 7), r = (int)((k >> 3) & 15);
+    const int64_t bg = k >> 7, band = bg / (np / 8), G = bg - band * (np / 8);
+    const int64_t p = G * 8 + e;
     const int64_t j = pmap[p];
     uint16_t h = 0, m = 0, l = 0;
-    if (j >= 0) split3(x[v * n_src + j], h, m, l);
+    if (j >= 0 && r < nr) split3(x[(band * nrhs + r0 + r) * n_src + j], h, m, l);
     xs[k] = h;
     xs[xsplit + k] = m;
     xs[2 * xsplit + k] = l;
 }
 
-// Phase A: one wavefront per task; lane (c = lane % 16, q = lane / 16) feeds
-// rank row c of each 16-rank tile and right-hand side c of the x operand,
-// over rows 8q..8q+7 of each 32-row step.  Result lane layout: rank 4q + v
-// of the tile, right-hand side c.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_mf_phase_a(const MfVt *__restrict__ tasks, int64_t ntask,
-                                                    const uint16_t *__restrict__ xs, int64_t xsplit, int64_t ldx,
-                                                    int64_t xbs, double *__restrict__ part, int64_t ldp, int r0,
-                                                    int nr) {
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= ntask) return;
-    const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4;
-    const MfVt tk = tasks[w];
-    const bool rl = c < nr;
-    const uint16_t *xb = xs + (int64_t)tk.band * xbs + (int64_t)(r0 + (rl ? c : 0)) * ldx + tk.xoff;
-    const int nt = min(4, (tk.k - tk.kt0 + 15) / 16);
-    f32x4 acc[4];
-    double a64[4][4];
+struct MfOps {
+    static constexpr int NS = MODE == kMatvecAccurate ? 3 : 2;   // operand splits used
+    bf16x8 bx[NS], a[4], al[4];
+};
+
+template <int MODE>
+__device__ __forceinline__ void mf_products(const MfOps<MODE> &o, int nt, f32x4 acc[4], double a64[4][4]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 4; ++t) {
+        if (t < nt) {
+            if constexpr (MODE == kMatvecLow) {
+                acc[t] = mfma(o.a[t], o.bx[0], acc[t]);
+                acc[t] = mfma(o.a[t], o.bx[1], acc[t]);
+            } else {
+                f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                z = mfma(o.a[t], o.bx[0], z);
+                z = mfma(o.a[t], o.bx[1], z);
+                z = mfma(o.a[t], o.bx[2], z);
+                z = mfma(o.al[t], o.bx[0], z);
+                z = mfma(o.al[t], o.bx[1], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
-    for (int g0 = 0; g0 < tk.ng; g0 += 4) {
-        const int g = g0 + q;
-        const bool live = g < tk.ng;
-        bf16x8 bh = zero8(), bm = zero8(), bl = zero8();
-        if (live && rl) {
-            bh = ld8(xb + 8 * g);
-            bm = ld8(xb + xsplit + 8 * g);
-            if constexpr (MODE == kMatvecAccurate) bl = ld8(xb + 2 * xsplit + 8 * g);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (t < nt) {
-                const int rk = tk.kt0 + 16 * t + c;
-                const bool ok = live && rk < tk.k;
-                const int64_t o = ((int64_t)g * tk.k + rk) * 8;
-                const bf16x8 a = ok ? ld8(tk.V + o) : zero8();
-                if constexpr (MODE == kMatvecLow) {
-                    acc[t] = mfma(a, bh, acc[t]);
-                    acc[t] = mfma(a, bm, acc[t]);
-                } else {
-                    const bf16x8 al = ok ? ld8(tk.Vlo + o) : zero8();
-                    f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-                    z = mfma(a, bh, z);
-                    z = mfma(a, bm, z);
-                    z = mfma(a, bl, z);
-                    z = mfma(al, bh, z);
-                    z = mfma(al, bm, z);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) a64[t][v] += (double)z[v];
-                }
+                for (int v = 0; v < 4; ++v) a64[t][v] += (double)z[v];
             }
         }
     }
-    if (!rl) return;
+}
+
+// Resources and geometry of one phase A task or phase B segment.
+template <int MODE>
+struct MfSrc {
+    rsrc_t a, al, x[3];
+    int k;      // phase A: rank (row length of V); phase B: slice rows (ld)
+    int ngr;    // 8-groups of the K dimension
+};
+
+// Phase A.  Lane (c = lane % 16, q = lane / 16) feeds rank row c of each
+// 16-rank tile and right-hand side c of the x operand, over rows 8q..8q+7 of
+// each 32-row step.  Result lane layout: rank 4q + v of the tile, right-hand
+// side c.  A wavefront walks tasks w, w + nw, w + 2 nw, ... (the list is
+// sorted by size, so the strided walk balances) as one pipeline over
+// (task, step), two operand sets in turn: the next step's operands, possibly
+// of the next task, are in flight while the current products run.  A
+// one-chunk block writes its t splits (zero padding up to pad8(k) included)
+// directly; larger blocks leave FP64 partials for k_mf_tstage.
+template <int MODE>
+__device__ __forceinline__ MfSrc<MODE> mf_src_a(const MfVt &tk, const uint16_t *xs, int64_t xsplit, int64_t np) {
+    MfSrc<MODE> r;
+    const int vbytes = tk.ng * tk.k * 16;
+    r.a = make_rsrc(tk.V, vbytes);
+    if constexpr (MODE == kMatvecAccurate) r.al = make_rsrc(tk.Vlo, vbytes);
+    const uint16_t *xb = xs + ((int64_t)tk.band * (np / 8) + tk.xoff / 8) * 128;
+#pragma unroll
+    for (int sp = 0; sp < MfOps<MODE>::NS; ++sp) r.x[sp] = make_rsrc(xb + sp * xsplit, tk.ng * 256);
+    r.k = tk.k;
+    r.ngr = tk.ng;
+    return r;
+}
+
+template <int MODE>
+__device__ __forceinline__ void mf_load_a(const MfSrc<MODE> &r, int kt0, int g0, bool valid, int c, int q,
+                                          MfOps<MODE> &o) {
+    const int g = g0 + q;
+    const int xo = valid ? (g * 16 + c) * 16 : kOOB;
+#pragma unroll
+    for (int sp = 0; sp < MfOps<MODE>::NS; ++sp) o.bx[sp] = bload(r.x[sp], xo);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int rk = kt0 + 16 * t + c;
+        const int off = valid && rk < r.k ? (g * r.k + rk) * 16 : kOOB;
+        o.a[t] = bload(r.a, off);
+        if constexpr (MODE == kMatvecAccurate) o.al[t] = bload(r.al, off);
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void mf_finish_a(const MfVt &tk, int c, int q, const f32x4 acc[4], const double a64[4][4],
+                                            double *part, int64_t ldp, uint16_t *ts, int64_t tsplit, int r0, int nr) {
+    const int nt = min(4, (tk.k - tk.kt0 + 15) / 16);
+    const int k8 = (int)pad8(tk.k);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         if (t < nt) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rk = tk.kt0 + 16 * t + 4 * q + v;
-                if (rk < tk.k)
-                    part[(int64_t)(r0 + c) * ldp + tk.out + rk] = MODE == kMatvecLow ? (double)acc[t][v] : a64[t][v];
+                const double val = rk < tk.k ? (MODE == kMatvecLow ? (double)acc[t][v] : a64[t][v]) : 0.0;
+                if (tk.direct) {
+                    if (rk < k8) {
+                        uint16_t h, m, lo;
+                        split3(val, h, m, lo);
+                        const int64_t off = ((tk.out + rk) / 8 * 16 + c) * 8 + rk % 8;
+                        ts[off] = h;
+                        ts[tsplit + off] = m;
+                        ts[2 * tsplit + off] = lo;
+                    }
+                } else if (rk < tk.k && c < nr) {
+                    part[(int64_t)(r0 + c) * ldp + tk.out + rk] = val;
+                }
             }
         }
     }
 }
 
-// t_b = sum of the chunk partials (fixed order), split into hi, mid, lo;
-// one wavefront per block, entries k..pad8(k)-1 are zeros
-__global__ __launch_bounds__(256) void k_mf_tstage(const MfRed *__restrict__ red, int64_t nred,
-                                                   const double *__restrict__ part, int64_t ldp,
-                                                   uint16_t *__restrict__ ts, int64_t tsplit, int64_t ldt, int r0,
-                                                   int nr) {
-    const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (item >= nred) return;
-    const MfRed rd = red[item];
-    const int k8 = (int)pad8(rd.k);
-    for (int l = threadIdx.x & 63; l < k8; l += 64)
-        for (int r = 0; r < nr; ++r) {
-            double sum = 0.0;
-            if (l < rd.k)
-                for (int c = 0; c < rd.chunks; ++c) sum += part[(int64_t)(r0 + r) * ldp + rd.part + (int64_t)c * rd.k + l];
-            uint16_t h, m, lo;
-            split3(sum, h, m, lo);
-            const int64_t o = (int64_t)(r0 + r) * ldt + rd.toff + l;
-            ts[o] = h;
-            ts[tsplit + o] = m;
-            ts[2 * tsplit + o] = lo;
+template <int MODE>
+__global__ __launch_bounds__(256) void k_mf_phase_a(const MfVt *__restrict__ tasks, int64_t ntask, int64_t nw,
+                                                    const uint16_t *__restrict__ xs, int64_t xsplit, int64_t np,
+                                                    double *__restrict__ part, int64_t ldp, uint16_t *__restrict__ ts,
+                                                    int64_t tsplit, int r0, int nr) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t ti = (int64_t)blockIdx.x * 4 + wave;
+    if (ti >= ntask) return;
+    const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4;
+    f32x4 acc[4];
+    double a64[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
+    // pipeline state: the task of the operands being consumed, and the next
+    MfVt cur = tasks[ti];
+    MfSrc<MODE> rc = mf_src_a<MODE>(cur, xs, xsplit, np);
+    int g0 = 0;
+    MfOps<MODE> o0, o1;   // two operand sets in turn (named: an indexed pair would live in scratch)
+    mf_load_a<MODE>(rc, cur.kt0, 0, true, c, q, o0);
+    int64_t tl = ti;      // task of the last issued load
+    MfVt tkl = cur;
+    MfSrc<MODE> rl = rc;
+    int gl = 0;
+    bool done = false;
+    // issue the loads of the step after (tl, gl) into `nx`, then the products of
+    // `cu`; the loads run one step ahead, so when a task's last step is consumed
+    // the next task is the one the loads have just moved to
+    auto step = [&](const MfOps<MODE> &cu, MfOps<MODE> &nx) {
+        int gn = gl + 4;
+        int64_t tn = tl;
+        if (gn >= tkl.ng) {
+            tn = tl + nw;
+            gn = 0;
+            if (tn < ntask) {
+                tkl = tasks[tn];
+                rl = mf_src_a<MODE>(tkl, xs, xsplit, np);
+            }
         }
+        // past the end: the same loads at out-of-range offsets (zeros)
+        mf_load_a<MODE>(rl, tkl.kt0, gn, tn < ntask, c, q, nx);
+        mf_products<MODE>(cu, min(4, (cur.k - cur.kt0 + 15) / 16), acc, a64);
+        g0 += 4;
+        if (g0 >= cur.ng) {
+            mf_finish_a<MODE>(cur, c, q, acc, a64, part, ldp, ts, tsplit, r0, nr);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
+            ti += nw;
+            g0 = 0;
+            if (ti < ntask) cur = tkl;
+            else done = true;
+        }
+        tl = tn;
+        gl = gn;
+    };
+    while (true) {
+        step(o0, o1);
+        if (done) break;
+        step(o1, o0);
+        if (done) break;
+    }
+}
+
+// t_b = sum of the chunk partials (fixed order), split into hi, mid, lo, for
+// the blocks of more than one chunk: one workgroup per block, a thread per
+// (right-hand side, rank) pair; entries k..pad8(k)-1 and right-hand sides
+// beyond the group's count are zeros
+__global__ __launch_bounds__(256) void k_mf_tstage(const MfRed *__restrict__ red, const double *__restrict__ part,
+                                                   int64_t ldp, uint16_t *__restrict__ ts, int64_t tsplit, int r0,
+                                                   int nr) {
+    const MfRed rd = red[blockIdx.x];
+    const int k8 = (int)pad8(rd.k);
+    for (int e = threadIdx.x; e < 16 * k8; e += blockDim.x) {
+        const int r = e / k8, l = e - r * k8;
+        double sum = 0.0;
+        if (l < rd.k && r < nr) {
+            const double *p = part + (int64_t)(r0 + r) * ldp + rd.part + l;
+            for (int c = 0; c < rd.chunks; ++c) sum += p[(int64_t)c * rd.k];
+        }
+        uint16_t h, m, lo;
+        split3(sum, h, m, lo);
+        const int64_t o = ((rd.toff + l) / 8 * 16 + r) * 8 + l % 8;
+        ts[o] = h;
+        ts[tsplit + o] = m;
+        ts[2 * tsplit + o] = lo;
+    }
 }
 
 // Phase B: one workgroup per (band, target leaf), W wavefronts over its
 // segments.  Lane (c, q) feeds row c of each 16-row tile and right-hand side
 // c of the coefficient operand, over columns 8q..8q+7 of each 32-column step.
 // Result lane layout: row 4q + v of the tile, right-hand side c; the W
-// wavefront sums are added in a fixed order through LDS.
+// wavefront sums are added in a fixed order through LDS.  Each wavefront runs
+// one pipeline over (segment, step), two operand sets in turn.
+template <int MODE>
+__device__ __forceinline__ MfSrc<MODE> mf_src_b(const Seg &sg, const uint16_t *xb, int64_t xsplit, const uint16_t *tb,
+                                                int64_t tsplit) {
+    MfSrc<MODE> r;
+    const int kg = (sg.K + 7) / 8;
+    const int abytes = kg * sg.ld * 16;
+    r.a = make_rsrc(sg.data, abytes);
+    if constexpr (MODE == kMatvecAccurate) r.al = make_rsrc(sg.lo, abytes);
+    const uint16_t *src = (sg.is_lr ? tb : xb) + sg.coef_off / 8 * 128;
+    const int64_t sst = sg.is_lr ? tsplit : xsplit;
+#pragma unroll
+    for (int sp = 0; sp < MfOps<MODE>::NS; ++sp) r.x[sp] = make_rsrc(src + sp * sst, kg * 256);
+    r.k = sg.ld;
+    r.ngr = kg;
+    return r;
+}
+
+template <int MODE>
+__device__ __forceinline__ void mf_load_b(const MfSrc<MODE> &r, int g0, bool valid, int c, int q, int rb, int rows,
+                                          MfOps<MODE> &o) {
+    const int g = g0 + q;
+    const int xo = valid ? (g * 16 + c) * 16 : kOOB;
+#pragma unroll
+    for (int sp = 0; sp < MfOps<MODE>::NS; ++sp) o.bx[sp] = bload(r.x[sp], xo);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int row = rb + 16 * t + c;
+        const int off = valid && row < rows ? (g * r.k + row) * 16 : kOOB;
+        o.a[t] = bload(r.a, off);
+        if constexpr (MODE == kMatvecAccurate) o.al[t] = bload(r.al, off);
+    }
+}
+
 template <int MODE, int W>
 __global__ __launch_bounds__(64 * W) void k_mf_phase_b(const LeafWork *__restrict__ leaves,
                                                        const Seg *__restrict__ segs, const uint16_t *__restrict__ xs,
-                                                       int64_t xsplit, int64_t ldx, int64_t xbs,
-                                                       const uint16_t *__restrict__ ts, int64_t tsplit, int64_t ldt,
-                                                       const double *__restrict__ y0, double *__restrict__ y,
-                                                       int64_t ldy, int64_t ybs, int r0, int nr) {
+                                                       int64_t xsplit, int64_t np, const uint16_t *__restrict__ ts,
+                                                       int64_t tsplit, const double *__restrict__ y0,
+                                                       double *__restrict__ y, int64_t ldy, int64_t ybs, int r0,
+                                                       int nr) {
     using PT = typename std::conditional<MODE == kMatvecAccurate, double, float>::type;
     __shared__ PT part[W][64][17];
     const LeafWork lw = leaves[blockIdx.x];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, c = lane & 15, q = lane >> 4;
-    const bool rl = c < nr;
-    const int rc = r0 + (rl ? c : 0);
-    const uint16_t *xb = xs + (int64_t)lw.band * xbs + (int64_t)rc * ldx;
-    const uint16_t *tb = ts + (int64_t)rc * ldt;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4;
+    const uint16_t *xb = xs + (int64_t)lw.band * (np / 8) * 128;
     y += (int64_t)lw.band * ybs;
     if (y0) y0 += (int64_t)lw.band * ybs;
     for (int rb = 0; rb < lw.rows; rb += 64) {
@@ -461,44 +611,43 @@ __global__ __launch_bounds__(64 * W) void k_mf_phase_b(const LeafWork *__restric
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
-        for (int s = lw.seg0 + wid; s < lw.seg1; s += W) {
-            const Seg sg = segs[s];
-            const uint16_t *src = (sg.is_lr ? tb : xb) + sg.coef_off;
-            const int64_t sst = sg.is_lr ? tsplit : xsplit;
-            const uint16_t *A = static_cast<const uint16_t *>(sg.data), *Al = static_cast<const uint16_t *>(sg.lo);
-            const int kg = (sg.K + 7) / 8;
-            for (int g0 = 0; g0 < kg; g0 += 4) {
-                const int g = g0 + q;
-                const bool live = g < kg;
-                bf16x8 bh = zero8(), bm = zero8(), bl = zero8();
-                if (live && rl) {
-                    bh = ld8(src + 8 * g);
-                    bm = ld8(src + sst + 8 * g);
-                    if constexpr (MODE == kMatvecAccurate) bl = ld8(src + 2 * sst + 8 * g);
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (t < nrt) {
-                        const int row = rb + 16 * t + c;
-                        const bool ok = live && row < lw.rows;
-                        const int64_t o = ((int64_t)g * sg.ld + row) * 8;
-                        const bf16x8 a = ok ? ld8(A + o) : zero8();
-                        if constexpr (MODE == kMatvecLow) {
-                            acc[t] = mfma(a, bh, acc[t]);
-                            acc[t] = mfma(a, bm, acc[t]);
-                        } else {
-                            const bf16x8 al = ok ? ld8(Al + o) : zero8();
-                            f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-                            z = mfma(a, bh, z);
-                            z = mfma(a, bm, z);
-                            z = mfma(a, bl, z);
-                            z = mfma(al, bh, z);
-                            z = mfma(al, bm, z);
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) a64[t][v] += (double)z[v];
-                        }
+        int si = lw.seg0 + wid;
+        if (si < lw.seg1) {
+            Seg sl = segs[si];                       // segment of the last issued load
+            MfSrc<MODE> rl = mf_src_b<MODE>(sl, xb, xsplit, ts, tsplit);
+            int gl = 0, g0 = 0, sc = si;              // (sc, g0): step being consumed
+            int kgc = rl.ngr;
+            MfOps<MODE> o0, o1;   // two operand sets in turn (named: an indexed pair would live in scratch)
+            mf_load_b<MODE>(rl, 0, true, c, q, rb, lw.rows, o0);
+            int sl_i = si;
+            bool done = false;
+            auto step = [&](const MfOps<MODE> &cu, MfOps<MODE> &nx) {
+                int gn = gl + 4, sn = sl_i;
+                if (gn >= rl.ngr) {
+                    sn = sl_i + W;
+                    gn = 0;
+                    if (sn < lw.seg1) {
+                        sl = segs[sn];
+                        rl = mf_src_b<MODE>(sl, xb, xsplit, ts, tsplit);
                     }
                 }
+                mf_load_b<MODE>(rl, gn, sn < lw.seg1, c, q, rb, lw.rows, nx);
+                mf_products<MODE>(cu, nrt, acc, a64);
+                g0 += 4;
+                if (g0 >= kgc) {
+                    sc += W;
+                    g0 = 0;
+                    if (sc < lw.seg1) kgc = rl.ngr;   // the loads have just moved to segment sc
+                    else done = true;
+                }
+                sl_i = sn;
+                gl = gn;
+            };
+            while (true) {
+                step(o0, o1);
+                if (done) break;
+                step(o1, o0);
+                if (done) break;
             }
         }
 #pragma unroll
@@ -578,44 +727,58 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
     }
 }
 
-// BF16 storage on the matrix cores.  Workspace (per call): phase A partials
-// [nrhs][npart] FP64, then the staged x [3][nb * nrhs][np] and t [3][nrhs][ktot]
-// BF16 splits.
+// Workgroups of `kernel` (block threads, no dynamic LDS) that are resident at
+// once on the current device: a persistent launch uses exactly these.
+template <typename K>
+int64_t resident_workgroups(K kernel, int block) {
+    int dev = 0, cus = 0, per_cu = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0));
+    return std::max<int64_t>(1, (int64_t)cus * std::max(per_cu, 1));
+}
+
+// BF16 storage on the matrix cores.  Workspace: phase A partials [nrhs][npart]
+// FP64, then the staged operands of one group of 16 right-hand sides, x
+// [3][nb][np / 8][16][8] and t [3][ktot / 8][16][8] BF16.
 template <int MODE>
 void launch_mf(const MatvecPlan &mp, int nrhs, const double *x, const double *y0, double *y, double *tb,
                hipStream_t s) {
     const int64_t ldp = std::max<int64_t>(mp.npart, 1);
     double *part = tb;
     uint16_t *xs = reinterpret_cast<uint16_t *>(tb + ((ldp * nrhs + 1) & ~(int64_t)1));   // 16-byte aligned
-    const int64_t nvec = (int64_t)mp.nb * nrhs, xsplit = nvec * mp.np;
+    const int64_t xsplit = (int64_t)mp.nb * mp.np * 16;
     uint16_t *ts = xs + 3 * xsplit;
-    const int64_t tsplit = (int64_t)nrhs * mp.ktot;
-    const int64_t xbs = (int64_t)nrhs * mp.np, ybs = (int64_t)nrhs * mp.n_tgt;
-    if (xsplit) {
-        k_mf_xstage<<<(unsigned)((xsplit + 255) / 256), 256, 0, s>>>(mp.pmap_p, mp.np, nvec, x, mp.n_src, xs, xsplit);
-        HIP_LAUNCH_CHECK();
-    }
+    const int64_t tsplit = mp.ktot * 16;
+    const int64_t ybs = (int64_t)nrhs * mp.n_tgt;
     for (int r0 = 0; r0 < nrhs; r0 += 16) {
         const int nr = std::min(16, nrhs - r0);
+        k_mf_xstage<<<(unsigned)((xsplit + 255) / 256), 256, 0, s>>>(mp.pmap_p, mp.np, mp.nb, nrhs, r0, nr, x,
+                                                                     mp.n_src, xs, xsplit);
+        HIP_LAUNCH_CHECK();
         if (mp.n_vt) {
-            k_mf_phase_a<MODE><<<(unsigned)((mp.n_vt + 3) / 4), 256, 0, s>>>(mp.vt.as<MfVt>(), mp.n_vt, xs, xsplit,
-                                                                          mp.np, xbs, part, ldp, r0, nr);
+            // the resident wavefronts, each walking a strided task list
+            static const int64_t resident = resident_workgroups(k_mf_phase_a<MODE>, 256);
+            const int64_t nwg = std::min<int64_t>((mp.n_vt + 3) / 4, resident);
+            k_mf_phase_a<MODE><<<(unsigned)nwg, 256, 0, s>>>(mp.vt.as<MfVt>(), mp.n_vt, nwg * 4, xs, xsplit, mp.np,
+                                                             part, ldp, ts, tsplit, r0, nr);
             HIP_LAUNCH_CHECK();
-            k_mf_tstage<<<(unsigned)((mp.n_red + 3) / 4), 256, 0, s>>>(mp.red.as<MfRed>(), mp.n_red, part, ldp, ts,
-                                                                      tsplit, mp.ktot, r0, nr);
-            HIP_LAUNCH_CHECK();
+            if (mp.n_red) {
+                k_mf_tstage<<<(unsigned)mp.n_red, 256, 0, s>>>(mp.red.as<MfRed>(), part, ldp, ts, tsplit, r0, nr);
+                HIP_LAUNCH_CHECK();
+            }
         }
         k_mf_phase_b<MODE, 4><<<(unsigned)mp.n_leaf, 256, 0, s>>>(mp.leaf.as<LeafWork>(), mp.seg.as<Seg>(), xs, xsplit,
-                                                                mp.np, xbs, ts, tsplit, mp.ktot, y0, y, mp.n_tgt,
-                                                                ybs, r0, nr);
+                                                                mp.np, ts, tsplit, y0, y, mp.n_tgt, ybs, r0, nr);
         HIP_LAUNCH_CHECK();
     }
 }
 
-// workspace doubles per right-hand side
-int64_t ws_words(const MatvecPlan &mp) {
-    if (!mp.mf) return mp.ktot + mp.npart;
-    return std::max<int64_t>(mp.npart, 1) + (6 * (int64_t)mp.nb * mp.np + 6 * mp.ktot + 15) / 8 + 2;
+// workspace doubles of a call with nrhs right-hand sides
+int64_t ws_words(const MatvecPlan &mp, int nrhs) {
+    if (!mp.mf) return (mp.ktot + mp.npart) * nrhs;
+    const int64_t bf16 = 3 * 16 * ((int64_t)mp.nb * mp.np + mp.ktot);
+    return std::max<int64_t>(mp.npart, 1) * nrhs + 2 + (2 * bf16 + 7) / 8;
 }
 
 }  // namespace
@@ -637,7 +800,7 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     std::vector<VtReduce> red;
     int64_t ktot = 0, npart = 0, maxk = 0;
     // about this many bytes of V per wavefront task
-    const int64_t chunk_bytes = 48 * 1024;
+    const int64_t chunk_bytes = 48 * 1024, mf_task_bytes = 64 * 1024;
     const int64_t esz = H.precision == RTE_FP64 ? 8 : H.precision == RTE_FP32 ? 4 : 2;
     const auto &leaves = P.tgt_leaves;
     std::vector<int64_t> starts;
@@ -660,17 +823,23 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
             const int32_t k = B.rank[b];
             const int64_t wp = H.pwidth(bl.s0, bl.s1);
             toff[b] = ktot;
-            const int64_t rows = std::max<int64_t>(32, chunk_bytes / (2 * k) / 32 * 32);
+            // about mf_task_bytes of V per task (a task takes up to 64 ranks)
+            const int64_t rows = std::min<int64_t>(8192, std::max<int64_t>(256, mf_task_bytes / (2 * std::min(64, k)))) / 32 * 32;
             const int64_t chunks = (wp + rows - 1) / rows;
-            mred.push_back({npart, ktot, (int32_t)chunks, k});
             const uint16_t *V = static_cast<const uint16_t *>(B.V[b]), *Vl = static_cast<const uint16_t *>(B.Vlo[b]);
-            for (int64_t c = 0; c < chunks; ++c) {
-                const int64_t nj = std::min(rows, wp - c * rows);
+            if (chunks == 1) {
                 for (int32_t kt0 = 0; kt0 < k; kt0 += 64)
-                    mvt.push_back({V + c * rows * k, Vl + c * rows * k, H.src_p_h[bl.s0] + c * rows, npart + c * k,
-                                   (int32_t)(nj / 8), k, bi, kt0});
+                    mvt.push_back({V, Vl, H.src_p_h[bl.s0], ktot, (int32_t)(wp / 8), k, bi, kt0, 1});
+            } else {
+                mred.push_back({npart, ktot, (int32_t)chunks, k});
+                for (int64_t c = 0; c < chunks; ++c) {
+                    const int64_t nj = std::min(rows, wp - c * rows);
+                    for (int32_t kt0 = 0; kt0 < k; kt0 += 64)
+                        mvt.push_back({V + c * rows * k, Vl + c * rows * k, H.src_p_h[bl.s0] + c * rows,
+                                       npart + c * k, (int32_t)(nj / 8), k, bi, kt0, 0});
+                }
+                npart += chunks * k;
             }
-            npart += chunks * k;
             maxk = std::max<int64_t>(maxk, k);
             ktot += pad8(k);
         }
@@ -786,7 +955,7 @@ void matvec_build_all(HMat &H, hipStream_t s) {
     H.mv_all = build_plan(H, all, s);
 }
 
-int64_t matvec_ktot_all(const HMat &H) { return ws_words(H.mv_all ? *H.mv_all : *H.mv[0]); }
+int64_t matvec_ws_all(const HMat &H, int nrhs) { return ws_words(H.mv_all ? *H.mv_all : *H.mv[0], nrhs); }
 
 void matvec_launch_all(const HMat &H, int nrhs, const double *x_c, double *y_c, const double *y0_c, double *tbuf,
                        hipStream_t s, int mode) {
@@ -794,7 +963,7 @@ void matvec_launch_all(const HMat &H, int nrhs, const double *x_c, double *y_c, 
 }
 
 // workspace doubles per right-hand side: t, then the partial sums of chunked blocks
-int64_t matvec_ktot(const HMat &H, int band) { return ws_words(*H.mv[band]); }
+int64_t matvec_ws(const HMat &H, int band, int nrhs) { return ws_words(*H.mv[band], nrhs); }
 
 void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                       double *tbuf, hipStream_t s, int mode) {
@@ -803,7 +972,7 @@ void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, doub
 
 void matvec_launch(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                    hipStream_t s, int mode) {
-    DevBuf tb(sizeof(double) * (size_t)matvec_ktot(H, band) * nrhs);
+    DevBuf tb(sizeof(double) * (size_t)matvec_ws(H, band, nrhs));
     matvec_launch_ws(H, band, nrhs, x_c, y_c, y0_c, tb.as<double>(), s, mode);
     HIP_CHECK(hipStreamSynchronize(s));
 }

@@ -28,10 +28,10 @@ double factorial(int k) {
 }
 
 struct Moments {
-    int nvert;
+    int nvert, degree;
     std::vector<std::vector<int>> alpha;
     std::vector<double> exact;
-    Moments(int nv, int degree) : nvert(nv) {
+    Moments(int nv, int deg) : nvert(nv), degree(deg) {
         std::vector<int> a(nv, 0);
         std::function<void(int, int)> rec = [&](int pos, int left) {
             if (pos == nv - 1) {
@@ -69,12 +69,21 @@ std::vector<double> residual(const Moments &M, const Builder &b, const std::vect
     std::vector<std::vector<double>> pts;
     std::vector<double> w;
     b(x, pts, w);
+    // integer powers of every barycentric coordinate, up to the rule degree
+    const int D = M.degree + 1;
+    std::vector<double> pw(pts.size() * M.nvert * D);
+    for (size_t q = 0; q < pts.size(); ++q)
+        for (int d = 0; d < M.nvert; ++d) {
+            double *p = &pw[(q * M.nvert + d) * D];
+            p[0] = 1.0;
+            for (int e = 1; e < D; ++e) p[e] = p[e - 1] * pts[q][d];
+        }
     std::vector<double> r(M.alpha.size());
     for (size_t k = 0; k < M.alpha.size(); ++k) {
         double v = 0;
         for (size_t q = 0; q < pts.size(); ++q) {
             double m = w[q];
-            for (int d = 0; d < M.nvert; ++d) m *= std::pow(pts[q][d], M.alpha[k][d]);
+            for (int d = 0; d < M.nvert; ++d) m *= pw[(q * M.nvert + d) * D + M.alpha[k][d]];
             v += m;
         }
         r[k] = v - M.exact[k];

@@ -239,14 +239,14 @@ constexpr int kMatvecLow = 0;
 constexpr int kMatvecAccurate = 1;
 void matvec_launch(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                    hipStream_t s, int mode = kMatvecAccurate);
-// Same with a caller-provided workspace of nrhs * matvec_ktot(H, band) doubles; does not synchronise.
+// Same with a caller-provided workspace of matvec_ws(H, band, nrhs) doubles; does not synchronise.
 void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                       double *tbuf, hipStream_t s, int mode = kMatvecAccurate);
-int64_t matvec_ktot(const HMat &H, int band);
+int64_t matvec_ws(const HMat &H, int band, int nrhs);
 // All bands at once: x, y, y0 are [n_bands][nrhs][N] (band-major); workspace
-// nrhs * matvec_ktot_all(H) doubles.  Does not synchronise.
+// matvec_ws_all(H, nrhs) doubles.  Does not synchronise.
 void matvec_build_all(HMat &H, hipStream_t s);
-int64_t matvec_ktot_all(const HMat &H);
+int64_t matvec_ws_all(const HMat &H, int nrhs);
 void matvec_launch_all(const HMat &H, int nrhs, const double *x_c, double *y_c, const double *y0_c, double *tbuf,
                        hipStream_t s, int mode = kMatvecAccurate);
 void permute_gather(const int64_t *perm, int64_t n, int nrhs, int64_t ld_in, int64_t ld_out, const double *in,

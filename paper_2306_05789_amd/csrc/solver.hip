@@ -171,6 +171,39 @@ __global__ void k_sub(const double *__restrict__ a, const double *__restrict__ b
     if (k < n) out[k] = a[k] - b[k];
 }
 
+// Captured sweeps of one solve, keyed by what the captured launches bake in:
+// the operator, the Newton step, and the buffers (J and Jn swap every sweep).
+struct GraphKey {
+    int mode;
+    bool newton;
+    const void *y0, *sub, *J, *Jn, *S;
+    bool operator==(const GraphKey &o) const {
+        return mode == o.mode && newton == o.newton && y0 == o.y0 && sub == o.sub && J == o.J && Jn == o.Jn &&
+               S == o.S;
+    }
+};
+
+struct GraphCache {
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> items;
+    hipGraphExec_t find(const GraphKey &k) const {
+        for (auto &it : items)
+            if (it.first == k) return it.second;
+        return nullptr;
+    }
+    hipGraphExec_t add(const GraphKey &k, hipGraph_t g) {
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) throw Error(RTE_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        items.push_back({k, ex});
+        return ex;
+    }
+    int size() const { return (int)items.size(); }
+    ~GraphCache() {
+        for (auto &it : items) (void)hipGraphExecDestroy(it.second);
+    }
+};
+
 void check_desc(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_desc_t &d) {
     RTE_REQUIRE(G.kind == RTE_VOLUME && S.kind == RTE_SURFACE, "solve: need a volume and a surface H-matrix");
     RTE_REQUIRE(G.mesh == &m && S.mesh == &m, "solve: H-matrices were assembled on another mesh");
@@ -183,6 +216,7 @@ void check_desc(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_des
     RTE_REQUIRE(d.max_iter >= 1, "solve: max_iter must be >= 1");
     RTE_REQUIRE(d.precision == RTE_FP64 || d.precision == RTE_FP32 || d.precision == RTE_MIXED_BF16,
                 "solve: unknown precision");
+    RTE_REQUIRE(d.launch == RTE_LAUNCH_STREAM || d.launch == RTE_LAUNCH_GRAPH, "solve: unknown launch mode");
     RTE_REQUIRE(d.precision != RTE_MIXED_BF16 || G.precision == RTE_MIXED_BF16,
                 "solve: the mixed-precision iteration needs a volume matrix assembled with RTE_MIXED_BF16");
     if (!d.grey) {
@@ -200,9 +234,35 @@ void check_desc(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_des
 
 }  // namespace
 
+// Graph launch works on a stream of its own (non-blocking, default priority):
+// capture is not allowed on the null stream.  It is ordered after the caller's
+// stream on entry, and the caller's stream after it on exit.
+struct SolveStream {
+    hipStream_t user, own = nullptr;
+    hipEvent_t ev = nullptr;
+    SolveStream(hipStream_t u, bool separate) : user(u) {
+        if (!separate) return;
+        HIP_CHECK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(ev, user));
+        HIP_CHECK(hipStreamWaitEvent(own, ev, 0));
+    }
+    hipStream_t get() const { return own ? own : user; }
+    ~SolveStream() {
+        if (!own) return;
+        (void)hipEventRecord(ev, own);
+        (void)hipStreamWaitEvent(user, ev, 0);
+        (void)hipStreamSynchronize(own);
+        (void)hipEventDestroy(ev);
+        (void)hipStreamDestroy(own);
+    }
+};
+
 rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_desc_t &d,
-                               double *T_out, double *J_out, rte_solve_stats_t *st, hipStream_t s) {
+                               double *T_out, double *J_out, rte_solve_stats_t *st, hipStream_t s_user) {
     check_desc(m, G, S, d);
+    SolveStream ss(s_user, d.launch == RTE_LAUNCH_GRAPH);
+    const hipStream_t s = ss.get();
     const auto t_start = std::chrono::steady_clock::now();
     const int nb = d.n_bands, nr = d.nrhs;
     const int64_t N = m.N, L = m.L;
@@ -233,8 +293,8 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
         Sv(sizeof(double) * vecN * nb), J(sizeof(double) * vecN * nb), Jn(sizeof(double) * vecN * nb),
         T(sizeof(double) * vecN), part(sizeof(double) * 2 * kResidBlocks * nb * nr),
         res(sizeof(double) * 2 * nb * nr), viol(sizeof(unsigned long long));
-    const int64_t kt = std::max<int64_t>({1, matvec_ktot_all(G), matvec_ktot_all(S)});
-    DevBuf tbuf(sizeof(double) * kt * nr);
+    const int64_t kt = std::max<int64_t>({1, matvec_ws_all(G, nr), matvec_ws_all(S, nr)});
+    DevBuf tbuf(sizeof(double) * kt);
     const unsigned gN = (unsigned)((vecN + 255) / 256), gL = (unsigned)((L * nr + 255) / 256);
 
     // boundary source: Q_b = B_b(T_wall) and S^E_b = S_hat_b Q_b
@@ -256,15 +316,16 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
     DevBuf Jacc(mixed ? sizeof(double) * vecN * nb : 0), Sm(mixed ? sizeof(double) * vecN * nb : 0);
 
     // one sweep: S = S(T, J) (minus Sm when given); Jn = y0 + G S over all bands;
-    // residual(J, Jn); T = T(Jn); J <- Jn
-    auto sweep = [&](int mode, const double *y0, bool newton, const double *sub) -> double {
+    // residual(J, Jn); T = T(Jn); J <- Jn.  The kernels only (no copies, no
+    // memsets), so that a sweep can be captured in a graph.
+    auto enqueue = [&](int mode, const double *y0, bool newton, const double *sub, bool timed) {
         k_source<<<gN, 256, 0, s>>>(bp, T.as<double>(), J.as<double>(), N, nr, Sv.as<double>());
         if (sub)
             k_sub<<<(unsigned)((vecN * nb + 255) / 256), 256, 0, s>>>(Sv.as<double>(), sub, vecN * nb, Sv.as<double>());
         HIP_LAUNCH_CHECK();
-        HIP_CHECK(hipEventRecord(e0, s));
+        if (timed) HIP_CHECK(hipEventRecord(e0, s));
         matvec_launch_all(G, nr, Sv.as<double>(), Jn.as<double>(), y0, tbuf.as<double>(), s, mode);
-        HIP_CHECK(hipEventRecord(e1, s));
+        if (timed) HIP_CHECK(hipEventRecord(e1, s));
         k_resid_partial<<<dim3(kResidBlocks, nb * nr), 256, 0, s>>>(J.as<double>(), Jn.as<double>(), N,
                                                                      part.as<double>());
         k_resid_final<<<(nb * nr + 63) / 64, 64, 0, s>>>(part.as<double>(), nb * nr, res.as<double>());
@@ -272,6 +333,31 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
             k_newton<<<gN, 256, 0, s>>>(bp, Jn.as<double>(), G.kappa_c.as<double>(), N, nr, T.as<double>(),
                                         viol.as<unsigned long long>());
         HIP_LAUNCH_CHECK();
+    };
+    GraphCache graphs;
+    auto sweep = [&](int mode, const double *y0, bool newton, const double *sub) -> double {
+        if (d.launch == RTE_LAUNCH_GRAPH) {
+            const GraphKey key{mode, newton, y0, sub, J.p, Jn.p, Sv.p};
+            hipGraphExec_t ex = graphs.find(key);
+            if (!ex) {
+                hipGraph_t g = nullptr;
+                HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                try {
+                    enqueue(mode, y0, newton, sub, false);
+                } catch (...) {
+                    // leave the stream out of capture mode before reporting
+                    if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                HIP_CHECK(hipStreamEndCapture(s, &g));
+                ex = graphs.add(key, g);
+            }
+            HIP_CHECK(hipEventRecord(e0, s));
+            HIP_CHECK(hipGraphLaunch(ex, s));
+            HIP_CHECK(hipEventRecord(e1, s));
+        } else {
+            enqueue(mode, y0, newton, sub, true);
+        }
         HIP_CHECK(hipMemcpyAsync(rv.data(), res.p, sizeof(double) * rv.size(), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         float ms = 0.0f;
@@ -343,6 +429,7 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
         st->monotone_violations = (int64_t)nviol;
         st->ms_matvec = mv_ms;
         st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        st->graphs = graphs.size();
     }
     if (!std::isfinite(r)) throw Error(RTE_E_INTERNAL, "solve: the residual is not finite");
     return conv ? RTE_OK : RTE_E_NOT_CONVERGED;

@@ -60,12 +60,13 @@ class SolveDesc(C.Structure):
     _fields_ = [("n_bands", C.c_int32), ("nu", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
                 ("a", C.POINTER(C.c_double)), ("grey", C.c_int32), ("nrhs", C.c_int32),
                 ("T_wall", C.c_void_p), ("T0", C.c_void_p), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("launch", C.c_int32)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("outer_steps", C.c_int32), ("residual", C.c_double),
-                ("monotone_violations", C.c_int64), ("ms_total", C.c_double), ("ms_matvec", C.c_double)]
+                ("monotone_violations", C.c_int64), ("ms_total", C.c_double), ("ms_matvec", C.c_double),
+                ("graphs", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,6 +87,7 @@ SIGNATURES = {
     "rte_hmat_assemble": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(HmatOpts), C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
     "rte_hmat_matvec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rte_hmat_matvec_batched": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "rte_hmat_stats": (C.c_int, [C.c_void_p, C.POINTER(HmatStats)]),
     "rte_hmat_block_factors": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
@@ -242,6 +244,17 @@ def rte_hmat_matvec(hmat: HMat, band, x, y, stream=None):
     return y
 
 
+RTE_OP_ACCURATE, RTE_OP_LOW = 0, 1
+RTE_LAUNCH_STREAM, RTE_LAUNCH_GRAPH = 0, 1
+
+
+def rte_hmat_matvec_batched(hmat: HMat, x, y, op=RTE_OP_ACCURATE, stream=None):
+    """x: float64 device [n_bands, nrhs, N_src]; y: [n_bands, nrhs, N_tgt]."""
+    nrhs = int(x.shape[1])
+    _check(load().rte_hmat_matvec_batched(hmat.handle, nrhs, _ptr(x), _ptr(y), int(op), _stream(stream)))
+    return y
+
+
 def rte_hmat_stats(hmat: HMat) -> dict:
     st = HmatStats()
     _check(load().rte_hmat_stats(hmat.handle, C.byref(st)))
@@ -266,7 +279,7 @@ def rte_hmat_block_factors(hmat: HMat, band: int, block: int, factors: bool = Tr
 
 def rte_fixed_point_solve(mesh: Mesh, vol: HMat, surf: HMat, T_wall, T_out, J_out=None, *, grey=True,
                           nu=None, w=None, a=None, T0=None, tol=1e-10, max_iter=1000, precision=RTE_FP64,
-                          stream=None, allow_not_converged=False) -> dict:
+                          launch=None, stream=None, allow_not_converged=False) -> dict:
     """T_wall: float64 device [nrhs, L]; T_out: [nrhs, N]; J_out: [nrhs, n_bands, N] or None."""
     nrhs = 1 if T_wall.dim() == 1 else int(T_wall.shape[0])
     nb = 1 if grey else len(nu)
@@ -278,6 +291,7 @@ def rte_fixed_point_solve(mesh: Mesh, vol: HMat, surf: HMat, T_wall, T_out, J_ou
     d.T_wall = T_wall.data_ptr()
     d.T0 = T0.data_ptr() if T0 is not None else None
     d.tol, d.max_iter, d.precision = float(tol), int(max_iter), int(precision)
+    d.launch = RTE_LAUNCH_GRAPH if launch is None else int(launch)
     st = SolveStats()
     allow = (RTE_OK, RTE_E_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
     status = _check(load().rte_fixed_point_solve(mesh.handle, vol.handle, surf.handle, C.byref(d), _ptr(T_out),
