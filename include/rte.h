@@ -226,6 +226,74 @@ rte_status_t rte_fixed_point_solve(rte_mesh_t mesh, rte_hmat_t vol, rte_hmat_t s
                                    const rte_solve_desc_t *desc, double *T_out, double *J_out,
                                    rte_solve_stats_t *stats, void *stream);
 
+/* ------------------------------------------------------------------ request server
+ * Fixed-point solves of many requests on resident meshes, continuously
+ * batched: a request names a mesh, a subset of the band catalogue, a kappa
+ * multiplier per band (of the mesh's base field) and wall temperatures.  A
+ * multiplier m is snapped to the level l = round(levels_per_decade log10 m)
+ * of the ladder 10^(l / levels_per_decade) (ties to the lower level); the
+ * snapped value defines the request.  The operators of a (mesh, level) are
+ * assembled on first use, shared by every band of every request at that
+ * level and evicted least recently used, when unused, to stay within the HBM
+ * budget.  Requests are admitted in arrival order when their operators and
+ * state fit; each rte_server_step runs one sweep of every admitted request
+ * (columns that share an operator in one matvec) and retires the ones that
+ * converged.  Band weights are the trapezoid weights of the whole catalogue.
+ * Not thread safe: one thread drives a server. */
+typedef struct rte_server *rte_server_t;
+
+typedef struct {
+    int64_t hbm_budget;          /* bytes of operators and request state; 0 = 80% of the free device memory */
+    int32_t n_catalogue;         /* band catalogue size */
+    const double *nu;            /* host [n_catalogue], increasing */
+    int32_t levels_per_decade;   /* kappa ladder resolution */
+    int32_t leaf_size;
+    double eta, aca_eps;
+    int32_t precision;           /* RTE_FP64 (plain sweeps) or RTE_MIXED_BF16 (defect-corrected) */
+    int32_t max_active;          /* requests iterated together (1: one at a time) */
+} rte_server_desc_t;
+
+typedef struct {
+    int32_t mesh_id;
+    int32_t n_bands;
+    const int32_t *bands;        /* host [n_bands], increasing catalogue indices */
+    const double *kappa_mult;    /* host [n_bands], > 0 */
+    const double *T_wall;        /* device [L] (emitting vertices in ascending id order), copied at submit */
+    double tol;                  /* relative change of J that ends the request (FP64 residual) */
+    int32_t max_iter;
+} rte_request_t;
+
+enum { RTE_REQ_PENDING = 0, RTE_REQ_ACTIVE = 1, RTE_REQ_DONE = 2 };
+
+typedef struct {
+    int32_t state;               /* RTE_REQ_* */
+    int32_t converged;
+    int32_t iterations, outer_steps;
+    double residual;
+    int32_t n_bands;
+} rte_request_info_t;
+
+typedef struct {
+    int64_t budget, resident_bytes, operators;
+    int64_t assembled, evicted, over_budget;   /* over_budget: admitted alone beyond the budget */
+    int64_t submitted, completed, steps, columns;
+    double assemble_ms, sweep_ms;
+} rte_server_stats_t;
+
+rte_status_t rte_server_create(const rte_server_desc_t *desc, void *stream, rte_server_t *out);
+/* kappa: device [N], natural order (the base field); copied */
+rte_status_t rte_server_add_mesh(rte_server_t s, const rte_mesh_desc_t *mesh, const double *kappa, int32_t *mesh_id);
+rte_status_t rte_server_submit(rte_server_t s, const rte_request_t *req, int64_t *id);
+/* admission, then one sweep of every admitted request; synchronises the server's stream */
+rte_status_t rte_server_step(rte_server_t s, int32_t *n_active, int32_t *n_pending);
+rte_status_t rte_server_poll(rte_server_t s, int64_t id, rte_request_info_t *info);
+/* the snapped ladder level of every band of a request: host [n_bands] */
+rte_status_t rte_server_levels(rte_server_t s, int64_t id, int32_t *levels);
+/* T of a finished request (device [N], natural order); the request is then forgotten */
+rte_status_t rte_server_fetch(rte_server_t s, int64_t id, double *T_out);
+rte_status_t rte_server_stats(rte_server_t s, rte_server_stats_t *stats);
+void rte_server_destroy(rte_server_t s);
+
 /* ------------------------------------------------------------------ misc */
 const char *rte_status_string(rte_status_t s);
 const char *rte_last_error(void);

@@ -7,10 +7,7 @@
 #include <unordered_set>
 
 #include "rte_internal.h"
-
-namespace rte {
-void mesh_init(Mesh &M, const rte_mesh_desc_t &d);
-}
+#include "serve.h"
 
 using namespace rte;
 
@@ -68,7 +65,203 @@ void check_kappa(const double *kappa, int64_t n, hipStream_t s) {
 
 }  // namespace
 
+namespace rte {
+
+// Assembly of one H-matrix per band on a validated plan and kappa (device,
+// [n_bands][N], natural order); see rte_hmat_assemble.
+std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::unique_ptr<Plan> plan, int n_bands, const double *kappa,
+                                        hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    auto hm = std::make_unique<rte_hmat>();
+    HMat &H = hm->h;
+    HIP_CHECK(hipGetDevice(&H.device));
+    H.mesh = &m;
+    H.n_bands = n_bands;
+    const rte_hmat_opts_t *opts = &plan->opts;
+    H.precision = opts->precision;
+    H.kind = opts->kind;
+    H.plan = std::move(plan);
+    const Plan &P = *H.plan;
+    H.tgt_nat = upload(P.tgt_nat, s);
+    H.src_nat = upload(P.src_nat, s);
+    H.src_pos = upload(opts->kind == RTE_VOLUME ? P.tgt_nat : P.src.perm, s);
+    // FP64 / FP32 slices are column-major with rows padded to 4 (vector
+    // loads along the rows); BF16 slices are K-grouped (8 columns of a row
+    // contiguous) with unpadded rows and sources counted in stored
+    // coordinates in which every source leaf is rounded up to 8
+    const bool kgrouped = H.precision == RTE_MIXED_BF16;
+    H.kgroup = kgrouped ? 8 : 1;
+    const int64_t unit = kgrouped ? 1 : 4;
+    H.leaf_prp_h.assign(1, 0);
+    for (auto &lf : P.tgt_leaves)
+        H.leaf_prp_h.push_back(H.leaf_prp_h.back() + (lf.second - lf.first + unit - 1) / unit * unit);
+    H.leaf_start = upload(P.leaf_start, s);
+    H.leaf_prp = upload(H.leaf_prp_h, s);
+    {
+        const int64_t ns = (int64_t)P.src_nat.size();
+        H.src_p_h.assign(ns + 1, 0);
+        std::vector<int64_t> pmap;
+        int64_t pos = 0;
+        for (int id : P.src.leaves) {
+            const ClusterNode &nd = P.src.nodes[id];
+            for (int64_t j = nd.start; j < nd.stop; ++j) {
+                H.src_p_h[j] = pos + (j - nd.start);
+                pmap.push_back(j);
+            }
+            const int64_t w = kgrouped ? ((nd.stop - nd.start + 7) & ~(int64_t)7) : nd.stop - nd.start;
+            for (int64_t e = nd.stop - nd.start; e < w; ++e) pmap.push_back(-1);
+            pos += w;
+        }
+        H.src_p_h[ns] = pos;
+        H.n_src_p = pos;
+        H.src_p = upload(H.src_p_h, s);
+        H.src_pmap = upload(pmap, s);
+    }
+    H.kappa_c.alloc(sizeof(double) * (size_t)m.N * n_bands);
+    permute_gather(H.tgt_nat.as<int64_t>(), m.N, n_bands, m.N, m.N, kappa, H.kappa_c.as<double>(), s);
+    H.bands.resize(n_bands);
+    int64_t evaluated = 0, bytes = 0, dense_e = 0, lr_e = 0, nfb = 0, aca_e = 0;
+    double aca_ms = 0, fill_ms = 0, aca_entry_ms = 0;
+    int aca_l = 0, fill_l = 0, aca_entry_l = 0;
+    double wsum = 0, wr = 0;
+    int maxr = 0;
+    for (int b = 0; b < n_bands; ++b) {
+        assemble_band(H, b, kappa + (int64_t)b * m.N, s);
+        matvec_build(H, b, s);
+        const BandStore &B = H.bands[b];
+        evaluated += B.evaluated;
+        aca_e += B.aca_entries;
+        aca_ms += B.aca_ms;
+        aca_entry_ms += B.aca_entry_ms;
+        aca_entry_l += B.aca_entry_launches;
+        fill_ms += B.fill_ms;
+        aca_l += B.aca_launches;
+        fill_l += B.fill_launches;
+        bytes += B.bytes;
+        dense_e += B.dense_entries;
+        lr_e += B.lr_entries;
+        for (size_t k = 0; k < P.lowrank.size(); ++k) {
+            const Block &bl = P.lowrank[k];
+            const double mn = (double)((bl.t1 - bl.t0) + (bl.s1 - bl.s0));
+            if (B.rank[k] < 0) { ++nfb; continue; }
+            wsum += mn;
+            wr += mn * B.rank[k];
+            maxr = std::max(maxr, B.rank[k]);
+        }
+    }
+    matvec_build_all(H, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    rte_hmat_stats_t &st = H.stats;
+    st.n_tgt = (int64_t)P.tgt_nat.size();
+    st.n_src = (int64_t)P.src_nat.size();
+    st.n_bands = n_bands;
+    st.precision = H.precision;
+    st.n_dense = (int64_t)P.dense.size();
+    st.n_lowrank = (int64_t)P.lowrank.size();
+    st.n_fallback_dense = nfb;
+    st.dense_entries = dense_e;
+    st.lowrank_entries = lr_e;
+    st.max_rank = maxr;
+    st.mean_rank = wsum > 0 ? wr / wsum : 0.0;
+    st.compression = 1.0 - (double)(dense_e + lr_e) / ((double)st.n_tgt * st.n_src * n_bands);
+    st.bytes = bytes;
+    st.entries_evaluated = evaluated;
+    st.aca_entries = aca_e;
+    st.aca_kernel_ms = aca_ms;
+    st.aca_launches = aca_l;
+    st.aca_entry_ms = aca_entry_ms;
+    st.aca_entry_launches = aca_entry_l;
+    st.fill_kernel_ms = fill_ms;
+    st.fill_launches = fill_l;
+    st.assemble_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return hm;
+}
+
+}  // namespace rte
+
 extern "C" {
+
+rte_status_t rte_server_create(const rte_server_desc_t *desc, void *stream, rte_server_t *out) {
+    return guard([&] {
+        RTE_REQUIRE(desc && out, "rte_server_create: NULL argument");
+        *out = nullptr;
+        auto h = std::make_unique<rte_server>();
+        h->srv = server_create(*desc, (hipStream_t)stream);
+        *out = h.release();
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_server_add_mesh(rte_server_t s, const rte_mesh_desc_t *mesh, const double *kappa, int32_t *mesh_id) {
+    return guard([&] {
+        RTE_REQUIRE(s && mesh && mesh_id, "rte_server_add_mesh: NULL argument");
+        Mesh probe;
+        mesh_init(probe, *mesh);
+        check_kappa(kappa, probe.N, nullptr);
+        *mesh_id = server_add_mesh(*s->srv, *mesh, kappa);
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_server_submit(rte_server_t s, const rte_request_t *req, int64_t *id) {
+    return guard([&] {
+        RTE_REQUIRE(s && req && id, "rte_server_submit: NULL argument");
+        int64_t L = 0;
+        server_mesh_size(*s->srv, req->mesh_id, &L);
+        check_device_pointer(req->T_wall, "T_wall");
+        auto tw = to_host(req->T_wall, L, nullptr);
+        for (double v : tw) RTE_REQUIRE(std::isfinite(v) && v > 0.0, "request: T_wall must be finite and > 0");
+        *id = server_submit(*s->srv, *req);
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_server_step(rte_server_t s, int32_t *n_active, int32_t *n_pending) {
+    return guard([&] {
+        RTE_REQUIRE(s, "rte_server_step: NULL server");
+        server_step(*s->srv, n_active, n_pending);
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_server_poll(rte_server_t s, int64_t id, rte_request_info_t *info) {
+    return guard([&] {
+        RTE_REQUIRE(s && info, "rte_server_poll: NULL argument");
+        server_poll(*s->srv, id, *info);
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_server_levels(rte_server_t s, int64_t id, int32_t *levels) {
+    return guard([&] {
+        RTE_REQUIRE(s && levels, "rte_server_levels: NULL argument");
+        server_levels(*s->srv, id, levels);
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_server_fetch(rte_server_t s, int64_t id, double *T_out) {
+    return guard([&] {
+        RTE_REQUIRE(s && T_out, "rte_server_fetch: NULL argument");
+        check_device_pointer(T_out, "T_out");
+        server_fetch(*s->srv, id, T_out);
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_server_stats(rte_server_t s, rte_server_stats_t *stats) {
+    return guard([&] {
+        RTE_REQUIRE(s && stats, "rte_server_stats: NULL argument");
+        *stats = server_stats(*s->srv);
+        return RTE_OK;
+    });
+}
+
+void rte_server_destroy(rte_server_t s) {
+    if (!s) return;
+    server_destroy(s->srv);
+    delete s;
+}
 
 const char *rte_status_string(rte_status_t s) {
     switch (s) {
@@ -205,109 +398,7 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
         const Mesh &m = mesh->m;
         auto plan = build_plan(m, *opts);
         check_kappa(kappa, m.N * n_bands, s);
-        const auto t0 = std::chrono::steady_clock::now();
-        auto hm = std::make_unique<rte_hmat>();
-        HMat &H = hm->h;
-        HIP_CHECK(hipGetDevice(&H.device));
-        H.mesh = &m;
-        H.n_bands = n_bands;
-        H.precision = opts->precision;
-        H.kind = opts->kind;
-        H.plan = std::move(plan);
-        const Plan &P = *H.plan;
-        H.tgt_nat = upload(P.tgt_nat, s);
-        H.src_nat = upload(P.src_nat, s);
-        H.src_pos = upload(opts->kind == RTE_VOLUME ? P.tgt_nat : P.src.perm, s);
-        // FP64 / FP32 slices are column-major with rows padded to 4 (vector
-        // loads along the rows); BF16 slices are K-grouped (8 columns of a row
-        // contiguous) with unpadded rows and sources counted in stored
-        // coordinates in which every source leaf is rounded up to 8
-        const bool kgrouped = H.precision == RTE_MIXED_BF16;
-        H.kgroup = kgrouped ? 8 : 1;
-        const int64_t unit = kgrouped ? 1 : 4;
-        H.leaf_prp_h.assign(1, 0);
-        for (auto &lf : P.tgt_leaves)
-            H.leaf_prp_h.push_back(H.leaf_prp_h.back() + (lf.second - lf.first + unit - 1) / unit * unit);
-        H.leaf_start = upload(P.leaf_start, s);
-        H.leaf_prp = upload(H.leaf_prp_h, s);
-        {
-            const int64_t ns = (int64_t)P.src_nat.size();
-            H.src_p_h.assign(ns + 1, 0);
-            std::vector<int64_t> pmap;
-            int64_t pos = 0;
-            for (int id : P.src.leaves) {
-                const ClusterNode &nd = P.src.nodes[id];
-                for (int64_t j = nd.start; j < nd.stop; ++j) {
-                    H.src_p_h[j] = pos + (j - nd.start);
-                    pmap.push_back(j);
-                }
-                const int64_t w = kgrouped ? ((nd.stop - nd.start + 7) & ~(int64_t)7) : nd.stop - nd.start;
-                for (int64_t e = nd.stop - nd.start; e < w; ++e) pmap.push_back(-1);
-                pos += w;
-            }
-            H.src_p_h[ns] = pos;
-            H.n_src_p = pos;
-            H.src_p = upload(H.src_p_h, s);
-            H.src_pmap = upload(pmap, s);
-        }
-        H.kappa_c.alloc(sizeof(double) * (size_t)m.N * n_bands);
-        permute_gather(H.tgt_nat.as<int64_t>(), m.N, n_bands, m.N, m.N, kappa, H.kappa_c.as<double>(), s);
-        H.bands.resize(n_bands);
-        int64_t evaluated = 0, bytes = 0, dense_e = 0, lr_e = 0, nfb = 0, aca_e = 0;
-        double aca_ms = 0, fill_ms = 0, aca_entry_ms = 0;
-        int aca_l = 0, fill_l = 0, aca_entry_l = 0;
-        double wsum = 0, wr = 0;
-        int maxr = 0;
-        for (int b = 0; b < n_bands; ++b) {
-            assemble_band(H, b, kappa + (int64_t)b * m.N, s);
-            matvec_build(H, b, s);
-            const BandStore &B = H.bands[b];
-            evaluated += B.evaluated;
-            aca_e += B.aca_entries;
-            aca_ms += B.aca_ms;
-            aca_entry_ms += B.aca_entry_ms;
-            aca_entry_l += B.aca_entry_launches;
-            fill_ms += B.fill_ms;
-            aca_l += B.aca_launches;
-            fill_l += B.fill_launches;
-            bytes += B.bytes;
-            dense_e += B.dense_entries;
-            lr_e += B.lr_entries;
-            for (size_t k = 0; k < P.lowrank.size(); ++k) {
-                const Block &bl = P.lowrank[k];
-                const double mn = (double)((bl.t1 - bl.t0) + (bl.s1 - bl.s0));
-                if (B.rank[k] < 0) { ++nfb; continue; }
-                wsum += mn;
-                wr += mn * B.rank[k];
-                maxr = std::max(maxr, B.rank[k]);
-            }
-        }
-        matvec_build_all(H, s);
-        HIP_CHECK(hipStreamSynchronize(s));
-        rte_hmat_stats_t &st = H.stats;
-        st.n_tgt = (int64_t)P.tgt_nat.size();
-        st.n_src = (int64_t)P.src_nat.size();
-        st.n_bands = n_bands;
-        st.precision = H.precision;
-        st.n_dense = (int64_t)P.dense.size();
-        st.n_lowrank = (int64_t)P.lowrank.size();
-        st.n_fallback_dense = nfb;
-        st.dense_entries = dense_e;
-        st.lowrank_entries = lr_e;
-        st.max_rank = maxr;
-        st.mean_rank = wsum > 0 ? wr / wsum : 0.0;
-        st.compression = 1.0 - (double)(dense_e + lr_e) / ((double)st.n_tgt * st.n_src * n_bands);
-        st.bytes = bytes;
-        st.entries_evaluated = evaluated;
-        st.aca_entries = aca_e;
-        st.aca_kernel_ms = aca_ms;
-        st.aca_launches = aca_l;
-        st.aca_entry_ms = aca_entry_ms;
-        st.aca_entry_launches = aca_entry_l;
-        st.fill_kernel_ms = fill_ms;
-        st.fill_launches = fill_l;
-        st.assemble_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        *out = hm.release();
+        *out = assemble_hmat(m, std::move(plan), n_bands, kappa, s).release();
         return RTE_OK;
     });
 }

@@ -1,0 +1,74 @@
+// Source terms and the per-vertex temperature balance shared by the fixed-point
+// solver and the request server (Algorithm of Section "Fixed Point
+// Iterations"; eq. grey for the one-band case).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rte {
+
+constexpr double kSigma = 6.493939402266829;   // pi^4 / 15
+
+// rescaled Planck function B_nu(T) = nu^3 / (exp(nu / T) - 1), B(0) = 0
+__device__ __forceinline__ double planck(double nu, double T) {
+    if (!(T > 0.0)) return 0.0;
+    const double x = nu / T;
+    if (x > 700.0) return 0.0;
+    return nu * nu * nu / expm1(x);
+}
+
+// B and dB/dT
+__device__ __forceinline__ void planck_d(double nu, double T, double &B, double &dB) {
+    B = 0.0;
+    dB = 0.0;
+    if (!(T > 0.0)) return;
+    const double x = nu / T;
+    if (x > 700.0) return;
+    const double e = expm1(x);
+    B = nu * nu * nu / e;
+    dB = B * ((e + 1.0) / e) * (x / T);
+}
+
+// The temperature T >= 0 solving sum_b c_b (J_b - B_{nu_b}(T)) = 0 with
+// c_b >= 0 (c_b = w_b kappa_b (1 - a_b)), started from Told.  band(b, nu, c, J)
+// gives nu_b, c_b and J_b.  f decreases in T and f(0) = sum c_b J_b: a
+// bracketed Newton iteration, a step that leaves the bracket replaced by
+// bisection.
+template <typename Band>
+__device__ double solve_temperature(int nb, double Told, Band band) {
+    double f0 = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        double nu, c, j;
+        band(b, nu, c, j);
+        f0 += c * j;
+    }
+    if (!(f0 > 0.0)) return 0.0;
+    auto f = [&](double t, double &df) {
+        double s = 0.0, d = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            double nu, c, j, B, dB;
+            band(b, nu, c, j);
+            planck_d(nu, t, B, dB);
+            s += c * (j - B);
+            d -= c * dB;
+        }
+        df = d;
+        return s;
+    };
+    double lo = 0.0, hi = Told > 0.0 ? 2.0 * Told : 1.0, d;
+    for (int it = 0; it < 200 && f(hi, d) > 0.0; ++it) { lo = hi; hi *= 2.0; }
+    double x = (Told > lo && Told < hi) ? Told : 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        const double fx = f(x, d);
+        if (fx == 0.0) break;
+        if (fx > 0.0) lo = x; else hi = x;
+        double xn = (d < 0.0) ? x - fx / d : 0.5 * (lo + hi);
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        const double dx = fabs(xn - x);
+        x = xn;
+        if (dx <= 2.3e-16 * x || hi - lo <= 2.3e-16 * hi) break;
+    }
+    return x;
+}
+
+}  // namespace rte

@@ -259,5 +259,10 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
 }  // namespace rte
 
 struct rte_mesh { rte::Mesh m; };
+struct rte_hmat;
+namespace rte {
+std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::unique_ptr<Plan> plan, int n_bands, const double *kappa,
+                                        hipStream_t s);
+}
 struct rte_plan { std::unique_ptr<rte::Plan> p; };
 struct rte_hmat { rte::HMat h; };

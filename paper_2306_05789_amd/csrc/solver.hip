@@ -14,31 +14,11 @@
 #include <cmath>
 
 #include "kernels.h"
+#include "physics.h"
 
 namespace rte {
 
 namespace {
-
-constexpr double kSigma = 6.493939402266829;   // pi^4 / 15
-
-__device__ __forceinline__ double planck(double nu, double T) {
-    if (!(T > 0.0)) return 0.0;
-    const double x = nu / T;
-    if (x > 700.0) return 0.0;
-    return nu * nu * nu / expm1(x);
-}
-
-// B and dB/dT
-__device__ __forceinline__ void planck_d(double nu, double T, double &B, double &dB) {
-    B = 0.0;
-    dB = 0.0;
-    if (!(T > 0.0)) return;
-    const double x = nu / T;
-    if (x > 700.0) return;
-    const double e = expm1(x);
-    B = nu * nu * nu / e;
-    dB = B * ((e + 1.0) / e) * (x / T);
-}
 
 struct BandParams {
     int nb;
@@ -128,39 +108,11 @@ __global__ void k_newton(BandParams bp, const double *__restrict__ J, const doub
         const double j = J[k];
         Tn = j > 0.0 ? sqrt(sqrt(j / kSigma)) : 0.0;
     } else {
-        double f0 = 0.0;
-        for (int b = 0; b < bp.nb; ++b)
-            f0 += bp.w[b] * kap[(int64_t)b * N + i] * (1.0 - bp.a[b]) * J[(int64_t)b * tot + k];
-        if (!(f0 > 0.0)) {
-            Tn = 0.0;
-        } else {
-            auto f = [&](double t, double &df) {
-                double s = 0.0, d = 0.0;
-                for (int b = 0; b < bp.nb; ++b) {
-                    const double c = bp.w[b] * kap[(int64_t)b * N + i] * (1.0 - bp.a[b]);
-                    double B, dB;
-                    planck_d(bp.nu[b], t, B, dB);
-                    s += c * (J[(int64_t)b * tot + k] - B);
-                    d -= c * dB;
-                }
-                df = d;
-                return s;
-            };
-            double lo = 0.0, hi = Told > 0.0 ? 2.0 * Told : 1.0, d;
-            for (int it = 0; it < 200 && f(hi, d) > 0.0; ++it) { lo = hi; hi *= 2.0; }
-            double x = (Told > lo && Told < hi) ? Told : 0.5 * (lo + hi);
-            for (int it = 0; it < 100; ++it) {
-                const double fx = f(x, d);
-                if (fx == 0.0) break;
-                if (fx > 0.0) lo = x; else hi = x;
-                double xn = (d < 0.0) ? x - fx / d : 0.5 * (lo + hi);
-                if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-                const double dx = fabs(xn - x);
-                x = xn;
-                if (dx <= 2.3e-16 * x || hi - lo <= 2.3e-16 * hi) break;
-            }
-            Tn = x;
-        }
+        Tn = solve_temperature(bp.nb, Told, [&](int b, double &nu, double &c, double &j) {
+            nu = bp.nu[b];
+            c = bp.w[b] * kap[(int64_t)b * N + i] * (1.0 - bp.a[b]);
+            j = J[(int64_t)b * tot + k];
+        });
     }
     if (Tn < Told) atomicAdd(viol, 1ull);
     T[k] = Tn;

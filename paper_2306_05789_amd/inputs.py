@@ -100,13 +100,18 @@ def reflective_bands(n=(65, 33, 33), bands=8) -> Workload:
                     T_wall=np.ones((1, L)), tol=1e-6)
 
 
+def catalogue(bands=32, seed=4):
+    """Band catalogue of the batched and served workloads: nu_b log-spaced in
+    [0.25, 16] and the kappa factor c_b of each band, lognormal(0, 1)."""
+    return np.geomspace(0.25, 16.0, bands), np.random.default_rng(seed).lognormal(0.0, 1.0, bands)
+
+
 def batched(n=49, bands=32, nrhs=16, seed_bands=4, seed_rhs=5) -> Workload:
     """Unit cube on n^3, `bands` bands with kappa_b = c_b kappa(x), c_b lognormal(0,1),
     nu_b log-spaced in [0.25, 16], all faces emitting with nrhs random wall
     temperature fields in [0.5, 2]."""
     pos = grid_positions((n, n, n), (0, 0, 0), (1, 1, 1))
-    c = np.random.default_rng(seed_bands).lognormal(0.0, 1.0, bands)
-    nu = np.geomspace(0.25, 16.0, bands)
+    nu, c = catalogue(bands, seed_bands)
     L = n_emitting((n, n, n), ALL_FACES)
     Tw = np.random.default_rng(seed_rhs).uniform(0.5, 2.0, (nrhs, L))
     return Workload(f"cube{n}_{bands}bands_{nrhs}rhs", (n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0),
@@ -119,7 +124,7 @@ class Request:
     arrival: float          # seconds from the stream start
     mesh: int               # index into the resident mesh list
     bands: np.ndarray       # subset of the band catalogue (sorted indices)
-    scale: float            # kappa multiplier before snapping to the resident ladder
+    scale: float            # kappa scale of the request; band b's multiplier is scale * c_b
     T_wall: np.ndarray      # [L] wall temperatures on the mesh's emitting vertices
 
 

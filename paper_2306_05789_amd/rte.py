@@ -72,6 +72,36 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("n_catalogue", C.c_int32), ("nu", C.POINTER(C.c_double)),
+                ("levels_per_decade", C.c_int32), ("leaf_size", C.c_int32), ("eta", C.c_double),
+                ("aca_eps", C.c_double), ("precision", C.c_int32), ("max_active", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("mesh_id", C.c_int32), ("n_bands", C.c_int32), ("bands", C.POINTER(C.c_int32)),
+                ("kappa_mult", C.POINTER(C.c_double)), ("T_wall", C.c_void_p), ("tol", C.c_double),
+                ("max_iter", C.c_int32)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("converged", C.c_int32), ("iterations", C.c_int32),
+                ("outer_steps", C.c_int32), ("residual", C.c_double), ("n_bands", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("budget", C.c_int64), ("resident_bytes", C.c_int64), ("operators", C.c_int64),
+                ("assembled", C.c_int64), ("evicted", C.c_int64), ("over_budget", C.c_int64),
+                ("submitted", C.c_int64), ("completed", C.c_int64), ("steps", C.c_int64), ("columns", C.c_int64),
+                ("assemble_ms", C.c_double), ("sweep_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # name -> (restype, argtypes); the declarations of include/rte.h
 SIGNATURES = {
     "rte_mesh_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(C.c_void_p)]),
@@ -89,6 +119,15 @@ SIGNATURES = {
     "rte_hmat_matvec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_hmat_matvec_batched": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "rte_hmat_stats": (C.c_int, [C.c_void_p, C.POINTER(HmatStats)]),
+    "rte_server_create": (C.c_int, [C.POINTER(ServerDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "rte_server_add_mesh": (C.c_int, [C.c_void_p, C.POINTER(MeshDesc), C.c_void_p, C.POINTER(C.c_int32)]),
+    "rte_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_int64)]),
+    "rte_server_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "rte_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(RequestInfo)]),
+    "rte_server_levels": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32)]),
+    "rte_server_fetch": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
+    "rte_server_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "rte_server_destroy": (None, [C.c_void_p]),
     "rte_hmat_block_factors": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
     "rte_hmat_destroy": (None, [C.c_void_p]),
@@ -156,13 +195,19 @@ class Mesh:
             self.handle = None
 
 
-def rte_mesh_create(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), reflect_axis=-1, reflect_side=0, R=0.0,
-                    emit_faces=1) -> Mesh:
+def mesh_desc(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), reflect_axis=-1, reflect_side=0, R=0.0,
+              emit_faces=1) -> MeshDesc:
     d = MeshDesc()
     d.n[:] = [int(v) for v in n]
     d.lo[:] = [float(v) for v in lo]
     d.hi[:] = [float(v) for v in hi]
     d.reflect_axis, d.reflect_side, d.R, d.emit_faces = int(reflect_axis), int(reflect_side), float(R), int(emit_faces)
+    return d
+
+
+def rte_mesh_create(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), reflect_axis=-1, reflect_side=0, R=0.0,
+                    emit_faces=1) -> Mesh:
+    d = mesh_desc(n, lo, hi, reflect_axis, reflect_side, R, emit_faces)
     h = C.c_void_p()
     _check(load().rte_mesh_create(C.byref(d), C.byref(h)))
     N, L = C.c_int64(), C.c_int64()
@@ -246,6 +291,7 @@ def rte_hmat_matvec(hmat: HMat, band, x, y, stream=None):
 
 RTE_OP_ACCURATE, RTE_OP_LOW = 0, 1
 RTE_LAUNCH_STREAM, RTE_LAUNCH_GRAPH = 0, 1
+RTE_REQ_PENDING, RTE_REQ_ACTIVE, RTE_REQ_DONE = 0, 1, 2
 
 
 def rte_hmat_matvec_batched(hmat: HMat, x, y, op=RTE_OP_ACCURATE, stream=None):
