@@ -151,6 +151,29 @@ typedef enum { RTE_OP_ACCURATE = 0, RTE_OP_LOW = 1 } rte_operator_t;
 rte_status_t rte_hmat_matvec_batched(rte_hmat_t h, int32_t nrhs, const double *x, double *y, int32_t op,
                                      void *stream);
 
+/* Launch shape of the matvec of one H-matrix: wavefronts per phase-B
+ * workgroup (one workgroup per target leaf and band; matrix cores: 2, 4 or 8,
+ * vector ALU: 4 or 8), bytes of V per phase-A task (KiB), and 16-rank tiles
+ * per phase-A task on the matrix cores (1, 2 or 4; the rank bucket a task
+ * covers).  Changing it rebuilds the work lists and regroups partial sums:
+ * results agree to rounding (FP32 accumulation: ~1e-7, FP64: ~1e-15). */
+typedef struct {
+    int32_t phase_b_waves;
+    int32_t phase_a_kib;
+    int32_t phase_a_tiles;
+} rte_matvec_config_t;
+
+rte_status_t rte_hmat_get_config(rte_hmat_t h, rte_matvec_config_t *cfg);
+rte_status_t rte_hmat_set_config(rte_hmat_t h, const rte_matvec_config_t *cfg, void *stream);
+/* Autotuner: times every candidate shape (reps all-band matvecs of nrhs
+ * right-hand sides, operator op, HIP events) on this matrix and keeps the
+ * fastest; best_ms: its time per matvec; trials: candidates timed.
+ * Synchronises `stream`. */
+rte_status_t rte_hmat_autotune(rte_hmat_t h, int32_t nrhs, int32_t op, int32_t reps, void *stream,
+                               rte_matvec_config_t *best, double *best_ms, int32_t *trials);
+/* HIP-event time of one all-band matvec (nrhs right-hand sides, operator op), mean of reps. */
+rte_status_t rte_hmat_time_matvec(rte_hmat_t h, int32_t nrhs, int32_t op, int32_t reps, void *stream, double *ms);
+
 typedef struct {
     int64_t n_tgt, n_src;
     int32_t n_bands, precision;

@@ -78,6 +78,9 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::unique_ptr<Plan> pla
     H.mesh = &m;
     H.n_bands = n_bands;
     const rte_hmat_opts_t *opts = &plan->opts;
+    // default launch shape per path (the autotuner may change it)
+    if (opts->precision == RTE_MIXED_BF16) H.cfg = MatvecConfig{4, 64, 4};
+    else H.cfg = MatvecConfig{8, 48, 4};
     H.precision = opts->precision;
     H.kind = opts->kind;
     H.plan = std::move(plan);
@@ -435,11 +438,61 @@ rte_status_t rte_hmat_matvec_batched(rte_hmat_t h, int32_t nrhs, const double *x
         const int64_t ns = H.stats.n_src, nt = H.stats.n_tgt, nv = (int64_t)nrhs * H.n_bands;
         DevBuf xc(sizeof(double) * ns * nv), yc(sizeof(double) * nt * nv),
             ws(sizeof(double) * (size_t)matvec_ws_all(H, nrhs));
+        poison(ws, s);
         permute_gather(H.src_pos.as<int64_t>(), ns, (int)nv, ns, ns, x, xc.as<double>(), s);
         matvec_launch_all(H, nrhs, xc.as<double>(), yc.as<double>(), nullptr, ws.as<double>(), s,
                           op == RTE_OP_LOW ? kMatvecLow : kMatvecAccurate);
         permute_scatter(H.tgt_nat.as<int64_t>(), nt, (int)nv, nt, nt, yc.as<double>(), y, s);
         HIP_CHECK(hipStreamSynchronize(s));
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_get_config(rte_hmat_t h, rte_matvec_config_t *cfg) {
+    return guard([&] {
+        RTE_REQUIRE(h && cfg, "rte_hmat_get_config: NULL argument");
+        cfg->phase_b_waves = h->h.cfg.waves_b;
+        cfg->phase_a_kib = h->h.cfg.task_kib;
+        cfg->phase_a_tiles = h->h.cfg.tiles;
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_set_config(rte_hmat_t h, const rte_matvec_config_t *cfg, void *stream) {
+    return guard([&] {
+        RTE_REQUIRE(h && cfg, "rte_hmat_set_config: NULL argument");
+        matvec_configure(h->h, MatvecConfig{cfg->phase_b_waves, cfg->phase_a_kib, cfg->phase_a_tiles},
+                         (hipStream_t)stream);
+        HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_autotune(rte_hmat_t h, int32_t nrhs, int32_t op, int32_t reps, void *stream,
+                               rte_matvec_config_t *best, double *best_ms, int32_t *trials) {
+    return guard([&] {
+        RTE_REQUIRE(h, "rte_hmat_autotune: NULL matrix");
+        RTE_REQUIRE(nrhs >= 1 && nrhs <= 4096, "rte_hmat_autotune: nrhs out of range");
+        RTE_REQUIRE(op == RTE_OP_ACCURATE || op == RTE_OP_LOW, "rte_hmat_autotune: unknown operator");
+        RTE_REQUIRE(reps >= 1 && reps <= 1000, "rte_hmat_autotune: reps out of range");
+        int n = 0;
+        double ms = 0;
+        const MatvecConfig c = matvec_autotune(h->h, nrhs, op == RTE_OP_LOW ? kMatvecLow : kMatvecAccurate, reps,
+                                               (hipStream_t)stream, &ms, &n);
+        if (best) *best = rte_matvec_config_t{c.waves_b, c.task_kib, c.tiles};
+        if (best_ms) *best_ms = ms;
+        if (trials) *trials = n;
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_time_matvec(rte_hmat_t h, int32_t nrhs, int32_t op, int32_t reps, void *stream, double *ms) {
+    return guard([&] {
+        RTE_REQUIRE(h && ms, "rte_hmat_time_matvec: NULL argument");
+        RTE_REQUIRE(nrhs >= 1 && nrhs <= 4096, "rte_hmat_time_matvec: nrhs out of range");
+        RTE_REQUIRE(op == RTE_OP_ACCURATE || op == RTE_OP_LOW, "rte_hmat_time_matvec: unknown operator");
+        RTE_REQUIRE(reps >= 1 && reps <= 1000, "rte_hmat_time_matvec: reps out of range");
+        *ms = matvec_time(h->h, nrhs, op == RTE_OP_LOW ? kMatvecLow : kMatvecAccurate, reps, (hipStream_t)stream);
         return RTE_OK;
     });
 }

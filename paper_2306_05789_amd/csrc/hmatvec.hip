@@ -69,6 +69,7 @@ struct MfVt {
     int64_t out;               // direct: offset of t_b in the t splits; else partial-sum offset of the chunk
     int32_t ng, k, band, kt0;  // 8-row groups in the chunk, rank, band, first rank of the task
     int32_t direct;            // 1: the block is one chunk, its t splits are written here
+    int32_t tiles;             // 16-rank tiles of this task (ranks kt0 .. kt0 + 16 tiles)
 };
 
 // BF16 t staging: sum a block's chunk partials, split into hi, mid, lo
@@ -388,6 +389,7 @@ struct MfSrc {
     rsrc_t a, al, x[3];
     int k;      // phase A: rank (row length of V); phase B: slice rows (ld)
     int ngr;    // 8-groups of the K dimension
+    int nt;     // phase A: 16-rank tiles of the task
 };
 
 // Phase A.  Lane (c = lane % 16, q = lane / 16) feeds rank row c of each
@@ -410,6 +412,7 @@ __device__ __forceinline__ MfSrc<MODE> mf_src_a(const MfVt &tk, const uint16_t *
     for (int sp = 0; sp < MfOps<MODE>::NS; ++sp) r.x[sp] = make_rsrc(xb + sp * xsplit, tk.ng * 256);
     r.k = tk.k;
     r.ngr = tk.ng;
+    r.nt = min(tk.tiles, (tk.k - tk.kt0 + 15) / 16);
     return r;
 }
 
@@ -423,7 +426,7 @@ __device__ __forceinline__ void mf_load_a(const MfSrc<MODE> &r, int kt0, int g0,
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int rk = kt0 + 16 * t + c;
-        const int off = valid && rk < r.k ? (g * r.k + rk) * 16 : kOOB;
+        const int off = valid && t < r.nt && rk < r.k ? (g * r.k + rk) * 16 : kOOB;
         o.a[t] = bload(r.a, off);
         if constexpr (MODE == kMatvecAccurate) o.al[t] = bload(r.al, off);
     }
@@ -432,7 +435,7 @@ __device__ __forceinline__ void mf_load_a(const MfSrc<MODE> &r, int kt0, int g0,
 template <int MODE>
 __device__ __forceinline__ void mf_finish_a(const MfVt &tk, int c, int q, const f32x4 acc[4], const double a64[4][4],
                                             double *part, int64_t ldp, uint16_t *ts, int64_t tsplit, int r0, int nr) {
-    const int nt = min(4, (tk.k - tk.kt0 + 15) / 16);
+    const int nt = min(tk.tiles, (tk.k - tk.kt0 + 15) / 16);
     const int k8 = (int)pad8(tk.k);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(256) void k_mf_phase_a(const MfVt *__restrict__ tas
         }
         // past the end: the same loads at out-of-range offsets (zeros)
         mf_load_a<MODE>(rl, tkl.kt0, gn, tn < ntask, c, q, nx);
-        mf_products<MODE>(cu, min(4, (cur.k - cur.kt0 + 15) / 16), acc, a64);
+        mf_products<MODE>(cu, min(cur.tiles, (cur.k - cur.kt0 + 15) / 16), acc, a64);
         g0 += 4;
         if (g0 >= cur.ng) {
             mf_finish_a<MODE>(cur, c, q, acc, a64, part, ldp, ts, tsplit, r0, nr);
@@ -687,9 +690,24 @@ __global__ void k_scatter(const int64_t *__restrict__ perm, int64_t n, int nrhs,
     out[r * ld_out + perm[p]] = in[r * ld_in + p];
 }
 
+// phase B of the vector-ALU path with W wavefronts per workgroup
+template <int ST, int MODE, typename A, int NR>
+void phase_b_valu(int W, unsigned gb, const LeafWork *lw, const Seg *sg, const double *x, int64_t ldx, int64_t xbs,
+                  const double *t, int64_t ldt, const double *y0, double *y, int64_t ldy, int64_t ybs, int r0, int nr,
+                  hipStream_t s) {
+    if (W == 2)
+        k_phase_b<ST, MODE, A, NR, 2><<<gb, 128, 0, s>>>(lw, sg, x, ldx, xbs, t, ldt, y0, y, ldy, ybs, r0, nr);
+    else if (W == 4)
+        k_phase_b<ST, MODE, A, NR, 4><<<gb, 256, 0, s>>>(lw, sg, x, ldx, xbs, t, ldt, y0, y, ldy, ybs, r0, nr);
+    else
+        k_phase_b<ST, MODE, A, NR, 8><<<gb, 512, 0, s>>>(lw, sg, x, ldx, xbs, t, ldt, y0, y, ldy, ybs, r0, nr);
+}
+
+// wb: wavefronts per phase B workgroup for up to 4 right-hand sides (half of
+// it for 16, whose accumulators are four times larger)
 template <int ST, int MODE, typename A>
 void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double *y0, double *y, double *tb,
-                  hipStream_t s) {
+                  hipStream_t s, int wb) {
     double *part = tb + mp.ktot * (int64_t)nrhs;   // the workspace holds t, then the partials
     const int64_t ldp = std::max<int64_t>(mp.npart, 1);
     const int64_t xbs = (int64_t)nrhs * mp.n_src, ybs = (int64_t)nrhs * mp.n_tgt;
@@ -715,14 +733,12 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
         const LeafWork *lw = mp.leaf.as<LeafWork>();
         const Seg *sg = mp.seg.as<Seg>();
         if (nr == 1)
-            k_phase_b<ST, MODE, A, 1, 8><<<gb, 512, 0, s>>>(lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt,
-                                                          ybs, r0, nr);
+            phase_b_valu<ST, MODE, A, 1>(wb, gb, lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt, ybs, r0, nr, s);
         else if (nr <= 4)
-            k_phase_b<ST, MODE, A, 4, 8><<<gb, 512, 0, s>>>(lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt,
-                                                          ybs, r0, nr);
+            phase_b_valu<ST, MODE, A, 4>(wb, gb, lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt, ybs, r0, nr, s);
         else
-            k_phase_b<ST, MODE, A, 16, 4><<<gb, 256, 0, s>>>(lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt,
-                                                           ybs, r0, nr);
+            phase_b_valu<ST, MODE, A, 16>(std::max(2, wb / 2), gb, lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y,
+                                          mp.n_tgt, ybs, r0, nr, s);
         HIP_LAUNCH_CHECK();
     }
 }
@@ -743,7 +759,7 @@ int64_t resident_workgroups(K kernel, int block) {
 // [3][nb][np / 8][16][8] and t [3][ktot / 8][16][8] BF16.
 template <int MODE>
 void launch_mf(const MatvecPlan &mp, int nrhs, const double *x, const double *y0, double *y, double *tb,
-               hipStream_t s) {
+               hipStream_t s, int wb) {
     const int64_t ldp = std::max<int64_t>(mp.npart, 1);
     double *part = tb;
     uint16_t *xs = reinterpret_cast<uint16_t *>(tb + ((ldp * nrhs + 1) & ~(int64_t)1));   // 16-byte aligned
@@ -768,8 +784,15 @@ void launch_mf(const MatvecPlan &mp, int nrhs, const double *x, const double *y0
                 HIP_LAUNCH_CHECK();
             }
         }
-        k_mf_phase_b<MODE, 4><<<(unsigned)mp.n_leaf, 256, 0, s>>>(mp.leaf.as<LeafWork>(), mp.seg.as<Seg>(), xs, xsplit,
-                                                                mp.np, ts, tsplit, y0, y, mp.n_tgt, ybs, r0, nr);
+        const unsigned gb = (unsigned)mp.n_leaf;
+        const LeafWork *lw = mp.leaf.as<LeafWork>();
+        const Seg *sg = mp.seg.as<Seg>();
+        if (wb == 2)
+            k_mf_phase_b<MODE, 2><<<gb, 128, 0, s>>>(lw, sg, xs, xsplit, mp.np, ts, tsplit, y0, y, mp.n_tgt, ybs, r0, nr);
+        else if (wb == 8)
+            k_mf_phase_b<MODE, 8><<<gb, 512, 0, s>>>(lw, sg, xs, xsplit, mp.np, ts, tsplit, y0, y, mp.n_tgt, ybs, r0, nr);
+        else
+            k_mf_phase_b<MODE, 4><<<gb, 256, 0, s>>>(lw, sg, xs, xsplit, mp.np, ts, tsplit, y0, y, mp.n_tgt, ybs, r0, nr);
         HIP_LAUNCH_CHECK();
     }
 }
@@ -800,7 +823,8 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     std::vector<VtReduce> red;
     int64_t ktot = 0, npart = 0, maxk = 0;
     // about this many bytes of V per wavefront task
-    const int64_t chunk_bytes = 48 * 1024, mf_task_bytes = 64 * 1024;
+    const int64_t chunk_bytes = (int64_t)H.cfg.task_kib * 1024, mf_task_bytes = chunk_bytes;
+    const int tiles = H.cfg.tiles;
     const int64_t esz = H.precision == RTE_FP64 ? 8 : H.precision == RTE_FP32 ? 4 : 2;
     const auto &leaves = P.tgt_leaves;
     std::vector<int64_t> starts;
@@ -823,20 +847,21 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
             const int32_t k = B.rank[b];
             const int64_t wp = H.pwidth(bl.s0, bl.s1);
             toff[b] = ktot;
-            // about mf_task_bytes of V per task (a task takes up to 64 ranks)
-            const int64_t rows = std::min<int64_t>(8192, std::max<int64_t>(256, mf_task_bytes / (2 * std::min(64, k)))) / 32 * 32;
+            // about mf_task_bytes of V per task (a task takes up to 16 tiles ranks)
+            const int64_t rows =
+                std::min<int64_t>(8192, std::max<int64_t>(256, mf_task_bytes / (2 * std::min(16 * tiles, k)))) / 32 * 32;
             const int64_t chunks = (wp + rows - 1) / rows;
             const uint16_t *V = static_cast<const uint16_t *>(B.V[b]), *Vl = static_cast<const uint16_t *>(B.Vlo[b]);
             if (chunks == 1) {
-                for (int32_t kt0 = 0; kt0 < k; kt0 += 64)
-                    mvt.push_back({V, Vl, H.src_p_h[bl.s0], ktot, (int32_t)(wp / 8), k, bi, kt0, 1});
+                for (int32_t kt0 = 0; kt0 < k; kt0 += 16 * tiles)
+                    mvt.push_back({V, Vl, H.src_p_h[bl.s0], ktot, (int32_t)(wp / 8), k, bi, kt0, 1, tiles});
             } else {
                 mred.push_back({npart, ktot, (int32_t)chunks, k});
                 for (int64_t c = 0; c < chunks; ++c) {
                     const int64_t nj = std::min(rows, wp - c * rows);
-                    for (int32_t kt0 = 0; kt0 < k; kt0 += 64)
+                    for (int32_t kt0 = 0; kt0 < k; kt0 += 16 * tiles)
                         mvt.push_back({V + c * rows * k, Vl + c * rows * k, H.src_p_h[bl.s0] + c * rows,
-                                       npart + c * k, (int32_t)(nj / 8), k, bi, kt0, 0});
+                                       npart + c * k, (int32_t)(nj / 8), k, bi, kt0, 0, tiles});
                 }
                 npart += chunks * k;
             }
@@ -906,7 +931,7 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
         return (int64_t)a.nj * a.k > (int64_t)b.nj * b.k;
     });
     std::stable_sort(mvt.begin(), mvt.end(), [](const MfVt &a, const MfVt &b) {
-        return (int64_t)a.ng * std::min(64, a.k - a.kt0) > (int64_t)b.ng * std::min(64, b.k - b.kt0);
+        return (int64_t)a.ng * std::min(16 * a.tiles, a.k - a.kt0) > (int64_t)b.ng * std::min(16 * b.tiles, b.k - b.kt0);
     });
     mp->ktot = std::max<int64_t>(ktot, mf ? 8 : 1);
     mp->npart = npart;
@@ -935,10 +960,11 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
 
 void launch_plan(const HMat &H, const MatvecPlan &mp, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                  double *tbuf, hipStream_t s, int mode) {
-    if (H.precision == RTE_FP64) launch_typed<ST_F64, 0, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
-    else if (H.precision == RTE_FP32) launch_typed<ST_F32, 0, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
-    else if (mode == kMatvecAccurate) launch_mf<kMatvecAccurate>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
-    else launch_mf<kMatvecLow>(mp, nrhs, x_c, y0_c, y_c, tbuf, s);
+    const int wb = H.cfg.waves_b;
+    if (H.precision == RTE_FP64) launch_typed<ST_F64, 0, double>(mp, nrhs, x_c, y0_c, y_c, tbuf, s, wb);
+    else if (H.precision == RTE_FP32) launch_typed<ST_F32, 0, float>(mp, nrhs, x_c, y0_c, y_c, tbuf, s, wb);
+    else if (mode == kMatvecAccurate) launch_mf<kMatvecAccurate>(mp, nrhs, x_c, y0_c, y_c, tbuf, s, wb);
+    else launch_mf<kMatvecLow>(mp, nrhs, x_c, y0_c, y_c, tbuf, s, wb);
 }
 
 }  // namespace
@@ -962,6 +988,63 @@ void matvec_launch_all(const HMat &H, int nrhs, const double *x_c, double *y_c, 
     launch_plan(H, H.mv_all ? *H.mv_all : *H.mv[0], nrhs, x_c, y_c, y0_c, tbuf, s, mode);
 }
 
+void matvec_configure(HMat &H, const MatvecConfig &cfg, hipStream_t s) {
+    const bool mf = H.precision == RTE_MIXED_BF16;
+    RTE_REQUIRE(cfg.waves_b == 2 || cfg.waves_b == 4 || cfg.waves_b == 8, "matvec config: waves must be 2, 4 or 8");
+    RTE_REQUIRE(mf || cfg.waves_b >= 4, "matvec config: the vector-ALU path takes 4 or 8 waves");
+    RTE_REQUIRE(cfg.task_kib >= 4 && cfg.task_kib <= 4096, "matvec config: task size out of range");
+    RTE_REQUIRE(cfg.tiles == 1 || cfg.tiles == 2 || cfg.tiles == 4, "matvec config: tiles must be 1, 2 or 4");
+    H.cfg = cfg;
+    for (int b = 0; b < H.n_bands; ++b) matvec_build(H, b, s);
+    matvec_build_all(H, s);
+}
+
+namespace {
+__global__ void k_fill(double *p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+}  // namespace
+
+double matvec_time(const HMat &H, int nrhs, int mode, int reps, hipStream_t s) {
+    const int64_t nx = (int64_t)H.n_bands * nrhs * H.stats.n_src, ny = (int64_t)H.n_bands * nrhs * H.stats.n_tgt;
+    DevBuf x(sizeof(double) * nx), y(sizeof(double) * ny), ws(sizeof(double) * (size_t)matvec_ws_all(H, nrhs));
+    poison(ws, s);
+    k_fill<<<(unsigned)((nx + 255) / 256), 256, 0, s>>>(x.as<double>(), nx, 1.0);
+    HIP_LAUNCH_CHECK();
+    matvec_launch_all(H, nrhs, x.as<double>(), y.as<double>(), nullptr, ws.as<double>(), s, mode);   // warm-up
+    EventTimer tm(s);
+    tm.start();
+    for (int r = 0; r < reps; ++r)
+        matvec_launch_all(H, nrhs, x.as<double>(), y.as<double>(), nullptr, ws.as<double>(), s, mode);
+    tm.stop();
+    const double ms = tm.ms() / std::max(reps, 1);
+    HIP_CHECK(hipStreamSynchronize(s));
+    return ms;
+}
+
+MatvecConfig matvec_autotune(HMat &H, int nrhs, int mode, int reps, hipStream_t s, double *best_ms, int *trials) {
+    const bool mf = H.precision == RTE_MIXED_BF16;
+    const std::vector<int> waves = mf ? std::vector<int>{2, 4, 8} : std::vector<int>{4, 8};
+    const std::vector<int> kib = {16, 64, 256};
+    const std::vector<int> tiles = mf ? std::vector<int>{2, 4} : std::vector<int>{4};
+    MatvecConfig best = H.cfg;
+    double bt = INFINITY;
+    int n = 0;
+    for (int w : waves)
+        for (int k : kib)
+            for (int t : tiles) {
+                matvec_configure(H, MatvecConfig{w, k, t}, s);
+                const double ms = matvec_time(H, nrhs, mode, reps, s);
+                ++n;
+                if (ms < bt) { bt = ms; best = H.cfg; }
+            }
+    matvec_configure(H, best, s);
+    if (best_ms) *best_ms = bt;
+    if (trials) *trials = n;
+    return best;
+}
+
 // workspace doubles per right-hand side: t, then the partial sums of chunked blocks
 int64_t matvec_ws(const HMat &H, int band, int nrhs) { return ws_words(*H.mv[band], nrhs); }
 
@@ -973,6 +1056,7 @@ void matvec_launch_ws(const HMat &H, int band, int nrhs, const double *x_c, doub
 void matvec_launch(const HMat &H, int band, int nrhs, const double *x_c, double *y_c, const double *y0_c,
                    hipStream_t s, int mode) {
     DevBuf tb(sizeof(double) * (size_t)matvec_ws(H, band, nrhs));
+    poison(tb, s);
     matvec_launch_ws(H, band, nrhs, x_c, y_c, y0_c, tb.as<double>(), s, mode);
     HIP_CHECK(hipStreamSynchronize(s));
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -158,6 +159,15 @@ struct DevBuf {
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Checking aid: with RTE_POISON_WORKSPACE set in the environment, scratch
+// buffers are filled with 0xFF bytes (NaN in every floating format) when they
+// are allocated, so a read of something never written shows up as NaN instead
+// of hiding behind freshly zeroed memory.  Called outside graph capture.
+inline void poison(DevBuf &b, hipStream_t s) {
+    static const bool on = std::getenv("RTE_POISON_WORKSPACE") != nullptr;
+    if (on && b.bytes) HIP_CHECK(hipMemsetAsync(b.p, 0xFF, b.bytes, s));
+}
+
 template <typename T>
 DevBuf upload(const std::vector<T> &v, hipStream_t s) {
     DevBuf b(v.size() * sizeof(T));
@@ -201,6 +211,13 @@ struct BandStore {
 
 struct MatvecPlan;   // device work lists (hmatvec.hip)
 
+// Launch shape of the matvec (chosen by the autotuner, or set).
+struct MatvecConfig {
+    int waves_b = 4;      // phase B wavefronts per workgroup (matrix cores: 2, 4, 8; vector ALU: 4, 8)
+    int task_kib = 64;    // phase A: bytes of V per task, KiB
+    int tiles = 4;        // matrix cores: 16-rank tiles per phase A task (1, 2, 4)
+};
+
 struct HMat {
     const Mesh *mesh = nullptr;     // not owned: the mesh must outlive the matrix
     std::unique_ptr<Plan> plan;
@@ -219,6 +236,7 @@ struct HMat {
     int64_t n_src_p = 0;
     // stored width of the source range [s0, s1) (a union of source leaves)
     int64_t pwidth(int64_t s0, int64_t s1) const { return src_p_h[s1] - src_p_h[s0]; }
+    MatvecConfig cfg;
     std::vector<std::unique_ptr<MatvecPlan>> mv;   // per band
     std::unique_ptr<MatvecPlan> mv_all;            // all bands in one launch (multi-band matrices)
     rte_hmat_stats_t stats{};
@@ -249,6 +267,12 @@ void matvec_build_all(HMat &H, hipStream_t s);
 int64_t matvec_ws_all(const HMat &H, int nrhs);
 void matvec_launch_all(const HMat &H, int nrhs, const double *x_c, double *y_c, const double *y0_c, double *tbuf,
                        hipStream_t s, int mode = kMatvecAccurate);
+// Rebuild the work lists of every band and of the all-band launch for `cfg`.
+void matvec_configure(HMat &H, const MatvecConfig &cfg, hipStream_t s);
+// HIP-event time (ms) of one all-band matvec with nrhs right-hand sides, mean of reps.
+double matvec_time(const HMat &H, int nrhs, int mode, int reps, hipStream_t s);
+// Time every candidate launch shape on H itself, keep the fastest.
+MatvecConfig matvec_autotune(HMat &H, int nrhs, int mode, int reps, hipStream_t s, double *best_ms, int *trials);
 void permute_gather(const int64_t *perm, int64_t n, int nrhs, int64_t ld_in, int64_t ld_out, const double *in,
                     double *out, hipStream_t s);
 void permute_scatter(const int64_t *perm, int64_t n, int nrhs, int64_t ld_in, int64_t ld_out, const double *in,

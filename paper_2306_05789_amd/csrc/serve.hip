@@ -143,8 +143,11 @@ __global__ void k_scale(const double *__restrict__ in, double a, int64_t n, doub
 }
 
 template <typename T>
-void grow(DevBuf &b, int64_t count) {
-    if ((int64_t)b.bytes < count * (int64_t)sizeof(T)) b.alloc(sizeof(T) * (size_t)count);
+void grow(DevBuf &b, int64_t count, hipStream_t s) {
+    if ((int64_t)b.bytes < count * (int64_t)sizeof(T)) {
+        b.alloc(sizeof(T) * (size_t)count);
+        poison(b, s);
+    }
 }
 
 // Pinned staging for the small per-step tables.
@@ -328,38 +331,52 @@ struct Server {
     bool admit_head() {
         SrvReq &r = *pending.front();
         SrvMesh &M = *meshes[r.mesh];
+        std::vector<int> levels = r.levels;
+        std::sort(levels.begin(), levels.end());
+        levels.erase(std::unique(levels.begin(), levels.end()), levels.end());
+        // the request's resident operators are pinned (one user each) before
+        // anything is evicted, so the eviction cannot take them
+        std::vector<SrvOp *> pinned;
         std::vector<int> missing;
-        for (int l : r.levels)
-            if (!find_op(r.mesh, l) && std::find(missing.begin(), missing.end(), l) == missing.end())
+        for (int l : levels) {
+            if (SrvOp *o = find_op(r.mesh, l)) {
+                o->users += 1;
+                pinned.push_back(o);
+            } else {
                 missing.push_back(l);
+            }
+        }
         const int64_t need = state_bytes(r) + (int64_t)missing.size() * M.est_bytes;
         while (resident + need > desc.hbm_budget && evictable()) evict_one();
         if (resident + need > desc.hbm_budget) {
-            if (!active.empty()) return false;   // wait for running requests to retire
-            stats.over_budget += 1;              // alone it must run: admitted beyond the budget
+            if (!active.empty()) {   // wait for running requests to retire
+                for (SrvOp *o : pinned) o->users -= 1;
+                return false;
+            }
+            stats.over_budget += 1;   // alone it must run: admitted beyond the budget
         }
-        for (int l : missing) assemble(r.mesh, l);
+        for (int l : missing) assemble(r.mesh, l)->users += 1;
         const int nb = (int)r.bands.size();
         const int64_t N = M.mesh.N, L = M.mesh.L;
         r.ops.clear();
-        for (int b = 0; b < nb; ++b) r.ops.push_back(find_op(r.mesh, r.levels[b]));
-        std::vector<SrvOp *> distinct = r.ops;
-        std::sort(distinct.begin(), distinct.end());
-        distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
-        for (SrvOp *o : distinct) o->users += 1;
+        for (int b = 0; b < nb; ++b) {
+            SrvOp *o = find_op(r.mesh, r.levels[b]);
+            RTE_REQUIRE(o, "server: operator of an admitted request is missing");
+            r.ops.push_back(o);
+        }
         r.state_bytes = state_bytes(r);
         r.st.alloc((size_t)r.state_bytes);
         HIP_CHECK(hipMemsetAsync(r.st.p, 0, r.st.bytes, s));   // T = 0, J = 0
         resident += r.state_bytes;
         // S^E_b = S_hat Q_b, Q_b = B_nu(T_wall), wall values in surface cluster order
-        grow<double>(q, 2 * L);
+        grow<double>(q, 2 * L, s);
         permute_gather(M.src_pos.as<int64_t>(), L, 1, L, L, r.Tw.as<double>(), q.as<double>() + L, s);
         for (int b = 0; b < nb; ++b) {
             k_srv_emission<<<(unsigned)((L + 255) / 256), 256, 0, s>>>(nu[r.bands[b]], q.as<double>() + L, L,
                                                                        q.as<double>());
             HIP_LAUNCH_CHECK();
             const HMat &S = r.ops[b]->S->h;
-            grow<double>(ws, matvec_ws_all(S, 1));
+            grow<double>(ws, matvec_ws_all(S, 1), s);
             matvec_launch_all(S, 1, q.as<double>(), r.SE(N, b), nullptr, ws.as<double>(), s, kMatvecAccurate);
         }
         r.state = RTE_REQ_ACTIVE;
@@ -431,19 +448,19 @@ struct Server {
         }
         hcols.reserve(sizeof(SrvCol) * ncol);
         std::memcpy(hcols.p, all.data(), sizeof(SrvCol) * ncol);
-        grow<SrvCol>(cols, ncol);
+        grow<SrvCol>(cols, ncol, s);
         HIP_CHECK(hipMemcpyAsync(cols.p, hcols.p, sizeof(SrvCol) * ncol, hipMemcpyHostToDevice, s));
-        grow<double>(part, (int64_t)ncol * kSrvResidBlocks * 2);
-        grow<double>(res, 2 * (int64_t)ncol);
+        grow<double>(part, (int64_t)ncol * kSrvResidBlocks * 2, s);
+        grow<double>(res, 2 * (int64_t)ncol, s);
         const auto t0 = std::chrono::steady_clock::now();
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const Group &g = groups[gi];
             const HMat &G = g.op->G->h;
             const int64_t N = meshes[g.op->mesh]->mesh.N;
             const int nc = (int)g.cols.size();
-            grow<double>(x, (int64_t)nc * N);
-            grow<double>(y, (int64_t)nc * N);
-            grow<double>(ws, matvec_ws_all(G, nc));
+            grow<double>(x, (int64_t)nc * N, s);
+            grow<double>(y, (int64_t)nc * N, s);
+            grow<double>(ws, matvec_ws_all(G, nc), s);
             const SrvCol *dc = cols.as<SrvCol>() + goff[gi];
             k_srv_x<<<dim3((unsigned)((N + 255) / 256), (unsigned)nc), 256, 0, s>>>(dc, N, x.as<double>());
             HIP_LAUNCH_CHECK();
@@ -472,8 +489,8 @@ struct Server {
         hband.reserve(sizeof(SrvBand) * bt.size());
         std::memcpy(hnewt.p, nt.data(), sizeof(SrvNewt) * nt.size());
         std::memcpy(hband.p, bt.data(), sizeof(SrvBand) * bt.size());
-        grow<SrvNewt>(newt, (int64_t)nt.size());
-        grow<SrvBand>(bandt, (int64_t)bt.size());
+        grow<SrvNewt>(newt, (int64_t)nt.size(), s);
+        grow<SrvBand>(bandt, (int64_t)bt.size(), s);
         HIP_CHECK(hipMemcpyAsync(newt.p, hnewt.p, sizeof(SrvNewt) * nt.size(), hipMemcpyHostToDevice, s));
         HIP_CHECK(hipMemcpyAsync(bandt.p, hband.p, sizeof(SrvBand) * bt.size(), hipMemcpyHostToDevice, s));
         k_srv_newton<<<dim3((unsigned)((maxN + 255) / 256), (unsigned)nt.size()), 256, 0, s>>>(newt.as<SrvNewt>(),

@@ -247,6 +247,7 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
         res(sizeof(double) * 2 * nb * nr), viol(sizeof(unsigned long long));
     const int64_t kt = std::max<int64_t>({1, matvec_ws_all(G, nr), matvec_ws_all(S, nr)});
     DevBuf tbuf(sizeof(double) * kt);
+    poison(tbuf, s);
     const unsigned gN = (unsigned)((vecN + 255) / 256), gL = (unsigned)((L * nr + 255) / 256);
 
     // boundary source: Q_b = B_b(T_wall) and S^E_b = S_hat_b Q_b

@@ -72,6 +72,13 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class MatvecConfig(C.Structure):
+    _fields_ = [("phase_b_waves", C.c_int32), ("phase_a_kib", C.c_int32), ("phase_a_tiles", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ServerDesc(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("n_catalogue", C.c_int32), ("nu", C.POINTER(C.c_double)),
                 ("levels_per_decade", C.c_int32), ("leaf_size", C.c_int32), ("eta", C.c_double),
@@ -119,6 +126,12 @@ SIGNATURES = {
     "rte_hmat_matvec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_hmat_matvec_batched": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "rte_hmat_stats": (C.c_int, [C.c_void_p, C.POINTER(HmatStats)]),
+    "rte_hmat_get_config": (C.c_int, [C.c_void_p, C.POINTER(MatvecConfig)]),
+    "rte_hmat_set_config": (C.c_int, [C.c_void_p, C.POINTER(MatvecConfig), C.c_void_p]),
+    "rte_hmat_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(MatvecConfig),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "rte_hmat_time_matvec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                       C.POINTER(C.c_double)]),
     "rte_server_create": (C.c_int, [C.POINTER(ServerDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
     "rte_server_add_mesh": (C.c_int, [C.c_void_p, C.POINTER(MeshDesc), C.c_void_p, C.POINTER(C.c_int32)]),
     "rte_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_int64)]),
@@ -299,6 +312,30 @@ def rte_hmat_matvec_batched(hmat: HMat, x, y, op=RTE_OP_ACCURATE, stream=None):
     nrhs = int(x.shape[1])
     _check(load().rte_hmat_matvec_batched(hmat.handle, nrhs, _ptr(x), _ptr(y), int(op), _stream(stream)))
     return y
+
+
+def rte_hmat_get_config(hmat: HMat) -> dict:
+    c = MatvecConfig()
+    _check(load().rte_hmat_get_config(hmat.handle, C.byref(c)))
+    return c.as_dict()
+
+
+def rte_hmat_set_config(hmat: HMat, cfg: dict, stream=None):
+    c = MatvecConfig(int(cfg["phase_b_waves"]), int(cfg["phase_a_kib"]), int(cfg["phase_a_tiles"]))
+    _check(load().rte_hmat_set_config(hmat.handle, C.byref(c), _stream(stream)))
+
+
+def rte_hmat_autotune(hmat: HMat, nrhs=1, op=RTE_OP_ACCURATE, reps=3, stream=None) -> dict:
+    c, ms, n = MatvecConfig(), C.c_double(), C.c_int32()
+    _check(load().rte_hmat_autotune(hmat.handle, int(nrhs), int(op), int(reps), _stream(stream), C.byref(c),
+                                    C.byref(ms), C.byref(n)))
+    return {"config": c.as_dict(), "ms": ms.value, "trials": n.value}
+
+
+def rte_hmat_time_matvec(hmat: HMat, nrhs=1, op=RTE_OP_ACCURATE, reps=3, stream=None) -> float:
+    ms = C.c_double()
+    _check(load().rte_hmat_time_matvec(hmat.handle, int(nrhs), int(op), int(reps), _stream(stream), C.byref(ms)))
+    return ms.value
 
 
 def rte_hmat_stats(hmat: HMat) -> dict:

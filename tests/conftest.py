@@ -3,6 +3,10 @@ import sys
 
 import pytest
 
+# every workspace the library allocates starts as NaN bytes in the tests, so a
+# kernel that reads scratch it never wrote fails instead of reading zeros
+os.environ.setdefault("RTE_POISON_WORKSPACE", "1")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

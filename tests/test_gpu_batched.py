@@ -134,3 +134,40 @@ def test_mixed_batched_solve_matches_oracle(small):
         SEs = np.array([Ss[b] @ osolve.planck(wl.nu[b], wl.T_wall[r]) for b in range(len(wl.nu))])
         ref = osolve.fixed_point(Gs, SEs, grey=False, nu=wl.nu, kappa_v=wl.kappa, tol=1e-13)
         assert np.max(np.abs(Tn[r] - ref.T) / ref.T) < 3e-4, r
+
+
+@pytest.mark.parametrize("precision", [rte.RTE_FP64, rte.RTE_MIXED_BF16])
+def test_autotuner_picks_a_shape_and_results_hold(small, precision, tmp_path):
+    """The autotuner times its candidate launch shapes on the matrix, keeps the
+    fastest and caches it; every shape computes the same product to rounding."""
+    from paper_2306_05789_amd import tune
+    wl, mesh = small
+    G = _assemble(mesh, wl, rte.RTE_VOLUME, precision)
+    nb = wl.kappa.shape[0]
+    x = torch.tensor(np.random.default_rng(12).uniform(0.5, 2.0, (nb, 16, mesh.N)), device=DEV)
+    y0, y1 = torch.empty_like(x), torch.empty_like(x)
+    rte.rte_hmat_matvec_batched(G, x, y0, rte.RTE_OP_ACCURATE)
+    cache = str(tmp_path / "tune.json")
+    r = tune.autotune(G, nrhs=16, cache=cache, reps=2)
+    assert r["source"] == "timed" and r["trials"] >= 6 and r["ms"] > 0
+    assert rte.rte_hmat_get_config(G) == r["config"]
+    rte.rte_hmat_matvec_batched(G, x, y1, rte.RTE_OP_ACCURATE)
+    rel = (torch.max(torch.abs(y1 - y0) / torch.abs(y0))).item()
+    assert rel < 1e-12, rel
+    for cfg in ({"phase_b_waves": 4, "phase_a_kib": 16, "phase_a_tiles": 4},
+                {"phase_b_waves": 8, "phase_a_kib": 256, "phase_a_tiles": 2 if precision == rte.RTE_MIXED_BF16 else 4}):
+        rte.rte_hmat_set_config(G, cfg)
+        rte.rte_hmat_matvec_batched(G, x, y1, rte.RTE_OP_ACCURATE)
+        assert (torch.max(torch.abs(y1 - y0) / torch.abs(y0))).item() < 1e-12
+        if precision == rte.RTE_MIXED_BF16:
+            ya, yb = torch.empty_like(x), torch.empty_like(x)
+            rte.rte_hmat_matvec_batched(G, x, yb, rte.RTE_OP_LOW)
+            rte.rte_hmat_set_config(G, r["config"])
+            rte.rte_hmat_matvec_batched(G, x, ya, rte.RTE_OP_LOW)
+            assert (torch.max(torch.abs(ya - yb) / torch.abs(ya))).item() < 1e-5
+    # a second run of the same shape takes the cached choice without timing
+    G2 = _assemble(mesh, wl, rte.RTE_VOLUME, precision)
+    r2 = tune.autotune(G2, nrhs=16, cache=cache, reps=2)
+    assert r2["source"] == "cache" and rte.rte_hmat_get_config(G2) == r["config"]
+    with pytest.raises(rte.RteError):
+        rte.rte_hmat_set_config(G, {"phase_b_waves": 3, "phase_a_kib": 64, "phase_a_tiles": 4})
