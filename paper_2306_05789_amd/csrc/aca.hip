@@ -38,6 +38,7 @@ struct AcaState {
     const AcaTask *task;
     int nb;
     int *k, *istar, *jstar, *status, *havepiv;
+    int64_t *ents;              // per block: entries evaluated (rows and columns)
     T *pivot, *normS2;
     unsigned *used;             // row bitmaps
     const int64_t *ubase;       // first bitmap word of each block
@@ -114,13 +115,17 @@ __global__ __launch_bounds__(256) void k_aca_init(AcaState<T> st) {
         st.havepiv[b] = 0;
         st.normS2[b] = (T)0;
         st.pivot[b] = (T)0;
+        st.ents[b] = 0;
     }
     const int words = (st.task[b].m + 31) / 32;
     for (int w = threadIdx.x; w < words; w += blockDim.x) st.used[st.ubase[b] + w] = 0u;
 }
 
-// Prefix sums of the widths of the blocks taking part in a phase, and the
-// list of those blocks.  One workgroup of 1024 lanes.
+// Prefix sums of the widths (row phase: n, column phase: m and the update
+// chunks) of the active blocks, and the list of those blocks.  The lists are
+// rebuilt every few rank steps; in between, the kernels skip blocks that have
+// stopped (or, in the column phase, have no pivot this step).  One workgroup
+// of 1024 lanes.
 template <typename T, bool COLS>
 __global__ __launch_bounds__(1024) void k_aca_scan(AcaState<T> st) {
     __shared__ int64_t sw[1024], sq[1024];
@@ -131,7 +136,7 @@ __global__ __launch_bounds__(1024) void k_aca_scan(AcaState<T> st) {
     int64_t w = 0, q = 0;
     int c = 0;
     for (int b = b0; b < b1; ++b) {
-        const bool on = COLS ? (st.status[b] == kActive && st.havepiv[b]) : (st.status[b] == kActive);
+        const bool on = st.status[b] == kActive;
         if (on) {
             w += COLS ? st.task[b].m : st.task[b].n;
             q += (st.task[b].m + st.task[b].n + kChunk - 1) / kChunk;
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(1024) void k_aca_scan(AcaState<T> st) {
     for (int b = b0; b < b1; ++b) {
         offs[b] = off;
         if (COLS) st.chunkoff[b] = qoff;
-        const bool on = COLS ? (st.status[b] == kActive && st.havepiv[b]) : (st.status[b] == kActive);
+        const bool on = st.status[b] == kActive;
         if (on) {
             off += COLS ? st.task[b].m : st.task[b].n;
             qoff += (st.task[b].m + st.task[b].n + kChunk - 1) / kChunk;
@@ -185,6 +190,7 @@ __global__ __launch_bounds__(256) void k_aca_rows(EntryCtx<T> c, AcaState<T> st,
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= total) return;
     const int b = find_block(st.rowoff, st.nb, e);
+    if (st.status[b] != kActive) return;
     const AcaTask tk = st.task[b];
     const int j = (int)(e - st.rowoff[b]);
     const int k = st.k[b], is = st.istar[b];
@@ -201,9 +207,11 @@ __global__ __launch_bounds__(256) void k_aca_pivot(AcaState<T> st) {
     __shared__ T sa[4], ss[4];
     __shared__ int si[4];
     const int b = st.act[blockIdx.x];
+    if (st.status[b] != kActive) return;
     const AcaTask tk = st.task[b];
     const int k = st.k[b];
     const T *V = st.Vs + tk.voff + (int64_t)k * tk.n;
+    if (threadIdx.x == 0) st.ents[b] += tk.n;
     unsigned *bits = st.used + st.ubase[b];
     T best = (T)-1, sv = (T)0;
     int bj = INT_MAX;
@@ -246,6 +254,7 @@ __global__ __launch_bounds__(256) void k_aca_cols(EntryCtx<T> c, AcaState<T> st,
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= total) return;
     const int b = find_block(st.coloff, st.nb, e);
+    if (st.status[b] != kActive || !st.havepiv[b]) return;
     const AcaTask tk = st.task[b];
     const int i = (int)(e - st.coloff[b]);
     const int k = st.k[b], js = st.jstar[b];
@@ -268,6 +277,7 @@ __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
     __shared__ int si[4];
     const int64_t c = blockIdx.x;
     const int b = find_block(st.chunkoff, st.nb, c);
+    if (st.status[b] != kActive || !st.havepiv[b]) return;   // uniform over the workgroup
     const AcaTask tk = st.task[b];
     const int k = st.k[b], m = tk.m, n = tk.n;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -315,8 +325,10 @@ __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
 template <typename T>
 __global__ __launch_bounds__(64) void k_aca_finish(AcaState<T> st, T eps) {
     const int b = st.act2[blockIdx.x];
+    if (st.status[b] != kActive || !st.havepiv[b]) return;
     const AcaTask tk = st.task[b];
     const int k = st.k[b], lane = threadIdx.x;
+    if (lane == 0) st.ents[b] += tk.m;
     const int64_t c0 = st.chunkoff[b], c1 = st.chunkoff[b + 1];
     T cross = (T)0, u2 = (T)0, v2 = (T)0;
     for (int l = lane; l <= k; l += 64) {
@@ -517,6 +529,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     DevBuf dt = upload(tasks, s), dub = upload(ubase, s);
     int64_t max_chunks = 0;
     for (auto &t : tasks) max_chunks += (t.m + t.n + kChunk - 1) / kChunk;
+    DevBuf ents(sizeof(int64_t) * (size_t)nb);
     DevBuf ints(sizeof(int) * (size_t)nb * 7), reals(sizeof(T) * (size_t)nb * 2),
         used(sizeof(unsigned) * (size_t)words), offs(sizeof(int64_t) * (size_t)(nb + 1) * 3),
         tot(sizeof(int64_t) * 5), part(sizeof(T) * (size_t)max_chunks * kPartStride),
@@ -532,6 +545,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     st.havepiv = ip + 4 * nb;
     st.act = ip + 5 * nb;
     st.act2 = ip + 6 * nb;
+    st.ents = ents.as<int64_t>();
     st.pivot = reals.as<T>();
     st.normS2 = reals.as<T>() + nb;
     st.used = used.as<unsigned>();
@@ -552,54 +566,73 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     int max_steps = 0;
     for (auto &t : tasks) max_steps = std::max(max_steps, t.kcap + t.m);
 
-    EventTimer ent(s), whole(s);
-    double entry_ms = 0.0;
-    int64_t entries = 0;
+    EventTimer whole(s);
+    // HIP events around the entry launches, read once after the batch
+    std::vector<hipEvent_t> evs;
+    auto mark = [&]() {
+        hipEvent_t e;
+        HIP_CHECK(hipEventCreate(&e));
+        HIP_CHECK(hipEventRecord(e, s));
+        evs.push_back(e);
+    };
     int launches = 0;
     whole.start();
     k_aca_init<T><<<nb, 256, 0, s>>>(st);
     HIP_LAUNCH_CHECK();
+    // The active lists are rebuilt every kCompact steps (one host read of the
+    // totals); in between, every step reuses them and the kernels skip the
+    // blocks that have stopped, so a step costs five launches and no host
+    // synchronisation.
+    constexpr int kCompact = 8;
     int64_t ht[5];
-    for (int step = 0; step <= max_steps; ++step) {
+    for (int step = 0; step <= max_steps;) {
         k_aca_scan<T, false><<<1, 1024, 0, s>>>(st);
-        HIP_LAUNCH_CHECK();
-        HIP_CHECK(hipMemcpyAsync(ht, st.tot, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        if (ht[1] == 0) break;
-        const int64_t nrow = ht[0];
-        ent.start();
-        if (H.kind == RTE_VOLUME)
-            k_aca_rows<T, RTE_VOLUME><<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn);
-        else
-            k_aca_rows<T, RTE_SURFACE><<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn);
-        HIP_LAUNCH_CHECK();
-        ent.stop();
-        entries += nrow;
-        k_aca_pivot<T><<<(unsigned)ht[1], 256, 0, s>>>(st);
         k_aca_scan<T, true><<<1, 1024, 0, s>>>(st);
         HIP_LAUNCH_CHECK();
-        HIP_CHECK(hipMemcpyAsync(ht + 2, st.tot + 2, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(ht, st.tot, sizeof(int64_t) * 5, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
-        entry_ms += ent.ms();
-        ++launches;
-        if (ht[3] == 0) continue;
-        const int64_t ncol = ht[2];
-        ent.start();
-        if (H.kind == RTE_VOLUME)
-            k_aca_cols<T, RTE_VOLUME><<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn);
-        else
-            k_aca_cols<T, RTE_SURFACE><<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn);
-        HIP_LAUNCH_CHECK();
-        ent.stop();
-        entries += ncol;
-        k_aca_dots<T><<<(unsigned)ht[4], 256, 0, s>>>(st);
-        k_aca_finish<T><<<(unsigned)ht[3], 64, 0, s>>>(st, eps);
-        HIP_LAUNCH_CHECK();
-        entry_ms += ent.ms();
-        ++launches;
+        if (ht[1] == 0) break;
+        const int64_t nrow = ht[0], nact = ht[1], ncol = ht[2], nchunk = ht[4];
+        for (int r = 0; r < kCompact && step <= max_steps; ++r, ++step) {
+            mark();
+            if (H.kind == RTE_VOLUME)
+                k_aca_rows<T, RTE_VOLUME><<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn);
+            else
+                k_aca_rows<T, RTE_SURFACE><<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn);
+            HIP_LAUNCH_CHECK();
+            mark();
+            k_aca_pivot<T><<<(unsigned)nact, 256, 0, s>>>(st);
+            HIP_LAUNCH_CHECK();
+            mark();
+            if (H.kind == RTE_VOLUME)
+                k_aca_cols<T, RTE_VOLUME><<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn);
+            else
+                k_aca_cols<T, RTE_SURFACE><<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn);
+            HIP_LAUNCH_CHECK();
+            mark();
+            k_aca_dots<T><<<(unsigned)nchunk, 256, 0, s>>>(st);
+            k_aca_finish<T><<<(unsigned)nact, 64, 0, s>>>(st, eps);
+            HIP_LAUNCH_CHECK();
+            launches += 2;
+        }
     }
     whole.stop();
-    B.aca_ms += whole.ms();
+    const double whole_ms = whole.ms();   // synchronises: every event below has completed
+    double entry_ms = 0.0;
+    for (size_t e = 0; e + 1 < evs.size(); e += 2) {
+        float ms = 0.0f;
+        HIP_CHECK(hipEventElapsedTime(&ms, evs[e], evs[e + 1]));
+        entry_ms += ms;
+    }
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    // exact count of the entries evaluated (per-block counters)
+    int64_t entries = 0;
+    {
+        std::vector<int64_t> he(nb);
+        HIP_CHECK(hipMemcpy(he.data(), st.ents, sizeof(int64_t) * nb, hipMemcpyDeviceToHost));
+        for (int64_t v : he) entries += v;
+    }
+    B.aca_ms += whole_ms;
     B.aca_entry_ms += entry_ms;
     B.aca_entry_launches += launches;
     B.aca_launches += 1;
