@@ -629,7 +629,8 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     int64_t entries = 0;
     {
         std::vector<int64_t> he(nb);
-        HIP_CHECK(hipMemcpy(he.data(), st.ents, sizeof(int64_t) * nb, hipMemcpyDeviceToHost));
+        HIP_CHECK(hipMemcpyAsync(he.data(), st.ents, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
         for (int64_t v : he) entries += v;
     }
     B.aca_ms += whole_ms;

@@ -29,7 +29,10 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <condition_variable>
 #include <map>
+#include <mutex>
+#include <thread>
 
 #include "kernels.h"
 #include "physics.h"
@@ -172,6 +175,8 @@ struct SrvOp {
     int mesh = 0, level = 0;
     std::unique_ptr<rte_hmat> G, S;
     int64_t bytes = 0;
+    int64_t reserved = 0;   // bytes held for it while it was being assembled
+    double ms = 0.0;        // assembly wall time
     int users = 0;
     uint64_t used = 0;
 };
@@ -210,22 +215,39 @@ struct SrvReq {
 };
 
 struct Server {
+    // requests scanned for admission in one pass, and the oldest waiting
+    // requests whose missing operators are assembled ahead of their admission
+    static constexpr int kWindow = 256, kLookahead = 4;
+
     rte_server_desc_t desc{};
     std::vector<double> nu, w;   // catalogue
-    hipStream_t s = nullptr;
+    hipStream_t user = nullptr;  // the caller's stream (inputs are ordered after it)
+    hipStream_t s = nullptr;     // sweeps (the server's own, non-blocking, default priority)
+    hipStream_t as = nullptr;    // assembly (the assembler thread's)
     int device = 0;
     std::vector<std::unique_ptr<SrvMesh>> meshes;
-    std::vector<std::unique_ptr<SrvOp>> ops;
+    std::vector<std::unique_ptr<SrvOp>> ops;   // resident operators (main thread only)
     std::map<int64_t, std::unique_ptr<SrvReq>> reqs;
     std::deque<SrvReq *> pending;
     std::vector<SrvReq *> active;
     int64_t next_id = 1;
     uint64_t clock = 0;
-    int64_t resident = 0;
+    int64_t resident = 0;        // operator and request-state bytes held
+    int64_t reserved = 0;        // estimated bytes of the operators being assembled
     rte_server_stats_t stats{};
     // per-step device and pinned buffers
     DevBuf x, y, ws, cols, part, res, newt, bandt, q;
     Pinned hcols, hres, hnewt, hband;
+    // the assembler thread
+    struct Job { SrvMesh *m; int mesh, level; int64_t reserved; };
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::deque<Job> jobs;                        // waiting
+    std::vector<std::pair<int, int>> inflight;   // queued or running (mesh, level)
+    std::vector<std::unique_ptr<SrvOp>> built;   // finished, not yet published
+    std::string worker_error;
+    bool stopping = false;
 
     bool mixed() const { return desc.precision == RTE_MIXED_BF16; }
 
@@ -264,62 +286,151 @@ struct Server {
 
     SrvOp *find_op(int mesh, int level) {
         for (auto &o : ops)
-            if (o->mesh == mesh && o->level == level && o->G) return o.get();
+            if (o->mesh == mesh && o->level == level) return o.get();
         return nullptr;
     }
-
-    void evict_one() {
-        SrvOp *v = nullptr;
-        for (auto &o : ops)
-            if (o->G && o->users == 0 && (!v || o->used < v->used)) v = o.get();
-        RTE_REQUIRE(v, "server: nothing to evict");
-        resident -= v->bytes;
-        v->G.reset();
-        v->S.reset();
-        v->bytes = 0;
-        stats.evicted += 1;
-        ops.erase(std::remove_if(ops.begin(), ops.end(), [](const std::unique_ptr<SrvOp> &o) { return !o->G; }),
-                  ops.end());
+    bool in_flight(int mesh, int level) {
+        return std::find(inflight.begin(), inflight.end(), std::make_pair(mesh, level)) != inflight.end();
     }
 
-    bool evictable() const {
-        for (auto &o : ops)
-            if (o->G && o->users == 0) return true;
-        return false;
-    }
-
-    SrvOp *assemble(int mi, int level) {
-        SrvMesh &M = *meshes[mi];
+    // ------------------------------------------------ the assembler thread
+    // Operators of one (mesh, level) on the assembler's stream; touches no
+    // server state but the mesh's cluster-order tables on its first operator
+    // (no request of that mesh can be admitted before it is published).
+    std::unique_ptr<SrvOp> build_op(SrvMesh &M, int mi, int level) {
         const auto t0 = std::chrono::steady_clock::now();
         DevBuf kap(sizeof(double) * (size_t)M.mesh.N);
         const double mult = std::pow(10.0, (double)level / desc.levels_per_decade);
-        k_scale<<<(unsigned)((M.mesh.N + 255) / 256), 256, 0, s>>>(M.kappa.as<double>(), mult, M.mesh.N,
-                                                                   kap.as<double>());
+        k_scale<<<(unsigned)((M.mesh.N + 255) / 256), 256, 0, as>>>(M.kappa.as<double>(), mult, M.mesh.N,
+                                                                    kap.as<double>());
         HIP_LAUNCH_CHECK();
         auto op = std::make_unique<SrvOp>();
         op->mesh = mi;
         op->level = level;
-        op->G = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_VOLUME)), 1, kap.as<double>(), s);
-        op->S = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_SURFACE)), 1, kap.as<double>(), s);
+        op->G = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_VOLUME)), 1, kap.as<double>(), as);
+        op->S = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_SURFACE)), 1, kap.as<double>(), as);
         op->bytes = op->G->h.stats.bytes + op->S->h.stats.bytes;
         if (!M.have_order) {
-            const HMat &G = op->G->h;
             M.tgt_nat.alloc(sizeof(int64_t) * (size_t)M.mesh.N);
-            HIP_CHECK(hipMemcpyAsync(M.tgt_nat.p, G.tgt_nat.p, M.tgt_nat.bytes, hipMemcpyDeviceToDevice, s));
+            HIP_CHECK(hipMemcpyAsync(M.tgt_nat.p, op->G->h.tgt_nat.p, M.tgt_nat.bytes, hipMemcpyDeviceToDevice, as));
             M.src_pos.alloc(sizeof(int64_t) * (size_t)M.mesh.L);
-            HIP_CHECK(hipMemcpyAsync(M.src_pos.p, op->S->h.src_pos.p, M.src_pos.bytes, hipMemcpyDeviceToDevice, s));
+            HIP_CHECK(hipMemcpyAsync(M.src_pos.p, op->S->h.src_pos.p, M.src_pos.bytes, hipMemcpyDeviceToDevice, as));
             M.kap_c.alloc(sizeof(double) * (size_t)M.mesh.N);
             permute_gather(M.tgt_nat.as<int64_t>(), M.mesh.N, 1, M.mesh.N, M.mesh.N, M.kappa.as<double>(),
-                           M.kap_c.as<double>(), s);
+                           M.kap_c.as<double>(), as);
             M.have_order = true;
         }
-        HIP_CHECK(hipStreamSynchronize(s));   // kap is released on return
-        M.est_bytes = std::max(M.est_bytes, op->bytes);
-        resident += op->bytes;
-        stats.assembled += 1;
-        stats.assemble_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        ops.push_back(std::move(op));
-        return ops.back().get();
+        HIP_CHECK(hipStreamSynchronize(as));   // kap is released on return
+        op->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return op;
+    }
+
+    void worker_loop() {
+        (void)hipSetDevice(device);
+        for (;;) {
+            Job j;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stopping || !jobs.empty(); });
+                if (stopping) return;
+                j = jobs.front();
+                jobs.pop_front();
+            }
+            std::unique_ptr<SrvOp> op;
+            std::string err;
+            try {
+                op = build_op(*j.m, j.mesh, j.level);
+                op->reserved = j.reserved;
+            } catch (const std::exception &e) {
+                err = e.what();
+            }
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (op) built.push_back(std::move(op));
+                else {
+                    worker_error = err.empty() ? "assembly failed" : err;
+                    inflight.erase(std::remove(inflight.begin(), inflight.end(), std::make_pair(j.mesh, j.level)),
+                                   inflight.end());
+                    reserved -= j.reserved;
+                }
+            }
+            done_cv.notify_all();
+        }
+    }
+
+    // move finished operators into the resident set (main thread)
+    void publish() {
+        std::vector<std::unique_ptr<SrvOp>> got;
+        std::string err;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            got.swap(built);
+            err.swap(worker_error);
+            for (auto &o : got) {
+                inflight.erase(std::remove(inflight.begin(), inflight.end(), std::make_pair(o->mesh, o->level)),
+                               inflight.end());
+                reserved -= o->reserved;
+            }
+        }
+        for (auto &o : got) {
+            resident += o->bytes;
+            SrvMesh &M = *meshes[o->mesh];
+            M.est_bytes = std::max(M.est_bytes, o->bytes);
+            stats.assembled += 1;
+            stats.assemble_ms += o->ms;
+            o->used = ++clock;
+            ops.push_back(std::move(o));
+        }
+        if (!err.empty()) throw Error(RTE_E_INTERNAL, "server: " + err);
+    }
+
+    void enqueue(int mi, int level, int64_t est) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            jobs.push_back({meshes[mi].get(), mi, level, est});
+            inflight.push_back({mi, level});
+            reserved += est;
+        }
+        cv.notify_one();
+    }
+
+    bool busy() {
+        std::lock_guard<std::mutex> lk(mu);
+        return !inflight.empty();
+    }
+
+    // ------------------------------------------------ budget
+    // Evict unused operators (least recently used first, those the oldest
+    // waiting requests need last) until `bytes` more fit; false if they do not.
+    bool make_room(int64_t bytes, const std::vector<std::pair<int, int>> &wanted) {
+        auto held = [&] {
+            std::lock_guard<std::mutex> lk(mu);
+            return resident + reserved;
+        };
+        while (held() + bytes > desc.hbm_budget) {
+            SrvOp *v = nullptr;
+            bool v_wanted = true;
+            for (auto &o : ops) {
+                if (o->users) continue;
+                const bool wn = std::find(wanted.begin(), wanted.end(), std::make_pair(o->mesh, o->level)) !=
+                                wanted.end();
+                if (!v || (v_wanted && !wn) || (v_wanted == wn && o->used < v->used)) {
+                    v = o.get();
+                    v_wanted = wn;
+                }
+            }
+            if (!v) return false;
+            resident -= v->bytes;
+            stats.evicted += 1;
+            ops.erase(std::remove_if(ops.begin(), ops.end(), [&](const std::unique_ptr<SrvOp> &o) { return o.get() == v; }),
+                      ops.end());
+        }
+        return true;
+    }
+
+    bool fits_now(int64_t bytes) {
+        std::lock_guard<std::mutex> lk(mu);
+        return resident + reserved + bytes <= desc.hbm_budget;
     }
 
     int64_t state_bytes(const SrvReq &r) const {
@@ -327,41 +438,24 @@ struct Server {
         return (int64_t)sizeof(double) * N * (2 + 4 * (int64_t)r.bands.size());
     }
 
-    // admit the head of the queue if its operators and state fit the budget
-    bool admit_head() {
-        SrvReq &r = *pending.front();
+    std::vector<int> distinct_levels(const SrvReq &r) const {
+        std::vector<int> l = r.levels;
+        std::sort(l.begin(), l.end());
+        l.erase(std::unique(l.begin(), l.end()), l.end());
+        return l;
+    }
+
+    // admit a request whose operators are all resident
+    void admit(SrvReq &r) {
         SrvMesh &M = *meshes[r.mesh];
-        std::vector<int> levels = r.levels;
-        std::sort(levels.begin(), levels.end());
-        levels.erase(std::unique(levels.begin(), levels.end()), levels.end());
-        // the request's resident operators are pinned (one user each) before
-        // anything is evicted, so the eviction cannot take them
-        std::vector<SrvOp *> pinned;
-        std::vector<int> missing;
-        for (int l : levels) {
-            if (SrvOp *o = find_op(r.mesh, l)) {
-                o->users += 1;
-                pinned.push_back(o);
-            } else {
-                missing.push_back(l);
-            }
-        }
-        const int64_t need = state_bytes(r) + (int64_t)missing.size() * M.est_bytes;
-        while (resident + need > desc.hbm_budget && evictable()) evict_one();
-        if (resident + need > desc.hbm_budget) {
-            if (!active.empty()) {   // wait for running requests to retire
-                for (SrvOp *o : pinned) o->users -= 1;
-                return false;
-            }
-            stats.over_budget += 1;   // alone it must run: admitted beyond the budget
-        }
-        for (int l : missing) assemble(r.mesh, l)->users += 1;
+        for (int l : distinct_levels(r)) find_op(r.mesh, l)->users += 1;
         const int nb = (int)r.bands.size();
         const int64_t N = M.mesh.N, L = M.mesh.L;
         r.ops.clear();
         for (int b = 0; b < nb; ++b) {
             SrvOp *o = find_op(r.mesh, r.levels[b]);
             RTE_REQUIRE(o, "server: operator of an admitted request is missing");
+            o->used = ++clock;
             r.ops.push_back(o);
         }
         r.state_bytes = state_bytes(r);
@@ -382,8 +476,78 @@ struct Server {
         r.state = RTE_REQ_ACTIVE;
         r.phase = 0;
         active.push_back(&r);
-        pending.pop_front();
-        return true;
+    }
+
+    // One admission pass.  (1) In arrival order, every waiting request whose
+    // operators are resident is admitted while slots and the budget allow.
+    // (2) The missing operators of the oldest waiting requests are queued for
+    // the assembler, within the budget (unused operators are evicted, those
+    // these requests need last).  With nothing running and nothing being
+    // assembled, the oldest request is served even beyond the budget, so the
+    // server always makes progress.
+    void admission() {
+        publish();
+        std::vector<std::pair<int, int>> wanted;
+        {
+            int look = 0;
+            for (SrvReq *r : pending) {
+                if (look++ >= kLookahead) break;
+                for (int l : r->levels) wanted.push_back({r->mesh, l});
+            }
+        }
+        int scanned = 0;
+        for (auto it = pending.begin(); it != pending.end() && (int)active.size() < desc.max_active &&
+                                        scanned < kWindow;
+             ++scanned) {
+            SrvReq &r = **it;
+            bool ready = true;
+            for (int l : r.levels) ready = ready && find_op(r.mesh, l) != nullptr;
+            if (!ready) {
+                ++it;
+                continue;
+            }
+            // pin this request's operators while room is made for its state
+            std::vector<SrvOp *> mine;
+            for (int l : distinct_levels(r)) {
+                SrvOp *o = find_op(r.mesh, l);
+                o->users += 1;
+                mine.push_back(o);
+            }
+            const bool fits = make_room(state_bytes(r), wanted);
+            for (SrvOp *o : mine) o->users -= 1;
+            if (!fits && !(active.empty() && !busy())) break;
+            if (!fits) stats.over_budget += 1;
+            admit(r);
+            it = pending.erase(it);
+        }
+        // assembly ahead of admission for the oldest waiting requests.  Only
+        // the oldest may evict (its resident operators pinned meanwhile, so
+        // making room for its missing levels never evicts the ones it already
+        // has); the others are assembled only into free room.  Letting them
+        // evict too can livelock: two requests that together exceed the budget
+        // evict each other's operators without end.
+        int look = 0;
+        for (SrvReq *r : pending) {
+            const bool head = look == 0;
+            if (look++ >= kLookahead) break;
+            const SrvMesh &M = *meshes[r->mesh];
+            std::vector<SrvOp *> pin;
+            if (head)
+                for (int l : distinct_levels(*r))
+                    if (SrvOp *o = find_op(r->mesh, l)) { o->users += 1; pin.push_back(o); }
+            bool stop = false;
+            for (int l : distinct_levels(*r)) {
+                if (find_op(r->mesh, l) || in_flight(r->mesh, l)) continue;
+                const bool room = head ? make_room(M.est_bytes, wanted) : fits_now(M.est_bytes);
+                if (!room) {
+                    if (!(head && active.empty() && !busy())) { stop = true; break; }
+                    stats.over_budget += 1;
+                }
+                enqueue(r->mesh, l, M.est_bytes);
+            }
+            for (SrvOp *o : pin) o->users -= 1;
+            if (stop) return;
+        }
     }
 
     void retire(SrvReq &r) {
@@ -391,10 +555,8 @@ struct Server {
         r.out.alloc(sizeof(double) * (size_t)M.mesh.N);
         permute_scatter(M.tgt_nat.as<int64_t>(), M.mesh.N, 1, M.mesh.N, M.mesh.N, r.T(), r.out.as<double>(), s);
         HIP_CHECK(hipStreamSynchronize(s));
-        std::vector<SrvOp *> distinct = r.ops;
-        std::sort(distinct.begin(), distinct.end());
-        distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
-        for (SrvOp *o : distinct) {
+        for (int l : distinct_levels(r)) {
+            SrvOp *o = find_op(r.mesh, l);
             o->users -= 1;
             o->used = ++clock;
         }
@@ -403,7 +565,6 @@ struct Server {
         r.state = RTE_REQ_DONE;
         stats.completed += 1;
     }
-
     // one sweep of every active request
     void sweep() {
         // columns grouped by (operator, inner) in a fixed order
@@ -540,11 +701,32 @@ struct Server {
 
     void step() {
         HIP_CHECK(hipSetDevice(device));
-        while (!pending.empty() && (int)active.size() < desc.max_active && admit_head()) {
+        admission();
+        if (!active.empty()) {
+            sweep();
+        } else if (!pending.empty()) {
+            // nothing to sweep: wait (briefly) for the assembler
+            std::unique_lock<std::mutex> lk(mu);
+            done_cv.wait_for(lk, std::chrono::milliseconds(5), [&] { return !built.empty() || !worker_error.empty(); });
         }
-        if (!active.empty()) sweep();
         stats.resident_bytes = resident;
         stats.operators = (int64_t)ops.size();
+    }
+
+    ~Server() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stopping = true;
+        }
+        cv.notify_all();
+        if (worker.joinable()) worker.join();
+        if (s) (void)hipStreamSynchronize(s);
+        if (as) (void)hipStreamSynchronize(as);
+        reqs.clear();
+        ops.clear();
+        built.clear();
+        if (s) (void)hipStreamDestroy(s);
+        if (as) (void)hipStreamDestroy(as);
     }
 };
 
@@ -558,8 +740,10 @@ Server *server_create(const rte_server_desc_t &d, hipStream_t s) {
     RTE_REQUIRE(d.hbm_budget >= 0, "server: hbm_budget must be >= 0");
     auto S = std::make_unique<Server>();
     S->desc = d;
-    S->s = s;
+    S->user = s;
     HIP_CHECK(hipGetDevice(&S->device));
+    HIP_CHECK(hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking));
+    HIP_CHECK(hipStreamCreateWithFlags(&S->as, hipStreamNonBlocking));
     for (int b = 0; b < d.n_catalogue; ++b) {
         RTE_REQUIRE(std::isfinite(d.nu[b]) && d.nu[b] > 0 && (b == 0 || d.nu[b] > d.nu[b - 1]),
                     "server: catalogue frequencies must be positive and increasing");
@@ -579,13 +763,21 @@ Server *server_create(const rte_server_desc_t &d, hipStream_t s) {
         S->desc.hbm_budget = (int64_t)(0.8 * (double)fr);
     }
     S->stats.budget = S->desc.hbm_budget;
+    Server *raw = S.get();
+    S->worker = std::thread([raw] { raw->worker_loop(); });
     return S.release();
 }
 
-void server_destroy(Server *S) {
-    if (!S) return;
-    (void)hipStreamSynchronize(S->s);
-    delete S;
+void server_destroy(Server *S) { delete S; }
+
+// order the server's sweep stream after the caller's (inputs written there)
+static void after_user(Server &S) {
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_CHECK(hipEventRecord(e, S.user));
+    HIP_CHECK(hipStreamWaitEvent(S.s, e, 0));
+    HIP_CHECK(hipStreamWaitEvent(S.as, e, 0));
+    (void)hipEventDestroy(e);
 }
 
 int server_add_mesh(Server &S, const rte_mesh_desc_t &md, const double *kappa) {
@@ -593,6 +785,7 @@ int server_add_mesh(Server &S, const rte_mesh_desc_t &md, const double *kappa) {
     mesh_init(M->mesh, md);
     RTE_REQUIRE(M->mesh.L > 0, "server: the mesh has no emitting face");
     M->kappa.alloc(sizeof(double) * (size_t)M->mesh.N);
+    after_user(S);
     HIP_CHECK(hipMemcpyAsync(M->kappa.p, kappa, M->kappa.bytes, hipMemcpyDeviceToDevice, S.s));
     HIP_CHECK(hipStreamSynchronize(S.s));
     M->est_bytes = S.bound_bytes(M->mesh);
@@ -620,6 +813,7 @@ int64_t server_submit(Server &S, const rte_request_t &q) {
     r->tol = q.tol;
     r->max_iter = q.max_iter;
     r->Tw.alloc(sizeof(double) * (size_t)M.mesh.L);
+    after_user(S);
     HIP_CHECK(hipMemcpyAsync(r->Tw.p, q.T_wall, r->Tw.bytes, hipMemcpyDeviceToDevice, S.s));
     HIP_CHECK(hipStreamSynchronize(S.s));
     const int64_t id = r->id;
