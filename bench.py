@@ -29,6 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the ACA entry launches (k_aca_rows / k_aca_cols, volume,
+# FP64), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over this benchmark's step,
+# calibrated on a plain 1 GiB copy (FETCH_SIZE reads half the bytes, WRITE_SIZE all):
+# the summary is profiles/cube41_grey_fp64_hmatrix_hbm_traffic.md.  Set to None
+# whenever those kernels change.
+ACA_ENTRY_TRAFFIC_BYTES = 201.2e6
 FP64_PEAK_TFLOPS = 78.6
 # algorithmic FP64 operations of one kernel entry (see the design notes):
 # per ray-march piece, per quadrature term, and per entry
@@ -217,7 +223,8 @@ def main():
     if dominant == "aca":
         roof = {"kernel": "k_aca_rows + k_aca_cols (FP64 kernel entries of the ACA rank steps, volume matrix)",
                 "bound": "alu", "achieved": aca_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": aca_tflops / FP64_PEAK_TFLOPS, "traffic": None,
+                "frac": aca_tflops / FP64_PEAK_TFLOPS, "traffic": ACA_ENTRY_TRAFFIC_BYTES,
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 counters)",
                 "flop_per_entry": f_entry, "entries_per_launch": aca_entries_G / nl,
                 "launch_ms": aca_launch_ms_G, "launches": nl}
     else:

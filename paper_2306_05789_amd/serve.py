@@ -29,8 +29,9 @@ class Server:
         self._sizes = []
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            rte.load().rte_server_destroy(self.handle)
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "handle", None) and rte is not None and getattr(rte, "_lib", None) is not None:
+            rte._lib.rte_server_destroy(self.handle)
             self.handle = None
 
     def add_mesh(self, n, kappa, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), emit_faces=63) -> int:
