@@ -13,6 +13,19 @@ Prints one JSON line.  `value` is whole-solve throughput (solves/s); the
 `roofline` object covers the kernel with the largest share of the step; the
 `hmatvec` object reports the matvec's HBM rate; `cpu_baseline` times the FP64
 CPU oracle on a bounded sample of the same workload.
+
+Other workloads (`--workload`), each one JSON line of its own; the default run
+is the 41^3 FP64 solve above:
+  reflective  box [0,2]x[0,1]^2 on 65x33x33, mirror wall z = 0 (R = 0.5), 8 bands,
+              mixed precision against plain FP64 (assembly, event-timed matvecs,
+              solves to 1e-6)
+  batched     unit cube 49^3, 32 bands x 16 right-hand sides, mixed precision, all
+              bands and right-hand sides in one launch per phase, autotuned launch
+              shape; `--bands B` takes every (32/B)-th band, `--compare` adds plain
+              FP64 on the same bands
+  served      256 Poisson(20/s) requests over resident 21^3/29^3/41^3/49^3 meshes
+              through the request server (mixed, continuous batching) and, with
+              `--compare R`, the first R of them through plain FP64 one at a time
 """
 from __future__ import annotations
 
@@ -126,6 +139,192 @@ def cpu_baseline(wl, budget_s=12.0):
                       f"({full:.0f} s), fixed-point iterations excluded"}
 
 
+def _say(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
+def _hstats(st, keys=("assemble_ms", "aca_kernel_ms", "aca_entry_ms", "fill_kernel_ms", "bytes", "compression",
+                      "mean_rank", "max_rank", "n_lowrank", "n_fallback_dense")):
+    return {k: st[k] for k in keys}
+
+
+def _operator_bytes(st, op):
+    """Stored bytes one matvec streams: all of them, or the BF16 high parts alone
+    (half of the split storage) for the low operator."""
+    from paper_2306_05789_amd import rte
+    if st["precision"] == rte.RTE_MIXED_BF16 and op == rte.RTE_OP_LOW:
+        return st["bytes"] // 2
+    return st["bytes"]
+
+
+def _matvec_entry(G, nrhs, op, reps=3):
+    """Event-timed all-band matvec and its HBM rate over algorithmic bytes: the
+    operator's stored bytes plus x read and y written in FP64."""
+    from paper_2306_05789_amd import rte
+    st = rte.rte_hmat_stats(G)
+    ms = rte.rte_hmat_time_matvec(G, nrhs, op, reps)
+    b = _operator_bytes(st, op) + 8 * st["n_bands"] * nrhs * (st["n_src"] + st["n_tgt"])
+    gbs = b / (ms * 1e-3) / 1e9
+    return {"nrhs": nrhs, "op": "low" if op == rte.RTE_OP_LOW else "accurate", "ms": ms, "bytes": b,
+            "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
+def _solve_series(rte, mesh, G, S, Tw, T, nu, precision, tol, steps, warmup):
+    for _ in range(warmup):
+        rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=False, nu=nu, tol=tol, max_iter=3000, precision=precision)
+    import torch
+    torch.cuda.synchronize()
+    lat, st = [], None
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        st = rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=False, nu=nu, tol=tol, max_iter=3000,
+                                       precision=precision)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        _say(f"solve {lat[-1] * 1e3:.1f} ms, {st['iterations']} sweeps, residual {st['residual']:.2e}")
+    return lat, st
+
+
+def run_reflective(args):
+    """Reflective box, 8 bands: mixed precision (FP32 entries and ACA, BF16 factors,
+    FP64 defect correction) against plain FP64, both to a 1e-6 residual."""
+    import torch
+    from paper_2306_05789_amd import inputs, rte
+    wl = inputs.reflective_bands()
+    dev = torch.device("cuda:0")
+    mesh = rte.rte_mesh_create(wl.n, wl.lo, wl.hi, reflect_axis=wl.wall_axis, reflect_side=wl.wall_side, R=wl.R,
+                               emit_faces=wl.emit_faces)
+    kap = torch.tensor(wl.kappa, device=dev)
+    Tw = torch.tensor(wl.T_wall, device=dev)
+    res, Ts = {}, {}
+    for name in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
+        p = rte.PRECISIONS[name]
+        G = rte.rte_hmat_assemble(mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, precision=p))
+        S = rte.rte_hmat_assemble(mesh, kap, rte.hmat_opts(kind=rte.RTE_SURFACE, precision=p))
+        gs, ss = rte.rte_hmat_stats(G), rte.rte_hmat_stats(S)
+        _say(f"{name}: G {gs['assemble_ms']:.0f} ms, S {ss['assemble_ms']:.0f} ms")
+        T = torch.empty((1, mesh.N), device=dev, dtype=torch.float64)
+        lat, st = _solve_series(rte, mesh, G, S, Tw, T, wl.nu, p, 1e-6, args.steps, args.warmup)
+        ops = [rte.RTE_OP_LOW, rte.RTE_OP_ACCURATE] if p == rte.RTE_MIXED_BF16 else [rte.RTE_OP_ACCURATE]
+        solve_s = float(np.mean(lat))
+        res[name] = {"assemble_G": _hstats(gs), "assemble_S": _hstats(ss),
+                     "solve_ms": solve_s * 1e3, "sweeps": st["iterations"], "outer_steps": st["outer_steps"],
+                     "residual": st["residual"],
+                     "resident_solves_per_s": 1.0 / solve_s,
+                     "solves_per_s": 1.0 / (solve_s + (gs["assemble_ms"] + ss["assemble_ms"]) * 1e-3),
+                     "matvec": [_matvec_entry(G, 1, op) for op in ops]}
+        Ts[name] = T.cpu().numpy()
+        del G, S
+        torch.cuda.empty_cache()
+    head = res.get("mixed", next(iter(res.values())))
+    out = {"metric": "fixed-point solves/sec (assembly + solve, 1e-6 residual), 8 bands", "value": head["solves_per_s"],
+           "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 entries/ACA, bf16 factors, f64 correction" if "mixed" in res else "f64",
+           "data": "synthetic",
+           "config": {"workload": "box65x33x33_reflective_8band", "N": mesh.N, "bands": len(wl.nu), "R": wl.R},
+           "results": res}
+    if len(Ts) == 2:
+        out["mixed_vs_fp64_max_rel_T"] = float(np.max(np.abs(Ts["mixed"] - Ts["fp64"]) / Ts["fp64"]))
+    print(json.dumps(out))
+
+
+def run_batched(args):
+    """49^3 cube, 32 bands x 16 right-hand sides: all bands and right-hand sides per
+    launch, autotuned launch shape, mixed precision; `--compare` adds plain FP64 on
+    the same bands (32 FP64 bands do not fit one GPU: take a share with --bands)."""
+    import torch
+    from paper_2306_05789_amd import inputs, rte, tune
+    wl = inputs.batched()
+    nb_all = wl.kappa.shape[0]
+    bands = list(range(0, nb_all, max(1, nb_all // args.bands))) if args.bands else list(range(nb_all))
+    dev = torch.device("cuda:0")
+    mesh = rte.rte_mesh_create(wl.n, emit_faces=wl.emit_faces)
+    kap = torch.tensor(wl.kappa[bands], device=dev)
+    nu = wl.nu[bands]
+    Tw = torch.tensor(wl.T_wall, device=dev)
+    nrhs = Tw.shape[0]
+    names = ["mixed", "fp64"] if args.compare else ["mixed"]
+    res, Ts = {}, {}
+    for name in names:
+        p = rte.PRECISIONS[name]
+        G = rte.rte_hmat_assemble(mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, precision=p))
+        S = rte.rte_hmat_assemble(mesh, kap, rte.hmat_opts(kind=rte.RTE_SURFACE, precision=p))
+        gs, ss = rte.rte_hmat_stats(G), rte.rte_hmat_stats(S)
+        _say(f"{name}: {len(bands)} bands, G {gs['assemble_ms']:.0f} ms ({gs['bytes'] / 1e9:.1f} GB), "
+             f"S {ss['assemble_ms']:.0f} ms")
+        hot = rte.RTE_OP_LOW if p == rte.RTE_MIXED_BF16 else rte.RTE_OP_ACCURATE
+        tuned = tune.autotune(G, nrhs=nrhs, op=hot, reps=2)
+        _say(f"{name}: autotuned {tuned['config']} ({tuned['ms']:.2f} ms, {tuned['trials']} shapes)")
+        ops = [rte.RTE_OP_LOW, rte.RTE_OP_ACCURATE] if p == rte.RTE_MIXED_BF16 else [rte.RTE_OP_ACCURATE]
+        mv = [_matvec_entry(G, r, op) for op in ops for r in (1, nrhs)]
+        T = torch.empty((nrhs, mesh.N), device=dev, dtype=torch.float64)
+        lat, st = _solve_series(rte, mesh, G, S, Tw, T, nu, p, 1e-6, args.steps, args.warmup)
+        solve_s = float(np.mean(lat))
+        res[name] = {"assemble_G": _hstats(gs), "assemble_S": _hstats(ss), "autotuned": tuned,
+                     "solve_ms": solve_s * 1e3, "sweeps": st["iterations"], "outer_steps": st["outer_steps"],
+                     "residual": st["residual"], "graphs": st["graphs"],
+                     "rhs_solves_per_s": nrhs / solve_s, "matvec": mv}
+        Ts[name] = T.cpu().numpy()
+        del G, S
+        torch.cuda.empty_cache()
+    head = res["mixed"]
+    hot = next(m for m in head["matvec"] if m["op"] == "low" and m["nrhs"] == nrhs)
+    out = {"metric": f"right-hand-side solves/sec at 1e-6 residual ({len(bands)} bands x {nrhs} RHS, operators resident)",
+           "value": head["rhs_solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 entries/ACA, bf16 factors, f64 correction", "data": "synthetic",
+           "config": {"workload": f"cube49_{len(bands)}band_{nrhs}rhs", "N": mesh.N, "bands": bands, "nrhs": nrhs},
+           "roofline": {"kernel": "k_mf_phase_a + k_mf_phase_b (low operator, all bands x 16 RHS)", "bound": "hbm",
+                        "achieved": hot["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hot["frac"],
+                        "traffic": None},
+           "results": res}
+    if len(Ts) == 2:
+        out["mixed_vs_fp64_max_rel_T"] = float(np.max(np.abs(Ts["mixed"] - Ts["fp64"]) / Ts["fp64"]))
+        out["speedup_mixed_over_fp64"] = res["fp64"]["solve_ms"] / res["mixed"]["solve_ms"]
+    print(json.dumps(out))
+
+
+def run_served(args):
+    """The request stream through the server: mixed precision with continuous
+    batching, and (with --compare R) the first R requests through plain FP64 one
+    at a time on the same server code."""
+    import torch
+    from paper_2306_05789_amd import inputs, rte
+    from paper_2306_05789_amd.serve import Server, run_stream
+    meshes = (21, 29, 41, 49)
+    nu, c = inputs.catalogue(32)
+    reqs = inputs.request_stream(max(args.requests, args.compare, 1))
+    legs = [("mixed", rte.RTE_MIXED_BF16, 64, reqs[:args.requests])] if args.requests else []
+    if args.compare:
+        legs.append(("fp64", rte.RTE_FP64, 1, reqs[:args.compare]))
+    res = {}
+    for name, prec, active, rq in legs:
+        srv = Server(nu, budget=int(args.budget_gb * 1e9), precision=prec, max_active=active)
+        ids = [srv.add_mesh((n, n, n), torch.tensor(inputs.smooth_kappa(
+            inputs.grid_positions((n, n, n), (0, 0, 0), (1, 1, 1))), device="cuda:0")) for n in meshes]
+        t0 = time.perf_counter()
+
+        def log(k, st, lat, name=name, t0=t0):
+            q = rq[k]
+            _say(f"{name} [{time.perf_counter() - t0:7.1f} s] request {k} mesh {meshes[q.mesh]}^3 "
+                 f"{len(q.bands)} bands: {st['iterations']} sweeps, latency {lat * 1e3:.0f} ms")
+        r = run_stream(srv, rq, ids, [n ** 3 for n in meshes], c, tol=1e-6, log=log)
+        res[name] = {"requests": len(rq), "max_active": active, "wall_s": r["wall_s"],
+                     "solves_per_s": r["solves_per_s"], "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                     "converged": int(sum(1 for i in r["info"] if i and i["converged"])), "server": srv.stats()}
+        del srv
+    head = res["mixed"] if "mixed" in res else res["fp64"]
+    out = {"metric": "served fixed-point solves/sec with p50/p99 latency (1e-6 residual)",
+           "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 entries/ACA, bf16 factors, f64 correction" if "mixed" in res else "f64", "data": "synthetic",
+           "config": {"workload": f"served_{head['requests']}req_poisson20", "meshes": list(meshes),
+                      "budget_GB": args.budget_gb},
+           "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]}, "results": res}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,11 +332,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=41, help="vertices per axis of the cube")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="cube41", choices=("cube41", "reflective", "batched", "served"))
+    ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"), help="reflective workload")
+    ap.add_argument("--bands", type=int, default=0, help="batched workload: bands taken (0 = all 32)")
+    ap.add_argument("--compare", type=int, default=0,
+                    help="batched: add plain FP64 (1); served: requests replayed through plain FP64")
+    ap.add_argument("--requests", type=int, default=256,
+                    help="served workload: requests of the stream served in mixed precision (0: none)")
+    ap.add_argument("--budget-gb", type=float, default=250.0, help="served workload: HBM budget of the server")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU band sharding is a design, not a build "
               "(see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "cube41":
+        {"reflective": run_reflective, "batched": run_batched, "served": run_served}[args.workload](args)
+        return
 
     import torch
     from paper_2306_05789_amd import inputs, rte

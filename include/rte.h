@@ -258,10 +258,16 @@ rte_status_t rte_fixed_point_solve(rte_mesh_t mesh, rte_hmat_t vol, rte_hmat_t s
  * snapped value defines the request.  The operators of a (mesh, level) are
  * assembled on first use, shared by every band of every request at that
  * level and evicted least recently used, when unused, to stay within the HBM
- * budget.  Requests are admitted in arrival order when their operators and
- * state fit; each rte_server_step runs one sweep of every admitted request
- * (columns that share an operator in one matvec) and retires the ones that
- * converged.  Band weights are the trapezoid weights of the whole catalogue.
+ * budget.  A waiting request whose operators are resident is admitted, in
+ * arrival order among such requests, once its state fits; missing operators
+ * are assembled by a thread of the server on a stream of its own, for the
+ * oldest few waiting requests, and only the oldest may evict.  Each
+ * rte_server_step runs one sweep of every admitted request (columns that
+ * share an operator in one matvec) and retires the ones that converged.  Band
+ * weights are the trapezoid weights of the whole catalogue (the band sum of
+ * Section "Test 2: the General Case").  The fixed point of every request is the
+ * one of Section "Fixed Point Iterations", defect-corrected with mixed
+ * precision storage as in rte_fixed_point_solve.
  * Not thread safe: one thread drives a server. */
 typedef struct rte_server *rte_server_t;
 

@@ -13,9 +13,14 @@
 // of every request at that level, kept while the HBM budget allows and
 // evicted least recently used when not in use.
 //
-// Requests wait in arrival order; the head is admitted when its operators and
-// state fit the budget (the oldest waiting request is never overtaken).  Each
-// step runs one sweep of every admitted request: the (request, band) columns
+// Requests wait in arrival order.  A waiting request whose operators are all
+// resident is admitted as soon as its state fits the budget, in arrival order
+// among such requests (one with missing operators does not hold up the ones
+// behind it).  A background thread on its own stream assembles the missing
+// operators of the oldest few waiting requests; only the oldest may evict
+// unused operators to make room, the others are assembled into free room
+// only, so the oldest request always makes progress.  Each step runs one
+// sweep of every admitted request: the (request, band) columns
 // that share an operator go through one multi-right-hand-side matvec, then
 // one launch updates every request's temperatures.  A request that converges
 // (or reaches its iteration cap) retires at once and frees its slot; the
