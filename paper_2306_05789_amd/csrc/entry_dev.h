@@ -83,64 +83,115 @@ constexpr KuhnStar make_star() {
 constexpr KuhnStar kStar = make_star();
 
 // ---------------------------------------------------------------- P1 kappa and the march
+// Minimum of two finite values without the quieting of signalling NaNs that
+// fmin() adds on this target (two extra instructions per call in the march).
+__device__ __forceinline__ double fmin_finite(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float fmin_finite(float a, float b) {
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// kappa is read through a buffer resource sized to the grid: an index
+// outside [0, N) returns 0 instead of touching other memory.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
 template <typename T>
-__device__ __forceinline__ T kappa_grid(const GridDev &g, const T *__restrict__ kap, T X, T Y, T Z) {
-    int c0 = min(max((int)floor(X), 0), g.n[0] - 2);
-    int c1 = min(max((int)floor(Y), 0), g.n[1] - 2);
-    int c2 = min(max((int)floor(Z), 0), g.n[2] - 2);
-    T u0 = X - (T)c0, u1 = Y - (T)c1, u2 = Z - (T)c2;
+__device__ __forceinline__ rsrc_t kappa_rsrc(const GridDev &g, const T *kap) {
+    const int bytes = g.n[0] * g.n[1] * g.n[2] * (int)sizeof(T);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(kap), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ double kload(rsrc_t r, int idx, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
+}
+__device__ __forceinline__ float kload(rsrc_t r, int idx, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
+}
+
+// P1 (Freudenthal) interpolation of kappa in the cell with flat base index b
+// at local coordinates (u0, u1, u2) in [0, 1]^3 (grid units).
+template <typename T>
+__device__ __forceinline__ T kappa_in_cell(const GridDev &g, rsrc_t kr, int b, T u0, T u1, T u2) {
     int s0 = g.stride[0], s1 = g.stride[1], s2 = 1;
     // order the local coordinates decreasingly, carrying the axis strides
     if (u1 > u0) { T t = u0; u0 = u1; u1 = t; int s = s0; s0 = s1; s1 = s; }
     if (u2 > u1) { T t = u1; u1 = u2; u2 = t; int s = s1; s1 = s2; s2 = s; }
     if (u1 > u0) { T t = u0; u0 = u1; u1 = t; int s = s0; s0 = s1; s1 = s; }
-    int b = c0 * g.stride[0] + c1 * g.stride[1] + c2;
-    int v1 = b + s0, v2 = v1 + s1, v3 = b + g.stride[0] + g.stride[1] + 1;
-    return ((T)1 - u0) * kap[b] + (u0 - u1) * kap[v1] + (u1 - u2) * kap[v2] + u2 * kap[v3];
+    const int v1 = b + s0, v2 = v1 + s1, v3 = b + g.stride[0] + g.stride[1] + 1;
+    const T kb = kload(kr, b, T()), k1 = kload(kr, v1, T()), k2 = kload(kr, v2, T()), k3 = kload(kr, v3, T());
+    return kb + u0 * (k1 - kb) + u1 * (k2 - k1) + u2 * (k3 - k2);
 }
 
-// tau along the segment P -> Q given in grid coordinates.
+// tau along the segment P -> Q given in grid coordinates, both in the closed
+// box.  The P1 kappa is linear between consecutive crossings of the six plane
+// families, so each piece contributes its length times kappa at its midpoint
+// (exact).  The next crossing time of family f advances by the constant
+// 1/|dF_f| per crossing; a crossing of family a (a < 3) moves the cell by one
+// along axis a, which updates its flat index and P's coordinates relative to
+// the cell corner.  Only the last crossing of a family can be taken a few
+// rounding units early (the segment ends on a vertex, that is on a plane of
+// every family); the piece that follows is of rounding length, and its
+// loads stay in bounds through the buffer resource.
 template <typename T>
 __device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3]) {
     const T D[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
     const T wx = D[0] * (T)g.h[0], wy = D[1] * (T)g.h[1], wz = D[2] * (T)g.h[2];
     const T len = sqrt(wx * wx + wy * wy + wz * wz);
     if (len == (T)0) return (T)0;
+    const rsrc_t kr = kappa_rsrc(g, kap);
     const T F0[6] = {P[0], P[1], P[2], P[0] - P[1], P[1] - P[2], P[0] - P[2]};
     const T dF[6] = {D[0], D[1], D[2], D[0] - D[1], D[1] - D[2], D[0] - D[2]};
-    T inv[6], m[6], st[6], tn[6];
+    T tn[6], dt[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         if (dF[f] != (T)0) {
-            inv[f] = (T)1 / dF[f];
-            st[f] = dF[f] > (T)0 ? (T)1 : (T)-1;
-            m[f] = dF[f] > (T)0 ? floor(F0[f]) + (T)1 : ceil(F0[f]) - (T)1;
-            tn[f] = (m[f] - F0[f]) * inv[f];
+            const T next = dF[f] > (T)0 ? floor(F0[f]) + (T)1 : ceil(F0[f]) - (T)1;
+            dt[f] = (T)1 / fabs(dF[f]);
+            tn[f] = (next - F0[f]) / dF[f];
         } else {
-            inv[f] = (T)0;
-            st[f] = (T)0;
-            m[f] = (T)0;
+            dt[f] = (T)0;
             tn[f] = (T)2;   // never before the end of the segment
         }
+    }
+    // cell of the first piece: along a, the one the segment enters from P
+    // (the top cell when the segment lies in the top plane of a)
+    int b = 0, db[3];
+    T w[3], ws[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int sa = D[a] > (T)0 ? 1 : (D[a] < (T)0 ? -1 : 0);
+        int ca = D[a] < (T)0 ? (int)ceil(P[a]) - 1 : (int)floor(P[a]);
+        ca = min(max(ca, 0), g.n[a] - 2);
+        b += ca * g.stride[a];
+        db[a] = sa * g.stride[a];
+        w[a] = P[a] - (T)ca;
+        ws[a] = (T)sa;
     }
     T tp = (T)0, acc = (T)0;
     // every step advances at least one family; the pieces number at most
     // sum_f |dF_f| + 7 <= 3 (|D0|+|D1|+|D2|) + 7
     const int cap = 3 * (g.n[0] + g.n[1] + g.n[2]) + 16;
     for (int it = 0; it < cap; ++it) {
-        T t = fmin(fmin(fmin(tn[0], tn[1]), fmin(tn[2], tn[3])), fmin(tn[4], tn[5]));
-        t = fmin(t, (T)1);
+        T t = fmin_finite(fmin_finite(fmin_finite(tn[0], tn[1]), fmin_finite(tn[2], tn[3])),
+                          fmin_finite(fmin_finite(tn[4], tn[5]), (T)1));
         if (t > tp) {
             const T tm = (T)0.5 * (tp + t);
-            acc += (t - tp) * kappa_grid(g, kap, P[0] + tm * D[0], P[1] + tm * D[1], P[2] + tm * D[2]);
+            acc += (t - tp) * kappa_in_cell(g, kr, b, w[0] + tm * D[0], w[1] + tm * D[1], w[2] + tm * D[2]);
         }
         if (t >= (T)1) break;
 #pragma unroll
-        for (int f = 0; f < 6; ++f)
+        for (int f = 0; f < 3; ++f)
             if (tn[f] <= t) {
-                m[f] += st[f];
-                tn[f] = (m[f] - F0[f]) * inv[f];
+                tn[f] += dt[f];
+                b += db[f];
+                w[f] -= ws[f];
             }
+#pragma unroll
+        for (int f = 3; f < 6; ++f)
+            if (tn[f] <= t) tn[f] += dt[f];
         tp = t;
     }
     return len * acc;
@@ -244,22 +295,25 @@ __device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
     int ii[3], jj[3];
     vtx_index(g, i, ii);
     vtx_index(g, j, jj);
+    const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
+    const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
+    // optical depths first: the star of j is loaded after the march, so its
+    // 27 values do not stay live through it
+    const T att = exp(-tau_segment(g, c.kappa, P, Q));
+    const T att_m = g.wall_axis >= 0 ? (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) : (T)0;
     T kn[27];
     int cellmask;
     load_star(c, jj, kn, cellmask);
     const T h2[3] = {(T)(g.h[0] * g.h[0]), (T)(g.h[1] * g.h[1]), (T)(g.h[2] * g.h[2])};
-    const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
-    const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
     const T dg[3] = {P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
-    T G = exp(-tau_segment(g, c.kappa, P, Q)) * vol_quad(c, kn, cellmask, dg, h2, cheb3(ii, jj) <= kNearCheb);
+    T G = att * vol_quad(c, kn, cellmask, dg, h2, cheb3(ii, jj) <= kNearCheb);
     if (g.wall_axis >= 0) {
         const int a = g.wall_axis;
         const int Ci = g.wall_side ? g.n[a] - 1 : 0;
         int mi[3] = {ii[0], ii[1], ii[2]};
         mi[a] = 2 * Ci - ii[a];
         const T dgm[3] = {(T)mi[0] - Q[0], (T)mi[1] - Q[1], (T)mi[2] - Q[2]};
-        G += (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) *
-             vol_quad(c, kn, cellmask, dgm, h2, cheb3(mi, jj) <= kNearCheb);
+        G += att_m * vol_quad(c, kn, cellmask, dgm, h2, cheb3(mi, jj) <= kNearCheb);
     }
     return G * (T)g.vol_scale;
 }

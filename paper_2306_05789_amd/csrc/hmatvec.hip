@@ -703,25 +703,26 @@ void phase_b_valu(int W, unsigned gb, const LeafWork *lw, const Seg *sg, const d
         k_phase_b<ST, MODE, A, NR, 8><<<gb, 512, 0, s>>>(lw, sg, x, ldx, xbs, t, ldt, y0, y, ldy, ybs, r0, nr);
 }
 
-// wb: wavefronts per phase B workgroup for up to 4 right-hand sides (half of
-// it for 16, whose accumulators are four times larger)
+// wb: wavefronts per phase B workgroup.  Right-hand sides go in groups of at
+// most 4: with 16 per launch the accumulators (4 rows x 16 columns per lane)
+// leave one wavefront per SIMD and the stream stalls, so four passes over the
+// matrix are faster than one.
 template <int ST, int MODE, typename A>
 void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double *y0, double *y, double *tb,
                   hipStream_t s, int wb) {
     double *part = tb + mp.ktot * (int64_t)nrhs;   // the workspace holds t, then the partials
     const int64_t ldp = std::max<int64_t>(mp.npart, 1);
     const int64_t xbs = (int64_t)nrhs * mp.n_src, ybs = (int64_t)nrhs * mp.n_tgt;
-    for (int r0 = 0; r0 < nrhs; r0 += 16) {
-        const int nr = std::min(16, nrhs - r0);
+    constexpr int kGroup = 4;
+    for (int r0 = 0; r0 < nrhs; r0 += kGroup) {
+        const int nr = std::min(kGroup, nrhs - r0);
         if (mp.n_vt) {
             const unsigned ga = (unsigned)((mp.n_vt + 3) / 4);
             const VtTask *vt = mp.vt.as<VtTask>();
             if (nr == 1)
                 k_phase_a<ST, MODE, A, 1><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, xbs, tb, mp.ktot, part, ldp, r0, nr);
-            else if (nr <= 4)
-                k_phase_a<ST, MODE, A, 4><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, xbs, tb, mp.ktot, part, ldp, r0, nr);
             else
-                k_phase_a<ST, MODE, A, 16><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, xbs, tb, mp.ktot, part, ldp, r0, nr);
+                k_phase_a<ST, MODE, A, 4><<<ga, 256, 0, s>>>(vt, mp.n_vt, x, mp.n_src, xbs, tb, mp.ktot, part, ldp, r0, nr);
             HIP_LAUNCH_CHECK();
             if (mp.n_red) {
                 k_phase_a_reduce<<<(unsigned)((mp.n_red + 3) / 4), 256, 0, s>>>(mp.red.as<VtReduce>(), mp.n_red, part,
@@ -734,11 +735,8 @@ void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double 
         const Seg *sg = mp.seg.as<Seg>();
         if (nr == 1)
             phase_b_valu<ST, MODE, A, 1>(wb, gb, lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt, ybs, r0, nr, s);
-        else if (nr <= 4)
-            phase_b_valu<ST, MODE, A, 4>(wb, gb, lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt, ybs, r0, nr, s);
         else
-            phase_b_valu<ST, MODE, A, 16>(std::max(2, wb / 2), gb, lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y,
-                                          mp.n_tgt, ybs, r0, nr, s);
+            phase_b_valu<ST, MODE, A, 4>(wb, gb, lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt, ybs, r0, nr, s);
         HIP_LAUNCH_CHECK();
     }
 }

@@ -34,8 +34,9 @@ def test_batched_matvec_equals_single_calls(small, precision):
     """Every band and right-hand side of the batched product equals the single-band,
     single right-hand-side product.  On the matrix cores (BF16 storage) every column
     is reduced in the same fixed order whatever shares the launch: bit for bit.  The
-    vector-ALU kernels (FP64, FP32) split a leaf's segments over 8 wavefronts for one
-    right-hand side and over 4 for 16, so the sums are regrouped: rounding level."""
+    vector-ALU kernels (FP64, FP32) take right-hand sides in groups of 4, with kernels
+    instantiated per group width that the compiler may contract differently: rounding
+    level."""
     wl, mesh = small
     G = _assemble(mesh, wl, rte.RTE_VOLUME, precision)
     nb, nr = wl.kappa.shape[0], 16
