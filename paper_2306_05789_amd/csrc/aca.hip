@@ -184,7 +184,7 @@ __global__ __launch_bounds__(1024) void k_aca_scan(AcaState<T> st) {
 
 // Step 1: residual rows of every active block, one lane per entry.
 template <typename T, int KIND>
-__global__ __launch_bounds__(256) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
+__global__ __launch_bounds__(256, 4) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_aca_pivot(AcaState<T> st) {
 
 // Step 3: residual columns of the pivoted blocks, one lane per entry.
 template <typename T, int KIND>
-__global__ __launch_bounds__(256) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
+__global__ __launch_bounds__(256, 4) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -268,11 +268,18 @@ __global__ __launch_bounds__(256) void k_aca_cols(EntryCtx<T> c, AcaState<T> st,
 
 // Steps 4-5, first part: scale v_k and form the partial dot products
 // (u_l.u_k), (v_l.v_k), l <= k, and the partial argmax of |u_k| over unused
-// rows, on one chunk of the concatenated (u_k, v_k) range of a block.
+// rows, on one chunk of the concatenated (u_k, v_k) range of a block.  The
+// chunk of (u_k, v_k) is staged in LDS (v_k scaled there and in memory).  For
+// l < k a group of P consecutive lanes owns rank index l: its lanes read
+// every P-th element of row l (contiguous across the group), and one
+// butterfly over the group ends the sum, for all groups of a wavefront at
+// once.  P is the largest power of two with 256 / P groups covering the k
+// indices (at most 64).  The squares of u_k and v_k (l = k) come from the
+// staging pass.
 template <typename T>
 __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
-    __shared__ T red_u[4][kAcaMaxRank + 1];
-    __shared__ T red_v[4][kAcaMaxRank + 1];
+    __shared__ T ck[kChunk];
+    __shared__ T sq[2][4];
     __shared__ T sa[4], ss[4];
     __shared__ int si[4];
     const int64_t c = blockIdx.x;
@@ -287,33 +294,54 @@ __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
     T *V = st.Vs + tk.voff;
     const unsigned *bits = st.used + st.ubase[b];
     const T inv = (T)1 / st.pivot[b];
-    T bu = (T)-1, busv = (T)0;
+    T bu = (T)-1, busv = (T)0, su = (T)0, sv = (T)0;
     int bi = INT_MAX;
     for (int e = e0 + tid; e < e1; e += 256) {
         if (e < m) {
             const T u = U[(int64_t)k * m + e];
+            ck[e - e0] = u;
+            su += u * u;
             if (!is_used(bits, e) && fabs(u) > bu) { bu = fabs(u); bi = e; busv = u; }
         } else {
-            V[(int64_t)k * n + (e - m)] *= inv;   // read back below by this lane only
+            T *vp = V + (int64_t)k * n + (e - m);
+            const T v = *vp * inv;
+            *vp = v;
+            ck[e - e0] = v;
+            sv += v * v;
         }
     }
-    for (int l = 0; l <= k; ++l) {
-        T pu = (T)0, pv = (T)0;
-        for (int e = e0 + tid; e < e1; e += 256) {
-            if (e < m) pu += U[(int64_t)l * m + e] * U[(int64_t)k * m + e];
-            else pv += V[(int64_t)l * n + (e - m)] * V[(int64_t)k * n + (e - m)];
-        }
-        pu = wave_sum(pu);
-        pv = wave_sum(pv);
-        if (lane == 0) { red_u[wid][l] = pu; red_v[wid][l] = pv; }
-    }
-    block_argmax(bu, bi, busv, sa, si, ss);   // includes the barrier for red_u / red_v
+    su = wave_sum(su);
+    sv = wave_sum(sv);
+    if (lane == 0) { sq[0][wid] = su; sq[1][wid] = sv; }
+    block_argmax(bu, bi, busv, sa, si, ss);   // its barriers publish ck and sq
     T *part = st.part + c * kPartStride;
-    for (int l = tid; l <= k; l += 256) {
-        part[l] = ((red_u[0][l] + red_u[1][l]) + red_u[2][l]) + red_u[3][l];
-        part[kAcaMaxRank + 1 + l] = ((red_v[0][l] + red_v[1][l]) + red_v[2][l]) + red_v[3][l];
+    if (k > 0) {
+        int P = 64;
+        while (P > 1 && 256 / P < k) P >>= 1;
+        const int G = 256 / P, g = tid / P, q = tid - g * P;
+        const int eu1 = min(e1, m), ev0 = max(e0, m);
+        for (int l0 = 0; l0 < k; l0 += G) {
+            const int l = l0 + g;
+            T pu = (T)0, pv = (T)0;
+            if (l < k) {
+                const T *ur = U + (int64_t)l * m;
+                const T *vr = V + (int64_t)l * n - m;
+                for (int e = e0 + q; e < eu1; e += P) pu += ur[e] * ck[e - e0];
+                for (int e = ev0 + q; e < e1; e += P) pv += vr[e] * ck[e - e0];
+            }
+            for (int o = P >> 1; o > 0; o >>= 1) {
+                pu += __shfl_xor(pu, o, 64);
+                pv += __shfl_xor(pv, o, 64);
+            }
+            if (l < k && q == 0) {
+                part[l] = pu;
+                part[kAcaMaxRank + 1 + l] = pv;
+            }
+        }
     }
     if (tid == 0) {
+        part[k] = ((sq[0][0] + sq[0][1]) + sq[0][2]) + sq[0][3];
+        part[kAcaMaxRank + 1 + k] = ((sq[1][0] + sq[1][1]) + sq[1][2]) + sq[1][3];
         st.pmax[2 * c] = bu;
         st.pmax[2 * c + 1] = busv;
         st.pidx[c] = bi;

@@ -18,7 +18,7 @@ __global__ __launch_bounds__(256) void k_entries(EntryCtx<T> c, int64_t n, const
 // dense block: the lanes of a wavefront march rays from a cluster of targets
 // to one source and write contiguous rows of the leaf-sliced storage.
 template <typename T, int KIND, bool SPLIT>
-__global__ __launch_bounds__(256) void k_dense_fill(EntryCtx<T> c, const FillTask *__restrict__ tasks,
+__global__ __launch_bounds__(256, 3) void k_dense_fill(EntryCtx<T> c, const FillTask *__restrict__ tasks,
                                                     const int64_t *__restrict__ tgt_nat,
                                                     const int64_t *__restrict__ src_nat, SliceMap sm) {
     const FillTask tk = tasks[blockIdx.x];

@@ -111,18 +111,25 @@ __device__ __forceinline__ float kload(rsrc_t r, int idx, float) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
 }
 
-// P1 (Freudenthal) interpolation of kappa in the cell with flat base index b
-// at local coordinates (u0, u1, u2) in [0, 1]^3 (grid units).
+// The four vertex values of the Kuhn tetrahedron of a point in the cell with
+// flat base index b, at local coordinates (u0, u1, u2) in [0, 1]^3 (grid
+// units), and the coordinates sorted decreasingly: kappa there is the P1
+// (Freudenthal) interpolant kb + u0 (k1 - kb) + u1 (k2 - k1) + u2 (k3 - k2).
 template <typename T>
-__device__ __forceinline__ T kappa_in_cell(const GridDev &g, rsrc_t kr, int b, T u0, T u1, T u2) {
+struct TetSample {
+    T kb, k1, k2, k3, u0, u1, u2;
+    __device__ __forceinline__ T value() const { return kb + u0 * (k1 - kb) + u1 * (k2 - k1) + u2 * (k3 - k2); }
+};
+
+template <typename T>
+__device__ __forceinline__ TetSample<T> tet_sample(const GridDev &g, rsrc_t kr, int b, T u0, T u1, T u2) {
     int s0 = g.stride[0], s1 = g.stride[1], s2 = 1;
     // order the local coordinates decreasingly, carrying the axis strides
     if (u1 > u0) { T t = u0; u0 = u1; u1 = t; int s = s0; s0 = s1; s1 = s; }
     if (u2 > u1) { T t = u1; u1 = u2; u2 = t; int s = s1; s1 = s2; s2 = s; }
     if (u1 > u0) { T t = u0; u0 = u1; u1 = t; int s = s0; s0 = s1; s1 = s; }
     const int v1 = b + s0, v2 = v1 + s1, v3 = b + g.stride[0] + g.stride[1] + 1;
-    const T kb = kload(kr, b, T()), k1 = kload(kr, v1, T()), k2 = kload(kr, v2, T()), k3 = kload(kr, v3, T());
-    return kb + u0 * (k1 - kb) + u1 * (k2 - k1) + u2 * (k3 - k2);
+    return {kload(kr, b, T()), kload(kr, v1, T()), kload(kr, v2, T()), kload(kr, v3, T()), u0, u1, u2};
 }
 
 // tau along the segment P -> Q given in grid coordinates, both in the closed
@@ -134,7 +141,10 @@ __device__ __forceinline__ T kappa_in_cell(const GridDev &g, rsrc_t kr, int b, T
 // the cell corner.  Only the last crossing of a family can be taken a few
 // rounding units early (the segment ends on a vertex, that is on a plane of
 // every family); the piece that follows is of rounding length, and its
-// loads stay in bounds through the buffer resource.
+// loads stay in bounds through the buffer resource.  The loop is software
+// pipelined: the kappa values of the next piece are loaded while the current
+// one is added (a piece of zero length, where two families cross together,
+// adds zero).
 template <typename T>
 __device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3]) {
     const T D[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
@@ -170,18 +180,19 @@ __device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[
         w[a] = P[a] - (T)ca;
         ws[a] = (T)sa;
     }
-    T tp = (T)0, acc = (T)0;
+    auto next_end = [&]() {
+        return fmin_finite(fmin_finite(fmin_finite(tn[0], tn[1]), fmin_finite(tn[2], tn[3])),
+                           fmin_finite(fmin_finite(tn[4], tn[5]), (T)1));
+    };
+    T tp = (T)0, t = next_end(), acc = (T)0;
+    T tm = (T)0.5 * t;
+    TetSample<T> cur = tet_sample(g, kr, b, w[0] + tm * D[0], w[1] + tm * D[1], w[2] + tm * D[2]);
     // every step advances at least one family; the pieces number at most
     // sum_f |dF_f| + 7 <= 3 (|D0|+|D1|+|D2|) + 7
     const int cap = 3 * (g.n[0] + g.n[1] + g.n[2]) + 16;
     for (int it = 0; it < cap; ++it) {
-        T t = fmin_finite(fmin_finite(fmin_finite(tn[0], tn[1]), fmin_finite(tn[2], tn[3])),
-                          fmin_finite(fmin_finite(tn[4], tn[5]), (T)1));
-        if (t > tp) {
-            const T tm = (T)0.5 * (tp + t);
-            acc += (t - tp) * kappa_in_cell(g, kr, b, w[0] + tm * D[0], w[1] + tm * D[1], w[2] + tm * D[2]);
-        }
-        if (t >= (T)1) break;
+        const bool last = t >= (T)1;
+        // families crossed at t move on; the cell follows the axis families
 #pragma unroll
         for (int f = 0; f < 3; ++f)
             if (tn[f] <= t) {
@@ -192,7 +203,14 @@ __device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[
 #pragma unroll
         for (int f = 3; f < 6; ++f)
             if (tn[f] <= t) tn[f] += dt[f];
+        const T tq = next_end();
+        tm = (T)0.5 * (t + tq);
+        const TetSample<T> nxt = tet_sample(g, kr, b, w[0] + tm * D[0], w[1] + tm * D[1], w[2] + tm * D[2]);
+        acc += (t - tp) * cur.value();
+        if (last) break;
+        cur = nxt;
         tp = t;
+        t = tq;
     }
     return len * acc;
 }
