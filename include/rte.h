@@ -56,7 +56,8 @@ typedef struct rte_hmat *rte_hmat_t;
 /* ------------------------------------------------------------------ mesh
  * Section "FEM discretization": a tetrahedral mesh of the domain and a
  * triangular mesh of its boundary.  Here the domain is the box [lo,hi] with
- * n[a] >= 2 vertices per axis; each cell is split into the six Kuhn
+ * n[a] >= 2 vertices per axis (fewer than 2^28 in all, else
+ * RTE_E_INVALID_ARG); each cell is split into the six Kuhn
  * tetrahedra that share its (0,0,0)-(1,1,1) diagonal, and each boundary square
  * into the two triangles of its low-to-high diagonal.
  * reflect_axis in {-1,0,1,2}: -1 = no reflective wall; else the box face

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(1024) void k_aca_scan(AcaState<T> st) {
 
 // Step 1: residual rows of every active block, one lane per entry.
 template <typename T, int KIND>
-__global__ __launch_bounds__(256, 4) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_aca_pivot(AcaState<T> st) {
 
 // Step 3: residual columns of the pivoted blocks, one lane per entry.
 template <typename T, int KIND>
-__global__ __launch_bounds__(256, 4) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;

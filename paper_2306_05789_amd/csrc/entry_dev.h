@@ -121,15 +121,22 @@ struct TetSample {
     __device__ __forceinline__ T value() const { return kb + u0 * (k1 - kb) + u1 * (k2 - k1) + u2 * (k3 - k2); }
 };
 
+// The Kuhn tetrahedron of the point is given by the decreasing order of its
+// local coordinates: from the base corner it adds the axis of the largest
+// coordinate, then that of the middle one.  Ties pick the lowest axis as the
+// largest and the highest axis as the smallest, so the two never coincide
+// (the value is continuous across the faces the ties lie on).
 template <typename T>
 __device__ __forceinline__ TetSample<T> tet_sample(const GridDev &g, rsrc_t kr, int b, T u0, T u1, T u2) {
-    int s0 = g.stride[0], s1 = g.stride[1], s2 = 1;
-    // order the local coordinates decreasingly, carrying the axis strides
-    if (u1 > u0) { T t = u0; u0 = u1; u1 = t; int s = s0; s0 = s1; s1 = s; }
-    if (u2 > u1) { T t = u1; u1 = u2; u2 = t; int s = s1; s1 = s2; s2 = s; }
-    if (u1 > u0) { T t = u0; u0 = u1; u1 = t; int s = s0; s0 = s1; s1 = s; }
-    const int v1 = b + s0, v2 = v1 + s1, v3 = b + g.stride[0] + g.stride[1] + 1;
-    return {kload(kr, b, T()), kload(kr, v1, T()), kload(kr, v2, T()), kload(kr, v3, T()), u0, u1, u2};
+    const int S0 = g.stride[0], S1 = g.stride[1];
+    const bool c01 = u0 >= u1, c02 = u0 >= u2, c12 = u1 >= u2;
+    const int smax = (c01 && c02) ? S0 : (c12 ? S1 : 1);
+    const int smin = (c02 && c12) ? 1 : (c01 ? S1 : S0);
+    const T hi = fmax(fmax(u0, u1), u2), lo = fmin(fmin(u0, u1), u2);
+    const T mid = fmax(fmin(u0, u1), fmin(fmax(u0, u1), u2));
+    const int v3 = b + S0 + S1 + 1;
+    const int v1 = b + smax, v2 = v3 - smin;
+    return {kload(kr, b, T()), kload(kr, v1, T()), kload(kr, v2, T()), kload(kr, v3, T()), hi, mid, lo};
 }
 
 // tau along the segment P -> Q given in grid coordinates, both in the closed
@@ -144,7 +151,7 @@ __device__ __forceinline__ TetSample<T> tet_sample(const GridDev &g, rsrc_t kr, 
 // loads stay in bounds through the buffer resource.  The loop is software
 // pipelined: the kappa values of the next piece are loaded while the current
 // one is added (a piece of zero length, where two families cross together,
-// adds zero).
+// adds zero; after the last piece one more sample is loaded and unused).
 template <typename T>
 __device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3]) {
     const T D[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
@@ -185,14 +192,11 @@ __device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[
                            fmin_finite(fmin_finite(tn[4], tn[5]), (T)1));
     };
     T tp = (T)0, t = next_end(), acc = (T)0;
-    T tm = (T)0.5 * t;
-    TetSample<T> cur = tet_sample(g, kr, b, w[0] + tm * D[0], w[1] + tm * D[1], w[2] + tm * D[2]);
-    // every step advances at least one family; the pieces number at most
-    // sum_f |dF_f| + 7 <= 3 (|D0|+|D1|+|D2|) + 7
-    const int cap = 3 * (g.n[0] + g.n[1] + g.n[2]) + 16;
-    for (int it = 0; it < cap; ++it) {
+    // one piece: the families crossed at t move on (the cell follows the axis
+    // families), the next piece's tetrahedron is sampled, this piece is added;
+    // true once the piece ends the segment
+    auto piece = [&](const TetSample<T> &cur, TetSample<T> &nxt) {
         const bool last = t >= (T)1;
-        // families crossed at t move on; the cell follows the axis families
 #pragma unroll
         for (int f = 0; f < 3; ++f)
             if (tn[f] <= t) {
@@ -204,13 +208,22 @@ __device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[
         for (int f = 3; f < 6; ++f)
             if (tn[f] <= t) tn[f] += dt[f];
         const T tq = next_end();
-        tm = (T)0.5 * (t + tq);
-        const TetSample<T> nxt = tet_sample(g, kr, b, w[0] + tm * D[0], w[1] + tm * D[1], w[2] + tm * D[2]);
+        const T tm = (T)0.5 * (t + tq);
+        nxt = tet_sample(g, kr, b, w[0] + tm * D[0], w[1] + tm * D[1], w[2] + tm * D[2]);
         acc += (t - tp) * cur.value();
-        if (last) break;
-        cur = nxt;
         tp = t;
         t = tq;
+        return last;
+    };
+    const T tm0 = (T)0.5 * t;
+    // two named samples in turn, so that no copy closes the loop
+    TetSample<T> sa = tet_sample(g, kr, b, w[0] + tm0 * D[0], w[1] + tm0 * D[1], w[2] + tm0 * D[2]), sb;
+    // every step advances at least one family; the pieces number at most
+    // sum_f |dF_f| + 7 <= 3 (|D0|+|D1|+|D2|) + 7
+    const int cap = 3 * (g.n[0] + g.n[1] + g.n[2]) + 16;
+    for (int it = 0; it < cap; it += 2) {
+        if (piece(sa, sb)) break;
+        if (piece(sb, sa)) break;
     }
     return len * acc;
 }
@@ -240,11 +253,13 @@ __device__ __forceinline__ int cheb3(const int a[3], const int b[3]) {
     return max(max(abs(a[0] - b[0]), abs(a[1] - b[1])), abs(a[2] - b[2]));
 }
 
+// grid index of vertex v (fewer than 2^28 vertices: 32-bit unsigned division)
 __device__ __forceinline__ void vtx_index(const GridDev &g, int64_t v, int idx[3]) {
-    idx[0] = (int)(v / g.stride[0]);
-    int64_t r = v - (int64_t)idx[0] * g.stride[0];
-    idx[1] = (int)(r / g.stride[1]);
-    idx[2] = (int)(r - (int64_t)idx[1] * g.stride[1]);
+    const unsigned u = (unsigned)v, s0 = (unsigned)g.stride[0], s1 = (unsigned)g.stride[1];
+    const unsigned i0 = u / s0, r = u - i0 * s0, i1 = r / s1;
+    idx[0] = (int)i0;
+    idx[1] = (int)i1;
+    idx[2] = (int)(r - i1 * s1);
 }
 
 // ---------------------------------------------------------------- volume quadrature

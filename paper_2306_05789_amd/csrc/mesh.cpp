@@ -191,6 +191,8 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
         RTE_REQUIRE(std::isfinite(d.lo[a]) && std::isfinite(d.hi[a]) && d.lo[a] < d.hi[a],
                     "mesh: need finite lo < hi on every axis");
     }
+    // the device kernels index vertices (and kappa bytes) with 32-bit integers
+    RTE_REQUIRE((int64_t)d.n[0] * d.n[1] * d.n[2] < ((int64_t)1 << 28), "mesh: at most 2^28 vertices");
     RTE_REQUIRE(d.reflect_axis >= -1 && d.reflect_axis <= 2, "mesh: reflect_axis must be -1, 0, 1 or 2");
     RTE_REQUIRE(d.reflect_side == 0 || d.reflect_side == 1, "mesh: reflect_side must be 0 or 1");
     RTE_REQUIRE(d.reflect_axis < 0 || (std::isfinite(d.R) && d.R >= 0.0 && d.R <= 1.0),
