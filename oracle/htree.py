@@ -15,6 +15,8 @@ reached at the leaves is kept dense.  Readings used here:
     gap between the two bounding boxes (0 when they touch or overlap), so
     touching blocks are never admissible; the test is evaluated as
     R^2 < eta^2 * dist^2 in FP64;
+  - a block whose storage break-even rank floor(m n / (m + n)) is below
+    MIN_LOW_RANK is not admissible (it is split or kept dense);
   - if exactly one side of a non-admissible block is a leaf, the other side
     is split; if both are leaves the block is dense.
 """
@@ -63,14 +65,24 @@ def cluster_tree(points: np.ndarray, leaf_size: int):
     return perm, root
 
 
-def admissible(t: Cluster, s: Cluster, eta: float) -> bool:
-    ht = 0.5 * (t.bmax - t.bmin)
-    hs = 0.5 * (s.bmax - s.bmin)
+MIN_LOW_RANK = 24
+
+
+def _separated(tmin, tmax, smin, smax, eta: float) -> bool:
+    ht = 0.5 * (tmax - tmin)
+    hs = 0.5 * (smax - smin)
     rt2 = ht[0] * ht[0] + ht[1] * ht[1] + ht[2] * ht[2]
     rs2 = hs[0] * hs[0] + hs[1] * hs[1] + hs[2] * hs[2]
-    gap = np.maximum(0.0, np.maximum(s.bmin - t.bmax, t.bmin - s.bmax))
+    gap = np.maximum(0.0, np.maximum(smin - tmax, tmin - smax))
     d2 = gap[0] * gap[0] + gap[1] * gap[1] + gap[2] * gap[2]
     return max(rt2, rs2) < eta * eta * d2
+
+
+def admissible(t: Cluster, s: Cluster, eta: float) -> bool:
+    m, n = t.size, s.size
+    if m * n // (m + n) < MIN_LOW_RANK:
+        return False
+    return _separated(t.bmin, t.bmax, s.bmin, s.bmax, eta)
 
 
 def block_tree(troot: Cluster, sroot: Cluster, eta: float):

@@ -48,14 +48,14 @@ struct AcaState {
     int64_t *tot;               // [0] row entries, [1] active blocks, [2] column entries, [3] pivoted blocks,
                                 // [4] update chunks
     T *Us, *Vs;                 // U^T [kcap][m] and V^T [kcap][n] per block
-    T *part;                    // per chunk: [2][kAcaMaxRank + 1] partial dot products
+    T *part;                    // per chunk: [2][half] partial dot products (half > every kcap)
+    int half;                   // partials per kind in a chunk
     T *pmax;                    // per chunk: |u| max and its signed value
     int *pidx;                  // per chunk: row of the max
 };
 
 // elements of the concatenated (u_k, v_k) range of a block handled by one update chunk
 constexpr int kChunk = 1024;
-constexpr int kPartStride = 2 * (kAcaMaxRank + 1);
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
     sv = wave_sum(sv);
     if (lane == 0) { sq[0][wid] = su; sq[1][wid] = sv; }
     block_argmax(bu, bi, busv, sa, si, ss);   // its barriers publish ck and sq
-    T *part = st.part + c * kPartStride;
+    T *part = st.part + c * 2 * (int64_t)st.half;
     if (k > 0) {
         int P = 64;
         while (P > 1 && 256 / P < k) P >>= 1;
@@ -335,13 +335,13 @@ __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
             }
             if (l < k && q == 0) {
                 part[l] = pu;
-                part[kAcaMaxRank + 1 + l] = pv;
+                part[st.half + l] = pv;
             }
         }
     }
     if (tid == 0) {
         part[k] = ((sq[0][0] + sq[0][1]) + sq[0][2]) + sq[0][3];
-        part[kAcaMaxRank + 1 + k] = ((sq[1][0] + sq[1][1]) + sq[1][2]) + sq[1][3];
+        part[st.half + k] = ((sq[1][0] + sq[1][1]) + sq[1][2]) + sq[1][3];
         st.pmax[2 * c] = bu;
         st.pmax[2 * c + 1] = busv;
         st.pidx[c] = bi;
@@ -362,8 +362,8 @@ __global__ __launch_bounds__(64) void k_aca_finish(AcaState<T> st, T eps) {
     for (int l = lane; l <= k; l += 64) {
         T su = (T)0, sv = (T)0;
         for (int64_t c = c0; c < c1; ++c) {
-            su += st.part[c * kPartStride + l];
-            sv += st.part[c * kPartStride + kAcaMaxRank + 1 + l];
+            su += st.part[c * 2 * st.half + l];
+            sv += st.part[c * 2 * st.half + st.half + l];
         }
         if (l < k) cross += su * sv;
         else { u2 = su; v2 = sv; }
@@ -542,11 +542,16 @@ void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Bl
     if (split) B.bufs.push_back(std::move(lo));
 }
 
+// One batch of blocks through the step-synchronous ACA.  A block that stops
+// at its cap goes to `retry` when its storage break-even rank exceeds the cap
+// (the next pass runs it again with a larger one), else to `fallback` (dense).
 template <typename T>
 void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &tasks, const std::vector<size_t> &ids,
-               int64_t uo, int64_t vo, std::vector<Block> &fallback, hipStream_t s) {
+               int64_t uo, int64_t vo, std::vector<Block> &fallback, std::vector<size_t> &retry, hipStream_t s) {
     const Plan &P = *H.plan;
     const int nb = (int)tasks.size();
+    int kmax = 1;
+    for (auto &t : tasks) kmax = std::max(kmax, t.kcap);
     std::vector<int64_t> ubase(nb);
     int64_t words = 0;
     for (int b = 0; b < nb; ++b) {
@@ -560,7 +565,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     DevBuf ents(sizeof(int64_t) * (size_t)nb);
     DevBuf ints(sizeof(int) * (size_t)nb * 7), reals(sizeof(T) * (size_t)nb * 2),
         used(sizeof(unsigned) * (size_t)words), offs(sizeof(int64_t) * (size_t)(nb + 1) * 3),
-        tot(sizeof(int64_t) * 5), part(sizeof(T) * (size_t)max_chunks * kPartStride),
+        tot(sizeof(int64_t) * 5), part(sizeof(T) * (size_t)max_chunks * 2 * (size_t)(kmax + 1)),
         pmax(sizeof(T) * (size_t)max_chunks * 2), pidx(sizeof(int) * (size_t)max_chunks);
     AcaState<T> st;
     st.task = dt.as<AcaTask>();
@@ -583,6 +588,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     st.chunkoff = offs.as<int64_t>() + 2 * (nb + 1);
     st.tot = tot.as<int64_t>();
     st.part = part.as<T>();
+    st.half = kmax + 1;
     st.pmax = pmax.as<T>();
     st.pidx = pidx.as<int>();
     st.Us = Us.as<T>();
@@ -689,7 +695,9 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     for (int t = 0; t < nb; ++t) {
         const size_t b = ids[t];
         if (rk[t] <= 0) {
-            fallback.push_back(P.lowrank[b]);
+            const int64_t m = tasks[t].m, n = tasks[t].n;
+            if (m * n / (m + n) > tasks[t].kcap && tasks[t].kcap < kAcaRetryRank) retry.push_back(b);
+            else fallback.push_back(P.lowrank[b]);
             continue;
         }
         const int64_t nu = round8(stored_u(H, tasks[t].t0, tasks[t].t0 + tasks[t].m, rk[t])),
@@ -734,30 +742,43 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
     B.Vlo.assign(nlr, nullptr);
     std::vector<Block> fallback;
     const size_t scratch_limit = (size_t)8 << 30;   // bytes of U/V scratch per batch
-    std::vector<AcaTask> tasks;
-    std::vector<size_t> ids;
-    int64_t uo = 0, vo = 0;
-    for (size_t b = 0; b < nlr; ++b) {
-        const Block &bl = P.lowrank[b];
-        const int32_t m = (int32_t)(bl.t1 - bl.t0), n = (int32_t)(bl.s1 - bl.s0);
-        const int32_t kcap = (int32_t)std::min<int64_t>((int64_t)m * n / (m + n), kAcaMaxRank);
-        if (kcap < 1) {
-            fallback.push_back(bl);
-            continue;
+    // First pass: every admissible block with the rank cap kAcaMaxRank.  Second
+    // pass: the blocks that reached it while their break-even rank is larger
+    // (large, barely admissible blocks, common with a reflective wall, whose
+    // two kernel terms add their ranks), again from the start with the cap
+    // kAcaRetryRank; only what still reaches its cap is stored dense.
+    std::vector<size_t> todo(nlr), retry;
+    for (size_t b = 0; b < nlr; ++b) todo[b] = b;
+    for (int pass = 0; pass < 2 && !todo.empty(); ++pass) {
+        const int64_t cap = pass == 0 ? kAcaMaxRank : kAcaRetryRank;
+        std::vector<AcaTask> tasks;
+        std::vector<size_t> ids;
+        int64_t uo = 0, vo = 0;
+        for (size_t b : todo) {
+            const Block &bl = P.lowrank[b];
+            const int32_t m = (int32_t)(bl.t1 - bl.t0), n = (int32_t)(bl.s1 - bl.s0);
+            const int32_t kcap = (int32_t)std::min<int64_t>((int64_t)m * n / (m + n), cap);
+            if (kcap < 1) {
+                fallback.push_back(bl);
+                continue;
+            }
+            const int64_t need = (int64_t)kcap * (m + n);
+            if (!tasks.empty() && (size_t)(uo + vo + need) * sizeof(T) > scratch_limit) {
+                aca_batch<T>(H, B, kap, tasks, ids, uo, vo, fallback, retry, s);
+                tasks.clear();
+                ids.clear();
+                uo = vo = 0;
+            }
+            tasks.push_back({bl.t0, bl.s0, m, n, kcap, 0, uo, vo});
+            ids.push_back(b);
+            uo += (int64_t)kcap * m;
+            vo += (int64_t)kcap * n;
         }
-        const int64_t need = (int64_t)kcap * (m + n);
-        if (!tasks.empty() && (size_t)(uo + vo + need) * sizeof(T) > scratch_limit) {
-            aca_batch<T>(H, B, kap, tasks, ids, uo, vo, fallback, s);
-            tasks.clear();
-            ids.clear();
-            uo = vo = 0;
-        }
-        tasks.push_back({bl.t0, bl.s0, m, n, kcap, 0, uo, vo});
-        ids.push_back(b);
-        uo += (int64_t)kcap * m;
-        vo += (int64_t)kcap * n;
+        if (!tasks.empty()) aca_batch<T>(H, B, kap, tasks, ids, uo, vo, fallback, retry, s);
+        todo.swap(retry);
+        retry.clear();
     }
-    if (!tasks.empty()) aca_batch<T>(H, B, kap, tasks, ids, uo, vo, fallback, s);
+    for (size_t b : todo) fallback.push_back(P.lowrank[b]);
     fill_dense_blocks<T>(H, B, kap, fallback, s);
 }
 

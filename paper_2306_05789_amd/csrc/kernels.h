@@ -17,7 +17,8 @@ __host__ __device__ __forceinline__ uint16_t f2bf(float x) {
 __host__ __device__ __forceinline__ float bf2f(uint16_t h) {
     return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
-constexpr int kAcaMaxRank = 192;   // rank cap of one ACA block before dense fallback
+constexpr int kAcaMaxRank = 192;     // rank cap of an ACA block in the first pass
+constexpr int kAcaRetryRank = 1024;  // cap of the second pass (blocks whose break-even rank is larger)
 
 __host__ __device__ constexpr int64_t pad4(int64_t k) { return (k + 3) & ~(int64_t)3; }
 __host__ __device__ constexpr int64_t pad8(int64_t k) { return (k + 7) & ~(int64_t)7; }
@@ -68,7 +69,7 @@ struct FillTask {
 struct AcaTask {
     int64_t t0, s0;
     int32_t m, n;
-    int32_t kcap;     // rank cap (<= min(m n / (m + n), kAcaMaxRank))
+    int32_t kcap;     // rank cap (<= min(m n / (m + n), the pass's cap))
     int32_t pad;
     int64_t uoff, voff;   // scratch offsets (elements) of U^T [kcap][m] and V^T [kcap][n]
 };

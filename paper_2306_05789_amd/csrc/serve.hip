@@ -193,7 +193,7 @@ struct SrvMesh {
     DevBuf tgt_nat;        // volume cluster position -> vertex
     DevBuf src_pos;        // surface cluster position -> position in the caller's wall vector
     bool have_order = false;
-    int64_t est_bytes = 0;   // operator bytes of one level (bound, then the largest seen)
+    int64_t est_bytes = 0;   // operator bytes of one level (estimate, then the largest seen)
 };
 
 struct SrvReq {
@@ -267,8 +267,10 @@ struct Server {
         return o;
     }
 
-    // upper bound of one level's operator bytes from the plans (no assembly):
-    // dense leaves in full, admissible blocks at their rank cap or dense
+    // estimate of one level's operator bytes from the plans (no assembly):
+    // dense leaves in full, admissible blocks at the first pass's rank cap
+    // (a block stored dense after its ACA can exceed it; the largest level
+    // assembled so far replaces the estimate)
     int64_t bound_bytes(const Mesh &m) const {
         const int64_t esz = mixed() ? 4 : 8;
         int64_t e = 0;

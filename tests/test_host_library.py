@@ -41,16 +41,20 @@ def _oracle_plan(n, lo, hi, kind, emit, leaf, eta, dense=False):
     return tperm, snat, d, l
 
 
-@pytest.mark.parametrize("n,hi,kind,emit,leaf", [
-    ((11, 11, 11), (1, 1, 1), rte.RTE_VOLUME, 1, 64),
-    ((21, 21, 21), (1, 1, 1), rte.RTE_VOLUME, 1, 64),
-    ((33, 17, 17), (2, 1, 1), rte.RTE_VOLUME, 1, 64),
-    ((17, 13, 9), (1.3, 1, 0.7), rte.RTE_VOLUME, 1, 32),
-    ((21, 21, 21), (1, 1, 1), rte.RTE_SURFACE, 63, 64),
-    ((33, 17, 17), (2, 1, 1), rte.RTE_SURFACE, 1, 64),
+@pytest.mark.parametrize("n,hi,kind,emit,leaf,wall", [
+    ((11, 11, 11), (1, 1, 1), rte.RTE_VOLUME, 1, 64, None),
+    ((21, 21, 21), (1, 1, 1), rte.RTE_VOLUME, 1, 64, None),
+    ((33, 17, 17), (2, 1, 1), rte.RTE_VOLUME, 1, 64, None),
+    ((17, 13, 9), (1.3, 1, 0.7), rte.RTE_VOLUME, 1, 32, None),
+    ((21, 21, 21), (1, 1, 1), rte.RTE_SURFACE, 63, 64, None),
+    ((33, 17, 17), (2, 1, 1), rte.RTE_SURFACE, 1, 64, None),
+    ((33, 17, 17), (2, 1, 1), rte.RTE_VOLUME, 1, 64, (2, 0)),
+    ((17, 13, 9), (1.3, 1, 0.7), rte.RTE_VOLUME, 1, 32, (1, 1)),
+    ((33, 17, 17), (2, 1, 1), rte.RTE_SURFACE, 1, 64, (2, 0)),
 ])
-def test_host_trees_match_oracle_exactly(n, hi, kind, emit, leaf):
-    mesh = rte.rte_mesh_create(n, (0, 0, 0), hi, emit_faces=emit)
+def test_host_trees_match_oracle_exactly(n, hi, kind, emit, leaf, wall):
+    kw = {} if wall is None else dict(reflect_axis=wall[0], reflect_side=wall[1], R=0.5)
+    mesh = rte.rte_mesh_create(n, (0, 0, 0), hi, emit_faces=emit, **kw)
     plan = rte.rte_plan_create(mesh, rte.hmat_opts(kind=kind, leaf_size=leaf, eta=2.0))
     tp, sp, blocks = rte.rte_plan_export(plan)
     rte.rte_plan_destroy(plan)

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle.core import Grid
-from oracle.htree import admissible, block_tree, cluster_tree, leaves
+from oracle.htree import MIN_LOW_RANK, admissible, block_tree, cluster_tree, leaves
 
 
 @pytest.mark.parametrize("n,leaf", [((9, 9, 9), 32), ((13, 7, 7), 64), ((11, 11, 11), 64)])
@@ -63,3 +63,19 @@ def test_split_rule_midpoint_longest_axis_lower_child_takes_the_plane():
     assert lo.size == 18 and hi.size == 12
     # within a child the parent's (natural) order is kept
     assert np.all(np.diff(perm[lo.start:lo.stop]) > 0)
+
+
+def test_low_rank_blocks_pay_for_their_rank():
+    """Every compressed block can hold a rank of at least MIN_LOW_RANK below its
+    storage break-even floor(m n / (m + n)); smaller admissible blocks are split
+    or kept dense, and the partition still covers the matrix once."""
+    g = Grid((13, 13, 13))
+    pts = g.positions()
+    perm, root = cluster_tree(pts, 32)
+    dense, low = block_tree(root, root, 2.0)
+    assert low and all((t1 - t0) * (s1 - s0) // ((t1 - t0) + (s1 - s0)) >= MIN_LOW_RANK for t0, t1, s0, s1 in low)
+    cover = np.zeros((g.N, g.N), dtype=np.int32)
+    for t0, t1, s0, s1 in dense + low:
+        cover[t0:t1, s0:s1] += 1
+    assert np.all(cover == 1)
+
