@@ -326,7 +326,9 @@ __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
             if (l < k) {
                 const T *ur = U + (int64_t)l * m;
                 const T *vr = V + (int64_t)l * n - m;
+#pragma unroll 8
                 for (int e = e0 + q; e < eu1; e += P) pu += ur[e] * ck[e - e0];
+#pragma unroll 8
                 for (int e = ev0 + q; e < e1; e += P) pv += vr[e] * ck[e - e0];
             }
             for (int o = P >> 1; o > 0; o >>= 1) {

@@ -34,6 +34,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <condition_variable>
 #include <map>
 #include <mutex>
@@ -228,7 +229,8 @@ struct Server {
     std::vector<double> nu, w;   // catalogue
     hipStream_t user = nullptr;  // the caller's stream (inputs are ordered after it)
     hipStream_t s = nullptr;     // sweeps (the server's own, non-blocking, default priority)
-    hipStream_t as = nullptr;    // assembly (the assembler thread's)
+    hipStream_t as = nullptr;    // assembly (the assembler thread's): the volume operator
+    hipStream_t as2 = nullptr;   // assembly: the boundary-source operator, concurrently
     int device = 0;
     std::vector<std::unique_ptr<SrvMesh>> meshes;
     std::vector<std::unique_ptr<SrvOp>> ops;   // resident operators (main thread only)
@@ -314,8 +316,33 @@ struct Server {
         auto op = std::make_unique<SrvOp>();
         op->mesh = mi;
         op->level = level;
-        op->G = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_VOLUME)), 1, kap.as<double>(), as);
-        op->S = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_SURFACE)), 1, kap.as<double>(), as);
+        // G and S are independent: S is assembled by a second thread on its own
+        // stream (ordered after the scaling), G on this one
+        hipEvent_t ready;
+        HIP_CHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(ready, as));
+        HIP_CHECK(hipStreamWaitEvent(as2, ready, 0));
+        std::unique_ptr<rte_hmat> Sop;
+        std::exception_ptr serr;
+        std::thread ts([&] {
+            try {
+                HIP_CHECK(hipSetDevice(device));
+                Sop = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_SURFACE)), 1, kap.as<double>(), as2);
+            } catch (...) {
+                serr = std::current_exception();
+            }
+        });
+        std::exception_ptr gerr;
+        try {
+            op->G = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_VOLUME)), 1, kap.as<double>(), as);
+        } catch (...) {
+            gerr = std::current_exception();
+        }
+        ts.join();
+        (void)hipEventDestroy(ready);
+        if (gerr) std::rethrow_exception(gerr);
+        if (serr) std::rethrow_exception(serr);
+        op->S = std::move(Sop);
         op->bytes = op->G->h.stats.bytes + op->S->h.stats.bytes;
         if (!M.have_order) {
             M.tgt_nat.alloc(sizeof(int64_t) * (size_t)M.mesh.N);
@@ -734,6 +761,7 @@ struct Server {
         built.clear();
         if (s) (void)hipStreamDestroy(s);
         if (as) (void)hipStreamDestroy(as);
+        if (as2) (void)hipStreamDestroy(as2);
     }
 };
 
@@ -751,6 +779,7 @@ Server *server_create(const rte_server_desc_t &d, hipStream_t s) {
     HIP_CHECK(hipGetDevice(&S->device));
     HIP_CHECK(hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking));
     HIP_CHECK(hipStreamCreateWithFlags(&S->as, hipStreamNonBlocking));
+    HIP_CHECK(hipStreamCreateWithFlags(&S->as2, hipStreamNonBlocking));
     for (int b = 0; b < d.n_catalogue; ++b) {
         RTE_REQUIRE(std::isfinite(d.nu[b]) && d.nu[b] > 0 && (b == 0 || d.nu[b] > d.nu[b - 1]),
                     "server: catalogue frequencies must be positive and increasing");
