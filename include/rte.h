@@ -194,6 +194,7 @@ typedef struct {
     double fill_kernel_ms;                        /* HIP-event time of the dense-fill launches, summed */
     int32_t fill_launches;
     int64_t aca_entries;                          /* entries evaluated inside the ACA launches */
+    int64_t aca_retried;                          /* blocks run again with the larger second-pass cap */
 } rte_hmat_stats_t;
 
 rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats);

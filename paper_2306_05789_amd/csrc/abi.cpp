@@ -123,7 +123,7 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::unique_ptr<Plan> pla
     H.kappa_c.alloc(sizeof(double) * (size_t)m.N * n_bands);
     permute_gather(H.tgt_nat.as<int64_t>(), m.N, n_bands, m.N, m.N, kappa, H.kappa_c.as<double>(), s);
     H.bands.resize(n_bands);
-    int64_t evaluated = 0, bytes = 0, dense_e = 0, lr_e = 0, nfb = 0, aca_e = 0;
+    int64_t evaluated = 0, bytes = 0, dense_e = 0, lr_e = 0, nfb = 0, aca_e = 0, retried = 0;
     double aca_ms = 0, fill_ms = 0, aca_entry_ms = 0;
     int aca_l = 0, fill_l = 0, aca_entry_l = 0;
     double wsum = 0, wr = 0;
@@ -134,6 +134,7 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::unique_ptr<Plan> pla
         const BandStore &B = H.bands[b];
         evaluated += B.evaluated;
         aca_e += B.aca_entries;
+        retried += B.aca_retried;
         aca_ms += B.aca_ms;
         aca_entry_ms += B.aca_entry_ms;
         aca_entry_l += B.aca_entry_launches;
@@ -170,6 +171,7 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::unique_ptr<Plan> pla
     st.bytes = bytes;
     st.entries_evaluated = evaluated;
     st.aca_entries = aca_e;
+    st.aca_retried = retried;
     st.aca_kernel_ms = aca_ms;
     st.aca_launches = aca_l;
     st.aca_entry_ms = aca_entry_ms;

@@ -749,10 +749,17 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
     // (large, barely admissible blocks, common with a reflective wall, whose
     // two kernel terms add their ranks), again from the start with the cap
     // kAcaRetryRank; only what still reaches its cap is stored dense.
+    // Checking aid: RTE_ACA_FIRST_CAP in the environment lowers the first
+    // pass's cap (1 .. kAcaMaxRank), so that small problems exercise the
+    // second pass; the stored operator does not depend on it.
+    int64_t first_cap = kAcaMaxRank;
+    if (const char *e = std::getenv("RTE_ACA_FIRST_CAP"))
+        first_cap = std::min<int64_t>(kAcaMaxRank, std::max<int64_t>(1, std::atoll(e)));
     std::vector<size_t> todo(nlr), retry;
     for (size_t b = 0; b < nlr; ++b) todo[b] = b;
     for (int pass = 0; pass < 2 && !todo.empty(); ++pass) {
-        const int64_t cap = pass == 0 ? kAcaMaxRank : kAcaRetryRank;
+        const int64_t cap = pass == 0 ? first_cap : kAcaRetryRank;
+        if (pass == 1) B.aca_retried += (int64_t)todo.size();
         std::vector<AcaTask> tasks;
         std::vector<size_t> ids;
         int64_t uo = 0, vo = 0;

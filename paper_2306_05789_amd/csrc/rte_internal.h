@@ -204,7 +204,7 @@ struct BandStore {
     std::vector<int32_t> rank;              // per plan LR block; -1 = stored dense (fallback)
     std::vector<const void *> U, V;         // per plan LR block (nullptr for fallbacks)
     std::vector<const void *> Ulo, Vlo;     // mixed precision: BF16 lo parts
-    int64_t bytes = 0, dense_entries = 0, lr_entries = 0, evaluated = 0, aca_entries = 0;
+    int64_t bytes = 0, dense_entries = 0, lr_entries = 0, evaluated = 0, aca_entries = 0, aca_retried = 0;
     double aca_ms = 0.0, fill_ms = 0.0, aca_entry_ms = 0.0;   // HIP-event kernel times
     int aca_launches = 0, fill_launches = 0, aca_entry_launches = 0;
 };

@@ -50,7 +50,8 @@ class HmatStats(C.Structure):
                 ("entries_evaluated", C.c_int64), ("assemble_ms", C.c_double),
                 ("aca_kernel_ms", C.c_double), ("aca_launches", C.c_int32),
                 ("aca_entry_ms", C.c_double), ("aca_entry_launches", C.c_int32),
-                ("fill_kernel_ms", C.c_double), ("fill_launches", C.c_int32), ("aca_entries", C.c_int64)]
+                ("fill_kernel_ms", C.c_double), ("fill_launches", C.c_int32), ("aca_entries", C.c_int64),
+                ("aca_retried", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -204,6 +204,44 @@ def test_aca_blocks_meet_the_tolerance(small_h):
     assert errs.max() < 100 * eps and np.median(errs) < 10 * eps, (errs.max(), np.median(errs))
 
 
+@pytest.mark.parametrize("precision", [rte.RTE_FP64, rte.RTE_MIXED_BF16])
+def test_second_aca_pass_reproduces_a_single_pass(small_h, monkeypatch, precision):
+    """Blocks that stop at the first pass's rank cap while their break-even rank is
+    larger run again from the start with a larger cap.  With the first cap lowered to
+    4 (a checking aid) most blocks take that second pass; every block's rank and
+    factors, and the matvec, come out bit for bit as with the ordinary first cap, and
+    the factors still meet the ACA tolerance against the oracle's dense blocks."""
+    P, mesh, kap, G, S = small_h
+    kw = dict(leaf_size=32, eta=2.0, aca_eps=1e-5, precision=precision)
+    H1 = _assemble(mesh, kap, rte.RTE_VOLUME, **kw)
+    monkeypatch.setenv("RTE_ACA_FIRST_CAP", "4")
+    H2 = _assemble(mesh, kap, rte.RTE_VOLUME, **kw)
+    monkeypatch.delenv("RTE_ACA_FIRST_CAP")
+    s1, s2 = rte.rte_hmat_stats(H1), rte.rte_hmat_stats(H2)
+    assert s1["aca_retried"] == 0 and s2["aca_retried"] > s2["n_lowrank"] // 2
+    assert s1["n_fallback_dense"] == s2["n_fallback_dense"] and s1["bytes"] == s2["bytes"]
+    plan = rte.rte_plan_create(mesh, rte.hmat_opts(**kw))
+    tp, sp, blocks = rte.rte_plan_export(plan)
+    rte.rte_plan_destroy(plan)
+    low = blocks[blocks[:, 4] == 1]
+    worst = 0.0
+    for b in range(len(low)):
+        k1, U1, V1 = rte.rte_hmat_block_factors(H1, 0, b)
+        k2, U2, V2 = rte.rte_hmat_block_factors(H2, 0, b)
+        assert k1 == k2, b
+        if k1 > 0:
+            assert np.array_equal(U1, U2) and np.array_equal(V1, V2), b
+            t0, t1, s0, s1_ = low[b][:4]
+            A = G[np.ix_(tp[t0:t1], sp[s0:s1_])]
+            worst = max(worst, np.linalg.norm(A - U1 @ V1.T) / np.linalg.norm(A))
+    assert worst < 100 * 1e-5 * (1 if precision == rte.RTE_FP64 else 10), worst
+    x = torch.tensor(np.random.default_rng(4).uniform(0.5, 2.0, (2, mesh.N)), device=DEV)
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    rte.rte_hmat_matvec(H1, 0, x, y1)
+    rte.rte_hmat_matvec(H2, 0, x, y2)
+    assert torch.equal(y1, y2)
+
+
 def test_hmatrix_solve_close_to_dense_oracle(small_h):
     P, mesh, kap, G, S = small_h
     SE = S @ np.full(len(P.emitting), osolve.SIGMA)
