@@ -29,6 +29,8 @@
 // with FP32 accumulation; the accurate operator takes hi + lo factors times
 // hi + mid + lo and adds every 32-column step's FP32 result into FP64.
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <type_traits>
 
 #include "kernels.h"
@@ -62,14 +64,21 @@ struct LeafWork {
     int32_t rows, seg0, seg1, band;
 };
 
-// BF16 (matrix-core) phase A task: 64 ranks of one chunk of a low-rank block
-struct MfVt {
-    const uint16_t *V, *Vlo;   // first 8-row group of the chunk in V [nP/8][k][8]
-    int64_t xoff;              // stored source coordinate of the chunk's first row
+// BF16 (matrix-core) phase A task: up to kMfTiles 16-rank tiles over one chunk
+// of stored source rows.  The tiles may come from different low-rank blocks
+// whose V covers the same chunk (blocks of one source cluster are chunked
+// alike), so the x operand loaded for a step serves all of them.
+constexpr int kMfTiles = 4;
+struct MfTile {
+    const uint16_t *V, *Vlo;   // first 8-row group of the chunk in the block's V [nP/8][k][8]
     int64_t out;               // direct: offset of t_b in the t splits; else partial-sum offset of the chunk
-    int32_t ng, k, band, kt0;  // 8-row groups in the chunk, rank, band, first rank of the task
-    int32_t direct;            // 1: the block is one chunk, its t splits are written here
-    int32_t tiles;             // 16-rank tiles of this task (ranks kt0 .. kt0 + 16 tiles)
+    int32_t k, kt0;            // block rank, first rank of the tile
+    int32_t direct, pad;       // direct: the block is one chunk, its t splits are written here
+};
+struct MfVt {
+    MfTile tile[kMfTiles];
+    int64_t xoff;              // stored source coordinate of the chunk's first row
+    int32_t ng, band, nt, pad; // 8-row groups in the chunk, band, tiles used
 };
 
 // BF16 t staging: sum a block's chunk partials, split into hi, mid, lo
@@ -383,13 +392,20 @@ __device__ __forceinline__ void mf_products(const MfOps<MODE> &o, int nt, f32x4 
     }
 }
 
-// Resources and geometry of one phase A task or phase B segment.
+// Resources and geometry of one phase B segment.
 template <int MODE>
 struct MfSrc {
     rsrc_t a, al, x[3];
-    int k;      // phase A: rank (row length of V); phase B: slice rows (ld)
+    int k;      // slice rows (ld)
     int ngr;    // 8-groups of the K dimension
-    int nt;     // phase A: 16-rank tiles of the task
+};
+
+// Resources and geometry of one phase A task: per tile its block's V.
+template <int MODE>
+struct MfSrcA {
+    rsrc_t a[kMfTiles], al[kMfTiles], x[3];
+    int k[kMfTiles], kt0[kMfTiles];
+    int ngr, nt;
 };
 
 // Phase A.  Lane (c = lane % 16, q = lane / 16) feeds rank row c of each
@@ -398,63 +414,68 @@ struct MfSrc {
 // side c.  A wavefront walks tasks w, w + nw, w + 2 nw, ... (the list is
 // sorted by size, so the strided walk balances) as one pipeline over
 // (task, step), two operand sets in turn: the next step's operands, possibly
-// of the next task, are in flight while the current products run.  A
-// one-chunk block writes its t splits (zero padding up to pad8(k) included)
-// directly; larger blocks leave FP64 partials for k_mf_tstage.
+// of the next task, are in flight while the current products run.  A tile of
+// a one-chunk block writes its t splits (zero padding up to pad8(k)
+// included) directly; tiles of larger blocks leave FP64 partials for
+// k_mf_tstage.
 template <int MODE>
-__device__ __forceinline__ MfSrc<MODE> mf_src_a(const MfVt &tk, const uint16_t *xs, int64_t xsplit, int64_t np) {
-    MfSrc<MODE> r;
-    const int vbytes = tk.ng * tk.k * 16;
-    r.a = make_rsrc(tk.V, vbytes);
-    if constexpr (MODE == kMatvecAccurate) r.al = make_rsrc(tk.Vlo, vbytes);
+__device__ __forceinline__ MfSrcA<MODE> mf_src_a(const MfVt &tk, const uint16_t *xs, int64_t xsplit, int64_t np) {
+    MfSrcA<MODE> r;
+#pragma unroll
+    for (int t = 0; t < kMfTiles; ++t) {
+        const MfTile &tl = tk.tile[t < tk.nt ? t : 0];
+        const int vbytes = tk.ng * tl.k * 16;
+        r.a[t] = make_rsrc(tl.V, vbytes);
+        if constexpr (MODE == kMatvecAccurate) r.al[t] = make_rsrc(tl.Vlo, vbytes);
+        r.k[t] = tl.k;
+        r.kt0[t] = tl.kt0;
+    }
     const uint16_t *xb = xs + ((int64_t)tk.band * (np / 8) + tk.xoff / 8) * 128;
 #pragma unroll
     for (int sp = 0; sp < MfOps<MODE>::NS; ++sp) r.x[sp] = make_rsrc(xb + sp * xsplit, tk.ng * 256);
-    r.k = tk.k;
     r.ngr = tk.ng;
-    r.nt = min(tk.tiles, (tk.k - tk.kt0 + 15) / 16);
+    r.nt = tk.nt;
     return r;
 }
 
 template <int MODE>
-__device__ __forceinline__ void mf_load_a(const MfSrc<MODE> &r, int kt0, int g0, bool valid, int c, int q,
-                                          MfOps<MODE> &o) {
+__device__ __forceinline__ void mf_load_a(const MfSrcA<MODE> &r, int g0, bool valid, int c, int q, MfOps<MODE> &o) {
     const int g = g0 + q;
     const int xo = valid ? (g * 16 + c) * 16 : kOOB;
 #pragma unroll
     for (int sp = 0; sp < MfOps<MODE>::NS; ++sp) o.bx[sp] = bload(r.x[sp], xo);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int rk = kt0 + 16 * t + c;
-        const int off = valid && t < r.nt && rk < r.k ? (g * r.k + rk) * 16 : kOOB;
-        o.a[t] = bload(r.a, off);
-        if constexpr (MODE == kMatvecAccurate) o.al[t] = bload(r.al, off);
+    for (int t = 0; t < kMfTiles; ++t) {
+        const int rk = r.kt0[t] + c;
+        const int off = valid && t < r.nt && rk < r.k[t] ? (g * r.k[t] + rk) * 16 : kOOB;
+        o.a[t] = bload(r.a[t], off);
+        if constexpr (MODE == kMatvecAccurate) o.al[t] = bload(r.al[t], off);
     }
 }
 
 template <int MODE>
 __device__ __forceinline__ void mf_finish_a(const MfVt &tk, int c, int q, const f32x4 acc[4], const double a64[4][4],
                                             double *part, int64_t ldp, uint16_t *ts, int64_t tsplit, int r0, int nr) {
-    const int nt = min(tk.tiles, (tk.k - tk.kt0 + 15) / 16);
-    const int k8 = (int)pad8(tk.k);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (t < nt) {
+    for (int t = 0; t < kMfTiles; ++t) {
+        if (t < tk.nt) {
+            const MfTile &tl = tk.tile[t];
+            const int k8 = (int)pad8(tl.k);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int rk = tk.kt0 + 16 * t + 4 * q + v;
-                const double val = rk < tk.k ? (MODE == kMatvecLow ? (double)acc[t][v] : a64[t][v]) : 0.0;
-                if (tk.direct) {
+                const int rk = tl.kt0 + 4 * q + v;
+                const double val = rk < tl.k ? (MODE == kMatvecLow ? (double)acc[t][v] : a64[t][v]) : 0.0;
+                if (tl.direct) {
                     if (rk < k8) {
                         uint16_t h, m, lo;
                         split3(val, h, m, lo);
-                        const int64_t off = ((tk.out + rk) / 8 * 16 + c) * 8 + rk % 8;
+                        const int64_t off = ((tl.out + rk) / 8 * 16 + c) * 8 + rk % 8;
                         ts[off] = h;
                         ts[tsplit + off] = m;
                         ts[2 * tsplit + off] = lo;
                     }
-                } else if (rk < tk.k && c < nr) {
-                    part[(int64_t)(r0 + c) * ldp + tk.out + rk] = val;
+                } else if (rk < tl.k && c < nr) {
+                    part[(int64_t)(r0 + c) * ldp + tl.out + rk] = val;
                 }
             }
         }
@@ -477,14 +498,12 @@ __global__ __launch_bounds__(256) void k_mf_phase_a(const MfVt *__restrict__ tas
 #pragma unroll
         for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
     // pipeline state: the task of the operands being consumed, and the next
-    MfVt cur = tasks[ti];
-    MfSrc<MODE> rc = mf_src_a<MODE>(cur, xs, xsplit, np);
-    int g0 = 0;
+    int64_t cur = ti;     // task being consumed
+    MfSrcA<MODE> rl = mf_src_a<MODE>(tasks[ti], xs, xsplit, np);
+    int g0 = 0, ngc = rl.ngr, ntc = rl.nt;
     MfOps<MODE> o0, o1;   // two operand sets in turn (named: an indexed pair would live in scratch)
-    mf_load_a<MODE>(rc, cur.kt0, 0, true, c, q, o0);
+    mf_load_a<MODE>(rl, 0, true, c, q, o0);
     int64_t tl = ti;      // task of the last issued load
-    MfVt tkl = cur;
-    MfSrc<MODE> rl = rc;
     int gl = 0;
     bool done = false;
     // issue the loads of the step after (tl, gl) into `nx`, then the products of
@@ -493,28 +512,30 @@ __global__ __launch_bounds__(256) void k_mf_phase_a(const MfVt *__restrict__ tas
     auto step = [&](const MfOps<MODE> &cu, MfOps<MODE> &nx) {
         int gn = gl + 4;
         int64_t tn = tl;
-        if (gn >= tkl.ng) {
+        if (gn >= rl.ngr) {
             tn = tl + nw;
             gn = 0;
-            if (tn < ntask) {
-                tkl = tasks[tn];
-                rl = mf_src_a<MODE>(tkl, xs, xsplit, np);
-            }
+            if (tn < ntask) rl = mf_src_a<MODE>(tasks[tn], xs, xsplit, np);
         }
         // past the end: the same loads at out-of-range offsets (zeros)
-        mf_load_a<MODE>(rl, tkl.kt0, gn, tn < ntask, c, q, nx);
-        mf_products<MODE>(cu, min(cur.tiles, (cur.k - cur.kt0 + 15) / 16), acc, a64);
+        mf_load_a<MODE>(rl, gn, tn < ntask, c, q, nx);
+        mf_products<MODE>(cu, ntc, acc, a64);
         g0 += 4;
-        if (g0 >= cur.ng) {
-            mf_finish_a<MODE>(cur, c, q, acc, a64, part, ldp, ts, tsplit, r0, nr);
+        if (g0 >= ngc) {
+            mf_finish_a<MODE>(tasks[cur], c, q, acc, a64, part, ldp, ts, tsplit, r0, nr);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
-            ti += nw;
+            cur += nw;
             g0 = 0;
-            if (ti < ntask) cur = tkl;
-            else done = true;
+            if (cur < ntask) {
+                // the loads have just moved to task cur
+                ngc = rl.ngr;
+                ntc = rl.nt;
+            } else {
+                done = true;
+            }
         }
         tl = tn;
         gl = gn;
@@ -821,7 +842,7 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     std::vector<VtReduce> red;
     int64_t ktot = 0, npart = 0, maxk = 0;
     // about this many bytes of V per wavefront task
-    const int64_t chunk_bytes = (int64_t)H.cfg.task_kib * 1024, mf_task_bytes = chunk_bytes;
+    const int64_t chunk_bytes = (int64_t)H.cfg.task_kib * 1024;
     const int tiles = H.cfg.tiles;
     const int64_t esz = H.precision == RTE_FP64 ? 8 : H.precision == RTE_FP32 ? 4 : 2;
     const auto &leaves = P.tgt_leaves;
@@ -835,6 +856,9 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     const bool mf = H.precision == RTE_MIXED_BF16;
     std::vector<MfVt> mvt;
     std::vector<MfRed> mred;
+    // matrix-core phase A: tiles grouped by (band, first stored row, rows) of their chunk
+    std::map<std::tuple<int, int64_t, int64_t>, std::vector<MfTile>> mtiles;
+    const int64_t mf_rows = std::min<int64_t>(8192, std::max<int64_t>(256, chunk_bytes / 128)) / 8 * 8;
     const int64_t g = H.kgroup;
     for (int bi = 0; bi < (int)bands.size(); ++bi) {
         const BandStore &B = H.bands[bands[bi]];
@@ -845,24 +869,20 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
             const int32_t k = B.rank[b];
             const int64_t wp = H.pwidth(bl.s0, bl.s1);
             toff[b] = ktot;
-            // about mf_task_bytes of V per task (a task takes up to 16 tiles ranks)
-            const int64_t rows =
-                std::min<int64_t>(8192, std::max<int64_t>(256, mf_task_bytes / (2 * std::min(16 * tiles, k)))) / 32 * 32;
-            const int64_t chunks = (wp + rows - 1) / rows;
+            // chunks of mf_rows stored rows from the source cluster's start:
+            // blocks of one source cluster are chunked alike and their tiles
+            // can share a task
+            const int64_t chunks = (wp + mf_rows - 1) / mf_rows;
             const uint16_t *V = static_cast<const uint16_t *>(B.V[b]), *Vl = static_cast<const uint16_t *>(B.Vlo[b]);
-            if (chunks == 1) {
-                for (int32_t kt0 = 0; kt0 < k; kt0 += 16 * tiles)
-                    mvt.push_back({V, Vl, H.src_p_h[bl.s0], ktot, (int32_t)(wp / 8), k, bi, kt0, 1, tiles});
-            } else {
-                mred.push_back({npart, ktot, (int32_t)chunks, k});
-                for (int64_t c = 0; c < chunks; ++c) {
-                    const int64_t nj = std::min(rows, wp - c * rows);
-                    for (int32_t kt0 = 0; kt0 < k; kt0 += 16 * tiles)
-                        mvt.push_back({V + c * rows * k, Vl + c * rows * k, H.src_p_h[bl.s0] + c * rows,
-                                       npart + c * k, (int32_t)(nj / 8), k, bi, kt0, 0, tiles});
-                }
-                npart += chunks * k;
+            if (chunks > 1) mred.push_back({npart, ktot, (int32_t)chunks, k});
+            for (int64_t c = 0; c < chunks; ++c) {
+                const int64_t nj = std::min(mf_rows, wp - c * mf_rows);
+                auto &grp = mtiles[std::make_tuple(bi, H.src_p_h[bl.s0] + c * mf_rows, nj)];
+                for (int32_t kt0 = 0; kt0 < k; kt0 += 16)
+                    grp.push_back({V + c * mf_rows * k, Vl + c * mf_rows * k, chunks == 1 ? ktot : npart + c * k, k,
+                                   kt0, chunks == 1 ? 1 : 0, 0});
             }
+            if (chunks > 1) npart += chunks * k;
             maxk = std::max<int64_t>(maxk, k);
             ktot += pad8(k);
         }
@@ -928,8 +948,21 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     std::stable_sort(vt.begin(), vt.end(), [](const VtTask &a, const VtTask &b) {
         return (int64_t)a.nj * a.k > (int64_t)b.nj * b.k;
     });
+    // tasks of up to `tiles` tiles of one chunk (in block order)
+    for (auto &kv : mtiles) {
+        const std::vector<MfTile> &grp = kv.second;
+        for (size_t i = 0; i < grp.size(); i += (size_t)tiles) {
+            MfVt t{};
+            t.nt = (int32_t)std::min<size_t>((size_t)tiles, grp.size() - i);
+            for (int j = 0; j < t.nt; ++j) t.tile[j] = grp[i + j];
+            t.xoff = std::get<1>(kv.first);
+            t.ng = (int32_t)(std::get<2>(kv.first) / 8);
+            t.band = std::get<0>(kv.first);
+            mvt.push_back(t);
+        }
+    }
     std::stable_sort(mvt.begin(), mvt.end(), [](const MfVt &a, const MfVt &b) {
-        return (int64_t)a.ng * std::min(16 * a.tiles, a.k - a.kt0) > (int64_t)b.ng * std::min(16 * b.tiles, b.k - b.kt0);
+        return (int64_t)a.ng * a.nt > (int64_t)b.ng * b.nt;
     });
     mp->ktot = std::max<int64_t>(ktot, mf ? 8 : 1);
     mp->npart = npart;
