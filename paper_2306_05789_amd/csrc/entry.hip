@@ -54,6 +54,7 @@ EntryCtx<T> make_ctx(const Mesh &m, const T *kappa) {
     EntryCtx<T> c;
     c.g = m.dev;
     c.kappa = kappa;
+    c.near = static_cast<const T *>(m.near_table(std::is_same<T, double>::value));
     if constexpr (std::is_same<T, double>::value) c.st = stencil_device().d;
     else c.st = stencil_device().f;
     return c;

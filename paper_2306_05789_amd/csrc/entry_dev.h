@@ -30,6 +30,7 @@ struct EntryCtx {
     GridDev g;
     const T *__restrict__ kappa;   // [N] P1 vertex values of one band
     StencilDev<T> st;
+    const T *__restrict__ near;    // near-field weights of the mesh [125 offsets][8 cells][8 corners]
 };
 
 // ---------------------------------------------------------------- compile-time Kuhn star
@@ -302,12 +303,32 @@ __device__ __forceinline__ T vol_quad_all(std::integer_sequence<int, ts...>, con
     return acc;
 }
 
-// g(x, j) without the 1/(4 pi)|e| factor; dg = (x - x_j) in grid units
+// Near field (grid offset d = x - x_j with |d_a| <= 2): the degree-5 rule's
+// sums, tabulated per mesh by cell and corner, so g is 64 products with the
+// star's kappa values (cells outside the grid skipped).
 template <typename T>
-__device__ __forceinline__ T vol_quad(const EntryCtx<T> &c, const T kn[27], int cellmask, const T dg[3],
+__device__ __forceinline__ T vol_near(const T *__restrict__ tab, const T kn[27], int cellmask, const int d[3]) {
+    const T *row = tab + ((d[0] + 2) * 25 + (d[1] + 2) * 5 + (d[2] + 2)) * 64;
+    T acc = (T)0;
+#pragma unroll
+    for (int bits = 0; bits < 8; ++bits) {
+        if (!((cellmask >> bits) & 1)) continue;
+        const int o0 = bits & 1, o1 = (bits >> 1) & 1, o2 = (bits >> 2) & 1;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int slot = ((e & 1) - o0 + 1) * 9 + (((e >> 1) & 1) - o1 + 1) * 3 + (((e >> 2) & 1) - o2 + 1);
+            acc += row[bits * 8 + e] * kn[slot];
+        }
+    }
+    return acc;
+}
+
+// g(x, j) without the 1/(4 pi)|e| factor; d = (x - x_j) in grid units
+template <typename T>
+__device__ __forceinline__ T vol_quad(const EntryCtx<T> &c, const T kn[27], int cellmask, const int d[3],
                                       const T h2[3], bool near) {
-    if (near)
-        return vol_quad_all<T, 14>(std::make_integer_sequence<int, kTets>{}, c.st.vol_near, kn, cellmask, dg, h2);
+    if (near) return vol_near(c.near, kn, cellmask, d);
+    const T dg[3] = {(T)d[0], (T)d[1], (T)d[2]};
     return vol_quad_all<T, 4>(std::make_integer_sequence<int, kTets>{}, c.st.vol_far, kn, cellmask, dg, h2);
 }
 
@@ -351,14 +372,14 @@ __device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
     int cellmask;
     load_star(c, jj, kn, cellmask);
     const T h2[3] = {(T)(g.h[0] * g.h[0]), (T)(g.h[1] * g.h[1]), (T)(g.h[2] * g.h[2])};
-    const T dg[3] = {P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
+    const int dg[3] = {ii[0] - jj[0], ii[1] - jj[1], ii[2] - jj[2]};
     T G = att * vol_quad(c, kn, cellmask, dg, h2, cheb3(ii, jj) <= kNearCheb);
     if (g.wall_axis >= 0) {
         const int a = g.wall_axis;
         const int Ci = g.wall_side ? g.n[a] - 1 : 0;
         int mi[3] = {ii[0], ii[1], ii[2]};
         mi[a] = 2 * Ci - ii[a];
-        const T dgm[3] = {(T)mi[0] - Q[0], (T)mi[1] - Q[1], (T)mi[2] - Q[2]};
+        const int dgm[3] = {mi[0] - jj[0], mi[1] - jj[1], mi[2] - jj[2]};
         G += att_m * vol_quad(c, kn, cellmask, dgm, h2, cheb3(mi, jj) <= kNearCheb);
     }
     return G * (T)g.vol_scale;

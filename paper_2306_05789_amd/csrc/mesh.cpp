@@ -184,6 +184,63 @@ const StencilBuffers &stencil_device() {
     return per_dev.emplace(dev, B).first->second;
 }
 
+// Weights of the near table (see NearTables): the same sums as the device's
+// degree-5 loop, grouped by the cell and corner whose kappa they multiply.
+static std::vector<double> make_near_table(const double h[3]) {
+    static_assert(kNearCheb == 2 && kNearOffsets == 125, "the near table covers offsets in [-2, 2]^3");
+    const StencilHost &S = stencil_host();
+    const int nq = S.nq_vol_near;
+    std::vector<double> T((size_t)kNearOffsets * 64, 0.0);
+    for (int dx = -2; dx <= 2; ++dx)
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dz = -2; dz <= 2; ++dz) {
+                const int d[3] = {dx, dy, dz};
+                double *row = &T[(size_t)((dx + 2) * 25 + (dy + 2) * 5 + (dz + 2)) * 64];
+                for (int t = 0; t < kTets; ++t) {
+                    const int bits = S.tet_meta[5 * t + 4];
+                    const int o[3] = {bits & 1, (bits >> 1) & 1, (bits >> 2) & 1};
+                    for (int q = 0; q < nq; ++q) {
+                        const double *e = &S.vol_near[((size_t)t * nq + q) * 8];
+                        double r2 = 0.0;
+                        for (int a = 0; a < 3; ++a) r2 += h[a] * h[a] * (d[a] - e[a]) * (d[a] - e[a]);
+                        const double w = e[3] / r2;
+                        for (int k = 0; k < 4; ++k) {
+                            const int slot = S.tet_meta[5 * t + k];
+                            const int s3[3] = {slot / 9 - 1, (slot / 3) % 3 - 1, slot % 3 - 1};
+                            const int corner = (s3[0] + o[0]) + 2 * (s3[1] + o[1]) + 4 * (s3[2] + o[2]);
+                            row[bits * 8 + corner] += w * e[4 + k];
+                        }
+                    }
+                }
+            }
+    return T;
+}
+
+NearTables::~NearTables() {
+    for (auto &kv : dev) {
+        (void)hipFree(kv.second.first);
+        (void)hipFree(kv.second.second);
+    }
+}
+
+const void *Mesh::near_table(bool fp64) const {
+    int d = 0;
+    HIP_CHECK(hipGetDevice(&d));
+    std::lock_guard<std::mutex> lk(near->mu);
+    auto it = near->dev.find(d);
+    if (it == near->dev.end()) {
+        const std::vector<double> &H = near->host;
+        std::vector<float> F(H.begin(), H.end());
+        void *pd = nullptr, *pf = nullptr;
+        HIP_CHECK(hipMalloc(&pd, H.size() * sizeof(double)));
+        HIP_CHECK(hipMalloc(&pf, F.size() * sizeof(float)));
+        HIP_CHECK(hipMemcpy(pd, H.data(), H.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_CHECK(hipMemcpy(pf, F.data(), F.size() * sizeof(float), hipMemcpyHostToDevice));
+        it = near->dev.emplace(d, std::make_pair(pd, pf)).first;
+    }
+    return fp64 ? it->second.first : it->second.second;
+}
+
 void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
     for (int a = 0; a < 3; ++a) {
         RTE_REQUIRE(d.n[a] >= 2, "mesh: every axis needs at least 2 vertices");
@@ -206,6 +263,8 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
     M.desc = d;
     M.N = N;
     for (int a = 0; a < 3; ++a) M.h[a] = (d.hi[a] - d.lo[a]) / (d.n[a] - 1);
+    M.near = std::make_shared<NearTables>();
+    M.near->host = make_near_table(M.h);
     M.emitting.clear();
     for (int64_t v = 0; v < N; ++v) {
         int idx[3] = {(int)(v / ((int64_t)d.n[1] * d.n[2])), (int)((v / d.n[2]) % d.n[1]), (int)(v % d.n[2])};

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -76,12 +78,27 @@ struct StencilDev {
 };
 
 // ---------------------------------------------------------------- mesh
+// Near-field volume quadrature of a mesh (the degree-5 rule, grid Chebyshev
+// distance <= 2 between target and source): for each offset d in [-2, 2]^3,
+// each of the 8 cells around the source vertex and each of the cell's 8
+// corners, the weight of the corner's kappa in g(x_j + d, j).  It depends on
+// the spacing only.  Host copy at mesh creation, device copies on first use.
+constexpr int kNearOffsets = 125;
+struct NearTables {
+    std::vector<double> host;    // [kNearOffsets][8 cells][8 corners]
+    std::mutex mu;
+    std::map<int, std::pair<void *, void *>> dev;   // device -> (FP64, FP32) copies
+    ~NearTables();
+};
+
 struct Mesh {
     rte_mesh_desc_t desc{};
     int64_t N = 0, L = 0;
     double h[3] = {0, 0, 0};
     std::vector<int64_t> emitting;   // natural ids, ascending
     GridDev dev{};
+    std::shared_ptr<NearTables> near;
+    const void *near_table(bool fp64) const;   // device copy on the current device
     std::vector<double> positions() const;            // [N][3]
     std::vector<double> emitting_positions() const;   // [L][3]
 };
