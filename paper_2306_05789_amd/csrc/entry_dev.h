@@ -30,7 +30,7 @@ struct EntryCtx {
     GridDev g;
     const T *__restrict__ kappa;   // [N] P1 vertex values of one band
     StencilDev<T> st;
-    const T *__restrict__ near;    // near-field weights of the mesh [125 offsets][8 cells][8 corners]
+    const T *__restrict__ near;    // quadrature tables of the mesh: near [125][8][8], then far [24][4][8]
 };
 
 // ---------------------------------------------------------------- compile-time Kuhn star
@@ -277,32 +277,6 @@ __device__ __forceinline__ double recip(double x) {
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------- volume quadrature
-template <typename T, int NQ, int t>
-__device__ __forceinline__ void vol_tet(const T *__restrict__ tab, const T kn[27], int cellmask,
-                                        const T dg[3], const T h2[3], T &acc) {
-    constexpr TetInfo ti = kStar.tet[t];
-    if (!((cellmask >> ti.bits) & 1)) return;
-    const T k0 = kn[ti.slot[0]], k1 = kn[ti.slot[1]], k2 = kn[ti.slot[2]], k3 = kn[ti.slot[3]];
-    const T *e = tab + t * NQ * 8;
-    T s = (T)0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const T ex = dg[0] - e[8 * q + 0], ey = dg[1] - e[8 * q + 1], ez = dg[2] - e[8 * q + 2];
-        const T r2 = h2[0] * ex * ex + h2[1] * ey * ey + h2[2] * ez * ez;
-        const T kq = e[8 * q + 4] * k0 + e[8 * q + 5] * k1 + e[8 * q + 6] * k2 + e[8 * q + 7] * k3;
-        s += e[8 * q + 3] * kq * recip(r2);
-    }
-    acc += s;
-}
-
-template <typename T, int NQ, int... ts>
-__device__ __forceinline__ T vol_quad_all(std::integer_sequence<int, ts...>, const T *__restrict__ tab,
-                                          const T kn[27], int cellmask, const T dg[3], const T h2[3]) {
-    T acc = (T)0;
-    (vol_tet<T, NQ, ts>(tab, kn, cellmask, dg, h2, acc), ...);
-    return acc;
-}
-
 // Near field (grid offset d = x - x_j with |d_a| <= 2): the degree-5 rule's
 // sums, tabulated per mesh by cell and corner, so g is 64 products with the
 // star's kappa values (cells outside the grid skipped).
@@ -323,13 +297,42 @@ __device__ __forceinline__ T vol_near(const T *__restrict__ tab, const T kn[27],
     return acc;
 }
 
+// Far field, one tetrahedron of the star: its 4 points' terms a_q / r_q added
+// over a common denominator, so one reciprocal serves the 4 points.
+template <typename T, int t>
+__device__ __forceinline__ void vol_far_tet(const T *__restrict__ ft, const T kn[27], int cellmask, T D2,
+                                            const T dg[3], T &acc) {
+    constexpr TetInfo ti = kStar.tet[t];
+    if (!((cellmask >> ti.bits) & 1)) return;
+    const T k0 = kn[ti.slot[0]], k1 = kn[ti.slot[1]], k2 = kn[ti.slot[2]], k3 = kn[ti.slot[3]];
+    const T *e = ft + t * 32;
+    T a[4], r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        r[q] = D2 + e[8 * q + 3] + e[8 * q + 0] * dg[0] + e[8 * q + 1] * dg[1] + e[8 * q + 2] * dg[2];
+        a[q] = e[8 * q + 4] * k0 + e[8 * q + 5] * k1 + e[8 * q + 6] * k2 + e[8 * q + 7] * k3;
+    }
+    const T n01 = a[0] * r[1] + a[1] * r[0], d01 = r[0] * r[1];
+    const T n23 = a[2] * r[3] + a[3] * r[2], d23 = r[2] * r[3];
+    acc += (n01 * d23 + n23 * d01) * recip(d01 * d23);
+}
+
+template <typename T, int... ts>
+__device__ __forceinline__ T vol_far_all(std::integer_sequence<int, ts...>, const T *__restrict__ ft, const T kn[27],
+                                         int cellmask, T D2, const T dg[3]) {
+    T acc = (T)0;
+    (vol_far_tet<T, ts>(ft, kn, cellmask, D2, dg, acc), ...);
+    return acc;
+}
+
 // g(x, j) without the 1/(4 pi)|e| factor; d = (x - x_j) in grid units
 template <typename T>
 __device__ __forceinline__ T vol_quad(const EntryCtx<T> &c, const T kn[27], int cellmask, const int d[3],
                                       const T h2[3], bool near) {
     if (near) return vol_near(c.near, kn, cellmask, d);
     const T dg[3] = {(T)d[0], (T)d[1], (T)d[2]};
-    return vol_quad_all<T, 4>(std::make_integer_sequence<int, kTets>{}, c.st.vol_far, kn, cellmask, dg, h2);
+    const T D2 = h2[0] * dg[0] * dg[0] + h2[1] * dg[1] * dg[1] + h2[2] * dg[2] * dg[2];
+    return vol_far_all<T>(std::make_integer_sequence<int, kTets>{}, c.near + kNearSize, kn, cellmask, D2, dg);
 }
 
 template <typename T>

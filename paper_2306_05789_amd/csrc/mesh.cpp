@@ -213,6 +213,22 @@ static std::vector<double> make_near_table(const double h[3]) {
                     }
                 }
             }
+    // far field
+    T.resize((size_t)kNearSize + kFarSize, 0.0);
+    const int nf = S.nq_vol_far;
+    if (nf != 4) throw Error(RTE_E_INTERNAL, "far rule size");
+    for (int t = 0; t < kTets; ++t)
+        for (int q = 0; q < nf; ++q) {
+            const double *e = &S.vol_far[((size_t)t * nf + q) * 8];
+            double *f = &T[(size_t)kNearSize + ((size_t)t * 4 + q) * 8];
+            double c = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                f[a] = -2.0 * h[a] * h[a] * e[a];
+                c += h[a] * h[a] * e[a] * e[a];
+            }
+            f[3] = c;
+            for (int k = 0; k < 4; ++k) f[4 + k] = e[3] * e[4 + k];
+        }
     return T;
 }
 

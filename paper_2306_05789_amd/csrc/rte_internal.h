@@ -78,14 +78,20 @@ struct StencilDev {
 };
 
 // ---------------------------------------------------------------- mesh
-// Near-field volume quadrature of a mesh (the degree-5 rule, grid Chebyshev
-// distance <= 2 between target and source): for each offset d in [-2, 2]^3,
-// each of the 8 cells around the source vertex and each of the cell's 8
-// corners, the weight of the corner's kappa in g(x_j + d, j).  It depends on
-// the spacing only.  Host copy at mesh creation, device copies on first use.
+// Volume quadrature tables of a mesh (they depend on the spacing only).
+// Near field (the degree-5 rule, grid Chebyshev distance <= 2 between target
+// and source): for each offset d in [-2, 2]^3, each of the 8 cells around the
+// source vertex and each of the cell's 8 corners, the weight of the corner's
+// kappa in g(x_j + d, j).  Far field (the degree-2 rule): per tetrahedron of
+// the star and quadrature point, A_a = -2 h_a^2 e_a and C = sum h_a^2 e_a^2
+// (e the point's offset from the source vertex, grid units), so that
+// |x - y|^2 = |h d|^2 + A.d + C, then w_q lambda_j b_k for the 4 vertices.
+// Host copy at mesh creation, device copies on first use.
 constexpr int kNearOffsets = 125;
+constexpr int kNearSize = kNearOffsets * 64;
+constexpr int kFarSize = kTets * 4 * 8;
 struct NearTables {
-    std::vector<double> host;    // [kNearOffsets][8 cells][8 corners]
+    std::vector<double> host;    // near [kNearOffsets][8 cells][8 corners], then far [kTets][4][8]
     std::mutex mu;
     std::map<int, std::pair<void *, void *>> dev;   // device -> (FP64, FP32) copies
     ~NearTables();
