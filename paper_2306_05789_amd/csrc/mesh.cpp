@@ -175,12 +175,8 @@ const StencilBuffers &stencil_device() {
     StencilBuffers B;
     const int *tm = upload_ints(H.tet_meta);
     const int *rm = upload_ints(H.tri_meta);
-    B.d = {upload_forever<double>(H.vol_far), upload_forever<double>(H.vol_near),
-           upload_forever<double>(H.tri_far), upload_forever<double>(H.tri_near),
-           H.nq_vol_far, H.nq_vol_near, H.nq_tri_far, H.nq_tri_near, tm, rm};
-    B.f = {upload_forever<float>(H.vol_far), upload_forever<float>(H.vol_near),
-           upload_forever<float>(H.tri_far), upload_forever<float>(H.tri_near),
-           H.nq_vol_far, H.nq_vol_near, H.nq_tri_far, H.nq_tri_near, tm, rm};
+    B.d = {upload_forever<double>(H.tri_far), upload_forever<double>(H.tri_near), H.nq_tri_far, H.nq_tri_near, tm, rm};
+    B.f = {upload_forever<float>(H.tri_far), upload_forever<float>(H.tri_near), H.nq_tri_far, H.nq_tri_near, tm, rm};
     return per_dev.emplace(dev, B).first->second;
 }
 

@@ -64,15 +64,14 @@ struct GridDev {
     double area_scale[3];   // |triangle| / (4 pi) for faces normal to axis a
 };
 
-// Stencil tables on the device, one set per precision (T = double or float).
-// Volume, per rule: [kTets][nq][8] = offset (3, grid units, from the source
-// vertex), coef = w_q * lambda_j(y_q), barycentrics b0..b3 of the tet vertices.
-// Surface, per rule: [kTris][nq][4] = offset along the face's two axes (grid
-// units), coef = w_q * lambda_l(y_q), pad.
+// Surface stencil tables on the device, one set per precision (T = double or
+// float), per rule: [kTris][nq][4] = offset along the face's two axes (grid
+// units), coef = w_q * lambda_l(y_q), pad.  (The volume rules reach the device
+// through the per-mesh tables of NearTables.)
 template <typename T>
 struct StencilDev {
-    const T *vol_far, *vol_near, *tri_far, *tri_near;
-    int nq_vol_far, nq_vol_near, nq_tri_far, nq_tri_near;
+    const T *tri_far, *tri_near;
+    int nq_tri_far, nq_tri_near;
     const int *tet_meta;    // [kTets][5]: 4 neighbour slots (0..26 of the 3x3x3 block), cell corner bits
     const int *tri_meta;    // [kTris][2]: square offset bits along the face axes (b, c)
 };
