@@ -169,6 +169,22 @@ def _matvec_entry(G, nrhs, op, reps=3):
             "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
 
 
+def _assemble_pair(rte, mesh, kap, optG, optS):
+    """G and S assembled concurrently, each by its own host thread on its own
+    stream; returns both and the wall time of the pair in ms."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    streams = (torch.cuda.Stream(), torch.cuda.Stream())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(2) as pool:
+        fG = pool.submit(rte.rte_hmat_assemble, mesh, kap, optG, streams[0].cuda_stream)
+        fS = pool.submit(rte.rte_hmat_assemble, mesh, kap, optS, streams[1].cuda_stream)
+        G, S = fG.result(), fS.result()
+    torch.cuda.synchronize()
+    return G, S, (time.perf_counter() - t0) * 1e3
+
+
 def _solve_series(rte, mesh, G, S, Tw, T, nu, precision, tol, steps, warmup):
     for _ in range(warmup):
         rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=False, nu=nu, tol=tol, max_iter=3000, precision=precision)
@@ -199,19 +215,19 @@ def run_reflective(args):
     res, Ts = {}, {}
     for name in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
         p = rte.PRECISIONS[name]
-        G = rte.rte_hmat_assemble(mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, precision=p))
-        S = rte.rte_hmat_assemble(mesh, kap, rte.hmat_opts(kind=rte.RTE_SURFACE, precision=p))
+        G, S, wall_ms = _assemble_pair(rte, mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, precision=p),
+                                       rte.hmat_opts(kind=rte.RTE_SURFACE, precision=p))
         gs, ss = rte.rte_hmat_stats(G), rte.rte_hmat_stats(S)
-        _say(f"{name}: G {gs['assemble_ms']:.0f} ms, S {ss['assemble_ms']:.0f} ms")
+        _say(f"{name}: G {gs['assemble_ms']:.0f} ms, S {ss['assemble_ms']:.0f} ms, concurrently {wall_ms:.0f} ms")
         T = torch.empty((1, mesh.N), device=dev, dtype=torch.float64)
         lat, st = _solve_series(rte, mesh, G, S, Tw, T, wl.nu, p, 1e-6, args.steps, args.warmup)
         ops = [rte.RTE_OP_LOW, rte.RTE_OP_ACCURATE] if p == rte.RTE_MIXED_BF16 else [rte.RTE_OP_ACCURATE]
         solve_s = float(np.mean(lat))
-        res[name] = {"assemble_G": _hstats(gs), "assemble_S": _hstats(ss),
+        res[name] = {"assemble_G": _hstats(gs), "assemble_S": _hstats(ss), "assemble_wall_ms": wall_ms,
                      "solve_ms": solve_s * 1e3, "sweeps": st["iterations"], "outer_steps": st["outer_steps"],
                      "residual": st["residual"],
                      "resident_solves_per_s": 1.0 / solve_s,
-                     "solves_per_s": 1.0 / (solve_s + (gs["assemble_ms"] + ss["assemble_ms"]) * 1e-3),
+                     "solves_per_s": 1.0 / (solve_s + wall_ms * 1e-3),
                      "matvec": [_matvec_entry(G, 1, op) for op in ops]}
         Ts[name] = T.cpu().numpy()
         del G, S
