@@ -69,7 +69,8 @@ namespace rte {
 
 // Assembly of one H-matrix per band on a validated plan and kappa (device,
 // [n_bands][N], natural order); see rte_hmat_assemble.
-std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::unique_ptr<Plan> plan, int n_bands, const double *kappa,
+std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Plan> plan,
+                                        const rte_hmat_opts_t &o, int n_bands, const double *kappa,
                                         hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     auto hm = std::make_unique<rte_hmat>();
@@ -77,7 +78,8 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::unique_ptr<Plan> pla
     HIP_CHECK(hipGetDevice(&H.device));
     H.mesh = &m;
     H.n_bands = n_bands;
-    const rte_hmat_opts_t *opts = &plan->opts;
+    const rte_hmat_opts_t *opts = &o;
+    H.opts = o;
     // default launch shape per path (the autotuner may change it)
     if (opts->precision == RTE_MIXED_BF16) H.cfg = MatvecConfig{4, 64, 4};
     else H.cfg = MatvecConfig{8, 48, 4};
@@ -401,9 +403,9 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
         RTE_REQUIRE(n_bands >= 1 && n_bands <= 4096, "rte_hmat_assemble: n_bands out of range");
         hipStream_t s = (hipStream_t)stream;
         const Mesh &m = mesh->m;
-        auto plan = build_plan(m, *opts);
+        auto plan = mesh_plan(m, *opts);
         check_kappa(kappa, m.N * n_bands, s);
-        *out = assemble_hmat(m, std::move(plan), n_bands, kappa, s).release();
+        *out = assemble_hmat(m, std::move(plan), *opts, n_bands, kappa, s).release();
         return RTE_OK;
     });
 }

@@ -399,40 +399,70 @@ __global__ void k_aca_ranks(const int *__restrict__ k, const int *__restrict__ s
     if (b < nb) out[b] = status[b] == kConverged ? k[b] : -1;
 }
 
+// One piece of a block's compaction: rows [r0, r1) of U (part 0) or a range
+// [r0, r1) of V (part 1: sources for FP64 / FP32 storage, groups of 8 stored
+// source coordinates for BF16), so that the large blocks are spread over
+// many workgroups instead of setting the length of the launch.
 struct CompactTask {
     const void *su, *sv;
     void *du, *dv;
     void *dul, *dvl;      // BF16 lo parts (mixed precision)
     int64_t t0, s0;       // first target row and first source of the block
     int32_t m, n, k, li0; // li0: target leaf of t0
+    int32_t part, r0, r1, pad;
 };
+constexpr int kCompactRows = 512;   // U rows per piece
+constexpr int kCompactCols = 256;   // V sources per piece (FP64 / FP32)
+constexpr int kCompactGroups = 32;  // V groups of 8 stored coordinates per piece (BF16)
 
 // Final layout of a low-rank block (FP64 / FP32 storage): U in target-leaf
 // slices, each column-major [k][rp], and V row-major [n][kp], kp = pad4(k).
-// A thread owns a row of U (one slice lookup, then its k columns: reads of
-// the U^T rows and writes of the slice columns are contiguous across
-// threads) and 4 consecutive coefficients of a row of V (vector stores).
-// Padding stays zero (the output is cleared beforehand).
+// U: a thread owns 8 consecutive columns of one row (one slice lookup, 8
+// loads issued before any store; reads of the U^T rows and writes of the
+// slice columns are contiguous across threads).  V: [k][n] -> [n][kp] is a
+// transpose, taken through an LDS tile of 32 ranks x 64 sources so that both
+// the reads and the writes are contiguous.  Padding is written as zero.
 template <typename T>
 __global__ __launch_bounds__(256) void k_compact(const CompactTask *__restrict__ tasks, SliceMap sm) {
+    __shared__ T tile[32][65];
     const CompactTask t = tasks[blockIdx.x];
-    const T *su = static_cast<const T *>(t.su), *sv = static_cast<const T *>(t.sv);
-    T *du = static_cast<T *>(t.du), *dv = static_cast<T *>(t.dv);
-    for (int64_t i = threadIdx.x; i < t.m; i += blockDim.x) {
-        const SliceRow sr = slice_row(sm, t.li0, t.t0 + i, t.k);
-        for (int l = 0; l < t.k; ++l) du[sr.base + l * sr.rp + sr.r] = su[(int64_t)l * t.m + i];
-    }
-    const int q4 = (int)(pad4(t.k) / 4);
-    const int64_t nv = (int64_t)q4 * t.n;
-    for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
-        const int64_t j = e / q4;
-        const int l0 = 4 * (int)(e - j * q4);
-        T v[4];
+    const T *__restrict__ su = static_cast<const T *>(t.su);
+    const T *__restrict__ sv = static_cast<const T *>(t.sv);
+    T *__restrict__ du = static_cast<T *>(t.du);
+    T *__restrict__ dv = static_cast<T *>(t.dv);
+    const int m = t.m, n = t.n, k = t.k, tid = threadIdx.x;
+    if (t.part == 0) {
+        const int rows = t.r1 - t.r0;
+        const int64_t nu = (int64_t)((k + 7) / 8) * rows;
+        for (int64_t e = tid; e < nu; e += blockDim.x) {
+            const int lg = (int)(e / rows), i = t.r0 + (int)(e - (int64_t)lg * rows);
+            const SliceRow sr = slice_row(sm, t.li0, t.t0 + i, k, t.li0 + i + 1);
+            const int l0 = 8 * lg;
+            T v[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = l0 + u < t.k ? sv[(int64_t)(l0 + u) * t.n + j] : (T)0;
+            for (int u = 0; u < 8; ++u) v[u] = l0 + u < k ? su[(int64_t)(l0 + u) * m + i] : (T)0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) dv[j * 4 * q4 + l0 + u] = v[u];
+            for (int u = 0; u < 8; ++u)
+                if (l0 + u < k) du[sr.base + (int64_t)(l0 + u) * sr.rp + sr.r] = v[u];
+        }
+        return;
     }
+    const int kp = (int)pad4(k);   // the branch is uniform over the workgroup: the barriers below are safe
+    for (int j0 = t.r0; j0 < t.r1; j0 += 64)
+        for (int l0 = 0; l0 < kp; l0 += 32) {
+            const int jl = tid & 63;
+            for (int p = tid >> 6; p < 32; p += 4) {
+                const int l = l0 + p, j = j0 + jl;
+                tile[p][jl] = l < k && j < t.r1 ? sv[(int64_t)l * n + j] : (T)0;
+            }
+            __syncthreads();
+            const int ll = tid & 31;
+            for (int q = tid >> 5; q < 64; q += 8) {
+                const int l = l0 + ll, j = j0 + q;
+                if (j < t.r1 && l < kp) dv[(int64_t)j * kp + l] = tile[ll][q];
+            }
+            __syncthreads();
+        }
 }
 
 // Mixed precision (K-grouped BF16 storage): each factor element x (FP32) is
@@ -457,20 +487,23 @@ __global__ __launch_bounds__(256) void k_compact_bf16(const CompactTask *__restr
         *reinterpret_cast<uint4 *>(hi + o) = make_uint4(h[0], h[1], h[2], h[3]);
         *reinterpret_cast<uint4 *>(lo + o) = make_uint4(l[0], l[1], l[2], l[3]);
     };
-    const int kg = (t.k + 7) / 8;
-    const int64_t nu = (int64_t)kg * t.m;
-    for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) {
-        const int64_t lg = e / t.m, i = e - lg * t.m;
-        const SliceRow sr = slice_row(sm, t.li0, t.t0 + i, t.k);
-        float x[8];
+    if (t.part == 0) {
+        const int kg = (t.k + 7) / 8, rows = t.r1 - t.r0;
+        const int64_t nu = (int64_t)kg * rows;
+        for (int64_t e = threadIdx.x; e < nu; e += blockDim.x) {
+            const int64_t lg = e / rows, i = t.r0 + (e - lg * rows);
+            const SliceRow sr = slice_row(sm, t.li0, t.t0 + i, t.k, t.li0 + (int)i + 1);
+            float x[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = 8 * lg + u < t.k ? su[(8 * lg + u) * t.m + i] : 0.0f;
-        put8(uh, ul, sr.base + (lg * sr.rp + sr.r) * 8, x);
+            for (int u = 0; u < 8; ++u) x[u] = 8 * lg + u < t.k ? su[(8 * lg + u) * t.m + i] : 0.0f;
+            put8(uh, ul, sr.base + (lg * sr.rp + sr.r) * 8, x);
+        }
+        return;
     }
-    const int64_t p0 = sm.src_p[t.s0], np = sm.src_p[t.s0 + t.n] - p0;
-    const int64_t nv = (np / 8) * t.k;
+    const int64_t p0 = sm.src_p[t.s0];
+    const int64_t nv = (int64_t)(t.r1 - t.r0) * t.k;
     for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
-        const int64_t jg = e / t.k, l = e - jg * t.k;
+        const int64_t jg = t.r0 + e / t.k, l = e % t.k;
         float x[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -596,7 +629,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     st.Us = Us.as<T>();
     st.Vs = Vs.as<T>();
     auto c = make_ctx<T>(*H.mesh, kap);
-    const T eps = (T)P.opts.aca_eps;
+    const T eps = (T)H.opts.aca_eps;
     const int64_t *tn = H.tgt_nat.as<int64_t>(), *sn = H.src_nat.as<int64_t>();
     // every step raises a rank or consumes a zero row, so this bounds the steps
     int max_steps = 0;
@@ -707,8 +740,24 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
         char *du = static_cast<char *>(out.p) + off * esz, *dv = du + nu * esz;
         char *dul = split ? static_cast<char *>(outlo.p) + off * esz : nullptr;
         char *dvl = split ? dul + nu * esz : nullptr;
-        ct.push_back({Us.as<T>() + tasks[t].uoff, Vs.as<T>() + tasks[t].voff, du, dv, dul, dvl, tasks[t].t0,
-                      tasks[t].s0, tasks[t].m, tasks[t].n, rk[t], P.leaf_of(tasks[t].t0)});
+        const CompactTask whole{Us.as<T>() + tasks[t].uoff, Vs.as<T>() + tasks[t].voff, du, dv, dul, dvl,
+                                tasks[t].t0, tasks[t].s0, tasks[t].m, tasks[t].n, rk[t], P.leaf_of(tasks[t].t0),
+                                0, 0, 0, 0};
+        for (int r0 = 0; r0 < whole.m; r0 += kCompactRows) {
+            CompactTask piece = whole;
+            piece.r0 = r0;
+            piece.r1 = (int)std::min<int64_t>(whole.m, r0 + kCompactRows);
+            ct.push_back(piece);
+        }
+        const int64_t vend = split ? H.pwidth(tasks[t].s0, tasks[t].s0 + tasks[t].n) / 8 : tasks[t].n;
+        const int vstep = split ? kCompactGroups : kCompactCols;
+        for (int64_t r0 = 0; r0 < vend; r0 += vstep) {
+            CompactTask piece = whole;
+            piece.part = 1;
+            piece.r0 = (int)r0;
+            piece.r1 = (int)std::min<int64_t>(vend, r0 + vstep);
+            ct.push_back(piece);
+        }
         B.rank[b] = rk[t];
         B.U[b] = du;
         B.V[b] = dv;
@@ -743,7 +792,12 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
     B.Ulo.assign(nlr, nullptr);
     B.Vlo.assign(nlr, nullptr);
     std::vector<Block> fallback;
-    const size_t scratch_limit = (size_t)8 << 30;   // bytes of U/V scratch per batch
+    // bytes of U/V scratch per batch: a quarter of the free memory, within
+    // [2, 48] GiB (one batch for the common sizes: every batch has its own
+    // set-up and its own tail of a few high-rank blocks)
+    size_t free_b = 0, total_b = 0;
+    HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+    const size_t scratch_limit = std::clamp(free_b / 4, (size_t)2 << 30, (size_t)48 << 30);
     // First pass: every admissible block with the rank cap kAcaMaxRank.  Second
     // pass: the blocks that reached it while their break-even rank is larger
     // (large, barely admissible blocks, common with a reflective wall, whose

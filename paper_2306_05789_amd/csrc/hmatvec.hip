@@ -910,35 +910,48 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
             maxk = std::max<int64_t>(maxk, k);
             ktot += k;
         }
-        std::vector<std::vector<Seg>> per(leaves.size());
         // one segment per (block, target leaf slice); slice li of a block with K
-        // columns starts K * (prp[li] - prp[li0]) elements after the block
-        auto slices = [&](const Block &bl, const void *hi, const void *lo, int64_t K, int64_t coef, int is_lr) {
+        // columns starts K * (prp[li] - prp[li0]) elements after the block.
+        // Laid out per target leaf (dense blocks, then low-rank ones, each in
+        // block order): a counting pass, then a filling pass.
+        const int64_t nleaf = (int64_t)leaves.size();
+        auto for_slices = [&](const Block &bl, auto &&fn) {
             const int64_t li0 = leaf_of(bl.t0);
+            for (int64_t li = li0; li < nleaf && leaves[li].first < bl.t1; ++li) fn(li0, li);
+        };
+        std::vector<int64_t> pos(nleaf + 1, 0);
+        auto count = [&](int64_t, int64_t li) { ++pos[li + 1]; };
+        for (const Block &bl : B.dense_blocks) for_slices(bl, count);
+        for (size_t b = 0; b < P.lowrank.size(); ++b)
+            if (B.rank[b] > 0) for_slices(P.lowrank[b], count);
+        const int64_t base = (int64_t)segs.size();
+        for (int64_t li = 0; li < nleaf; ++li) pos[li + 1] += pos[li];
+        segs.resize((size_t)(base + pos[nleaf]));
+        std::vector<int64_t> cur(pos.begin(), pos.end() - 1);
+        auto put = [&](const Block &bl, const void *hi, const void *lo, int64_t K, int64_t coef, int is_lr) {
             const int64_t Kp = (K + g - 1) / g * g;
-            for (int64_t li = li0; li < (int64_t)leaves.size() && leaves[li].first < bl.t1; ++li) {
+            for_slices(bl, [&](int64_t li0, int64_t li) {
                 const int64_t off = Kp * (H.leaf_prp_h[li] - H.leaf_prp_h[li0]) * esz;
                 const int32_t rp = (int32_t)(H.leaf_prp_h[li + 1] - H.leaf_prp_h[li]);
-                per[li].push_back({static_cast<const char *>(hi) + off,
-                                   lo ? static_cast<const char *>(lo) + off : nullptr, coef, rp, 0, (int32_t)K,
-                                   is_lr});
-            }
+                segs[(size_t)(base + cur[li]++)] = {static_cast<const char *>(hi) + off,
+                                                    lo ? static_cast<const char *>(lo) + off : nullptr, coef, rp, 0,
+                                                    (int32_t)K, is_lr};
+            });
         };
         for (size_t d = 0; d < B.dense_blocks.size(); ++d) {
             const Block &bl = B.dense_blocks[d];
-            slices(bl, B.dense_ptr[d], B.dense_lo[d], H.pwidth(bl.s0, bl.s1), H.src_p_h[bl.s0], 0);
+            put(bl, B.dense_ptr[d], B.dense_lo[d], H.pwidth(bl.s0, bl.s1), H.src_p_h[bl.s0], 0);
         }
         for (size_t b = 0; b < P.lowrank.size(); ++b) {
             if (B.rank[b] <= 0) continue;
-            slices(P.lowrank[b], B.U[b], B.Ulo.empty() ? nullptr : B.Ulo[b], B.rank[b], toff[b], 1);
+            put(P.lowrank[b], B.U[b], B.Ulo.empty() ? nullptr : B.Ulo[b], B.rank[b], toff[b], 1);
         }
-        for (size_t li = 0; li < leaves.size(); ++li) {
+        for (int64_t li = 0; li < nleaf; ++li) {
             LeafWork w{};
             w.r0 = leaves[li].first;
             w.rows = (int32_t)(leaves[li].second - leaves[li].first);
-            w.seg0 = (int32_t)segs.size();
-            segs.insert(segs.end(), per[li].begin(), per[li].end());
-            w.seg1 = (int32_t)segs.size();
+            w.seg0 = (int32_t)(base + pos[li]);
+            w.seg1 = (int32_t)(base + pos[li + 1]);
             w.band = bi;
             lw.push_back(w);
             mp->max_rows = std::max(mp->max_rows, w.rows);

@@ -23,6 +23,10 @@
 //     in the ACA and fall back to dense storage after the ACA's work;
 //   - when one side of a non-admissible block is a leaf, the other is split.
 #include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
 
 #include "rte_internal.h"
 
@@ -146,7 +150,7 @@ ClusterTree build_cluster_tree(const std::vector<double> &pts, int leaf_size) {
     return T;
 }
 
-std::unique_ptr<Plan> build_plan(const Mesh &m, const rte_hmat_opts_t &o) {
+void validate_opts(const Mesh &m, const rte_hmat_opts_t &o) {
     RTE_REQUIRE(o.kind == RTE_VOLUME || o.kind == RTE_SURFACE, "opts.kind must be RTE_VOLUME or RTE_SURFACE");
     RTE_REQUIRE(o.leaf_size >= 1 && o.leaf_size <= 1024, "opts.leaf_size must be in [1, 1024]");
     RTE_REQUIRE(o.dense || (o.eta > 0 && std::isfinite(o.eta)), "opts.eta must be > 0");
@@ -154,6 +158,10 @@ std::unique_ptr<Plan> build_plan(const Mesh &m, const rte_hmat_opts_t &o) {
     RTE_REQUIRE(o.precision == RTE_FP64 || o.precision == RTE_FP32 || o.precision == RTE_MIXED_BF16,
                 "opts.precision must be RTE_FP64, RTE_FP32 or RTE_MIXED_BF16");
     if (o.kind == RTE_SURFACE) RTE_REQUIRE(m.L > 0, "surface matrix: the mesh has no emitting face");
+}
+
+std::unique_ptr<Plan> build_plan(const Mesh &m, const rte_hmat_opts_t &o) {
+    validate_opts(m, o);
     auto P = std::make_unique<Plan>();
     P->opts = o;
     auto pts = m.positions();
@@ -176,6 +184,30 @@ std::unique_ptr<Plan> build_plan(const Mesh &m, const rte_hmat_opts_t &o) {
         P->leaf_start.push_back(lf.second);
     }
     return P;
+}
+
+struct PlanCache {
+    std::mutex mu;
+    std::map<std::tuple<int, int, int, double>, std::shared_ptr<const Plan>> plans;
+};
+
+std::shared_ptr<PlanCache> new_plan_cache() { return std::make_shared<PlanCache>(); }
+
+std::shared_ptr<const Plan> mesh_plan(const Mesh &m, const rte_hmat_opts_t &o) {
+    validate_opts(m, o);
+    RTE_REQUIRE(m.plans != nullptr, "mesh_plan: mesh without a plan cache");
+    const auto key = std::make_tuple((int)o.kind, (int)(o.dense != 0), (int)o.leaf_size, o.dense ? 0.0 : o.eta);
+    PlanCache &C = *m.plans;
+    {
+        std::lock_guard<std::mutex> g(C.mu);
+        auto it = C.plans.find(key);
+        if (it != C.plans.end()) return it->second;
+    }
+    std::shared_ptr<const Plan> P = build_plan(m, o);   // outside the lock: G and S build theirs concurrently
+    std::lock_guard<std::mutex> g(C.mu);
+    if (C.plans.size() >= 16) C.plans.clear();   // a bound, not a policy: a handful of option sets in practice
+    auto ins = C.plans.emplace(key, P);
+    return ins.first->second;
 }
 
 }  // namespace rte

@@ -38,8 +38,10 @@ struct SliceMap {
 struct SliceRow {
     int64_t base, rp, r;
 };
-__device__ __forceinline__ SliceRow slice_row(const SliceMap &sm, int li0, int64_t grow, int64_t K) {
-    int lo = li0, hi = sm.nleaf;   // start[lo] <= grow < start[hi]
+// `hi_bound` (optional) is a leaf index known to lie past the row's leaf.
+__device__ __forceinline__ SliceRow slice_row(const SliceMap &sm, int li0, int64_t grow, int64_t K,
+                                              int hi_bound = 0x7fffffff) {
+    int lo = li0, hi = hi_bound < sm.nleaf ? hi_bound : sm.nleaf;   // start[lo] <= grow < start[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (sm.start[mid] <= grow) lo = mid;
@@ -51,8 +53,9 @@ __device__ __forceinline__ SliceRow slice_row(const SliceMap &sm, int li0, int64
 
 // element offset of (row `grow`, stored column `col`) in a block of stored
 // width K whose first target leaf is li0
-__device__ __forceinline__ int64_t slice_offset(const SliceMap &sm, int li0, int64_t grow, int64_t K, int64_t col) {
-    const SliceRow sr = slice_row(sm, li0, grow, K);
+__device__ __forceinline__ int64_t slice_offset(const SliceMap &sm, int li0, int64_t grow, int64_t K, int64_t col,
+                                                int hi_bound = 0x7fffffff) {
+    const SliceRow sr = slice_row(sm, li0, grow, K, hi_bound);
     const int64_t g = sm.g;
     return sr.base + ((col / g) * sr.rp + sr.r) * g + col % g;
 }

@@ -276,6 +276,7 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
     M.N = N;
     for (int a = 0; a < 3; ++a) M.h[a] = (d.hi[a] - d.lo[a]) / (d.n[a] - 1);
     M.near = std::make_shared<NearTables>();
+    M.plans = new_plan_cache();
     M.near->host = make_near_table(M.h);
     M.emitting.clear();
     for (int64_t v = 0; v < N; ++v) {

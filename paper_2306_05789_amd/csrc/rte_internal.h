@@ -96,6 +96,8 @@ struct NearTables {
     ~NearTables();
 };
 
+struct PlanCache;   // block-tree plans of a mesh (htree.cpp)
+
 struct Mesh {
     rte_mesh_desc_t desc{};
     int64_t N = 0, L = 0;
@@ -103,6 +105,7 @@ struct Mesh {
     std::vector<int64_t> emitting;   // natural ids, ascending
     GridDev dev{};
     std::shared_ptr<NearTables> near;
+    std::shared_ptr<PlanCache> plans;
     const void *near_table(bool fp64) const;   // device copy on the current device
     std::vector<double> positions() const;            // [N][3]
     std::vector<double> emitting_positions() const;   // [L][3]
@@ -152,7 +155,14 @@ struct Plan {
     int leaf_of(int64_t row) const;    // target leaf holding a row (cluster order)
 };
 
+void validate_opts(const Mesh &m, const rte_hmat_opts_t &opts);
 std::unique_ptr<Plan> build_plan(const Mesh &m, const rte_hmat_opts_t &opts);
+// The plan of a mesh for (kind, leaf size, eta, dense), built on first use and
+// shared afterwards: the trees and the block partition depend on the geometry
+// and these options only, not on kappa, precision or the ACA tolerance (the
+// returned plan's own `opts` are those of its first use).  Thread-safe.
+std::shared_ptr<const Plan> mesh_plan(const Mesh &m, const rte_hmat_opts_t &opts);
+std::shared_ptr<PlanCache> new_plan_cache();
 
 // ---------------------------------------------------------------- device memory helper
 struct DevBuf {
@@ -242,7 +252,8 @@ struct MatvecConfig {
 
 struct HMat {
     const Mesh *mesh = nullptr;     // not owned: the mesh must outlive the matrix
-    std::unique_ptr<Plan> plan;
+    std::shared_ptr<const Plan> plan;
+    rte_hmat_opts_t opts{};   // the options of this assembly
     int n_bands = 0;
     int precision = RTE_FP64;
     int kind = RTE_VOLUME;
@@ -307,7 +318,8 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
 struct rte_mesh { rte::Mesh m; };
 struct rte_hmat;
 namespace rte {
-std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::unique_ptr<Plan> plan, int n_bands, const double *kappa,
+std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Plan> plan,
+                                        const rte_hmat_opts_t &opts, int n_bands, const double *kappa,
                                         hipStream_t s);
 }
 struct rte_plan { std::unique_ptr<rte::Plan> p; };

@@ -277,7 +277,7 @@ struct Server {
         const int64_t esz = mixed() ? 4 : 8;
         int64_t e = 0;
         for (int kind : {RTE_VOLUME, RTE_SURFACE}) {
-            auto P = build_plan(m, opts(kind));
+            auto P = mesh_plan(m, opts(kind));
             for (auto &b : P->dense) e += (b.t1 - b.t0) * (b.s1 - b.s0);
             for (auto &b : P->lowrank) {
                 const int64_t mm = b.t1 - b.t0, nn = b.s1 - b.s0;
@@ -327,14 +327,15 @@ struct Server {
         std::thread ts([&] {
             try {
                 HIP_CHECK(hipSetDevice(device));
-                Sop = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_SURFACE)), 1, kap.as<double>(), as2);
+                Sop = assemble_hmat(M.mesh, mesh_plan(M.mesh, opts(RTE_SURFACE)), opts(RTE_SURFACE), 1, kap.as<double>(),
+                                     as2);
             } catch (...) {
                 serr = std::current_exception();
             }
         });
         std::exception_ptr gerr;
         try {
-            op->G = assemble_hmat(M.mesh, build_plan(M.mesh, opts(RTE_VOLUME)), 1, kap.as<double>(), as);
+            op->G = assemble_hmat(M.mesh, mesh_plan(M.mesh, opts(RTE_VOLUME)), opts(RTE_VOLUME), 1, kap.as<double>(), as);
         } catch (...) {
             gerr = std::current_exception();
         }
