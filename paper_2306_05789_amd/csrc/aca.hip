@@ -191,12 +191,19 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_rows(EntryC
     if (e >= total) return;
     const int b = find_block(st.rowoff, st.nb, e);
     if (st.status[b] != kActive) return;
-    const AcaTask tk = st.task[b];
     const int j = (int)(e - st.rowoff[b]);
+    T a;
+    {
+        const AcaTask tk = st.task[b];
+        a = entry<T, KIND>(c, tgt_nat[tk.t0 + st.istar[b]], src_nat[tk.s0 + j]);
+    }
+    // the block's state is read again after the march (only b and j stay
+    // live through it; the barrier keeps the compiler from reusing the loads)
+    asm volatile("" ::: "memory");
+    const AcaTask tk = st.task[b];
     const int k = st.k[b], is = st.istar[b];
     const T *U = st.Us + tk.uoff;
     T *V = st.Vs + tk.voff;
-    T a = entry<T, KIND>(c, tgt_nat[tk.t0 + is], src_nat[tk.s0 + j]);
     for (int l = 0; l < k; ++l) a -= U[(int64_t)l * tk.m + is] * V[(int64_t)l * tk.n + j];
     V[(int64_t)k * tk.n + j] = a;
 }
@@ -255,12 +262,17 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_cols(EntryC
     if (e >= total) return;
     const int b = find_block(st.coloff, st.nb, e);
     if (st.status[b] != kActive || !st.havepiv[b]) return;
-    const AcaTask tk = st.task[b];
     const int i = (int)(e - st.coloff[b]);
+    T a;
+    {
+        const AcaTask tk = st.task[b];
+        a = entry<T, KIND>(c, tgt_nat[tk.t0 + i], src_nat[tk.s0 + st.jstar[b]]);
+    }
+    asm volatile("" ::: "memory");   // as in k_aca_rows
+    const AcaTask tk = st.task[b];
     const int k = st.k[b], js = st.jstar[b];
     T *U = st.Us + tk.uoff;
     const T *V = st.Vs + tk.voff;
-    T a = entry<T, KIND>(c, tgt_nat[tk.t0 + i], src_nat[tk.s0 + js]);
     // V_l(j*) for l < k is already scaled; V_k is scaled in step 4
     for (int l = 0; l < k; ++l) a -= V[(int64_t)l * tk.n + js] * U[(int64_t)l * tk.m + i];
     U[(int64_t)k * tk.m + i] = a;
@@ -726,6 +738,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     HIP_CHECK(hipMemsetAsync(out.p, 0, out.bytes, s));   // slice and row padding stays zero
     if (split) HIP_CHECK(hipMemsetAsync(outlo.p, 0, outlo.bytes, s));
     std::vector<CompactTask> ct;
+    ct.reserve((size_t)nb * 2);
     int64_t off = 0;
     for (int t = 0; t < nb; ++t) {
         const size_t b = ids[t];

@@ -846,11 +846,7 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     const int tiles = H.cfg.tiles;
     const int64_t esz = H.precision == RTE_FP64 ? 8 : H.precision == RTE_FP32 ? 4 : 2;
     const auto &leaves = P.tgt_leaves;
-    std::vector<int64_t> starts;
-    for (auto &lf : leaves) starts.push_back(lf.first);
-    auto leaf_of = [&](int64_t row) {
-        return (int64_t)(std::upper_bound(starts.begin(), starts.end(), row) - starts.begin()) - 1;
-    };
+    auto leaf_of = [&](int64_t row) { return (int64_t)P.leaf_of(row); };
     std::vector<Seg> segs;
     std::vector<LeafWork> lw;
     const bool mf = H.precision == RTE_MIXED_BF16;

@@ -134,11 +134,6 @@ struct BlockBuilder {
 
 }  // namespace
 
-int Plan::leaf_of(int64_t row) const {
-    // leaf_start is increasing; the last entry is N_tgt
-    return (int)(std::upper_bound(leaf_start.begin(), leaf_start.end() - 1, row) - leaf_start.begin()) - 1;
-}
-
 ClusterTree build_cluster_tree(const std::vector<double> &pts, int leaf_size) {
     ClusterTree T;
     int64_t n = (int64_t)pts.size() / 3;
@@ -183,6 +178,9 @@ std::unique_ptr<Plan> build_plan(const Mesh &m, const rte_hmat_opts_t &o) {
         P->leaf_start.back() = lf.first;
         P->leaf_start.push_back(lf.second);
     }
+    P->row_leaf.resize(P->tgt_nat.size());
+    for (size_t li = 0; li < P->tgt_leaves.size(); ++li)
+        for (int64_t r = P->tgt_leaves[li].first; r < P->tgt_leaves[li].second; ++r) P->row_leaf[(size_t)r] = (int32_t)li;
     return P;
 }
 

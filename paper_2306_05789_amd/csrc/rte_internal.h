@@ -152,7 +152,8 @@ struct Plan {
     std::vector<Block> dense, lowrank;
     std::vector<std::pair<int64_t, int64_t>> tgt_leaves;   // [start, stop) of target leaves
     std::vector<int64_t> leaf_start;   // [n_leaves + 1] first row of each target leaf, then N_tgt
-    int leaf_of(int64_t row) const;    // target leaf holding a row (cluster order)
+    std::vector<int32_t> row_leaf;     // [N_tgt] target leaf of each row (cluster order)
+    int leaf_of(int64_t row) const { return row_leaf[(size_t)row]; }
 };
 
 void validate_opts(const Mesh &m, const rte_hmat_opts_t &opts);
