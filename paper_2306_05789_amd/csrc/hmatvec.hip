@@ -28,6 +28,12 @@
 // of x or t.  The low operator (inner sweeps) takes hi factors times hi + mid
 // with FP32 accumulation; the accurate operator takes hi + lo factors times
 // hi + mid + lo and adds every 32-column step's FP32 result into FP64.
+// FP64 storage with more than 4 right-hand sides runs both phases on the
+// FP64 matrix cores (v_mfma_f64_16x16x4_f64) over the same work lists, 16
+// right-hand sides per pass, so the operator is streamed once per 16 instead
+// of once per 4: a 16-rank (phase A) or 16-row (phase B) tile times 4 sources
+// or columns times 16 right-hand sides per instruction, with 4 tiles per
+// wavefront sharing the right-hand-side operand.
 #include <algorithm>
 #include <map>
 #include <tuple>
@@ -309,6 +315,159 @@ __global__ __launch_bounds__(64 * W) void k_phase_b(const LeafWork *__restrict__
             }
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- FP64 matrix cores, 16 right-hand sides
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// D += A B with A 16 x 4 (lane l holds A[l % 16][l / 16]), B 4 x 16 (lane l
+// holds B[l / 16][l % 16]); lane l's component v of D is D[4 v + l / 16][l % 16]
+__device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Phase A: one wavefront per task (a chunk of V [nj][kp] rows), ranks in
+// slices of 64 = 4 tiles of 16.  A lane loads 2 consecutive ranks of a row in
+// one 16-byte load: the even one feeds tile 0 (2) and the odd one tile 1
+// (3), so tile tl holds the ranks L0 + 32 (tl / 2) + 2 i + tl % 2, i < 16.  A
+// rank past k but inside the row's padding to 4 reads the padding's zero.
+// Per step of 4 sources a lane also loads one x value (right-hand side
+// l % 16, source l / 16).
+__global__ __launch_bounds__(256) void k_phase_a_mf64(const VtTask *__restrict__ tasks, int64_t ntask,
+                                                      const double *__restrict__ x, int64_t ldx, int64_t xbs,
+                                                      double *__restrict__ t, int64_t ldt, double *__restrict__ part,
+                                                      int64_t ldp, int r0, int nr) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= ntask) return;
+    const int lane = threadIdx.x & 63, col = lane & 15, sub = lane >> 4;
+    const VtTask tk = tasks[w];
+    double *dst = tk.partial ? part : t;
+    const int64_t ldd = tk.partial ? ldp : ldt;
+    const int kp = (int)pad4(tk.k);
+    const double *V = static_cast<const double *>(tk.V);
+    const bool xl = col < nr;
+    const double *xr = x + (int64_t)tk.band * xbs + (int64_t)(r0 + (xl ? col : 0)) * ldx + tk.s0;
+    for (int L0 = 0; L0 < tk.k; L0 += 64) {
+        const bool h0 = L0 + 2 * col < tk.k, h1 = L0 + 32 + 2 * col < tk.k;
+        const bool two = L0 + 32 < tk.k;   // uniform: the second pair of tiles has ranks
+        f64x4 acc[4];
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl) acc[tl] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int jj = 0; jj < tk.nj; jj += 4) {
+            const int j = jj + sub;
+            const bool jl = j < tk.nj;
+            const double b = xl && jl ? xr[j] : 0.0;
+            const double2 *vr = reinterpret_cast<const double2 *>(V + (int64_t)j * kp + L0) + col;
+            const double2 z{0.0, 0.0};
+            const double2 a0 = jl && h0 ? vr[0] : z;
+            acc[0] = mfma64(a0.x, b, acc[0]);
+            acc[1] = mfma64(a0.y, b, acc[1]);
+            if (two) {
+                const double2 a1 = jl && h1 ? vr[16] : z;
+                acc[2] = mfma64(a1.x, b, acc[2]);
+                acc[3] = mfma64(a1.y, b, acc[3]);
+            }
+        }
+        if (xl) {
+#pragma unroll
+            for (int tl = 0; tl < 4; ++tl)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int l = L0 + 32 * (tl >> 1) + 2 * (4 * v + sub) + (tl & 1);
+                    if (l < tk.k) dst[(int64_t)(r0 + col) * ldd + tk.out + l] = acc[tl][v];
+                }
+        }
+    }
+}
+
+// Phase B: W wavefronts per (band, target leaf), every W-th segment each;
+// rows in passes of 64 = 4 tiles of 16, columns in steps of 4.  As in phase
+// A a lane loads 2 consecutive rows in one 16-byte load, so tile tl holds the
+// rows rb + 32 (tl / 2) + 2 i + tl % 2 (a row past the leaf inside the slice's
+// padding to 4 reads zero).  The W partial results are added in a fixed
+// order.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_phase_b_mf64(const LeafWork *__restrict__ leaves,
+                                                         const Seg *__restrict__ segs, const double *__restrict__ x,
+                                                         int64_t ldx, int64_t xbs, const double *__restrict__ t,
+                                                         int64_t ldt, const double *__restrict__ y0,
+                                                         double *__restrict__ y, int64_t ldy, int64_t ybs, int r0,
+                                                         int nr) {
+    __shared__ double red[W][4][4][64];
+    const LeafWork lw = leaves[blockIdx.x];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, col = lane & 15, sub = lane >> 4;
+    const bool xl = col < nr;
+    const int rc = r0 + (xl ? col : 0);   // right-hand side of this lane's coefficient loads
+    x += (int64_t)lw.band * xbs;
+    y += (int64_t)lw.band * ybs;
+    if (y0) y0 += (int64_t)lw.band * ybs;
+    for (int rb = 0; rb < lw.rows; rb += 64) {
+        const bool h0 = rb + 2 * col < lw.rows, h1 = rb + 32 + 2 * col < lw.rows;
+        const bool two = rb + 32 < lw.rows;
+        f64x4 acc[4];
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl) acc[tl] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int s = lw.seg0 + wid; s < lw.seg1; s += W) {
+            const Seg cur = segs[s];
+            const double *cr = (cur.is_lr ? t + (int64_t)rc * ldt : x + (int64_t)rc * ldx) + cur.coef_off;
+            const double *D = static_cast<const double *>(cur.data) + rb;
+#pragma unroll 4
+            for (int c0 = 0; c0 < cur.K; c0 += 4) {
+                const int c = c0 + sub;
+                const bool cl = c < cur.K;
+                const double b = xl && cl ? cr[c] : 0.0;
+                const double2 *dc = reinterpret_cast<const double2 *>(D + (int64_t)c * cur.ld) + col;
+                const double2 z{0.0, 0.0};
+                const double2 a0 = cl && h0 ? dc[0] : z;
+                acc[0] = mfma64(a0.x, b, acc[0]);
+                acc[1] = mfma64(a0.y, b, acc[1]);
+                if (two) {
+                    const double2 a1 = cl && h1 ? dc[16] : z;
+                    acc[2] = mfma64(a1.x, b, acc[2]);
+                    acc[3] = mfma64(a1.y, b, acc[3]);
+                }
+            }
+        }
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[wid][tl][v][lane] = acc[tl][v];
+        __syncthreads();
+        if (wid == 0 && xl) {
+#pragma unroll
+            for (int tl = 0; tl < 4; ++tl)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rb + 32 * (tl >> 1) + 2 * (4 * v + sub) + (tl & 1);
+                    if (row < lw.rows) {
+                        double sum = red[0][tl][v][lane];
+#pragma unroll
+                        for (int q = 1; q < W; ++q) sum += red[q][tl][v][lane];
+                        const int64_t at = (int64_t)(r0 + col) * ldy + lw.r0 + row;
+                        y[at] = (y0 ? y0[at] : 0.0) + sum;
+                    }
+                }
+        }
+        __syncthreads();
+    }
+}
+
+// Partial sums of the chunked blocks of phase A, 16 right-hand sides: a
+// workgroup per block, a thread per (right-hand side, rank), the chunks added
+// in order.
+__global__ __launch_bounds__(256) void k_phase_a_reduce16(const VtReduce *__restrict__ red,
+                                                          const double *__restrict__ part, int64_t ldp,
+                                                          double *__restrict__ t, int64_t ldt, int r0, int nr) {
+    const VtReduce rd = red[blockIdx.x];
+    const int n = nr * rd.k;
+    for (int e = threadIdx.x; e < n; e += 256) {
+        const int r = e / rd.k, w = e - r * rd.k;
+        const double *p = part + (int64_t)(r0 + r) * ldp + rd.part + w;
+        double s = 0.0;
+        for (int c = 0; c < rd.chunks; ++c) s += p[(int64_t)c * rd.k];
+        t[(int64_t)(r0 + r) * ldt + rd.toff + w] = s;
     }
 }
 
@@ -724,16 +883,47 @@ void phase_b_valu(int W, unsigned gb, const LeafWork *lw, const Seg *sg, const d
         k_phase_b<ST, MODE, A, NR, 8><<<gb, 512, 0, s>>>(lw, sg, x, ldx, xbs, t, ldt, y0, y, ldy, ybs, r0, nr);
 }
 
-// wb: wavefronts per phase B workgroup.  Right-hand sides go in groups of at
-// most 4: with 16 per launch the accumulators (4 rows x 16 columns per lane)
-// leave one wavefront per SIMD and the stream stalls, so four passes over the
-// matrix are faster than one.
+// wb: wavefronts per phase B workgroup.  FP64 with more than 4 right-hand
+// sides: the matrix-core kernels, 16 per pass.  Otherwise groups of at most 4
+// on the vector ALUs: with 16 per launch the accumulators (4 rows x 16
+// columns per lane) leave one wavefront per SIMD and the stream stalls.
 template <int ST, int MODE, typename A>
 void launch_typed(const MatvecPlan &mp, int nrhs, const double *x, const double *y0, double *y, double *tb,
                   hipStream_t s, int wb) {
     double *part = tb + mp.ktot * (int64_t)nrhs;   // the workspace holds t, then the partials
     const int64_t ldp = std::max<int64_t>(mp.npart, 1);
     const int64_t xbs = (int64_t)nrhs * mp.n_src, ybs = (int64_t)nrhs * mp.n_tgt;
+    if constexpr (ST == ST_F64) {
+        if (nrhs > 4) {   // 16 right-hand sides per pass on the matrix cores
+            for (int r0 = 0; r0 < nrhs; r0 += 16) {
+                const int nr = std::min(16, nrhs - r0);
+                if (mp.n_vt) {
+                    k_phase_a_mf64<<<(unsigned)((mp.n_vt + 3) / 4), 256, 0, s>>>(
+                        mp.vt.as<VtTask>(), mp.n_vt, x, mp.n_src, xbs, tb, mp.ktot, part, ldp, r0, nr);
+                    HIP_LAUNCH_CHECK();
+                    if (mp.n_red) {
+                        k_phase_a_reduce16<<<(unsigned)mp.n_red, 256, 0, s>>>(mp.red.as<VtReduce>(), part, ldp, tb,
+                                                                             mp.ktot, r0, nr);
+                        HIP_LAUNCH_CHECK();
+                    }
+                }
+                const unsigned gb = (unsigned)mp.n_leaf;
+                const LeafWork *lw = mp.leaf.as<LeafWork>();
+                const Seg *sg = mp.seg.as<Seg>();
+                if (wb == 2)
+                    k_phase_b_mf64<2><<<gb, 128, 0, s>>>(lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt, ybs,
+                                                         r0, nr);
+                else if (wb == 4)
+                    k_phase_b_mf64<4><<<gb, 256, 0, s>>>(lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt, ybs,
+                                                         r0, nr);
+                else
+                    k_phase_b_mf64<8><<<gb, 512, 0, s>>>(lw, sg, x, mp.n_src, xbs, tb, mp.ktot, y0, y, mp.n_tgt, ybs,
+                                                         r0, nr);
+                HIP_LAUNCH_CHECK();
+            }
+            return;
+        }
+    }
     constexpr int kGroup = 4;
     for (int r0 = 0; r0 < nrhs; r0 += kGroup) {
         const int nr = std::min(kGroup, nrhs - r0);

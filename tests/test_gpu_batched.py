@@ -33,10 +33,10 @@ def _assemble(mesh, wl, kind, precision):
 def test_batched_matvec_equals_single_calls(small, precision):
     """Every band and right-hand side of the batched product equals the single-band,
     single right-hand-side product.  On the matrix cores (BF16 storage) every column
-    is reduced in the same fixed order whatever shares the launch: bit for bit.  The
-    vector-ALU kernels (FP64, FP32) take right-hand sides in groups of 4, with kernels
-    instantiated per group width that the compiler may contract differently: rounding
-    level."""
+    is reduced in the same fixed order whatever shares the launch: bit for bit.  FP64
+    with 16 right-hand sides runs on the FP64 matrix cores and one at a time on the
+    vector ALUs, FP32 in groups of 4 with kernels instantiated per group width that
+    the compiler may contract differently: rounding level."""
     wl, mesh = small
     G = _assemble(mesh, wl, rte.RTE_VOLUME, precision)
     nb, nr = wl.kappa.shape[0], 16

@@ -204,6 +204,48 @@ def test_aca_blocks_meet_the_tolerance(small_h):
     assert errs.max() < 100 * eps and np.median(errs) < 10 * eps, (errs.max(), np.median(errs))
 
 
+@pytest.mark.parametrize("nrhs", [5, 16, 20])
+def test_fp64_matrix_core_matvec(small_h, nrhs):
+    """FP64 storage with more than 4 right-hand sides runs on the FP64 matrix cores,
+    16 per pass (5: one ragged pass; 20: a full and a ragged one): against the
+    oracle's dense G within the compression bound, and against one-at-a-time
+    products (vector ALU) at the rounding level."""
+    P, mesh, kap, G, S = small_h
+    H = _assemble(mesh, kap, rte.RTE_VOLUME, leaf_size=32, eta=2.0, aca_eps=1e-5)
+    X = np.random.default_rng(30 + nrhs).uniform(-0.5, 2.0, (nrhs, mesh.N))
+    xt = torch.tensor(X, device=DEV)
+    y = torch.empty_like(xt)
+    rte.rte_hmat_matvec(H, 0, xt, y)
+    Y = y.cpu().numpy()
+    ref = X @ G.T
+    for r in range(nrhs):
+        assert np.linalg.norm(Y[r] - ref[r]) / np.linalg.norm(ref[r]) < 2e-4, r
+        y1 = torch.empty((1, mesh.N), device=DEV, dtype=torch.float64)
+        rte.rte_hmat_matvec(H, 0, xt[r:r + 1].contiguous(), y1)
+        d = np.max(np.abs(y1.cpu().numpy()[0] - Y[r])) / np.max(np.abs(Y[r]))
+        assert d < 1e-13, (r, d)
+
+
+def test_fp64_matrix_core_matvec_large_ranks():
+    """A 25^3 operator with leaf 64 has blocks of rank above 64 (several rank slices
+    per wavefront) and blocks split into source chunks (partial sums added by the
+    reduction pass): 16 right-hand sides on the matrix cores against one-at-a-time
+    products, per element, at the rounding level."""
+    n = 25
+    P, mesh, kap = _case((n, n, n), kappa=lambda X: 0.3 + 2.0 * X[:, 0] * X[:, 1] + X[:, 2] ** 2, emit=1)
+    H = _assemble(mesh, kap, rte.RTE_VOLUME, leaf_size=64, eta=2.0, aca_eps=1e-6)
+    st = rte.rte_hmat_stats(H)
+    assert st["max_rank"] > 64, st["max_rank"]
+    X = torch.tensor(np.random.default_rng(41).uniform(0.0, 1.0, (16, mesh.N)), device=DEV)
+    Y = torch.empty_like(X)
+    rte.rte_hmat_matvec(H, 0, X, Y)
+    for r in (0, 5, 15):
+        y1 = torch.empty((1, mesh.N), device=DEV, dtype=torch.float64)
+        rte.rte_hmat_matvec(H, 0, X[r:r + 1].contiguous(), y1)
+        d = torch.max(torch.abs(y1[0] - Y[r]) / torch.abs(Y[r])).item()
+        assert d < 1e-12, (r, d)
+
+
 @pytest.mark.parametrize("precision", [rte.RTE_FP64, rte.RTE_MIXED_BF16])
 def test_second_aca_pass_reproduces_a_single_pass(small_h, monkeypatch, precision):
     """Blocks that stop at the first pass's rank cap while their break-even rank is
