@@ -202,6 +202,7 @@ __global__ __launch_bounds__(256) void k_phase_a_reduce(const VtReduce *__restri
     for (int w = threadIdx.x & 63; w < rd.k; w += 64)
         for (int r = 0; r < nr; ++r) {
             double s = 0.0;
+#pragma unroll 8
             for (int c = 0; c < rd.chunks; ++c) s += part[(int64_t)(r0 + r) * ldp + rd.part + (int64_t)c * rd.k + w];
             t[(int64_t)(r0 + r) * ldt + rd.toff + w] = s;
         }
@@ -409,8 +410,13 @@ __global__ __launch_bounds__(64 * W) void k_phase_b_mf64(const LeafWork *__restr
         f64x4 acc[4];
 #pragma unroll
         for (int tl = 0; tl < 4; ++tl) acc[tl] = f64x4{0.0, 0.0, 0.0, 0.0};
-        for (int s = lw.seg0 + wid; s < lw.seg1; s += W) {
-            const Seg cur = segs[s];
+        int s = lw.seg0 + wid;
+        Seg nxt;
+        if (s < lw.seg1) nxt = segs[s];
+        for (; s < lw.seg1; s += W) {
+            // the next descriptor is fetched while this segment streams
+            const Seg cur = nxt;
+            if (s + W < lw.seg1) nxt = segs[s + W];
             const double *cr = (cur.is_lr ? t + (int64_t)rc * ldt : x + (int64_t)rc * ldx) + cur.coef_off;
             const double *D = static_cast<const double *>(cur.data) + rb;
 #pragma unroll 4
@@ -466,6 +472,7 @@ __global__ __launch_bounds__(256) void k_phase_a_reduce16(const VtReduce *__rest
         const int r = e / rd.k, w = e - r * rd.k;
         const double *p = part + (int64_t)(r0 + r) * ldp + rd.part + w;
         double s = 0.0;
+#pragma unroll 8
         for (int c = 0; c < rd.chunks; ++c) s += p[(int64_t)c * rd.k];
         t[(int64_t)(r0 + r) * ldt + rd.toff + w] = s;
     }
@@ -1163,6 +1170,22 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     std::stable_sort(mvt.begin(), mvt.end(), [](const MfVt &a, const MfVt &b) {
         return (int64_t)a.ng * a.nt > (int64_t)b.ng * b.nt;
     });
+    // phase B: the (band, leaf) items with the most columns to stream first
+    // (workgroups start in list order, so the small ones fill the tail
+    // instead of a few large ones running alone at the end)
+    {
+        std::vector<int64_t> cols(lw.size(), 0);
+        for (size_t i = 0; i < lw.size(); ++i)
+            for (int32_t q = lw[i].seg0; q < lw[i].seg1; ++q) cols[i] += segs[(size_t)q].K;
+        std::vector<size_t> ord(lw.size());
+        for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+            return cols[a] * lw[a].rows > cols[b] * lw[b].rows;
+        });
+        std::vector<LeafWork> sorted(lw.size());
+        for (size_t i = 0; i < ord.size(); ++i) sorted[i] = lw[ord[i]];
+        lw.swap(sorted);
+    }
     mp->ktot = std::max<int64_t>(ktot, mf ? 8 : 1);
     mp->npart = npart;
     mp->n_red_threads = maxk;
