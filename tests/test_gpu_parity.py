@@ -284,6 +284,31 @@ def test_second_aca_pass_reproduces_a_single_pass(small_h, monkeypatch, precisio
     assert torch.equal(y1, y2)
 
 
+def test_cached_plan_gives_the_operator_of_a_fresh_mesh(small_h):
+    """The block-tree plan is built once per (mesh, kind, leaf size, eta) and shared by
+    later assemblies whatever their kappa, precision or ACA tolerance: an operator
+    assembled on a mesh that already served other options is, bit for bit, the one a
+    fresh mesh gives."""
+    P, mesh, kap, G, S = small_h
+    n = tuple(int(v) for v in P.grid.n)
+    used = rte.rte_mesh_create(n, emit_faces=1)
+    fresh = rte.rte_mesh_create(n, emit_faces=1)
+    kap2 = (kap * 1.7 + 0.1).contiguous()
+    for o in ({}, dict(precision=rte.RTE_MIXED_BF16, aca_eps=1e-6)):   # fill the cache
+        rte.rte_hmat_assemble(used, kap[None, :].contiguous(),
+                              rte.hmat_opts(kind=rte.RTE_VOLUME, leaf_size=32, eta=2.0, **o))
+    kw = dict(kind=rte.RTE_VOLUME, leaf_size=32, eta=2.0, aca_eps=1e-4, precision=rte.RTE_FP64)
+    Hu = rte.rte_hmat_assemble(used, kap2[None, :].contiguous(), rte.hmat_opts(**kw))
+    Hf = rte.rte_hmat_assemble(fresh, kap2[None, :].contiguous(), rte.hmat_opts(**kw))
+    su, sf = rte.rte_hmat_stats(Hu), rte.rte_hmat_stats(Hf)
+    assert (su["n_lowrank"], su["max_rank"], su["bytes"]) == (sf["n_lowrank"], sf["max_rank"], sf["bytes"])
+    x = torch.tensor(np.random.default_rng(3).uniform(0, 1, (3, P.grid.N)), device=DEV)
+    yu, yf = torch.empty_like(x), torch.empty_like(x)
+    rte.rte_hmat_matvec(Hu, 0, x, yu)
+    rte.rte_hmat_matvec(Hf, 0, x, yf)
+    assert torch.equal(yu, yf)
+
+
 def test_hmatrix_solve_close_to_dense_oracle(small_h):
     P, mesh, kap, G, S = small_h
     SE = S @ np.full(len(P.emitting), osolve.SIGMA)
