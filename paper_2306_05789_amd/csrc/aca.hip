@@ -52,6 +52,9 @@ struct AcaState {
     int half;                   // partials per kind in a chunk
     T *pmax;                    // per chunk: |u| max and its signed value
     int *pidx;                  // per chunk: row of the max
+    int *hint_r, *hint_c;       // per 256 row / column entries: position in act / act2 of the
+                                // block holding the first one (set after every scan)
+    int *cblock;                // per update chunk: its block (set after every scan)
 };
 
 // elements of the concatenated (u_k, v_k) range of a block handled by one update chunk
@@ -91,16 +94,6 @@ __device__ __forceinline__ void block_argmax(T &a, int &idx, T &sv, T *sa, int *
 
 __device__ __forceinline__ bool is_used(const unsigned *bits, int r) { return (bits[r >> 5] >> (r & 31)) & 1u; }
 
-// the block whose range [off[b], off[b+1]) holds e (zero-width blocks are skipped)
-__device__ __forceinline__ int find_block(const int64_t *off, int nb, int64_t e) {
-    int lo = 0, hi = nb;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= e) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
 
 }  // namespace
 
@@ -182,6 +175,49 @@ __global__ __launch_bounds__(1024) void k_aca_scan(AcaState<T> st) {
     }
 }
 
+// For each run of 256 entries (one workgroup of the row or column launch):
+// the position in the active list of the block holding its first entry, so
+// that a lane finds its block by stepping forward over a few blocks instead
+// of a binary search over all of them.
+template <typename T, bool COLS>
+__global__ __launch_bounds__(256) void k_aca_hint(AcaState<T> st, int64_t nwg, int nact) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nwg) return;
+    const int64_t e = c * 256;
+    const int64_t *off = COLS ? st.coloff : st.rowoff;
+    const int *list = COLS ? st.act2 : st.act;
+    int lo = 0, hi = nact;   // first i with off[list[i] + 1] > e
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (off[list[mid] + 1] > e) hi = mid;
+        else lo = mid + 1;
+    }
+    (COLS ? st.hint_c : st.hint_r)[c] = lo;
+}
+
+// the block of every update chunk (a workgroup of k_aca_dots)
+template <typename T>
+__global__ __launch_bounds__(256) void k_aca_chunk_block(AcaState<T> st, int64_t nchunk, int nact) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nchunk) return;
+    int lo = 0, hi = nact;   // first i with chunkoff[act2[i] + 1] > c
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (st.chunkoff[st.act2[mid] + 1] > c) hi = mid;
+        else lo = mid + 1;
+    }
+    st.cblock[c] = st.act2[lo];
+}
+
+// the block of entry e (below the launch's total) from its workgroup's hint
+__device__ __forceinline__ int hinted_block(const int64_t *__restrict__ off, const int *__restrict__ list,
+                                            const int *__restrict__ hint, int64_t e) {
+    int i = hint[blockIdx.x];
+    int b = list[i];
+    while (off[b + 1] <= e) b = list[++i];
+    return b;
+}
+
 // Step 1: residual rows of every active block, one lane per entry.
 template <typename T, int KIND>
 __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
@@ -189,7 +225,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_rows(EntryC
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= total) return;
-    const int b = find_block(st.rowoff, st.nb, e);
+    const int b = hinted_block(st.rowoff, st.act, st.hint_r, e);
     if (st.status[b] != kActive) return;
     const int j = (int)(e - st.rowoff[b]);
     T a;
@@ -260,7 +296,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_cols(EntryC
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= total) return;
-    const int b = find_block(st.coloff, st.nb, e);
+    const int b = hinted_block(st.coloff, st.act2, st.hint_c, e);
     if (st.status[b] != kActive || !st.havepiv[b]) return;
     const int i = (int)(e - st.coloff[b]);
     T a;
@@ -295,7 +331,7 @@ __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
     __shared__ T sa[4], ss[4];
     __shared__ int si[4];
     const int64_t c = blockIdx.x;
-    const int b = find_block(st.chunkoff, st.nb, c);
+    const int b = st.cblock[c];
     if (st.status[b] != kActive || !st.havepiv[b]) return;   // uniform over the workgroup
     const AcaTask tk = st.task[b];
     const int k = st.k[b], m = tk.m, n = tk.n;
@@ -614,6 +650,12 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
         used(sizeof(unsigned) * (size_t)words), offs(sizeof(int64_t) * (size_t)(nb + 1) * 3),
         tot(sizeof(int64_t) * 5), part(sizeof(T) * (size_t)max_chunks * 2 * (size_t)(kmax + 1)),
         pmax(sizeof(T) * (size_t)max_chunks * 2), pidx(sizeof(int) * (size_t)max_chunks);
+    int64_t sum_m = 0, sum_n = 0;
+    for (auto &t : tasks) {
+        sum_m += t.m;
+        sum_n += t.n;
+    }
+    DevBuf hints(sizeof(int) * (size_t)((sum_n + 255) / 256 + (sum_m + 255) / 256 + 2));
     AcaState<T> st;
     st.task = dt.as<AcaTask>();
     st.nb = nb;
@@ -638,6 +680,10 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     st.half = kmax + 1;
     st.pmax = pmax.as<T>();
     st.pidx = pidx.as<int>();
+    st.hint_r = hints.as<int>();
+    st.hint_c = hints.as<int>() + (sum_n + 255) / 256 + 1;
+    DevBuf cblock(sizeof(int) * (size_t)std::max<int64_t>(max_chunks, 1));
+    st.cblock = cblock.as<int>();
     st.Us = Us.as<T>();
     st.Vs = Vs.as<T>();
     auto c = make_ctx<T>(*H.mesh, kap);
@@ -674,6 +720,11 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
         HIP_CHECK(hipStreamSynchronize(s));
         if (ht[1] == 0) break;
         const int64_t nrow = ht[0], nact = ht[1], ncol = ht[2], nchunk = ht[4];
+        const int64_t wr = (nrow + 255) / 256, wc = (ncol + 255) / 256;
+        k_aca_hint<T, false><<<(unsigned)((wr + 255) / 256), 256, 0, s>>>(st, wr, (int)nact);
+        k_aca_hint<T, true><<<(unsigned)((wc + 255) / 256), 256, 0, s>>>(st, wc, (int)ht[3]);
+        k_aca_chunk_block<T><<<(unsigned)((nchunk + 255) / 256), 256, 0, s>>>(st, nchunk, (int)ht[3]);
+        HIP_LAUNCH_CHECK();
         for (int r = 0; r < kCompact && step <= max_steps; ++r, ++step) {
             mark();
             if (H.kind == RTE_VOLUME)

@@ -355,7 +355,6 @@ __global__ __launch_bounds__(256) void k_phase_a_mf64(const VtTask *__restrict__
         f64x4 acc[4];
 #pragma unroll
         for (int tl = 0; tl < 4; ++tl) acc[tl] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
         for (int jj = 0; jj < tk.nj; jj += 4) {
             const int j = jj + sub;
             const bool jl = j < tk.nj;
@@ -419,7 +418,6 @@ __global__ __launch_bounds__(64 * W) void k_phase_b_mf64(const LeafWork *__restr
             if (s + W < lw.seg1) nxt = segs[s + W];
             const double *cr = (cur.is_lr ? t + (int64_t)rc * ldt : x + (int64_t)rc * ldx) + cur.coef_off;
             const double *D = static_cast<const double *>(cur.data) + rb;
-#pragma unroll 4
             for (int c0 = 0; c0 < cur.K; c0 += 4) {
                 const int c = c0 + sub;
                 const bool cl = c < cur.K;
