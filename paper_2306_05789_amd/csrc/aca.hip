@@ -218,6 +218,28 @@ __device__ __forceinline__ int hinted_block(const int64_t *__restrict__ off, con
     return b;
 }
 
+// a - sum_l p[l * sp] q[l * sq], l < k, subtracted in order of l; the loads
+// of 8 terms are issued before their products (the factors were written by
+// earlier rank steps and come from L2 or HBM).  Terms past k are zero and
+// subtracting them leaves a unchanged, so the result is that of the plain
+// loop.
+template <typename T>
+__device__ __forceinline__ T residual(T a, const T *p, int64_t sp, const T *q, int64_t sq, int k) {
+    constexpr int B = 8;
+    for (int l = 0; l < k; l += B) {
+        T x[B], y[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const bool in = l + u < k;
+            x[u] = in ? p[(int64_t)(l + u) * sp] : (T)0;
+            y[u] = in ? q[(int64_t)(l + u) * sq] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) a -= x[u] * y[u];
+    }
+    return a;
+}
+
 // Step 1: residual rows of every active block, one lane per entry.
 template <typename T, int KIND>
 __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
@@ -240,7 +262,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_rows(EntryC
     const int k = st.k[b], is = st.istar[b];
     const T *U = st.Us + tk.uoff;
     T *V = st.Vs + tk.voff;
-    for (int l = 0; l < k; ++l) a -= U[(int64_t)l * tk.m + is] * V[(int64_t)l * tk.n + j];
+    a = residual(a, U + is, tk.m, V + j, tk.n, k);
     V[(int64_t)k * tk.n + j] = a;
 }
 
@@ -310,7 +332,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_cols(EntryC
     T *U = st.Us + tk.uoff;
     const T *V = st.Vs + tk.voff;
     // V_l(j*) for l < k is already scaled; V_k is scaled in step 4
-    for (int l = 0; l < k; ++l) a -= V[(int64_t)l * tk.n + js] * U[(int64_t)l * tk.m + i];
+    a = residual(a, V + js, tk.n, U + i, tk.m, k);
     U[(int64_t)k * tk.m + i] = a;
 }
 
