@@ -42,6 +42,7 @@ struct SliceRow {
 __device__ __forceinline__ SliceRow slice_row(const SliceMap &sm, int li0, int64_t grow, int64_t K,
                                               int hi_bound = 0x7fffffff) {
     int lo = li0, hi = hi_bound < sm.nleaf ? hi_bound : sm.nleaf;   // start[lo] <= grow < start[hi]
+    if (hi - lo > 1 && sm.start[lo + 1] > grow) hi = lo + 1;         // in the first leaf: the common case
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (sm.start[mid] <= grow) lo = mid;
