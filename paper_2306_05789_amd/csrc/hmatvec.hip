@@ -1168,22 +1168,6 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
     std::stable_sort(mvt.begin(), mvt.end(), [](const MfVt &a, const MfVt &b) {
         return (int64_t)a.ng * a.nt > (int64_t)b.ng * b.nt;
     });
-    // phase B: the (band, leaf) items with the most columns to stream first
-    // (workgroups start in list order, so the small ones fill the tail
-    // instead of a few large ones running alone at the end)
-    {
-        std::vector<int64_t> cols(lw.size(), 0);
-        for (size_t i = 0; i < lw.size(); ++i)
-            for (int32_t q = lw[i].seg0; q < lw[i].seg1; ++q) cols[i] += segs[(size_t)q].K;
-        std::vector<size_t> ord(lw.size());
-        for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
-        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
-            return cols[a] * lw[a].rows > cols[b] * lw[b].rows;
-        });
-        std::vector<LeafWork> sorted(lw.size());
-        for (size_t i = 0; i < ord.size(); ++i) sorted[i] = lw[ord[i]];
-        lw.swap(sorted);
-    }
     mp->ktot = std::max<int64_t>(ktot, mf ? 8 : 1);
     mp->npart = npart;
     mp->n_red_threads = maxk;
