@@ -21,6 +21,7 @@
 // active block.  Reductions use wavefront shuffles and one LDS stage in a
 // fixed order, so results are bitwise reproducible.
 #include <algorithm>
+#include <map>
 #include <climits>
 #include <numeric>
 
@@ -611,7 +612,8 @@ int64_t stored_v(const HMat &H, int64_t s0, int64_t s1, int64_t k) {
 }
 
 template <typename T>
-void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Block> &blocks, hipStream_t s) {
+void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Block> &blocks, bool pair,
+                       hipStream_t s) {
     if (blocks.empty()) return;
     const Plan &P = *H.plan;
     const bool split = H.precision == RTE_MIXED_BF16;
@@ -624,18 +626,42 @@ void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Bl
     DevBuf buf(esz * (size_t)stored), lo(split ? esz * (size_t)stored : 0);
     HIP_CHECK(hipMemsetAsync(buf.p, 0, buf.bytes, s));   // the row padding stays zero
     if (split) HIP_CHECK(hipMemsetAsync(lo.p, 0, lo.bytes, s));
-    std::vector<FillTask> tasks;
+    std::vector<char *> ptr(blocks.size()), ptrl(blocks.size());
     int64_t off = 0;
-    for (auto &b : blocks) {
-        const int m = (int)(b.t1 - b.t0), n = (int)(b.s1 - b.s0), li0 = P.leaf_of(b.t0);
-        char *p = static_cast<char *>(buf.p) + off * esz;
-        char *pl = split ? static_cast<char *>(lo.p) + off * esz : nullptr;
+    for (size_t d = 0; d < blocks.size(); ++d) {
+        const Block &b = blocks[d];
+        ptr[d] = static_cast<char *>(buf.p) + off * esz;
+        ptrl[d] = split ? static_cast<char *>(lo.p) + off * esz : nullptr;
         B.dense_blocks.push_back(b);
-        B.dense_ptr.push_back(p);
-        B.dense_lo.push_back(pl);
+        B.dense_ptr.push_back(ptr[d]);
+        B.dense_lo.push_back(ptrl[d]);
+        off += round8(stored_u(H, b.t0, b.t1, H.pwidth(b.s0, b.s1)));
+    }
+    // volume operator: an off-diagonal block and its transpose are filled by
+    // one set of tasks (each lane computes G(i, j) and G(j, i) on one march)
+    std::map<std::pair<int64_t, int64_t>, size_t> at;
+    if (pair)
+        for (size_t d = 0; d < blocks.size(); ++d) at[{blocks[d].t0, blocks[d].s0}] = d;
+    std::vector<FillTask> tasks;
+    for (size_t d = 0; d < blocks.size(); ++d) {
+        const Block &b = blocks[d];
+        const int m = (int)(b.t1 - b.t0), n = (int)(b.s1 - b.s0), li0 = P.leaf_of(b.t0);
         const int32_t kw = (int32_t)H.pwidth(b.s0, b.s1);
-        for (int64_t f = 0; f < (int64_t)m * n; f += kFillChunk) tasks.push_back({p, pl, b.t0, b.s0, m, n, li0, kw, f});
-        off += round8(stored_u(H, b.t0, b.t1, kw));
+        FillTask t{ptr[d], ptrl[d], b.t0, b.s0, m, n, li0, kw, 0, nullptr, nullptr, 0, 0};
+        if (pair && b.t0 != b.s0) {
+            auto it = at.find({b.s0, b.t0});
+            if (it != at.end() && blocks[it->second].t1 == b.s1 && blocks[it->second].s1 == b.t1) {
+                if (b.t0 > b.s0) continue;   // filled with its transpose
+                t.out_t = ptr[it->second];
+                t.outlo_t = ptrl[it->second];
+                t.li0_t = P.leaf_of(b.s0);
+                t.kw_t = (int32_t)H.pwidth(b.t0, b.t1);
+            }
+        }
+        for (int64_t f = 0; f < (int64_t)m * n; f += kFillChunk) {
+            t.first = f;
+            tasks.push_back(t);
+        }
     }
     B.fill_ms += dense_fill_launch<T>(*H.mesh, H.kind, kap, tasks, H.tgt_nat.as<int64_t>(), H.src_nat.as<int64_t>(),
                                       slice_map(H), split, s);
@@ -928,13 +954,13 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
         retry.clear();
     }
     for (size_t b : todo) fallback.push_back(P.lowrank[b]);
-    fill_dense_blocks<T>(H, B, kap, fallback, s);
+    fill_dense_blocks<T>(H, B, kap, fallback, false, s);
 }
 
 template <typename T>
 void assemble_typed(HMat &H, int band, const T *kap, hipStream_t s) {
     BandStore &B = H.bands[band];
-    fill_dense_blocks<T>(H, B, kap, H.plan->dense, s);
+    fill_dense_blocks<T>(H, B, kap, H.plan->dense, H.kind == RTE_VOLUME, s);
     run_aca<T>(H, B, kap, s);
 }
 

@@ -26,20 +26,40 @@ template <typename T>
 constexpr int fill_split() { return sizeof(T) == 8 ? kFillChunk / 256 : 1; }
 static_assert(kFillChunk % 256 == 0, "fill tasks are whole workgroups");
 
+// KIND of the tasks that fill a volume block and its transpose together
+constexpr int kPairedVolume = 2;
+
 template <typename T, int KIND, bool SPLIT>
 __device__ __forceinline__ void fill_one(const EntryCtx<T> &c, const FillTask &tk, int64_t e,
                                          const int64_t *__restrict__ tgt_nat, const int64_t *__restrict__ src_nat,
                                          const SliceMap &sm) {
     const int64_t jl = e / tk.m, il = e - jl * tk.m;
-    const T v = entry<T, KIND>(c, tgt_nat[tk.t0 + il], src_nat[tk.s0 + jl]);
-    const int64_t o = slice_offset(sm, tk.li0, tk.t0 + il, tk.kw, sm.src_p[tk.s0 + jl] - sm.src_p[tk.s0],
-                                   tk.li0 + (int)il + 1);
-    if constexpr (SPLIT) {
-        const uint16_t h = f2bf((float)v);
-        static_cast<uint16_t *>(tk.out)[o] = h;
-        static_cast<uint16_t *>(tk.outlo)[o] = f2bf((float)v - bf2f(h));
+    auto put = [&](void *out, void *outlo, int64_t o, T v) {
+        if constexpr (SPLIT) {
+            const uint16_t h = f2bf((float)v);
+            static_cast<uint16_t *>(out)[o] = h;
+            static_cast<uint16_t *>(outlo)[o] = f2bf((float)v - bf2f(h));
+        } else {
+            static_cast<T *>(out)[o] = v;
+        }
+    };
+    // the stored positions are looked up after the entries (not live through the march)
+    if constexpr (KIND == kPairedVolume) {
+        // this entry and its transpose (the volume tree's targets and sources coincide)
+        T v, vt;
+        volume_entry_pair(c, tgt_nat[tk.t0 + il], tgt_nat[tk.s0 + jl], v, vt);
+        put(tk.out, tk.outlo,
+            slice_offset(sm, tk.li0, tk.t0 + il, tk.kw, sm.src_p[tk.s0 + jl] - sm.src_p[tk.s0], tk.li0 + (int)il + 1),
+            v);
+        put(tk.out_t, tk.outlo_t,
+            slice_offset(sm, tk.li0_t, tk.s0 + jl, tk.kw_t, sm.src_p[tk.t0 + il] - sm.src_p[tk.t0],
+                         tk.li0_t + (int)jl + 1),
+            vt);
     } else {
-        static_cast<T *>(tk.out)[o] = v;
+        const T v = entry<T, KIND>(c, tgt_nat[tk.t0 + il], src_nat[tk.s0 + jl]);
+        put(tk.out, tk.outlo,
+            slice_offset(sm, tk.li0, tk.t0 + il, tk.kw, sm.src_p[tk.s0 + jl] - sm.src_p[tk.s0], tk.li0 + (int)il + 1),
+            v);
     }
 }
 
@@ -111,20 +131,32 @@ template <typename T>
 double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
                          const int64_t *tgt_nat, const int64_t *src_nat, SliceMap sm, bool split, hipStream_t s) {
     if (tasks.empty()) return 0.0;
-    DevBuf dt = upload(tasks, s);
-    auto c = make_ctx<T>(m, kappa);
-    if (tasks.size() > ((size_t)1 << 31) / fill_split<T>())
+    // the paired tasks (volume block and transpose) first, then the single ones
+    std::vector<FillTask> order;
+    order.reserve(tasks.size());
+    for (const FillTask &t : tasks)
+        if (t.out_t) order.push_back(t);
+    const size_t npair = order.size();
+    for (const FillTask &t : tasks)
+        if (!t.out_t) order.push_back(t);
+    RTE_REQUIRE(npair == 0 || kind == RTE_VOLUME, "dense fill: paired tasks are for the volume operator");
+    if (order.size() > ((size_t)1 << 31) / fill_split<T>())
         throw std::runtime_error("dense fill: too many tasks for one grid");
-    const unsigned grid = (unsigned)(tasks.size() * fill_split<T>());
+    DevBuf dt = upload(order, s);
+    auto c = make_ctx<T>(m, kappa);
     const FillTask *d = dt.as<FillTask>();
+    const unsigned gp = (unsigned)(npair * fill_split<T>()), gs = (unsigned)((order.size() - npair) * fill_split<T>());
+    const FillTask *ds = d + npair;
     EventTimer tm(s);
     tm.start();
     if (split) {
-        if (kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, true><<<grid, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
-        else k_dense_fill<T, RTE_SURFACE, true><<<grid, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+        if (gp) k_dense_fill<T, kPairedVolume, true><<<gp, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+        if (gs && kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, true><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
+        else if (gs) k_dense_fill<T, RTE_SURFACE, true><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
     } else {
-        if (kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, false><<<grid, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
-        else k_dense_fill<T, RTE_SURFACE, false><<<grid, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+        if (gp) k_dense_fill<T, kPairedVolume, false><<<gp, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+        if (gs && kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, false><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
+        else if (gs) k_dense_fill<T, RTE_SURFACE, false><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
     }
     HIP_LAUNCH_CHECK();
     tm.stop();

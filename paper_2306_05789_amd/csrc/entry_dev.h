@@ -388,6 +388,45 @@ __device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
     return G * (T)g.vol_scale;
 }
 
+// The quadrature part of G(target tt, source ss) given the attenuation along
+// the direct and the reflected path.
+template <typename T>
+__device__ __forceinline__ T vol_from_att(const EntryCtx<T> &c, T att, T att_m, const int tt[3], const int ss[3]) {
+    const GridDev &g = c.g;
+    const T h2[3] = {(T)(g.h[0] * g.h[0]), (T)(g.h[1] * g.h[1]), (T)(g.h[2] * g.h[2])};
+    T kn[27];
+    int cellmask;
+    load_star(c, ss, kn, cellmask);
+    const int dg[3] = {tt[0] - ss[0], tt[1] - ss[1], tt[2] - ss[2]};
+    T G = att * vol_quad(c, kn, cellmask, dg, h2, cheb3(tt, ss) <= kNearCheb);
+    if (g.wall_axis >= 0) {
+        const int a = g.wall_axis;
+        const int Ci = g.wall_side ? g.n[a] - 1 : 0;
+        int mt[3] = {tt[0], tt[1], tt[2]};
+        mt[a] = 2 * Ci - tt[a];
+        const int dgm[3] = {mt[0] - ss[0], mt[1] - ss[1], mt[2] - ss[2]};
+        G += att_m * vol_quad(c, kn, cellmask, dgm, h2, cheb3(mt, ss) <= kNearCheb);
+    }
+    return G * (T)g.vol_scale;
+}
+
+// G(i, j) and G(j, i) together: the optical depth along the segment (and along
+// the reflected path, whose wall point is the same seen from either end) is
+// shared; each entry takes its own source star and quadrature.
+template <typename T>
+__device__ __forceinline__ void volume_entry_pair(const EntryCtx<T> &c, int64_t i, int64_t j, T &gij, T &gji) {
+    const GridDev &g = c.g;
+    int ii[3], jj[3];
+    vtx_index(g, i, ii);
+    vtx_index(g, j, jj);
+    const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
+    const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
+    const T att = exp(-tau_segment(g, c.kappa, P, Q));
+    const T att_m = g.wall_axis >= 0 ? (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) : (T)0;
+    gij = vol_from_att(c, att, att_m, ii, jj);
+    gji = vol_from_att(c, att, att_m, jj, ii);
+}
+
 // ---------------------------------------------------------------- surface quadrature
 template <typename T, int NQ, int t>
 __device__ __forceinline__ void tri_term(const T *__restrict__ tab, const int lb, const int lc, const int nb,

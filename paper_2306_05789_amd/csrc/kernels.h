@@ -68,6 +68,10 @@ struct FillTask {
     int32_t m, n, li0;
     int32_t kw;       // stored width (columns) of the block
     int64_t first;    // first entry (column-major over m x n) of this task
+    // volume operator: the transposed block (rows s0.., columns t0..) filled by
+    // the same lanes (the optical depth of a vertex pair is symmetric), or null
+    void *out_t, *outlo_t;
+    int32_t li0_t, kw_t;
 };
 
 struct AcaTask {
