@@ -187,9 +187,13 @@ typedef struct {
     int64_t bytes;                                /* device bytes of the stored operator */
     int64_t entries_evaluated;                    /* kernel entries computed during assembly */
     double assemble_ms;                           /* host wall time of the assembly call */
-    double aca_kernel_ms;                         /* HIP-event time of the whole ACA (all rank steps) */
+    double aca_kernel_ms;                         /* HIP-event time of the whole ACA (all rank steps),
+                                                     summed over bands (bands of a multi-band matrix are
+                                                     assembled two at a time, so the sum can exceed
+                                                     assemble_ms) */
     int32_t aca_launches;                         /* ACA batches */
-    double aca_entry_ms;                          /* HIP-event time of the ACA row/column entry launches */
+    double aca_entry_ms;                          /* HIP-event time of the ACA row/column entry launches,
+                                                     summed over bands */
     int32_t aca_entry_launches;
     double fill_kernel_ms;                        /* HIP-event time of the dense-fill launches, summed */
     int32_t fill_launches;

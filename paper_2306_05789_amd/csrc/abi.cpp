@@ -1,6 +1,9 @@
 // The C ABI (include/rte.h): argument validation, handle management and
 // error translation.  Every entry point catches everything and returns a
 // status; the message of the last error is kept per thread.
+#include <exception>
+#include <thread>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -130,9 +133,54 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Pla
     int aca_l = 0, fill_l = 0, aca_entry_l = 0;
     double wsum = 0, wr = 0;
     int maxr = 0;
+    matvec_reserve(H, n_bands);   // the bands' plans are then built from two threads
+    // Bands are independent: with more than one, a second host thread on its
+    // own stream takes every other band as it comes free, so one band's ACA
+    // tail and host work overlap the other's kernels.
+    {
+        std::atomic<int> next{0};
+        auto run = [&](hipStream_t st) {
+            for (int b; (b = next.fetch_add(1)) < n_bands;) {
+                assemble_band(H, b, kappa + (int64_t)b * m.N, st);
+                matvec_build(H, b, st);
+            }
+        };
+        if (n_bands == 1) {
+            run(s);
+        } else {
+            hipStream_t s2 = nullptr;
+            hipEvent_t ready = nullptr;
+            HIP_CHECK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+            HIP_CHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+            HIP_CHECK(hipEventRecord(ready, s));   // the uploads above come first
+            HIP_CHECK(hipStreamWaitEvent(s2, ready, 0));
+            const int dev = H.device;
+            std::exception_ptr e1, e2;
+            std::thread t2([&] {
+                try {
+                    HIP_CHECK(hipSetDevice(dev));
+                    run(s2);
+                    HIP_CHECK(hipStreamSynchronize(s2));
+                } catch (...) {
+                    e2 = std::current_exception();
+                    next.store(n_bands);   // the other thread stops taking bands
+                }
+            });
+            try {
+                run(s);
+            } catch (...) {
+                e1 = std::current_exception();
+                next.store(n_bands);
+            }
+            t2.join();
+            (void)hipStreamSynchronize(s2);
+            (void)hipEventDestroy(ready);
+            (void)hipStreamDestroy(s2);
+            if (e1) std::rethrow_exception(e1);
+            if (e2) std::rethrow_exception(e2);
+        }
+    }
     for (int b = 0; b < n_bands; ++b) {
-        assemble_band(H, b, kappa + (int64_t)b * m.N, s);
-        matvec_build(H, b, s);
         const BandStore &B = H.bands[b];
         evaluated += B.evaluated;
         aca_e += B.aca_entries;

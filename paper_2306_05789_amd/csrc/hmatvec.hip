@@ -1204,6 +1204,10 @@ void launch_plan(const HMat &H, const MatvecPlan &mp, int nrhs, const double *x_
 
 }  // namespace
 
+void matvec_reserve(HMat &H, int n_bands) {
+    if ((int)H.mv.size() < n_bands) H.mv.resize(n_bands);
+}
+
 void matvec_build(HMat &H, int band, hipStream_t s) {
     if ((int)H.mv.size() <= band) H.mv.resize(band + 1);
     H.mv[band] = build_plan(H, {band}, s);

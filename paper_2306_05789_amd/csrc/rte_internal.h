@@ -283,6 +283,7 @@ struct HMat {
 void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, const int64_t *rows,
                     const int64_t *cols, double *out, int precision, hipStream_t s);
 void assemble_band(HMat &H, int band, const double *kappa_band, hipStream_t s);
+void matvec_reserve(HMat &H, int n_bands);   // room for the per-band plans (before building them concurrently)
 void matvec_build(HMat &H, int band, hipStream_t s);
 // Operator applied by a matvec on mixed-precision storage: the BF16-hi
 // factors with FP32 accumulation (inner sweeps), or hi + lo with FP64
