@@ -194,6 +194,7 @@ struct SrvMesh {
     DevBuf tgt_nat;        // volume cluster position -> vertex
     DevBuf src_pos;        // surface cluster position -> position in the caller's wall vector
     bool have_order = false;
+    std::mutex order_mu;     // the assembler that builds the first operator sets the tables above
     int64_t est_bytes = 0;   // operator bytes of one level (estimate, then the largest seen)
 };
 
@@ -229,8 +230,11 @@ struct Server {
     std::vector<double> nu, w;   // catalogue
     hipStream_t user = nullptr;  // the caller's stream (inputs are ordered after it)
     hipStream_t s = nullptr;     // sweeps (the server's own, non-blocking, default priority)
-    hipStream_t as = nullptr;    // assembly (the assembler thread's): the volume operator
-    hipStream_t as2 = nullptr;   // assembly: the boundary-source operator, concurrently
+    // assemblers: each builds one operator at a time (the volume one on as[w],
+    // the boundary-source one concurrently on as2[w]), so two operators are
+    // assembled at once and one's ACA tail and host work overlap the other's
+    static constexpr int kAssemblers = 2;
+    hipStream_t as[kAssemblers] = {}, as2[kAssemblers] = {};
     int device = 0;
     std::vector<std::unique_ptr<SrvMesh>> meshes;
     std::vector<std::unique_ptr<SrvOp>> ops;   // resident operators (main thread only)
@@ -247,7 +251,7 @@ struct Server {
     Pinned hcols, hres, hnewt, hband;
     // the assembler thread
     struct Job { SrvMesh *m; int mesh, level; int64_t reserved; };
-    std::thread worker;
+    std::vector<std::thread> workers;
     std::mutex mu;
     std::condition_variable cv, done_cv;
     std::deque<Job> jobs;                        // waiting
@@ -306,7 +310,7 @@ struct Server {
     // Operators of one (mesh, level) on the assembler's stream; touches no
     // server state but the mesh's cluster-order tables on its first operator
     // (no request of that mesh can be admitted before it is published).
-    std::unique_ptr<SrvOp> build_op(SrvMesh &M, int mi, int level) {
+    std::unique_ptr<SrvOp> build_op(SrvMesh &M, int mi, int level, hipStream_t as, hipStream_t as2) {
         const auto t0 = std::chrono::steady_clock::now();
         DevBuf kap(sizeof(double) * (size_t)M.mesh.N);
         const double mult = std::pow(10.0, (double)level / desc.levels_per_decade);
@@ -345,6 +349,7 @@ struct Server {
         if (serr) std::rethrow_exception(serr);
         op->S = std::move(Sop);
         op->bytes = op->G->h.stats.bytes + op->S->h.stats.bytes;
+        std::lock_guard<std::mutex> order_lock(M.order_mu);   // another assembler may build this mesh too
         if (!M.have_order) {
             M.tgt_nat.alloc(sizeof(int64_t) * (size_t)M.mesh.N);
             HIP_CHECK(hipMemcpyAsync(M.tgt_nat.p, op->G->h.tgt_nat.p, M.tgt_nat.bytes, hipMemcpyDeviceToDevice, as));
@@ -353,6 +358,7 @@ struct Server {
             M.kap_c.alloc(sizeof(double) * (size_t)M.mesh.N);
             permute_gather(M.tgt_nat.as<int64_t>(), M.mesh.N, 1, M.mesh.N, M.mesh.N, M.kappa.as<double>(),
                            M.kap_c.as<double>(), as);
+            HIP_CHECK(hipStreamSynchronize(as));   // the tables are complete before another op can be published
             M.have_order = true;
         }
         HIP_CHECK(hipStreamSynchronize(as));   // kap is released on return
@@ -360,7 +366,7 @@ struct Server {
         return op;
     }
 
-    void worker_loop() {
+    void worker_loop(int w) {
         (void)hipSetDevice(device);
         for (;;) {
             Job j;
@@ -374,7 +380,7 @@ struct Server {
             std::unique_ptr<SrvOp> op;
             std::string err;
             try {
-                op = build_op(*j.m, j.mesh, j.level);
+                op = build_op(*j.m, j.mesh, j.level, as[w], as2[w]);
                 op->reserved = j.reserved;
             } catch (const std::exception &e) {
                 err = e.what();
@@ -754,15 +760,21 @@ struct Server {
             stopping = true;
         }
         cv.notify_all();
-        if (worker.joinable()) worker.join();
+        for (auto &t : workers)
+            if (t.joinable()) t.join();
         if (s) (void)hipStreamSynchronize(s);
-        if (as) (void)hipStreamSynchronize(as);
+        for (int w = 0; w < kAssemblers; ++w) {
+            if (as[w]) (void)hipStreamSynchronize(as[w]);
+            if (as2[w]) (void)hipStreamSynchronize(as2[w]);
+        }
         reqs.clear();
         ops.clear();
         built.clear();
         if (s) (void)hipStreamDestroy(s);
-        if (as) (void)hipStreamDestroy(as);
-        if (as2) (void)hipStreamDestroy(as2);
+        for (int w = 0; w < kAssemblers; ++w) {
+            if (as[w]) (void)hipStreamDestroy(as[w]);
+            if (as2[w]) (void)hipStreamDestroy(as2[w]);
+        }
     }
 };
 
@@ -779,8 +791,10 @@ Server *server_create(const rte_server_desc_t &d, hipStream_t s) {
     S->user = s;
     HIP_CHECK(hipGetDevice(&S->device));
     HIP_CHECK(hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking));
-    HIP_CHECK(hipStreamCreateWithFlags(&S->as, hipStreamNonBlocking));
-    HIP_CHECK(hipStreamCreateWithFlags(&S->as2, hipStreamNonBlocking));
+    for (int w = 0; w < Server::kAssemblers; ++w) {
+        HIP_CHECK(hipStreamCreateWithFlags(&S->as[w], hipStreamNonBlocking));
+        HIP_CHECK(hipStreamCreateWithFlags(&S->as2[w], hipStreamNonBlocking));
+    }
     for (int b = 0; b < d.n_catalogue; ++b) {
         RTE_REQUIRE(std::isfinite(d.nu[b]) && d.nu[b] > 0 && (b == 0 || d.nu[b] > d.nu[b - 1]),
                     "server: catalogue frequencies must be positive and increasing");
@@ -801,7 +815,7 @@ Server *server_create(const rte_server_desc_t &d, hipStream_t s) {
     }
     S->stats.budget = S->desc.hbm_budget;
     Server *raw = S.get();
-    S->worker = std::thread([raw] { raw->worker_loop(); });
+    for (int w = 0; w < Server::kAssemblers; ++w) S->workers.emplace_back([raw, w] { raw->worker_loop(w); });
     return S.release();
 }
 
@@ -813,7 +827,7 @@ static void after_user(Server &S) {
     HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIP_CHECK(hipEventRecord(e, S.user));
     HIP_CHECK(hipStreamWaitEvent(S.s, e, 0));
-    HIP_CHECK(hipStreamWaitEvent(S.as, e, 0));
+    for (int w = 0; w < Server::kAssemblers; ++w) HIP_CHECK(hipStreamWaitEvent(S.as[w], e, 0));
     (void)hipEventDestroy(e);
 }
 
