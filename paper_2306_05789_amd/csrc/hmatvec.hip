@@ -1148,10 +1148,16 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
             mp->max_rows = std::max(mp->max_rows, w.rows);
         }
     }
-    // large tasks first so that long wavefronts start early
-    std::stable_sort(vt.begin(), vt.end(), [](const VtTask &a, const VtTask &b) {
-        return (int64_t)a.nj * a.k > (int64_t)b.nj * b.k;
-    });
+    // large tasks first so that long wavefronts start early (a stable order:
+    // (size, position) keys sorted, then the tasks gathered once)
+    {
+        std::vector<std::pair<int64_t, uint32_t>> key(vt.size());
+        for (size_t i = 0; i < vt.size(); ++i) key[i] = {-(int64_t)vt[i].nj * vt[i].k, (uint32_t)i};
+        std::sort(key.begin(), key.end());
+        std::vector<VtTask> sorted(vt.size());
+        for (size_t i = 0; i < key.size(); ++i) sorted[i] = vt[key[i].second];
+        vt.swap(sorted);
+    }
     // tasks of up to `tiles` tiles of one chunk (in block order)
     for (auto &kv : mtiles) {
         const std::vector<MfTile> &grp = kv.second;
