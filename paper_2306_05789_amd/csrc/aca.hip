@@ -345,8 +345,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_cols(EntryC
 // every P-th element of row l (contiguous across the group), and one
 // butterfly over the group ends the sum, for all groups of a wavefront at
 // once.  P is the largest power of two with 256 / P groups covering the k
-// indices (at most 64).  The squares of u_k and v_k (l = k) come from the
-// staging pass.
+// indices (at most 64), but at least 8 (64 contiguous bytes of a row per
+// load; the 32 groups then take the k indices in passes).  The squares of
+// u_k and v_k (l = k) come from the staging pass.
 template <typename T>
 __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
     __shared__ T ck[kChunk];
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
     T *part = st.part + c * 2 * (int64_t)st.half;
     if (k > 0) {
         int P = 64;
-        while (P > 1 && 256 / P < k) P >>= 1;
+        while (P > 8 && 256 / P < k) P >>= 1;
         const int G = 256 / P, g = tid / P, q = tid - g * P;
         const int eu1 = min(e1, m), ev0 = max(e0, m);
         for (int l0 = 0; l0 < k; l0 += G) {
