@@ -219,6 +219,15 @@ __device__ __forceinline__ int hinted_block(const int64_t *__restrict__ off, con
     return b;
 }
 
+// Waves per SIMD the entry launches are compiled for: the register budget
+// that keeps the march free of spills (the surface entry needs more
+// registers than the volume one; measured per kind and precision).
+template <typename T, int KIND>
+constexpr int entry_waves() {
+    if constexpr (sizeof(T) == 8) return KIND == RTE_VOLUME ? 4 : 3;
+    else return KIND == RTE_VOLUME ? 6 : 5;
+}
+
 // a - sum_l p[l * sp] q[l * sq], l < k, subtracted in order of l; the loads
 // of 8 terms are issued before their products (the factors were written by
 // earlier rank steps and come from L2 or HBM).  Terms past k are zero and
@@ -243,7 +252,7 @@ __device__ __forceinline__ T residual(T a, const T *p, int64_t sp, const T *q, i
 
 // Step 1: residual rows of every active block, one lane per entry.
 template <typename T, int KIND>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
+__global__ __launch_bounds__(256, (entry_waves<T, KIND>())) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -314,7 +323,7 @@ __global__ __launch_bounds__(256) void k_aca_pivot(AcaState<T> st) {
 
 // Step 3: residual columns of the pivoted blocks, one lane per entry.
 template <typename T, int KIND>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 6) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
+__global__ __launch_bounds__(256, (entry_waves<T, KIND>())) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
