@@ -222,10 +222,10 @@ __device__ __forceinline__ int hinted_block(const int64_t *__restrict__ off, con
 // Waves per SIMD the entry launches are compiled for: the register budget
 // that keeps the march free of spills (the surface entry needs more
 // registers than the volume one; measured per kind and precision).
-template <typename T, int KIND>
+template <typename T, int KIND, bool WALL>
 constexpr int entry_waves() {
     if constexpr (sizeof(T) == 8) return KIND == RTE_VOLUME ? 4 : 3;
-    else return KIND == RTE_VOLUME ? 6 : 5;
+    else return KIND == RTE_VOLUME ? (WALL ? 6 : 7) : 5;
 }
 
 // a - sum_l p[l * sp] q[l * sq], l < k, subtracted in order of l; the loads
@@ -251,8 +251,8 @@ __device__ __forceinline__ T residual(T a, const T *p, int64_t sp, const T *q, i
 }
 
 // Step 1: residual rows of every active block, one lane per entry.
-template <typename T, int KIND>
-__global__ __launch_bounds__(256, (entry_waves<T, KIND>())) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
+template <typename T, int KIND, bool WALL>
+__global__ __launch_bounds__(256, (entry_waves<T, KIND, WALL>())) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256, (entry_waves<T, KIND>())) void k_aca_rows(Entr
     T a;
     {
         const AcaTask tk = st.task[b];
-        a = entry<T, KIND>(c, tgt_nat[tk.t0 + st.istar[b]], src_nat[tk.s0 + j]);
+        a = entry<T, KIND, WALL>(c, tgt_nat[tk.t0 + st.istar[b]], src_nat[tk.s0 + j]);
     }
     // the block's state is read again after the march (only b and j stay
     // live through it; the barrier keeps the compiler from reusing the loads)
@@ -322,8 +322,8 @@ __global__ __launch_bounds__(256) void k_aca_pivot(AcaState<T> st) {
 }
 
 // Step 3: residual columns of the pivoted blocks, one lane per entry.
-template <typename T, int KIND>
-__global__ __launch_bounds__(256, (entry_waves<T, KIND>())) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
+template <typename T, int KIND, bool WALL>
+__global__ __launch_bounds__(256, (entry_waves<T, KIND, WALL>())) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256, (entry_waves<T, KIND>())) void k_aca_cols(Entr
     T a;
     {
         const AcaTask tk = st.task[b];
-        a = entry<T, KIND>(c, tgt_nat[tk.t0 + i], src_nat[tk.s0 + st.jstar[b]]);
+        a = entry<T, KIND, WALL>(c, tgt_nat[tk.t0 + i], src_nat[tk.s0 + st.jstar[b]]);
     }
     asm volatile("" ::: "memory");   // as in k_aca_rows
     const AcaTask tk = st.task[b];
@@ -783,21 +783,25 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
         k_aca_hint<T, true><<<(unsigned)((wc + 255) / 256), 256, 0, s>>>(st, wc, (int)ht[3]);
         k_aca_chunk_block<T><<<(unsigned)((nchunk + 255) / 256), 256, 0, s>>>(st, nchunk, (int)ht[3]);
         HIP_LAUNCH_CHECK();
+        // the entry launches, compiled without the reflected term when the mesh has no wall
+        const bool wall = c.g.wall_axis >= 0;
+        auto rows = [&](auto kernel) { kernel<<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn); };
+        auto cols = [&](auto kernel) { kernel<<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn); };
         for (int r = 0; r < kCompact && step <= max_steps; ++r, ++step) {
             mark();
             if (H.kind == RTE_VOLUME)
-                k_aca_rows<T, RTE_VOLUME><<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn);
+                wall ? rows(k_aca_rows<T, RTE_VOLUME, true>) : rows(k_aca_rows<T, RTE_VOLUME, false>);
             else
-                k_aca_rows<T, RTE_SURFACE><<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn);
+                wall ? rows(k_aca_rows<T, RTE_SURFACE, true>) : rows(k_aca_rows<T, RTE_SURFACE, false>);
             HIP_LAUNCH_CHECK();
             mark();
             k_aca_pivot<T><<<(unsigned)nact, 256, 0, s>>>(st);
             HIP_LAUNCH_CHECK();
             mark();
             if (H.kind == RTE_VOLUME)
-                k_aca_cols<T, RTE_VOLUME><<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn);
+                wall ? cols(k_aca_cols<T, RTE_VOLUME, true>) : cols(k_aca_cols<T, RTE_VOLUME, false>);
             else
-                k_aca_cols<T, RTE_SURFACE><<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn);
+                wall ? cols(k_aca_cols<T, RTE_SURFACE, true>) : cols(k_aca_cols<T, RTE_SURFACE, false>);
             HIP_LAUNCH_CHECK();
             mark();
             k_aca_dots<T><<<(unsigned)nchunk, 256, 0, s>>>(st);

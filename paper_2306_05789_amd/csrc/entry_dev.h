@@ -359,7 +359,10 @@ __device__ __forceinline__ void load_star(const EntryCtx<T> &c, const int jj[3],
     }
 }
 
-template <typename T>
+// WALL = false: the mesh has no reflective wall (the reflected term and its
+// registers compiled out); WALL = true: whether there is one is read from the
+// grid.
+template <typename T, bool WALL = true>
 __device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
     const GridDev &g = c.g;
     int ii[3], jj[3];
@@ -370,14 +373,15 @@ __device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
     // optical depths first: the star of j is loaded after the march, so its
     // 27 values do not stay live through it
     const T att = exp(-tau_segment(g, c.kappa, P, Q));
-    const T att_m = g.wall_axis >= 0 ? (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) : (T)0;
+    const bool wall = WALL && g.wall_axis >= 0;
+    const T att_m = wall ? (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) : (T)0;
     T kn[27];
     int cellmask;
     load_star(c, jj, kn, cellmask);
     const T h2[3] = {(T)(g.h[0] * g.h[0]), (T)(g.h[1] * g.h[1]), (T)(g.h[2] * g.h[2])};
     const int dg[3] = {ii[0] - jj[0], ii[1] - jj[1], ii[2] - jj[2]};
     T G = att * vol_quad(c, kn, cellmask, dg, h2, cheb3(ii, jj) <= kNearCheb);
-    if (g.wall_axis >= 0) {
+    if (wall) {
         const int a = g.wall_axis;
         const int Ci = g.wall_side ? g.n[a] - 1 : 0;
         int mi[3] = {ii[0], ii[1], ii[2]};
@@ -499,7 +503,7 @@ __device__ T surf_quad(const EntryCtx<T> &c, const int xi[3], const int ll[3], b
     return acc;
 }
 
-template <typename T>
+template <typename T, bool WALL = true>
 __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
     const GridDev &g = c.g;
     int ii[3], ll[3];
@@ -508,7 +512,7 @@ __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)ll[0], (T)ll[1], (T)ll[2]};
     T S = exp(-tau_segment(g, c.kappa, P, Q)) * surf_quad(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
-    if (g.wall_axis >= 0) {
+    if (WALL && g.wall_axis >= 0) {
         const int a = g.wall_axis;
         const int Ci = g.wall_side ? g.n[a] - 1 : 0;
         int mi[3] = {ii[0], ii[1], ii[2]};
@@ -518,10 +522,10 @@ __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
     return S;
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, bool WALL = true>
 __device__ __forceinline__ T entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
-    if constexpr (KIND == RTE_VOLUME) return volume_entry(c, i, j);
-    else return surface_entry(c, i, j);
+    if constexpr (KIND == RTE_VOLUME) return volume_entry<T, WALL>(c, i, j);
+    else return surface_entry<T, WALL>(c, i, j);
 }
 
 }  // namespace rte
