@@ -77,6 +77,27 @@ def _solve(mesh, G, S, wl, Tw, precision, tol, launch=None):
     return T, J, st
 
 
+@pytest.mark.parametrize("precision", [rte.RTE_FP64, rte.RTE_MIXED_BF16])
+def test_multiband_assembly_equals_single_band_assemblies(small, precision):
+    """The bands of a multi-band operator are assembled two at a time on two host
+    threads and streams; each band's operator is bit for bit the one a single-band
+    assembly of that band gives (ranks, stored bytes, products)."""
+    wl, mesh = small
+    kap = torch.tensor(wl.kappa, device=DEV)
+    opts = rte.hmat_opts(kind=rte.RTE_VOLUME, leaf_size=LEAF, precision=precision)
+    G = rte.rte_hmat_assemble(mesh, kap, opts)
+    x = torch.tensor(np.random.default_rng(12).uniform(0.0, 2.0, (3, mesh.N)), device=DEV)
+    total = 0
+    for b in range(wl.kappa.shape[0]):
+        Gb = rte.rte_hmat_assemble(mesh, kap[b:b + 1].contiguous(), opts)
+        total += rte.rte_hmat_stats(Gb)["bytes"]
+        y, yb = torch.empty_like(x), torch.empty_like(x)
+        rte.rte_hmat_matvec(G, b, x, y)
+        rte.rte_hmat_matvec(Gb, 0, x, yb)
+        assert torch.equal(y, yb), b
+    assert rte.rte_hmat_stats(G)["bytes"] == total
+
+
 def test_batched_solve_equals_single_rhs_solves(small):
     """16 right-hand sides in one solve against each solved alone (FP64 storage): the
     batched solve stops on the slowest right-hand side, so the others take extra
