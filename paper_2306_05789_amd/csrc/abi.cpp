@@ -83,9 +83,10 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Pla
     H.n_bands = n_bands;
     const rte_hmat_opts_t *opts = &o;
     H.opts = o;
-    // default launch shape per path (the autotuner may change it)
-    if (opts->precision == RTE_MIXED_BF16) H.cfg = MatvecConfig{4, 64, 4};
-    else H.cfg = MatvecConfig{8, 48, 4};
+    // default launch shape (the autotuner may change it): 8 waves per phase-B
+    // workgroup, 256 KiB phase-A chunks (fewer partials to add), 4 tiles per
+    // matrix-core task; the fastest or within 2 % of it on the 29^3-49^3 cubes
+    H.cfg = MatvecConfig{8, 256, 4};
     H.precision = opts->precision;
     H.kind = opts->kind;
     H.plan = std::move(plan);
