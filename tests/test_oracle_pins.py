@@ -355,6 +355,52 @@ def test_near_field_entries_against_exact_integral():
     assert abs(e2 - e_self / 2) < 1e-12 * e_self, (e2, e_self)
 
 
+def test_near_field_surface_entries_against_exact_integral():
+    """Near-field surface entries (degree-5 triangle rule on the boundary triangles around
+    x~^l, Section "FEM discretization", kernel |(x-y).n| / |x-y|^3 of the boundary source)
+    against the exact integral for constant kappa, targets one and two layers off the
+    emitting face x = 0 (a smooth integrand whose width is the mesh size): within 1e-3."""
+    kap = 0.7
+    g = Grid((9, 9, 9))
+    P = Problem(g, np.full(g.N, kap), emit_faces=1, near_cheb=2)
+    h = np.array(g.h)
+
+    def exact(i, l):
+        x = g.positions()[i]
+        L = g.index(l)
+        d = abs(x[0] - g.lo[0])
+        tot = 0.0
+        for o in range(4):
+            sq = (L[1] - (o & 1), L[2] - ((o >> 1) & 1))
+            if not (0 <= sq[0] <= g.n[1] - 2 and 0 <= sq[1] <= g.n[2] - 2):
+                continue
+            for t in range(2):   # each square split along its (0,0)-(1,1) diagonal
+                tv = [(sq[0], sq[1]), (sq[0] + 1, sq[1]) if t == 0 else (sq[0], sq[1] + 1),
+                      (sq[0] + 1, sq[1] + 1)]
+                if (L[1], L[2]) not in tv:
+                    continue
+                F = np.array([[g.lo[0], g.lo[1] + a * h[1], g.lo[2] + b * h[2]] for a, b in tv])
+                fv = [1.0 if v == (L[1], L[2]) else 0.0 for v in tv]
+                u, wu = _gl01(64)
+                U, V = np.meshgrid(u, u, indexing="ij")
+                a, b, c = F
+                y = a + U[..., None] * ((b - a) + V[..., None] * (c - b))
+                f = (1 - U) * fv[0] + U * (1 - V) * fv[1] + U * V * fv[2]
+                jac = U * np.linalg.norm(np.cross(b - a, c - b))
+                r2 = np.sum((y - x) ** 2, axis=-1)
+                tot += np.sum(np.outer(wu, wu) * jac * f * d / r2 ** 1.5)
+        return tot / (4 * np.pi)
+
+    for xi, ll in [((1, 4, 4), (0, 4, 4)), ((1, 4, 4), (0, 5, 4)), ((1, 4, 4), (0, 5, 5)),
+                   ((1, 4, 4), (0, 3, 5)), ((2, 4, 4), (0, 4, 4)), ((2, 4, 4), (0, 5, 5)),
+                   ((2, 4, 4), (0, 6, 4)), ((1, 0, 0), (0, 0, 0)), ((1, 8, 3), (0, 8, 2))]:
+        i, l = int(g.vid(xi)), int(g.vid(ll))
+        r = np.linalg.norm(g.positions()[i] - g.positions()[l])
+        e = P.surface_pairs([i], [l])[0] * np.exp(kap * r)
+        ex = exact(i, l)
+        assert abs(e - ex) < 1e-3 * ex, (xi, ll, e, ex)
+
+
 def _box_centre_closed_form(kappa, L=1.0, n=96):
     """(1/4pi) int_{S^2} (1 - exp(-kappa rho)) dw at the centre of a cube of side L,
     written as 1 - (1/4pi) sum over faces of int exp(-kappa r) d / r^3 dGamma."""
