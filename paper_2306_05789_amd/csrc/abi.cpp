@@ -143,7 +143,8 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Pla
         auto run = [&](hipStream_t st) {
             for (int b; (b = next.fetch_add(1)) < n_bands;) {
                 assemble_band(H, b, kappa + (int64_t)b * m.N, st);
-                matvec_build(H, b, st);
+                matvec_build(H, b, st);   // host work while the band's last kernels run
+                band_settle(H.bands[b], st);
             }
         };
         if (n_bands == 1) {

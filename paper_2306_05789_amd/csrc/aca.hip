@@ -673,8 +673,8 @@ void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Bl
             tasks.push_back(t);
         }
     }
-    B.fill_ms += dense_fill_launch<T>(*H.mesh, H.kind, kap, tasks, H.tgt_nat.as<int64_t>(), H.src_nat.as<int64_t>(),
-                                      slice_map(H), split, s);
+    dense_fill_launch<T>(*H.mesh, H.kind, kap, tasks, H.tgt_nat.as<int64_t>(), H.src_nat.as<int64_t>(), slice_map(H),
+                         split, B, s);
     B.fill_launches += 1;
     B.dense_entries += total;
     B.evaluated += total;
@@ -689,6 +689,11 @@ void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Bl
 template <typename T>
 void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &tasks, const std::vector<size_t> &ids,
                int64_t uo, int64_t vo, std::vector<Block> &fallback, std::vector<size_t> &retry, hipStream_t s) {
+    {   // an earlier batch's scratch is freed first (a fill's task list may stay queued)
+        size_t pending = 0;
+        for (const DevBuf &d : B.retire) pending += d.bytes;
+        if (pending > ((size_t)256 << 20)) band_settle(B, s);
+    }
     const Plan &P = *H.plan;
     const int nb = (int)tasks.size();
     int kmax = 1;
@@ -901,8 +906,13 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
                                                               H.src_pmap.as<int64_t>());
         else k_compact<T><<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>(), slice_map(H));
         HIP_LAUNCH_CHECK();
-        HIP_CHECK(hipStreamSynchronize(s));
+        B.retire.push_back(std::move(dct));
     }
+    // The compaction reads the scratch while the host goes on (dense fallback,
+    // matvec plan): every buffer of the batch is freed by band_settle().
+    for (DevBuf *d : {&Us, &Vs, &dt, &dub, &ents, &ints, &reals, &used, &offs, &tot, &part, &pmax, &pidx, &hints,
+                      &cblock, &dr})
+        B.retire.push_back(std::move(*d));
     B.bytes += (int64_t)(out.bytes + outlo.bytes);
     B.bufs.push_back(std::move(out));
     if (split) B.bufs.push_back(std::move(outlo));
@@ -987,8 +997,19 @@ void assemble_band(HMat &H, int band, const double *kappa_band, hipStream_t s) {
         DevBuf kf(sizeof(float) * (size_t)H.mesh->N);
         to_float(kappa_band, kf.as<float>(), H.mesh->N, s);
         assemble_typed<float>(H, band, kf.as<float>(), s);
-        HIP_CHECK(hipStreamSynchronize(s));
+        H.bands[band].retire.push_back(std::move(kf));   // read by queued launches
     }
+}
+
+void band_settle(BandStore &B, hipStream_t s) {
+    HIP_CHECK(hipStreamSynchronize(s));
+    for (const EventPair &e : B.fill_events) {
+        float ms = 0.0f;
+        HIP_CHECK(hipEventElapsedTime(&ms, e.a, e.b));
+        B.fill_ms += ms;
+    }
+    B.fill_events.clear();
+    B.retire.clear();
 }
 
 }  // namespace rte

@@ -128,9 +128,10 @@ void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, con
 }
 
 template <typename T>
-double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
-                         const int64_t *tgt_nat, const int64_t *src_nat, SliceMap sm, bool split, hipStream_t s) {
-    if (tasks.empty()) return 0.0;
+void dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
+                       const int64_t *tgt_nat, const int64_t *src_nat, SliceMap sm, bool split, BandStore &B,
+                       hipStream_t s) {
+    if (tasks.empty()) return;
     // the paired tasks (volume block and transpose) first, then the single ones
     std::vector<FillTask> order;
     order.reserve(tasks.size());
@@ -147,8 +148,8 @@ double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vec
     const FillTask *d = dt.as<FillTask>();
     const unsigned gp = (unsigned)(npair * fill_split<T>()), gs = (unsigned)((order.size() - npair) * fill_split<T>());
     const FillTask *ds = d + npair;
-    EventTimer tm(s);
-    tm.start();
+    EventPair ev;
+    HIP_CHECK(hipEventRecord(ev.a, s));
     if (split) {
         if (gp) k_dense_fill<T, kPairedVolume, true><<<gp, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
         if (gs && kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, true><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
@@ -159,14 +160,13 @@ double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vec
         else if (gs) k_dense_fill<T, RTE_SURFACE, false><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
     }
     HIP_LAUNCH_CHECK();
-    tm.stop();
-    const double ms = tm.ms();
-    HIP_CHECK(hipStreamSynchronize(s));   // the task list is released on return
-    return ms;
+    HIP_CHECK(hipEventRecord(ev.b, s));
+    B.fill_events.push_back(std::move(ev));
+    B.retire.push_back(std::move(dt));   // read by the queued launches
 }
-template double dense_fill_launch<double>(const Mesh &, int, const double *, const std::vector<FillTask> &,
-                                          const int64_t *, const int64_t *, SliceMap, bool, hipStream_t);
-template double dense_fill_launch<float>(const Mesh &, int, const float *, const std::vector<FillTask> &,
-                                         const int64_t *, const int64_t *, SliceMap, bool, hipStream_t);
+template void dense_fill_launch<double>(const Mesh &, int, const double *, const std::vector<FillTask> &,
+                                        const int64_t *, const int64_t *, SliceMap, bool, BandStore &, hipStream_t);
+template void dense_fill_launch<float>(const Mesh &, int, const float *, const std::vector<FillTask> &,
+                                       const int64_t *, const int64_t *, SliceMap, bool, BandStore &, hipStream_t);
 
 }  // namespace rte

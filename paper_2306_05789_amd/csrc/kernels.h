@@ -107,9 +107,11 @@ struct EventTimer {
 template <typename T> struct EntryCtx;
 template <typename T> EntryCtx<T> make_ctx(const Mesh &m, const T *kappa);
 void to_float(const double *in, float *out, int64_t n, hipStream_t s);
-// returns the HIP-event time of the fill launch in ms; split: write BF16 hi/lo
+// queues the fill on s without waiting: the task list and the launch's event
+// pair go to B.retire / B.fill_events (read by band_settle); split: write BF16 hi/lo
 template <typename T>
-double dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
-                         const int64_t *tgt_nat, const int64_t *src_nat, SliceMap sm, bool split, hipStream_t s);
+void dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
+                       const int64_t *tgt_nat, const int64_t *src_nat, SliceMap sm, bool split, BandStore &B,
+                       hipStream_t s);
 
 }  // namespace rte

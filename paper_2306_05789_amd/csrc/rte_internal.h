@@ -10,6 +10,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "rte.h"
@@ -229,8 +230,34 @@ DevBuf upload(const std::vector<T> &v, hipStream_t s) {
 // Padding is zero.  Mixed precision stores every element x as BF16 hi =
 // bf16(x) and lo = bf16(x - hi) in two arrays of the same layout (BF16
 // keeps FP32's exponent range, so no scale is needed).
+// The two events around one queued launch (read after the stream has drained).
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() {
+        HIP_CHECK(hipEventCreate(&a));
+        HIP_CHECK(hipEventCreate(&b));
+    }
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+    EventPair(EventPair &&o) noexcept : a(o.a), b(o.b) { o.a = o.b = nullptr; }
+    EventPair &operator=(EventPair &&o) noexcept {
+        std::swap(a, o.a);
+        std::swap(b, o.b);
+        return *this;
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 struct BandStore {
     std::vector<DevBuf> bufs;               // owning storage chunks
+    // Work still queued when the band's host work goes on: buffers its kernels
+    // read (task lists, ACA scratch) and the events of its fill launches.
+    // band_settle() waits for the stream, adds the fill times and frees them.
+    std::vector<DevBuf> retire;
+    std::vector<EventPair> fill_events;
     std::vector<Block> dense_blocks;        // plan dense leaves, then ACA fallbacks
     std::vector<const void *> dense_ptr;    // per dense block
     std::vector<const void *> dense_lo;     // per dense block: BF16 lo part (mixed precision)
@@ -283,6 +310,7 @@ struct HMat {
 void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, const int64_t *rows,
                     const int64_t *cols, double *out, int precision, hipStream_t s);
 void assemble_band(HMat &H, int band, const double *kappa_band, hipStream_t s);
+void band_settle(BandStore &B, hipStream_t s);   // after the band's last queued work
 void matvec_reserve(HMat &H, int n_bands);   // room for the per-band plans (before building them concurrently)
 void matvec_build(HMat &H, int band, hipStream_t s);
 // Operator applied by a matvec on mixed-precision storage: the BF16-hi
