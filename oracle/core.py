@@ -49,7 +49,8 @@ class _Problem(C.Structure):
         ("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("h", C.c_double * 3),
         ("flip_axis", C.c_int32), ("flip_cells", C.c_int32),
         ("kappa", C.POINTER(C.c_double)),
-        ("wall_axis", C.c_int32), ("wall_side", C.c_int32), ("R", C.c_double),
+        ("n_walls", C.c_int32), ("wall_axis", C.c_int32 * 6), ("wall_side", C.c_int32 * 6),
+        ("R", C.c_double * 6),
         ("emit_faces", C.c_uint32), ("near_cheb", C.c_int32),
         ("nq_tet_far", C.c_int32), ("nq_tet_near", C.c_int32),
         ("nq_tri_far", C.c_int32), ("nq_tri_near", C.c_int32),
@@ -135,8 +136,9 @@ class Grid:
 
 @dataclass
 class Problem:
-    """One kappa field on one grid, with an optional planar reflective wall
-    covering a whole box face (one reflection, Hypothesis 1 with M = 1)."""
+    """One kappa field on one grid, with planar reflective walls, each covering a
+    whole box face and reflecting once (Hypothesis 1): either one wall given by
+    wall_axis / wall_side / R, or a list `walls` of (axis, side, R)."""
     grid: Grid
     kappa: np.ndarray
     emit_faces: int = 1
@@ -146,6 +148,7 @@ class Problem:
     near_cheb: int = 2
     flip_axis: int = -1
     flip_cells: int = 0
+    walls: list = None
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -165,7 +168,12 @@ class Problem:
         s.h[:] = list(self.grid.h)
         s.flip_axis, s.flip_cells = self.flip_axis, self.flip_cells
         s.kappa = _dptr(self.kappa)
-        s.wall_axis, s.wall_side, s.R = self.wall_axis, self.wall_side, float(self.R)
+        if self.walls is None:
+            self.walls = [(self.wall_axis, self.wall_side, float(self.R))] if self.wall_axis >= 0 else []
+        assert len(self.walls) <= 6 and len({(a, sd) for a, sd, _ in self.walls}) == len(self.walls)
+        s.n_walls = len(self.walls)
+        for w, (a, sd, r) in enumerate(self.walls):
+            s.wall_axis[w], s.wall_side[w], s.R[w] = int(a), int(sd), float(r)
         s.emit_faces, s.near_cheb = self.emit_faces, self.near_cheb
         (tfp, tfw), (tnp, tnw), (sfp, sfw), (snp, snw) = rules
         s.nq_tet_far, s.nq_tet_near, s.nq_tri_far, s.nq_tri_near = len(tfw), len(tnw), len(sfw), len(snw)
@@ -227,9 +235,13 @@ class Problem:
         lib().og_kappa_points(self.ref, len(x), x, out)
         return out
 
-    def tau(self, p, q, mirrored: bool = False) -> np.ndarray:
+    def tau(self, p, q, mirrored: bool = False, wall: int = None) -> np.ndarray:
+        """Optical depth of the segments p -> q, or of the paths reflected by wall
+        `wall` (mirrored=True: the first wall)."""
         p = np.ascontiguousarray(np.atleast_2d(p), dtype=np.float64)
         q = np.ascontiguousarray(np.atleast_2d(q), dtype=np.float64)
         out = np.empty(len(p))
-        lib().og_tau_segments(self.ref, len(p), p, q, int(mirrored), out)
+        w = wall if wall is not None else (0 if mirrored else -1)
+        assert w < len(self.walls)
+        lib().og_tau_segments(self.ref, len(p), p, q, int(w), out)
         return out

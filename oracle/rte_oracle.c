@@ -16,6 +16,9 @@
  *     where x' is where the segment from the mirror image of x to y meets the
  *     wall; for the boundary source the kernel is the solid-angle density
  *     |(x-y).n| / |x-y|^3 (eq. SE1), seen from x and from its mirror image.
+ *     With several planar walls (the three planes of the academic test) and at
+ *     most one reflection per ray (Hypothesis 1), every wall adds its own
+ *     mirror-image term.
  *   - Section "FEM discretization": P1 collocation, G^{ij} integrates
  *     kappa * kernel * w^j over the tetrahedra around vertex j with a
  *     degree-5 (14 point) rule near x^i and degree-2 (4 point) rule
@@ -47,9 +50,10 @@ typedef struct {
     int32_t flip_axis;     /* -1: plain Kuhn grid; else mirrored cells below flip_cells */
     int32_t flip_cells;
     const double *kappa;   /* [N] P1 vertex values, natural order */
-    int32_t wall_axis;     /* -1: no reflective wall */
-    int32_t wall_side;     /* 0: plane at lo, 1: plane at hi */
-    double R;              /* reflection coefficient */
+    int32_t n_walls;       /* planar reflective walls, each a whole box face */
+    int32_t wall_axis[6];
+    int32_t wall_side[6];  /* 0: plane at lo, 1: plane at hi */
+    double R[6];           /* reflection coefficients */
     uint32_t emit_faces;   /* bit f: face (axis f/2, side f%2) emits */
     int32_t near_cheb;
     int32_t nq_tet_far, nq_tet_near, nq_tri_far, nq_tri_near;
@@ -218,40 +222,40 @@ double og_tau(const og_problem_t *P, const double p[3], const double q[3])
     return sqrt(len2) * sum;
 }
 
-static double wall_plane(const og_problem_t *P)
+static double wall_plane(const og_problem_t *P, int w)
 {
-    int a = P->wall_axis;
-    return P->wall_side == 0 ? P->lo[a] : P->lo[a] + (P->n[a] - 1) * P->h[a];
+    int a = P->wall_axis[w];
+    return P->wall_side[w] == 0 ? P->lo[a] : P->lo[a] + (P->n[a] - 1) * P->h[a];
 }
 
-static void mirror_point(const og_problem_t *P, const double x[3], double xb[3])
+static void mirror_point(const og_problem_t *P, int w, const double x[3], double xb[3])
 {
-    double c = wall_plane(P);
+    double c = wall_plane(P, w);
     for (int a = 0; a < 3; ++a) xb[a] = x[a];
-    xb[P->wall_axis] = 2.0 * c - x[P->wall_axis];
+    xb[P->wall_axis[w]] = 2.0 * c - x[P->wall_axis[w]];
 }
 
-static void mirror_index(const og_problem_t *P, const int idx[3], int mb[3])
+static void mirror_index(const og_problem_t *P, int w, const int idx[3], int mb[3])
 {
-    int a = P->wall_axis;
+    int a = P->wall_axis[w];
     for (int b = 0; b < 3; ++b) mb[b] = idx[b];
-    mb[a] = P->wall_side == 0 ? -idx[a] : 2 * (P->n[a] - 1) - idx[a];
+    mb[a] = P->wall_side[w] == 0 ? -idx[a] : 2 * (P->n[a] - 1) - idx[a];
 }
 
 /* Optical depth along the broken path x -> x' -> y, where x' is the point of
- * the wall on the segment from the mirror image of x to y. */
-double og_tau_mirror(const og_problem_t *P, const double x[3], const double y[3])
+ * wall w on the segment from the mirror image of x to y. */
+double og_tau_mirror(const og_problem_t *P, int w, const double x[3], const double y[3])
 {
     double xb[3], xp[3];
-    int a = P->wall_axis;
-    mirror_point(P, x, xb);
+    int a = P->wall_axis[w];
+    mirror_point(P, w, x, xb);
     double den = y[a] - xb[a];
     if (den == 0.0) {
         for (int b = 0; b < 3; ++b) xp[b] = y[b];
     } else {
-        double t = (wall_plane(P) - xb[a]) / den;
+        double t = (wall_plane(P, w) - xb[a]) / den;
         for (int b = 0; b < 3; ++b) xp[b] = xb[b] + t * (y[b] - xb[b]);
-        xp[a] = wall_plane(P);
+        xp[a] = wall_plane(P, w);
     }
     return og_tau(P, x, xp) + og_tau(P, xp, y);
 }
@@ -321,12 +325,13 @@ double og_volume_entry(const og_problem_t *P, int64_t i, int64_t j)
     vpos(P, ii, xi);
     vpos(P, jj, xj);
     double G = exp(-og_tau(P, xi, xj)) * volume_quad(P, xi, jj, cheb(ii, jj) <= P->near_cheb);
-    if (P->wall_axis >= 0 && P->R != 0.0) {
+    for (int w = 0; w < P->n_walls; ++w) {
+        if (P->R[w] == 0.0) continue;
         double xb[3];
         int mb[3];
-        mirror_point(P, xi, xb);
-        mirror_index(P, ii, mb);
-        G += P->R * exp(-og_tau_mirror(P, xi, xj)) *
+        mirror_point(P, w, xi, xb);
+        mirror_index(P, w, ii, mb);
+        G += P->R[w] * exp(-og_tau_mirror(P, w, xi, xj)) *
              volume_quad(P, xb, jj, cheb(mb, jj) <= P->near_cheb);
     }
     return G;
@@ -421,12 +426,13 @@ double og_surface_entry(const og_problem_t *P, int64_t i, int64_t l)
     vpos(P, ii, xi);
     vpos(P, ll, xl);
     double S = exp(-og_tau(P, xi, xl)) * surface_quad(P, xi, ii, ll, cheb(ii, ll) <= P->near_cheb);
-    if (P->wall_axis >= 0 && P->R != 0.0) {
+    for (int w = 0; w < P->n_walls; ++w) {
+        if (P->R[w] == 0.0) continue;
         double xb[3];
         int mb[3];
-        mirror_point(P, xi, xb);
-        mirror_index(P, ii, mb);
-        S += P->R * exp(-og_tau_mirror(P, xi, xl)) *
+        mirror_point(P, w, xi, xb);
+        mirror_index(P, w, ii, mb);
+        S += P->R[w] * exp(-og_tau_mirror(P, w, xi, xl)) *
              surface_quad(P, xb, mb, ll, cheb(mb, ll) <= P->near_cheb);
     }
     return S;
@@ -469,10 +475,11 @@ void og_kappa_points(const og_problem_t *P, int64_t n, const double *x, double *
     for (int64_t k = 0; k < n; ++k) out[k] = og_kappa_at(P, x + 3 * k);
 }
 
+/* wall < 0: the straight segment; else the path reflected by wall `wall` */
 void og_tau_segments(const og_problem_t *P, int64_t n, const double *p, const double *q,
-                     int32_t mirrored, double *out)
+                     int32_t wall, double *out)
 {
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < n; ++k)
-        out[k] = mirrored ? og_tau_mirror(P, p + 3 * k, q + 3 * k) : og_tau(P, p + 3 * k, q + 3 * k);
+        out[k] = wall >= 0 ? og_tau_mirror(P, wall, p + 3 * k, q + 3 * k) : og_tau(P, p + 3 * k, q + 3 * k);
 }

@@ -91,6 +91,8 @@ def fixed_point(G, SE, *, grey: bool, nu=None, w=None, a=None, kappa_v=None, T0=
     G: list of B dense [N,N] operators (kappa inside, Section "FEM discretization").
     SE: [B, N] boundary source S^E_b = S_b_hat Q_b.
     grey: single band with B(T) = sigma T^4.
+    a: [B] scattering coefficients (default 0); the source is S_b = (1 - a_b) B_b(T) + a_b J_b
+    (eq. eqS) in both formulations.
     kappa_v: [B, N] kappa at the vertices (weights of the temperature balance).
     Stops when max_b ||J_b^{k+1} - J_b^k|| / ||J_b^{k+1}|| <= tol.
     """
@@ -105,10 +107,8 @@ def fixed_point(G, SE, *, grey: bool, nu=None, w=None, a=None, kappa_v=None, T0=
         w = band_weights(nu) if w is None else np.asarray(w, dtype=np.float64)
         coef = w[:, None] * np.asarray(kappa_v, dtype=np.float64) * (1.0 - a)[:, None]
     for k in range(max_iter):
-        if grey:
-            S = SIGMA * T[None, :] ** 4
-        else:
-            S = (1.0 - a)[:, None] * planck(nu[:, None], T[None, :]) + a[:, None] * J
+        emission = SIGMA * T[None, :] ** 4 if grey else planck(nu[:, None], T[None, :])
+        S = (1.0 - a)[:, None] * emission + a[:, None] * J
         Jn = np.stack([SE[b] + G[b] @ S[b] for b in range(B)])
         num = np.linalg.norm(Jn - J, axis=1)
         den = np.linalg.norm(Jn, axis=1)

@@ -112,21 +112,24 @@ def test_tau_matches_fine_sampling_of_p1_kappa():
         assert abs(P.tau(p, q)[0] - ref) < 1e-8 * max(ref, 1.0)
 
 
-def _doubled(P: Problem):
-    """The mirror-doubled domain of a problem whose wall is the x = lo face."""
+def _doubled(P: Problem, axis: int = 0):
+    """The mirror-doubled domain of a problem whose wall is the lo face of `axis`."""
     g = P.grid
-    n0 = g.n[0]
-    L = g.hi[0] - g.lo[0]
-    gd = Grid((2 * n0 - 1, g.n[1], g.n[2]), (g.lo[0] - L, g.lo[1], g.lo[2]), g.hi)
+    na = g.n[axis]
+    L = g.hi[axis] - g.lo[axis]
+    n2, lo2 = list(g.n), list(g.lo)
+    n2[axis] = 2 * na - 1
+    lo2[axis] = g.lo[axis] - L
+    gd = Grid(tuple(n2), tuple(lo2), g.hi)
     idx = gd.index(np.arange(gd.N))
     src = idx.copy()
-    src[:, 0] = np.abs(idx[:, 0] - (n0 - 1))
+    src[:, axis] = np.abs(idx[:, axis] - (na - 1))
     emit = 0
     for f in range(6):
         if (P.emit_faces >> f) & 1:
-            assert f // 2 != 0, "the doubled check keeps emitting faces off the wall axis"
+            assert f // 2 != axis, "the doubled check keeps emitting faces off the wall axis"
             emit |= 1 << f
-    Pd = Problem(gd, P.kappa[g.vid(src)], emit_faces=emit, flip_axis=0, flip_cells=n0 - 1)
+    Pd = Problem(gd, P.kappa[g.vid(src)], emit_faces=emit, flip_axis=axis, flip_cells=na - 1)
     return Pd
 
 
@@ -145,35 +148,64 @@ def test_mirror_tau_equals_straight_tau_in_doubled_domain():
     assert np.max(np.abs(Pd.kappa_at(ym) - P.kappa_at(y))) < 1e-14
 
 
-def test_reflective_operator_equals_doubled_domain_for_R1():
-    """Section "Results": reflection on a plane is equivalent to extending the domain
-    by symmetry.  With R = 1 the reflective G and S equal the doubled-domain matrices
-    folded onto the original vertices, entry by entry."""
+@pytest.mark.parametrize("axis", [0, 2])
+def test_reflective_operator_equals_doubled_domain_for_R1(axis):
+    """Section "Results" (Test-1): a planar reflection is the same as extending the
+    domain by its mirror image.  With R = 1 the reflective G and S equal the
+    doubled-domain matrices folded onto the original vertices, entry by entry."""
     rng = np.random.default_rng(5)
+    emit = 4 | 32 if axis == 0 else 1 | 8
     P = _grid_problem((5, 4, 4), kappa=lambda X: rng.uniform(0.2, 1.5, len(X)),
-                      wall_axis=0, wall_side=0, R=1.0, emit_faces=4 | 32)
-    Pd = _doubled(P)
+                      wall_axis=axis, wall_side=0, R=1.0, emit_faces=emit)
+    Pd = _doubled(P, axis)
     g, gd = P.grid, Pd.grid
-    n0 = g.n[0]
+    na = g.n[axis]
+    shift = np.zeros(3, dtype=np.int64)
+    shift[axis] = na - 1
+    flip = np.ones(3, dtype=np.int64)
+    flip[axis] = -1
     ids = np.arange(g.N)
     idx = g.index(ids)
-    dir_ids = gd.vid(idx + [n0 - 1, 0, 0])
-    mir_ids = gd.vid(idx * [-1, 1, 1] + [n0 - 1, 0, 0])
+    dir_ids = gd.vid(idx + shift)
+    mir_ids = gd.vid(idx * flip + shift)
     GR = P.dense_G()
     Gd = Pd.volume_block(dir_ids, np.concatenate([dir_ids, mir_ids]))
-    fold = Gd[:, :g.N] + np.where(idx[:, 0] > 0, 1.0, 0.0)[None, :] * Gd[:, g.N:]
+    fold = Gd[:, :g.N] + np.where(idx[:, axis] > 0, 1.0, 0.0)[None, :] * Gd[:, g.N:]
     assert np.max(np.abs(GR - fold)) < 1e-13 * np.max(np.abs(GR))
     em = P.emitting
     eidx = g.index(em)
     SR = P.dense_S()
-    e_dir = gd.vid(eidx + [n0 - 1, 0, 0])
-    e_mir = gd.vid(eidx * [-1, 1, 1] + [n0 - 1, 0, 0])
+    e_dir = gd.vid(eidx + shift)
+    e_mir = gd.vid(eidx * flip + shift)
     Sd = Pd.surface_block(dir_ids, np.concatenate([e_dir, e_mir]))
-    foldS = Sd[:, :len(em)] + np.where(eidx[:, 0] > 0, 1.0, 0.0)[None, :] * Sd[:, len(em):]
+    foldS = Sd[:, :len(em)] + np.where(eidx[:, axis] > 0, 1.0, 0.0)[None, :] * Sd[:, len(em):]
     assert np.max(np.abs(SR - foldS)) < 1e-13 * np.max(np.abs(SR))
     # R = 0 is a different operator (the check has teeth)
-    P0 = _grid_problem((5, 4, 4), kappa=P.kappa, emit_faces=4 | 32)
+    P0 = _grid_problem((5, 4, 4), kappa=P.kappa, emit_faces=emit)
     assert np.max(np.abs(P0.dense_G() - fold)) > 1e-3 * np.max(np.abs(GR))
+
+
+def test_several_walls_add_one_image_each():
+    """Several planar walls, one reflection per ray (Hypothesis 1; the three planes
+    of the academic test): every entry is the direct term plus, per wall, that
+    wall's own mirror-image term, i.e. G(walls) = G(none) + sum_w [G(wall w alone) -
+    G(none)] with each single-wall operator pinned by the doubled domain above."""
+    rng = np.random.default_rng(15)
+    kap = rng.uniform(0.2, 1.5, 6 * 5 * 4)
+    walls = [(0, 0, 0.6), (1, 1, 0.3), (2, 0, 1.0)]
+    kw = dict(kappa=kap, emit_faces=2 | 32)
+    P = _grid_problem((6, 5, 4), hi=(1.2, 1, 0.8), walls=walls, **kw)
+    P0 = _grid_problem((6, 5, 4), hi=(1.2, 1, 0.8), **kw)
+    singles = [_grid_problem((6, 5, 4), hi=(1.2, 1, 0.8), wall_axis=a, wall_side=sd, R=r, **kw)
+               for a, sd, r in walls]
+    for name in ("dense_G", "dense_S"):
+        got = getattr(P, name)()
+        base = getattr(P0, name)()
+        ref = base + sum(getattr(Q, name)() - base for Q in singles)
+        assert np.max(np.abs(got - ref)) < 1e-14 * np.max(np.abs(got))
+        # each wall contributes (the check has teeth)
+        for Q in singles:
+            assert np.max(np.abs(got - getattr(Q, name)())) > 1e-4 * np.max(np.abs(got))
 
 
 def test_operator_is_affine_in_R():
@@ -568,3 +600,61 @@ def test_multiband_fixed_point_approaches_grey_with_fine_bands():
     w = solve.band_weights(nu)
     res = solve.fixed_point([G] * B, SE, grey=False, nu=nu, w=w, kappa_v=np.full((B, 64), 0.7), tol=1e-12)
     assert np.max(np.abs(res.T - grey.T) / grey.T) < 1e-5
+
+
+# ---------------------------------------------------------------- scattering (eq. eqS)
+
+@pytest.fixture(scope="module")
+def three_bands():
+    rng = np.random.default_rng(17)
+    P = _grid_problem((6, 5, 5), hi=(1.5, 1, 1), kappa=lambda X: rng.uniform(0.3, 1.5, len(X)), emit_faces=1)
+    nu = np.array([0.5, 1.4, 4.0])
+    kb = P.kappa[None, :] * nu[:, None] ** -1.5
+    Gs, SEs = [], []
+    for b in range(3):
+        Pb = _grid_problem((6, 5, 5), hi=(1.5, 1, 1), kappa=kb[b], emit_faces=1)
+        Gs.append(Pb.dense_G())
+        SEs.append(Pb.dense_S() @ solve.planck(nu[b], np.ones(len(Pb.emitting))))
+    return nu, kb, Gs, np.array(SEs)
+
+
+def test_scattering_fixed_point_satisfies_its_equations(three_bands):
+    """With a_nu > 0 the converged oracle solution satisfies, each recomputed here:
+    J_b = S^E_b + G_b S_b with S_b = (1 - a_b) B_b(T) + a_b J_b (eq. eqS), and the
+    temperature balance sum_b w_b kappa_b (1 - a_b) (J_b - B_b(T)) = 0."""
+    nu, kb, Gs, SE = three_bands
+    a = np.array([0.3, 0.7, 0.1])
+    res = solve.fixed_point(Gs, SE, grey=False, nu=nu, a=a, kappa_v=kb, tol=1e-14)
+    B = np.stack([nu[b] ** 3 / np.expm1(nu[b] / res.T) for b in range(3)])
+    S = (1 - a)[:, None] * B + a[:, None] * res.J
+    for b in range(3):
+        r = res.J[b] - SE[b] - Gs[b] @ S[b]
+        assert np.max(np.abs(r)) < 1e-12 * np.max(res.J[b])
+    w = solve.band_weights(nu)
+    bal = np.sum((w * (1 - a))[:, None] * kb * (res.J - B), axis=0)
+    scale = np.sum((w * (1 - a))[:, None] * kb * res.J, axis=0)
+    assert np.max(np.abs(bal) / scale) < 1e-12
+    # scattering changes the solution
+    res0 = solve.fixed_point(Gs, SE, grey=False, nu=nu, kappa_v=kb, tol=1e-14)
+    assert np.max(np.abs(res0.T - res.T) / res.T) > 1e-3
+
+
+def test_scattering_fixed_point_is_monotone(three_bands):
+    """The monotonicity Proposition covers scattering: from T^0 = 0 the iterates of
+    T and J increase."""
+    nu, kb, Gs, SE = three_bands
+    res = solve.fixed_point(Gs, SE, grey=False, nu=nu, a=np.array([0.5, 0.2, 0.9]), kappa_v=kb, tol=1e-12,
+                            keep_history=True)
+    assert np.all(np.diff(np.array(res.T_history), axis=0) >= -1e-14)
+    assert np.all(np.diff(np.array(res.J_history), axis=0) >= -1e-14)
+
+
+def test_grey_scattering_leaves_the_iteration_unchanged(config1_like):
+    """Grey case: the balance kappa (1 - a)(J - sigma T^4) = 0 gives sigma T^4 = J, so
+    the source (1 - a) sigma T^4 + a J equals J for every a and the iterates do not
+    depend on a."""
+    P, G, SE = config1_like
+    r0 = solve.fixed_point([G], SE[None], grey=True, tol=1e-13)
+    r7 = solve.fixed_point([G], SE[None], grey=True, a=np.array([0.7]), tol=1e-13)
+    assert r0.iterations == r7.iterations
+    assert np.max(np.abs(r7.J - r0.J)) < 1e-13 * np.max(r0.J)
