@@ -42,9 +42,10 @@ typedef enum {
 typedef enum {
     RTE_FP64 = 0,        /* FP64 entries, ACA, storage and matvec */
     RTE_FP32 = 1,        /* FP32 entries, ACA, storage; FP32 accumulation */
-    RTE_MIXED_BF16 = 2   /* FP32 entries and ACA; low-rank factors stored as BF16 hi + lo
-                            with per-block FP32 scale, dense leaves FP32; solves use
-                            BF16-hi sweeps with FP64 defect correction */
+    RTE_MIXED_BF16 = 2   /* FP32 entries and ACA; every stored element (low-rank factors
+                            and dense leaves) as BF16 hi + lo, hi = bf16(x), lo =
+                            bf16(x - hi); solves use BF16-hi sweeps with FP64 defect
+                            correction */
 } rte_precision_t;
 
 typedef enum { RTE_VOLUME = 0, RTE_SURFACE = 1 } rte_kind_t;
@@ -63,8 +64,13 @@ typedef struct rte_hmat *rte_hmat_t;
  * reflect_axis in {-1,0,1,2}: -1 = no reflective wall; else the box face
  * x[reflect_axis] = (reflect_side ? hi : lo) reflects with coefficient
  * R in [0,1] (Corollary, planar wall, one reflection: Hypothesis 1 with M = 1).
+ * reflect_faces: bit f (faces numbered as for emit_faces) marks further
+ * reflective faces, face f with coefficient R_faces[f] in [0,1] (the several
+ * reflective planes of Section "An Academic Test"); every wall adds the term
+ * of its own mirror image and each ray reflects at most once (Hypothesis 1).
+ * A face may be given once.
  * emit_faces: bit f (0..5 = x-,x+,y-,y+,z-,z+) marks a black emitting face
- * (boundary source Q = B_nu(T_wall), eq. SE1); the reflective face may not emit. */
+ * (boundary source Q = B_nu(T_wall), eq. SE1); a reflective face may not emit. */
 typedef struct {
     int32_t n[3];
     double lo[3], hi[3];
@@ -72,6 +78,8 @@ typedef struct {
     int32_t reflect_side;
     double R;
     uint32_t emit_faces;
+    uint32_t reflect_faces;
+    double R_faces[6];
 } rte_mesh_desc_t;
 
 rte_status_t rte_mesh_create(const rte_mesh_desc_t *desc, rte_mesh_t *out);
@@ -140,9 +148,13 @@ rte_status_t rte_hmat_matvec(rte_hmat_t h, int32_t band, int32_t nrhs, const dou
                              double *y, void *stream);
 
 /* Operator of a matvec on RTE_MIXED_BF16 storage (the other storages have one):
- * RTE_OP_ACCURATE multiplies by the hi + lo factors and adds the FP32
- * matrix-core steps in FP64 (the operator of the defect steps); RTE_OP_LOW
- * multiplies by the BF16 hi factors with FP32 accumulation (inner sweeps). */
+ * RTE_OP_ACCURATE multiplies by the hi + lo factors, with the vector carried
+ * as three BF16 parts (24 significant bits), and adds the FP32 matrix-core
+ * steps in FP64 (the operator of the defect steps); RTE_OP_LOW multiplies the
+ * BF16 hi factors by the vector (and the intermediate V^T x) carried as two
+ * BF16 parts (16 significant bits) with FP32 accumulation: the operator of
+ * the inner sweeps, which apply it to the change of the source since the last
+ * defect step. */
 typedef enum { RTE_OP_ACCURATE = 0, RTE_OP_LOW = 1 } rte_operator_t;
 
 /* y_b = H_b x_b for every band b and nrhs right-hand sides, each phase one
@@ -199,6 +211,10 @@ typedef struct {
     int32_t fill_launches;
     int64_t aca_entries;                          /* entries evaluated inside the ACA launches */
     int64_t aca_retried;                          /* blocks run again with the larger second-pass cap */
+    double alloc_ms;                              /* host time spent allocating and freeing device memory
+                                                     during the assembly, summed over its threads */
+    int64_t free_bytes;                           /* device memory free when the assembly started (including
+                                                     the library's idle scratch pool) */
 } rte_hmat_stats_t;
 
 rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats);
@@ -211,6 +227,24 @@ rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats);
  * then buffers of m*rank and n*rank doubles.  Synchronous. */
 rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, int32_t *rank, int64_t *m,
                                     int64_t *n, double *U, double *V);
+/* Same for one operator of RTE_MIXED_BF16 storage (op: rte_operator_t):
+ * RTE_OP_ACCURATE reads hi + lo, RTE_OP_LOW the BF16 hi parts alone, the
+ * values the low operator multiplies by.  Other storages ignore op. */
+rte_status_t rte_hmat_block_factors_op(rte_hmat_t h, int32_t band, int64_t block, int32_t op, int32_t *rank,
+                                       int64_t *m, int64_t *n, double *U, double *V);
+/* Dense blocks of band `band` (Section "Compression": blocks that reach the
+ * leaves without becoming admissible are stored whole; here also the
+ * admissible blocks whose ACA rank reached the storage break-even and were
+ * stored whole instead), read back to host FP64 so that the stored operator
+ * can be applied by an independent product.  *count receives the number of
+ * dense blocks of the band (the plan's dense leaves, then the admissible
+ * blocks stored dense).  When range or A is non-NULL, block `index` (0 <=
+ * index < *count) is read: range[4] = (t0, t1, s0, s1), half-open row and
+ * column ranges in the cluster orders of rte_plan_export; A: host
+ * [t1 - t0][s1 - s0] row-major, the stored values (FP64, FP32 widened, BF16
+ * hi + lo, or hi alone for op = RTE_OP_LOW).  Synchronous. */
+rte_status_t rte_hmat_dense_block(rte_hmat_t h, int32_t band, int64_t index, int32_t op, int64_t *count,
+                                  int64_t *range, double *A);
 void rte_hmat_destroy(rte_hmat_t h);
 
 /* ------------------------------------------------------------------ fixed point
@@ -249,6 +283,12 @@ typedef struct {
     int64_t monotone_violations;/* vertex-steps where T decreased (from T0 = 0 it should be 0) */
     double ms_total, ms_matvec; /* ms_matvec: HIP-event time of the matvecs (graph launch: of the whole sweeps) */
     int32_t graphs;             /* sweep graphs captured (RTE_LAUNCH_GRAPH) */
+    double ms_matvec_low;       /* HIP-event time of the volume matvecs on the low operator (mixed
+                                   inner sweeps), also inside captured sweeps; -1 if the runtime
+                                   cannot time events recorded inside a graph */
+    int32_t matvecs_low;        /* their number */
+    double ms_matvec_acc;       /* same for the matvecs on the accurate (or only) operator */
+    int32_t matvecs_acc;
 } rte_solve_stats_t;
 
 rte_status_t rte_fixed_point_solve(rte_mesh_t mesh, rte_hmat_t vol, rte_hmat_t surf,
@@ -293,6 +333,8 @@ typedef struct {
     int32_t n_bands;
     const int32_t *bands;        /* host [n_bands], increasing catalogue indices */
     const double *kappa_mult;    /* host [n_bands], > 0 */
+    const double *a;             /* host [n_bands] scattering coefficients in [0, 1) (eq. eqS:
+                                    S = (1 - a) B(T) + a J), or NULL for none */
     const double *T_wall;        /* device [L] (emitting vertices in ascending id order), copied at submit */
     double tol;                  /* relative change of J that ends the request (FP64 residual) */
     int32_t max_iter;

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librte.so")
 
-SOURCES = ["quadrule.cpp", "mesh.cpp", "htree.cpp", "abi.cpp",
+SOURCES = ["quadrule.cpp", "mesh.cpp", "htree.cpp", "abi.cpp", "pool.cpp",
            "entry.hip", "aca.hip", "hmatvec.hip", "solver.hip", "serve.hip"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

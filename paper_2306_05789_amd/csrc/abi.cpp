@@ -66,6 +66,79 @@ void check_kappa(const double *kappa, int64_t n, hipStream_t s) {
     for (double v : h) RTE_REQUIRE(std::isfinite(v) && v >= 0.0, "kappa must be finite and >= 0");
 }
 
+// Stored elements [0, count) of one array of band storage as FP64: FP64 as is,
+// FP32 widened, BF16 hi (+ lo for the accurate operator) summed in FP64.
+std::vector<double> read_stored(const HMat &H, const void *hi, const void *lo, int64_t count, int op) {
+    std::vector<double> out((size_t)count);
+    if (count == 0) return out;
+    if (H.precision == RTE_FP64) {
+        HIP_CHECK(hipMemcpy(out.data(), hi, sizeof(double) * count, hipMemcpyDeviceToHost));
+    } else if (H.precision == RTE_FP32) {
+        std::vector<float> f((size_t)count);
+        HIP_CHECK(hipMemcpy(f.data(), hi, sizeof(float) * count, hipMemcpyDeviceToHost));
+        for (int64_t e = 0; e < count; ++e) out[e] = f[e];
+    } else {
+        auto wid = [](uint16_t h) {
+            const uint32_t u = (uint32_t)h << 16;
+            float f;
+            std::memcpy(&f, &u, 4);
+            return (double)f;
+        };
+        std::vector<uint16_t> h((size_t)count), l(op == RTE_OP_LOW ? 0 : (size_t)count);
+        HIP_CHECK(hipMemcpy(h.data(), hi, 2 * count, hipMemcpyDeviceToHost));
+        if (op != RTE_OP_LOW) HIP_CHECK(hipMemcpy(l.data(), lo, 2 * count, hipMemcpyDeviceToHost));
+        for (int64_t e = 0; e < count; ++e) out[e] = wid(h[e]) + (op == RTE_OP_LOW ? 0.0 : wid(l[e]));
+    }
+    return out;
+}
+
+// The row side of a block (rows [t0, t1) x K stored columns, split into
+// target-leaf slices) as a row-major [m][ncol] matrix; column c of the result
+// is stored column col(c).
+template <typename ColOf>
+void unpack_rows(const HMat &H, const void *hi, const void *lo, int64_t t0, int64_t t1, int64_t K, int64_t ncol,
+                 ColOf col, int op, double *out) {
+    const Plan &P = *H.plan;
+    const int64_t g = H.kgroup, kgp = (K + g - 1) / g * g;
+    const int li0 = P.leaf_of(t0);
+    const int64_t total = kgp * (H.leaf_prp_h[P.leaf_of(t1 - 1) + 1] - H.leaf_prp_h[li0]);
+    const std::vector<double> v = read_stored(H, hi, lo, total, op);
+    for (int64_t i = 0; i < t1 - t0; ++i) {
+        const int li = P.leaf_of(t0 + i);
+        const int64_t rp = H.leaf_prp_h[li + 1] - H.leaf_prp_h[li];
+        const int64_t base = kgp * (H.leaf_prp_h[li] - H.leaf_prp_h[li0]), r = t0 + i - P.leaf_start[li];
+        // element (row r of the slice, column l) at ((l / g) * rp + r) * g + l % g
+        for (int64_t c = 0; c < ncol; ++c) {
+            const int64_t l = col(c);
+            out[i * ncol + c] = v[(size_t)(base + ((l / g) * rp + r) * g + l % g)];
+        }
+    }
+}
+
+void block_factors(const HMat &H, int band, int64_t block, int op, int32_t *rank, int64_t *mo, int64_t *no,
+                   double *U, double *V) {
+    RTE_REQUIRE(band >= 0 && band < H.n_bands, "rte_hmat_block_factors: band out of range");
+    RTE_REQUIRE(block >= 0 && block < (int64_t)H.plan->lowrank.size(), "rte_hmat_block_factors: block out of range");
+    RTE_REQUIRE(op == RTE_OP_ACCURATE || op == RTE_OP_LOW, "rte_hmat_block_factors: unknown operator");
+    const BandStore &B = H.bands[band];
+    const Block &bl = H.plan->lowrank[block];
+    const int64_t m = bl.t1 - bl.t0, n = bl.s1 - bl.s0, k = B.rank[block];
+    *rank = B.rank[block];
+    *mo = m;
+    *no = n;
+    if (!U || !V || k <= 0) return;
+    unpack_rows(H, B.U[block], B.Ulo[block], bl.t0, bl.t1, k, k, [](int64_t c) { return c; }, op, U);
+    // V: [n][pad4(k)], or [nP/8][k][8] over stored source coordinates
+    const int64_t g = H.kgroup;
+    const int64_t nv = g > 1 ? H.pwidth(bl.s0, bl.s1) * k : n * ((k + 3) & ~(int64_t)3);
+    const std::vector<double> vt = read_stored(H, B.V[block], B.Vlo[block], nv, op);
+    for (int64_t j = 0; j < n; ++j) {
+        const int64_t jp = H.src_p_h[bl.s0 + j] - H.src_p_h[bl.s0];
+        for (int64_t l = 0; l < k; ++l)
+            V[j * k + l] = g > 1 ? vt[((jp / 8) * k + l) * 8 + jp % 8] : vt[j * ((k + 3) & ~(int64_t)3) + l];
+    }
+}
+
 }  // namespace
 
 namespace rte {
@@ -76,6 +149,11 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Pla
                                         const rte_hmat_opts_t &o, int n_bands, const double *kappa,
                                         hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
+    const double alloc0 = alloc_ms_this_thread();
+    double alloc_other = 0.0;   // allocation time of the second band thread
+    size_t free_at_start = 0, total_mem = 0;
+    HIP_CHECK(hipMemGetInfo(&free_at_start, &total_mem));
+    free_at_start += pool_idle_bytes();
     auto hm = std::make_unique<rte_hmat>();
     HMat &H = hm->h;
     HIP_CHECK(hipGetDevice(&H.device));
@@ -163,6 +241,7 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Pla
                     HIP_CHECK(hipSetDevice(dev));
                     run(s2);
                     HIP_CHECK(hipStreamSynchronize(s2));
+                    alloc_other = alloc_ms_this_thread();
                 } catch (...) {
                     e2 = std::current_exception();
                     next.store(n_bands);   // the other thread stops taking bands
@@ -231,6 +310,8 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Pla
     st.fill_kernel_ms = fill_ms;
     st.fill_launches = fill_l;
     st.assemble_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st.alloc_ms = alloc_ms_this_thread() - alloc0 + alloc_other;
+    st.free_bytes = (int64_t)free_at_start;
     return hm;
 }
 
@@ -563,61 +644,43 @@ rte_status_t rte_hmat_block_factors(rte_hmat_t h, int32_t band, int64_t block, i
                                     int64_t *no, double *U, double *V) {
     return guard([&] {
         RTE_REQUIRE(h && rank && mo && no, "rte_hmat_block_factors: NULL argument");
+        block_factors(h->h, band, block, RTE_OP_ACCURATE, rank, mo, no, U, V);
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_block_factors_op(rte_hmat_t h, int32_t band, int64_t block, int32_t op, int32_t *rank,
+                                       int64_t *mo, int64_t *no, double *U, double *V) {
+    return guard([&] {
+        RTE_REQUIRE(h && rank && mo && no, "rte_hmat_block_factors_op: NULL argument");
+        block_factors(h->h, band, block, op, rank, mo, no, U, V);
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_dense_block(rte_hmat_t h, int32_t band, int64_t index, int32_t op, int64_t *count,
+                                  int64_t *range, double *A) {
+    return guard([&] {
+        RTE_REQUIRE(h && count, "rte_hmat_dense_block: NULL argument");
         const HMat &H = h->h;
-        RTE_REQUIRE(band >= 0 && band < H.n_bands, "rte_hmat_block_factors: band out of range");
-        RTE_REQUIRE(block >= 0 && block < (int64_t)H.plan->lowrank.size(), "rte_hmat_block_factors: block out of range");
+        RTE_REQUIRE(band >= 0 && band < H.n_bands, "rte_hmat_dense_block: band out of range");
+        RTE_REQUIRE(op == RTE_OP_ACCURATE || op == RTE_OP_LOW, "rte_hmat_dense_block: unknown operator");
         const BandStore &B = H.bands[band];
-        const Block &bl = H.plan->lowrank[block];
-        const int64_t m = bl.t1 - bl.t0, n = bl.s1 - bl.s0, k = B.rank[block];
-        *rank = B.rank[block];
-        *mo = m;
-        *no = n;
-        if (!U || !V || k <= 0) return RTE_OK;
-        const Plan &P = *H.plan;
-        const int64_t g = H.kgroup, kgp = (k + g - 1) / g * g;
-        const int li0 = P.leaf_of(bl.t0);
-        const int64_t mu = kgp * (H.leaf_prp_h[P.leaf_of(bl.t1 - 1) + 1] - H.leaf_prp_h[li0]);
-        const int64_t nv = g > 1 ? H.pwidth(bl.s0, bl.s1) * k : n * ((k + 3) & ~(int64_t)3);
-        std::vector<double> ut(mu), vt(nv);
-        if (H.precision == RTE_FP64) {
-            HIP_CHECK(hipMemcpy(ut.data(), B.U[block], sizeof(double) * mu, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vt.data(), B.V[block], sizeof(double) * nv, hipMemcpyDeviceToHost));
-        } else if (H.precision == RTE_FP32) {
-            std::vector<float> uf(mu), vf(nv);
-            HIP_CHECK(hipMemcpy(uf.data(), B.U[block], sizeof(float) * mu, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vf.data(), B.V[block], sizeof(float) * nv, hipMemcpyDeviceToHost));
-            for (int64_t e = 0; e < mu; ++e) ut[e] = uf[e];
-            for (int64_t e = 0; e < nv; ++e) vt[e] = vf[e];
-        } else {
-            // BF16 hi + lo: the factor value is hi + lo
-            std::vector<uint16_t> uh(mu), ul(mu), vh(nv), vl(nv);
-            HIP_CHECK(hipMemcpy(uh.data(), B.U[block], 2 * mu, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(ul.data(), B.Ulo[block], 2 * mu, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vh.data(), B.V[block], 2 * nv, hipMemcpyDeviceToHost));
-            HIP_CHECK(hipMemcpy(vl.data(), B.Vlo[block], 2 * nv, hipMemcpyDeviceToHost));
-            auto wid = [](uint16_t h) {
-                uint32_t u = (uint32_t)h << 16;
-                float f;
-                std::memcpy(&f, &u, 4);
-                return (double)f;
-            };
-            for (int64_t e = 0; e < mu; ++e) ut[e] = wid(uh[e]) + wid(ul[e]);
-            for (int64_t e = 0; e < nv; ++e) vt[e] = wid(vh[e]) + wid(vl[e]);
+        *count = (int64_t)B.dense_blocks.size();
+        if (!range && !A) return RTE_OK;
+        RTE_REQUIRE(index >= 0 && index < *count, "rte_hmat_dense_block: index out of range");
+        const Block &bl = B.dense_blocks[(size_t)index];
+        if (range) {
+            range[0] = bl.t0;
+            range[1] = bl.t1;
+            range[2] = bl.s0;
+            range[3] = bl.s1;
         }
-        // U: target-leaf slices; element (row r of slice, column l) at
-        // ((l / g) * rp + r) * g + l % g
-        for (int64_t i = 0; i < m; ++i) {
-            const int li = P.leaf_of(bl.t0 + i);
-            const int64_t rp = H.leaf_prp_h[li + 1] - H.leaf_prp_h[li];
-            const int64_t base = kgp * (H.leaf_prp_h[li] - H.leaf_prp_h[li0]), r = bl.t0 + i - P.leaf_start[li];
-            for (int64_t l = 0; l < k; ++l) U[i * k + l] = ut[base + ((l / g) * rp + r) * g + l % g];
-        }
-        // V: [n][pad4(k)], or [nP/8][k][8] over stored source coordinates
-        for (int64_t j = 0; j < n; ++j) {
-            const int64_t jp = H.src_p_h[bl.s0 + j] - H.src_p_h[bl.s0];
-            for (int64_t l = 0; l < k; ++l)
-                V[j * k + l] = g > 1 ? vt[((jp / 8) * k + l) * 8 + jp % 8] : vt[j * ((k + 3) & ~(int64_t)3) + l];
-        }
+        if (!A) return RTE_OK;
+        // columns in stored source coordinates (padded per source leaf on BF16 storage)
+        const int64_t s0p = H.src_p_h[bl.s0];
+        unpack_rows(H, B.dense_ptr[(size_t)index], B.dense_lo[(size_t)index], bl.t0, bl.t1, H.pwidth(bl.s0, bl.s1),
+                    bl.s1 - bl.s0, [&](int64_t c) { return H.src_p_h[bl.s0 + c] - s0p; }, op, A);
         return RTE_OK;
     });
 }

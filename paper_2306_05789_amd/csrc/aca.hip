@@ -222,10 +222,10 @@ __device__ __forceinline__ int hinted_block(const int64_t *__restrict__ off, con
 // Waves per SIMD the entry launches are compiled for: the register budget
 // that keeps the march free of spills (the surface entry needs more
 // registers than the volume one; measured per kind and precision).
-template <typename T, int KIND, bool WALL>
+template <typename T, int KIND, int NW>
 constexpr int entry_waves() {
     if constexpr (sizeof(T) == 8) return KIND == RTE_VOLUME ? 4 : 3;
-    else return KIND == RTE_VOLUME ? (WALL ? 6 : 7) : 5;
+    else return KIND == RTE_VOLUME ? (NW != kNoWall ? 6 : 7) : 5;
 }
 
 // a - sum_l p[l * sp] q[l * sq], l < k, subtracted in order of l; the loads
@@ -251,8 +251,8 @@ __device__ __forceinline__ T residual(T a, const T *p, int64_t sp, const T *q, i
 }
 
 // Step 1: residual rows of every active block, one lane per entry.
-template <typename T, int KIND, bool WALL>
-__global__ __launch_bounds__(256, (entry_waves<T, KIND, WALL>())) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
+template <typename T, int KIND, int NW>
+__global__ __launch_bounds__(256, (entry_waves<T, KIND, NW>())) void k_aca_rows(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256, (entry_waves<T, KIND, WALL>())) void k_aca_row
     T a;
     {
         const AcaTask tk = st.task[b];
-        a = entry<T, KIND, WALL>(c, tgt_nat[tk.t0 + st.istar[b]], src_nat[tk.s0 + j]);
+        a = entry<T, KIND, NW>(c, tgt_nat[tk.t0 + st.istar[b]], src_nat[tk.s0 + j]);
     }
     // the block's state is read again after the march (only b and j stay
     // live through it; the barrier keeps the compiler from reusing the loads)
@@ -322,8 +322,8 @@ __global__ __launch_bounds__(256) void k_aca_pivot(AcaState<T> st) {
 }
 
 // Step 3: residual columns of the pivoted blocks, one lane per entry.
-template <typename T, int KIND, bool WALL>
-__global__ __launch_bounds__(256, (entry_waves<T, KIND, WALL>())) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
+template <typename T, int KIND, int NW>
+__global__ __launch_bounds__(256, (entry_waves<T, KIND, NW>())) void k_aca_cols(EntryCtx<T> c, AcaState<T> st, int64_t total,
                                                   const int64_t *__restrict__ tgt_nat,
                                                   const int64_t *__restrict__ src_nat) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256, (entry_waves<T, KIND, WALL>())) void k_aca_col
     T a;
     {
         const AcaTask tk = st.task[b];
-        a = entry<T, KIND, WALL>(c, tgt_nat[tk.t0 + i], src_nat[tk.s0 + st.jstar[b]]);
+        a = entry<T, KIND, NW>(c, tgt_nat[tk.t0 + i], src_nat[tk.s0 + st.jstar[b]]);
     }
     asm volatile("" ::: "memory");   // as in k_aca_rows
     const AcaTask tk = st.task[b];
@@ -704,21 +704,25 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
         ubase[b] = words;
         words += (tasks[b].m + 31) / 32;
     }
-    DevBuf Us(sizeof(T) * (size_t)uo), Vs(sizeof(T) * (size_t)vo);
-    DevBuf dt = upload(tasks, s), dub = upload(ubase, s);
+    // every buffer of the batch comes from the scratch pool and goes back to it
+    // once the band's stream has drained (band_settle)
+    auto scratch = [](size_t b) { return DevBuf::scratch(b); };
+    DevBuf Us = scratch(sizeof(T) * (size_t)uo), Vs = scratch(sizeof(T) * (size_t)vo);
+    DevBuf dt = upload_scratch(tasks, s), dub = upload_scratch(ubase, s);
     int64_t max_chunks = 0;
     for (auto &t : tasks) max_chunks += (t.m + t.n + kChunk - 1) / kChunk;
-    DevBuf ents(sizeof(int64_t) * (size_t)nb);
-    DevBuf ints(sizeof(int) * (size_t)nb * 7), reals(sizeof(T) * (size_t)nb * 2),
-        used(sizeof(unsigned) * (size_t)words), offs(sizeof(int64_t) * (size_t)(nb + 1) * 3),
-        tot(sizeof(int64_t) * 5), part(sizeof(T) * (size_t)max_chunks * 2 * (size_t)(kmax + 1)),
-        pmax(sizeof(T) * (size_t)max_chunks * 2), pidx(sizeof(int) * (size_t)max_chunks);
+    DevBuf ents = scratch(sizeof(int64_t) * (size_t)nb);
+    DevBuf ints = scratch(sizeof(int) * (size_t)nb * 7), reals = scratch(sizeof(T) * (size_t)nb * 2),
+           used = scratch(sizeof(unsigned) * (size_t)words), offs = scratch(sizeof(int64_t) * (size_t)(nb + 1) * 3),
+           tot = scratch(sizeof(int64_t) * 5),
+           part = scratch(sizeof(T) * (size_t)max_chunks * 2 * (size_t)(kmax + 1)),
+           pmax = scratch(sizeof(T) * (size_t)max_chunks * 2), pidx = scratch(sizeof(int) * (size_t)max_chunks);
     int64_t sum_m = 0, sum_n = 0;
     for (auto &t : tasks) {
         sum_m += t.m;
         sum_n += t.n;
     }
-    DevBuf hints(sizeof(int) * (size_t)((sum_n + 255) / 256 + (sum_m + 255) / 256 + 2));
+    DevBuf hints = scratch(sizeof(int) * (size_t)((sum_n + 255) / 256 + (sum_m + 255) / 256 + 2));
     AcaState<T> st;
     st.task = dt.as<AcaTask>();
     st.nb = nb;
@@ -745,7 +749,10 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     st.pidx = pidx.as<int>();
     st.hint_r = hints.as<int>();
     st.hint_c = hints.as<int>() + (sum_n + 255) / 256 + 1;
-    DevBuf cblock(sizeof(int) * (size_t)std::max<int64_t>(max_chunks, 1));
+    DevBuf cblock = scratch(sizeof(int) * (size_t)std::max<int64_t>(max_chunks, 1));
+    // pooled scratch holds what an earlier batch left: the checking aid fills it with NaN bytes
+    for (DevBuf *d : {&Us, &Vs, &ents, &ints, &reals, &used, &offs, &tot, &part, &pmax, &pidx, &hints, &cblock})
+        poison(*d, s);
     st.cblock = cblock.as<int>();
     st.Us = Us.as<T>();
     st.Vs = Vs.as<T>();
@@ -788,25 +795,41 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
         k_aca_hint<T, true><<<(unsigned)((wc + 255) / 256), 256, 0, s>>>(st, wc, (int)ht[3]);
         k_aca_chunk_block<T><<<(unsigned)((nchunk + 255) / 256), 256, 0, s>>>(st, nchunk, (int)ht[3]);
         HIP_LAUNCH_CHECK();
-        // the entry launches, compiled without the reflected term when the mesh has no wall
-        const bool wall = c.g.wall_axis >= 0;
+        // the entry launches, compiled for the mesh's wall mode (no wall, one, several)
+        const int wm = wall_mode(c.g);
         auto rows = [&](auto kernel) { kernel<<<(unsigned)((nrow + 255) / 256), 256, 0, s>>>(c, st, nrow, tn, sn); };
         auto cols = [&](auto kernel) { kernel<<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(c, st, ncol, tn, sn); };
+        auto launch_rows = [&]() {
+            if (H.kind == RTE_VOLUME) {
+                if (wm == kNoWall) rows(k_aca_rows<T, RTE_VOLUME, kNoWall>);
+                else if (wm == kOneWall) rows(k_aca_rows<T, RTE_VOLUME, kOneWall>);
+                else rows(k_aca_rows<T, RTE_VOLUME, kAnyWalls>);
+            } else {
+                if (wm == kNoWall) rows(k_aca_rows<T, RTE_SURFACE, kNoWall>);
+                else if (wm == kOneWall) rows(k_aca_rows<T, RTE_SURFACE, kOneWall>);
+                else rows(k_aca_rows<T, RTE_SURFACE, kAnyWalls>);
+            }
+        };
+        auto launch_cols = [&]() {
+            if (H.kind == RTE_VOLUME) {
+                if (wm == kNoWall) cols(k_aca_cols<T, RTE_VOLUME, kNoWall>);
+                else if (wm == kOneWall) cols(k_aca_cols<T, RTE_VOLUME, kOneWall>);
+                else cols(k_aca_cols<T, RTE_VOLUME, kAnyWalls>);
+            } else {
+                if (wm == kNoWall) cols(k_aca_cols<T, RTE_SURFACE, kNoWall>);
+                else if (wm == kOneWall) cols(k_aca_cols<T, RTE_SURFACE, kOneWall>);
+                else cols(k_aca_cols<T, RTE_SURFACE, kAnyWalls>);
+            }
+        };
         for (int r = 0; r < kCompact && step <= max_steps; ++r, ++step) {
             mark();
-            if (H.kind == RTE_VOLUME)
-                wall ? rows(k_aca_rows<T, RTE_VOLUME, true>) : rows(k_aca_rows<T, RTE_VOLUME, false>);
-            else
-                wall ? rows(k_aca_rows<T, RTE_SURFACE, true>) : rows(k_aca_rows<T, RTE_SURFACE, false>);
+            launch_rows();
             HIP_LAUNCH_CHECK();
             mark();
             k_aca_pivot<T><<<(unsigned)nact, 256, 0, s>>>(st);
             HIP_LAUNCH_CHECK();
             mark();
-            if (H.kind == RTE_VOLUME)
-                wall ? cols(k_aca_cols<T, RTE_VOLUME, true>) : cols(k_aca_cols<T, RTE_VOLUME, false>);
-            else
-                wall ? cols(k_aca_cols<T, RTE_SURFACE, true>) : cols(k_aca_cols<T, RTE_SURFACE, false>);
+            launch_cols();
             HIP_LAUNCH_CHECK();
             mark();
             k_aca_dots<T><<<(unsigned)nchunk, 256, 0, s>>>(st);
@@ -839,7 +862,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     B.aca_entries += entries;
     B.evaluated += entries;
 
-    DevBuf dr(sizeof(int) * (size_t)nb);
+    DevBuf dr = scratch(sizeof(int) * (size_t)nb);
     k_aca_ranks<<<(nb + 255) / 256, 256, 0, s>>>(st.k, st.status, nb, dr.as<int>());
     HIP_LAUNCH_CHECK();
     std::vector<int> rk(nb);
@@ -900,7 +923,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
         off += nu + nv;   // U and V each start 16-byte aligned for BF16, 32-byte for FP64
     }
     if (!ct.empty()) {
-        DevBuf dct = upload(ct, s);
+        DevBuf dct = upload_scratch(ct, s);
         if (split)
             k_compact_bf16<<<(unsigned)ct.size(), 256, 0, s>>>(dct.as<CompactTask>(), slice_map(H),
                                                               H.src_pmap.as<int64_t>());
@@ -933,6 +956,7 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
     // set-up and its own tail of a few high-rank blocks)
     size_t free_b = 0, total_b = 0;
     HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+    free_b += pool_idle_bytes();   // idle pooled scratch is free for this purpose
     const size_t scratch_limit = std::clamp(free_b / 4, (size_t)2 << 30, (size_t)48 << 30);
     // First pass: every admissible block with the rank cap kAcaMaxRank.  Second
     // pass: the blocks that reached it while their break-even rank is larger
@@ -994,7 +1018,7 @@ void assemble_band(HMat &H, int band, const double *kappa_band, hipStream_t s) {
     if (H.precision == RTE_FP64) {
         assemble_typed<double>(H, band, kappa_band, s);
     } else {
-        DevBuf kf(sizeof(float) * (size_t)H.mesh->N);
+        DevBuf kf = DevBuf::scratch(sizeof(float) * (size_t)H.mesh->N);
         to_float(kappa_band, kf.as<float>(), H.mesh->N, s);
         assemble_typed<float>(H, band, kf.as<float>(), s);
         H.bands[band].retire.push_back(std::move(kf));   // read by queued launches
@@ -1009,6 +1033,7 @@ void band_settle(BandStore &B, hipStream_t s) {
         B.fill_ms += ms;
     }
     B.fill_events.clear();
+    for (DevBuf &d : B.retire) d.settled = true;   // the stream has drained: pooled scratch may be reused
     B.retire.clear();
 }
 

@@ -29,7 +29,7 @@ static_assert(kFillChunk % 256 == 0, "fill tasks are whole workgroups");
 // KIND of the tasks that fill a volume block and its transpose together
 constexpr int kPairedVolume = 2;
 
-template <typename T, int KIND, bool SPLIT>
+template <typename T, int KIND, bool SPLIT, int NW>
 __device__ __forceinline__ void fill_one(const EntryCtx<T> &c, const FillTask &tk, int64_t e,
                                          const int64_t *__restrict__ tgt_nat, const int64_t *__restrict__ src_nat,
                                          const SliceMap &sm) {
@@ -47,7 +47,7 @@ __device__ __forceinline__ void fill_one(const EntryCtx<T> &c, const FillTask &t
     if constexpr (KIND == kPairedVolume) {
         // this entry and its transpose (the volume tree's targets and sources coincide)
         T v, vt;
-        volume_entry_pair(c, tgt_nat[tk.t0 + il], tgt_nat[tk.s0 + jl], v, vt);
+        volume_entry_pair<T, NW>(c, tgt_nat[tk.t0 + il], tgt_nat[tk.s0 + jl], v, vt);
         put(tk.out, tk.outlo,
             slice_offset(sm, tk.li0, tk.t0 + il, tk.kw, sm.src_p[tk.s0 + jl] - sm.src_p[tk.s0], tk.li0 + (int)il + 1),
             v);
@@ -56,14 +56,14 @@ __device__ __forceinline__ void fill_one(const EntryCtx<T> &c, const FillTask &t
                          tk.li0_t + (int)jl + 1),
             vt);
     } else {
-        const T v = entry<T, KIND>(c, tgt_nat[tk.t0 + il], src_nat[tk.s0 + jl]);
+        const T v = entry<T, KIND, NW>(c, tgt_nat[tk.t0 + il], src_nat[tk.s0 + jl]);
         put(tk.out, tk.outlo,
             slice_offset(sm, tk.li0, tk.t0 + il, tk.kw, sm.src_p[tk.s0 + jl] - sm.src_p[tk.s0], tk.li0 + (int)il + 1),
             v);
     }
 }
 
-template <typename T, int KIND, bool SPLIT>
+template <typename T, int KIND, bool SPLIT, int NW>
 __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 3) void k_dense_fill(EntryCtx<T> c,
                                                                         const FillTask *__restrict__ tasks,
                                                                         const int64_t *__restrict__ tgt_nat,
@@ -74,11 +74,11 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 4 : 3) void k_dense_fill(Entr
     const int64_t total = (int64_t)tk.m * tk.n;
     if constexpr (split == kFillChunk / 256) {
         const int64_t e = tk.first + (int64_t)(blockIdx.x % split) * 256 + threadIdx.x;
-        if (e < total) fill_one<T, KIND, SPLIT>(c, tk, e, tgt_nat, src_nat, sm);
+        if (e < total) fill_one<T, KIND, SPLIT, NW>(c, tk, e, tgt_nat, src_nat, sm);
     } else {
         const int64_t end = min(total, tk.first + (int64_t)kFillChunk);
         for (int64_t e = tk.first + threadIdx.x; e < end; e += blockDim.x)
-            fill_one<T, KIND, SPLIT>(c, tk, e, tgt_nat, src_nat, sm);
+            fill_one<T, KIND, SPLIT, NW>(c, tk, e, tgt_nat, src_nat, sm);
     }
 }
 
@@ -143,21 +143,29 @@ void dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vecto
     RTE_REQUIRE(npair == 0 || kind == RTE_VOLUME, "dense fill: paired tasks are for the volume operator");
     if (order.size() > ((size_t)1 << 31) / fill_split<T>())
         throw std::runtime_error("dense fill: too many tasks for one grid");
-    DevBuf dt = upload(order, s);
+    DevBuf dt = upload_scratch(order, s);
     auto c = make_ctx<T>(m, kappa);
     const FillTask *d = dt.as<FillTask>();
     const unsigned gp = (unsigned)(npair * fill_split<T>()), gs = (unsigned)((order.size() - npair) * fill_split<T>());
     const FillTask *ds = d + npair;
     EventPair ev;
     HIP_CHECK(hipEventRecord(ev.a, s));
-    if (split) {
-        if (gp) k_dense_fill<T, kPairedVolume, true><<<gp, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
-        if (gs && kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, true><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
-        else if (gs) k_dense_fill<T, RTE_SURFACE, true><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
-    } else {
-        if (gp) k_dense_fill<T, kPairedVolume, false><<<gp, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
-        if (gs && kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, false><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
-        else if (gs) k_dense_fill<T, RTE_SURFACE, false><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
+    auto launch = [&](auto nw) {
+        constexpr int NW = decltype(nw)::value;
+        if (split) {
+            if (gp) k_dense_fill<T, kPairedVolume, true, NW><<<gp, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+            if (gs && kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, true, NW><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
+            else if (gs) k_dense_fill<T, RTE_SURFACE, true, NW><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
+        } else {
+            if (gp) k_dense_fill<T, kPairedVolume, false, NW><<<gp, 256, 0, s>>>(c, d, tgt_nat, src_nat, sm);
+            if (gs && kind == RTE_VOLUME) k_dense_fill<T, RTE_VOLUME, false, NW><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
+            else if (gs) k_dense_fill<T, RTE_SURFACE, false, NW><<<gs, 256, 0, s>>>(c, ds, tgt_nat, src_nat, sm);
+        }
+    };
+    switch (wall_mode(m.dev)) {
+        case kNoWall: launch(std::integral_constant<int, kNoWall>()); break;
+        case kOneWall: launch(std::integral_constant<int, kOneWall>()); break;
+        default: launch(std::integral_constant<int, kAnyWalls>()); break;
     }
     HIP_LAUNCH_CHECK();
     HIP_CHECK(hipEventRecord(ev.b, s));

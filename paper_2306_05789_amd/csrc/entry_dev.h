@@ -229,12 +229,28 @@ __device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[
     return len * acc;
 }
 
-// Optical depth of the path from x (grid coords P) to the wall and on to y (Q),
+// Wall w's axis, side and coefficient, picked by selects over the constant
+// indices: an index into the grid's arrays that is not a compile-time constant
+// would copy the whole kernel argument to scratch memory.
+struct WallInfo {
+    int axis, side;
+    double R;
+};
+__device__ __forceinline__ WallInfo wall_info(const GridDev &g, int w) {
+    WallInfo r{g.wall_axis[0], g.wall_side[0], g.R[0]};
+#pragma unroll
+    for (int k = 1; k < 6; ++k)
+        if (w == k) r = WallInfo{g.wall_axis[k], g.wall_side[k], g.R[k]};
+    return r;
+}
+
+// Optical depth of the path from x (grid coords P) to wall w and on to y (Q),
 // the wall point being where the segment from the mirror image of x to y meets it.
 template <typename T>
-__device__ T tau_mirror(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3]) {
-    const int a = g.wall_axis;
-    const T C = g.wall_side ? (T)(g.n[a] - 1) : (T)0;
+__device__ T tau_mirror(const GridDev &g, int w, const T *__restrict__ kap, const T P[3], const T Q[3]) {
+    const WallInfo wi = wall_info(g, w);
+    const int a = wi.axis;
+    const T C = wi.side ? (T)(g.n[a] - 1) : (T)0;
     T Pb[3] = {P[0], P[1], P[2]};
     Pb[a] = (T)2 * C - P[a];
     T X[3];
@@ -248,6 +264,17 @@ __device__ T tau_mirror(const GridDev &g, const T *__restrict__ kap, const T P[3
         X[a] = C;
     }
     return tau_segment(g, kap, P, X) + tau_segment(g, kap, X, Q);
+}
+
+// grid index of the mirror image of vertex xi in wall w
+__device__ __forceinline__ void mirror_index(const GridDev &g, int w, const int xi[3], int mi[3]) {
+    const WallInfo wi = wall_info(g, w);
+    const int a = wi.axis;
+    const int Ci = wi.side ? g.n[a] - 1 : 0;
+    mi[0] = xi[0];
+    mi[1] = xi[1];
+    mi[2] = xi[2];
+    mi[a] = 2 * Ci - xi[a];
 }
 
 __device__ __forceinline__ int cheb3(const int a[3], const int b[3]) {
@@ -359,43 +386,19 @@ __device__ __forceinline__ void load_star(const EntryCtx<T> &c, const int jj[3],
     }
 }
 
-// WALL = false: the mesh has no reflective wall (the reflected term and its
-// registers compiled out); WALL = true: whether there is one is read from the
-// grid.
-template <typename T, bool WALL = true>
-__device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
-    const GridDev &g = c.g;
-    int ii[3], jj[3];
-    vtx_index(g, i, ii);
-    vtx_index(g, j, jj);
-    const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
-    const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
-    // optical depths first: the star of j is loaded after the march, so its
-    // 27 values do not stay live through it
-    const T att = exp(-tau_segment(g, c.kappa, P, Q));
-    const bool wall = WALL && g.wall_axis >= 0;
-    const T att_m = wall ? (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) : (T)0;
-    T kn[27];
-    int cellmask;
-    load_star(c, jj, kn, cellmask);
-    const T h2[3] = {(T)(g.h[0] * g.h[0]), (T)(g.h[1] * g.h[1]), (T)(g.h[2] * g.h[2])};
-    const int dg[3] = {ii[0] - jj[0], ii[1] - jj[1], ii[2] - jj[2]};
-    T G = att * vol_quad(c, kn, cellmask, dg, h2, cheb3(ii, jj) <= kNearCheb);
-    if (wall) {
-        const int a = g.wall_axis;
-        const int Ci = g.wall_side ? g.n[a] - 1 : 0;
-        int mi[3] = {ii[0], ii[1], ii[2]};
-        mi[a] = 2 * Ci - ii[a];
-        const int dgm[3] = {mi[0] - jj[0], mi[1] - jj[1], mi[2] - jj[2]};
-        G += att_m * vol_quad(c, kn, cellmask, dgm, h2, cheb3(mi, jj) <= kNearCheb);
-    }
-    return G * (T)g.vol_scale;
-}
+// Wall modes the entry code is compiled for: no wall, exactly one wall (the
+// common reflective case, kept as straight-line code), or any number of walls
+// read from the grid (a loop; its per-wall attenuations go through a small
+// array in scratch memory).
+constexpr int kNoWall = 0, kOneWall = 1, kAnyWalls = 6;
+inline int wall_mode(const GridDev &g) { return g.n_walls == 0 ? kNoWall : (g.n_walls == 1 ? kOneWall : kAnyWalls); }
 
-// The quadrature part of G(target tt, source ss) given the attenuation along
-// the direct and the reflected path.
-template <typename T>
-__device__ __forceinline__ T vol_from_att(const EntryCtx<T> &c, T att, T att_m, const int tt[3], const int ss[3]) {
+// sum over the direct path and the walls of attenuation times the quadrature
+// of the source star of ss seen from target tt (or from its mirror image in
+// each wall); att_w[w] = R_w exp(-tau_w)
+template <typename T, int NW>
+__device__ __forceinline__ T vol_sum(const EntryCtx<T> &c, T att, const T att_w[6], const int tt[3],
+                                     const int ss[3]) {
     const GridDev &g = c.g;
     const T h2[3] = {(T)(g.h[0] * g.h[0]), (T)(g.h[1] * g.h[1]), (T)(g.h[2] * g.h[2])};
     T kn[27];
@@ -403,21 +406,51 @@ __device__ __forceinline__ T vol_from_att(const EntryCtx<T> &c, T att, T att_m, 
     load_star(c, ss, kn, cellmask);
     const int dg[3] = {tt[0] - ss[0], tt[1] - ss[1], tt[2] - ss[2]};
     T G = att * vol_quad(c, kn, cellmask, dg, h2, cheb3(tt, ss) <= kNearCheb);
-    if (g.wall_axis >= 0) {
-        const int a = g.wall_axis;
-        const int Ci = g.wall_side ? g.n[a] - 1 : 0;
-        int mt[3] = {tt[0], tt[1], tt[2]};
-        mt[a] = 2 * Ci - tt[a];
-        const int dgm[3] = {mt[0] - ss[0], mt[1] - ss[1], mt[2] - ss[2]};
-        G += att_m * vol_quad(c, kn, cellmask, dgm, h2, cheb3(mt, ss) <= kNearCheb);
+    if constexpr (NW != kNoWall) {
+        const int nw = NW == kOneWall ? 1 : g.n_walls;
+        for (int w = 0; w < nw; ++w) {
+            int mt[3];
+            mirror_index(g, w, tt, mt);
+            const int dgm[3] = {mt[0] - ss[0], mt[1] - ss[1], mt[2] - ss[2]};
+            G += att_w[w] * vol_quad(c, kn, cellmask, dgm, h2, cheb3(mt, ss) <= kNearCheb);
+        }
     }
     return G * (T)g.vol_scale;
 }
 
+// The optical depths of a pair: direct, and R_w exp(-tau_w) per wall.
+template <typename T, int NW>
+__device__ __forceinline__ T attenuations(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3],
+                                          T att_w[6]) {
+    const T att = exp(-tau_segment(g, kap, P, Q));
+    if constexpr (NW == kOneWall) {
+        att_w[0] = (T)g.R[0] * exp(-tau_mirror(g, 0, kap, P, Q));
+    } else if constexpr (NW == kAnyWalls) {
+        for (int w = 0; w < g.n_walls; ++w) att_w[w] = (T)wall_info(g, w).R * exp(-tau_mirror(g, w, kap, P, Q));
+    }
+    return att;
+}
+
+// G(i, j).  Every wall adds its own mirror-image term (one reflection per
+// ray).  The optical depths come first: the star of j is loaded after the
+// marches, so its 27 values do not stay live through them.
+template <typename T, int NW = kAnyWalls>
+__device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
+    const GridDev &g = c.g;
+    int ii[3], jj[3];
+    vtx_index(g, i, ii);
+    vtx_index(g, j, jj);
+    const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
+    const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
+    T att_w[6];
+    const T att = attenuations<T, NW>(g, c.kappa, P, Q, att_w);
+    return vol_sum<T, NW>(c, att, att_w, ii, jj);
+}
+
 // G(i, j) and G(j, i) together: the optical depth along the segment (and along
-// the reflected path, whose wall point is the same seen from either end) is
+// each reflected path, whose wall point is the same seen from either end) is
 // shared; each entry takes its own source star and quadrature.
-template <typename T>
+template <typename T, int NW = kAnyWalls>
 __device__ __forceinline__ void volume_entry_pair(const EntryCtx<T> &c, int64_t i, int64_t j, T &gij, T &gji) {
     const GridDev &g = c.g;
     int ii[3], jj[3];
@@ -425,10 +458,10 @@ __device__ __forceinline__ void volume_entry_pair(const EntryCtx<T> &c, int64_t 
     vtx_index(g, j, jj);
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
-    const T att = exp(-tau_segment(g, c.kappa, P, Q));
-    const T att_m = g.wall_axis >= 0 ? (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) : (T)0;
-    gij = vol_from_att(c, att, att_m, ii, jj);
-    gji = vol_from_att(c, att, att_m, jj, ii);
+    T att_w[6];
+    const T att = attenuations<T, NW>(g, c.kappa, P, Q, att_w);
+    gij = vol_sum<T, NW>(c, att, att_w, ii, jj);
+    gji = vol_sum<T, NW>(c, att, att_w, jj, ii);
 }
 
 // ---------------------------------------------------------------- surface quadrature
@@ -503,7 +536,7 @@ __device__ T surf_quad(const EntryCtx<T> &c, const int xi[3], const int ll[3], b
     return acc;
 }
 
-template <typename T, bool WALL = true>
+template <typename T, int NW = kAnyWalls>
 __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
     const GridDev &g = c.g;
     int ii[3], ll[3];
@@ -512,20 +545,22 @@ __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)ll[0], (T)ll[1], (T)ll[2]};
     T S = exp(-tau_segment(g, c.kappa, P, Q)) * surf_quad(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
-    if (WALL && g.wall_axis >= 0) {
-        const int a = g.wall_axis;
-        const int Ci = g.wall_side ? g.n[a] - 1 : 0;
-        int mi[3] = {ii[0], ii[1], ii[2]};
-        mi[a] = 2 * Ci - ii[a];
-        S += (T)g.R * exp(-tau_mirror(g, c.kappa, P, Q)) * surf_quad(c, mi, ll, cheb3(mi, ll) <= kNearCheb);
+    if constexpr (NW != kNoWall) {
+        const int nw = NW == kOneWall ? 1 : g.n_walls;
+        for (int w = 0; w < nw; ++w) {
+            int mi[3];
+            mirror_index(g, w, ii, mi);
+            S += (T)wall_info(g, w).R * exp(-tau_mirror(g, w, c.kappa, P, Q)) *
+                 surf_quad(c, mi, ll, cheb3(mi, ll) <= kNearCheb);
+        }
     }
     return S;
 }
 
-template <typename T, int KIND, bool WALL = true>
+template <typename T, int KIND, int NW = kAnyWalls>
 __device__ __forceinline__ T entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
-    if constexpr (KIND == RTE_VOLUME) return volume_entry<T, WALL>(c, i, j);
-    else return surface_entry<T, WALL>(c, i, j);
+    if constexpr (KIND == RTE_VOLUME) return volume_entry<T, NW>(c, i, j);
+    else return surface_entry<T, NW>(c, i, j);
 }
 
 }  // namespace rte

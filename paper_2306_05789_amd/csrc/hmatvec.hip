@@ -25,8 +25,9 @@
 // source coordinates, phase A multiplies 16-rank tiles of V^T by them, a
 // fixed-order pass adds the chunk partials and splits t the same way, and
 // phase B multiplies 16-row tiles of the K-grouped slices by 32-column steps
-// of x or t.  The low operator (inner sweeps) takes hi factors times hi + mid
-// with FP32 accumulation; the accurate operator takes hi + lo factors times
+// of x or t.  The low operator (inner sweeps, applied to the change of the
+// source between defect steps) takes hi factors times hi + mid with FP32
+// accumulation; the accurate operator takes hi + lo factors times
 // hi + mid + lo and adds every 32-column step's FP32 result into FP64.
 // FP64 storage with more than 4 right-hand sides runs both phases on the
 // FP64 matrix cores (v_mfma_f64_16x16x4_f64) over the same work lists, 16
@@ -530,7 +531,11 @@ __global__ void k_mf_xstage(const int64_t *__restrict__ pmap, int64_t np, int nb
 
 template <int MODE>
 struct MfOps {
-    static constexpr int NS = MODE == kMatvecAccurate ? 3 : 2;   // operand splits used
+    // operand splits used: the accurate operator carries the vector in three
+    // BF16 parts (24 significant bits), the low operator in two (16 bits).
+    // With the hi part alone the inner sweeps stall at the BF16 rounding of
+    // the source change (measured: a mixed solve to 1e-9 no longer converged).
+    static constexpr int NS = MODE == kMatvecAccurate ? 3 : 2;
     bf16x8 bx[NS], a[4], al[4];
 };
 

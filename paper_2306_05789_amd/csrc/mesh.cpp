@@ -267,9 +267,20 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
     RTE_REQUIRE(d.reflect_axis < 0 || (std::isfinite(d.R) && d.R >= 0.0 && d.R <= 1.0),
                 "mesh: R must lie in [0, 1]");
     RTE_REQUIRE(d.emit_faces < 64u, "mesh: emit_faces has 6 bits");
-    if (d.reflect_axis >= 0)
-        RTE_REQUIRE(!((d.emit_faces >> (2 * d.reflect_axis + d.reflect_side)) & 1u),
-                    "mesh: the reflective face cannot also emit");
+    RTE_REQUIRE(d.reflect_faces < 64u, "mesh: reflect_faces has 6 bits");
+    // the reflective walls: the single one of reflect_axis, then those of reflect_faces
+    std::vector<std::pair<int, double>> walls;   // (face, R)
+    if (d.reflect_axis >= 0) walls.push_back({2 * d.reflect_axis + d.reflect_side, d.R});
+    for (int f = 0; f < 6; ++f)
+        if ((d.reflect_faces >> f) & 1u) {
+            RTE_REQUIRE(d.reflect_axis < 0 || f != 2 * d.reflect_axis + d.reflect_side,
+                        "mesh: a face is given as reflective twice");
+            RTE_REQUIRE(std::isfinite(d.R_faces[f]) && d.R_faces[f] >= 0.0 && d.R_faces[f] <= 1.0,
+                        "mesh: R_faces must lie in [0, 1]");
+            walls.push_back({f, d.R_faces[f]});
+        }
+    for (auto &w : walls)
+        RTE_REQUIRE(!((d.emit_faces >> w.first) & 1u), "mesh: a reflective face cannot also emit");
     int64_t N = (int64_t)d.n[0] * d.n[1] * d.n[2];
     RTE_REQUIRE(N < (int64_t)1 << 31, "mesh: more than 2^31 vertices");
     M.desc = d;
@@ -296,9 +307,20 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
     g.stride[0] = d.n[1] * d.n[2];
     g.stride[1] = d.n[2];
     g.stride[2] = 1;
-    g.wall_axis = (d.reflect_axis >= 0 && d.R > 0.0) ? d.reflect_axis : -1;
-    g.wall_side = d.reflect_side;
-    g.R = d.reflect_axis >= 0 ? d.R : 0.0;
+    // walls with R = 0 add nothing and are left out
+    g.n_walls = 0;
+    for (auto &w : walls) {
+        if (!(w.second > 0.0)) continue;
+        g.wall_axis[g.n_walls] = w.first / 2;
+        g.wall_side[g.n_walls] = w.first % 2;
+        g.R[g.n_walls] = w.second;
+        ++g.n_walls;
+    }
+    for (int k = g.n_walls; k < 6; ++k) {
+        g.wall_axis[k] = 0;
+        g.wall_side[k] = 0;
+        g.R[k] = 0.0;
+    }
     g.emit_faces = d.emit_faces;
     const double four_pi = 4.0 * M_PI;
     g.vol_scale = M.h[0] * M.h[1] * M.h[2] / 6.0 / four_pi;

@@ -31,9 +31,15 @@ __device__ __forceinline__ void planck_d(double nu, double T, double &B, double 
 
 // The temperature T >= 0 solving sum_b c_b (J_b - B_{nu_b}(T)) = 0 with
 // c_b >= 0 (c_b = w_b kappa_b (1 - a_b)), started from Told.  band(b, nu, c, J)
-// gives nu_b, c_b and J_b.  f decreases in T and f(0) = sum c_b J_b: a
-// bracketed Newton iteration, a step that leaves the bracket replaced by
-// bisection.
+// gives nu_b, c_b and J_b.  f decreases in T and f(0) = sum c_b J_b > 0: a
+// safeguarded Newton iteration.  Every evaluation narrows the bracket
+// [lo, hi] by the sign of f (hi starts unbounded); a step that leaves it is
+// replaced by bisection, or by doubling while hi is unbounded.  Newton
+// converges quadratically from the previous sweep's temperature, so once a
+// Newton step is below 1e-13 relative the iterate after it is at the rounding
+// level and the iteration stops, whether or not that step lands strictly
+// inside the bracket (at the root the step rounds to nothing, and rejecting it
+// for a bisection would restart the search from the far end of the bracket).
 template <typename Band>
 __device__ double solve_temperature(int nb, double Told, Band band) {
     double f0 = 0.0;
@@ -55,18 +61,20 @@ __device__ double solve_temperature(int nb, double Told, Band band) {
         df = d;
         return s;
     };
-    double lo = 0.0, hi = Told > 0.0 ? 2.0 * Told : 1.0, d;
-    for (int it = 0; it < 200 && f(hi, d) > 0.0; ++it) { lo = hi; hi *= 2.0; }
-    double x = (Told > lo && Told < hi) ? Told : 0.5 * (lo + hi);
-    for (int it = 0; it < 100; ++it) {
+    double lo = 0.0, hi = INFINITY, d;
+    double x = Told > 0.0 ? Told : 1.0;
+    for (int it = 0; it < 200; ++it) {
         const double fx = f(x, d);
         if (fx == 0.0) break;
         if (fx > 0.0) lo = x; else hi = x;
-        double xn = (d < 0.0) ? x - fx / d : 0.5 * (lo + hi);
-        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        const double dx = fabs(xn - x);
+        double xn = (d < 0.0) ? x - fx / d : -1.0;
+        if (xn > 0.0 && fabs(xn - x) <= 1e-13 * x) {   // the Newton step is at the rounding level
+            x = xn;
+            break;
+        }
+        if (!(xn > lo && xn < hi)) xn = isinf(hi) ? 2.0 * x : 0.5 * (lo + hi);
         x = xn;
-        if (dx <= 2.3e-16 * x || hi - lo <= 2.3e-16 * hi) break;
+        if (hi - lo <= 2.3e-16 * hi && !isinf(hi)) break;
     }
     return x;
 }

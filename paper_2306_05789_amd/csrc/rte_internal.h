@@ -57,9 +57,10 @@ struct GridDev {
     int n[3];
     int stride[3];          // natural-order strides: n1*n2, n2, 1
     double lo[3], h[3];
-    int wall_axis;          // -1: none
-    int wall_side;
-    double R;
+    int n_walls;            // planar reflective walls (whole box faces, one reflection each)
+    int wall_axis[6];
+    int wall_side[6];       // 0: the plane at lo, 1: at hi
+    double R[6];
     unsigned emit_faces;
     double vol_scale;       // |tet| / (4 pi)
     double area_scale[3];   // |triangle| / (4 pi) for faces normal to axis a
@@ -167,31 +168,55 @@ std::shared_ptr<const Plan> mesh_plan(const Mesh &m, const rte_hmat_opts_t &opts
 std::shared_ptr<PlanCache> new_plan_cache();
 
 // ---------------------------------------------------------------- device memory helper
+// An owned device allocation.  DevBuf(b) / alloc(b) take it from hipMalloc
+// (on out-of-memory the idle scratch pool is released and the call retried);
+// DevBuf::scratch(b) takes it from the per-device scratch pool (pool.cpp).
+// A scratch buffer goes back to the pool on release only when `settled` was
+// set, which says that no queued work reads it any more (its stream has
+// drained); otherwise it is freed with hipFree, which waits for the device.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    size_t cap = 0;          // scratch: capacity of the pooled allocation
+    bool pooled = false;
+    bool settled = false;
     DevBuf() = default;
     explicit DevBuf(size_t b) { alloc(b); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept { take(o); }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        if (this != &o) {
+            release();
+            take(o);
+        }
         return *this;
     }
     ~DevBuf() { release(); }
-    void alloc(size_t b) {
-        release();
-        if (b) HIP_CHECK(hipMalloc(&p, b));
-        bytes = b;
-    }
-    void release() noexcept {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
+    void alloc(size_t b);
+    void release() noexcept;
+    static DevBuf scratch(size_t b);
     template <typename T> T *as() const { return static_cast<T *>(p); }
+
+private:
+    void take(DevBuf &o) noexcept {
+        p = o.p;
+        bytes = o.bytes;
+        cap = o.cap;
+        pooled = o.pooled;
+        settled = o.settled;
+        o.p = nullptr;
+        o.bytes = o.cap = 0;
+        o.pooled = o.settled = false;
+    }
 };
+
+// Scratch pool of the current device (pool.cpp).
+void *pool_take(size_t bytes, size_t *cap);
+void pool_give(void *p, size_t cap);
+size_t pool_idle_bytes();   // idle pooled bytes on the current device
+void pool_trim();           // free the idle pooled buffers of the current device
+double &alloc_ms_this_thread();   // host ms this thread spent allocating and freeing device memory
 
 // Checking aid: with RTE_POISON_WORKSPACE set in the environment, scratch
 // buffers are filled with 0xFF bytes (NaN in every floating format) when they
@@ -205,6 +230,16 @@ inline void poison(DevBuf &b, hipStream_t s) {
 template <typename T>
 DevBuf upload(const std::vector<T> &v, hipStream_t s) {
     DevBuf b(v.size() * sizeof(T));
+    if (!v.empty()) {
+        HIP_CHECK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    return b;
+}
+
+// Same into pooled scratch (for task lists retired with the band's scratch).
+template <typename T>
+DevBuf upload_scratch(const std::vector<T> &v, hipStream_t s) {
+    DevBuf b = DevBuf::scratch(v.size() * sizeof(T));
     if (!v.empty()) {
         HIP_CHECK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
     }

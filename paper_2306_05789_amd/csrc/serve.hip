@@ -53,6 +53,7 @@ constexpr int kSrvResidBlocks = 32;
 // one (request, band) column of a sweep
 struct SrvCol {
     double nu;
+    double a;            // scattering coefficient of the band (eq. eqS)
     const double *T;     // request temperatures [N], cluster order
     double *Sm;          // source of the last defect step (mixed), else null
     const double *y0;    // S^E (plain sweep, defect step) or J_acc (inner sweep)
@@ -62,13 +63,15 @@ struct SrvCol {
     int32_t save;        // defect step of the mixed iteration: keep S(T) and J_acc
 };
 
-// x[c] = B_nu(T) (minus S_m on inner sweeps); a defect step keeps B_nu(T) in S_m
+// x[c] = S = (1 - a) B_nu(T) + a J (minus S_m on inner sweeps); a defect step
+// keeps S in S_m
 __global__ void k_srv_x(const SrvCol *__restrict__ cols, int64_t N, double *__restrict__ x) {
     const int c = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const SrvCol col = cols[c];
-    const double s = planck(col.nu, col.T[i]);
+    const double e = planck(col.nu, col.T[i]);
+    const double s = col.a != 0.0 ? (1.0 - col.a) * e + col.a * col.J[i] : e;
     x[(int64_t)c * N + i] = col.inner ? s - col.Sm[i] : s;
     if (col.save) col.Sm[i] = s;
 }
@@ -123,7 +126,7 @@ struct SrvNewt {
     int32_t nb, b0;
 };
 struct SrvBand {
-    double nu, w, mult;   // frequency, catalogue weight, snapped kappa multiplier
+    double nu, w, mult, a;   // frequency, catalogue weight, snapped kappa multiplier, scattering
     const double *J;
 };
 
@@ -135,7 +138,7 @@ __global__ void k_srv_newton(const SrvNewt *__restrict__ reqs, const SrvBand *__
     r.T[i] = solve_temperature(r.nb, r.T[i], [&](int b, double &nu, double &c, double &j) {
         const SrvBand &bd = bands[r.b0 + b];
         nu = bd.nu;
-        c = bd.w * bd.mult * k;
+        c = bd.w * bd.mult * k * (1.0 - bd.a);
         j = bd.J[i];
     });
 }
@@ -202,6 +205,7 @@ struct SrvReq {
     int64_t id = 0;
     int mesh = 0;
     std::vector<int> bands, levels;
+    std::vector<double> a;      // scattering coefficient per band
     std::vector<SrvOp *> ops;   // per band
     double tol = 1e-6;
     int max_iter = 1000;
@@ -617,8 +621,9 @@ struct Server {
             const bool inner = mixed() && r->phase == 1;
             const bool save = mixed() && r->phase == 0;
             for (int b = 0; b < (int)r->bands.size(); ++b) {
-                SrvCol c{nu[r->bands[b]], r->T(), mixed() ? r->Sm(N, b) : nullptr, inner ? r->Jacc(N, b) : r->SE(N, b),
-                         r->J(N, b), mixed() ? r->Jacc(N, b) : nullptr, inner ? 1 : 0, save ? 1 : 0};
+                SrvCol c{nu[r->bands[b]], r->a[b], r->T(), mixed() ? r->Sm(N, b) : nullptr,
+                         inner ? r->Jacc(N, b) : r->SE(N, b), r->J(N, b), mixed() ? r->Jacc(N, b) : nullptr,
+                         inner ? 1 : 0, save ? 1 : 0};
                 auto it = std::find_if(groups.begin(), groups.end(),
                                        [&](const Group &g) { return g.op == r->ops[b] && g.inner == (int)inner; });
                 if (it == groups.end()) {
@@ -684,7 +689,7 @@ struct Server {
             nt.push_back({r->T(), M.kap_c.as<double>(), M.mesh.N, (int32_t)r->bands.size(), (int32_t)bt.size()});
             for (int b = 0; b < (int)r->bands.size(); ++b)
                 bt.push_back({nu[r->bands[b]], w[r->bands[b]], std::pow(10.0, (double)r->levels[b] / desc.levels_per_decade),
-                              r->J(M.mesh.N, b)});
+                              r->a[b], r->J(M.mesh.N, b)});
             maxN = std::max(maxN, M.mesh.N);
         }
         hnewt.reserve(sizeof(SrvNewt) * nt.size());
@@ -858,6 +863,9 @@ int64_t server_submit(Server &S, const rte_request_t &q) {
         RTE_REQUIRE(q.bands[b] >= 0 && q.bands[b] < (int)S.nu.size() && (b == 0 || q.bands[b] > q.bands[b - 1]),
                     "request: band indices must be increasing catalogue indices");
         RTE_REQUIRE(std::isfinite(q.kappa_mult[b]) && q.kappa_mult[b] > 0, "request: kappa multipliers must be > 0");
+        const double ab = q.a ? q.a[b] : 0.0;
+        RTE_REQUIRE(std::isfinite(ab) && ab >= 0.0 && ab < 1.0, "request: scattering coefficients must lie in [0, 1)");
+        r->a.push_back(ab);
         r->bands.push_back(q.bands[b]);
         r->levels.push_back(Server::snap(q.kappa_mult[b], S.desc.levels_per_decade));
     }

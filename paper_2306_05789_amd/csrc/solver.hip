@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "kernels.h"
 #include "physics.h"
@@ -184,6 +185,42 @@ void check_desc(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_des
             RTE_REQUIRE(std::isfinite(d.a[b]) && d.a[b] >= 0 && d.a[b] < 1, "solve: a must lie in [0, 1)");
 }
 
+__global__ void k_probe(int *p) {
+    if (p && threadIdx.x == 0) p[0] = 1;
+}
+
+// Whether events recorded inside a captured graph (event record nodes) give
+// elapsed times on this runtime: probed once per process on a tiny graph, so
+// that the solver can time the matvecs inside its graph-launched sweeps.
+bool graph_events_work(hipStream_t s) {
+    static std::once_flag once;
+    static bool ok = false;
+    std::call_once(once, [&] {
+        hipEvent_t a = nullptr, b = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        bool good = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+                    hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (good) {
+            bool rec = hipEventRecord(a, s) == hipSuccess;
+            k_probe<<<1, 64, 0, s>>>(nullptr);
+            rec = rec && hipGetLastError() == hipSuccess && hipEventRecord(b, s) == hipSuccess;
+            good = hipStreamEndCapture(s, &g) == hipSuccess && g && rec;
+        }
+        good = good && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+        good = good && hipGraphLaunch(ex, s) == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
+        float ms = -1.0f;
+        good = good && hipEventElapsedTime(&ms, a, b) == hipSuccess && ms >= 0.0f;
+        (void)hipGetLastError();
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (g) (void)hipGraphDestroy(g);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        ok = good;
+    });
+    return ok;
+}
+
 }  // namespace
 
 // Graph launch works on a stream of its own (non-blocking, default priority):
@@ -260,10 +297,17 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
     HIP_CHECK(hipMemsetAsync(J.p, 0, J.bytes, s));
     HIP_CHECK(hipMemsetAsync(viol.p, 0, viol.bytes, s));
 
-    hipEvent_t e0, e1;
+    hipEvent_t e0, e1, m0, m1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
+    HIP_CHECK(hipEventCreate(&m0));
+    HIP_CHECK(hipEventCreate(&m1));
     float mv_ms = 0.0f;
+    // volume-matvec time per operator: events around the matvec launches, also
+    // inside captured sweeps when the runtime times event record nodes
+    const bool mv_events = d.launch != RTE_LAUNCH_GRAPH || graph_events_work(s);
+    double op_ms[2] = {0.0, 0.0};
+    int op_count[2] = {0, 0};
     std::vector<double> rv(2 * nb * nr);
     const bool mixed = d.precision == RTE_MIXED_BF16;
     DevBuf Jacc(mixed ? sizeof(double) * vecN * nb : 0), Sm(mixed ? sizeof(double) * vecN * nb : 0);
@@ -277,7 +321,9 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
             k_sub<<<(unsigned)((vecN * nb + 255) / 256), 256, 0, s>>>(Sv.as<double>(), sub, vecN * nb, Sv.as<double>());
         HIP_LAUNCH_CHECK();
         if (timed) HIP_CHECK(hipEventRecord(e0, s));
+        if (mv_events) HIP_CHECK(hipEventRecord(m0, s));
         matvec_launch_all(G, nr, Sv.as<double>(), Jn.as<double>(), y0, tbuf.as<double>(), s, mode);
+        if (mv_events) HIP_CHECK(hipEventRecord(m1, s));
         if (timed) HIP_CHECK(hipEventRecord(e1, s));
         k_resid_partial<<<dim3(kResidBlocks, nb * nr), 256, 0, s>>>(J.as<double>(), Jn.as<double>(), N,
                                                                      part.as<double>());
@@ -316,6 +362,12 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
         float ms = 0.0f;
         HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
         mv_ms += ms;
+        if (mv_events) {
+            float mm = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&mm, m0, m1));
+            op_ms[mode == kMatvecLow ? 0 : 1] += mm;
+            op_count[mode == kMatvecLow ? 0 : 1] += 1;
+        }
         double q = 0.0;
         for (int v = 0; v < nb * nr; ++v) {
             const double num = rv[2 * v], den = rv[2 * v + 1];
@@ -366,6 +418,8 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(m0);
+    (void)hipEventDestroy(m1);
     if (T_out) permute_scatter(G.tgt_nat.as<int64_t>(), N, nr, N, N, T.as<double>(), T_out, s);
     if (J_out)
         for (int b = 0; b < nb; ++b)
@@ -383,6 +437,10 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
         st->ms_matvec = mv_ms;
         st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         st->graphs = graphs.size();
+        st->ms_matvec_low = mv_events ? op_ms[0] : -1.0;
+        st->matvecs_low = op_count[0];
+        st->ms_matvec_acc = mv_events ? op_ms[1] : -1.0;
+        st->matvecs_acc = op_count[1];
     }
     if (!std::isfinite(r)) throw Error(RTE_E_INTERNAL, "solve: the residual is not finite");
     return conv ? RTE_OK : RTE_E_NOT_CONVERGED;

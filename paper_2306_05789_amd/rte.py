@@ -28,7 +28,7 @@ class RteError(RuntimeError):
 class MeshDesc(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("reflect_axis", C.c_int32), ("reflect_side", C.c_int32), ("R", C.c_double),
-                ("emit_faces", C.c_uint32)]
+                ("emit_faces", C.c_uint32), ("reflect_faces", C.c_uint32), ("R_faces", C.c_double * 6)]
 
 
 class HmatOpts(C.Structure):
@@ -51,7 +51,7 @@ class HmatStats(C.Structure):
                 ("aca_kernel_ms", C.c_double), ("aca_launches", C.c_int32),
                 ("aca_entry_ms", C.c_double), ("aca_entry_launches", C.c_int32),
                 ("fill_kernel_ms", C.c_double), ("fill_launches", C.c_int32), ("aca_entries", C.c_int64),
-                ("aca_retried", C.c_int64)]
+                ("aca_retried", C.c_int64), ("alloc_ms", C.c_double), ("free_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -67,7 +67,8 @@ class SolveDesc(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("outer_steps", C.c_int32), ("residual", C.c_double),
                 ("monotone_violations", C.c_int64), ("ms_total", C.c_double), ("ms_matvec", C.c_double),
-                ("graphs", C.c_int32)]
+                ("graphs", C.c_int32), ("ms_matvec_low", C.c_double), ("matvecs_low", C.c_int32),
+                ("ms_matvec_acc", C.c_double), ("matvecs_acc", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -88,8 +89,8 @@ class ServerDesc(C.Structure):
 
 class Request(C.Structure):
     _fields_ = [("mesh_id", C.c_int32), ("n_bands", C.c_int32), ("bands", C.POINTER(C.c_int32)),
-                ("kappa_mult", C.POINTER(C.c_double)), ("T_wall", C.c_void_p), ("tol", C.c_double),
-                ("max_iter", C.c_int32)]
+                ("kappa_mult", C.POINTER(C.c_double)), ("a", C.POINTER(C.c_double)), ("T_wall", C.c_void_p),
+                ("tol", C.c_double), ("max_iter", C.c_int32)]
 
 
 class RequestInfo(C.Structure):
@@ -144,6 +145,10 @@ SIGNATURES = {
     "rte_server_destroy": (None, [C.c_void_p]),
     "rte_hmat_block_factors": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
+    "rte_hmat_block_factors_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
+    "rte_hmat_dense_block": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_int64),
+                                       C.c_void_p, C.c_void_p]),
     "rte_hmat_destroy": (None, [C.c_void_p]),
     "rte_fixed_point_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveDesc),
                                         C.c_void_p, C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),
@@ -210,18 +215,24 @@ class Mesh:
 
 
 def mesh_desc(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), reflect_axis=-1, reflect_side=0, R=0.0,
-              emit_faces=1) -> MeshDesc:
+              emit_faces=1, walls=None) -> MeshDesc:
+    """walls: further reflective faces as (axis, side, R) triples."""
     d = MeshDesc()
     d.n[:] = [int(v) for v in n]
     d.lo[:] = [float(v) for v in lo]
     d.hi[:] = [float(v) for v in hi]
     d.reflect_axis, d.reflect_side, d.R, d.emit_faces = int(reflect_axis), int(reflect_side), float(R), int(emit_faces)
+    d.reflect_faces = 0
+    for axis, side, r in (walls or []):
+        f = 2 * int(axis) + int(side)
+        d.reflect_faces |= 1 << f
+        d.R_faces[f] = float(r)
     return d
 
 
 def rte_mesh_create(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), reflect_axis=-1, reflect_side=0, R=0.0,
-                    emit_faces=1) -> Mesh:
-    d = mesh_desc(n, lo, hi, reflect_axis, reflect_side, R, emit_faces)
+                    emit_faces=1, walls=None) -> Mesh:
+    d = mesh_desc(n, lo, hi, reflect_axis, reflect_side, R, emit_faces, walls)
     h = C.c_void_p()
     _check(load().rte_mesh_create(C.byref(d), C.byref(h)))
     N, L = C.c_int64(), C.c_int64()
@@ -359,6 +370,42 @@ def rte_hmat_block_factors(hmat: HMat, band: int, block: int, factors: bool = Tr
     _check(_lib.rte_hmat_block_factors(hmat.handle, int(band), int(block), C.byref(k), C.byref(m), C.byref(n),
                                        U.ctypes.data_as(C.c_void_p), V.ctypes.data_as(C.c_void_p)))
     return k.value, U, V
+
+
+def rte_hmat_block_factors_op(hmat: HMat, band: int, block: int, op: int):
+    """(rank, U, V) of an admissible block for one operator (RTE_OP_LOW: the BF16 hi
+    parts of mixed-precision storage); U, V are None when the block is stored dense."""
+    import numpy as np
+    k, m, n = C.c_int32(), C.c_int64(), C.c_int64()
+    _check(load().rte_hmat_block_factors_op(hmat.handle, int(band), int(block), int(op), C.byref(k), C.byref(m),
+                                            C.byref(n), None, None))
+    if k.value <= 0:
+        return k.value, None, None
+    U = np.empty((m.value, k.value))
+    V = np.empty((n.value, k.value))
+    _check(_lib.rte_hmat_block_factors_op(hmat.handle, int(band), int(block), int(op), C.byref(k), C.byref(m),
+                                          C.byref(n), U.ctypes.data_as(C.c_void_p), V.ctypes.data_as(C.c_void_p)))
+    return k.value, U, V
+
+
+def rte_hmat_dense_count(hmat: HMat, band: int) -> int:
+    cnt = C.c_int64()
+    _check(load().rte_hmat_dense_block(hmat.handle, int(band), 0, RTE_OP_ACCURATE, C.byref(cnt), None, None))
+    return cnt.value
+
+
+def rte_hmat_dense_block(hmat: HMat, band: int, index: int, op: int = 0):
+    """((t0, t1, s0, s1), A) of dense block `index` of a band, A as stored (FP64)."""
+    import numpy as np
+    cnt = C.c_int64()
+    rng = np.empty(4, dtype=np.int64)
+    _check(load().rte_hmat_dense_block(hmat.handle, int(band), int(index), int(op), C.byref(cnt),
+                                       rng.ctypes.data_as(C.c_void_p), None))
+    t0, t1, s0, s1 = (int(v) for v in rng)
+    A = np.empty((t1 - t0, s1 - s0))
+    _check(_lib.rte_hmat_dense_block(hmat.handle, int(band), int(index), int(op), C.byref(cnt),
+                                     rng.ctypes.data_as(C.c_void_p), A.ctypes.data_as(C.c_void_p)))
+    return (t0, t1, s0, s1), A
 
 
 def rte_fixed_point_solve(mesh: Mesh, vol: HMat, surf: HMat, T_wall, T_out, J_out=None, *, grey=True,

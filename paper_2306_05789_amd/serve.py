@@ -41,13 +41,16 @@ class Server:
         rte._check(rte.load().rte_server_add_mesh(self.handle, C.byref(md), rte._ptr(kappa), C.byref(mid)))
         return mid.value
 
-    def submit(self, mesh_id, bands, kappa_mult, T_wall, tol=1e-6, max_iter=2000) -> int:
+    def submit(self, mesh_id, bands, kappa_mult, T_wall, tol=1e-6, max_iter=2000, a=None) -> int:
+        """a: scattering coefficient per band (None: no scattering)."""
         b = np.ascontiguousarray(bands, dtype=np.int32)
         m = np.ascontiguousarray(kappa_mult, dtype=np.float64)
+        sc = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
         q = rte.Request()
         q.mesh_id, q.n_bands = int(mesh_id), len(b)
         q.bands = b.ctypes.data_as(C.POINTER(C.c_int32))
         q.kappa_mult = m.ctypes.data_as(C.POINTER(C.c_double))
+        q.a = sc.ctypes.data_as(C.POINTER(C.c_double)) if sc is not None else None
         q.T_wall = T_wall.data_ptr()
         q.tol, q.max_iter = float(tol), int(max_iter)
         rid = C.c_int64()
