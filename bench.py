@@ -1,28 +1,34 @@
 #!/usr/bin/env python
 """Benchmark of the integral-form radiative transfer hot path on one MI355X.
 
-One step = one full solve of the FP64 H-matrix workload (unit cube, 41^3
-vertices, grey, smooth kappa(x) = 0.5 + 0.4 sin(2 pi x) cos(2 pi y) z, wall
-x = 0 at T = 1, leaf 64, eta 2, ACA 1e-5, fixed point to 1e-10): assembly of
-the volume matrix G and the boundary-source matrix S on the GPU (entry
-kernel + ACA + dense leaves; the two on concurrent streams), then the
-monotone fixed point (H-matvecs + per-vertex temperature update).  Inputs (kappa, wall temperatures) are
-resident in HBM before the timed region.
+Headline (the default): the batched mixed-precision workload.  Unit cube on a
+49^3 grid (117,649 vertices), 32 frequency bands with kappa_b = c_b kappa(x)
+(c_b lognormal(0, 1), seed 4), all six faces emitting with 16 right-hand
+sides of random wall temperatures in [0.5, 2] (seed 5); leaf 64, eta 2, ACA
+1e-5; FP32 entries and ACA, BF16 hi + lo factors; every solve runs BF16 sweeps
+over all 32 bands and 16 right-hand sides (one launch per phase, replayed from
+captured hipGraphs) with FP64 defect correction, to an FP64 relative residual
+of 1e-6.  The operators (G and S of every band) are assembled once before the
+timed region and stay resident; the assembly is timed and reported under its
+own key.  One step = one 16-RHS fixed-point solve; `value` is right-hand-side
+solves per second.
 
-Prints one JSON line.  `value` is whole-solve throughput (solves/s); the
-`roofline` object covers the kernel with the largest share of the step; the
-`hmatvec` object reports the matvec's HBM rate; `cpu_baseline` times the FP64
-CPU oracle on a bounded sample of the same workload.
+The `roofline` object covers the kernel group with the largest share of a
+step, the low-operator H-matvec of the inner sweeps, event-timed by the
+library inside the timed solves: algorithmic bytes (stored BF16 hi entries,
+no padding, plus x read and y written in FP64) per launch / mean launch time.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload.  Extra keys: the plain FP64 GPU method against the mixed one on 4 of
+the 32 bands (one GPU's share of an 8-GPU band split), the 41^3 FP64
+H-matrix solve with assembly (per-step latency), and the 11^3 dense case with
+the oracle timed in full.
 
-Other workloads (`--workload`), each one JSON line of its own; the default run
-is the 41^3 FP64 solve above:
+Other workloads (`--workload`), one JSON line each:
+  cube41      the 41^3 grey FP64 H-matrix solve, assembly + solve per step
   reflective  box [0,2]x[0,1]^2 on 65x33x33, mirror wall z = 0 (R = 0.5), 8 bands,
-              mixed precision against plain FP64 (assembly, event-timed matvecs,
-              solves to 1e-6)
-  batched     unit cube 49^3, 32 bands x 16 right-hand sides, mixed precision, all
-              bands and right-hand sides in one launch per phase, autotuned launch
-              shape; `--bands B` takes every (32/B)-th band, `--compare` adds plain
-              FP64 on the same bands
+              mixed precision against plain FP64
+  batched     the headline workload with an autotuned launch shape; `--bands B` takes
+              every (32/B)-th band, `--compare` adds plain FP64 on the same bands
   served      256 Poisson(20/s) requests over resident 21^3/29^3/41^3/49^3 meshes
               through the request server (mixed, continuous batching) and, with
               `--compare R`, the first R of them through plain FP64 one at a time
@@ -49,9 +55,20 @@ HBM_PEAK_GBS = 8000.0
 # whenever those kernels change.
 ACA_ENTRY_TRAFFIC_BYTES = 372.1e6
 FP64_PEAK_TFLOPS = 78.6
-# algorithmic FP64 operations of one kernel entry (see the design notes):
-# per ray-march piece, per quadrature term, and per entry
-F_PIECE, F_TERM, F_ENTRY = 46, 21, 60
+# Algorithmic FP64 operations of one kernel entry, counted from the code of the
+# march and the quadrature with an FMA as 2 and a reciprocal, square root or
+# exponential as 1 (compares, min/max and index arithmetic not counted):
+#   per ray-march piece: crossing update 1.5 (one family advances; an axis
+#     family also moves the cell), midpoint 2, sample position 6, P1 value 9,
+#     accumulation 3;
+#   per far-field tetrahedron (4 points of the degree-2 rule): squared
+#     distances 28, kappa weights 28, common denominator 8, refined reciprocal
+#     and accumulation 15;
+#   per near-field cell (degree-5 rule, tabulated): 8 products, 16;
+#   per entry: segment set-up 45, optical depth and exponential 2, far-field
+#     distance 8, scaling 2.
+# The ACA's residual update (2 k per entry at rank step k) is not counted.
+F_PIECE, F_FAR_TET, F_NEAR_CELL, F_ENTRY = 21.5, 79, 16, 57
 
 
 def _phi(q: int) -> int:
@@ -90,24 +107,28 @@ def pieces_between(d) -> int:
     return 1 + sum(_phi(q) for q in qs)
 
 
-def valid_tets(idx, n) -> int:
-    cnt = 0
+def valid_cells_tets(idx, n):
+    """Cells of the grid around vertex idx, and the Kuhn tetrahedra of those cells
+    that have idx as a vertex."""
+    cells = tets = 0
     for bits in range(8):
         o = [(bits >> a) & 1 for a in range(3)]
         if all((idx[a] >= 1) if o[a] else (idx[a] <= n[a] - 2) for a in range(3)):
+            cells += 1
             # tets of cell j-o containing j: corner (0,0,0) or (1,1,1) -> 6, else 2
-            cnt += 6 if sum(o) in (0, 3) else 2
-    return cnt
+            tets += 6 if sum(o) in (0, 3) else 2
+    return cells, tets
 
 
 def entry_flops_sample(n, pairs, near_cheb=2):
-    """Mean algorithmic FLOPs of an entry over sampled (i_idx, j_idx) pairs."""
+    """Mean algorithmic FLOPs of a volume entry over sampled (i_idx, j_idx) pairs."""
     tot = 0.0
     for ii, jj in pairs:
         d = [jj[a] - ii[a] for a in range(3)]
         near = max(abs(v) for v in d) <= near_cheb
-        terms = valid_tets(jj, n) * (14 if near else 4)
-        tot += F_PIECE * pieces_between(d) + F_TERM * terms + F_ENTRY
+        cells, tets = valid_cells_tets(jj, n)
+        quad = F_NEAR_CELL * cells if near else F_FAR_TET * tets
+        tot += F_PIECE * pieces_between(d) + quad + F_ENTRY
     return tot / len(pairs)
 
 
@@ -341,30 +362,264 @@ def run_served(args):
     print(json.dumps(out))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=41, help="vertices per axis of the cube")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="cube41", choices=("cube41", "reflective", "batched", "served"))
-    ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"), help="reflective workload")
-    ap.add_argument("--bands", type=int, default=0, help="batched workload: bands taken (0 = all 32)")
-    ap.add_argument("--compare", type=int, default=0,
-                    help="batched: add plain FP64 (1); served: requests replayed through plain FP64")
-    ap.add_argument("--requests", type=int, default=256,
-                    help="served workload: requests of the stream served in mixed precision (0: none)")
-    ap.add_argument("--budget-gb", type=float, default=250.0, help="served workload: HBM budget of the server")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the multi-GPU band sharding is a design, not a build "
-              "(see the design notes); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    if args.workload != "cube41":
-        {"reflective": run_reflective, "batched": run_batched, "served": run_served}[args.workload](args)
-        return
+# HBM bytes per launch of the low-operator matvec of the headline workload (the
+# four launches k_mf_xstage, k_mf_phase_a, k_mf_tstage, k_mf_phase_b), from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE passes calibrated on a plain 1 GiB copy
+# (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all): 122.3 GB read and
+# 8.9 GB written (profiles/cube49_32band_16rhs_mixed_matvec_traffic.md).  Set
+# to None whenever those kernels change.
+LOW_MATVEC_TRAFFIC_BYTES = 131.2e9
 
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def _sample_operator(mesh, G, rng, count):
+    """A random sample of `count` dense and `count` low-rank blocks of band 0 of the
+    volume operator, read back through the C ABI (hi + lo, widened to FP64), as an
+    oracle H-operator over those blocks only; and the stored entries it holds."""
+    from oracle.hmatrix import HOperator
+    from paper_2306_05789_amd import rte
+    st = rte.rte_hmat_stats(G)
+    optG = rte.hmat_opts(kind=rte.RTE_VOLUME, precision=st["precision"])
+    plan = rte.rte_plan_create(mesh, optG)
+    tp, sp, blocks = rte.rte_plan_export(plan)
+    rte.rte_plan_destroy(plan)
+    H = HOperator(tp, sp)
+    nd = rte.rte_hmat_dense_count(G, 0)
+    for d in rng.choice(nd, min(count, nd), replace=False):
+        (t0, t1, s0, s1), A = rte.rte_hmat_dense_block(G, 0, int(d))
+        H.dense.append((t0, t1, s0, s1, A))
+    low = blocks[blocks[:, 4] == 1]
+    for b in rng.choice(len(low), min(count, len(low)), replace=False):
+        k, U, V = rte.rte_hmat_block_factors_op(G, 0, int(b), rte.RTE_OP_ACCURATE)
+        if k > 0:
+            t0, t1, s0, s1 = (int(v) for v in low[b][:4])
+            H.lowrank.append((t0, t1, s0, s1, U, V))
+    return H, H.stored_entries()
+
+
+def cpu_baseline_headline(wl, G, mesh, gstats, sstats, sweeps, nrhs, budget_s=15.0):
+    """The oracle on a bounded sample of the headline workload: its entry cost on
+    sampled rows of band 0 (extrapolated to the entries the assembly evaluates), and
+    its FP64 block-by-block H-matvec (oracle-on-H) timed on a sample of band 0's
+    read-back blocks (extrapolated to every stored entry of the 32 bands), times
+    the sweeps of a solve."""
+    from oracle.core import Grid, Problem
+    g = Grid(wl.n)
+    P = Problem(g, wl.kappa[0], emit_faces=wl.emit_faces)
+    rng = np.random.default_rng(12)
+    cols = np.arange(g.N)
+    t0 = time.perf_counter()
+    P.volume_block(rng.choice(g.N, 2, replace=False), cols)
+    t_probe = (time.perf_counter() - t0) / (2 * g.N)
+    R = int(min(64, max(2, 0.4 * budget_s / max(t_probe * g.N, 1e-6))))
+    rows = rng.choice(g.N, R, replace=False)
+    t0 = time.perf_counter()
+    P.volume_block(rows, cols)
+    t_entry = (time.perf_counter() - t0) / (R * g.N)
+    evaluated = gstats["entries_evaluated"] + sstats["entries_evaluated"]
+    t_assembly = t_entry * evaluated
+    # oracle-on-H FP64 matvec over a sample of band 0's blocks
+    Hs, sampled = _sample_operator(mesh, G, rng, 400)
+    X = rng.uniform(0.5, 2.0, (nrhs, g.N))
+    Hs.matvec(X)
+    reps, t0 = 0, time.perf_counter()
+    while reps < 3 or (time.perf_counter() - t0 < 0.3 * budget_s and reps < 50):
+        Hs.matvec(X)
+        reps += 1
+    t_mv = (time.perf_counter() - t0) / reps / max(sampled, 1)   # per stored entry, 16 RHS
+    stored = gstats["dense_entries"] + gstats["lowrank_entries"]  # all bands
+    t_sweep = t_mv * stored
+    t_solve = sweeps * t_sweep
+    return {"value": nrhs / t_solve, "unit": "solves/s", "cores": _cpu_threads(), "kind": "oracle",
+            "cpu": _cpu_model(),
+            "sample": f"oracle entries on {R} random rows of band 0's G ({R * g.N} entries, "
+                      f"{t_entry * 1e9:.0f} ns each on {_cpu_threads()} threads) and the oracle's FP64 "
+                      f"block-by-block H-matvec of {nrhs} RHS over {sampled} stored entries of band 0 read back "
+                      f"from the GPU ({reps} reps); extrapolated: a sweep over all {wl.bands} bands "
+                      f"({stored} stored entries) {t_sweep:.1f} s, a solve of {sweeps} sweeps {t_solve:.0f} s "
+                      f"with resident operators; the assembly ({evaluated} entries) {t_assembly:.0f} s"}
+
+
+def run_headline(args):
+    """49^3, 32 bands x 16 RHS, mixed precision, operators resident; see the module docstring."""
+    import torch
+    from paper_2306_05789_amd import inputs, rte
+    wl = inputs.batched()
+    dev = torch.device("cuda:0")
+    mesh = rte.rte_mesh_create(wl.n, emit_faces=wl.emit_faces)
+    kap = torch.tensor(wl.kappa, device=dev)
+    Tw = torch.tensor(wl.T_wall, device=dev)
+    nrhs, nb = int(Tw.shape[0]), wl.bands
+    p = rte.RTE_MIXED_BF16
+    G, S, wall_ms = _assemble_pair(rte, mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, precision=p),
+                                   rte.hmat_opts(kind=rte.RTE_SURFACE, precision=p))
+    gs, ss = rte.rte_hmat_stats(G), rte.rte_hmat_stats(S)
+    _say(f"assembly: G {gs['assemble_ms']:.0f} ms ({gs['bytes'] / 1e9:.1f} GB), S {ss['assemble_ms']:.0f} ms "
+         f"({ss['bytes'] / 1e9:.1f} GB), concurrently {wall_ms:.0f} ms")
+    T = torch.empty((nrhs, mesh.N), device=dev, dtype=torch.float64)
+
+    def solve():
+        return rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=False, nu=wl.nu, tol=wl.tol, max_iter=3000,
+                                         precision=p, time_matvecs=True)
+
+    for _ in range(args.warmup):
+        st = solve()
+        _say(f"warmup solve: {st['ms_total']:.1f} ms, {st['iterations']} sweeps")
+    torch.cuda.synchronize()
+    lat, sts = [], []
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        st = solve()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        sts.append(st)
+        _say(f"step: {lat[-1] * 1e3:.1f} ms, {st['iterations']} sweeps ({st['outer_steps']} defect steps), "
+             f"residual {st['residual']:.2e}; low matvec {st['ms_matvec_low'] / max(st['matvecs_low'], 1):.2f} ms "
+             f"x {st['matvecs_low']}, accurate {st['ms_matvec_acc'] / max(st['matvecs_acc'], 1):.2f} ms "
+             f"x {st['matvecs_acc']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_all
+    K = args.steps
+    assert all(st["converged"] for st in sts)
+
+    # --- the kernel groups of a step: the two operators' volume matvecs (events inside the graphs)
+    low_ms = sum(st["ms_matvec_low"] for st in sts)
+    low_n = sum(st["matvecs_low"] for st in sts)
+    acc_ms = sum(st["ms_matvec_acc"] for st in sts)
+    acc_n = sum(st["matvecs_acc"] for st in sts)
+    solve_ms = sum(st["ms_total"] for st in sts)
+    vec = 8 * nb * nrhs * (gs["n_src"] + gs["n_tgt"])            # x read, y written (FP64)
+    bytes_low = 2 * (gs["dense_entries"] + gs["lowrank_entries"]) + vec      # BF16 hi parts, no padding
+    bytes_acc = 4 * (gs["dense_entries"] + gs["lowrank_entries"]) + vec      # hi + lo
+    per_low = low_ms / max(low_n, 1)
+    per_acc = acc_ms / max(acc_n, 1)
+    gbs_low = bytes_low / (per_low * 1e-3) / 1e9
+    gbs_acc = bytes_acc / (per_acc * 1e-3) / 1e9
+    roof = {"kernel": "low-operator H-matvec of the inner sweeps (k_mf_xstage + k_mf_phase_a + k_mf_tstage + "
+                      "k_mf_phase_b, all 32 bands x 16 RHS per launch)",
+            "bound": "hbm", "achieved": gbs_low, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs_low / HBM_PEAK_GBS,
+            "traffic": LOW_MATVEC_TRAFFIC_BYTES, "bytes_per_launch": bytes_low, "launch_ms": per_low,
+            "launches": low_n}
+    out = {
+        "metric": "fixed-point solves/sec + H-matvec HBM GB/s (% peak) at 1e-6 rel err; p50/p99 latency",
+        "value": nrhs * K / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": elapsed / K * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "dtype_detail": "FP32 entries and ACA; BF16 hi + lo factors, BF16 matrix cores with FP32 "
+                                          "accumulation in the sweeps; FP64 defect correction, residual and Newton",
+        "data": "synthetic",
+        "config": {"workload": "cube49_32band_16rhs_mixed", "N": mesh.N, "L": mesh.L, "bands": nb, "nrhs": nrhs,
+                   "leaf_size": wl.leaf_size, "eta": wl.eta, "aca_eps": wl.aca_eps, "tol": wl.tol,
+                   "precision": "mixed", "step": "one 16-RHS fixed-point solve on resident operators"},
+        "roofline": roof,
+        "hmatvec": {"low": {"ms": per_low, "bytes": bytes_low, "GB_s": gbs_low, "frac": gbs_low / HBM_PEAK_GBS},
+                    "accurate": {"ms": per_acc, "bytes": bytes_acc, "GB_s": gbs_acc,
+                                 "frac": gbs_acc / HBM_PEAK_GBS},
+                    "device_bytes_hi_lo": gs["bytes"]},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "breakdown_ms_per_step": {"low_matvecs": low_ms / K, "accurate_matvecs": acc_ms / K,
+                                  "rest_of_solve": (solve_ms - low_ms - acc_ms) / K},
+        "solve": {"sweeps": sts[-1]["iterations"], "defect_steps": sts[-1]["outer_steps"],
+                  "residual": sts[-1]["residual"], "graphs": sts[-1]["graphs"]},
+        "assembly": {"wall_ms": wall_ms, "G": _hstats(gs), "S": _hstats(ss),
+                     "entries_evaluated": gs["entries_evaluated"] + ss["entries_evaluated"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_headline(wl, G, mesh, gs, ss, sts[-1]["iterations"], nrhs)
+    del G, S
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["fp64_vs_mixed_4band_share"] = _share4(rte, wl, mesh, dev)
+        out["cube41_fp64_step"] = _cube41_leg(args)
+        out["cube11_dense"] = _cube11_leg(rte, dev)
+    print(json.dumps(out))
+
+
+def _share4(rte, wl, mesh, dev):
+    """4 of the 32 bands (0, 8, 16, 24): mixed against plain FP64, 16 RHS each, 1e-6."""
+    import torch
+    bands = [0, 8, 16, 24]
+    kap = torch.tensor(wl.kappa[bands], device=dev)
+    Tw = torch.tensor(wl.T_wall, device=dev)
+    nu = wl.nu[bands]
+    res, Ts = {}, {}
+    for name in ("mixed", "fp64"):
+        p = rte.PRECISIONS[name]
+        G, S, wall_ms = _assemble_pair(rte, mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, precision=p),
+                                       rte.hmat_opts(kind=rte.RTE_SURFACE, precision=p))
+        T = torch.empty((Tw.shape[0], mesh.N), device=dev, dtype=torch.float64)
+        lat, st = _solve_series(rte, mesh, G, S, Tw, T, nu, p, wl.tol, 3, 1)
+        res[name] = {"assemble_wall_ms": wall_ms, "solve_ms": float(np.mean(lat)) * 1e3, "sweeps": st["iterations"],
+                     "rhs_solves_per_s": Tw.shape[0] / float(np.mean(lat)), "G_bytes": rte.rte_hmat_stats(G)["bytes"]}
+        Ts[name] = T.cpu().numpy()
+        del G, S
+        torch.cuda.synchronize()
+    res["speedup_mixed_over_fp64"] = res["fp64"]["solve_ms"] / res["mixed"]["solve_ms"]
+    res["mixed_vs_fp64_max_rel_T"] = float(np.max(np.abs(Ts["mixed"] - Ts["fp64"]) / Ts["fp64"]))
+    return res
+
+
+def _cube41_leg(args):
+    ns = argparse.Namespace(**vars(args))
+    ns.steps, ns.warmup, ns.no_cpu_baseline, ns.n = 10, 2, True, 41
+    o = run_cube41(ns, emit=False)
+    return {k: o[k] for k in ("value", "unit", "ms_per_step", "latency_ms", "step_ms", "roofline", "hmatvec",
+                              "breakdown_ms", "solve", "config")}
+
+
+def _cube11_leg(rte, dev):
+    """The 11^3 dense case timed in full: GPU (dense assembly of G and S + fixed point
+    to 1e-10) and the oracle (dense G and S + its fixed point to 1e-10)."""
+    import torch
+    from paper_2306_05789_amd import inputs
+    from oracle import solve as osolve
+    from oracle.core import Grid, Problem
+    wl = inputs.config_tiny(11)
+    mesh = rte.rte_mesh_create(wl.n, emit_faces=wl.emit_faces)
+    kap = torch.tensor(wl.kappa, device=dev)
+    Tw = torch.tensor(wl.T_wall, device=dev)
+    T = torch.empty((1, mesh.N), device=dev, dtype=torch.float64)
+    lat = []
+    for k in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G = rte.rte_hmat_assemble(mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, dense=True))
+        S = rte.rte_hmat_assemble(mesh, kap, rte.hmat_opts(kind=rte.RTE_SURFACE, dense=True))
+        st = rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=True, tol=wl.tol, max_iter=500)
+        torch.cuda.synchronize()
+        if k:
+            lat.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    P = Problem(Grid(wl.n), wl.kappa[0], emit_faces=wl.emit_faces)
+    Gd, Sd = P.dense_G(), P.dense_S()
+    ref = osolve.fixed_point([Gd], (Sd @ (osolve.SIGMA * wl.T_wall[0] ** 4))[None], grey=True, tol=wl.tol)
+    t_cpu = time.perf_counter() - t0
+    err = float(np.max(np.abs(T.cpu().numpy()[0] - ref.T) / ref.T))
+    return {"gpu_ms": float(np.mean(lat)) * 1e3, "iterations": st["iterations"], "oracle_s": t_cpu,
+            "oracle_iterations": ref.iterations, "oracle_threads": _cpu_threads(), "max_rel_T_vs_oracle": err}
+
+
+def run_cube41(args, emit=True):
+    """The 41^3 grey FP64 H-matrix workload: one step = assembly of G and S (two host
+    threads, two streams) + the fixed point to 1e-10."""
     import torch
     from paper_2306_05789_amd import inputs, rte
 
@@ -385,25 +640,41 @@ def main():
     streams = (torch.cuda.Stream(), torch.cuda.Stream())
     torch.cuda.synchronize()
 
+    held = []   # the previous step's operators: released at the start of the next step, inside it
+
     def step():
+        t0 = time.perf_counter()
+        held.clear()
+        t_free = time.perf_counter() - t0
         fG = pool.submit(rte.rte_hmat_assemble, mesh, kap, optG, streams[0].cuda_stream)
         fS = pool.submit(rte.rte_hmat_assemble, mesh, kap, optS, streams[1].cuda_stream)
         G, S = fG.result(), fS.result()
-        st = rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=True, tol=wl.tol, max_iter=1000)
-        return G, S, st
+        st = rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=True, tol=wl.tol, max_iter=1000, time_matvecs=True)
+        held.extend([G, S])
+        return G, S, st, t_free
+
+    def show(tag, ms, G, S, st, t_free):
+        g, q = rte.rte_hmat_stats(G), rte.rte_hmat_stats(S)
+        _say(f"{tag}: {ms:.1f} ms, {st['iterations']} iterations; release {t_free * 1e3:.1f} ms; "
+             f"G {g['assemble_ms']:.1f} ms (ACA kernels {g['aca_kernel_ms']:.1f}, alloc {g['alloc_ms']:.1f}); "
+             f"S {q['assemble_ms']:.1f} ms (alloc {q['alloc_ms']:.1f}); solve {st['ms_total']:.1f} ms; "
+             f"free {g['free_bytes'] / 2 ** 30:.1f} GiB")
 
     for _ in range(args.warmup):
-        step()
+        t0 = time.perf_counter()
+        out = step()
+        torch.cuda.synchronize()
+        show("warmup", (time.perf_counter() - t0) * 1e3, *out)
     torch.cuda.synchronize()
     recs, lat = [], []
     t_all = time.perf_counter()
     for _ in range(args.steps):
         t0 = time.perf_counter()
-        G, S, st = step()
+        G, S, st, t_free = step()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
         recs.append((rte.rte_hmat_stats(G), rte.rte_hmat_stats(S), st))
-        print(f"# step: {lat[-1] * 1e3:.1f} ms, {st['iterations']} iterations", file=sys.stderr, flush=True)
+        show("step", lat[-1] * 1e3, G, S, st, t_free)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_all
     K = args.steps
@@ -446,11 +717,10 @@ def main():
     flop_per_launch = f_entry * aca_entries_G / nl
     aca_tflops = flop_per_launch / (aca_launch_ms_G * 1e-3) / 1e12
 
-    # --- H-matvec: algorithmic bytes per matvec
+    # --- H-matvec: algorithmic bytes per matvec (stored entries without padding,
+    # x read and y written in FP64)
     mv_per = mv_ms / max(iters, 1)
-    vec_bytes = 8 * (gs["n_src"] + 2 * gs["n_tgt"])        # x read, y0 read, y written
-    t_bytes = 8 * 2 * int(sum(r for r in ranks if r > 0))   # t written and read
-    mv_bytes = gs["bytes"] + vec_bytes + t_bytes
+    mv_bytes = 8 * (gs["dense_entries"] + gs["lowrank_entries"]) + 8 * (gs["n_src"] + gs["n_tgt"])
     mv_gbs = mv_bytes / (mv_per * 1e-3) / 1e9
 
     shares = {"aca": aca_ms, "dense_fill": fill_ms, "hmatvec": mv_ms}
@@ -478,11 +748,14 @@ def main():
                    "aca_eps": wl.aca_eps, "tol": wl.tol, "precision": "fp64"},
         "roofline": roof,
         "hmatvec": {"bound": "hbm", "achieved": mv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": mv_gbs / HBM_PEAK_GBS, "bytes_per_matvec": mv_bytes, "ms_per_matvec": mv_per},
+                    "frac": mv_gbs / HBM_PEAK_GBS, "bytes_per_matvec": mv_bytes, "ms_per_matvec": mv_per,
+                    "device_bytes": gs["bytes"]},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "breakdown_ms": {"aca_kernels": aca_ms, "dense_fill_kernels": fill_ms, "matvec_kernels": mv_ms,
                          "assemble_G_wall": gs["assemble_ms"], "assemble_S_wall": ss["assemble_ms"],
-                         "solve_wall": sts["ms_total"]},
+                         "solve_wall": sts["ms_total"],
+                         "alloc_host": float(np.mean([g["alloc_ms"] + s["alloc_ms"] for g, s, _ in recs]))},
+        "step_ms": [round(v * 1e3, 1) for v in lat],
         "solve": {"iterations": iters, "residual": sts["residual"], "monotone_violations": sts["monotone_violations"],
                   "resident_solves_per_s": 1e3 / sts["ms_total"]},
         "hmatrix": {"compression": gs["compression"], "mean_rank": gs["mean_rank"], "max_rank": gs["max_rank"],
@@ -491,7 +764,41 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
-    print(json.dumps(out))
+    pool.shutdown()
+    del G, S, Gh
+    held.clear()
+    torch.cuda.synchronize()
+    if emit:
+        print(json.dumps(out))
+    return out
+
+
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=41, help="cube41 workload: vertices per axis of the cube")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline: skip the FP64 share, 41^3 and 11^3 legs")
+    ap.add_argument("--workload", default="headline",
+                    choices=("headline", "cube41", "reflective", "batched", "served"))
+    ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"), help="reflective workload")
+    ap.add_argument("--bands", type=int, default=0, help="batched workload: bands taken (0 = all 32)")
+    ap.add_argument("--compare", type=int, default=0,
+                    help="batched: add plain FP64 (1); served: requests replayed through plain FP64")
+    ap.add_argument("--requests", type=int, default=256,
+                    help="served workload: requests of the stream served in mixed precision (0: none)")
+    ap.add_argument("--budget-gb", type=float, default=250.0, help="served workload: HBM budget of the server")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the multi-GPU band sharding is a design, not a build "
+              "(see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    {"headline": run_headline, "cube41": run_cube41, "reflective": run_reflective, "batched": run_batched,
+     "served": run_served}[args.workload](args)
 
 
 if __name__ == "__main__":

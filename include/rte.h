@@ -272,6 +272,10 @@ typedef struct {
     int32_t launch;        /* RTE_LAUNCH_STREAM: kernels enqueued one by one; RTE_LAUNCH_GRAPH: each
                               distinct sweep captured once in a hipGraph and replayed (same kernels,
                               same results; fewer launch round trips for small meshes) */
+    int32_t time_matvecs;  /* 1: HIP events around every volume matvec (stats ms_matvec_low/acc); with
+                              RTE_LAUNCH_GRAPH a sweep is then captured as three graphs, before the
+                              matvec, the matvec and after it, with the events between them.  0: stream
+                              launch still times the matvecs; graph launch times whole sweeps only */
 } rte_solve_desc_t;
 
 enum { RTE_LAUNCH_STREAM = 0, RTE_LAUNCH_GRAPH = 1 };
@@ -281,11 +285,11 @@ typedef struct {
     int32_t outer_steps;        /* FP64 defect-correction steps (mixed precision) */
     double residual;            /* final relative change of J */
     int64_t monotone_violations;/* vertex-steps where T decreased (from T0 = 0 it should be 0) */
-    double ms_total, ms_matvec; /* ms_matvec: HIP-event time of the matvecs (graph launch: of the whole sweeps) */
+    double ms_total, ms_matvec; /* ms_matvec: HIP-event time of the volume matvecs (graph launch without
+                                   time_matvecs: of the whole sweeps) */
     int32_t graphs;             /* sweep graphs captured (RTE_LAUNCH_GRAPH) */
     double ms_matvec_low;       /* HIP-event time of the volume matvecs on the low operator (mixed
-                                   inner sweeps), also inside captured sweeps; -1 if the runtime
-                                   cannot time events recorded inside a graph */
+                                   inner sweeps); -1 when not timed (graph launch without time_matvecs) */
     int32_t matvecs_low;        /* their number */
     double ms_matvec_acc;       /* same for the matvecs on the accurate (or only) operator */
     int32_t matvecs_acc;

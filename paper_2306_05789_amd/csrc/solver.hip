@@ -130,9 +130,10 @@ struct GraphKey {
     int mode;
     bool newton;
     const void *y0, *sub, *J, *Jn, *S;
+    int part;   // -1: the whole sweep; 0, 1, 2: before, the matvec, after (timed sweeps)
     bool operator==(const GraphKey &o) const {
         return mode == o.mode && newton == o.newton && y0 == o.y0 && sub == o.sub && J == o.J && Jn == o.Jn &&
-               S == o.S;
+               S == o.S && part == o.part;
     }
 };
 
@@ -170,6 +171,7 @@ void check_desc(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_des
     RTE_REQUIRE(d.precision == RTE_FP64 || d.precision == RTE_FP32 || d.precision == RTE_MIXED_BF16,
                 "solve: unknown precision");
     RTE_REQUIRE(d.launch == RTE_LAUNCH_STREAM || d.launch == RTE_LAUNCH_GRAPH, "solve: unknown launch mode");
+    RTE_REQUIRE(d.time_matvecs == 0 || d.time_matvecs == 1, "solve: time_matvecs must be 0 or 1");
     RTE_REQUIRE(d.precision != RTE_MIXED_BF16 || G.precision == RTE_MIXED_BF16,
                 "solve: the mixed-precision iteration needs a volume matrix assembled with RTE_MIXED_BF16");
     if (!d.grey) {
@@ -183,42 +185,6 @@ void check_desc(const Mesh &m, const HMat &G, const HMat &S, const rte_solve_des
     if (d.a)
         for (int b = 0; b < d.n_bands; ++b)
             RTE_REQUIRE(std::isfinite(d.a[b]) && d.a[b] >= 0 && d.a[b] < 1, "solve: a must lie in [0, 1)");
-}
-
-__global__ void k_probe(int *p) {
-    if (p && threadIdx.x == 0) p[0] = 1;
-}
-
-// Whether events recorded inside a captured graph (event record nodes) give
-// elapsed times on this runtime: probed once per process on a tiny graph, so
-// that the solver can time the matvecs inside its graph-launched sweeps.
-bool graph_events_work(hipStream_t s) {
-    static std::once_flag once;
-    static bool ok = false;
-    std::call_once(once, [&] {
-        hipEvent_t a = nullptr, b = nullptr;
-        hipGraph_t g = nullptr;
-        hipGraphExec_t ex = nullptr;
-        bool good = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
-                    hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        if (good) {
-            bool rec = hipEventRecord(a, s) == hipSuccess;
-            k_probe<<<1, 64, 0, s>>>(nullptr);
-            rec = rec && hipGetLastError() == hipSuccess && hipEventRecord(b, s) == hipSuccess;
-            good = hipStreamEndCapture(s, &g) == hipSuccess && g && rec;
-        }
-        good = good && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
-        good = good && hipGraphLaunch(ex, s) == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
-        float ms = -1.0f;
-        good = good && hipEventElapsedTime(&ms, a, b) == hipSuccess && ms >= 0.0f;
-        (void)hipGetLastError();
-        if (ex) (void)hipGraphExecDestroy(ex);
-        if (g) (void)hipGraphDestroy(g);
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
-        ok = good;
-    });
-    return ok;
 }
 
 }  // namespace
@@ -303,9 +269,10 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
     HIP_CHECK(hipEventCreate(&m0));
     HIP_CHECK(hipEventCreate(&m1));
     float mv_ms = 0.0f;
-    // volume-matvec time per operator: events around the matvec launches, also
-    // inside captured sweeps when the runtime times event record nodes
-    const bool mv_events = d.launch != RTE_LAUNCH_GRAPH || graph_events_work(s);
+    // volume-matvec time per operator (time_matvecs): events around the matvec
+    // launches; a graph-launched sweep is then captured as three graphs (before,
+    // the matvec, after) with the events between them
+    const bool mv_events = d.time_matvecs != 0;
     double op_ms[2] = {0.0, 0.0};
     int op_count[2] = {0, 0};
     std::vector<double> rv(2 * nb * nr);
@@ -315,16 +282,16 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
     // one sweep: S = S(T, J) (minus Sm when given); Jn = y0 + G S over all bands;
     // residual(J, Jn); T = T(Jn); J <- Jn.  The kernels only (no copies, no
     // memsets), so that a sweep can be captured in a graph.
-    auto enqueue = [&](int mode, const double *y0, bool newton, const double *sub, bool timed) {
+    auto enqueue_pre = [&](const double *sub) {
         k_source<<<gN, 256, 0, s>>>(bp, T.as<double>(), J.as<double>(), N, nr, Sv.as<double>());
         if (sub)
             k_sub<<<(unsigned)((vecN * nb + 255) / 256), 256, 0, s>>>(Sv.as<double>(), sub, vecN * nb, Sv.as<double>());
         HIP_LAUNCH_CHECK();
-        if (timed) HIP_CHECK(hipEventRecord(e0, s));
-        if (mv_events) HIP_CHECK(hipEventRecord(m0, s));
+    };
+    auto enqueue_mv = [&](int mode, const double *y0) {
         matvec_launch_all(G, nr, Sv.as<double>(), Jn.as<double>(), y0, tbuf.as<double>(), s, mode);
-        if (mv_events) HIP_CHECK(hipEventRecord(m1, s));
-        if (timed) HIP_CHECK(hipEventRecord(e1, s));
+    };
+    auto enqueue_post = [&](bool newton) {
         k_resid_partial<<<dim3(kResidBlocks, nb * nr), 256, 0, s>>>(J.as<double>(), Jn.as<double>(), N,
                                                                      part.as<double>());
         k_resid_final<<<(nb * nr + 63) / 64, 64, 0, s>>>(part.as<double>(), nb * nr, res.as<double>());
@@ -333,36 +300,57 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
                                         viol.as<unsigned long long>());
         HIP_LAUNCH_CHECK();
     };
+    // one sweep: S = S(T, J) (minus Sm when given); Jn = y0 + G S over all bands;
+    // residual(J, Jn); T = T(Jn); J <- Jn.  The kernels only (no copies, no
+    // memsets), so that a sweep can be captured in a graph.
+    auto enqueue = [&](int mode, const double *y0, bool newton, const double *sub, int part_) {
+        if (part_ < 0 || part_ == 0) enqueue_pre(sub);
+        if (part_ < 0 || part_ == 1) enqueue_mv(mode, y0);
+        if (part_ < 0 || part_ == 2) enqueue_post(newton);
+    };
     GraphCache graphs;
-    auto sweep = [&](int mode, const double *y0, bool newton, const double *sub) -> double {
-        if (d.launch == RTE_LAUNCH_GRAPH) {
-            const GraphKey key{mode, newton, y0, sub, J.p, Jn.p, Sv.p};
-            hipGraphExec_t ex = graphs.find(key);
-            if (!ex) {
-                hipGraph_t g = nullptr;
-                HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                try {
-                    enqueue(mode, y0, newton, sub, false);
-                } catch (...) {
-                    // leave the stream out of capture mode before reporting
-                    if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
-                    throw;
-                }
-                HIP_CHECK(hipStreamEndCapture(s, &g));
-                ex = graphs.add(key, g);
+    auto graph_of = [&](int mode, const double *y0, bool newton, const double *sub, int part_) {
+        const GraphKey key{mode, newton, y0, sub, J.p, Jn.p, Sv.p, part_};
+        hipGraphExec_t ex = graphs.find(key);
+        if (!ex) {
+            hipGraph_t g = nullptr;
+            HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue(mode, y0, newton, sub, part_);
+            } catch (...) {
+                // leave the stream out of capture mode before reporting
+                if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+                throw;
             }
-            HIP_CHECK(hipEventRecord(e0, s));
-            HIP_CHECK(hipGraphLaunch(ex, s));
-            HIP_CHECK(hipEventRecord(e1, s));
-        } else {
-            enqueue(mode, y0, newton, sub, true);
+            HIP_CHECK(hipStreamEndCapture(s, &g));
+            ex = graphs.add(key, g);
         }
+        return ex;
+    };
+    auto sweep = [&](int mode, const double *y0, bool newton, const double *sub) -> double {
+        HIP_CHECK(hipEventRecord(e0, s));
+        if (d.launch == RTE_LAUNCH_GRAPH && !mv_events) {
+            HIP_CHECK(hipGraphLaunch(graph_of(mode, y0, newton, sub, -1), s));
+        } else if (d.launch == RTE_LAUNCH_GRAPH) {
+            HIP_CHECK(hipGraphLaunch(graph_of(mode, y0, newton, sub, 0), s));
+            HIP_CHECK(hipEventRecord(m0, s));
+            HIP_CHECK(hipGraphLaunch(graph_of(mode, y0, newton, sub, 1), s));
+            HIP_CHECK(hipEventRecord(m1, s));
+            HIP_CHECK(hipGraphLaunch(graph_of(mode, y0, newton, sub, 2), s));
+        } else {
+            enqueue_pre(sub);
+            HIP_CHECK(hipEventRecord(m0, s));
+            enqueue_mv(mode, y0);
+            HIP_CHECK(hipEventRecord(m1, s));
+            enqueue_post(newton);
+        }
+        HIP_CHECK(hipEventRecord(e1, s));
         HIP_CHECK(hipMemcpyAsync(rv.data(), res.p, sizeof(double) * rv.size(), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         float ms = 0.0f;
         HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
         mv_ms += ms;
-        if (mv_events) {
+        if (mv_events || d.launch != RTE_LAUNCH_GRAPH) {
             float mm = 0.0f;
             HIP_CHECK(hipEventElapsedTime(&mm, m0, m1));
             op_ms[mode == kMatvecLow ? 0 : 1] += mm;
@@ -434,12 +422,13 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
         st->outer_steps = outer;
         st->residual = r;
         st->monotone_violations = (int64_t)nviol;
-        st->ms_matvec = mv_ms;
+        st->ms_matvec = (mv_events || d.launch != RTE_LAUNCH_GRAPH) ? op_ms[0] + op_ms[1] : mv_ms;
         st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         st->graphs = graphs.size();
-        st->ms_matvec_low = mv_events ? op_ms[0] : -1.0;
+        const bool timed = mv_events || d.launch != RTE_LAUNCH_GRAPH;
+        st->ms_matvec_low = timed ? op_ms[0] : -1.0;
         st->matvecs_low = op_count[0];
-        st->ms_matvec_acc = mv_events ? op_ms[1] : -1.0;
+        st->ms_matvec_acc = timed ? op_ms[1] : -1.0;
         st->matvecs_acc = op_count[1];
     }
     if (!std::isfinite(r)) throw Error(RTE_E_INTERNAL, "solve: the residual is not finite");

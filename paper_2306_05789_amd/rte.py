@@ -61,7 +61,7 @@ class SolveDesc(C.Structure):
     _fields_ = [("n_bands", C.c_int32), ("nu", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
                 ("a", C.POINTER(C.c_double)), ("grey", C.c_int32), ("nrhs", C.c_int32),
                 ("T_wall", C.c_void_p), ("T0", C.c_void_p), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("precision", C.c_int32), ("launch", C.c_int32)]
+                ("precision", C.c_int32), ("launch", C.c_int32), ("time_matvecs", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -410,7 +410,7 @@ def rte_hmat_dense_block(hmat: HMat, band: int, index: int, op: int = 0):
 
 def rte_fixed_point_solve(mesh: Mesh, vol: HMat, surf: HMat, T_wall, T_out, J_out=None, *, grey=True,
                           nu=None, w=None, a=None, T0=None, tol=1e-10, max_iter=1000, precision=RTE_FP64,
-                          launch=None, stream=None, allow_not_converged=False) -> dict:
+                          launch=None, stream=None, allow_not_converged=False, time_matvecs=False) -> dict:
     """T_wall: float64 device [nrhs, L]; T_out: [nrhs, N]; J_out: [nrhs, n_bands, N] or None."""
     nrhs = 1 if T_wall.dim() == 1 else int(T_wall.shape[0])
     nb = 1 if grey else len(nu)
@@ -423,6 +423,7 @@ def rte_fixed_point_solve(mesh: Mesh, vol: HMat, surf: HMat, T_wall, T_out, J_ou
     d.T0 = T0.data_ptr() if T0 is not None else None
     d.tol, d.max_iter, d.precision = float(tol), int(max_iter), int(precision)
     d.launch = RTE_LAUNCH_GRAPH if launch is None else int(launch)
+    d.time_matvecs = int(bool(time_matvecs))
     st = SolveStats()
     allow = (RTE_OK, RTE_E_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
     status = _check(load().rte_fixed_point_solve(mesh.handle, vol.handle, surf.handle, C.byref(d), _ptr(T_out),

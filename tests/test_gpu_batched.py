@@ -69,11 +69,11 @@ def test_batched_matvec_equals_single_calls(small, precision):
         assert 1e-6 < rel < 1e-2, rel
 
 
-def _solve(mesh, G, S, wl, Tw, precision, tol, launch=None):
+def _solve(mesh, G, S, wl, Tw, precision, tol, launch=None, time_matvecs=False):
     T = torch.empty((Tw.shape[0], mesh.N), device=DEV, dtype=torch.float64)
     J = torch.empty((Tw.shape[0], wl.kappa.shape[0], mesh.N), device=DEV, dtype=torch.float64)
     st = rte.rte_fixed_point_solve(mesh, G, S, Tw, T, J, grey=False, nu=wl.nu, tol=tol, max_iter=3000,
-                                   precision=precision, launch=launch)
+                                   precision=precision, launch=launch, time_matvecs=time_matvecs)
     return T, J, st
 
 
@@ -134,6 +134,13 @@ def test_graph_launch_equals_stream_launch(small, precision):
     # and again on the same matrices: a fresh set of graphs, the same numbers
     Tg2, _, stg2 = _solve(mesh, G, S, wl, Tw, precision, 1e-7, launch=rte.RTE_LAUNCH_GRAPH)
     assert torch.equal(Tg2, Ts) and stg2["iterations"] == sts["iterations"]
+    # timed sweeps (three graphs per sweep with events between): the same numbers,
+    # and every volume matvec timed
+    Tt, Jt, stt = _solve(mesh, G, S, wl, Tw, precision, 1e-7, launch=rte.RTE_LAUNCH_GRAPH, time_matvecs=True)
+    assert torch.equal(Tt, Ts) and torch.equal(Jt, Js) and stt["iterations"] == sts["iterations"]
+    assert stt["matvecs_low"] + stt["matvecs_acc"] == stt["iterations"]
+    assert stt["ms_matvec_acc"] > 0 and (precision != rte.RTE_MIXED_BF16 or stt["ms_matvec_low"] > 0)
+    assert stg["ms_matvec_low"] == -1.0 and sts["matvecs_acc"] > 0
 
 
 def test_mixed_batched_solve_matches_oracle(small):
