@@ -147,6 +147,20 @@ rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *k
 rte_status_t rte_hmat_matvec(rte_hmat_t h, int32_t band, int32_t nrhs, const double *x,
                              double *y, void *stream);
 
+/* The same product for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * y = H_band x with every intermediate (x and y in cluster order, the
+ * matvec's partial sums and staged operands) in a fixed workspace of 64 MiB
+ * that the library holds on each device for the life of the process; no
+ * hipMalloc, hipFree or allocating library call is made.  Calls on one device
+ * share that workspace: calls that overlap in time on one device (different
+ * streams or host threads) race and must be serialised by the caller.  Returns
+ * RTE_E_BUDGET, with nothing enqueued, when the product needs more workspace
+ * than that (about N_src + N_tgt doubles per right-hand side plus the partial
+ * sums).  Synchronises `stream`. */
+rte_status_t rte_hmat_matvec_noalloc(rte_hmat_t h, int32_t band, int32_t nrhs, const double *x,
+                                     double *y, void *stream);
+
 /* Operator of a matvec on RTE_MIXED_BF16 storage (the other storages have one):
  * RTE_OP_ACCURATE multiplies by the hi + lo factors, with the vector carried
  * as three BF16 parts (24 significant bits), and adds the FP32 matrix-core

@@ -7,6 +7,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <unordered_set>
 
 #include "rte_internal.h"
@@ -17,6 +19,30 @@ using namespace rte;
 namespace {
 
 thread_local std::string g_last_error;
+
+// Workspace of rte_hmat_matvec_noalloc: a file-scope device array, so that the
+// call allocates nothing.  Each device that runs the library holds its own copy
+// until the process ends.  Host code never uses the array's name as an address:
+// the device address of each copy is taken with hipGetSymbolAddress on the
+// call's first use on that device and kept per device.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;   // device -> device address of its copy of `scratch`
+
+void *scratch_address(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        throw Error(RTE_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return ptr;
+}
+
 
 template <typename F>
 rte_status_t guard(F &&f) {
@@ -555,6 +581,40 @@ rte_status_t rte_hmat_matvec(rte_hmat_t h, int32_t band, int32_t nrhs, const dou
         permute_gather(H.src_pos.as<int64_t>(), ns, nrhs, ns, ns, x, xc.as<double>(), s);
         matvec_launch(H, band, nrhs, xc.as<double>(), yc.as<double>(), nullptr, s);
         permute_scatter(H.tgt_nat.as<int64_t>(), nt, nrhs, nt, nt, yc.as<double>(), y, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_matvec_noalloc(rte_hmat_t h, int32_t band, int32_t nrhs, const double *x, double *y,
+                                     void *stream) {
+    return guard([&] {
+        RTE_REQUIRE(h, "rte_hmat_matvec_noalloc: NULL matrix");
+        const HMat &H = h->h;
+        RTE_REQUIRE(band >= 0 && band < H.n_bands, "rte_hmat_matvec_noalloc: band out of range");
+        RTE_REQUIRE(nrhs >= 1 && nrhs <= 4096, "rte_hmat_matvec_noalloc: nrhs out of range");
+        check_device_pointer(x, "x");
+        check_device_pointer(y, "y");
+        int dev = 0;
+        HIP_CHECK(hipGetDevice(&dev));
+        RTE_REQUIRE(dev == H.device, "rte_hmat_matvec_noalloc: the matrix lives on another device");
+        // layout of the workspace: x and y in cluster order, then the matvec's own
+        // workspace, each 256-byte aligned
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const int64_t ns = H.stats.n_src, nt = H.stats.n_tgt;
+        const size_t bx = al(sizeof(double) * (size_t)(ns * nrhs)), by = al(sizeof(double) * (size_t)(nt * nrhs));
+        const size_t bw = al(sizeof(double) * (size_t)matvec_ws(H, band, nrhs));
+        if (bx + by + bw > kNoAllocBytes)
+            throw Error(RTE_E_BUDGET, "rte_hmat_matvec_noalloc: needs " + std::to_string(bx + by + bw) +
+                                          " bytes of workspace, more than its fixed " +
+                                          std::to_string(kNoAllocBytes) + "; use rte_hmat_matvec");
+        char *base = static_cast<char *>(scratch_address(dev));
+        double *xc = reinterpret_cast<double *>(base), *yc = reinterpret_cast<double *>(base + bx);
+        double *ws = reinterpret_cast<double *>(base + bx + by);
+        hipStream_t s = (hipStream_t)stream;
+        permute_gather(H.src_pos.as<int64_t>(), ns, nrhs, ns, ns, x, xc, s);
+        matvec_launch_ws(H, band, nrhs, xc, yc, nullptr, ws, s);
+        permute_scatter(H.tgt_nat.as<int64_t>(), nt, nrhs, nt, nt, yc, y, s);
         HIP_CHECK(hipStreamSynchronize(s));
         return RTE_OK;
     });

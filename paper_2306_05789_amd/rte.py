@@ -126,6 +126,7 @@ SIGNATURES = {
     "rte_hmat_assemble": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(HmatOpts), C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
     "rte_hmat_matvec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rte_hmat_matvec_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_hmat_matvec_batched": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "rte_hmat_stats": (C.c_int, [C.c_void_p, C.POINTER(HmatStats)]),
     "rte_hmat_get_config": (C.c_int, [C.c_void_p, C.POINTER(MatvecConfig)]),
@@ -311,6 +312,13 @@ def rte_hmat_assemble(mesh: Mesh, kappa, opts: HmatOpts, stream=None) -> HMat:
 def rte_hmat_matvec(hmat: HMat, band, x, y, stream=None):
     nrhs = 1 if x.dim() == 1 else int(x.shape[0])
     _check(load().rte_hmat_matvec(hmat.handle, int(band), nrhs, _ptr(x), _ptr(y), _stream(stream)))
+    return y
+
+
+def rte_hmat_matvec_noalloc(hmat: HMat, band, x, y, stream=None):
+    """Same as rte_hmat_matvec, with the library's fixed device workspace (no allocation)."""
+    nrhs = 1 if x.dim() == 1 else int(x.shape[0])
+    _check(load().rte_hmat_matvec_noalloc(hmat.handle, int(band), nrhs, _ptr(x), _ptr(y), _stream(stream)))
     return y
 
 
