@@ -32,6 +32,8 @@ Other workloads (`--workload`), one JSON line each:
   served      256 Poisson(20/s) requests over resident 21^3/29^3/41^3/49^3 meshes
               through the request server (mixed, continuous batching) and, with
               `--compare R`, the first R of them through plain FP64 one at a time
+  matvec      the headline operator's matvecs alone after a 1 GiB calibration copy
+              (for the HBM traffic counters)
 """
 from __future__ import annotations
 
@@ -365,10 +367,10 @@ def run_served(args):
 # HBM bytes per launch of the low-operator matvec of the headline workload (the
 # four launches k_mf_xstage, k_mf_phase_a, k_mf_tstage, k_mf_phase_b), from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes calibrated on a plain 1 GiB copy
-# (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all): 122.3 GB read and
-# 8.9 GB written (profiles/cube49_32band_16rhs_mixed_matvec_traffic.md).  Set
+# (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all): 108.9 GB read and
+# 8.7 GB written (profiles/cube49_32band_16rhs_mixed_matvec_traffic.md).  Set
 # to None whenever those kernels change.
-LOW_MATVEC_TRAFFIC_BYTES = 131.2e9
+LOW_MATVEC_TRAFFIC_BYTES = 117.6e9
 
 
 def _cpu_model() -> str:
@@ -775,6 +777,36 @@ def run_cube41(args, emit=True):
 
 
 
+def run_matvec(args):
+    """The headline operator alone (49^3, 32 bands, mixed storage): a 1 GiB device
+    copy first (the calibration of the HBM traffic counters), then event-timed
+    all-band 16-RHS matvecs of the low and the accurate operator.  Used under
+    rocprofv3 --pmc to measure the matvec's HBM traffic."""
+    import torch
+    from paper_2306_05789_amd import inputs, rte
+    wl = inputs.batched()
+    mesh = rte.rte_mesh_create(wl.n, emit_faces=wl.emit_faces)
+    G = rte.rte_hmat_assemble(mesh, torch.tensor(wl.kappa, device="cuda:0"),
+                              rte.hmat_opts(kind=rte.RTE_VOLUME, precision=rte.RTE_MIXED_BF16))
+    st = rte.rte_hmat_stats(G)
+    _say(f"assembled in {st['assemble_ms']:.0f} ms")
+    a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    nrhs = int(wl.T_wall.shape[0])
+    vec = 8 * st["n_bands"] * nrhs * (st["n_src"] + st["n_tgt"])
+    res = {}
+    for op, name, esz in ((rte.RTE_OP_LOW, "low", 2), (rte.RTE_OP_ACCURATE, "accurate", 4)):
+        ms = rte.rte_hmat_time_matvec(G, nrhs, op, max(args.steps, 1))
+        byt = esz * (st["dense_entries"] + st["lowrank_entries"]) + vec
+        res[name] = {"ms": ms, "bytes": byt, "GB_s": byt / (ms * 1e-3) / 1e9, "frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        _say(f"{name}: {ms:.2f} ms, {res[name]['GB_s']:.0f} GB/s")
+    print(json.dumps({"workload": "cube49_32band_16rhs_mixed_matvec", "calibration_copy_bytes": 2 ** 30,
+                      "dense_entries": st["dense_entries"], "lowrank_entries": st["lowrank_entries"],
+                      "device_bytes": st["bytes"], "matvec": res}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -784,7 +816,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline: skip the FP64 share, 41^3 and 11^3 legs")
     ap.add_argument("--workload", default="headline",
-                    choices=("headline", "cube41", "reflective", "batched", "served"))
+                    choices=("headline", "cube41", "reflective", "batched", "served", "matvec"))
     ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"), help="reflective workload")
     ap.add_argument("--bands", type=int, default=0, help="batched workload: bands taken (0 = all 32)")
     ap.add_argument("--compare", type=int, default=0,
@@ -798,7 +830,7 @@ def main():
               "(see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     {"headline": run_headline, "cube41": run_cube41, "reflective": run_reflective, "batched": run_batched,
-     "served": run_served}[args.workload](args)
+     "served": run_served, "matvec": run_matvec}[args.workload](args)
 
 
 if __name__ == "__main__":
