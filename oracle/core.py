@@ -51,7 +51,9 @@ class _Problem(C.Structure):
         ("kappa", C.POINTER(C.c_double)),
         ("n_walls", C.c_int32), ("wall_axis", C.c_int32 * 6), ("wall_side", C.c_int32 * 6),
         ("R", C.c_double * 6),
-        ("emit_faces", C.c_uint32), ("near_cheb", C.c_int32),
+        ("emit_faces", C.c_uint32),
+        ("hole_lo", C.c_int32 * 3), ("hole_hi", C.c_int32 * 3), ("hole_emit", C.c_uint32),
+        ("near_cheb", C.c_int32),
         ("nq_tet_far", C.c_int32), ("nq_tet_near", C.c_int32),
         ("nq_tri_far", C.c_int32), ("nq_tri_near", C.c_int32),
         ("tet_far_p", C.POINTER(C.c_double)), ("tet_far_w", C.POINTER(C.c_double)),
@@ -80,6 +82,8 @@ def lib():
             f.argtypes = [P, C.c_int64, i64p, i64p, f64p]
             f.restype = None
         _lib.og_kappa_points.argtypes = [P, C.c_int64, f64p, f64p]
+        _lib.og_emitting_mask.argtypes = [P, np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
+        _lib.og_emitting_mask.restype = None
         _lib.og_tau_segments.argtypes = [P, C.c_int64, f64p, f64p, C.c_int32, f64p]
         _lib.og_volume_entry.argtypes = [P, C.c_int64, C.c_int64]
         _lib.og_volume_entry.restype = C.c_double
@@ -138,7 +142,12 @@ class Grid:
 class Problem:
     """One kappa field on one grid, with planar reflective walls, each covering a
     whole box face and reflecting once (Hypothesis 1): either one wall given by
-    wall_axis / wall_side / R, or a list `walls` of (axis, side, R)."""
+    wall_axis / wall_side / R, or a list `walls` of (axis, side, R).
+
+    A non-convex domain (Remark rem1): `hole` = ((i0, j0, k0), (i1, j1, k1)), the
+    grid cells [i0, i1) x [j0, j1) x [k0, k1) removed from the box (kappa =
+    +infinity there); bit f of `hole_emit` makes the hole's face on side f % 2
+    of axis f // 2 emit into the domain."""
     grid: Grid
     kappa: np.ndarray
     emit_faces: int = 1
@@ -149,6 +158,8 @@ class Problem:
     flip_axis: int = -1
     flip_cells: int = 0
     walls: list = None
+    hole: tuple = None
+    hole_emit: int = 0
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -175,6 +186,18 @@ class Problem:
         for w, (a, sd, r) in enumerate(self.walls):
             s.wall_axis[w], s.wall_side[w], s.R[w] = int(a), int(sd), float(r)
         s.emit_faces, s.near_cheb = self.emit_faces, self.near_cheb
+        if self.hole is not None:
+            lo, hi = self.hole
+            n = self.grid.n
+            assert all(0 <= lo[a] < hi[a] <= n[a] - 1 for a in range(3))
+            for f in range(6):   # an emitting hole face lies inside the box
+                if (self.hole_emit >> f) & 1:
+                    a = f // 2
+                    assert (hi[a] < n[a] - 1) if f % 2 else (lo[a] > 0)
+            s.hole_lo[:], s.hole_hi[:] = [int(v) for v in lo], [int(v) for v in hi]
+            s.hole_emit = self.hole_emit
+        else:
+            assert self.hole_emit == 0
         (tfp, tfw), (tnp, tnw), (sfp, sfw), (snp, snw) = rules
         s.nq_tet_far, s.nq_tet_near, s.nq_tri_far, s.nq_tri_near = len(tfw), len(tnw), len(sfw), len(snw)
         s.tet_far_p, s.tet_far_w = _dptr(tfp), _dptr(tfw)
@@ -189,7 +212,10 @@ class Problem:
 
     @property
     def emitting(self) -> np.ndarray:
-        return self.grid.emitting_vertices(self.emit_faces)
+        """Natural ids of the surface unknowns (corners of emitting face squares), ascending."""
+        mask = np.zeros(self.grid.N, dtype=np.uint8)
+        lib().og_emitting_mask(self.ref, mask)
+        return np.nonzero(mask)[0].astype(np.int64)
 
     # -- entries ---------------------------------------------------------
     def volume_block(self, rows, cols) -> np.ndarray:

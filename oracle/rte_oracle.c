@@ -29,6 +29,12 @@
  * mirror-doubled domain used as an independent check of the reflective term,
  * cells on one side of a plane may be the mirror images of Kuhn cells.
  *
+ * A non-convex domain is the box minus a box of grid cells (the inner cube of
+ * the academic test); following Remark rem1 the method is applied to the box
+ * with kappa = +infinity in the hole: a segment whose path crosses the hole's
+ * interior has an infinite optical depth, the hole's cells are in no vertex's
+ * star, and the hole's faces may emit into the domain.
+ *
  * Readings where the paper is silent (each also listed in the design notes):
  *   - one optical depth per vertex pair ("frozen tau"): the quadrature acts on
  *     kappa * w^j / r^2 only, and tau is the exact line integral of the P1
@@ -36,7 +42,15 @@
  *   - near rule iff the grid-index Chebyshev distance is <= near_cheb (2);
  *   - a target on the plane of an emitting face receives theta_F/(4 pi) from
  *     that face on the diagonal (the coplanar limit of the solid angle);
- *   - kappa(y) multiplies both the direct and the reflected volume terms.
+ *   - kappa(y) multiplies both the direct and the reflected volume terms;
+ *   - hole: a segment is blocked only when a positive length of it lies
+ *     outside the closed domain: in the hole's open interior or on a part of
+ *     a box face the hole covers (one grazing the hole's faces or edges inside
+ *     the box is not);
+ *     vertices with no non-hole cell have zero rows and columns (for them the
+ *     iteration gives J = 0 and T = 0); a face square is emitting when the
+ *     cell it bounds on the domain side is no hole cell, and theta_F on the
+ *     diagonal is pi/2 per emitting square at the vertex.
  */
 #include <math.h>
 #include <stdint.h>
@@ -55,6 +69,9 @@ typedef struct {
     int32_t wall_side[6];  /* 0: plane at lo, 1: plane at hi */
     double R[6];           /* reflection coefficients */
     uint32_t emit_faces;   /* bit f: face (axis f/2, side f%2) emits */
+    int32_t hole_lo[3];    /* non-convex domain: the box minus the cells [hole_lo, hole_hi), where */
+    int32_t hole_hi[3];    /* kappa is +infinity (no hole when hole_lo[0] >= hole_hi[0]) */
+    uint32_t hole_emit;    /* bit f: the hole's face on side f%2 of axis f/2 emits into the domain */
     int32_t near_cheb;
     int32_t nq_tet_far, nq_tet_near, nq_tri_far, nq_tri_near;
     const double *tet_far_p, *tet_far_w;     /* [nq][4], [nq] */
@@ -86,6 +103,50 @@ static void vpos(const og_problem_t *P, const int idx[3], double x[3])
 }
 
 static double kap(const og_problem_t *P, const int idx[3]) { return P->kappa[vid(P, idx)]; }
+
+static int has_hole(const og_problem_t *P)
+{
+    return P->hole_lo[0] < P->hole_hi[0] && P->hole_lo[1] < P->hole_hi[1] && P->hole_lo[2] < P->hole_hi[2];
+}
+
+/* is cell c one of the hole's cells */
+static int hole_cell(const og_problem_t *P, const int c[3])
+{
+    if (!has_hole(P)) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (c[a] < P->hole_lo[a] || c[a] >= P->hole_hi[a]) return 0;
+    return 1;
+}
+
+/* a vertex belongs to the closed domain when one of its cells is not a hole
+ * cell; the others (inside the hole, or on a box face the hole covers) have
+ * zero rows and columns */
+static int vertex_active(const og_problem_t *P, const int v[3])
+{
+    if (!has_hole(P)) return 1;
+    for (int o = 0; o < 8; ++o) {
+        int c[3], ok = 1;
+        for (int a = 0; a < 3; ++a) {
+            c[a] = v[a] - ((o >> a) & 1);
+            if (c[a] < 0 || c[a] > P->n[a] - 2) ok = 0;
+        }
+        if (ok && !hole_cell(P, c)) return 1;
+    }
+    return 0;
+}
+
+/* is the point X (grid coordinates) outside the closed domain: strictly
+ * inside the hole, or on a part of a box face that the hole covers (along an
+ * axis where the hole reaches the box face, the open range extends past it) */
+static int in_hole(const og_problem_t *P, const double X[3])
+{
+    if (!has_hole(P)) return 0;
+    for (int a = 0; a < 3; ++a) {
+        const int open_lo = P->hole_lo[a] == 0, open_hi = P->hole_hi[a] == P->n[a] - 1;
+        if (!((open_lo || X[a] > P->hole_lo[a]) && (open_hi || X[a] < P->hole_hi[a]))) return 0;
+    }
+    return 1;
+}
 
 /* The tetrahedron of cell c for axis order sig[]: its vertices are
  * base, base+s0 e_sig0, base+s0 e_sig0+s1 e_sig1, base+s.  For a plain Kuhn cell
@@ -210,6 +271,20 @@ double og_tau(const og_problem_t *P, const double p[3], const double q[3])
     }
     t[cnt++] = 1.0;
     qsort(t, cnt, sizeof(double), cmp_double);
+    /* kappa is +infinity in the hole: a piece (the hole's boundary planes are
+     * among the breakpoints) whose midpoint lies outside the closed domain
+     * blocks the segment.  Pieces of rounding length, where two families
+     * cross at the same point, carry no length and are passed over (between
+     * grid vertices a piece of positive length is longer than 1/n^2). */
+    for (size_t m = 1; m < cnt; ++m) {
+        if (t[m] - t[m - 1] <= 1e-12) continue;
+        double X[3], tm = 0.5 * (t[m - 1] + t[m]);
+        for (int a = 0; a < 3; ++a) X[a] = Pg[a] + tm * (Qg[a] - Pg[a]);
+        if (in_hole(P, X)) {
+            free(t);
+            return INFINITY;
+        }
+    }
     double sum = 0.0, kprev = 0.0;
     for (size_t m = 0; m < cnt; ++m) {
         double x[3];
@@ -285,7 +360,7 @@ static double volume_quad(const og_problem_t *P, const double x[3], const int j[
         int ok = 1;
         for (int a = 0; a < 3; ++a)
             if (c[a] < 0 || c[a] > P->n[a] - 2) ok = 0;
-        if (!ok) continue;
+        if (!ok || hole_cell(P, c)) continue;   /* the hole is not part of the domain */
         int base[3], step[3];
         cell_frame(P, c, base, step);
         for (int s = 0; s < 6; ++s) {
@@ -324,6 +399,7 @@ double og_volume_entry(const og_problem_t *P, int64_t i, int64_t j)
     vidx(P, j, jj);
     vpos(P, ii, xi);
     vpos(P, jj, xj);
+    if (!vertex_active(P, ii) || !vertex_active(P, jj)) return 0.0;
     double G = exp(-og_tau(P, xi, xj)) * volume_quad(P, xi, jj, cheb(ii, jj) <= P->near_cheb);
     for (int w = 0; w < P->n_walls; ++w) {
         if (P->R[w] == 0.0) continue;
@@ -337,47 +413,83 @@ double og_volume_entry(const og_problem_t *P, int64_t i, int64_t j)
     return G;
 }
 
-/* planar angle of face (axis a, plane index) at a point of its plane given by
- * grid indices: 2pi inside, pi on an edge, pi/2 at a corner, 0 outside */
-static double face_angle(const og_problem_t *P, int a, const int pidx[3])
+/* An emitting rectangle of the boundary: the plane x_a = pf (grid index), the
+ * normal pointing into the domain (sign * e_a), and the vertex index ranges
+ * [lo, hi] along the face's two other axes b < c.  The box's emitting faces,
+ * then the hole's. */
+typedef struct {
+    int a, pf, sign, lo[2], hi[2];
+} og_rect_t;
+
+static int emit_rects(const og_problem_t *P, og_rect_t r[12])
 {
-    double frac = 1.0;
-    for (int b = 0; b < 3; ++b) {
-        if (b == a) continue;
-        if (pidx[b] < 0 || pidx[b] > P->n[b] - 1) return 0.0;
-        if (pidx[b] == 0 || pidx[b] == P->n[b] - 1) frac *= 0.5;
+    int n = 0;
+    for (int f = 0; f < 6; ++f) {
+        if (!((P->emit_faces >> f) & 1u)) continue;
+        int a = f / 2, b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+        og_rect_t q = {a, (f & 1) ? P->n[a] - 1 : 0, (f & 1) ? -1 : 1, {0, 0}, {P->n[b] - 1, P->n[c] - 1}};
+        r[n++] = q;
     }
-    return 2.0 * OG_PI * frac;
+    if (has_hole(P))
+        for (int f = 0; f < 6; ++f) {
+            if (!((P->hole_emit >> f) & 1u)) continue;
+            int a = f / 2, b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+            og_rect_t q = {a, (f & 1) ? P->hole_hi[a] : P->hole_lo[a], (f & 1) ? 1 : -1,
+                           {P->hole_lo[b], P->hole_lo[c]}, {P->hole_hi[b], P->hole_hi[c]}};
+            r[n++] = q;
+        }
+    return n;
 }
 
-/* (1/4pi) sum over emitting faces F containing l of the integral over F of
- * w~^l(y) |(x-y).n_F| / |x-y|^3, or theta_F/(4pi) on the diagonal when the
- * point lies in the plane of F. */
+/* Does the grid square with lower corner (sq[0], sq[1]) (along the axes b < c
+ * other than R's) belong to the emitting surface: it lies in R and the cell
+ * it bounds on the domain side is not a hole cell (a box face is covered
+ * where the hole touches it). */
+static int emitting_square(const og_problem_t *P, const og_rect_t *R, const int sq[2])
+{
+    if (sq[0] < R->lo[0] || sq[0] > R->hi[0] - 1 || sq[1] < R->lo[1] || sq[1] > R->hi[1] - 1) return 0;
+    int a = R->a, b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2, cell[3];
+    cell[a] = R->sign > 0 ? R->pf : R->pf - 1;
+    cell[b] = sq[0];
+    cell[c] = sq[1];
+    return !hole_cell(P, cell);
+}
+
+/* (1/4pi) sum over emitting rectangles R containing l of the integral over R's
+ * emitting squares of w~^l(y) [(x-y).n_R]_+ / |x-y|^3 (a rectangle seen from
+ * behind adds nothing); on the diagonal, when the point lies in the plane of
+ * R, the planar angle theta of R's emitting squares at the point over 4pi
+ * (pi/2 per square). */
 static double surface_quad(const og_problem_t *P, const double x[3], const int xidx[3],
                            const int l[3], int near)
 {
     int nq = near ? P->nq_tri_near : P->nq_tri_far;
     const double *bp = near ? P->tri_near_p : P->tri_far_p;
     const double *bw = near ? P->tri_near_w : P->tri_far_w;
+    og_rect_t rects[12];
+    int nr = emit_rects(P, rects);
     double sum = 0.0;
-    for (int f = 0; f < 6; ++f) {
-        if (!((P->emit_faces >> f) & 1u)) continue;
-        int a = f / 2;
-        int pf = (f & 1) ? P->n[a] - 1 : 0;
+    for (int f = 0; f < nr; ++f) {
+        const og_rect_t *R = &rects[f];
+        int a = R->a, pf = R->pf;
+        int b = (a == 0) ? 1 : 0;
+        int c = (a == 2) ? 1 : 2;
         if (l[a] != pf) continue;
         double plane = P->lo[a] + pf * P->h[a];
         if (xidx[a] == pf) {
             if (xidx[0] == l[0] && xidx[1] == l[1] && xidx[2] == l[2])
-                sum += face_angle(P, a, xidx) / (4.0 * OG_PI);
+                for (int o = 0; o < 4; ++o) {
+                    int sq[2] = {l[b] - (o & 1), l[c] - ((o >> 1) & 1)};
+                    if (emitting_square(P, R, sq)) sum += 0.5 * OG_PI / (4.0 * OG_PI);
+                }
             continue;
         }
-        int b = (a == 0) ? 1 : 0;
-        int c = (a == 2) ? 1 : 2;
+        double d = (x[a] - plane) * R->sign;
+        if (d <= 0.0) continue;
         double area = 0.5 * P->h[b] * P->h[c];
-        double d = fabs(x[a] - plane);
         for (int o = 0; o < 4; ++o) {
             int sq[2] = {l[b] - (o & 1), l[c] - ((o >> 1) & 1)};
-            if (sq[0] < 0 || sq[0] > P->n[b] - 2 || sq[1] < 0 || sq[1] > P->n[c] - 2) continue;
+            if (!emitting_square(P, R, sq)) continue;
             /* square frame, mirrored like the cells when the flip axis lies in the face */
             int B[2] = {sq[0], sq[1]}, S[2] = {1, 1};
             if (P->flip_axis == b && sq[0] < P->flip_cells) { B[0] = sq[0] + 1; S[0] = -1; }
@@ -425,6 +537,7 @@ double og_surface_entry(const og_problem_t *P, int64_t i, int64_t l)
     vidx(P, l, ll);
     vpos(P, ii, xi);
     vpos(P, ll, xl);
+    if (!vertex_active(P, ii) || !vertex_active(P, ll)) return 0.0;
     double S = exp(-og_tau(P, xi, xl)) * surface_quad(P, xi, ii, ll, cheb(ii, ll) <= P->near_cheb);
     for (int w = 0; w < P->n_walls; ++w) {
         if (P->R[w] == 0.0) continue;
@@ -468,6 +581,29 @@ void og_surface_pairs(const og_problem_t *P, int64_t n, const int64_t *rows, con
 {
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < n; ++k) out[k] = og_surface_entry(P, rows[k], cols[k]);
+}
+
+/* mask[v] = 1 when vertex v is a corner of an emitting square (the surface
+ * unknowns, in natural order), else 0 */
+void og_emitting_mask(const og_problem_t *P, uint8_t *mask)
+{
+    og_rect_t rects[12];
+    int nr = emit_rects(P, rects);
+    int64_t N = (int64_t)P->n[0] * P->n[1] * P->n[2];
+    for (int64_t v = 0; v < N; ++v) {
+        int l[3];
+        vidx(P, v, l);
+        mask[v] = 0;
+        for (int f = 0; f < nr && !mask[v]; ++f) {
+            const og_rect_t *R = &rects[f];
+            int a = R->a, b = (a == 0) ? 1 : 0, c = (a == 2) ? 1 : 2;
+            if (l[a] != R->pf) continue;
+            for (int o = 0; o < 4; ++o) {
+                int sq[2] = {l[b] - (o & 1), l[c] - ((o >> 1) & 1)};
+                if (emitting_square(P, R, sq)) mask[v] = 1;
+            }
+        }
+    }
 }
 
 void og_kappa_points(const og_problem_t *P, int64_t n, const double *x, double *out)
