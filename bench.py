@@ -34,6 +34,9 @@ Other workloads (`--workload`), one JSON line each:
               `--compare R`, the first R of them through plain FP64 one at a time
   matvec      the headline operator's matvecs alone after a 1 GiB calibration copy
               (for the HBM traffic counters)
+  academic    Test-3 of the paper's academic test (box minus an inner cube, three
+              reflective planes), `--h` cm spacing: assembly + grey solve, FP64 and
+              mixed, beside the paper's CPU time on its nearest mesh
 """
 from __future__ import annotations
 
@@ -777,6 +780,71 @@ def run_cube41(args, emit=True):
 
 
 
+# The paper's whole-run CPU times of Test-3 (Section "An Academic Test", its CPU
+# table; MacBook Pro M1, precision not stated), quoted beside the nearest grid
+# as context: vertices -> seconds.
+PAPER_TEST3_CPU_S = {2758: 5.3, 8003: 16.5, 26189: 79.4, 84042: 389.0, 195974: 1563.0}
+
+
+def run_academic(args, emit=True):
+    """Test-3 of the academic test: D = (0,60) x (0,100) x (0,60) cm minus the cube
+    [0,10]^3, the three planes through the origin reflecting (R = 1), the cube's
+    three faces inside D emitting, kappa 0.1 per cm and 1e-4 in the cylinder
+    that prolongs the cube, grey.  One step = assembly of G and S (concurrently)
+    + the fixed point to a relative change of 1e-6 (the paper's six orders of
+    reduction), FP64 and mixed.  The paper's CPU time on its nearest mesh is
+    quoted as context."""
+    import torch
+    from paper_2306_05789_amd import inputs, rte
+    dev = "cuda:0"
+    wl = inputs.academic(args.h)
+    mesh = rte.rte_mesh_create(wl.n, wl.lo, wl.hi, emit_faces=wl.emit_faces, walls=wl.walls, hole=wl.hole,
+                               hole_emit=wl.hole_emit)
+    kap = torch.tensor(wl.kappa[None, :], device=dev)
+    Tw = torch.full((1, mesh.L), wl.T_hole, device=dev, dtype=torch.float64)
+    T = torch.empty((1, mesh.N), device=dev, dtype=torch.float64)
+    res = {}
+    for name in ("fp64", "mixed"):
+        p = rte.PRECISIONS[name]
+        steps = []
+        for k in range(min(max(args.steps, 1), 5) + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            G, S, wall_ms = _assemble_pair(rte, mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, precision=p),
+                                           rte.hmat_opts(kind=rte.RTE_SURFACE, precision=p))
+            t1 = time.perf_counter()
+            st = rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=True, tol=1e-6, max_iter=3000, precision=p)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            gs, ss = rte.rte_hmat_stats(G), rte.rte_hmat_stats(S)
+            if k:   # the first step is the warm-up
+                steps.append(((t2 - t0) * 1e3, (t1 - t0) * 1e3, (t2 - t1) * 1e3))
+            _say(f"academic {name}: step {(t2 - t0) * 1e3:.0f} ms (assembly {(t1 - t0) * 1e3:.0f}, solve "
+                 f"{(t2 - t1) * 1e3:.0f}), {st['iterations']} sweeps, residual {st['residual']:.1e}")
+            del G, S
+        stored_G = gs["dense_entries"] + gs["lowrank_entries"]
+        stored_S = ss["dense_entries"] + ss["lowrank_entries"]
+        ms = np.mean(np.array(steps), axis=0)
+        Tn = T.cpu().numpy()[0]
+        res[name] = {"step_ms": float(ms[0]), "assembly_ms": float(ms[1]), "solve_ms": float(ms[2]),
+                     "sweeps": st["iterations"], "residual": st["residual"], "converged": bool(st["converged"]),
+                     "compression_level_volume": 1.0 - stored_G / float(mesh.N) ** 2,
+                     "compression_level_surface": 1.0 - stored_S / float(mesh.N * mesh.L),
+                     "G_bytes": gs["bytes"], "S_bytes": ss["bytes"], "T_max": float(Tn.max())}
+        if name == "fp64":
+            T64 = Tn.copy()
+        else:
+            live = T64 > 0
+            res[name]["max_rel_T_vs_fp64"] = float(np.max(np.abs(Tn[live] - T64[live]) / T64[live]))
+    near = min(PAPER_TEST3_CPU_S, key=lambda v: abs(np.log(v / mesh.N)))
+    out = {"workload": f"academic_test3_h{args.h:g}", "N": mesh.N, "L": mesh.L, "n": list(wl.n), "results": res,
+           "paper_context": {"vertices": near, "cpu_s": PAPER_TEST3_CPU_S[near], "hardware": "MacBook Pro M1",
+                             "what": "whole run, precision and tolerance not stated"}}
+    if emit:
+        print(json.dumps(out))
+    return out
+
+
 def run_matvec(args):
     """The headline operator alone (49^3, 32 bands, mixed storage): a 1 GiB device
     copy first (the calibration of the HBM traffic counters), then event-timed
@@ -816,7 +884,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline: skip the FP64 share, 41^3 and 11^3 legs")
     ap.add_argument("--workload", default="headline",
-                    choices=("headline", "cube41", "reflective", "batched", "served", "matvec"))
+                    choices=("headline", "cube41", "reflective", "batched", "served", "matvec", "academic"))
+    ap.add_argument("--h", type=float, default=2.5, help="academic workload: grid spacing in cm (divides 10)")
     ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"), help="reflective workload")
     ap.add_argument("--bands", type=int, default=0, help="batched workload: bands taken (0 = all 32)")
     ap.add_argument("--compare", type=int, default=0,
@@ -830,7 +899,7 @@ def main():
               "(see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     {"headline": run_headline, "cube41": run_cube41, "reflective": run_reflective, "batched": run_batched,
-     "served": run_served, "matvec": run_matvec}[args.workload](args)
+     "served": run_served, "matvec": run_matvec, "academic": run_academic}[args.workload](args)
 
 
 if __name__ == "__main__":

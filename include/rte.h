@@ -70,7 +70,20 @@ typedef struct rte_hmat *rte_hmat_t;
  * of its own mirror image and each ray reflects at most once (Hypothesis 1).
  * A face may be given once.
  * emit_faces: bit f (0..5 = x-,x+,y-,y+,z-,z+) marks a black emitting face
- * (boundary source Q = B_nu(T_wall), eq. SE1); a reflective face may not emit. */
+ * (boundary source Q = B_nu(T_wall), eq. SE1); a reflective face may not emit.
+ * Non-convex domain (Remark rem1; the inner cube of Section "An Academic
+ * Test"): when hole_lo[a] < hole_hi[a] on every axis, the cells
+ * [hole_lo, hole_hi) (cell indices, 0 <= hole_lo[a] < hole_hi[a] <= n[a]-1)
+ * are removed, kappa = +infinity there.  A path that runs a positive length
+ * through the removed box, or over a part of a box face that the box covers,
+ * is blocked (one grazing the hole's faces or edges is not); the hole's cells
+ * belong to no vertex's star; vertices with no remaining cell keep zero rows
+ * and columns (the iteration leaves them at J = 0, T = 0).  hole_emit: bit f
+ * makes the hole's face on side f%2 of axis f/2 a black emitting face, which
+ * must lie inside the box (hole_lo[a] > 0 for side 0, hole_hi[a] < n[a]-1 for
+ * side 1).  The surface unknowns are the corners of the emitting face squares
+ * (a box-face square under the hole does not emit), in ascending vertex id.
+ * All-zero hole fields: the whole box. */
 typedef struct {
     int32_t n[3];
     double lo[3], hi[3];
@@ -80,6 +93,9 @@ typedef struct {
     uint32_t emit_faces;
     uint32_t reflect_faces;
     double R_faces[6];
+    int32_t hole_lo[3];
+    int32_t hole_hi[3];
+    uint32_t hole_emit;
 } rte_mesh_desc_t;
 
 rte_status_t rte_mesh_create(const rte_mesh_desc_t *desc, rte_mesh_t *out);

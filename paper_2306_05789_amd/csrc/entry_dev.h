@@ -277,6 +277,123 @@ __device__ __forceinline__ void mirror_index(const GridDev &g, int w, const int 
     mi[a] = 2 * Ci - xi[a];
 }
 
+// ---------------------------------------------------------------- the hole (non-convex domain)
+// A path is blocked when it runs a positive length through the removed box of
+// cells (kappa = +infinity there, Remark rem1) or over a part of a box face
+// that the box covers.  Both ends of a segment are grid vertices (integer
+// coordinates; a mirror image of one too), so the test is exact: the slab
+// method with the parameters of the box planes kept as fractions n / d, d > 0,
+// compared by cross multiplication.  An axis open on one side (bit 2a: below,
+// 2a+1: above) has no plane there.
+__device__ __forceinline__ bool frac_lt(int64_t an, int64_t ad, int64_t bn, int64_t bd) { return an * bd < bn * ad; }
+
+__device__ __forceinline__ bool seg_meets_box(const int P[3], const int Q[3], const int lo[3], const int hi[3],
+                                              unsigned open) {
+    int64_t t0n = 0, t0d = 1, t1n = 1, t1d = 1;   // the segment's own [0, 1]
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int D = Q[a] - P[a];
+        const bool ol = (open >> (2 * a)) & 1u, oh = (open >> (2 * a + 1)) & 1u;
+        if (D == 0) {
+            if (!((ol || P[a] > lo[a]) && (oh || P[a] < hi[a]))) return false;
+            continue;
+        }
+        const int64_t ad = D > 0 ? D : -D;
+        if (D > 0 ? !ol : !oh) {   // enters through the plane below (D > 0) or above
+            const int64_t en = D > 0 ? lo[a] - P[a] : P[a] - hi[a];
+            if (frac_lt(t0n, t0d, en, ad)) { t0n = en; t0d = ad; }
+        }
+        if (D > 0 ? !oh : !ol) {   // leaves through the plane above (D > 0) or below
+            const int64_t ex = D > 0 ? hi[a] - P[a] : P[a] - lo[a];
+            if (frac_lt(ex, ad, t1n, t1d)) { t1n = ex; t1d = ad; }
+        }
+    }
+    return frac_lt(t0n, t0d, t1n, t1d);
+}
+
+// the straight path between grid vertices P and Q crosses the hole
+__device__ __forceinline__ bool hole_blocks(const GridDev &g, const int P[3], const int Q[3]) {
+    return seg_meets_box(P, Q, g.hole_lo, g.hole_hi, g.hole_open);
+}
+
+// the path from P reflected at wall w to Q crosses the hole.  Unfolded, it is
+// the straight segment from P's mirror image to Q; its part beyond the wall
+// is the mirror image of the first leg, so the blocking region there is the
+// mirror image of the hole.  A hole that reaches the wall merges with its
+// image into one box twice as long; otherwise the two boxes are tested apart.
+__device__ __forceinline__ bool hole_blocks_mirror(const GridDev &g, int w, const int P[3], const int Q[3]) {
+    const WallInfo wi = wall_info(g, w);
+    const int a = wi.axis;
+    // the wall axis' values by selects (a is not a compile-time constant)
+    int Pb[3], lo[3], hi[3], C = 0, la = 0, ha = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = g.hole_lo[k];
+        hi[k] = g.hole_hi[k];
+        Pb[k] = P[k];
+        if (k == a) {
+            C = wi.side ? g.n[k] - 1 : 0;
+            Pb[k] = 2 * C - P[k];
+            la = g.hole_lo[k];
+            ha = g.hole_hi[k];
+        }
+    }
+    const unsigned ol = (g.hole_open >> (2 * a)) & 1u, oh = (g.hole_open >> (2 * a + 1)) & 1u;
+    const unsigned others = g.hole_open & ~(3u << (2 * a));
+    int blo[3], bhi[3];
+    if (wi.side == 0 ? ol : oh) {
+        // merged: (2C - hi, hi) at the low wall, (lo, 2C - lo) at the high one,
+        // unbounded at both ends when the hole also reaches the far face
+        const unsigned far = wi.side == 0 ? oh : ol;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            blo[k] = k == a ? (wi.side == 0 ? 2 * C - ha : la) : lo[k];
+            bhi[k] = k == a ? (wi.side == 0 ? ha : 2 * C - la) : hi[k];
+        }
+        return seg_meets_box(Pb, Q, blo, bhi, others | (far ? 3u << (2 * a) : 0u));
+    }
+    if (seg_meets_box(Pb, Q, lo, hi, g.hole_open)) return true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        blo[k] = k == a ? 2 * C - ha : lo[k];
+        bhi[k] = k == a ? 2 * C - la : hi[k];
+    }
+    return seg_meets_box(Pb, Q, blo, bhi, others | (oh << (2 * a)) | (ol << (2 * a + 1)));
+}
+
+// bit o of the 8 cells around vertex v (cell v - o) is set for the hole's cells
+__device__ __forceinline__ int hole_cells(const GridDev &g, const int v[3]) {
+    int m = 0;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int c = v[a] - ((o >> a) & 1);
+            in = in && c >= g.hole_lo[a] && c < g.hole_hi[a];
+        }
+        m |= in ? (1 << o) : 0;
+    }
+    return m;
+}
+
+// a vertex of the closed domain: one of its cells inside the grid is no hole cell
+__device__ __forceinline__ bool vertex_active(const GridDev &g, const int v[3]) {
+    if (!g.has_hole) return true;
+    int grid = 0;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int c = v[a] - ((o >> a) & 1);
+            ok = ok && c >= 0 && c <= g.n[a] - 2;
+        }
+        grid |= ok ? (1 << o) : 0;
+    }
+    return (grid & ~hole_cells(g, v)) != 0;
+}
+
 __device__ __forceinline__ int cheb3(const int a[3], const int b[3]) {
     return max(max(abs(a[0] - b[0]), abs(a[1] - b[1])), abs(a[2] - b[2]));
 }
@@ -387,11 +504,13 @@ __device__ __forceinline__ void load_star(const EntryCtx<T> &c, const int jj[3],
 }
 
 // Wall modes the entry code is compiled for: no wall, exactly one wall (the
-// common reflective case, kept as straight-line code), or any number of walls
-// read from the grid (a loop; its per-wall attenuations go through a small
-// array in scratch memory).
+// common reflective case, kept as straight-line code), or the general mode:
+// any number of walls read from the grid (a loop; its per-wall attenuations go
+// through a small array in scratch memory) and the hole of a non-convex domain.
 constexpr int kNoWall = 0, kOneWall = 1, kAnyWalls = 6;
-inline int wall_mode(const GridDev &g) { return g.n_walls == 0 ? kNoWall : (g.n_walls == 1 ? kOneWall : kAnyWalls); }
+inline int wall_mode(const GridDev &g) {
+    return (g.has_hole || g.n_walls > 1) ? kAnyWalls : (g.n_walls == 0 ? kNoWall : kOneWall);
+}
 
 // sum over the direct path and the walls of attenuation times the quadrature
 // of the source star of ss seen from target tt (or from its mirror image in
@@ -404,6 +523,8 @@ __device__ __forceinline__ T vol_sum(const EntryCtx<T> &c, T att, const T att_w[
     T kn[27];
     int cellmask;
     load_star(c, ss, kn, cellmask);
+    if constexpr (NW == kAnyWalls)
+        if (g.has_hole) cellmask &= ~hole_cells(g, ss);   // the hole's cells are in no star
     const int dg[3] = {tt[0] - ss[0], tt[1] - ss[1], tt[2] - ss[2]};
     T G = att * vol_quad(c, kn, cellmask, dg, h2, cheb3(tt, ss) <= kNearCheb);
     if constexpr (NW != kNoWall) {
@@ -418,17 +539,25 @@ __device__ __forceinline__ T vol_sum(const EntryCtx<T> &c, T att, const T att_w[
     return G * (T)g.vol_scale;
 }
 
-// The optical depths of a pair: direct, and R_w exp(-tau_w) per wall.
+// The optical depths of a pair: direct, and R_w exp(-tau_w) per wall; a path
+// that the hole blocks has tau = +infinity (no march).  Pi, Qi: the vertices'
+// grid indices, P, Q the same as reals.
 template <typename T, int NW>
-__device__ __forceinline__ T attenuations(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3],
-                                          T att_w[6]) {
-    const T att = exp(-tau_segment(g, kap, P, Q));
-    if constexpr (NW == kOneWall) {
-        att_w[0] = (T)g.R[0] * exp(-tau_mirror(g, 0, kap, P, Q));
-    } else if constexpr (NW == kAnyWalls) {
-        for (int w = 0; w < g.n_walls; ++w) att_w[w] = (T)wall_info(g, w).R * exp(-tau_mirror(g, w, kap, P, Q));
+__device__ __forceinline__ T attenuations(const GridDev &g, const T *__restrict__ kap, const int Pi[3],
+                                          const int Qi[3], const T P[3], const T Q[3], T att_w[6]) {
+    if constexpr (NW == kAnyWalls) {
+        const bool hole = g.has_hole;
+        const T att = (hole && hole_blocks(g, Pi, Qi)) ? (T)0 : exp(-tau_segment(g, kap, P, Q));
+        for (int w = 0; w < g.n_walls; ++w)
+            att_w[w] = (hole && hole_blocks_mirror(g, w, Pi, Qi))
+                           ? (T)0
+                           : (T)wall_info(g, w).R * exp(-tau_mirror(g, w, kap, P, Q));
+        return att;
+    } else {
+        const T att = exp(-tau_segment(g, kap, P, Q));
+        if constexpr (NW == kOneWall) att_w[0] = (T)g.R[0] * exp(-tau_mirror(g, 0, kap, P, Q));
+        return att;
     }
-    return att;
 }
 
 // G(i, j).  Every wall adds its own mirror-image term (one reflection per
@@ -440,10 +569,12 @@ __device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
     int ii[3], jj[3];
     vtx_index(g, i, ii);
     vtx_index(g, j, jj);
+    if constexpr (NW == kAnyWalls)
+        if (!vertex_active(g, ii)) return (T)0;   // a removed vertex (its column: an empty star)
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
     T att_w[6];
-    const T att = attenuations<T, NW>(g, c.kappa, P, Q, att_w);
+    const T att = attenuations<T, NW>(g, c.kappa, ii, jj, P, Q, att_w);
     return vol_sum<T, NW>(c, att, att_w, ii, jj);
 }
 
@@ -459,9 +590,13 @@ __device__ __forceinline__ void volume_entry_pair(const EntryCtx<T> &c, int64_t 
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
     T att_w[6];
-    const T att = attenuations<T, NW>(g, c.kappa, P, Q, att_w);
+    const T att = attenuations<T, NW>(g, c.kappa, ii, jj, P, Q, att_w);
     gij = vol_sum<T, NW>(c, att, att_w, ii, jj);
     gji = vol_sum<T, NW>(c, att, att_w, jj, ii);
+    if constexpr (NW == kAnyWalls) {   // removed vertices have zero rows
+        if (!vertex_active(g, ii)) gij = (T)0;
+        if (!vertex_active(g, jj)) gji = (T)0;
+    }
 }
 
 // ---------------------------------------------------------------- surface quadrature
@@ -536,6 +671,102 @@ __device__ T surf_quad(const EntryCtx<T> &c, const int xi[3], const int ll[3], b
     return acc;
 }
 
+// The general mode's surface quadrature: the emitting rectangles are the
+// emitting box faces (f < 6) and the hole's emitting faces (f >= 6); a square
+// emits when it lies in its rectangle and the cell it bounds on the domain
+// side is no hole cell (bit ob + 2 oc of sqmask: the square l - (ob, oc)).  A
+// rectangle seen from behind adds nothing; on the diagonal in the rectangle's
+// plane the planar angle of the emitting squares, pi/2 each, over 4 pi.  For
+// the box faces of a mesh without a hole this is surf_quad, term for term.
+template <typename T, int NQ, int t>
+__device__ __forceinline__ void tri_term_m(const T *__restrict__ tab, int sqmask, const T db, const T dc, const T da2,
+                                           const T hb2, const T hc2, T &acc) {
+    constexpr TriInfo ti = kStar.tri[t];
+    if (!((sqmask >> (ti.ob + 2 * ti.oc)) & 1)) return;
+    const T *e = tab + t * NQ * 4;
+    T s = (T)0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const T eb = db - e[4 * q + 0], ec = dc - e[4 * q + 1];
+        const T r2 = da2 + hb2 * eb * eb + hc2 * ec * ec;
+        s += e[4 * q + 2] * recip(r2 * sqrt(r2));
+    }
+    acc += s;
+}
+
+template <typename T, int NQ, int... ts>
+__device__ __forceinline__ T tri_all_m(std::integer_sequence<int, ts...>, const T *__restrict__ tab, int sqmask, T db,
+                                       T dc, T da2, T hb2, T hc2) {
+    T acc = (T)0;
+    (tri_term_m<T, NQ, ts>(tab, sqmask, db, dc, da2, hb2, hc2, acc), ...);
+    return acc;
+}
+
+template <typename T>
+__device__ T surf_quad_rects(const EntryCtx<T> &c, const int xi[3], const int ll[3], bool near) {
+    const GridDev &g = c.g;
+    T acc = (T)0;
+    for (int f = 0; f < 12; ++f) {
+        const bool box = f < 6;
+        const int fb = box ? f : f - 6;
+        if (!(((box ? g.emit_faces : g.hole_emit) >> fb) & 1u)) continue;
+        const int a = fb / 2, hi_side = fb & 1;
+        const int b = (a == 0) ? 1 : 0;
+        const int cc = (a == 2) ? 1 : 2;
+        // the rectangle's plane, inward normal sign and square ranges [lo, hi), by selects
+        int pf = 0, rlo[2] = {0, 0}, rhi[2] = {0, 0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int lo_k = box ? 0 : g.hole_lo[k], hi_k = box ? g.n[k] - 1 : g.hole_hi[k];
+            if (k == a) pf = hi_side ? hi_k : lo_k;
+            if (k == b) { rlo[0] = lo_k; rhi[0] = hi_k; }
+            if (k == cc) { rlo[1] = lo_k; rhi[1] = hi_k; }
+        }
+        const int sign = box ? (hi_side ? -1 : 1) : (hi_side ? 1 : -1);
+        if (ll[a] != pf) continue;
+        int sqmask = 0;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int sb = ll[b] - (o & 1), sc = ll[cc] - (o >> 1);
+            if (sb < rlo[0] || sb >= rhi[0] || sc < rlo[1] || sc >= rhi[1]) continue;
+            bool covered = false;
+            if (box && g.has_hole) {
+                int cell[3];
+                cell[0] = a == 0 ? (sign > 0 ? pf : pf - 1) : (b == 0 ? sb : sc);
+                cell[1] = a == 1 ? (sign > 0 ? pf : pf - 1) : (b == 1 ? sb : sc);
+                cell[2] = a == 2 ? (sign > 0 ? pf : pf - 1) : sc;
+                covered = cell[0] >= g.hole_lo[0] && cell[0] < g.hole_hi[0] && cell[1] >= g.hole_lo[1] &&
+                          cell[1] < g.hole_hi[1] && cell[2] >= g.hole_lo[2] && cell[2] < g.hole_hi[2];
+            }
+            sqmask |= covered ? 0 : (1 << o);
+        }
+        if (xi[a] == pf) {
+            // coplanar limit: theta(x)/(4 pi) on the diagonal, pi/2 per emitting square
+            if (xi[0] == ll[0] && xi[1] == ll[1] && xi[2] == ll[2]) acc += (T)0.125 * (T)__builtin_popcount(sqmask);
+            continue;
+        }
+        const int d = (xi[a] - pf) * sign;
+        if (d <= 0) continue;
+        T ha = (T)0, hb2 = (T)0, hc2 = (T)0, as = (T)0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k == a) { ha = (T)g.h[k]; as = (T)g.area_scale[k]; }
+            if (k == b) hb2 = (T)(g.h[k] * g.h[k]);
+            if (k == cc) hc2 = (T)(g.h[k] * g.h[k]);
+        }
+        const T da = (T)d * ha;
+        const T da2 = da * da;
+        const T db = (T)(xi[b] - ll[b]), dc = (T)(xi[cc] - ll[cc]);
+        T s;
+        if (near)
+            s = tri_all_m<T, 7>(std::make_integer_sequence<int, kTris>{}, c.st.tri_near, sqmask, db, dc, da2, hb2, hc2);
+        else
+            s = tri_all_m<T, 3>(std::make_integer_sequence<int, kTris>{}, c.st.tri_far, sqmask, db, dc, da2, hb2, hc2);
+        acc += s * da * as;
+    }
+    return acc;
+}
+
 template <typename T, int NW = kAnyWalls>
 __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
     const GridDev &g = c.g;
@@ -544,17 +775,27 @@ __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
     vtx_index(g, l, ll);
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)ll[0], (T)ll[1], (T)ll[2]};
-    T S = exp(-tau_segment(g, c.kappa, P, Q)) * surf_quad(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
-    if constexpr (NW != kNoWall) {
-        const int nw = NW == kOneWall ? 1 : g.n_walls;
-        for (int w = 0; w < nw; ++w) {
+    if constexpr (NW == kAnyWalls) {
+        if (!vertex_active(g, ii)) return (T)0;   // a removed vertex
+        T att_w[6];
+        const T att = attenuations<T, NW>(g, c.kappa, ii, ll, P, Q, att_w);
+        T S = att == (T)0 ? (T)0 : att * surf_quad_rects(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
+        for (int w = 0; w < g.n_walls; ++w) {
+            if (att_w[w] == (T)0) continue;
             int mi[3];
             mirror_index(g, w, ii, mi);
-            S += (T)wall_info(g, w).R * exp(-tau_mirror(g, w, c.kappa, P, Q)) *
-                 surf_quad(c, mi, ll, cheb3(mi, ll) <= kNearCheb);
+            S += att_w[w] * surf_quad_rects(c, mi, ll, cheb3(mi, ll) <= kNearCheb);
         }
+        return S;
+    } else {
+        T S = exp(-tau_segment(g, c.kappa, P, Q)) * surf_quad(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
+        if constexpr (NW == kOneWall) {
+            int mi[3];
+            mirror_index(g, 0, ii, mi);
+            S += (T)g.R[0] * exp(-tau_mirror(g, 0, c.kappa, P, Q)) * surf_quad(c, mi, ll, cheb3(mi, ll) <= kNearCheb);
+        }
+        return S;
     }
-    return S;
 }
 
 template <typename T, int KIND, int NW = kAnyWalls>

@@ -253,6 +253,24 @@ const void *Mesh::near_table(bool fp64) const {
     return fp64 ? it->second.first : it->second.second;
 }
 
+// The emitting rectangles of a mesh: the emitting box faces, then the hole's
+// emitting faces; square index ranges [lo, hi) along the two other axes.
+std::vector<EmitRect> emit_rects(const rte_mesh_desc_t &d) {
+    std::vector<EmitRect> r;
+    for (int f = 0; f < 6; ++f) {
+        if (!((d.emit_faces >> f) & 1u)) continue;
+        const int a = f / 2, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+        r.push_back({a, (f & 1) ? d.n[a] - 1 : 0, (f & 1) ? -1 : 1, {0, 0}, {d.n[b] - 1, d.n[c] - 1}});
+    }
+    for (int f = 0; f < 6; ++f) {
+        if (!((d.hole_emit >> f) & 1u)) continue;
+        const int a = f / 2, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+        r.push_back({a, (f & 1) ? d.hole_hi[a] : d.hole_lo[a], (f & 1) ? 1 : -1, {d.hole_lo[b], d.hole_lo[c]},
+                     {d.hole_hi[b], d.hole_hi[c]}});
+    }
+    return r;
+}
+
 void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
     for (int a = 0; a < 3; ++a) {
         RTE_REQUIRE(d.n[a] >= 2, "mesh: every axis needs at least 2 vertices");
@@ -281,6 +299,24 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
         }
     for (auto &w : walls)
         RTE_REQUIRE(!((d.emit_faces >> w.first) & 1u), "mesh: a reflective face cannot also emit");
+    // the removed box of cells (all-zero fields: none)
+    const bool hole = d.hole_lo[0] < d.hole_hi[0] || d.hole_lo[1] < d.hole_hi[1] || d.hole_lo[2] < d.hole_hi[2];
+    if (hole) {
+        for (int a = 0; a < 3; ++a)
+            RTE_REQUIRE(0 <= d.hole_lo[a] && d.hole_lo[a] < d.hole_hi[a] && d.hole_hi[a] <= d.n[a] - 1,
+                        "mesh: the hole must be a non-empty box of cells inside the grid");
+        RTE_REQUIRE(d.hole_emit < 64u, "mesh: hole_emit has 6 bits");
+        for (int f = 0; f < 6; ++f)
+            if ((d.hole_emit >> f) & 1u) {
+                const int a = f / 2;
+                RTE_REQUIRE((f & 1) ? d.hole_hi[a] < d.n[a] - 1 : d.hole_lo[a] > 0,
+                            "mesh: an emitting hole face must lie inside the box");
+            }
+    } else {
+        for (int a = 0; a < 3; ++a)
+            RTE_REQUIRE(d.hole_lo[a] == 0 && d.hole_hi[a] == 0, "mesh: the hole must be a non-empty box of cells");
+        RTE_REQUIRE(d.hole_emit == 0u, "mesh: hole_emit without a hole");
+    }
     int64_t N = (int64_t)d.n[0] * d.n[1] * d.n[2];
     RTE_REQUIRE(N < (int64_t)1 << 31, "mesh: more than 2^31 vertices");
     M.desc = d;
@@ -289,12 +325,33 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
     M.near = std::make_shared<NearTables>();
     M.plans = new_plan_cache();
     M.near->host = make_near_table(M.h);
+    // the surface unknowns: corners of the emitting squares (a box-face square
+    // whose cell is a hole cell is covered and does not emit)
+    auto hole_cell = [&](const int c[3]) {
+        if (!hole) return false;
+        for (int a = 0; a < 3; ++a)
+            if (c[a] < d.hole_lo[a] || c[a] >= d.hole_hi[a]) return false;
+        return true;
+    };
+    std::vector<EmitRect> rects = emit_rects(d);
     M.emitting.clear();
     for (int64_t v = 0; v < N; ++v) {
         int idx[3] = {(int)(v / ((int64_t)d.n[1] * d.n[2])), (int)((v / d.n[2]) % d.n[1]), (int)(v % d.n[2])};
         bool on = false;
-        for (int f = 0; f < 6; ++f)
-            if ((d.emit_faces >> f) & 1u) on |= idx[f / 2] == ((f & 1) ? d.n[f / 2] - 1 : 0);
+        for (const EmitRect &r : rects) {
+            if (idx[r.a] != r.plane) continue;
+            const int b = r.a == 0 ? 1 : 0, c = r.a == 2 ? 1 : 2;
+            for (int o = 0; o < 4 && !on; ++o) {
+                const int sb = idx[b] - (o & 1), sc = idx[c] - (o >> 1);
+                if (sb < r.lo[0] || sb >= r.hi[0] || sc < r.lo[1] || sc >= r.hi[1]) continue;
+                int cell[3];
+                cell[r.a] = r.sign > 0 ? r.plane : r.plane - 1;
+                cell[b] = sb;
+                cell[c] = sc;
+                on = !hole_cell(cell);
+            }
+            if (on) break;
+        }
         if (on) M.emitting.push_back(v);
     }
     M.L = (int64_t)M.emitting.size();
@@ -322,6 +379,15 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
         g.R[k] = 0.0;
     }
     g.emit_faces = d.emit_faces;
+    g.has_hole = hole ? 1 : 0;
+    g.hole_open = 0u;
+    for (int a = 0; a < 3; ++a) {
+        g.hole_lo[a] = hole ? d.hole_lo[a] : 0;
+        g.hole_hi[a] = hole ? d.hole_hi[a] : 0;
+        if (hole && d.hole_lo[a] == 0) g.hole_open |= 1u << (2 * a);
+        if (hole && d.hole_hi[a] == d.n[a] - 1) g.hole_open |= 1u << (2 * a + 1);
+    }
+    g.hole_emit = hole ? d.hole_emit : 0u;
     const double four_pi = 4.0 * M_PI;
     g.vol_scale = M.h[0] * M.h[1] * M.h[2] / 6.0 / four_pi;
     g.area_scale[0] = 0.5 * M.h[1] * M.h[2] / four_pi;

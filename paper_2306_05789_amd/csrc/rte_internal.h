@@ -62,6 +62,10 @@ struct GridDev {
     int wall_side[6];       // 0: the plane at lo, 1: at hi
     double R[6];
     unsigned emit_faces;
+    int has_hole;           // non-convex domain: the cells [hole_lo, hole_hi) are removed
+    int hole_lo[3], hole_hi[3];
+    unsigned hole_open;     // bit 2a (2a+1): the hole reaches the box face at the low (high) end of axis a
+    unsigned hole_emit;     // bit f: the hole's face on side f%2 of axis f/2 emits
     double vol_scale;       // |tet| / (4 pi)
     double area_scale[3];   // |triangle| / (4 pi) for faces normal to axis a
 };
@@ -99,6 +103,14 @@ struct NearTables {
 };
 
 struct PlanCache;   // block-tree plans of a mesh (htree.cpp)
+
+// An emitting rectangle of the boundary: the plane x_a = plane (grid index),
+// the normal into the domain sign * e_a, square index ranges [lo, hi) along
+// the two other axes b < c.
+struct EmitRect {
+    int a, plane, sign, lo[2], hi[2];
+};
+std::vector<EmitRect> emit_rects(const rte_mesh_desc_t &d);   // box faces, then the hole's
 
 struct Mesh {
     rte_mesh_desc_t desc{};

@@ -4,11 +4,13 @@ This module only draws and lays out inputs (grids, absorption fields, band
 frequencies, wall temperatures, request streams).  It holds none of the
 method's arithmetic and imports nothing from the GPU library or the oracle.
 
-The paper's own workloads (the Kobayashi-type box with an inner cube, the
-Chamonix valley terrain, the Gemini absorption spectra) are not available, so
-box-shaped grids with smooth analytic absorption fields stand in for them, at
-vertex counts inside the range of the paper's table (2.7K to 196K vertices)
-and optical thicknesses from about 0.1 to 10 per unit length.
+The academic test's geometry (a box with an inner cube, three reflective
+planes, a low-absorption cylinder) is written out from the paper's description
+(`academic`).  The paper's other workloads (the Chamonix valley terrain, the
+Gemini absorption spectra) are not available, so box-shaped grids with smooth
+analytic absorption fields stand in for them, at vertex counts inside the
+range of the paper's table (2.7K to 196K vertices) and optical thicknesses
+from about 0.1 to 10 per unit length.
 """
 from __future__ import annotations
 
@@ -59,6 +61,47 @@ class Workload:
     @property
     def bands(self) -> int:
         return int(self.kappa.shape[0])
+
+
+@dataclass
+class Academic:
+    """The geometry of the paper's academic test (Section "An Academic Test",
+    Test-3): the box D = (0,60) x (0,100) x (0,60) (cm) minus the cube
+    C = [0,10]^3 in the corner where the three reflective planes through the
+    origin (R = 1) meet; C's three faces inside D emit, D's outer faces absorb
+    and do not emit; kappa = 1e-4 in the cylinder (0,10) x (10,100) x (0,10)
+    that prolongs C and 0.1 elsewhere (per cm; at the vertices: 1e-4 on the
+    closed cylinder, the P1 interpolant in between); grey, no scattering.
+    Spacing h (cm, a divisor of 10): h = 5, 2.5, 5/3, 1.25 give 3.5K, 25.6K,
+    83.5K and 194K vertices, next to the paper's 2.8K to 196K meshes."""
+    h: float
+    n: tuple
+    lo: tuple
+    hi: tuple
+    kappa: np.ndarray        # [N], natural order
+    hole: tuple              # ((0, 0, 0), (m, m, m)), m = 10 / h cells
+    hole_emit: int           # the hole's faces x = 10, y = 10, z = 10
+    walls: list              # the planes x = 0, y = 0, z = 0, R = 1
+    emit_faces: int = 0
+    T_hole: float = 1.0      # temperature of the emitting faces (grey source sigma T^4)
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+
+def academic(h: float = 2.5) -> Academic:
+    m = 10.0 / h
+    assert abs(m - round(m)) < 1e-9, "h must divide 10"
+    m = int(round(m))
+    n = (6 * m + 1, 10 * m + 1, 6 * m + 1)
+    lo, hi = (0.0, 0.0, 0.0), (60.0, 100.0, 60.0)
+    pos = grid_positions(n, lo, hi)
+    eps = 1e-9 * h
+    cyl = (pos[:, 0] <= 10.0 + eps) & (pos[:, 1] >= 10.0 - eps) & (pos[:, 2] <= 10.0 + eps)
+    kappa = np.where(cyl, 1e-4, 0.1)
+    return Academic(h, n, lo, hi, kappa, ((0, 0, 0), (m, m, m)), FACE_X_HI | FACE_Y_HI | FACE_Z_HI,
+                    [(0, 0, 1.0), (1, 0, 1.0), (2, 0, 1.0)])
 
 
 def n_emitting(n, emit_faces) -> int:

@@ -8,7 +8,7 @@ import re
 import numpy as np
 import pytest
 
-from oracle.core import Grid
+from oracle.core import Grid, Problem
 from oracle.htree import block_tree, cluster_tree
 from paper_2306_05789_amd import rte
 
@@ -82,8 +82,27 @@ def test_mesh_sizes_and_emitting_ids():
     assert np.array_equal(rte.rte_mesh_emitting_ids(mesh), g.emitting_vertices(1 | 32))
 
 
+@pytest.mark.parametrize("emit,hole,hole_emit", [
+    (0, ((2, 2, 2), (5, 5, 5)), 63),          # a hole inside the box, every face emitting
+    (1 | 32, ((0, 1, 2), (2, 4, 6)), 2 | 8),  # reaching the faces x = 0 and z = 1: covered squares
+    (2 | 8 | 32, ((0, 0, 0), (2, 2, 2)), 2 | 8 | 32),   # the academic test's corner cube
+])
+def test_emitting_ids_with_a_hole_match_oracle(emit, hole, hole_emit):
+    n = (8, 7, 7)
+    mesh = rte.rte_mesh_create(n, emit_faces=emit, hole=hole, hole_emit=hole_emit)
+    g = Grid(n)
+    P = Problem(g, np.ones(g.N), emit_faces=emit, hole=hole, hole_emit=hole_emit)
+    assert np.array_equal(rte.rte_mesh_emitting_ids(mesh), P.emitting)
+    assert mesh.L == len(P.emitting)
+
+
 @pytest.mark.parametrize("kw,frag", [
     (dict(n=(1, 4, 4)), "at least 2"),
+    (dict(n=(6, 6, 6), hole=((1, 1, 1), (1, 3, 3))), "non-empty box"),
+    (dict(n=(6, 6, 6), hole=((1, 1, 1), (3, 3, 6))), "non-empty box"),
+    (dict(n=(6, 6, 6), hole=((0, 1, 1), (3, 3, 3)), hole_emit=1), "inside the box"),
+    (dict(n=(6, 6, 6), hole=((1, 1, 1), (3, 3, 5)), hole_emit=32), "inside the box"),
+    (dict(n=(6, 6, 6), hole_emit=2), "without a hole"),
     (dict(n=(4, 4, 4), hi=(0, 1, 1)), "lo < hi"),
     (dict(n=(4, 4, 4), reflect_axis=3), "reflect_axis"),
     (dict(n=(4, 4, 4), reflect_axis=2, R=1.5), "R must"),
