@@ -117,3 +117,22 @@ def truncated_svd(eps: float):
 def full_rank(A):
     """factor(A) = (A, I): the low-rank form of a block that loses nothing."""
     return A.copy(), np.eye(A.shape[1])
+
+
+def recompress(U, V, eps: float):
+    """The shortest truncation of the SVD of U V^T whose relative Frobenius error
+    is <= eps (at least rank 1): the recompression of an ACA block's factors
+    (Section "Compression": the ACA approximates the first terms of a block's
+    SVD; its factors are not orthogonal and usually longer than the SVD needs).
+    Written as the definition: U = Qu Ru and V = Qv Rv (QR), the SVD of the
+    small Ru Rv^T = W S Z^T, then U' = Qu W_r S_r and V' = Qv Z_r."""
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    Qu, Ru = np.linalg.qr(U)
+    Qv, Rv = np.linalg.qr(V)
+    w, sv, zt = np.linalg.svd(Ru @ Rv.T)
+    tail = np.sqrt(np.cumsum((sv ** 2)[::-1])[::-1])      # tail[r] = ||s[r:]||
+    total = tail[0] if len(sv) else 0.0
+    r = next((r for r in range(1, len(sv) + 1) if r == len(sv) or tail[r] <= eps * total), len(sv))
+    return Qu @ (w[:, :r] * sv[:r]), Qv @ zt[:r].T, sv
+

@@ -110,3 +110,51 @@ def test_dropped_or_doubled_block_is_detected(reflect9):
     swapped = hmatrix.HOperator(H.src_perm[::-1].copy(), H.src_perm, H.dense, H.lowrank)
     for bad in (drop, twice, swapped):
         assert np.max(np.abs(bad @ x - G @ x) / H.abs_matvec(x)) > 1e-6
+
+
+# ---------------------------------------------------------------- recompression of low-rank factors
+
+def _factors(rng, m, n, k, decay):
+    """Factors of a k-term product whose terms fall off like decay^l, with
+    non-orthogonal columns (as the ACA's are)."""
+    U = rng.standard_normal((m, k)) * decay ** np.arange(k)
+    V = rng.standard_normal((n, k)) + 0.3 * rng.standard_normal((n, 1))
+    return U, V
+
+
+def test_recompression_is_the_truncated_svd_of_the_product():
+    """Eckart-Young: the recompressed product is the best approximation of U V^T
+    of its rank, the dense truncated SVD of the product (same rank, same matrix)."""
+    rng = np.random.default_rng(31)
+    cut = 0
+    for m, n, k in ((120, 90, 30), (64, 200, 41), (300, 300, 12)):
+        U, V = _factors(rng, m, n, k, 0.6)
+        A = U @ V.T
+        for eps in (1e-5, 1e-3):
+            Ur, Vr, _ = hmatrix.recompress(U, V, eps)
+            Ud, Vd = hmatrix.truncated_svd(eps)(A)
+            assert Ur.shape[1] == Ud.shape[1] <= k
+            cut += Ur.shape[1] < k
+            assert np.linalg.norm(Ur @ Vr.T - Ud @ Vd.T) < 1e-12 * np.linalg.norm(A)
+    assert cut >= 4
+
+
+def test_recompression_error_is_the_dropped_tail():
+    """||U V^T - U' V'^T||_F equals the norm of the dropped singular values and
+    stays within eps of ||U V^T||_F; a product of planted rank r is recompressed
+    to rank r exactly."""
+    rng = np.random.default_rng(32)
+    U, V = _factors(rng, 150, 110, 40, 0.7)
+    A = U @ V.T
+    Ur, Vr, sv = hmatrix.recompress(U, V, 1e-4)
+    r = Ur.shape[1]
+    err = np.linalg.norm(A - Ur @ Vr.T)
+    assert abs(err - np.linalg.norm(sv[r:])) < 1e-10 * np.linalg.norm(A)
+    assert err <= 1e-4 * np.linalg.norm(A)
+    assert np.linalg.norm(sv[r - 1:]) > 1e-4 * np.linalg.norm(A)     # the shortest such
+    # planted rank: 40 columns spanning a 9-dimensional space
+    B = rng.standard_normal((150, 9)) @ rng.standard_normal((9, 40))
+    Ur, Vr, _ = hmatrix.recompress(B, V, 1e-10)
+    assert Ur.shape[1] == 9
+    assert np.linalg.norm(B @ V.T - Ur @ Vr.T) < 1e-12 * np.linalg.norm(B @ V.T)
+
