@@ -74,8 +74,12 @@ struct LeafWork {
 // BF16 (matrix-core) phase A task: up to kMfTiles 16-rank tiles over one chunk
 // of stored source rows.  The tiles may come from different low-rank blocks
 // whose V covers the same chunk (blocks of one source cluster are chunked
-// alike), so the x operand loaded for a step serves all of them.
-constexpr int kMfTiles = 4;
+// alike), so the x operand loaded for a step serves all of them.  The low
+// operator takes up to 8 tiles per task (its x operand, 64 bytes per source
+// row, then costs a quarter of the 256 bytes of V); the accurate operator,
+// with twice the operand registers per tile, takes up to 4, from a task list
+// of its own.
+constexpr int kMfTiles = 8;
 struct MfTile {
     const uint16_t *V, *Vlo;   // first 8-row group of the chunk in the block's V [nP/8][k][8]
     int64_t out;               // direct: offset of t_b in the t splits; else partial-sum offset of the chunk
@@ -96,6 +100,9 @@ struct MfRed {
 
 struct MatvecPlan {
     DevBuf vt, seg, leaf, red;
+    DevBuf vt4;                // matrix cores with 8-tile tasks: the accurate operator's list (at most 4)
+    int64_t n_vt4 = 0;
+    int tiles = 4;             // matrix cores: most tiles in a task of `vt`
     int64_t n_vt = 0, n_leaf = 0, ktot = 0, n_red = 0, n_red_threads = 0, npart = 0;
     int64_t n_src = 0, n_tgt = 0;
     int max_rows = 0;
@@ -529,20 +536,20 @@ __global__ void k_mf_xstage(const int64_t *__restrict__ pmap, int64_t np, int nb
     xs[2 * xsplit + k] = l;
 }
 
-template <int MODE>
+template <int MODE, int NT = 4>
 struct MfOps {
     // operand splits used: the accurate operator carries the vector in three
     // BF16 parts (24 significant bits), the low operator in two (16 bits).
     // With the hi part alone the inner sweeps stall at the BF16 rounding of
     // the source change (measured: a mixed solve to 1e-9 no longer converged).
     static constexpr int NS = MODE == kMatvecAccurate ? 3 : 2;
-    bf16x8 bx[NS], a[4], al[4];
+    bf16x8 bx[NS], a[NT], al[MODE == kMatvecAccurate ? NT : 1];
 };
 
-template <int MODE>
-__device__ __forceinline__ void mf_products(const MfOps<MODE> &o, int nt, f32x4 acc[4], double a64[4][4]) {
+template <int MODE, int NT = 4>
+__device__ __forceinline__ void mf_products(const MfOps<MODE, NT> &o, int nt, f32x4 acc[NT], double a64[NT][4]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NT; ++t) {
         if (t < nt) {
             if constexpr (MODE == kMatvecLow) {
                 acc[t] = mfma(o.a[t], o.bx[0], acc[t]);
@@ -570,10 +577,10 @@ struct MfSrc {
 };
 
 // Resources and geometry of one phase A task: per tile its block's V.
-template <int MODE>
+template <int MODE, int NT>
 struct MfSrcA {
-    rsrc_t a[kMfTiles], al[kMfTiles], x[3];
-    int k[kMfTiles], kt0[kMfTiles];
+    rsrc_t a[NT], al[MODE == kMatvecAccurate ? NT : 1], x[3];
+    int k[NT], kt0[NT];
     int ngr, nt;
 };
 
@@ -587,11 +594,11 @@ struct MfSrcA {
 // a one-chunk block writes its t splits (zero padding up to pad8(k)
 // included) directly; tiles of larger blocks leave FP64 partials for
 // k_mf_tstage.
-template <int MODE>
-__device__ __forceinline__ MfSrcA<MODE> mf_src_a(const MfVt &tk, const uint16_t *xs, int64_t xsplit, int64_t np) {
-    MfSrcA<MODE> r;
+template <int MODE, int NT>
+__device__ __forceinline__ MfSrcA<MODE, NT> mf_src_a(const MfVt &tk, const uint16_t *xs, int64_t xsplit, int64_t np) {
+    MfSrcA<MODE, NT> r;
 #pragma unroll
-    for (int t = 0; t < kMfTiles; ++t) {
+    for (int t = 0; t < NT; ++t) {
         const MfTile &tl = tk.tile[t < tk.nt ? t : 0];
         const int vbytes = tk.ng * tl.k * 16;
         r.a[t] = make_rsrc(tl.V, vbytes);
@@ -607,14 +614,15 @@ __device__ __forceinline__ MfSrcA<MODE> mf_src_a(const MfVt &tk, const uint16_t 
     return r;
 }
 
-template <int MODE>
-__device__ __forceinline__ void mf_load_a(const MfSrcA<MODE> &r, int g0, bool valid, int c, int q, MfOps<MODE> &o) {
+template <int MODE, int NT>
+__device__ __forceinline__ void mf_load_a(const MfSrcA<MODE, NT> &r, int g0, bool valid, int c, int q,
+                                          MfOps<MODE, NT> &o) {
     const int g = g0 + q;
     const int xo = valid ? (g * 16 + c) * 16 : kOOB;
 #pragma unroll
-    for (int sp = 0; sp < MfOps<MODE>::NS; ++sp) o.bx[sp] = bload(r.x[sp], xo);
+    for (int sp = 0; sp < MfOps<MODE, NT>::NS; ++sp) o.bx[sp] = bload(r.x[sp], xo);
 #pragma unroll
-    for (int t = 0; t < kMfTiles; ++t) {
+    for (int t = 0; t < NT; ++t) {
         const int rk = r.kt0[t] + c;
         const int off = valid && t < r.nt && rk < r.k[t] ? (g * r.k[t] + rk) * 16 : kOOB;
         o.a[t] = bload(r.a[t], off);
@@ -622,11 +630,11 @@ __device__ __forceinline__ void mf_load_a(const MfSrcA<MODE> &r, int g0, bool va
     }
 }
 
-template <int MODE>
-__device__ __forceinline__ void mf_finish_a(const MfVt &tk, int c, int q, const f32x4 acc[4], const double a64[4][4],
+template <int MODE, int NT>
+__device__ __forceinline__ void mf_finish_a(const MfVt &tk, int c, int q, const f32x4 acc[NT], const double a64[NT][4],
                                             double *part, int64_t ldp, uint16_t *ts, int64_t tsplit, int r0, int nr) {
 #pragma unroll
-    for (int t = 0; t < kMfTiles; ++t) {
+    for (int t = 0; t < NT; ++t) {
         if (t < tk.nt) {
             const MfTile &tl = tk.tile[t];
             if (tl.direct) {   // uniform: the tile's block is one chunk, its t splits are written here
@@ -686,7 +694,7 @@ __device__ __forceinline__ int64_t xcd_runs(int64_t b, int64_t G) {
     return ((q / R) * 8 + x) * R + q % R;
 }
 
-template <int MODE>
+template <int MODE, int NT>
 __global__ __launch_bounds__(256) void k_mf_phase_a(const MfVt *__restrict__ tasks, int64_t ntask, int64_t nw,
                                                     const uint16_t *__restrict__ xs, int64_t xsplit, int64_t np,
                                                     double *__restrict__ part, int64_t ldp, uint16_t *__restrict__ ts,
@@ -695,40 +703,40 @@ __global__ __launch_bounds__(256) void k_mf_phase_a(const MfVt *__restrict__ tas
     int64_t ti = xcd_runs<8>(blockIdx.x, gridDim.x) * 4 + wave;
     if (ti >= ntask) return;
     const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4;
-    f32x4 acc[4];
-    double a64[4][4];
+    f32x4 acc[NT];
+    double a64[NT][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
     // pipeline state: the task of the operands being consumed, and the next
     int64_t cur = ti;     // task being consumed
-    MfSrcA<MODE> rl = mf_src_a<MODE>(tasks[ti], xs, xsplit, np);
+    MfSrcA<MODE, NT> rl = mf_src_a<MODE, NT>(tasks[ti], xs, xsplit, np);
     int g0 = 0, ngc = rl.ngr, ntc = rl.nt;
-    MfOps<MODE> o0, o1;   // two operand sets in turn (named: an indexed pair would live in scratch)
-    mf_load_a<MODE>(rl, 0, true, c, q, o0);
+    MfOps<MODE, NT> o0, o1;   // two operand sets in turn (named: an indexed pair would live in scratch)
+    mf_load_a<MODE, NT>(rl, 0, true, c, q, o0);
     int64_t tl = ti;      // task of the last issued load
     int gl = 0;
     bool done = false;
     // issue the loads of the step after (tl, gl) into `nx`, then the products of
     // `cu`; the loads run one step ahead, so when a task's last step is consumed
     // the next task is the one the loads have just moved to
-    auto step = [&](const MfOps<MODE> &cu, MfOps<MODE> &nx) {
+    auto step = [&](const MfOps<MODE, NT> &cu, MfOps<MODE, NT> &nx) {
         int gn = gl + 4;
         int64_t tn = tl;
         if (gn >= rl.ngr) {
             tn = tl + nw;
             gn = 0;
-            if (tn < ntask) rl = mf_src_a<MODE>(tasks[tn], xs, xsplit, np);
+            if (tn < ntask) rl = mf_src_a<MODE, NT>(tasks[tn], xs, xsplit, np);
         }
         // past the end: the same loads at out-of-range offsets (zeros)
-        mf_load_a<MODE>(rl, gn, tn < ntask, c, q, nx);
-        mf_products<MODE>(cu, ntc, acc, a64);
+        mf_load_a<MODE, NT>(rl, gn, tn < ntask, c, q, nx);
+        mf_products<MODE, NT>(cu, ntc, acc, a64);
         g0 += 4;
         if (g0 >= ngc) {
-            mf_finish_a<MODE>(tasks[cur], c, q, acc, a64, part, ldp, ts, tsplit, r0, nr);
+            mf_finish_a<MODE, NT>(tasks[cur], c, q, acc, a64, part, ldp, ts, tsplit, r0, nr);
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) { acc[t][v] = 0.0f; a64[t][v] = 0.0; }
             cur += nw;
@@ -1028,10 +1036,23 @@ void launch_mf(const MatvecPlan &mp, int nrhs, const double *x, const double *y0
         HIP_LAUNCH_CHECK();
         if (mp.n_vt) {
             // the resident wavefronts, each walking a strided task list
-            static const int64_t resident = resident_workgroups(k_mf_phase_a<MODE>, 256);
-            const int64_t nwg = std::min<int64_t>((mp.n_vt + 3) / 4, resident);
-            k_mf_phase_a<MODE><<<(unsigned)nwg, 256, 0, s>>>(mp.vt.as<MfVt>(), mp.n_vt, nwg * 4, xs, xsplit, mp.np,
-                                                             part, ldp, ts, tsplit, r0, nr);
+            auto phase_a = [&](auto kernel, const MfVt *tasks, int64_t ntask) {
+                static const int64_t resident = resident_workgroups(kernel, 256);
+                const int64_t nwg = std::min<int64_t>((ntask + 3) / 4, resident);
+                kernel<<<(unsigned)nwg, 256, 0, s>>>(tasks, ntask, nwg * 4, xs, xsplit, mp.np, part, ldp, ts, tsplit,
+                                                     r0, nr);
+            };
+            bool eight = false;
+            if constexpr (MODE == kMatvecLow) {
+                if (mp.tiles == 8) {
+                    phase_a(k_mf_phase_a<MODE, 8>, mp.vt.as<MfVt>(), mp.n_vt);
+                    eight = true;
+                }
+            }
+            if (!eight) {
+                if (mp.n_vt4) phase_a(k_mf_phase_a<MODE, 4>, mp.vt4.as<MfVt>(), mp.n_vt4);
+                else phase_a(k_mf_phase_a<MODE, 4>, mp.vt.as<MfVt>(), mp.n_vt);
+            }
             HIP_LAUNCH_CHECK();
             if (mp.n_red) {
                 k_mf_tstage<<<(unsigned)mp.n_red, 256, 0, s>>>(mp.red.as<MfRed>(), part, ldp, ts, tsplit, r0, nr);
@@ -1198,22 +1219,31 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
         for (size_t i = 0; i < key.size(); ++i) sorted[i] = vt[key[i].second];
         vt.swap(sorted);
     }
-    // tasks of up to `tiles` tiles of one chunk (in block order)
-    for (auto &kv : mtiles) {
-        const std::vector<MfTile> &grp = kv.second;
-        for (size_t i = 0; i < grp.size(); i += (size_t)tiles) {
-            MfVt t{};
-            t.nt = (int32_t)std::min<size_t>((size_t)tiles, grp.size() - i);
-            for (int j = 0; j < t.nt; ++j) t.tile[j] = grp[i + j];
-            t.xoff = std::get<1>(kv.first);
-            t.ng = (int32_t)(std::get<2>(kv.first) / 8);
-            t.band = std::get<0>(kv.first);
-            mvt.push_back(t);
+    // tasks of up to `per` tiles of one chunk (in block order), large first
+    auto group_tasks = [&](int per) {
+        std::vector<MfVt> out;
+        for (auto &kv : mtiles) {
+            const std::vector<MfTile> &grp = kv.second;
+            for (size_t i = 0; i < grp.size(); i += (size_t)per) {
+                MfVt t{};
+                t.nt = (int32_t)std::min<size_t>((size_t)per, grp.size() - i);
+                for (int j = 0; j < t.nt; ++j) t.tile[j] = grp[i + j];
+                t.xoff = std::get<1>(kv.first);
+                t.ng = (int32_t)(std::get<2>(kv.first) / 8);
+                t.band = std::get<0>(kv.first);
+                out.push_back(t);
+            }
         }
+        std::stable_sort(out.begin(), out.end(), [](const MfVt &a, const MfVt &b) {
+            return (int64_t)a.ng * a.nt > (int64_t)b.ng * b.nt;
+        });
+        return out;
+    };
+    std::vector<MfVt> mvt4;
+    if (mf) {
+        mvt = group_tasks(tiles);
+        if (tiles > 4) mvt4 = group_tasks(4);   // the accurate operator's list
     }
-    std::stable_sort(mvt.begin(), mvt.end(), [](const MfVt &a, const MfVt &b) {
-        return (int64_t)a.ng * a.nt > (int64_t)b.ng * b.nt;
-    });
     mp->ktot = std::max<int64_t>(ktot, mf ? 8 : 1);
     mp->npart = npart;
     mp->n_red_threads = maxk;
@@ -1227,6 +1257,11 @@ std::unique_ptr<MatvecPlan> build_plan(const HMat &H, const std::vector<int> &ba
         mp->n_red = (int64_t)mred.size();
         mp->vt = upload(mvt, s);
         mp->red = upload(mred, s);
+        mp->tiles = tiles;
+        if (!mvt4.empty()) {
+            mp->n_vt4 = (int64_t)mvt4.size();
+            mp->vt4 = upload(mvt4, s);
+        }
     } else {
         mp->n_vt = (int64_t)vt.size();
         mp->n_red = (int64_t)red.size();
@@ -1278,7 +1313,8 @@ void matvec_configure(HMat &H, const MatvecConfig &cfg, hipStream_t s) {
     RTE_REQUIRE(cfg.waves_b == 2 || cfg.waves_b == 4 || cfg.waves_b == 8, "matvec config: waves must be 2, 4 or 8");
     RTE_REQUIRE(mf || cfg.waves_b >= 4, "matvec config: the vector-ALU path takes 4 or 8 waves");
     RTE_REQUIRE(cfg.task_kib >= 4 && cfg.task_kib <= 4096, "matvec config: task size out of range");
-    RTE_REQUIRE(cfg.tiles == 1 || cfg.tiles == 2 || cfg.tiles == 4, "matvec config: tiles must be 1, 2 or 4");
+    RTE_REQUIRE(cfg.tiles == 1 || cfg.tiles == 2 || cfg.tiles == 4 || cfg.tiles == 8,
+                "matvec config: tiles must be 1, 2, 4 or 8");
     H.cfg = cfg;
     for (int b = 0; b < H.n_bands; ++b) matvec_build(H, b, s);
     matvec_build_all(H, s);
@@ -1312,7 +1348,7 @@ MatvecConfig matvec_autotune(HMat &H, int nrhs, int mode, int reps, hipStream_t 
     const bool mf = H.precision == RTE_MIXED_BF16;
     const std::vector<int> waves = mf ? std::vector<int>{2, 4, 8} : std::vector<int>{4, 8};
     const std::vector<int> kib = {16, 64, 256};
-    const std::vector<int> tiles = mf ? std::vector<int>{2, 4} : std::vector<int>{4};
+    const std::vector<int> tiles = mf ? std::vector<int>{4, 8} : std::vector<int>{4};
     MatvecConfig best = H.cfg;
     double bt = INFINITY;
     int n = 0;

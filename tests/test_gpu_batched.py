@@ -194,6 +194,19 @@ def test_autotuner_picks_a_shape_and_results_hold(small, precision, tmp_path):
             rte.rte_hmat_set_config(G, r["config"])
             rte.rte_hmat_matvec_batched(G, x, ya, rte.RTE_OP_LOW)
             assert (torch.max(torch.abs(ya - yb) / torch.abs(ya))).item() < 1e-5
+    if precision == rte.RTE_MIXED_BF16:
+        # 8 tiles per phase-A task (low operator; the accurate one keeps tasks of 4):
+        # every tile sums over the same steps in the same order, so both products
+        # are bitwise those of 4-tile tasks
+        outs = []
+        for t in (4, 8):
+            rte.rte_hmat_set_config(G, {"phase_b_waves": 8, "phase_a_kib": 256, "phase_a_tiles": t})
+            yl, ya = torch.empty_like(x), torch.empty_like(x)
+            rte.rte_hmat_matvec_batched(G, x, yl, rte.RTE_OP_LOW)
+            rte.rte_hmat_matvec_batched(G, x, ya, rte.RTE_OP_ACCURATE)
+            outs.append((yl, ya))
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+        rte.rte_hmat_set_config(G, r["config"])
     # a second run of the same shape takes the cached choice without timing
     G2 = _assemble(mesh, wl, rte.RTE_VOLUME, precision)
     r2 = tune.autotune(G2, nrhs=16, cache=cache, reps=2)
