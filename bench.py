@@ -170,7 +170,8 @@ def _say(msg):
 
 
 def _hstats(st, keys=("assemble_ms", "aca_kernel_ms", "aca_entry_ms", "fill_kernel_ms", "bytes", "compression",
-                      "mean_rank", "max_rank", "n_lowrank", "n_fallback_dense")):
+                      "mean_rank", "max_rank", "n_lowrank", "n_fallback_dense", "lowrank_entries",
+                      "lowrank_entries_aca", "recompress_ms")):
     return {k: st[k] for k in keys}
 
 
@@ -470,11 +471,13 @@ def run_headline(args):
     Tw = torch.tensor(wl.T_wall, device=dev)
     nrhs, nb = int(Tw.shape[0]), wl.bands
     p = rte.RTE_MIXED_BF16
-    G, S, wall_ms = _assemble_pair(rte, mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, precision=p),
-                                   rte.hmat_opts(kind=rte.RTE_SURFACE, precision=p))
+    rc = not args.no_recompress
+    G, S, wall_ms = _assemble_pair(rte, mesh, kap, rte.hmat_opts(kind=rte.RTE_VOLUME, precision=p, recompress=rc),
+                                   rte.hmat_opts(kind=rte.RTE_SURFACE, precision=p, recompress=rc))
     gs, ss = rte.rte_hmat_stats(G), rte.rte_hmat_stats(S)
-    _say(f"assembly: G {gs['assemble_ms']:.0f} ms ({gs['bytes'] / 1e9:.1f} GB), S {ss['assemble_ms']:.0f} ms "
-         f"({ss['bytes'] / 1e9:.1f} GB), concurrently {wall_ms:.0f} ms")
+    _say(f"assembly: G {gs['assemble_ms']:.0f} ms ({gs['bytes'] / 1e9:.1f} GB; recompression {gs['recompress_ms']:.0f} "
+         f"ms, low-rank entries {gs['lowrank_entries_aca'] / 1e9:.2f} -> {gs['lowrank_entries'] / 1e9:.2f} G), "
+         f"S {ss['assemble_ms']:.0f} ms ({ss['bytes'] / 1e9:.1f} GB), concurrently {wall_ms:.0f} ms")
     T = torch.empty((nrhs, mesh.N), device=dev, dtype=torch.float64)
 
     def solve():
@@ -532,7 +535,8 @@ def run_headline(args):
         "data": "synthetic",
         "config": {"workload": "cube49_32band_16rhs_mixed", "N": mesh.N, "L": mesh.L, "bands": nb, "nrhs": nrhs,
                    "leaf_size": wl.leaf_size, "eta": wl.eta, "aca_eps": wl.aca_eps, "tol": wl.tol,
-                   "precision": "mixed", "step": "one 16-RHS fixed-point solve on resident operators"},
+                   "precision": "mixed", "recompress": rc,
+                   "step": "one 16-RHS fixed-point solve on resident operators"},
         "roofline": roof,
         "hmatvec": {"low": {"ms": per_low, "bytes": bytes_low, "GB_s": gbs_low, "frac": gbs_low / HBM_PEAK_GBS},
                     "accurate": {"ms": per_acc, "bytes": bytes_acc, "GB_s": gbs_acc,
@@ -855,7 +859,8 @@ def run_matvec(args):
     wl = inputs.batched()
     mesh = rte.rte_mesh_create(wl.n, emit_faces=wl.emit_faces)
     G = rte.rte_hmat_assemble(mesh, torch.tensor(wl.kappa, device="cuda:0"),
-                              rte.hmat_opts(kind=rte.RTE_VOLUME, precision=rte.RTE_MIXED_BF16))
+                              rte.hmat_opts(kind=rte.RTE_VOLUME, precision=rte.RTE_MIXED_BF16,
+                                            recompress=not args.no_recompress))
     st = rte.rte_hmat_stats(G)
     _say(f"assembled in {st['assemble_ms']:.0f} ms")
     a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
@@ -883,6 +888,8 @@ def main():
     ap.add_argument("--n", type=int, default=41, help="cube41 workload: vertices per axis of the cube")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline: skip the FP64 share, 41^3 and 11^3 legs")
+    ap.add_argument("--no-recompress", action="store_true",
+                    help="headline and matvec workloads: keep the ACA factors (no SVD recompression)")
     ap.add_argument("--workload", default="headline",
                     choices=("headline", "cube41", "reflective", "batched", "served", "matvec", "academic"))
     ap.add_argument("--h", type=float, default=2.5, help="academic workload: grid spacing in cm (divides 10)")

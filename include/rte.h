@@ -109,7 +109,11 @@ void rte_mesh_destroy(rte_mesh_t mesh);
  * Section "Compression": cluster tree by geometric bisection (leaf_size),
  * admissibility max(R1,R2) < eta * dist(box1, box2), partially pivoted ACA
  * with relative Frobenius tolerance aca_eps.  dense = 1 stores every block
- * dense (no compression). */
+ * dense (no compression).  recompress = 1: the factors of every block the ACA
+ * compressed (ranks up to 192) are replaced by the shortest truncation of the
+ * SVD of their product whose relative Frobenius error is <= aca_eps (a block
+ * whose factors are numerically dependent, or that would not get shorter,
+ * keeps them); the error against the ACA product adds at most aca_eps. */
 typedef struct {
     int32_t kind;        /* rte_kind_t: RTE_VOLUME (N x N matrix G) or RTE_SURFACE (N x L matrix S) */
     int32_t dense;
@@ -117,6 +121,7 @@ typedef struct {
     double eta;          /* > 0 */
     double aca_eps;      /* in (0,1) */
     int32_t precision;   /* rte_precision_t */
+    int32_t recompress;  /* 0 or 1 */
 } rte_hmat_opts_t;
 
 /* ------------------------------------------------------------------ plan (host only)
@@ -156,7 +161,9 @@ rte_status_t rte_entries(rte_mesh_t mesh, int32_t kind, const double *kappa, int
 rte_status_t rte_hmat_assemble(rte_mesh_t mesh, int32_t n_bands, const double *kappa,
                                const rte_hmat_opts_t *opts, void *stream, rte_hmat_t *out);
 
-/* y = H_band x for nrhs right-hand sides.  x: device [nrhs][N_src] FP64 (surface:
+/* y = H_band x for nrhs right-hand sides (Section "Compression": once the
+ * matrix is compressed, the fixed-point iterations only need such products;
+ * dense leaves contribute A x, admissible blocks U (V^T x)).  x: device [nrhs][N_src] FP64 (surface:
  * N_src = L, emitting vertices in ascending id order); y: device [nrhs][N_tgt].
  * Natural order on both sides.  Stored precision as assembled; FP64 accumulate
  * for FP64 storage, FP32 accumulate otherwise, results returned in FP64. */
@@ -197,8 +204,9 @@ rte_status_t rte_hmat_matvec_batched(rte_hmat_t h, int32_t nrhs, const double *x
 /* Launch shape of the matvec of one H-matrix: wavefronts per phase-B
  * workgroup (one workgroup per target leaf and band; matrix cores: 2, 4 or 8,
  * vector ALU: 4 or 8), bytes of V per phase-A task (KiB), and 16-rank tiles
- * per phase-A task on the matrix cores (1, 2 or 4; the rank bucket a task
- * covers).  Changing it rebuilds the work lists and regroups partial sums:
+ * per phase-A task on the matrix cores (1, 2, 4 or 8; the rank bucket a task
+ * covers; with 8 the accurate operator still takes tasks of at most 4).
+ * Changing it rebuilds the work lists and regroups partial sums:
  * results agree to rounding (FP32 accumulation: ~1e-7, FP64: ~1e-15). */
 typedef struct {
     int32_t phase_b_waves;
@@ -245,6 +253,9 @@ typedef struct {
                                                      during the assembly, summed over its threads */
     int64_t free_bytes;                           /* device memory free when the assembly started (including
                                                      the library's idle scratch pool) */
+    int64_t lowrank_entries_aca;                  /* lowrank_entries before the recompression (equal without it) */
+    int64_t recompressed_blocks;                  /* blocks the recompression examined, summed over bands */
+    double recompress_ms;                         /* HIP-event time of the recompression, summed over bands */
 } rte_hmat_stats_t;
 
 rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats);

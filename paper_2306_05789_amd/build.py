@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librte.so")
 
 SOURCES = ["quadrule.cpp", "mesh.cpp", "htree.cpp", "abi.cpp", "pool.cpp",
-           "entry.hip", "aca.hip", "hmatvec.hip", "solver.hip", "serve.hip"]
+           "entry.hip", "aca.hip", "recompress.hip", "hmatvec.hip", "solver.hip", "serve.hip"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -234,6 +234,8 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Pla
     permute_gather(H.tgt_nat.as<int64_t>(), m.N, n_bands, m.N, m.N, kappa, H.kappa_c.as<double>(), s);
     H.bands.resize(n_bands);
     int64_t evaluated = 0, bytes = 0, dense_e = 0, lr_e = 0, nfb = 0, aca_e = 0, retried = 0;
+    int64_t lr_aca = 0, rc_blocks = 0;
+    double rc_ms = 0.0;
     double aca_ms = 0, fill_ms = 0, aca_entry_ms = 0;
     int aca_l = 0, fill_l = 0, aca_entry_l = 0;
     double wsum = 0, wr = 0;
@@ -301,6 +303,9 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Pla
         bytes += B.bytes;
         dense_e += B.dense_entries;
         lr_e += B.lr_entries;
+        lr_aca += B.lr_entries + B.rc_before - B.rc_after;
+        rc_blocks += B.rc_blocks;
+        rc_ms += B.rc_ms;
         for (size_t k = 0; k < P.lowrank.size(); ++k) {
             const Block &bl = P.lowrank[k];
             const double mn = (double)((bl.t1 - bl.t0) + (bl.s1 - bl.s0));
@@ -338,6 +343,9 @@ std::unique_ptr<rte_hmat> assemble_hmat(const Mesh &m, std::shared_ptr<const Pla
     st.assemble_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     st.alloc_ms = alloc_ms_this_thread() - alloc0 + alloc_other;
     st.free_bytes = (int64_t)free_at_start;
+    st.lowrank_entries_aca = lr_aca;
+    st.recompressed_blocks = rc_blocks;
+    st.recompress_ms = rc_ms;
     return hm;
 }
 

@@ -868,6 +868,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
     std::vector<int> rk(nb);
     HIP_CHECK(hipMemcpyAsync(rk.data(), dr.p, sizeof(int) * rk.size(), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
+    if (H.opts.recompress) recompress_batch<T>(tasks, rk, Us.as<T>(), Vs.as<T>(), H.opts.aca_eps, B, s);
     int64_t total = 0;
     for (int t = 0; t < nb; ++t)
         if (rk[t] > 0)

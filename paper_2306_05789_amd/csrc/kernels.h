@@ -82,6 +82,14 @@ struct AcaTask {
     int64_t uoff, voff;   // scratch offsets (elements) of U^T [kcap][m] and V^T [kcap][n]
 };
 
+// Recompression of a batch's ACA factors (recompress.hip): the converged
+// blocks of rank 2..192 get the shortest truncation of the SVD of U V^T within
+// eps, computed and written in place in the ACA scratch (U^T at uoff, V^T at
+// voff); rk[t] becomes the new rank.  Synchronises `s` once per round.
+template <typename T>
+void recompress_batch(const std::vector<AcaTask> &tasks, std::vector<int> &rk, T *Us, T *Vs, double eps,
+                      BandStore &B, hipStream_t s);
+
 // Times the device work enqueued on `s` between start() and stop() with HIP events.
 struct EventTimer {
     hipEvent_t a = nullptr, b = nullptr;

@@ -312,7 +312,9 @@ struct BandStore {
     std::vector<const void *> U, V;         // per plan LR block (nullptr for fallbacks)
     std::vector<const void *> Ulo, Vlo;     // mixed precision: BF16 lo parts
     int64_t bytes = 0, dense_entries = 0, lr_entries = 0, evaluated = 0, aca_entries = 0, aca_retried = 0;
+    int64_t rc_before = 0, rc_after = 0, rc_blocks = 0;      // recompression: (m+n) k before and after
     double aca_ms = 0.0, fill_ms = 0.0, aca_entry_ms = 0.0;   // HIP-event kernel times
+    double rc_ms = 0.0;
     int aca_launches = 0, fill_launches = 0, aca_entry_launches = 0;
 };
 

@@ -34,7 +34,7 @@ class MeshDesc(C.Structure):
 
 class HmatOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dense", C.c_int32), ("leaf_size", C.c_int32),
-                ("eta", C.c_double), ("aca_eps", C.c_double), ("precision", C.c_int32)]
+                ("eta", C.c_double), ("aca_eps", C.c_double), ("precision", C.c_int32), ("recompress", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -52,7 +52,8 @@ class HmatStats(C.Structure):
                 ("aca_kernel_ms", C.c_double), ("aca_launches", C.c_int32),
                 ("aca_entry_ms", C.c_double), ("aca_entry_launches", C.c_int32),
                 ("fill_kernel_ms", C.c_double), ("fill_launches", C.c_int32), ("aca_entries", C.c_int64),
-                ("aca_retried", C.c_int64), ("alloc_ms", C.c_double), ("free_bytes", C.c_int64)]
+                ("aca_retried", C.c_int64), ("alloc_ms", C.c_double), ("free_bytes", C.c_int64),
+                ("lowrank_entries_aca", C.c_int64), ("recompressed_blocks", C.c_int64), ("recompress_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -255,10 +256,12 @@ def rte_mesh_emitting_ids(mesh: Mesh):
     return out
 
 
-def hmat_opts(kind=RTE_VOLUME, dense=False, leaf_size=64, eta=2.0, aca_eps=1e-5, precision=RTE_FP64) -> HmatOpts:
+def hmat_opts(kind=RTE_VOLUME, dense=False, leaf_size=64, eta=2.0, aca_eps=1e-5, precision=RTE_FP64,
+              recompress=False) -> HmatOpts:
     o = HmatOpts()
     o.kind, o.dense, o.leaf_size = int(kind), int(bool(dense)), int(leaf_size)
     o.eta, o.aca_eps = float(eta), float(aca_eps)
+    o.recompress = int(bool(recompress))
     o.precision = PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
     return o
 

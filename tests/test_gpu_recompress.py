@@ -1,0 +1,139 @@
+"""GPU: recompression of the ACA factors (the shortest truncation of the SVD of
+U V^T within the ACA tolerance, Section "Compression") against the oracle's
+recompression of the same factors, read back from an assembly without it;
+then the recompressed operators against the oracle: solves against the
+oracle's fixed point of the same read-back operators, products against the
+dense oracle within the compression bound."""
+import numpy as np
+import pytest
+import torch
+
+import readback
+from oracle import hmatrix
+from oracle import solve as osolve
+from oracle.core import Grid, Problem
+from paper_2306_05789_amd import inputs, rte
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+N3 = (21, 21, 21)
+EPS = 1e-5
+
+
+@pytest.fixture(scope="module")
+def setup():
+    """21^3 cube, smooth kappa, wall z = 0 (R = 0.5), faces x = 0 and y = 1 emitting."""
+    g = Grid(N3)
+    kap = inputs.smooth_kappa(g.positions())
+    mesh = rte.rte_mesh_create(N3, reflect_axis=2, reflect_side=0, R=0.5, emit_faces=1 | 8)
+    P = Problem(g, kap, emit_faces=1 | 8, wall_axis=2, wall_side=0, R=0.5)
+    return g, kap, mesh, P
+
+
+def _pair(mesh, kap, kind, precision):
+    kt = torch.tensor(kap[None, :], device=DEV)
+    off = rte.hmat_opts(kind=kind, leaf_size=32, precision=precision)
+    on = rte.hmat_opts(kind=kind, leaf_size=32, precision=precision, recompress=True)
+    return rte.rte_hmat_assemble(mesh, kt, off), rte.rte_hmat_assemble(mesh, kt, on), off, on
+
+
+@pytest.mark.parametrize("kind", [rte.RTE_VOLUME, rte.RTE_SURFACE])
+@pytest.mark.parametrize("precision", [rte.RTE_FP64, rte.RTE_FP32])
+def test_recompressed_blocks_match_oracle(setup, kind, precision):
+    g, kap, mesh, P = setup
+    H0, H1, o0, o1 = _pair(mesh, kap, kind, precision)
+    s0, s1 = rte.rte_hmat_stats(H0), rte.rte_hmat_stats(H1)
+    assert s1["lowrank_entries_aca"] == s0["lowrank_entries"]     # the same ACA underneath
+    assert s1["lowrank_entries"] < 0.9 * s0["lowrank_entries"]
+    assert s1["recompressed_blocks"] > 0
+    # arithmetic of the recompression: FP64 core; FP32 storage rounds the new factors
+    tol = 1e-9 if precision == rte.RTE_FP64 else 2e-6
+    plan = rte.rte_plan_create(mesh, o0)
+    try:
+        _, _, blocks = rte.rte_plan_export(plan)
+    finally:
+        rte.rte_plan_destroy(plan)
+    nlr = int((blocks[:, 4] == 1).sum())
+    n_cmp = n_rank_off = 0
+    for b in range(nlr):
+        k0, U0, V0 = rte.rte_hmat_block_factors_op(H0, 0, b, rte.RTE_OP_ACCURATE)
+        k1, U1, V1 = rte.rte_hmat_block_factors_op(H1, 0, b, rte.RTE_OP_ACCURATE)
+        if k0 <= 1 or k0 > 192:          # stored dense, rank 1, or beyond the recompressed ranks
+            assert k1 == k0
+            if k0 > 0:
+                assert np.array_equal(U0, U1) and np.array_equal(V0, V1)
+            continue
+        A = U0 @ V0.T
+        nA = np.linalg.norm(A)
+        Ur, Vr, sv = hmatrix.recompress(U0, V0, EPS)
+        # within eps of the ACA product whatever the rank chosen
+        assert np.linalg.norm(U1 @ V1.T - A) <= (EPS + tol) * nA, b
+        if k1 == k0:                      # kept: numerically dependent factors, or nothing to gain
+            assert Ur.shape[1] >= k0 - 1
+            continue
+        n_cmp += 1
+        if k1 != Ur.shape[1]:             # the rank test sits on the threshold
+            n_rank_off += 1
+            tail = np.sqrt(np.cumsum((sv ** 2)[::-1])[::-1])
+            r = min(k1, Ur.shape[1])
+            assert abs(tail[r] - EPS * tail[0]) < 1e-6 * EPS * tail[0], (b, k1, Ur.shape[1])
+            continue
+        assert np.linalg.norm(U1 @ V1.T - Ur @ Vr.T) <= tol * nA, b
+    assert n_cmp > 100
+    assert n_rank_off <= max(1, n_cmp // 100)
+
+
+@pytest.mark.parametrize("precision,gpu_tol,tol", [(rte.RTE_FP64, 1e-14, 1e-10), (rte.RTE_MIXED_BF16, 1e-9, 1e-6)])
+def test_recompressed_solve_matches_oracle_on_the_same_operator(setup, precision, gpu_tol, tol):
+    g, kap, mesh, P = setup
+    kt = torch.tensor(kap[None, :], device=DEV)
+    oG = rte.hmat_opts(kind=rte.RTE_VOLUME, leaf_size=32, precision=precision, recompress=True)
+    oS = rte.hmat_opts(kind=rte.RTE_SURFACE, leaf_size=32, precision=precision, recompress=True)
+    Gh, Sh = rte.rte_hmat_assemble(mesh, kt, oG), rte.rte_hmat_assemble(mesh, kt, oS)
+    HG, HS = readback.gpu_operator(mesh, Gh, oG), readback.gpu_operator(mesh, Sh, oS)
+    ref = osolve.fixed_point([HG], (HS @ np.full(mesh.L, osolve.SIGMA))[None], grey=True, tol=1e-14)
+    T = torch.empty((1, mesh.N), device=DEV, dtype=torch.float64)
+    st = rte.rte_fixed_point_solve(mesh, Gh, Sh, torch.ones((1, mesh.L), device=DEV, dtype=torch.float64), T,
+                                   grey=True, tol=gpu_tol, max_iter=2000, precision=precision)
+    assert st["converged"]
+    assert np.max(np.abs(T.cpu().numpy()[0] - ref.T) / ref.T) < tol
+
+
+def test_recompressed_matvec_within_compression_bound(setup):
+    """The recompressed operator against the dense oracle on sampled rows: the ACA
+    error plus at most eps of the truncation."""
+    g, kap, mesh, P = setup
+    H0, H1, _, _ = _pair(mesh, kap, rte.RTE_VOLUME, rte.RTE_FP64)
+    x = np.random.default_rng(21).uniform(0.5, 1.5, g.N)
+    rows = np.random.default_rng(22).choice(g.N, 60, replace=False)
+    ref = P.volume_block(rows, np.arange(g.N)) @ x
+    xt = torch.tensor(x[None, None, :], device=DEV)
+    errs = []
+    for H in (H0, H1):
+        y = torch.empty_like(xt)
+        rte.rte_hmat_matvec_batched(H, xt, y, rte.RTE_OP_ACCURATE)
+        errs.append(np.max(np.abs(y.cpu().numpy()[0, 0][rows] - ref) / ref))
+    assert errs[1] < 3e-4 and errs[1] < errs[0] + 2 * EPS
+
+
+def test_recompression_is_bitwise_reproducible(setup):
+    g, kap, mesh, P = setup
+    kt = torch.tensor(kap[None, :], device=DEV)
+    o = rte.hmat_opts(kind=rte.RTE_VOLUME, leaf_size=32, precision=rte.RTE_MIXED_BF16, recompress=True)
+    x = torch.tensor(np.random.default_rng(23).uniform(0.5, 1.5, (1, 16, g.N)), device=DEV)
+    ys = []
+    for _ in range(2):
+        H = rte.rte_hmat_assemble(mesh, kt, o)
+        y = torch.empty_like(x)
+        rte.rte_hmat_matvec_batched(H, x, y, rte.RTE_OP_LOW)
+        ys.append(y)
+        del H
+    assert torch.equal(ys[0], ys[1])
+
+
+def test_recompress_option_is_validated(setup):
+    g, kap, mesh, P = setup
+    o = rte.hmat_opts(kind=rte.RTE_VOLUME)
+    o.recompress = 2
+    with pytest.raises(rte.RteError):
+        rte.rte_hmat_assemble(mesh, torch.tensor(kap[None, :], device=DEV), o)
