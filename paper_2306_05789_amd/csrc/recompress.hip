@@ -33,7 +33,7 @@ namespace rte {
 
 namespace {
 
-constexpr int kRcMax = kAcaMaxRank;   // blocks of the first ACA pass (ranks <= 192)
+constexpr int kRcMax = 128;   // recompressed ranks: up to 128 (larger blocks, a few in a band, keep their factors)
 
 struct RcTask {
     int64_t uoff, voff;   // U^T [kcap][m] and V^T [kcap][n] in the ACA scratch (elements)
@@ -45,13 +45,21 @@ struct RcApply {
     int32_t task, side, i0, i1;   // rows [i0, i1) of U (side 0) or V (side 1)
 };
 
+// Launches go by rank bucket, each with the LDS its largest rank needs: the
+// factor tiles of k_rc_gram and k_rc_apply take kb x 33 doubles, the core of
+// k_rc_core (ranks up to kRcShared) 4 kb^2; small ranks then keep many
+// workgroups per CU.
+constexpr int kRcShared = 64;
+constexpr int kRcBuckets[] = {16, 32, 48, 64, 96, 128};
+constexpr int kRcStaticLds = 6144;   // k_rc_core's fixed LDS (per-rank vectors, flags), rounded up
+
 // Step 1: one workgroup per (block, factor).  The factor's rows are staged
 // 32 columns at a time in LDS (FP64); a thread accumulates a 4 x 4 tile of
 // the lower triangle of the Gram matrix, passes of 256 tiles cover it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rc_gram(const RcTask *__restrict__ tasks, const T *__restrict__ Us,
                                                  const T *__restrict__ Vs, double *__restrict__ W) {
-    __shared__ double sx[kRcMax][33];
+    extern __shared__ double sx[];   // [4 kt][33]
     const RcTask t = tasks[blockIdx.x];
     const int side = blockIdx.y;
     const T *__restrict__ X = side ? Vs + t.voff : Us + t.uoff;
@@ -76,7 +84,7 @@ __global__ __launch_bounds__(256) void k_rc_gram(const RcTask *__restrict__ task
             __syncthreads();
             for (int e = threadIdx.x; e < kt * 4 * 32; e += 256) {
                 const int l = e >> 5, i = e & 31;
-                sx[l][i] = (l < k && i0 + i < L) ? (double)X[(int64_t)l * L + i0 + i] : 0.0;
+                sx[l * 33 + i] = (l < k && i0 + i < L) ? (double)X[(int64_t)l * L + i0 + i] : 0.0;
             }
             __syncthreads();
             if (p < ntile) {
@@ -84,8 +92,8 @@ __global__ __launch_bounds__(256) void k_rc_gram(const RcTask *__restrict__ task
                     double xa[4], xb[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        xa[u] = sx[4 * a + u][i];
-                        xb[u] = sx[4 * b + u][i];
+                        xa[u] = sx[(4 * a + u) * 33 + i];
+                        xb[u] = sx[(4 * b + u) * 33 + i];
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
@@ -109,31 +117,41 @@ __global__ __launch_bounds__(256) void k_rc_gram(const RcTask *__restrict__ task
     }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // Steps 2 to 5 (small matrices): one workgroup per block.  Output: the new
 // rank (-1: keep the ACA factors) and the order of B's columns; the
-// transforms Ru^-1 B and Rv^-1 Z overwrite the columns of Mt and Zt.
+// transforms Ru^-1 B and Rv^-1 Z are written over the columns of the global
+// Mt and Zt, where k_rc_apply reads them.  Where the working matrices live:
+// SH = kRcAllLds (ranks up to kRcShared): the scaled Grams, their factors, the
+// core and Z in LDS; SH = kRcJacobiLds: the core and Z in LDS (the Jacobi
+// sweeps), the factors in the global workspace; SH = kRcGlobal: all global.
+enum { kRcGlobal = 0, kRcAllLds = 1, kRcJacobiLds = 2 };
+template <int SH>
 __global__ __launch_bounds__(256) void k_rc_core(const RcTask *__restrict__ tasks, double *__restrict__ W,
                                                  int *__restrict__ ord, int *__restrict__ rnew, double eps) {
+    extern __shared__ double smem[];   // the working matrices kept in LDS
     __shared__ double du[kRcMax], dv[kRcMax], sig[kRcMax];
     __shared__ int order[kRcMax];
     __shared__ int fail, rotated, rk;
     const RcTask t = tasks[blockIdx.x];
     const int k = t.k, tid = threadIdx.x;
-    double *__restrict__ Gu = W + t.woff;
-    double *__restrict__ Gv = Gu + (int64_t)k * k;
-    double *__restrict__ Mt = Gv + (int64_t)k * k;   // Mt[j * k + i] = M(i, j): column j contiguous
-    double *__restrict__ Zt = Mt + (int64_t)k * k;
+    const int64_t kk = (int64_t)k * k;
+    double *const Gg = W + t.woff;        // global: Gu, Gv, Mt, Zt (row stride k)
+    double *const Mg = Gg + 2 * kk;       // Mt[j * k + i] = M(i, j): column j contiguous
+    double *const Zg = Gg + 3 * kk;
+    // working copies: row strides ldl (factors) and ld (core, Z), odd in LDS so
+    // that a column's elements (stride ld doubles) fall in different banks
+    const int ldl = SH == kRcAllLds ? (k | 1) : k;
+    const int ld = SH != kRcGlobal ? (k | 1) : k;
+    const int64_t kl = (int64_t)k * ldl, km = (int64_t)k * ld;
+    double *Lu = SH == kRcAllLds ? smem : Gg;
+    double *Lv = Lu + kl;
+    double *Mt = SH == kRcAllLds ? smem + 2 * kl : (SH == kRcJacobiLds ? smem : Mg);
+    double *Zt = SH == kRcGlobal ? Zg : Mt + km;
     if (tid == 0) fail = 0;
     __syncthreads();
     for (int l = tid; l < k; l += 256) {
-        du[l] = sqrt(Gu[(int64_t)l * k + l]);
-        dv[l] = sqrt(Gv[(int64_t)l * k + l]);
+        du[l] = sqrt(Gg[(int64_t)l * k + l]);
+        dv[l] = sqrt(Gg[kk + (int64_t)l * k + l]);
         if (!(du[l] > 0.0) || !(dv[l] > 0.0)) fail = 1;
     }
     __syncthreads();
@@ -143,31 +161,31 @@ __global__ __launch_bounds__(256) void k_rc_core(const RcTask *__restrict__ task
     }
     for (int e = tid; e < k * k; e += 256) {
         const int i = e / k, j = e - i * k;
-        Gu[e] /= du[i] * du[j];
-        Gv[e] /= dv[i] * dv[j];
+        Lu[(int64_t)i * ldl + j] = Gg[e] / (du[i] * du[j]);
+        Lv[(int64_t)i * ldl + j] = Gg[kk + e] / (dv[i] * dv[j]);
     }
     __syncthreads();
-    // Cholesky of both scaled Grams at once (threads 0-127: Gu, 128-255: Gv),
+    // Cholesky of both scaled Grams at once (threads 0-127: Lu, 128-255: Lv),
     // lower factor in place, column by column
     {
         const int half = tid >> 7, lt = tid & 127;
-        double *__restrict__ G = half ? Gv : Gu;
+        double *G = half ? Lv : Lu;
         for (int j = 0; j < k; ++j) {
             if (lt == 0) {
-                double d = G[(int64_t)j * k + j];
-                for (int p = 0; p < j; ++p) d -= G[(int64_t)j * k + p] * G[(int64_t)j * k + p];
+                double d = G[(int64_t)j * ldl + j];
+                for (int p = 0; p < j; ++p) d -= G[(int64_t)j * ldl + p] * G[(int64_t)j * ldl + p];
                 if (!(d > 1e-13)) {   // numerically dependent columns
                     fail = 1;
                     d = 1.0;
                 }
-                G[(int64_t)j * k + j] = sqrt(d);
+                G[(int64_t)j * ldl + j] = sqrt(d);
             }
             __syncthreads();
-            const double piv = G[(int64_t)j * k + j];
+            const double piv = G[(int64_t)j * ldl + j];
             for (int i = j + 1 + lt; i < k; i += 128) {
-                double s = G[(int64_t)i * k + j];
-                for (int p = 0; p < j; ++p) s -= G[(int64_t)i * k + p] * G[(int64_t)j * k + p];
-                G[(int64_t)i * k + j] = s / piv;
+                double s = G[(int64_t)i * ldl + j];
+                for (int p = 0; p < j; ++p) s -= G[(int64_t)i * ldl + p] * G[(int64_t)j * ldl + p];
+                G[(int64_t)i * ldl + j] = s / piv;
             }
             __syncthreads();
         }
@@ -181,59 +199,75 @@ __global__ __launch_bounds__(256) void k_rc_core(const RcTask *__restrict__ task
         const int j = e / k, i = e - j * k;
         double s = 0.0;
         for (int p = i > j ? i : j; p < k; ++p)
-            s += (Gu[(int64_t)p * k + i] * du[p]) * (Gv[(int64_t)p * k + j] * dv[p]);
-        Mt[e] = s;
-        Zt[e] = i == j ? 1.0 : 0.0;
+            s += (Lu[(int64_t)p * ldl + i] * du[p]) * (Lv[(int64_t)p * ldl + j] * dv[p]);
+        Mt[(int64_t)j * ld + i] = s;
+        Zt[(int64_t)j * ld + i] = i == j ? 1.0 : 0.0;
     }
     __syncthreads();
     // one-sided Jacobi: sweeps of the round-robin pairing of the columns (a
-    // dummy column when k is odd), a wavefront per pair, until a sweep rotates
-    // nothing
-    const int n = k + (k & 1), wave = tid >> 6, lane = tid & 63;
-    for (int sweep = 0; sweep < 60; ++sweep) {
+    // dummy column when k is odd), 16 lanes per pair (16 pairs at a time),
+    // until a sweep rotates nothing.  A pair is rotated when its columns are
+    // not orthogonal to 1e-12 of their norms, far below the truncation
+    // tolerance; couplings below (1e-12 s)^2, s the largest column norm of M,
+    // are left: such columns are far beyond any truncation and would only
+    // trade rounding noise with the large ones.
+    for (int j = tid; j < k; j += 256) {
+        double c2 = 0.0;
+        for (int i = 0; i < k; ++i) c2 = fma(Mt[(int64_t)j * ld + i], Mt[(int64_t)j * ld + i], c2);
+        sig[j] = c2;
+    }
+    __syncthreads();
+    double s2 = 0.0;
+    for (int j = 0; j < k; ++j) s2 = sig[j] > s2 ? sig[j] : s2;
+    const double floor2 = 1e-24 * s2;
+    const int n = k + (k & 1), grp = tid >> 4, sl = tid & 15;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        __syncthreads();
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int r = 0; r < n - 1; ++r) {
-            for (int pi = wave; pi < n / 2; pi += 4) {
+            for (int pi = grp; pi < n / 2; pi += 16) {
                 const int qa = pi, qb = n - 1 - pi;
                 const int a = qa == 0 ? 0 : (qa - 1 + r) % (n - 1) + 1;
                 const int b = qb == 0 ? 0 : (qb - 1 + r) % (n - 1) + 1;
-                if (a >= k || b >= k) continue;   // the dummy column
+                if (a >= k || b >= k) continue;   // the dummy column (the whole group)
                 double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = lane; i < k; i += 64) {
-                    const double x = Mt[(int64_t)a * k + i], y = Mt[(int64_t)b * k + i];
+                for (int i = sl; i < k; i += 16) {
+                    const double x = Mt[(int64_t)a * ld + i], y = Mt[(int64_t)b * ld + i];
                     al = fma(x, x, al);
                     be = fma(y, y, be);
                     ga = fma(x, y, ga);
                 }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                ga = wave_sum(ga);
-                if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+#pragma unroll
+                for (int o = 8; o > 0; o >>= 1) {
+                    al += __shfl_xor(al, o, 16);
+                    be += __shfl_xor(be, o, 16);
+                    ga += __shfl_xor(ga, o, 16);
+                }
+                if (fabs(ga) > 1e-12 * sqrt(al * be) && fabs(ga) > floor2) {
                     const double zeta = (be - al) / (2.0 * ga);
                     const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-                    for (int i = lane; i < k; i += 64) {
-                        const double x = Mt[(int64_t)a * k + i], y = Mt[(int64_t)b * k + i];
-                        Mt[(int64_t)a * k + i] = c * x - s * y;
-                        Mt[(int64_t)b * k + i] = s * x + c * y;
-                        const double zx = Zt[(int64_t)a * k + i], zy = Zt[(int64_t)b * k + i];
-                        Zt[(int64_t)a * k + i] = c * zx - s * zy;
-                        Zt[(int64_t)b * k + i] = s * zx + c * zy;
+                    for (int i = sl; i < k; i += 16) {
+                        const double x = Mt[(int64_t)a * ld + i], y = Mt[(int64_t)b * ld + i];
+                        Mt[(int64_t)a * ld + i] = c * x - s * y;
+                        Mt[(int64_t)b * ld + i] = s * x + c * y;
+                        const double zx = Zt[(int64_t)a * ld + i], zy = Zt[(int64_t)b * ld + i];
+                        Zt[(int64_t)a * ld + i] = c * zx - s * zy;
+                        Zt[(int64_t)b * ld + i] = s * zx + c * zy;
                     }
-                    if (lane == 0) rotated = 1;
+                    if (sl == 0) rotated = 1;
                 }
             }
             __syncthreads();
         }
-        const int any = rotated;
-        __syncthreads();
-        if (!any) break;
+        if (!rotated) break;   // read by every thread after the round's barrier
     }
+    __syncthreads();
     // singular values, their decreasing order, the truncation rank
     for (int j = tid; j < k; j += 256) {
         double s = 0.0;
-        for (int i = 0; i < k; ++i) s = fma(Mt[(int64_t)j * k + i], Mt[(int64_t)j * k + i], s);
+        for (int i = 0; i < k; ++i) s = fma(Mt[(int64_t)j * ld + i], Mt[(int64_t)j * ld + i], s);
         sig[j] = sqrt(s);
     }
     __syncthreads();
@@ -262,21 +296,21 @@ __global__ __launch_bounds__(256) void k_rc_core(const RcTask *__restrict__ task
         return;
     }
     // transforms: column ord[c] of Mt becomes Ru^-1 B(:, ord[c]) = D_u^-1 L_u^-T b,
-    // the same column of Zt Rv^-1 Z(:, ord[c]); one thread per kept column
-    for (int c = tid; c < r; c += 256) {
-        const int j = order[c];
-        for (int side = 0; side < 2; ++side) {
-            const double *__restrict__ Lf = side ? Gv : Gu;
-            const double *__restrict__ d = side ? dv : du;
-            double *__restrict__ y = (side ? Zt : Mt) + (int64_t)j * k;
-            for (int i = k - 1; i >= 0; --i) {
-                double s = y[i];
-                for (int p = i + 1; p < k; ++p) s -= Lf[(int64_t)p * k + i] * y[p];
-                y[i] = s / Lf[(int64_t)i * k + i];
-            }
-            for (int i = 0; i < k; ++i) y[i] /= d[i];
+    // the same column of Zt Rv^-1 Z(:, ord[c]); a thread per (kept column, side),
+    // solved in place, then written to the global columns
+    for (int q = tid; q < 2 * r; q += 256) {
+        const int c = q >> 1, side = q & 1, j = order[c];
+        const double *Lf = side ? Lv : Lu;
+        const double *d = side ? dv : du;
+        double *y = (side ? Zt : Mt) + (int64_t)j * ld;
+        double *out = (side ? Zg : Mg) + (int64_t)j * k;
+        for (int i = k - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int p = i + 1; p < k; ++p) s -= Lf[(int64_t)p * ldl + i] * y[p];
+            y[i] = s / Lf[(int64_t)i * ldl + i];
         }
-        ord[(int64_t)t.idx * kRcMax + c] = j;
+        for (int i = 0; i < k; ++i) out[i] = y[i] / d[i];
+        if (side == 0) ord[(int64_t)t.idx * kRcMax + c] = j;
     }
     if (tid == 0) rnew[t.idx] = r;
 }
@@ -288,7 +322,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_rc_apply(const RcApply *__restrict__ ap, const RcTask *__restrict__ tasks,
                                                   T *__restrict__ Us, T *__restrict__ Vs, const double *__restrict__ W,
                                                   const int *__restrict__ ord, const int *__restrict__ rnew) {
-    __shared__ double sx[kRcMax][33];
+    extern __shared__ double sx[];   // [k][33]
     const RcApply a = ap[blockIdx.x];
     const RcTask t = tasks[a.task];
     const int r = rnew[t.idx];
@@ -298,7 +332,7 @@ __global__ __launch_bounds__(256) void k_rc_apply(const RcApply *__restrict__ ap
     const double *__restrict__ Tm = W + t.woff + (int64_t)(2 + a.side) * k * k;
     for (int e = threadIdx.x; e < k * 32; e += 256) {
         const int l = e >> 5, i = e & 31;
-        sx[l][i] = i < w ? (double)X[(int64_t)l * L + a.i0 + i] : 0.0;
+        sx[l * 33 + i] = i < w ? (double)X[(int64_t)l * L + a.i0 + i] : 0.0;
     }
     __syncthreads();
     const int i = threadIdx.x & 31, g = threadIdx.x >> 5;
@@ -306,7 +340,7 @@ __global__ __launch_bounds__(256) void k_rc_apply(const RcApply *__restrict__ ap
     for (int c = g; c < r; c += 8) {
         const double *__restrict__ col = Tm + (int64_t)ord[(int64_t)t.idx * kRcMax + c] * k;
         double s = 0.0;
-        for (int l = 0; l < k; ++l) s = fma(sx[l][i], col[l], s);
+        for (int l = 0; l < k; ++l) s = fma(sx[l * 33 + i], col[l], s);
         X[(int64_t)c * L + a.i0 + i] = (T)s;
     }
 }
@@ -316,18 +350,28 @@ __global__ __launch_bounds__(256) void k_rc_apply(const RcApply *__restrict__ ap
 template <typename T>
 void recompress_batch(const std::vector<AcaTask> &tasks, std::vector<int> &rk, T *Us, T *Vs, double eps,
                       BandStore &B, hipStream_t s) {
+    // candidates, by rank bucket
+    constexpr int NB = sizeof(kRcBuckets) / sizeof(kRcBuckets[0]);
     std::vector<size_t> cand;
-    for (size_t t = 0; t < tasks.size(); ++t)
-        if (rk[t] >= 2 && rk[t] <= kRcMax) cand.push_back(t);
+    for (int bk = 0; bk < NB; ++bk)
+        for (size_t t = 0; t < tasks.size(); ++t) {
+            const int k = rk[t], lo = bk ? kRcBuckets[bk - 1] : 1;
+            if (k >= 2 && k > lo && k <= kRcBuckets[bk]) cand.push_back(t);
+        }
     if (cand.empty()) return;
     EventTimer timer(s);
     timer.start();
+    // the LDS a workgroup may ask for (the cores of the larger buckets go global beyond it)
+    int dev = 0, lds_max = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     // rounds whose FP64 workspace (4 k^2 per block) stays within 1 GiB
     const int64_t cap_words = (int64_t)1 << 27;
     size_t c0 = 0;
     while (c0 < cand.size()) {
         std::vector<RcTask> rt;
         std::vector<RcApply> ap;
+        std::vector<int> bucket_end(NB, 0), apply_end(NB, 0);   // prefix ends per bucket
         int64_t words = 0;
         size_t c1 = c0;
         for (; c1 < cand.size(); ++c1) {
@@ -341,18 +385,44 @@ void recompress_batch(const std::vector<AcaTask> &tasks, std::vector<int> &rk, T
                 const int L = side ? a.n : a.m;
                 for (int i0 = 0; i0 < L; i0 += 32) ap.push_back({idx, side, i0, std::min(L, i0 + 32)});
             }
+            int bk = 0;
+            while (k > kRcBuckets[bk]) ++bk;
+            for (int q = bk; q < NB; ++q) {
+                bucket_end[q] = (int)rt.size();
+                apply_end[q] = (int)ap.size();
+            }
         }
         const int nt = (int)rt.size();
         DevBuf dt = upload_scratch(rt, s), dap = upload_scratch(ap, s);
         DevBuf W = DevBuf::scratch(sizeof(double) * (size_t)words);
         DevBuf dord = DevBuf::scratch(sizeof(int) * (size_t)nt * kRcMax), dr = DevBuf::scratch(sizeof(int) * (size_t)nt);
-        k_rc_gram<T><<<dim3((unsigned)nt, 2), 256, 0, s>>>(dt.as<RcTask>(), Us, Vs, W.as<double>());
-        HIP_LAUNCH_CHECK();
-        k_rc_core<<<(unsigned)nt, 256, 0, s>>>(dt.as<RcTask>(), W.as<double>(), dord.as<int>(), dr.as<int>(), eps);
-        HIP_LAUNCH_CHECK();
-        k_rc_apply<T><<<(unsigned)ap.size(), 256, 0, s>>>(dap.as<RcApply>(), dt.as<RcTask>(), Us, Vs, W.as<double>(),
-                                                          dord.as<int>(), dr.as<int>());
-        HIP_LAUNCH_CHECK();
+        const RcTask *tp = dt.as<RcTask>();
+        const RcApply *app = dap.as<RcApply>();
+        int t0 = 0, a0 = 0;
+        for (int bk = 0; bk < NB; ++bk) {   // the blocks of a bucket: t0..t1, their products a0..a1
+            const int t1 = bucket_end[bk], a1 = apply_end[bk], kb = kRcBuckets[bk];
+            if (t1 > t0) {
+                const size_t tile = sizeof(double) * (size_t)((kb + 3) / 4 * 4) * 33;
+                k_rc_gram<T><<<dim3((unsigned)(t1 - t0), 2), 256, tile, s>>>(tp + t0, Us, Vs, W.as<double>());
+                // LDS for the working matrices: all four, or the core and Z only, or none
+                const size_t all_lds = sizeof(double) * 4 * kb * (kb | 1), jac_lds = all_lds / 2;
+                const size_t room = (size_t)lds_max - kRcStaticLds;
+                if (kb <= kRcShared && all_lds <= room)
+                    k_rc_core<kRcAllLds><<<(unsigned)(t1 - t0), 256, all_lds, s>>>(
+                        tp + t0, W.as<double>(), dord.as<int>(), dr.as<int>(), eps);
+                else if (jac_lds <= room)
+                    k_rc_core<kRcJacobiLds><<<(unsigned)(t1 - t0), 256, jac_lds, s>>>(
+                        tp + t0, W.as<double>(), dord.as<int>(), dr.as<int>(), eps);
+                else
+                    k_rc_core<kRcGlobal><<<(unsigned)(t1 - t0), 256, 0, s>>>(tp + t0, W.as<double>(), dord.as<int>(),
+                                                                             dr.as<int>(), eps);
+                k_rc_apply<T><<<(unsigned)(a1 - a0), 256, sizeof(double) * kb * 33, s>>>(
+                    app + a0, tp, Us, Vs, W.as<double>(), dord.as<int>(), dr.as<int>());
+                HIP_LAUNCH_CHECK();
+            }
+            t0 = std::max(t0, t1);
+            a0 = std::max(a0, a1);
+        }
         std::vector<int> rn(nt);
         HIP_CHECK(hipMemcpyAsync(rn.data(), dr.p, sizeof(int) * nt, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));

@@ -213,3 +213,19 @@ def test_autotuner_picks_a_shape_and_results_hold(small, precision, tmp_path):
     assert r2["source"] == "cache" and rte.rte_hmat_get_config(G2) == r["config"]
     with pytest.raises(rte.RteError):
         rte.rte_hmat_set_config(G, {"phase_b_waves": 3, "phase_a_kib": 64, "phase_a_tiles": 4})
+
+
+def test_leaf_size_search_scores_every_candidate():
+    """The leaf-size search assembles at each candidate, autotunes its matvec and
+    keeps the one with the smallest assembly + sweeps x matvec time."""
+    from paper_2306_05789_amd import tune
+    n = 17
+    mesh = rte.rte_mesh_create((n, n, n), emit_faces=1)
+    kap = torch.tensor(inputs.smooth_kappa(inputs.grid_positions((n, n, n), (0, 0, 0), (1, 1, 1)))[None, :],
+                       device=DEV)
+    best, rec = tune.tune_leaf_size(mesh, kap, {"kind": rte.RTE_VOLUME, "precision": rte.RTE_FP64},
+                                    candidates=(32, 64), sweeps=20, reps=2)
+    assert [r["leaf_size"] for r in rec] == [32, 64]
+    assert all(r["assemble_ms"] > 0 and r["matvec_ms"] > 0 and r["bytes"] > 0 for r in rec)
+    assert best == min(rec, key=lambda r: r["score_ms"])["leaf_size"]
+    assert all(abs(r["score_ms"] - (r["assemble_ms"] + 20 * r["matvec_ms"])) < 1e-9 for r in rec)
