@@ -110,7 +110,7 @@ void rte_mesh_destroy(rte_mesh_t mesh);
  * admissibility max(R1,R2) < eta * dist(box1, box2), partially pivoted ACA
  * with relative Frobenius tolerance aca_eps.  dense = 1 stores every block
  * dense (no compression).  recompress = 1: the factors of every block the ACA
- * compressed (ranks up to 128) are replaced by the shortest truncation of the
+ * compressed (ranks up to 96) are replaced by the shortest truncation of the
  * SVD of their product whose relative Frobenius error is <= aca_eps (a block
  * whose factors are numerically dependent, or that would not get shorter,
  * keeps them); the error against the ACA product adds at most aca_eps. */

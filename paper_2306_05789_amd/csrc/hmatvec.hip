@@ -592,8 +592,8 @@ struct MfSrcA {
 // (task, step), two operand sets in turn: the next step's operands, possibly
 // of the next task, are in flight while the current products run.  A tile of
 // a one-chunk block writes its t splits (zero padding up to pad8(k)
-// included) directly; tiles of larger blocks leave FP64 partials for
-// k_mf_tstage.
+// included) directly; tiles of larger blocks leave partials (FP32 for the
+// low operator, FP64 for the accurate one) for k_mf_tstage.
 template <int MODE, int NT>
 __device__ __forceinline__ MfSrcA<MODE, NT> mf_src_a(const MfVt &tk, const uint16_t *xs, int64_t xsplit, int64_t np) {
     MfSrcA<MODE, NT> r;
@@ -655,24 +655,30 @@ __device__ __forceinline__ void mf_finish_a(const MfVt &tk, int c, int q, const 
                     w[1][v / 2] = (uint32_t)m0 | ((uint32_t)m1 << 16);
                     w[2][v / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
                 }
+                // the splits phase B reads: hi + mid for the low operator, all three for the accurate
+                constexpr int NSW = MfOps<MODE, NT>::NS;
                 uint32_t p[3][2];
 #pragma unroll
-                for (int sp = 0; sp < 3; ++sp)
+                for (int sp = 0; sp < NSW; ++sp)
 #pragma unroll
                     for (int e = 0; e < 2; ++e) p[sp][e] = (uint32_t)__shfl_xor((int)w[sp][e], 16, 64);
                 const int rk0 = tl.kt0 + 4 * q;   // a multiple of 8 when q is even
                 if ((q & 1) == 0 && rk0 < (int)pad8(tl.k)) {
                     const int64_t off = ((tl.out + rk0) / 8 * 16 + c) * 8;
 #pragma unroll
-                    for (int sp = 0; sp < 3; ++sp)
+                    for (int sp = 0; sp < NSW; ++sp)
                         *reinterpret_cast<uint4 *>(ts + sp * tsplit + off) = make_uint4(w[sp][0], w[sp][1], p[sp][0], p[sp][1]);
                 }
             } else if (c < nr) {
+                // chunk partials: FP32 for the low operator (its sums are FP32), FP64 for the accurate one
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int rk = tl.kt0 + 4 * q + v;
-                    if (rk < tl.k)
-                        part[(int64_t)(r0 + c) * ldp + tl.out + rk] = MODE == kMatvecLow ? (double)acc[t][v] : a64[t][v];
+                    const int64_t o = (int64_t)(r0 + c) * ldp + tl.out + rk;
+                    if (rk < tl.k) {
+                        if constexpr (MODE == kMatvecLow) reinterpret_cast<float *>(part)[o] = acc[t][v];
+                        else part[o] = a64[t][v];
+                    }
                 }
             }
         }
@@ -760,10 +766,11 @@ __global__ __launch_bounds__(256) void k_mf_phase_a(const MfVt *__restrict__ tas
     }
 }
 
-// t_b = sum of the chunk partials (fixed order), split into hi, mid, lo, for
+// t_b = sum of the chunk partials (fixed order, in FP64), split into hi, mid, lo, for
 // the blocks of more than one chunk: one workgroup per block, a thread per
 // (right-hand side, rank) pair; entries k..pad8(k)-1 and right-hand sides
 // beyond the group's count are zeros
+template <int MODE>
 __global__ __launch_bounds__(256) void k_mf_tstage(const MfRed *__restrict__ red, const double *__restrict__ part,
                                                    int64_t ldp, uint16_t *__restrict__ ts, int64_t tsplit, int r0,
                                                    int nr) {
@@ -773,15 +780,21 @@ __global__ __launch_bounds__(256) void k_mf_tstage(const MfRed *__restrict__ red
         const int r = e / k8, l = e - r * k8;
         double sum = 0.0;
         if (l < rd.k && r < nr) {
-            const double *p = part + (int64_t)(r0 + r) * ldp + rd.part + l;
-            for (int c = 0; c < rd.chunks; ++c) sum += p[(int64_t)c * rd.k];
+            const int64_t o0 = (int64_t)(r0 + r) * ldp + rd.part + l;
+            if constexpr (MODE == kMatvecLow) {   // FP32 partials, added in FP64 as before
+                const float *p = reinterpret_cast<const float *>(part) + o0;
+                for (int c = 0; c < rd.chunks; ++c) sum += (double)p[(int64_t)c * rd.k];
+            } else {
+                const double *p = part + o0;
+                for (int c = 0; c < rd.chunks; ++c) sum += p[(int64_t)c * rd.k];
+            }
         }
         uint16_t h, m, lo;
         split3(sum, h, m, lo);
         const int64_t o = ((rd.toff + l) / 8 * 16 + r) * 8 + l % 8;
         ts[o] = h;
         ts[tsplit + o] = m;
-        ts[2 * tsplit + o] = lo;
+        if constexpr (MODE == kMatvecAccurate) ts[2 * tsplit + o] = lo;   // the low operator reads hi + mid
     }
 }
 
@@ -1055,7 +1068,8 @@ void launch_mf(const MatvecPlan &mp, int nrhs, const double *x, const double *y0
             }
             HIP_LAUNCH_CHECK();
             if (mp.n_red) {
-                k_mf_tstage<<<(unsigned)mp.n_red, 256, 0, s>>>(mp.red.as<MfRed>(), part, ldp, ts, tsplit, r0, nr);
+                k_mf_tstage<MODE><<<(unsigned)mp.n_red, 256, 0, s>>>(mp.red.as<MfRed>(), part, ldp, ts, tsplit, r0,
+                                                                     nr);
                 HIP_LAUNCH_CHECK();
             }
         }

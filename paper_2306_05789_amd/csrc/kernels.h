@@ -83,7 +83,7 @@ struct AcaTask {
 };
 
 // Recompression of a batch's ACA factors (recompress.hip): the converged
-// blocks of rank 2..128 get the shortest truncation of the SVD of U V^T within
+// blocks of rank 2..96 get the shortest truncation of the SVD of U V^T within
 // eps, computed and written in place in the ACA scratch (U^T at uoff, V^T at
 // voff); rk[t] becomes the new rank.  Synchronises `s` once per round.
 template <typename T>

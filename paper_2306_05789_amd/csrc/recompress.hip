@@ -33,7 +33,7 @@ namespace rte {
 
 namespace {
 
-constexpr int kRcMax = 128;   // recompressed ranks: up to 128 (larger blocks, a few in a band, keep their factors)
+constexpr int kRcMax = 96;   // recompressed ranks: up to 96 (larger blocks, a few in a band, keep their factors)
 
 struct RcTask {
     int64_t uoff, voff;   // U^T [kcap][m] and V^T [kcap][n] in the ACA scratch (elements)
@@ -50,7 +50,7 @@ struct RcApply {
 // k_rc_core (ranks up to kRcShared) 4 kb^2; small ranks then keep many
 // workgroups per CU.
 constexpr int kRcShared = 64;
-constexpr int kRcBuckets[] = {16, 32, 48, 64, 96, 128};
+constexpr int kRcBuckets[] = {16, 32, 48, 64, 96};
 constexpr int kRcStaticLds = 6144;   // k_rc_core's fixed LDS (per-rank vectors, flags), rounded up
 
 // Step 1: one workgroup per (block, factor).  The factor's rows are staged
