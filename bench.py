@@ -371,10 +371,11 @@ def run_served(args):
 # HBM bytes per launch of the low-operator matvec of the headline workload (the
 # four launches k_mf_xstage, k_mf_phase_a, k_mf_tstage, k_mf_phase_b), from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes calibrated on a plain 1 GiB copy
-# (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all): 108.9 GB read and
-# 8.7 GB written (profiles/cube49_32band_16rhs_mixed_matvec_traffic.md).  Set
-# to None whenever those kernels change.
-LOW_MATVEC_TRAFFIC_BYTES = 117.6e9
+# (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all): 87.8 GB read and
+# 5.1 GB written, on the recompressed operator
+# (profiles/cube49_32band_16rhs_mixed_matvec_traffic.md).  Set to None
+# whenever those kernels or the operator's storage change.
+LOW_MATVEC_TRAFFIC_BYTES = 92.9e9
 
 
 def _cpu_model() -> str:
