@@ -260,6 +260,31 @@ typedef struct {
 
 rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats);
 
+/* ------------------------------------------------------------------ kappa levels
+ * Section "Compression": a few values of kappa_nu, each with its two matrices,
+ * stand for all frequencies as a piecewise-constant interpolation (Section
+ * "Test 2: the General Case": 8 values for 583 frequencies).  Adaptive
+ * levels for n positive multipliers values[b] (host): the fewest levels such
+ * that every value lies within a factor (1 + tol) of its level, chosen on the
+ * sorted logarithms by the greedy cover (optimal for intervals of one length
+ * on a line): each level is (1 + tol) times the smallest value it takes.
+ * levels[] (host, ascending, room for max_levels) and map[b] (host, the
+ * level of value b) are written; *n_levels the count.  tol > 0; more than
+ * max_levels needed: RTE_E_INVALID_ARG (raise tol). */
+rte_status_t rte_kappa_levels(const double *values, int32_t n, double tol, int32_t max_levels, double *levels,
+                              int32_t *map, int32_t *n_levels);
+
+/* A band-mapped view of an H-matrix: band b of the view is band band_op[b]
+ * of h (host array of n_bands entries, each in [0, h's band count)), with the
+ * absorption of that band.  The view shares h's stored operator (h must
+ * outlive it; destroy it with rte_hmat_destroy) and builds its own matvec
+ * work lists, so a solve on views of G and S runs each of its bands with its
+ * own frequency, weight and right-hand sides on the operator of its level
+ * (the levels of rte_kappa_levels); rte_hmat_stats of a view reports h's
+ * figures with the view's band count.  Synchronises `stream`. */
+rte_status_t rte_hmat_select_bands(rte_hmat_t h, int32_t n_bands, const int32_t *band_op, void *stream,
+                                   rte_hmat_t *out);
+
 /* Factors of admissible block `block` (0-based among admissible blocks, plan
  * order) of band `band`, copied to host FP64: U [m][rank] and V [n][rank],
  * rows in cluster order of the block's ranges; the block approximates rows

@@ -5,7 +5,9 @@
 #include <thread>
 #include <atomic>
 #include <chrono>
+#include <algorithm>
 #include <cmath>
+#include <numeric>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -704,6 +706,110 @@ rte_status_t rte_hmat_stats(rte_hmat_t h, rte_hmat_stats_t *stats) {
     return guard([&] {
         RTE_REQUIRE(h && stats, "rte_hmat_stats: NULL argument");
         *stats = h->h.stats;
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_kappa_levels(const double *values, int32_t n, double tol, int32_t max_levels, double *levels,
+                              int32_t *map, int32_t *n_levels) {
+    return guard([&] {
+        RTE_REQUIRE(values && levels && map && n_levels, "rte_kappa_levels: NULL argument");
+        RTE_REQUIRE(n >= 1 && max_levels >= 1, "rte_kappa_levels: need n >= 1 and max_levels >= 1");
+        RTE_REQUIRE(std::isfinite(tol) && tol > 0.0, "rte_kappa_levels: tol must be > 0");
+        for (int32_t b = 0; b < n; ++b)
+            RTE_REQUIRE(std::isfinite(values[b]) && values[b] > 0.0, "rte_kappa_levels: values must be finite and > 0");
+        // sorted order (ties by index), then the greedy cover of the logarithms by
+        // intervals [ln v, ln v + 2 ln(1 + tol)], each level at its middle
+        std::vector<int32_t> idx(n);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return values[a] < values[b]; });
+        const double w = std::log1p(tol);
+        int32_t nl = 0;
+        double level = 0.0, lo = 0.0;
+        for (int32_t q = 0; q < n; ++q) {
+            const int32_t b = idx[q];
+            const double lv = std::log(values[b]);
+            if (nl == 0 || lv > lo + 2.0 * w) {
+                RTE_REQUIRE(nl < max_levels, "rte_kappa_levels: more than max_levels levels needed (raise tol)");
+                lo = lv;
+                level = values[b] * (1.0 + tol);
+                levels[nl++] = level;
+            }
+            map[b] = nl - 1;
+        }
+        *n_levels = nl;
+        return RTE_OK;
+    });
+}
+
+rte_status_t rte_hmat_select_bands(rte_hmat_t h, int32_t n_bands, const int32_t *band_op, void *stream,
+                                   rte_hmat_t *out) {
+    return guard([&] {
+        RTE_REQUIRE(h && band_op && out, "rte_hmat_select_bands: NULL argument");
+        const HMat &H = h->h;
+        RTE_REQUIRE(n_bands >= 1 && n_bands <= 4096, "rte_hmat_select_bands: n_bands out of range");
+        for (int32_t b = 0; b < n_bands; ++b)
+            RTE_REQUIRE(band_op[b] >= 0 && band_op[b] < H.n_bands, "rte_hmat_select_bands: band index out of range");
+        hipStream_t s = (hipStream_t)stream;
+        int dev = 0;
+        HIP_CHECK(hipGetDevice(&dev));
+        RTE_REQUIRE(dev == H.device, "rte_hmat_select_bands: the matrix lives on another device");
+        auto hv = std::make_unique<rte_hmat>();
+        HMat &V = hv->h;
+        V.mesh = H.mesh;
+        V.plan = H.plan;
+        V.opts = H.opts;
+        V.n_bands = n_bands;
+        V.precision = H.precision;
+        V.kind = H.kind;
+        V.device = H.device;
+        V.cfg = H.cfg;
+        V.kgroup = H.kgroup;
+        V.leaf_prp_h = H.leaf_prp_h;
+        V.src_p_h = H.src_p_h;
+        V.n_src_p = H.n_src_p;
+        auto dup = [&](const DevBuf &a) {
+            DevBuf b(a.bytes);
+            if (a.bytes) HIP_CHECK(hipMemcpyAsync(b.p, a.p, a.bytes, hipMemcpyDeviceToDevice, s));
+            return b;
+        };
+        V.tgt_nat = dup(H.tgt_nat);
+        V.src_nat = dup(H.src_nat);
+        V.src_pos = dup(H.src_pos);
+        V.leaf_start = dup(H.leaf_start);
+        V.leaf_prp = dup(H.leaf_prp);
+        V.src_p = dup(H.src_p);
+        V.src_pmap = dup(H.src_pmap);
+        // kappa at the targets: the rows of the selected bands
+        const int64_t nt = (int64_t)H.plan->tgt_nat.size();
+        V.kappa_c.alloc(sizeof(double) * (size_t)nt * n_bands);
+        for (int32_t b = 0; b < n_bands; ++b)
+            HIP_CHECK(hipMemcpyAsync(V.kappa_c.as<double>() + (int64_t)b * nt, H.kappa_c.as<double>() + band_op[b] * nt,
+                                     sizeof(double) * nt, hipMemcpyDeviceToDevice, s));
+        // the stored blocks of the selected bands, not owned: h keeps the storage
+        V.bands.resize(n_bands);
+        for (int32_t b = 0; b < n_bands; ++b) {
+            const BandStore &B = H.bands[band_op[b]];
+            BandStore &C = V.bands[b];
+            C.dense_blocks = B.dense_blocks;
+            C.dense_ptr = B.dense_ptr;
+            C.dense_lo = B.dense_lo;
+            C.rank = B.rank;
+            C.U = B.U;
+            C.V = B.V;
+            C.Ulo = B.Ulo;
+            C.Vlo = B.Vlo;
+            C.bytes = B.bytes;
+            C.dense_entries = B.dense_entries;
+            C.lr_entries = B.lr_entries;
+        }
+        matvec_reserve(V, n_bands);
+        for (int32_t b = 0; b < n_bands; ++b) matvec_build(V, b, s);
+        matvec_build_all(V, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        V.stats = H.stats;
+        V.stats.n_bands = n_bands;
+        *out = hv.release();
         return RTE_OK;
     });
 }

@@ -131,6 +131,9 @@ SIGNATURES = {
     "rte_hmat_matvec_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_hmat_matvec_batched": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "rte_hmat_stats": (C.c_int, [C.c_void_p, C.POINTER(HmatStats)]),
+    "rte_kappa_levels": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_int32)]),
+    "rte_hmat_select_bands": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "rte_hmat_get_config": (C.c_int, [C.c_void_p, C.POINTER(MatvecConfig)]),
     "rte_hmat_set_config": (C.c_int, [C.c_void_p, C.POINTER(MatvecConfig), C.c_void_p]),
     "rte_hmat_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(MatvecConfig),
@@ -302,8 +305,9 @@ def rte_entries(mesh: Mesh, kind, kappa, rows, cols, out, precision=RTE_FP64, st
 
 
 class HMat:
-    def __init__(self, handle, mesh):
+    def __init__(self, handle, mesh, parent=None):
         self.handle, self.mesh = handle, mesh   # keep the mesh alive
+        self.parent = parent                    # a band view keeps its operator alive
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -317,6 +321,28 @@ def rte_hmat_assemble(mesh: Mesh, kappa, opts: HmatOpts, stream=None) -> HMat:
     h = C.c_void_p()
     _check(load().rte_hmat_assemble(mesh.handle, n_bands, _ptr(kappa), C.byref(opts), _stream(stream), C.byref(h)))
     return HMat(h, mesh)
+
+
+def rte_kappa_levels(values, tol: float, max_levels: int = 64):
+    """Adaptive kappa levels of positive multipliers: (levels ascending, map[b] = level of value b)."""
+    import numpy as np
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    levels = np.empty(max_levels, dtype=np.float64)
+    mp = np.empty(len(v), dtype=np.int32)
+    nl = C.c_int32()
+    _check(load().rte_kappa_levels(v.ctypes.data_as(C.c_void_p), len(v), float(tol), int(max_levels),
+                                   levels.ctypes.data_as(C.c_void_p), mp.ctypes.data_as(C.c_void_p), C.byref(nl)))
+    return levels[:nl.value].copy(), mp
+
+
+def rte_hmat_select_bands(hmat: HMat, band_op, stream=None) -> HMat:
+    """View whose band b is band band_op[b] of hmat (which the view keeps alive)."""
+    import numpy as np
+    bo = np.ascontiguousarray(band_op, dtype=np.int32)
+    h = C.c_void_p()
+    _check(load().rte_hmat_select_bands(hmat.handle, len(bo), bo.ctypes.data_as(C.c_void_p), _stream(stream),
+                                        C.byref(h)))
+    return HMat(h, hmat.mesh, parent=hmat)
 
 
 def rte_hmat_matvec(hmat: HMat, band, x, y, stream=None):

@@ -134,3 +134,38 @@ def test_surface_plan_needs_an_emitting_face():
     mesh = rte.rte_mesh_create((4, 4, 4), emit_faces=0)
     with pytest.raises(rte.RteError):
         rte.rte_plan_create(mesh, rte.hmat_opts(kind=rte.RTE_SURFACE))
+
+
+def _min_levels(v, tol):
+    """Brute force: the fewest groups of the sorted values, each spanning at most a
+    factor (1 + tol)^2 (one level within (1 + tol) of all), over every split into runs."""
+    x = np.sort(np.log(v))
+    n, best = len(x), len(x)
+    for mask in range(1 << (n - 1)):
+        cuts = [0] + [i + 1 for i in range(n - 1) if (mask >> i) & 1] + [n]
+        if all(x[b - 1] - x[a] <= 2 * np.log1p(tol) + 1e-12 for a, b in zip(cuts, cuts[1:])):
+            best = min(best, len(cuts) - 1)
+    return best
+
+
+def test_kappa_levels_are_the_fewest_within_tolerance():
+    rng = np.random.default_rng(41)
+    for trial in range(40):
+        n = int(rng.integers(1, 10))
+        v = np.exp(rng.normal(0.0, 1.0, n))
+        tol = float(rng.choice([0.05, 0.2, 0.5]))
+        levels, mp = rte.rte_kappa_levels(v, tol)
+        assert np.all(np.diff(levels) > 0)
+        ratio = v / levels[mp]
+        assert np.all(ratio <= 1 + tol + 1e-12) and np.all(1 / ratio <= 1 + tol + 1e-12)
+        assert len(levels) == _min_levels(v, tol), (v, tol)
+    # equal values share a level; one value is its own level times 1 / (1 + tol)
+    levels, mp = rte.rte_kappa_levels([2.0, 2.0, 2.0], 0.1)
+    assert len(levels) == 1 and np.all(mp == 0) and abs(levels[0] - 2.2) < 1e-15
+
+
+@pytest.mark.parametrize("values,tol,mx", [([1.0, -1.0], 0.1, 8), ([1.0, 2.0], 0.0, 8), ([1.0, 100.0], 0.1, 1),
+                                           ([np.nan], 0.1, 4)])
+def test_kappa_levels_validation(values, tol, mx):
+    with pytest.raises(rte.RteError):
+        rte.rte_kappa_levels(values, tol, mx)
