@@ -347,7 +347,9 @@ typedef struct {
 enum { RTE_LAUNCH_STREAM = 0, RTE_LAUNCH_GRAPH = 1 };
 
 typedef struct {
-    int32_t iterations;         /* matvec sweeps over all bands */
+    int32_t iterations;         /* matvec sweeps over all bands (from T0 = 0 the first sweep has a zero
+                                   source, G S = 0 exactly: it applies no operator and is counted here
+                                   but in neither matvecs_low nor matvecs_acc) */
     int32_t outer_steps;        /* FP64 defect-correction steps (mixed precision) */
     double residual;            /* final relative change of J */
     int64_t monotone_violations;/* vertex-steps where T decreased (from T0 = 0 it should be 0) */

@@ -327,9 +327,19 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
         }
         return ex;
     };
+    // The first sweep from T = 0 and J = 0 has a zero source (B(0) = 0): G S = 0
+    // exactly, so Jn = y0 without streaming the operator (the result is the same
+    // bit for bit: the products of zeros add +0)
+    bool zero_source = !d.T0;
     auto sweep = [&](int mode, const double *y0, bool newton, const double *sub) -> double {
         HIP_CHECK(hipEventRecord(e0, s));
-        if (d.launch == RTE_LAUNCH_GRAPH && !mv_events) {
+        const bool skip = zero_source;
+        zero_source = false;
+        if (skip) {
+            enqueue_pre(sub);   // S = 0 (the outer step keeps it as its source)
+            HIP_CHECK(hipMemcpyAsync(Jn.p, y0, Jn.bytes, hipMemcpyDeviceToDevice, s));
+            enqueue_post(newton);
+        } else if (d.launch == RTE_LAUNCH_GRAPH && !mv_events) {
             HIP_CHECK(hipGraphLaunch(graph_of(mode, y0, newton, sub, -1), s));
         } else if (d.launch == RTE_LAUNCH_GRAPH) {
             HIP_CHECK(hipGraphLaunch(graph_of(mode, y0, newton, sub, 0), s));
@@ -350,7 +360,7 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
         float ms = 0.0f;
         HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
         mv_ms += ms;
-        if (mv_events || d.launch != RTE_LAUNCH_GRAPH) {
+        if (!skip && (mv_events || d.launch != RTE_LAUNCH_GRAPH)) {
             float mm = 0.0f;
             HIP_CHECK(hipEventElapsedTime(&mm, m0, m1));
             op_ms[mode == kMatvecLow ? 0 : 1] += mm;

@@ -138,7 +138,8 @@ def test_graph_launch_equals_stream_launch(small, precision):
     # and every volume matvec timed
     Tt, Jt, stt = _solve(mesh, G, S, wl, Tw, precision, 1e-7, launch=rte.RTE_LAUNCH_GRAPH, time_matvecs=True)
     assert torch.equal(Tt, Ts) and torch.equal(Jt, Js) and stt["iterations"] == sts["iterations"]
-    assert stt["matvecs_low"] + stt["matvecs_acc"] == stt["iterations"]
+    # from T0 = 0 the first sweep has a zero source and streams no operator
+    assert stt["matvecs_low"] + stt["matvecs_acc"] == stt["iterations"] - 1
     assert stt["ms_matvec_acc"] > 0 and (precision != rte.RTE_MIXED_BF16 or stt["ms_matvec_low"] > 0)
     assert stg["ms_matvec_low"] == -1.0 and sts["matvecs_acc"] > 0
 
