@@ -484,7 +484,7 @@ def run_headline(args):
 
     def solve():
         return rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=False, nu=wl.nu, tol=wl.tol, max_iter=3000,
-                                         precision=p, time_matvecs=True)
+                                         precision=p, time_matvecs=True, history=True)
 
     for _ in range(args.warmup):
         st = solve()
@@ -548,7 +548,8 @@ def run_headline(args):
         "breakdown_ms_per_step": {"low_matvecs": low_ms / K, "accurate_matvecs": acc_ms / K,
                                   "rest_of_solve": (solve_ms - low_ms - acc_ms) / K},
         "solve": {"sweeps": sts[-1]["iterations"], "defect_steps": sts[-1]["outer_steps"],
-                  "residual": sts[-1]["residual"], "graphs": sts[-1]["graphs"]},
+                  "residual": sts[-1]["residual"], "graphs": sts[-1]["graphs"],
+                  "residuals": [float(f"{v:.3e}") for v in sts[-1]["residuals"]]},
         "assembly": {"wall_ms": wall_ms, "G": _hstats(gs), "S": _hstats(ss),
                      "entries_evaluated": gs["entries_evaluated"] + ss["entries_evaluated"]},
     }

@@ -342,6 +342,9 @@ typedef struct {
                               RTE_LAUNCH_GRAPH a sweep is then captured as three graphs, before the
                               matvec, the matvec and after it, with the events between them.  0: stream
                               launch still times the matvecs; graph launch times whole sweeps only */
+    double *residuals;     /* host [max_iter] or NULL: receives the residual of each sweep in order (the
+                              first stats.iterations entries are written; a mixed solve's defect steps
+                              and inner sweeps interleave as they ran) */
 } rte_solve_desc_t;
 
 enum { RTE_LAUNCH_STREAM = 0, RTE_LAUNCH_GRAPH = 1 };
@@ -352,7 +355,8 @@ typedef struct {
                                    but in neither matvecs_low nor matvecs_acc) */
     int32_t outer_steps;        /* FP64 defect-correction steps (mixed precision) */
     double residual;            /* final relative change of J */
-    int64_t monotone_violations;/* vertex-steps where T decreased (from T0 = 0 it should be 0) */
+    int64_t monotone_violations;/* vertex-steps where T decreased by more than 8 units of rounding
+                                   (2^-52 relative): from T0 = 0 it should be 0 */
     double ms_total, ms_matvec; /* ms_matvec: HIP-event time of the volume matvecs (graph launch without
                                    time_matvecs: of the whole sweeps) */
     int32_t graphs;             /* sweep graphs captured (RTE_LAUNCH_GRAPH) */

@@ -17,17 +17,6 @@ __device__ __forceinline__ double planck(double nu, double T) {
     return nu * nu * nu / expm1(x);
 }
 
-// B and dB/dT
-__device__ __forceinline__ void planck_d(double nu, double T, double &B, double &dB) {
-    B = 0.0;
-    dB = 0.0;
-    if (!(T > 0.0)) return;
-    const double x = nu / T;
-    if (x > 700.0) return;
-    const double e = expm1(x);
-    B = nu * nu * nu / e;
-    dB = B * ((e + 1.0) / e) * (x / T);
-}
 
 // The temperature T >= 0 solving sum_b c_b (J_b - B_{nu_b}(T)) = 0 with
 // c_b >= 0 (c_b = w_b kappa_b (1 - a_b)), started from Told.  band(b, nu, c, J)
@@ -40,24 +29,48 @@ __device__ __forceinline__ void planck_d(double nu, double T, double &B, double 
 // level and the iteration stops, whether or not that step lands strictly
 // inside the bracket (at the root the step rounds to nothing, and rejecting it
 // for a bisection would restart the search from the far end of the bracket).
-template <typename Band>
+//
+// NB > 0: the loops over the bands are unrolled to NB iterations guarded by
+// b < nb (nb <= NB), so that a caller can keep the bands' c_b and J_b in
+// registers; the sums are taken in the same order either way.
+template <int NB, typename F>
+__device__ __forceinline__ void for_bands(int nb, F f) {
+    if constexpr (NB > 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            if (b < nb) f(b);
+    } else {
+        for (int b = 0; b < nb; ++b) f(b);
+    }
+}
+
+template <int NB = 0, typename Band>
 __device__ double solve_temperature(int nb, double Told, Band band) {
     double f0 = 0.0;
-    for (int b = 0; b < nb; ++b) {
+    for_bands<NB>(nb, [&](int b) {
         double nu, c, j;
         band(b, nu, c, j);
         f0 += c * j;
-    }
+    });
     if (!(f0 > 0.0)) return 0.0;
+    // f and f' at t > 0: B = nu^3 r, dB/dT = B (1 + r) x / t with x = nu / t and
+    // r = 1 / (e^x - 1); one division per band
     auto f = [&](double t, double &df) {
         double s = 0.0, d = 0.0;
-        for (int b = 0; b < nb; ++b) {
-            double nu, c, j, B, dB;
+        const double it = 1.0 / t;
+        for_bands<NB>(nb, [&](int b) {
+            double nu, c, j;
             band(b, nu, c, j);
-            planck_d(nu, t, B, dB);
+            const double x = nu * it;
+            double B = 0.0, dB = 0.0;
+            if (x <= 700.0) {
+                const double r = 1.0 / expm1(x);
+                B = nu * nu * nu * r;
+                dB = B * (1.0 + r) * (x * it);
+            }
             s += c * (j - B);
             d -= c * dB;
-        }
+        });
         df = d;
         return s;
     };

@@ -39,8 +39,9 @@ __global__ void k_emission(BandParams bp, const double *__restrict__ Tw, int64_t
         Q[(int64_t)b * tot + k] = bp.grey ? kSigma * (T * T) * (T * T) : planck(bp.nu[b], T);
 }
 
+// S = (1 - a) B(T) + a J, minus sub (the source an inner sweep takes the change from) when given
 __global__ void k_source(BandParams bp, const double *__restrict__ T, const double *__restrict__ J, int64_t N,
-                         int nrhs, double *__restrict__ S) {
+                         int nrhs, const double *__restrict__ sub, double *__restrict__ S) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = N * nrhs;
     if (k >= tot) return;
@@ -49,7 +50,8 @@ __global__ void k_source(BandParams bp, const double *__restrict__ T, const doub
         const int64_t o = (int64_t)b * tot + k;
         const double ab = bp.a[b];
         const double e = bp.grey ? kSigma * (t * t) * (t * t) : planck(bp.nu[b], t);
-        S[o] = (1.0 - ab) * e + (ab != 0.0 ? ab * J[o] : 0.0);
+        const double v = (1.0 - ab) * e + (ab != 0.0 ? ab * J[o] : 0.0);
+        S[o] = sub ? v - sub[o] : v;
     }
 }
 
@@ -97,8 +99,13 @@ __global__ void k_resid_final(const double *__restrict__ part, int nvec, double 
 // Per vertex and right-hand side: T solving sum_b c_b (J_b - B_b(T)) = 0,
 // c_b = w_b kappa_b (1 - a_b).  Bracketed Newton: f decreases in T,
 // f(0) = sum c_b J_b > 0; a step leaving the bracket is replaced by bisection.
-__global__ void k_newton(BandParams bp, const double *__restrict__ J, const double *__restrict__ kap, int64_t N,
-                         int nrhs, double *__restrict__ T, unsigned long long *__restrict__ viol) {
+// NB > 0 (nb <= NB): each thread reads its bands' c_b and J_b once into
+// registers, and the Newton evaluations (every one a pass over the bands) run
+// on them; NB = 0 reads them from memory at each evaluation, for any nb.
+template <int NB>
+__global__ __launch_bounds__(256) void k_newton(BandParams bp, const double *__restrict__ J,
+                                                const double *__restrict__ kap, int64_t N, int nrhs,
+                                                double *__restrict__ T, unsigned long long *__restrict__ viol) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = N * nrhs;
     if (k >= tot) return;
@@ -108,6 +115,17 @@ __global__ void k_newton(BandParams bp, const double *__restrict__ J, const doub
     if (bp.grey) {
         const double j = J[k];
         Tn = j > 0.0 ? sqrt(sqrt(j / kSigma)) : 0.0;
+    } else if constexpr (NB > 0) {
+        double cc[NB], jj[NB];
+        for_bands<NB>(bp.nb, [&](int b) {
+            cc[b] = bp.w[b] * kap[(int64_t)b * N + i] * (1.0 - bp.a[b]);
+            jj[b] = J[(int64_t)b * tot + k];
+        });
+        Tn = solve_temperature<NB>(bp.nb, Told, [&](int b, double &nu, double &c, double &j) {
+            nu = bp.nu[b];
+            c = cc[b];
+            j = jj[b];
+        });
     } else {
         Tn = solve_temperature(bp.nb, Told, [&](int b, double &nu, double &c, double &j) {
             nu = bp.nu[b];
@@ -115,13 +133,19 @@ __global__ void k_newton(BandParams bp, const double *__restrict__ J, const doub
             j = J[(int64_t)b * tot + k];
         });
     }
-    if (Tn < Told) atomicAdd(viol, 1ull);
+    // a decrease beyond the rounding of the root (8 units of 2^-52 relative): at the
+    // converged state two sweeps' roots may differ in their last bits
+    if (Tn < Told * (1.0 - 8.0 * 2.220446049250313e-16)) atomicAdd(viol, 1ull);
     T[k] = Tn;
 }
 
-__global__ void k_sub(const double *__restrict__ a, const double *__restrict__ b, int64_t n, double *__restrict__ out) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) out[k] = a[k] - b[k];
+void newton_launch(const BandParams &bp, const double *J, const double *kap, int64_t N, int nrhs, double *T,
+                   unsigned long long *viol, hipStream_t s) {
+    const unsigned g = (unsigned)((N * nrhs + 255) / 256);
+    if (!bp.grey && bp.nb <= 8) k_newton<8><<<g, 256, 0, s>>>(bp, J, kap, N, nrhs, T, viol);
+    else if (!bp.grey && bp.nb <= 32) k_newton<32><<<g, 256, 0, s>>>(bp, J, kap, N, nrhs, T, viol);
+    else k_newton<0><<<g, 256, 0, s>>>(bp, J, kap, N, nrhs, T, viol);
+    HIP_LAUNCH_CHECK();
 }
 
 // Captured sweeps of one solve, keyed by what the captured launches bake in:
@@ -279,13 +303,9 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
     const bool mixed = d.precision == RTE_MIXED_BF16;
     DevBuf Jacc(mixed ? sizeof(double) * vecN * nb : 0), Sm(mixed ? sizeof(double) * vecN * nb : 0);
 
-    // one sweep: S = S(T, J) (minus Sm when given); Jn = y0 + G S over all bands;
-    // residual(J, Jn); T = T(Jn); J <- Jn.  The kernels only (no copies, no
-    // memsets), so that a sweep can be captured in a graph.
+    // the parts of a sweep: before the matvec, the matvec, after it
     auto enqueue_pre = [&](const double *sub) {
-        k_source<<<gN, 256, 0, s>>>(bp, T.as<double>(), J.as<double>(), N, nr, Sv.as<double>());
-        if (sub)
-            k_sub<<<(unsigned)((vecN * nb + 255) / 256), 256, 0, s>>>(Sv.as<double>(), sub, vecN * nb, Sv.as<double>());
+        k_source<<<gN, 256, 0, s>>>(bp, T.as<double>(), J.as<double>(), N, nr, sub, Sv.as<double>());
         HIP_LAUNCH_CHECK();
     };
     auto enqueue_mv = [&](int mode, const double *y0) {
@@ -295,10 +315,10 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
         k_resid_partial<<<dim3(kResidBlocks, nb * nr), 256, 0, s>>>(J.as<double>(), Jn.as<double>(), N,
                                                                      part.as<double>());
         k_resid_final<<<(nb * nr + 63) / 64, 64, 0, s>>>(part.as<double>(), nb * nr, res.as<double>());
-        if (newton)
-            k_newton<<<gN, 256, 0, s>>>(bp, Jn.as<double>(), G.kappa_c.as<double>(), N, nr, T.as<double>(),
-                                        viol.as<unsigned long long>());
         HIP_LAUNCH_CHECK();
+        if (newton)
+            newton_launch(bp, Jn.as<double>(), G.kappa_c.as<double>(), N, nr, T.as<double>(),
+                          viol.as<unsigned long long>(), s);
     };
     // one sweep: S = S(T, J) (minus Sm when given); Jn = y0 + G S over all bands;
     // residual(J, Jn); T = T(Jn); J <- Jn.  The kernels only (no copies, no
@@ -331,6 +351,7 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
     // exactly, so Jn = y0 without streaming the operator (the result is the same
     // bit for bit: the products of zeros add +0)
     bool zero_source = !d.T0;
+    int n_hist = 0;
     auto sweep = [&](int mode, const double *y0, bool newton, const double *sub) -> double {
         HIP_CHECK(hipEventRecord(e0, s));
         const bool skip = zero_source;
@@ -371,6 +392,7 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
             const double num = rv[2 * v], den = rv[2 * v + 1];
             q = std::max(q, den > 0.0 ? std::sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0));
         }
+        if (d.residuals && n_hist < d.max_iter) d.residuals[n_hist++] = q;
         return q;
     };
 
@@ -400,17 +422,23 @@ rte_status_t fixed_point_solve(const Mesh &m, const HMat &G, const HMat &S, cons
             if (!std::isfinite(r)) break;
             std::swap(Sm, Sv);   // S_m = the source of this outer step
             HIP_CHECK(hipMemcpyAsync(Jacc.p, Jn.p, Jacc.bytes, hipMemcpyDeviceToDevice, s));
-            k_newton<<<gN, 256, 0, s>>>(bp, Jn.as<double>(), G.kappa_c.as<double>(), N, nr, T.as<double>(),
-                                        viol.as<unsigned long long>());
-            HIP_LAUNCH_CHECK();
+            newton_launch(bp, Jn.as<double>(), G.kappa_c.as<double>(), N, nr, T.as<double>(),
+                          viol.as<unsigned long long>(), s);
             std::swap(J, Jn);
             if (r <= d.tol) { conv = true; break; }
             const double inner_tol = std::max(2e-3 * r, 0.25 * d.tol);
+            double r_prev = r;
             for (int k = 0; k < 200 && it < d.max_iter; ++k) {
                 const double ri = sweep(kMatvecLow, Jacc.as<double>(), true, Sm.as<double>());
                 ++it;
                 std::swap(J, Jn);
                 if (!std::isfinite(ri) || ri <= inner_tol) break;
+                // the sweeps contract J's change by rho = ri / r_prev each: when the
+                // next change, rho ri, is predicted within half the tolerance, the
+                // defect step (which decides convergence) comes next
+                const double rho = ri / r_prev;
+                if (rho < 1.0 && rho * ri <= 0.5 * d.tol) break;
+                r_prev = ri;
             }
         }
     }

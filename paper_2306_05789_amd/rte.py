@@ -63,7 +63,8 @@ class SolveDesc(C.Structure):
     _fields_ = [("n_bands", C.c_int32), ("nu", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
                 ("a", C.POINTER(C.c_double)), ("grey", C.c_int32), ("nrhs", C.c_int32),
                 ("T_wall", C.c_void_p), ("T0", C.c_void_p), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("precision", C.c_int32), ("launch", C.c_int32), ("time_matvecs", C.c_int32)]
+                ("precision", C.c_int32), ("launch", C.c_int32), ("time_matvecs", C.c_int32),
+                ("residuals", C.POINTER(C.c_double))]
 
 
 class SolveStats(C.Structure):
@@ -454,8 +455,10 @@ def rte_hmat_dense_block(hmat: HMat, band: int, index: int, op: int = 0):
 
 def rte_fixed_point_solve(mesh: Mesh, vol: HMat, surf: HMat, T_wall, T_out, J_out=None, *, grey=True,
                           nu=None, w=None, a=None, T0=None, tol=1e-10, max_iter=1000, precision=RTE_FP64,
-                          launch=None, stream=None, allow_not_converged=False, time_matvecs=False) -> dict:
-    """T_wall: float64 device [nrhs, L]; T_out: [nrhs, N]; J_out: [nrhs, n_bands, N] or None."""
+                          launch=None, stream=None, allow_not_converged=False, time_matvecs=False,
+                          history=False) -> dict:
+    """T_wall: float64 device [nrhs, L]; T_out: [nrhs, N]; J_out: [nrhs, n_bands, N] or None.
+    history: also return the residual of every sweep (numpy array, key "residuals")."""
     nrhs = 1 if T_wall.dim() == 1 else int(T_wall.shape[0])
     nb = 1 if grey else len(nu)
     d = SolveDesc()
@@ -468,12 +471,17 @@ def rte_fixed_point_solve(mesh: Mesh, vol: HMat, surf: HMat, T_wall, T_out, J_ou
     d.tol, d.max_iter, d.precision = float(tol), int(max_iter), int(precision)
     d.launch = RTE_LAUNCH_GRAPH if launch is None else int(launch)
     d.time_matvecs = int(bool(time_matvecs))
+    import numpy as np
+    hist = np.zeros(max(int(max_iter), 1)) if history else None
+    d.residuals = hist.ctypes.data_as(C.POINTER(C.c_double)) if history else None
     st = SolveStats()
     allow = (RTE_OK, RTE_E_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
     status = _check(load().rte_fixed_point_solve(mesh.handle, vol.handle, surf.handle, C.byref(d), _ptr(T_out),
                                                  _ptr(J_out), C.byref(st), _stream(stream)), allow)
     out = st.as_dict()
     out["converged"] = status == RTE_OK
+    if history:
+        out["residuals"] = hist[:out["iterations"]].copy()
     return out
 
 

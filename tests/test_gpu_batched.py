@@ -144,6 +144,23 @@ def test_graph_launch_equals_stream_launch(small, precision):
     assert stg["ms_matvec_low"] == -1.0 and sts["matvecs_acc"] > 0
 
 
+@pytest.mark.parametrize("precision", [rte.RTE_FP64, rte.RTE_MIXED_BF16])
+def test_residual_history(small, precision):
+    """The residual of every sweep: from J = 0 the first is exactly 1 (J^1 = S^E,
+    all of it new), the last is the reported one, at most tol."""
+    wl, mesh = small
+    G = _assemble(mesh, wl, rte.RTE_VOLUME, precision)
+    S = _assemble(mesh, wl, rte.RTE_SURFACE, precision)
+    Tw = torch.tensor(wl.T_wall[:2], device=DEV)
+    T = torch.empty((2, mesh.N), device=DEV, dtype=torch.float64)
+    st = rte.rte_fixed_point_solve(mesh, G, S, Tw, T, grey=False, nu=wl.nu, tol=1e-8, max_iter=3000,
+                                   precision=precision, history=True)
+    h = st["residuals"]
+    assert st["converged"] and len(h) == st["iterations"] > 2
+    assert h[0] == 1.0 and h[-1] == st["residual"] <= 1e-8
+    assert np.all(h[1:] < 1.0)
+
+
 def test_mixed_batched_solve_matches_oracle(small):
     """Mixed precision (FP32 entries and ACA, BF16 factors, FP64 defect correction),
     all bands and 4 right-hand sides at once, against the dense FP64 oracle per
