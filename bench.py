@@ -343,7 +343,8 @@ def run_served(args):
         legs.append(("fp64", rte.RTE_FP64, 1, reqs[:args.compare]))
     res = {}
     for name, prec, active, rq in legs:
-        srv = Server(nu, budget=int(args.budget_gb * 1e9), precision=prec, max_active=active)
+        srv = Server(nu, budget=int(args.budget_gb * 1e9), precision=prec, max_active=active,
+                     recompress=args.server_recompress)
         ids = [srv.add_mesh((n, n, n), torch.tensor(inputs.smooth_kappa(
             inputs.grid_positions((n, n, n), (0, 0, 0), (1, 1, 1))), device="cuda:0")) for n in meshes]
         t0 = time.perf_counter()
@@ -363,7 +364,7 @@ def run_served(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32 entries/ACA, bf16 factors, f64 correction" if "mixed" in res else "f64", "data": "synthetic",
            "config": {"workload": f"served_{head['requests']}req_poisson20", "meshes": list(meshes),
-                      "budget_GB": args.budget_gb},
+                      "budget_GB": args.budget_gb, "recompress": bool(args.server_recompress)},
            "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]}, "results": res}
     print(json.dumps(out))
 
@@ -934,6 +935,8 @@ def main():
     ap.add_argument("--requests", type=int, default=256,
                     help="served workload: requests of the stream served in mixed precision (0: none)")
     ap.add_argument("--budget-gb", type=float, default=250.0, help="served workload: HBM budget of the server")
+    ap.add_argument("--server-recompress", action="store_true",
+                    help="served workload: recompress the volume operators' ACA factors")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU band sharding is a design, not a build "

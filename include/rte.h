@@ -402,6 +402,8 @@ typedef struct {
     double eta, aca_eps;
     int32_t precision;           /* RTE_FP64 (plain sweeps) or RTE_MIXED_BF16 (defect-corrected) */
     int32_t max_active;          /* requests iterated together (1: one at a time) */
+    int32_t recompress;          /* 1: volume operators take the SVD recompression of their ACA factors
+                                    (rte_hmat_opts_t.recompress): smaller, longer to assemble */
 } rte_server_desc_t;
 
 typedef struct {

@@ -274,6 +274,7 @@ struct Server {
         o.eta = desc.eta;
         o.aca_eps = desc.aca_eps;
         o.precision = desc.precision;
+        o.recompress = kind == RTE_VOLUME ? desc.recompress : 0;
         return o;
     }
 
@@ -790,6 +791,7 @@ Server *server_create(const rte_server_desc_t &d, hipStream_t s) {
     RTE_REQUIRE(d.precision == RTE_FP64 || d.precision == RTE_MIXED_BF16,
                 "server: precision must be RTE_FP64 or RTE_MIXED_BF16");
     RTE_REQUIRE(d.max_active >= 1, "server: max_active must be >= 1");
+    RTE_REQUIRE(d.recompress == 0 || d.recompress == 1, "server: recompress must be 0 or 1");
     RTE_REQUIRE(d.hbm_budget >= 0, "server: hbm_budget must be >= 0");
     auto S = std::make_unique<Server>();
     S->desc = d;

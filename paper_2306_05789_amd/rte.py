@@ -87,7 +87,8 @@ class MatvecConfig(C.Structure):
 class ServerDesc(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("n_catalogue", C.c_int32), ("nu", C.POINTER(C.c_double)),
                 ("levels_per_decade", C.c_int32), ("leaf_size", C.c_int32), ("eta", C.c_double),
-                ("aca_eps", C.c_double), ("precision", C.c_int32), ("max_active", C.c_int32)]
+                ("aca_eps", C.c_double), ("precision", C.c_int32), ("max_active", C.c_int32),
+                ("recompress", C.c_int32)]
 
 
 class Request(C.Structure):

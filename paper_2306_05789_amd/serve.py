@@ -15,13 +15,13 @@ from . import rte
 
 class Server:
     def __init__(self, nu, *, budget=0, levels_per_decade=8, leaf_size=64, eta=2.0, aca_eps=1e-5,
-                 precision=rte.RTE_MIXED_BF16, max_active=64, stream=None):
+                 precision=rte.RTE_MIXED_BF16, max_active=64, recompress=False, stream=None):
         self._nu = np.ascontiguousarray(nu, dtype=np.float64)
         d = rte.ServerDesc()
         d.hbm_budget, d.n_catalogue = int(budget), len(self._nu)
         d.nu = self._nu.ctypes.data_as(C.POINTER(C.c_double))
         d.levels_per_decade, d.leaf_size, d.eta, d.aca_eps = int(levels_per_decade), int(leaf_size), eta, aca_eps
-        d.precision, d.max_active = int(precision), int(max_active)
+        d.precision, d.max_active, d.recompress = int(precision), int(max_active), int(bool(recompress))
         h = C.c_void_p()
         rte._check(rte.load().rte_server_create(C.byref(d), rte._stream(stream), C.byref(h)))
         self.handle = h
