@@ -21,7 +21,7 @@ class Server:
         d.hbm_budget, d.n_catalogue = int(budget), len(self._nu)
         d.nu = self._nu.ctypes.data_as(C.POINTER(C.c_double))
         d.levels_per_decade, d.leaf_size, d.eta, d.aca_eps = int(levels_per_decade), int(leaf_size), eta, aca_eps
-        d.precision, d.max_active, d.recompress = int(precision), int(max_active), int(bool(recompress))
+        d.precision, d.max_active, d.recompress = int(precision), int(max_active), int(recompress)
         h = C.c_void_p()
         rte._check(rte.load().rte_server_create(C.byref(d), rte._stream(stream), C.byref(h)))
         self.handle = h

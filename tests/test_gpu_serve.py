@@ -116,6 +116,40 @@ def test_served_request_matches_single_solve_and_oracle():
     assert np.max(np.abs(T_srv - ref.T) / ref.T) < 3e-4
 
 
+def test_recompressing_server_matches_single_solve_on_recompressed_operators():
+    """desc.recompress: the server's volume operators take the SVD recompression; a
+    request then matches the single solve on recompressed operators of its levels
+    (and not the one without it, which differs by the truncation)."""
+    n = 13
+    srv, ids = make_server([n], recompress=True)
+    bands = np.array([0, 2, 5])
+    Tw = np.random.default_rng(4).uniform(0.5, 2.0, inputs.n_emitting((n, n, n), inputs.ALL_FACES))
+    (T_srv,), (info,) = serve_all(srv, ids, [n], [inputs.Request(0.0, 0, bands, 0.8, Tw)], tol=1e-9)
+    assert info["converged"]
+    kb = 10.0 ** (np.asarray(info["levels"]) / 8.0)[:, None] * base_kappa(n)[None, :]
+    mesh = rte.rte_mesh_create((n, n, n), emit_faces=inputs.ALL_FACES)
+    kt = torch.tensor(kb, device=DEV)
+    S = rte.rte_hmat_assemble(mesh, kt, rte.hmat_opts(kind=rte.RTE_SURFACE, leaf_size=LEAF,
+                                                      precision=rte.RTE_MIXED_BF16))
+    errs = []
+    for rc in (True, False):
+        G = rte.rte_hmat_assemble(mesh, kt, rte.hmat_opts(kind=rte.RTE_VOLUME, leaf_size=LEAF,
+                                                          precision=rte.RTE_MIXED_BF16, recompress=rc))
+        if rc:
+            st = rte.rte_hmat_stats(G)
+            assert st["lowrank_entries"] < st["lowrank_entries_aca"]
+        T = torch.empty((1, mesh.N), device=DEV, dtype=torch.float64)
+        st = rte.rte_fixed_point_solve(mesh, G, S, torch.tensor(Tw[None, :], device=DEV), T, grey=False,
+                                       nu=NU[bands], w=catalogue_weights(NU)[bands], tol=1e-9, max_iter=2000,
+                                       precision=rte.RTE_MIXED_BF16)
+        assert st["converged"]
+        T1 = T.cpu().numpy()[0]
+        errs.append(np.max(np.abs(T_srv - T1) / T1))
+    assert errs[0] < 1e-8 and errs[1] > 10 * errs[0], errs
+    with pytest.raises(rte.RteError):
+        Server(NU, leaf_size=LEAF, recompress=2)
+
+
 def test_each_request_alone_equals_in_the_mix():
     """Requests on two meshes served together (shared operators, one multi-column
     matvec per operator, different phases of the defect correction side by side)
