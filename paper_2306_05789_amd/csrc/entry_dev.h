@@ -140,63 +140,66 @@ __device__ __forceinline__ TetSample<T> tet_sample(const GridDev &g, rsrc_t kr, 
     return {kload(kr, b, T()), kload(kr, v1, T()), kload(kr, v2, T()), kload(kr, v3, T()), hi, mid, lo};
 }
 
-// tau along the segment P -> Q given in grid coordinates, both in the closed
-// box.  The P1 kappa is linear between consecutive crossings of the six plane
-// families, so each piece contributes its length times kappa at its midpoint
-// (exact).  The next crossing time of family f advances by the constant
-// 1/|dF_f| per crossing; a crossing of family a (a < 3) moves the cell by one
-// along axis a, which updates its flat index and P's coordinates relative to
-// the cell corner.  Only the last crossing of a family can be taken a few
-// rounding units early (the segment ends on a vertex, that is on a plane of
-// every family); the piece that follows is of rounding length, and its
-// loads stay in bounds through the buffer resource.  The loop is software
-// pipelined: the kappa values of the next piece are loaded while the current
-// one is added (a piece of zero length, where two families cross together,
-// adds zero; after the last piece one more sample is loaded and unused).
+// The state of the march along one segment: start() sets it up for P -> Q
+// and samples the tetrahedron of its first piece; piece() moves the families
+// crossed at the end of the current piece on, samples the next piece's
+// tetrahedron into nxt (its loads run while this piece is added) and adds the
+// current one, true once that piece ends the segment; tau() is the optical
+// depth.
 template <typename T>
-__device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3]) {
-    const T D[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
-    const T wx = D[0] * (T)g.h[0], wy = D[1] * (T)g.h[1], wz = D[2] * (T)g.h[2];
-    const T len = sqrt(wx * wx + wy * wy + wz * wz);
-    if (len == (T)0) return (T)0;
-    const rsrc_t kr = kappa_rsrc(g, kap);
-    const T F0[6] = {P[0], P[1], P[2], P[0] - P[1], P[1] - P[2], P[0] - P[2]};
-    const T dF[6] = {D[0], D[1], D[2], D[0] - D[1], D[1] - D[2], D[0] - D[2]};
-    T tn[6], dt[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        if (dF[f] != (T)0) {
-            const T next = dF[f] > (T)0 ? floor(F0[f]) + (T)1 : ceil(F0[f]) - (T)1;
-            dt[f] = (T)1 / fabs(dF[f]);
-            tn[f] = (next - F0[f]) / dF[f];
-        } else {
-            dt[f] = (T)0;
-            tn[f] = (T)2;   // never before the end of the segment
-        }
-    }
-    // cell of the first piece: along a, the one the segment enters from P
-    // (the top cell when the segment lies in the top plane of a)
-    int b = 0, db[3];
-    T w[3], ws[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int sa = D[a] > (T)0 ? 1 : (D[a] < (T)0 ? -1 : 0);
-        int ca = D[a] < (T)0 ? (int)ceil(P[a]) - 1 : (int)floor(P[a]);
-        ca = min(max(ca, 0), g.n[a] - 2);
-        b += ca * g.stride[a];
-        db[a] = sa * g.stride[a];
-        w[a] = P[a] - (T)ca;
-        ws[a] = (T)sa;
-    }
-    auto next_end = [&]() {
+struct March {
+    T D[3], tn[6], dt[6], w[3], ws[3];
+    T len, tp, t, acc;
+    int b, db[3];
+
+    __device__ __forceinline__ T next_end() const {
         return fmin_finite(fmin_finite(fmin_finite(tn[0], tn[1]), fmin_finite(tn[2], tn[3])),
                            fmin_finite(fmin_finite(tn[4], tn[5]), (T)1));
-    };
-    T tp = (T)0, t = next_end(), acc = (T)0;
-    // one piece: the families crossed at t move on (the cell follows the axis
-    // families), the next piece's tetrahedron is sampled, this piece is added;
-    // true once the piece ends the segment
-    auto piece = [&](const TetSample<T> &cur, TetSample<T> &nxt) {
+    }
+
+    // false when the segment has zero length (tau = 0, nothing sampled)
+    __device__ __forceinline__ bool start(const GridDev &g, rsrc_t kr, const T P[3], const T Q[3],
+                                          TetSample<T> &first) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) D[a] = Q[a] - P[a];
+        const T wx = D[0] * (T)g.h[0], wy = D[1] * (T)g.h[1], wz = D[2] * (T)g.h[2];
+        len = sqrt(wx * wx + wy * wy + wz * wz);
+        if (len == (T)0) return false;
+        const T F0[6] = {P[0], P[1], P[2], P[0] - P[1], P[1] - P[2], P[0] - P[2]};
+        const T dF[6] = {D[0], D[1], D[2], D[0] - D[1], D[1] - D[2], D[0] - D[2]};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (dF[f] != (T)0) {
+                const T next = dF[f] > (T)0 ? floor(F0[f]) + (T)1 : ceil(F0[f]) - (T)1;
+                dt[f] = (T)1 / fabs(dF[f]);
+                tn[f] = (next - F0[f]) / dF[f];
+            } else {
+                dt[f] = (T)0;
+                tn[f] = (T)2;   // never before the end of the segment
+            }
+        }
+        // cell of the first piece: along a, the one the segment enters from P
+        // (the top cell when the segment lies in the top plane of a)
+        b = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int sa = D[a] > (T)0 ? 1 : (D[a] < (T)0 ? -1 : 0);
+            int ca = D[a] < (T)0 ? (int)ceil(P[a]) - 1 : (int)floor(P[a]);
+            ca = min(max(ca, 0), g.n[a] - 2);
+            b += ca * g.stride[a];
+            db[a] = sa * g.stride[a];
+            w[a] = P[a] - (T)ca;
+            ws[a] = (T)sa;
+        }
+        tp = (T)0;
+        t = next_end();
+        acc = (T)0;
+        const T tm0 = (T)0.5 * t;
+        first = tet_sample(g, kr, b, w[0] + tm0 * D[0], w[1] + tm0 * D[1], w[2] + tm0 * D[2]);
+        return true;
+    }
+
+    __device__ __forceinline__ bool piece(const GridDev &g, rsrc_t kr, const TetSample<T> &cur, TetSample<T> &nxt) {
         const bool last = t >= (T)1;
 #pragma unroll
         for (int f = 0; f < 3; ++f)
@@ -215,18 +218,41 @@ __device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[
         tp = t;
         t = tq;
         return last;
-    };
-    const T tm0 = (T)0.5 * t;
-    // two named samples in turn, so that no copy closes the loop
-    TetSample<T> sa = tet_sample(g, kr, b, w[0] + tm0 * D[0], w[1] + tm0 * D[1], w[2] + tm0 * D[2]), sb;
-    // every step advances at least one family; the pieces number at most
-    // sum_f |dF_f| + 7 <= 3 (|D0|+|D1|+|D2|) + 7
-    const int cap = 3 * (g.n[0] + g.n[1] + g.n[2]) + 16;
-    for (int it = 0; it < cap; it += 2) {
-        if (piece(sa, sb)) break;
-        if (piece(sb, sa)) break;
     }
-    return len * acc;
+
+    __device__ __forceinline__ T tau() const { return len * acc; }
+};
+
+// every piece advances at least one family: a segment has at most
+// sum_f |dF_f| + 7 <= 3 (|D0|+|D1|+|D2|) + 7 pieces
+__device__ __forceinline__ int march_cap(const GridDev &g) { return 3 * (g.n[0] + g.n[1] + g.n[2]) + 16; }
+
+// tau along the segment P -> Q given in grid coordinates, both in the closed
+// box.  The P1 kappa is linear between consecutive crossings of the six plane
+// families, so each piece contributes its length times kappa at its midpoint
+// (exact).  The next crossing time of family f advances by the constant
+// 1/|dF_f| per crossing; a crossing of family a (a < 3) moves the cell by one
+// along axis a, which updates its flat index and P's coordinates relative to
+// the cell corner.  Only the last crossing of a family can be taken a few
+// rounding units early (the segment ends on a vertex, that is on a plane of
+// every family); the piece that follows is of rounding length, and its
+// loads stay in bounds through the buffer resource.  The loop is software
+// pipelined: the kappa values of the next piece are loaded while the current
+// one is added (a piece of zero length, where two families cross together,
+// adds zero; after the last piece one more sample is loaded and unused).
+template <typename T>
+__device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3]) {
+    const rsrc_t kr = kappa_rsrc(g, kap);
+    March<T> m;
+    // two named samples in turn, so that no copy closes the loop
+    TetSample<T> sa, sb;
+    if (!m.start(g, kr, P, Q, sa)) return (T)0;
+    const int cap = march_cap(g);
+    for (int it = 0; it < cap; it += 2) {
+        if (m.piece(g, kr, sa, sb)) break;
+        if (m.piece(g, kr, sb, sa)) break;
+    }
+    return m.tau();
 }
 
 // Wall w's axis, side and coefficient, picked by selects over the constant
