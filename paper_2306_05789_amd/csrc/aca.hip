@@ -622,7 +622,7 @@ int64_t stored_v(const HMat &H, int64_t s0, int64_t s1, int64_t k) {
 }
 
 template <typename T>
-void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Block> &blocks, bool pair,
+void fill_dense_blocks(HMat &H, BandStore &B, BandKappa<T> kap, const std::vector<Block> &blocks, bool pair,
                        hipStream_t s) {
     if (blocks.empty()) return;
     const Plan &P = *H.plan;
@@ -687,7 +687,7 @@ void fill_dense_blocks(HMat &H, BandStore &B, const T *kap, const std::vector<Bl
 // at its cap goes to `retry` when its storage break-even rank exceeds the cap
 // (the next pass runs it again with a larger one), else to `fallback` (dense).
 template <typename T>
-void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &tasks, const std::vector<size_t> &ids,
+void aca_batch(HMat &H, BandStore &B, BandKappa<T> kap, const std::vector<AcaTask> &tasks, const std::vector<size_t> &ids,
                int64_t uo, int64_t vo, std::vector<Block> &fallback, std::vector<size_t> &retry, hipStream_t s) {
     {   // an earlier batch's scratch is freed first (a fill's task list may stay queued)
         size_t pending = 0;
@@ -943,7 +943,7 @@ void aca_batch(HMat &H, BandStore &B, const T *kap, const std::vector<AcaTask> &
 }
 
 template <typename T>
-void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
+void run_aca(HMat &H, BandStore &B, BandKappa<T> kap, hipStream_t s) {
     const Plan &P = *H.plan;
     const size_t nlr = P.lowrank.size();
     B.rank.assign(nlr, -1);
@@ -1007,7 +1007,7 @@ void run_aca(HMat &H, BandStore &B, const T *kap, hipStream_t s) {
 }
 
 template <typename T>
-void assemble_typed(HMat &H, int band, const T *kap, hipStream_t s) {
+void assemble_typed(HMat &H, int band, BandKappa<T> kap, hipStream_t s) {
     BandStore &B = H.bands[band];
     fill_dense_blocks<T>(H, B, kap, H.plan->dense, H.kind == RTE_VOLUME, s);
     run_aca<T>(H, B, kap, s);
@@ -1016,13 +1016,19 @@ void assemble_typed(HMat &H, int band, const T *kap, hipStream_t s) {
 }  // namespace
 
 void assemble_band(HMat &H, int band, const double *kappa_band, hipStream_t s) {
+    // FP32: the band's kappa and its tetrahedron table go to B.retire only
+    // after every launch reading them is queued (band_settle, which an ACA
+    // batch may call, releases what B.retire holds)
+    BandStore &B = H.bands[band];
     if (H.precision == RTE_FP64) {
-        assemble_typed<double>(H, band, kappa_band, s);
+        assemble_typed<double>(H, band, BandKappa<double>{kappa_band, nullptr}, s);
     } else {
         DevBuf kf = DevBuf::scratch(sizeof(float) * (size_t)H.mesh->N);
         to_float(kappa_band, kf.as<float>(), H.mesh->N, s);
-        assemble_typed<float>(H, band, kf.as<float>(), s);
-        H.bands[band].retire.push_back(std::move(kf));   // read by queued launches
+        DevBuf kt = tet_table<float>(*H.mesh, kf.as<float>(), s);
+        assemble_typed<float>(H, band, BandKappa<float>{kf.as<float>(), kt.as<float>()}, s);
+        B.retire.push_back(std::move(kf));
+        B.retire.push_back(std::move(kt));
     }
 }
 

@@ -93,42 +93,75 @@ void to_float(const double *in, float *out, int64_t n, hipStream_t s) {
     HIP_LAUNCH_CHECK();
 }
 
+// The four vertex values of every (cell base b, Kuhn tetrahedron t) pair, in
+// the order tet_sample reads them: b, b + s_L, b + s0 + s1 + 1 - s_S and
+// b + s0 + s1 + 1, L and S the tetrahedron's largest and smallest axes
+// (t = 2 L + (S > L ? S - 1 : S)).  A vertex past the grid (bases on the
+// upper faces) gives 0.
 template <typename T>
-EntryCtx<T> make_ctx(const Mesh &m, const T *kappa) {
+__global__ void k_tet_table(GridDev g, const T *__restrict__ kap, T *__restrict__ out) {
+    const int64_t N = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N * 6) return;
+    const int64_t b = k / 6;
+    const int t = (int)(k - b * 6), L = t >> 1, r = t & 1, S = r < L ? r : r + 1;
+    const int64_t s0 = g.stride[0], s1 = g.stride[1];
+    const int64_t sL = L == 0 ? s0 : (L == 1 ? s1 : 1), sS = S == 0 ? s0 : (S == 1 ? s1 : 1);
+    const int64_t v3 = b + s0 + s1 + 1;
+    const int64_t v1 = b + sL, v2 = v3 - sS;
+    out[4 * k + 0] = kap[b];
+    out[4 * k + 1] = v1 < N ? kap[v1] : (T)0;
+    out[4 * k + 2] = v2 < N ? kap[v2] : (T)0;
+    out[4 * k + 3] = v3 < N ? kap[v3] : (T)0;
+}
+
+template <typename T>
+DevBuf tet_table(const Mesh &m, const T *kappa, hipStream_t s) {
+    DevBuf d = DevBuf::scratch(sizeof(T) * (size_t)m.N * 24);
+    const int64_t n = m.N * 6;
+    k_tet_table<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(m.dev, kappa, d.as<T>());
+    HIP_LAUNCH_CHECK();
+    return d;
+}
+template DevBuf tet_table<float>(const Mesh &, const float *, hipStream_t);
+
+template <typename T>
+EntryCtx<T> make_ctx(const Mesh &m, BandKappa<T> kappa) {
     EntryCtx<T> c;
     c.g = m.dev;
-    c.kappa = kappa;
+    c.kappa = kappa.v;
+    c.ktet = kappa.tet;
     c.near = static_cast<const T *>(m.near_table(std::is_same<T, double>::value));
     if constexpr (std::is_same<T, double>::value) c.st = stencil_device().d;
     else c.st = stencil_device().f;
     return c;
 }
-template EntryCtx<double> make_ctx<double>(const Mesh &, const double *);
-template EntryCtx<float> make_ctx<float>(const Mesh &, const float *);
+template EntryCtx<double> make_ctx<double>(const Mesh &, BandKappa<double>);
+template EntryCtx<float> make_ctx<float>(const Mesh &, BandKappa<float>);
 
 void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, const int64_t *rows,
                     const int64_t *cols, double *out, int precision, hipStream_t s) {
     if (n == 0) return;
     const unsigned grid = (unsigned)((n + 255) / 256);
     if (precision == RTE_FP64) {
-        auto c = make_ctx<double>(m, kappa);
+        auto c = make_ctx<double>(m, BandKappa<double>{kappa, nullptr});
         if (kind == RTE_VOLUME) k_entries<double, RTE_VOLUME><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
         else k_entries<double, RTE_SURFACE><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
+        HIP_LAUNCH_CHECK();
     } else {
         DevBuf kf(sizeof(float) * (size_t)m.N);
         to_float(kappa, kf.as<float>(), m.N, s);
-        auto c = make_ctx<float>(m, kf.as<float>());
+        DevBuf kt = tet_table<float>(m, kf.as<float>(), s);
+        auto c = make_ctx<float>(m, BandKappa<float>{kf.as<float>(), kt.as<float>()});
         if (kind == RTE_VOLUME) k_entries<float, RTE_VOLUME><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
         else k_entries<float, RTE_SURFACE><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
         HIP_LAUNCH_CHECK();
-        HIP_CHECK(hipStreamSynchronize(s));   // kf is released on return
-        return;
+        HIP_CHECK(hipStreamSynchronize(s));   // kf and kt are released on return
     }
-    HIP_LAUNCH_CHECK();
 }
 
 template <typename T>
-void dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
+void dense_fill_launch(const Mesh &m, int kind, BandKappa<T> kappa, const std::vector<FillTask> &tasks,
                        const int64_t *tgt_nat, const int64_t *src_nat, SliceMap sm, bool split, BandStore &B,
                        hipStream_t s) {
     if (tasks.empty()) return;
@@ -172,9 +205,9 @@ void dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vecto
     B.fill_events.push_back(std::move(ev));
     B.retire.push_back(std::move(dt));   // read by the queued launches
 }
-template void dense_fill_launch<double>(const Mesh &, int, const double *, const std::vector<FillTask> &,
+template void dense_fill_launch<double>(const Mesh &, int, BandKappa<double>, const std::vector<FillTask> &,
                                         const int64_t *, const int64_t *, SliceMap, bool, BandStore &, hipStream_t);
-template void dense_fill_launch<float>(const Mesh &, int, const float *, const std::vector<FillTask> &,
+template void dense_fill_launch<float>(const Mesh &, int, BandKappa<float>, const std::vector<FillTask> &,
                                        const int64_t *, const int64_t *, SliceMap, bool, BandStore &, hipStream_t);
 
 }  // namespace rte

@@ -29,6 +29,8 @@ template <typename T>
 struct EntryCtx {
     GridDev g;
     const T *__restrict__ kappa;   // [N] P1 vertex values of one band
+    const T *__restrict__ ktet;    // FP32: [N][6][4], per cell base corner and Kuhn tetrahedron its four
+                                   // vertex values in the order of tet_sample (k_tet_table); FP64: unused
     StencilDev<T> st;
     const T *__restrict__ near;    // quadrature tables of the mesh: near [125][8][8], then far [24][4][8]
 };
@@ -97,20 +99,6 @@ __device__ __forceinline__ float fmin_finite(float a, float b) {
     return r;
 }
 
-// kappa is read through a buffer resource sized to the grid: an index
-// outside [0, N) returns 0 instead of touching other memory.
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-template <typename T>
-__device__ __forceinline__ rsrc_t kappa_rsrc(const GridDev &g, const T *kap) {
-    const int bytes = g.n[0] * g.n[1] * g.n[2] * (int)sizeof(T);
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(kap), (short)0, bytes, 0x00020000);
-}
-__device__ __forceinline__ double kload(rsrc_t r, int idx, double) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
-}
-__device__ __forceinline__ float kload(rsrc_t r, int idx, float) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
-}
 
 // The four vertex values of the Kuhn tetrahedron of a point in the cell with
 // flat base index b, at local coordinates (u0, u1, u2) in [0, 1]^3 (grid
@@ -127,17 +115,63 @@ struct TetSample {
 // coordinate, then that of the middle one.  Ties pick the lowest axis as the
 // largest and the highest axis as the smallest, so the two never coincide
 // (the value is continuous across the faces the ties lie on).
+//
+// The vertices are b, b + s_L, b + s0 + s1 + 1 - s_S and b + s0 + s1 + 1 (s_a
+// the axis strides, L and S the largest and smallest axes).  src is what the
+// march reads kappa from (KappaSrc<T>):
+//   FP32: the table of every (cell base, tetrahedron) pair, the tetrahedron
+//   numbered t = 2 L + (S > L ? S - 1 : S): one 16-byte load per piece
+//   instead of four gathers over the grid (the ACA entry launches of the 41^3
+//   operator 98.6 -> 78.0 ms).  A base outside the grid (only the unused
+//   sample after a segment's last piece, or a piece of rounding length) reads
+//   the nearest row.
+//   FP64: the vertex values, through a buffer resource sized to the grid (an
+//   index outside [0, N) returns 0); the 32-byte rows of a table were no
+//   faster there.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
 template <typename T>
-__device__ __forceinline__ TetSample<T> tet_sample(const GridDev &g, rsrc_t kr, int b, T u0, T u1, T u2) {
-    const int S0 = g.stride[0], S1 = g.stride[1];
+struct KappaSrc;
+template <>
+struct KappaSrc<float> {
+    const float *__restrict__ tet;   // [N][6][4]
+};
+template <>
+struct KappaSrc<double> {
+    rsrc_t kr;
+};
+__device__ __forceinline__ KappaSrc<float> kappa_src(const GridDev &, const float *, const float *ktet) {
+    return {ktet};
+}
+__device__ __forceinline__ KappaSrc<double> kappa_src(const GridDev &g, const double *kap, const double *) {
+    const int bytes = g.n[0] * g.n[1] * g.n[2] * (int)sizeof(double);
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(kap), (short)0, bytes, 0x00020000)};
+}
+__device__ __forceinline__ double kload(rsrc_t r, int idx) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ TetSample<T> tet_sample(const GridDev &g, const KappaSrc<T> &src, int b, T u0, T u1,
+                                                   T u2) {
     const bool c01 = u0 >= u1, c02 = u0 >= u2, c12 = u1 >= u2;
-    const int smax = (c01 && c02) ? S0 : (c12 ? S1 : 1);
-    const int smin = (c02 && c12) ? 1 : (c01 ? S1 : S0);
     const T hi = fmax(fmax(u0, u1), u2), lo = fmin(fmin(u0, u1), u2);
     const T mid = fmax(fmin(u0, u1), fmin(fmax(u0, u1), u2));
-    const int v3 = b + S0 + S1 + 1;
-    const int v1 = b + smax, v2 = v3 - smin;
-    return {kload(kr, b, T()), kload(kr, v1, T()), kload(kr, v2, T()), kload(kr, v3, T()), hi, mid, lo};
+    if constexpr (sizeof(T) == 4) {
+        const int L = (c01 && c02) ? 0 : (c12 ? 1 : 2);
+        const int S = (c02 && c12) ? 2 : (c01 ? 1 : 0);
+        const int t = 2 * L + (S > L ? S - 1 : S);
+        const int nv = g.n[0] * g.n[1] * g.n[2];
+        const int bc = min(max(b, 0), nv - 1);
+        const float4 q = *reinterpret_cast<const float4 *>(src.tet + ((int64_t)bc * 6 + t) * 4);
+        return {q.x, q.y, q.z, q.w, hi, mid, lo};
+    } else {
+        const int S0 = g.stride[0], S1 = g.stride[1];
+        const int smax = (c01 && c02) ? S0 : (c12 ? S1 : 1);
+        const int smin = (c02 && c12) ? 1 : (c01 ? S1 : S0);
+        const int v3 = b + S0 + S1 + 1;
+        const int v1 = b + smax, v2 = v3 - smin;
+        return {kload(src.kr, b), kload(src.kr, v1), kload(src.kr, v2), kload(src.kr, v3), hi, mid, lo};
+    }
 }
 
 // The state of the march along one segment: start() sets it up for P -> Q
@@ -158,7 +192,7 @@ struct March {
     }
 
     // false when the segment has zero length (tau = 0, nothing sampled)
-    __device__ __forceinline__ bool start(const GridDev &g, rsrc_t kr, const T P[3], const T Q[3],
+    __device__ __forceinline__ bool start(const GridDev &g, const KappaSrc<T> &kt, const T P[3], const T Q[3],
                                           TetSample<T> &first) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) D[a] = Q[a] - P[a];
@@ -195,11 +229,12 @@ struct March {
         t = next_end();
         acc = (T)0;
         const T tm0 = (T)0.5 * t;
-        first = tet_sample(g, kr, b, w[0] + tm0 * D[0], w[1] + tm0 * D[1], w[2] + tm0 * D[2]);
+        first = tet_sample(g, kt, b, w[0] + tm0 * D[0], w[1] + tm0 * D[1], w[2] + tm0 * D[2]);
         return true;
     }
 
-    __device__ __forceinline__ bool piece(const GridDev &g, rsrc_t kr, const TetSample<T> &cur, TetSample<T> &nxt) {
+    __device__ __forceinline__ bool piece(const GridDev &g, const KappaSrc<T> &kt, const TetSample<T> &cur,
+                                          TetSample<T> &nxt) {
         const bool last = t >= (T)1;
 #pragma unroll
         for (int f = 0; f < 3; ++f)
@@ -213,7 +248,7 @@ struct March {
             if (tn[f] <= t) tn[f] += dt[f];
         const T tq = next_end();
         const T tm = (T)0.5 * (t + tq);
-        nxt = tet_sample(g, kr, b, w[0] + tm * D[0], w[1] + tm * D[1], w[2] + tm * D[2]);
+        nxt = tet_sample(g, kt, b, w[0] + tm * D[0], w[1] + tm * D[1], w[2] + tm * D[2]);
         acc += (t - tp) * cur.value();
         tp = t;
         t = tq;
@@ -241,16 +276,15 @@ __device__ __forceinline__ int march_cap(const GridDev &g) { return 3 * (g.n[0] 
 // one is added (a piece of zero length, where two families cross together,
 // adds zero; after the last piece one more sample is loaded and unused).
 template <typename T>
-__device__ T tau_segment(const GridDev &g, const T *__restrict__ kap, const T P[3], const T Q[3]) {
-    const rsrc_t kr = kappa_rsrc(g, kap);
+__device__ T tau_segment(const GridDev &g, const KappaSrc<T> &kt, const T P[3], const T Q[3]) {
     March<T> m;
     // two named samples in turn, so that no copy closes the loop
     TetSample<T> sa, sb;
-    if (!m.start(g, kr, P, Q, sa)) return (T)0;
+    if (!m.start(g, kt, P, Q, sa)) return (T)0;
     const int cap = march_cap(g);
     for (int it = 0; it < cap; it += 2) {
-        if (m.piece(g, kr, sa, sb)) break;
-        if (m.piece(g, kr, sb, sa)) break;
+        if (m.piece(g, kt, sa, sb)) break;
+        if (m.piece(g, kt, sb, sa)) break;
     }
     return m.tau();
 }
@@ -273,7 +307,7 @@ __device__ __forceinline__ WallInfo wall_info(const GridDev &g, int w) {
 // Optical depth of the path from x (grid coords P) to wall w and on to y (Q),
 // the wall point being where the segment from the mirror image of x to y meets it.
 template <typename T>
-__device__ T tau_mirror(const GridDev &g, int w, const T *__restrict__ kap, const T P[3], const T Q[3]) {
+__device__ T tau_mirror(const GridDev &g, int w, const KappaSrc<T> &kt, const T P[3], const T Q[3]) {
     const WallInfo wi = wall_info(g, w);
     const int a = wi.axis;
     const T C = wi.side ? (T)(g.n[a] - 1) : (T)0;
@@ -289,7 +323,7 @@ __device__ T tau_mirror(const GridDev &g, int w, const T *__restrict__ kap, cons
         for (int b = 0; b < 3; ++b) X[b] = Pb[b] + t * (Q[b] - Pb[b]);
         X[a] = C;
     }
-    return tau_segment(g, kap, P, X) + tau_segment(g, kap, X, Q);
+    return tau_segment(g, kt, P, X) + tau_segment(g, kt, X, Q);
 }
 
 // grid index of the mirror image of vertex xi in wall w
@@ -569,19 +603,19 @@ __device__ __forceinline__ T vol_sum(const EntryCtx<T> &c, T att, const T att_w[
 // that the hole blocks has tau = +infinity (no march).  Pi, Qi: the vertices'
 // grid indices, P, Q the same as reals.
 template <typename T, int NW>
-__device__ __forceinline__ T attenuations(const GridDev &g, const T *__restrict__ kap, const int Pi[3],
+__device__ __forceinline__ T attenuations(const GridDev &g, const KappaSrc<T> &kt, const int Pi[3],
                                           const int Qi[3], const T P[3], const T Q[3], T att_w[6]) {
     if constexpr (NW == kAnyWalls) {
         const bool hole = g.has_hole;
-        const T att = (hole && hole_blocks(g, Pi, Qi)) ? (T)0 : exp(-tau_segment(g, kap, P, Q));
+        const T att = (hole && hole_blocks(g, Pi, Qi)) ? (T)0 : exp(-tau_segment(g, kt, P, Q));
         for (int w = 0; w < g.n_walls; ++w)
             att_w[w] = (hole && hole_blocks_mirror(g, w, Pi, Qi))
                            ? (T)0
-                           : (T)wall_info(g, w).R * exp(-tau_mirror(g, w, kap, P, Q));
+                           : (T)wall_info(g, w).R * exp(-tau_mirror(g, w, kt, P, Q));
         return att;
     } else {
-        const T att = exp(-tau_segment(g, kap, P, Q));
-        if constexpr (NW == kOneWall) att_w[0] = (T)g.R[0] * exp(-tau_mirror(g, 0, kap, P, Q));
+        const T att = exp(-tau_segment(g, kt, P, Q));
+        if constexpr (NW == kOneWall) att_w[0] = (T)g.R[0] * exp(-tau_mirror(g, 0, kt, P, Q));
         return att;
     }
 }
@@ -600,7 +634,7 @@ __device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
     T att_w[6];
-    const T att = attenuations<T, NW>(g, c.kappa, ii, jj, P, Q, att_w);
+    const T att = attenuations<T, NW>(g, kappa_src(g, c.kappa, c.ktet), ii, jj, P, Q, att_w);
     return vol_sum<T, NW>(c, att, att_w, ii, jj);
 }
 
@@ -616,7 +650,7 @@ __device__ __forceinline__ void volume_entry_pair(const EntryCtx<T> &c, int64_t 
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
     T att_w[6];
-    const T att = attenuations<T, NW>(g, c.kappa, ii, jj, P, Q, att_w);
+    const T att = attenuations<T, NW>(g, kappa_src(g, c.kappa, c.ktet), ii, jj, P, Q, att_w);
     gij = vol_sum<T, NW>(c, att, att_w, ii, jj);
     gji = vol_sum<T, NW>(c, att, att_w, jj, ii);
     if constexpr (NW == kAnyWalls) {   // removed vertices have zero rows
@@ -804,7 +838,7 @@ __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
     if constexpr (NW == kAnyWalls) {
         if (!vertex_active(g, ii)) return (T)0;   // a removed vertex
         T att_w[6];
-        const T att = attenuations<T, NW>(g, c.kappa, ii, ll, P, Q, att_w);
+        const T att = attenuations<T, NW>(g, kappa_src(g, c.kappa, c.ktet), ii, ll, P, Q, att_w);
         T S = att == (T)0 ? (T)0 : att * surf_quad_rects(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
         for (int w = 0; w < g.n_walls; ++w) {
             if (att_w[w] == (T)0) continue;
@@ -814,11 +848,12 @@ __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
         }
         return S;
     } else {
-        T S = exp(-tau_segment(g, c.kappa, P, Q)) * surf_quad(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
+        const KappaSrc<T> ks = kappa_src(g, c.kappa, c.ktet);
+        T S = exp(-tau_segment(g, ks, P, Q)) * surf_quad(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
         if constexpr (NW == kOneWall) {
             int mi[3];
             mirror_index(g, 0, ii, mi);
-            S += (T)g.R[0] * exp(-tau_mirror(g, 0, c.kappa, P, Q)) * surf_quad(c, mi, ll, cheb3(mi, ll) <= kNearCheb);
+            S += (T)g.R[0] * exp(-tau_mirror(g, 0, ks, P, Q)) * surf_quad(c, mi, ll, cheb3(mi, ll) <= kNearCheb);
         }
         return S;
     }

@@ -113,12 +113,23 @@ struct EventTimer {
 };
 
 template <typename T> struct EntryCtx;
-template <typename T> EntryCtx<T> make_ctx(const Mesh &m, const T *kappa);
+// One band's absorption as the entry kernels read it: the vertex values and,
+// in FP32, the table of the four vertex values of every (cell base, Kuhn
+// tetrahedron) pair that the ray march samples (tet_table).
+template <typename T>
+struct BandKappa {
+    const T *v;     // [N]
+    const T *tet;   // FP32: [N][6][4]; FP64: null (the march gathers from v)
+};
+template <typename T> EntryCtx<T> make_ctx(const Mesh &m, BandKappa<T> kappa);
+// the FP32 table of `kappa` on the mesh, queued on s (scratch; the caller keeps
+// it until the launches that read it have run)
+template <typename T> DevBuf tet_table(const Mesh &m, const T *kappa, hipStream_t s);
 void to_float(const double *in, float *out, int64_t n, hipStream_t s);
 // queues the fill on s without waiting: the task list and the launch's event
 // pair go to B.retire / B.fill_events (read by band_settle); split: write BF16 hi/lo
 template <typename T>
-void dense_fill_launch(const Mesh &m, int kind, const T *kappa, const std::vector<FillTask> &tasks,
+void dense_fill_launch(const Mesh &m, int kind, BandKappa<T> kappa, const std::vector<FillTask> &tasks,
                        const int64_t *tgt_nat, const int64_t *src_nat, SliceMap sm, bool split, BandStore &B,
                        hipStream_t s);
 
