@@ -1016,12 +1016,14 @@ void assemble_typed(HMat &H, int band, BandKappa<T> kap, hipStream_t s) {
 }  // namespace
 
 void assemble_band(HMat &H, int band, const double *kappa_band, hipStream_t s) {
-    // FP32: the band's kappa and its tetrahedron table go to B.retire only
-    // after every launch reading them is queued (band_settle, which an ACA
-    // batch may call, releases what B.retire holds)
+    // the band's kappa buffers go to B.retire only after every launch reading
+    // them is queued (band_settle, which an ACA batch may call, releases what
+    // B.retire holds)
     BandStore &B = H.bands[band];
     if (H.precision == RTE_FP64) {
-        assemble_typed<double>(H, band, BandKappa<double>{kappa_band, nullptr}, s);
+        DevBuf kt = tet_table<double>(*H.mesh, kappa_band, s);
+        assemble_typed<double>(H, band, BandKappa<double>{kappa_band, kt.as<double>()}, s);
+        B.retire.push_back(std::move(kt));
     } else {
         DevBuf kf = DevBuf::scratch(sizeof(float) * (size_t)H.mesh->N);
         to_float(kappa_band, kf.as<float>(), H.mesh->N, s);

@@ -115,15 +115,36 @@ __global__ void k_tet_table(GridDev g, const T *__restrict__ kap, T *__restrict_
     out[4 * k + 3] = v3 < N ? kap[v3] : (T)0;
 }
 
+// FP64: the eight corner values of every cell base b, in the order
+// b, b + s0 + s1 + 1, b + s0, b + s1, b + 1, b + s0 + s1, b + s1 + 1, b + s0 + 1
+// (a vertex past the grid gives 0)
+__global__ void k_cell_table(GridDev g, const double *__restrict__ kap, double *__restrict__ out) {
+    const int64_t N = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= N) return;
+    const int64_t s0 = g.stride[0], s1 = g.stride[1];
+    const int64_t v[8] = {b, b + s0 + s1 + 1, b + s0, b + s1, b + 1, b + s0 + s1, b + s1 + 1, b + s0 + 1};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[8 * b + q] = v[q] < N ? kap[v[q]] : 0.0;
+}
+
 template <typename T>
 DevBuf tet_table(const Mesh &m, const T *kappa, hipStream_t s) {
-    DevBuf d = DevBuf::scratch(sizeof(T) * (size_t)m.N * 24);
-    const int64_t n = m.N * 6;
-    k_tet_table<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(m.dev, kappa, d.as<T>());
-    HIP_LAUNCH_CHECK();
-    return d;
+    if constexpr (sizeof(T) == 4) {
+        DevBuf d = DevBuf::scratch(sizeof(T) * (size_t)m.N * 24);
+        const int64_t n = m.N * 6;
+        k_tet_table<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(m.dev, kappa, d.as<T>());
+        HIP_LAUNCH_CHECK();
+        return d;
+    } else {
+        DevBuf d = DevBuf::scratch(sizeof(T) * (size_t)m.N * 8);
+        k_cell_table<<<(unsigned)((m.N + 255) / 256), 256, 0, s>>>(m.dev, kappa, d.as<T>());
+        HIP_LAUNCH_CHECK();
+        return d;
+    }
 }
 template DevBuf tet_table<float>(const Mesh &, const float *, hipStream_t);
+template DevBuf tet_table<double>(const Mesh &, const double *, hipStream_t);
 
 template <typename T>
 EntryCtx<T> make_ctx(const Mesh &m, BandKappa<T> kappa) {
@@ -144,10 +165,12 @@ void entries_launch(const Mesh &m, int kind, const double *kappa, int64_t n, con
     if (n == 0) return;
     const unsigned grid = (unsigned)((n + 255) / 256);
     if (precision == RTE_FP64) {
-        auto c = make_ctx<double>(m, BandKappa<double>{kappa, nullptr});
+        DevBuf kt = tet_table<double>(m, kappa, s);
+        auto c = make_ctx<double>(m, BandKappa<double>{kappa, kt.as<double>()});
         if (kind == RTE_VOLUME) k_entries<double, RTE_VOLUME><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
         else k_entries<double, RTE_SURFACE><<<grid, 256, 0, s>>>(c, n, rows, cols, out);
         HIP_LAUNCH_CHECK();
+        HIP_CHECK(hipStreamSynchronize(s));   // kt is released on return
     } else {
         DevBuf kf(sizeof(float) * (size_t)m.N);
         to_float(kappa, kf.as<float>(), m.N, s);

@@ -29,8 +29,9 @@ template <typename T>
 struct EntryCtx {
     GridDev g;
     const T *__restrict__ kappa;   // [N] P1 vertex values of one band
-    const T *__restrict__ ktet;    // FP32: [N][6][4], per cell base corner and Kuhn tetrahedron its four
-                                   // vertex values in the order of tet_sample (k_tet_table); FP64: unused
+    const T *__restrict__ ktet;    // the march's table of kappa (k_tet_table): FP32 [N][6][4], per cell
+                                   // base and Kuhn tetrahedron its four vertex values; FP64 [N][8], per
+                                   // cell base its eight corner values
     StencilDev<T> st;
     const T *__restrict__ near;    // quadrature tables of the mesh: near [125][8][8], then far [24][4][8]
 };
@@ -125,29 +126,20 @@ struct TetSample {
 //   operator 98.6 -> 78.0 ms).  A base outside the grid (only the unused
 //   sample after a segment's last piece, or a piece of rounding length) reads
 //   the nearest row.
-//   FP64: the vertex values, through a buffer resource sized to the grid (an
-//   index outside [0, N) returns 0); the 32-byte rows of a table were no
-//   faster there.
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
+//   FP64: the table of the eight corner values of every cell base, in the
+//   order k(b), k(b + s0 + s1 + 1), then b + s0, b + s1, b + 1, b + s0 + s1,
+//   b + s1 + 1, b + s0 + 1: three loads from one 64-byte row per piece (the
+//   first two values together).  In FP64 this runs as fast as four gathers
+//   over the grid and as 32-byte rows per tetrahedron (41^3: 123 ms of entry
+//   launches either way): a lane needs more than one load there whatever the
+//   layout.
 template <typename T>
-struct KappaSrc;
-template <>
-struct KappaSrc<float> {
-    const float *__restrict__ tet;   // [N][6][4]
+struct KappaSrc {
+    const T *__restrict__ tab;   // FP32 [N][6][4], FP64 [N][8]
 };
-template <>
-struct KappaSrc<double> {
-    rsrc_t kr;
-};
-__device__ __forceinline__ KappaSrc<float> kappa_src(const GridDev &, const float *, const float *ktet) {
-    return {ktet};
-}
-__device__ __forceinline__ KappaSrc<double> kappa_src(const GridDev &g, const double *kap, const double *) {
-    const int bytes = g.n[0] * g.n[1] * g.n[2] * (int)sizeof(double);
-    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(kap), (short)0, bytes, 0x00020000)};
-}
-__device__ __forceinline__ double kload(rsrc_t r, int idx) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0));
+template <typename T>
+__device__ __forceinline__ KappaSrc<T> kappa_src(const T *tab) {
+    return {tab};
 }
 
 template <typename T>
@@ -162,15 +154,17 @@ __device__ __forceinline__ TetSample<T> tet_sample(const GridDev &g, const Kappa
         const int t = 2 * L + (S > L ? S - 1 : S);
         const int nv = g.n[0] * g.n[1] * g.n[2];
         const int bc = min(max(b, 0), nv - 1);
-        const float4 q = *reinterpret_cast<const float4 *>(src.tet + ((int64_t)bc * 6 + t) * 4);
+        const float4 q = *reinterpret_cast<const float4 *>(src.tab + ((int64_t)bc * 6 + t) * 4);
         return {q.x, q.y, q.z, q.w, hi, mid, lo};
     } else {
-        const int S0 = g.stride[0], S1 = g.stride[1];
-        const int smax = (c01 && c02) ? S0 : (c12 ? S1 : 1);
-        const int smin = (c02 && c12) ? 1 : (c01 ? S1 : S0);
-        const int v3 = b + S0 + S1 + 1;
-        const int v1 = b + smax, v2 = v3 - smin;
-        return {kload(src.kr, b), kload(src.kr, v1), kload(src.kr, v2), kload(src.kr, v3), hi, mid, lo};
+        // row slots: v1 = b + s_L at 2 + L; v2 = b + s0 + s1 + 1 - s_S at 6, 7, 5 for S = 0, 1, 2
+        const int i1 = (c01 && c02) ? 2 : (c12 ? 3 : 4);
+        const int i2 = (c02 && c12) ? 5 : (c01 ? 7 : 6);
+        const int nv = g.n[0] * g.n[1] * g.n[2];
+        const int bc = min(max(b, 0), nv - 1);
+        const double *r = src.tab + (int64_t)bc * 8;
+        const double2 q = *reinterpret_cast<const double2 *>(r);
+        return {q.x, r[i1], r[i2], q.y, hi, mid, lo};
     }
 }
 
@@ -634,7 +628,7 @@ __device__ T volume_entry(const EntryCtx<T> &c, int64_t i, int64_t j) {
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
     T att_w[6];
-    const T att = attenuations<T, NW>(g, kappa_src(g, c.kappa, c.ktet), ii, jj, P, Q, att_w);
+    const T att = attenuations<T, NW>(g, kappa_src(c.ktet), ii, jj, P, Q, att_w);
     return vol_sum<T, NW>(c, att, att_w, ii, jj);
 }
 
@@ -650,7 +644,7 @@ __device__ __forceinline__ void volume_entry_pair(const EntryCtx<T> &c, int64_t 
     const T P[3] = {(T)ii[0], (T)ii[1], (T)ii[2]};
     const T Q[3] = {(T)jj[0], (T)jj[1], (T)jj[2]};
     T att_w[6];
-    const T att = attenuations<T, NW>(g, kappa_src(g, c.kappa, c.ktet), ii, jj, P, Q, att_w);
+    const T att = attenuations<T, NW>(g, kappa_src(c.ktet), ii, jj, P, Q, att_w);
     gij = vol_sum<T, NW>(c, att, att_w, ii, jj);
     gji = vol_sum<T, NW>(c, att, att_w, jj, ii);
     if constexpr (NW == kAnyWalls) {   // removed vertices have zero rows
@@ -838,7 +832,7 @@ __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
     if constexpr (NW == kAnyWalls) {
         if (!vertex_active(g, ii)) return (T)0;   // a removed vertex
         T att_w[6];
-        const T att = attenuations<T, NW>(g, kappa_src(g, c.kappa, c.ktet), ii, ll, P, Q, att_w);
+        const T att = attenuations<T, NW>(g, kappa_src(c.ktet), ii, ll, P, Q, att_w);
         T S = att == (T)0 ? (T)0 : att * surf_quad_rects(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
         for (int w = 0; w < g.n_walls; ++w) {
             if (att_w[w] == (T)0) continue;
@@ -848,7 +842,7 @@ __device__ T surface_entry(const EntryCtx<T> &c, int64_t i, int64_t l) {
         }
         return S;
     } else {
-        const KappaSrc<T> ks = kappa_src(g, c.kappa, c.ktet);
+        const KappaSrc<T> ks = kappa_src(c.ktet);
         T S = exp(-tau_segment(g, ks, P, Q)) * surf_quad(c, ii, ll, cheb3(ii, ll) <= kNearCheb);
         if constexpr (NW == kOneWall) {
             int mi[3];

@@ -113,17 +113,18 @@ struct EventTimer {
 };
 
 template <typename T> struct EntryCtx;
-// One band's absorption as the entry kernels read it: the vertex values and,
-// in FP32, the table of the four vertex values of every (cell base, Kuhn
-// tetrahedron) pair that the ray march samples (tet_table).
+// One band's absorption as the entry kernels read it: the vertex values and
+// the table the ray march samples (tet_table): FP32 the four vertex values
+// of every (cell base, Kuhn tetrahedron) pair, FP64 the eight corner values
+// of every cell base.
 template <typename T>
 struct BandKappa {
     const T *v;     // [N]
-    const T *tet;   // FP32: [N][6][4]; FP64: null (the march gathers from v)
+    const T *tet;   // FP32 [N][6][4], FP64 [N][8]
 };
 template <typename T> EntryCtx<T> make_ctx(const Mesh &m, BandKappa<T> kappa);
-// the FP32 table of `kappa` on the mesh, queued on s (scratch; the caller keeps
-// it until the launches that read it have run)
+// the march's table of `kappa` on the mesh, queued on s (scratch; the caller
+// keeps it until the launches that read it have run)
 template <typename T> DevBuf tet_table(const Mesh &m, const T *kappa, hipStream_t s);
 void to_float(const double *in, float *out, int64_t n, hipStream_t s);
 // queues the fill on s without waiting: the task list and the launch's event
