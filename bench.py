@@ -58,7 +58,7 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on a plain 1 GiB copy (FETCH_SIZE reads half the bytes, WRITE_SIZE all):
 # the summary is profiles/cube41_grey_fp64_hmatrix_hbm_traffic.md.  Set to None
 # whenever those kernels change.
-ACA_ENTRY_TRAFFIC_BYTES = 372.1e6
+ACA_ENTRY_TRAFFIC_BYTES = 434.5e6
 FP64_PEAK_TFLOPS = 78.6
 # Algorithmic FP64 operations of one kernel entry, counted from the code of the
 # march and the quadrature with an FMA as 2 and a reciprocal, square root or
