@@ -24,11 +24,13 @@ __device__ __forceinline__ double planck(double nu, double T) {
 // safeguarded Newton iteration.  Every evaluation narrows the bracket
 // [lo, hi] by the sign of f (hi starts unbounded); a step that leaves it is
 // replaced by bisection, or by doubling while hi is unbounded.  Newton
-// converges quadratically from the previous sweep's temperature, so once a
-// Newton step is below 1e-13 relative the iterate after it is at the rounding
-// level and the iteration stops, whether or not that step lands strictly
-// inside the bracket (at the root the step rounds to nothing, and rejecting it
-// for a bisection would restart the search from the far end of the bracket).
+// converges quadratically from the previous sweep's temperature: once a
+// Newton step s is below 1e-8 relative, the iterate after it is within about
+// (nu / T) s^2 of the root, at the rounding level for the frequencies and
+// temperatures here, and the iteration stops, whether or not that step lands
+// strictly inside the bracket (near the root the step rounds to almost
+// nothing, and rejecting it for a bisection would restart the search from the
+// far end of the bracket).
 //
 // NB > 0: the loops over the bands are unrolled to NB iterations guarded by
 // b < nb (nb <= NB), so that a caller can keep the bands' c_b and J_b in
@@ -81,7 +83,7 @@ __device__ double solve_temperature(int nb, double Told, Band band) {
         if (fx == 0.0) break;
         if (fx > 0.0) lo = x; else hi = x;
         double xn = (d < 0.0) ? x - fx / d : -1.0;
-        if (xn > 0.0 && fabs(xn - x) <= 1e-13 * x) {   // the Newton step is at the rounding level
+        if (xn > 0.0 && fabs(xn - x) <= 1e-8 * x) {   // the next iterate is at the rounding level
             x = xn;
             break;
         }
