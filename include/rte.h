@@ -122,6 +122,9 @@ typedef struct {
     double aca_eps;      /* in (0,1) */
     int32_t precision;   /* rte_precision_t */
     int32_t recompress;  /* 0 or 1 */
+    int32_t aca_hits;    /* 0 or 1 (the default): the ACA of a block stops at the first rank step with
+                            |u_k| |v_k| <= aca_eps |S_k|_F; 2: only after two consecutive such steps
+                            (a somewhat higher rank; the worst blocks' true error about halves) */
 } rte_hmat_opts_t;
 
 /* ------------------------------------------------------------------ plan (host only)

@@ -39,6 +39,7 @@ struct AcaState {
     const AcaTask *task;
     int nb;
     int *k, *istar, *jstar, *status, *havepiv;
+    int *hits;                  // per block: consecutive rank steps that met the stopping test
     int64_t *ents;              // per block: entries evaluated (rows and columns)
     T *pivot, *normS2;
     unsigned *used;             // row bitmaps
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(256) void k_aca_init(AcaState<T> st) {
         st.jstar[b] = 0;
         st.status[b] = kActive;
         st.havepiv[b] = 0;
+        st.hits[b] = 0;
         st.normS2[b] = (T)0;
         st.pivot[b] = (T)0;
         st.ents[b] = 0;
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(256) void k_aca_dots(AcaState<T> st) {
 // Steps 4-5, second part: add the chunk partials in order, update ||S_k||,
 // test convergence and pick the next row.  One wavefront per pivoted block.
 template <typename T>
-__global__ __launch_bounds__(64) void k_aca_finish(AcaState<T> st, T eps) {
+__global__ __launch_bounds__(64) void k_aca_finish(AcaState<T> st, T eps, int need) {
     const int b = st.act2[blockIdx.x];
     if (st.status[b] != kActive || !st.havepiv[b]) return;
     const AcaTask tk = st.task[b];
@@ -465,7 +467,10 @@ __global__ __launch_bounds__(64) void k_aca_finish(AcaState<T> st, T eps) {
     (void)busv;
     const T s2 = st.normS2[b] + u2 * v2 + (T)2 * cross;
     st.normS2[b] = s2;
-    const bool stop = sqrt(u2 * v2) <= eps * sqrt(fabs(s2));
+    // the stopping test, met by `need` consecutive rank steps
+    const int hits = sqrt(u2 * v2) <= eps * sqrt(fabs(s2)) ? st.hits[b] + 1 : 0;
+    st.hits[b] = hits;
+    const bool stop = hits >= need;
     const int kn = k + 1;
     st.k[b] = kn;
     st.havepiv[b] = 0;
@@ -712,7 +717,7 @@ void aca_batch(HMat &H, BandStore &B, BandKappa<T> kap, const std::vector<AcaTas
     int64_t max_chunks = 0;
     for (auto &t : tasks) max_chunks += (t.m + t.n + kChunk - 1) / kChunk;
     DevBuf ents = scratch(sizeof(int64_t) * (size_t)nb);
-    DevBuf ints = scratch(sizeof(int) * (size_t)nb * 7), reals = scratch(sizeof(T) * (size_t)nb * 2),
+    DevBuf ints = scratch(sizeof(int) * (size_t)nb * 8), reals = scratch(sizeof(T) * (size_t)nb * 2),
            used = scratch(sizeof(unsigned) * (size_t)words), offs = scratch(sizeof(int64_t) * (size_t)(nb + 1) * 3),
            tot = scratch(sizeof(int64_t) * 5),
            part = scratch(sizeof(T) * (size_t)max_chunks * 2 * (size_t)(kmax + 1)),
@@ -734,6 +739,7 @@ void aca_batch(HMat &H, BandStore &B, BandKappa<T> kap, const std::vector<AcaTas
     st.havepiv = ip + 4 * nb;
     st.act = ip + 5 * nb;
     st.act2 = ip + 6 * nb;
+    st.hits = ip + 7 * nb;
     st.ents = ents.as<int64_t>();
     st.pivot = reals.as<T>();
     st.normS2 = reals.as<T>() + nb;
@@ -833,7 +839,7 @@ void aca_batch(HMat &H, BandStore &B, BandKappa<T> kap, const std::vector<AcaTas
             HIP_LAUNCH_CHECK();
             mark();
             k_aca_dots<T><<<(unsigned)nchunk, 256, 0, s>>>(st);
-            k_aca_finish<T><<<(unsigned)nact, 64, 0, s>>>(st, eps);
+            k_aca_finish<T><<<(unsigned)nact, 64, 0, s>>>(st, eps, std::max(1, H.opts.aca_hits));
             HIP_LAUNCH_CHECK();
             launches += 2;
         }

@@ -151,6 +151,7 @@ void validate_opts(const Mesh &m, const rte_hmat_opts_t &o) {
     RTE_REQUIRE(o.dense || (o.eta > 0 && std::isfinite(o.eta)), "opts.eta must be > 0");
     RTE_REQUIRE(o.dense || (o.aca_eps > 0 && o.aca_eps < 1), "opts.aca_eps must be in (0, 1)");
     RTE_REQUIRE(o.recompress == 0 || o.recompress == 1, "opts.recompress must be 0 or 1");
+    RTE_REQUIRE(o.aca_hits >= 0 && o.aca_hits <= 2, "opts.aca_hits must be 0, 1 or 2");
     RTE_REQUIRE(o.precision == RTE_FP64 || o.precision == RTE_FP32 || o.precision == RTE_MIXED_BF16,
                 "opts.precision must be RTE_FP64, RTE_FP32 or RTE_MIXED_BF16");
     if (o.kind == RTE_SURFACE) RTE_REQUIRE(m.L > 0, "surface matrix: the mesh has no emitting face");

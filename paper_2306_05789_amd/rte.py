@@ -34,7 +34,8 @@ class MeshDesc(C.Structure):
 
 class HmatOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dense", C.c_int32), ("leaf_size", C.c_int32),
-                ("eta", C.c_double), ("aca_eps", C.c_double), ("precision", C.c_int32), ("recompress", C.c_int32)]
+                ("eta", C.c_double), ("aca_eps", C.c_double), ("precision", C.c_int32), ("recompress", C.c_int32),
+                ("aca_hits", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -262,11 +263,12 @@ def rte_mesh_emitting_ids(mesh: Mesh):
 
 
 def hmat_opts(kind=RTE_VOLUME, dense=False, leaf_size=64, eta=2.0, aca_eps=1e-5, precision=RTE_FP64,
-              recompress=False) -> HmatOpts:
+              recompress=False, aca_hits=1) -> HmatOpts:
     o = HmatOpts()
     o.kind, o.dense, o.leaf_size = int(kind), int(bool(dense)), int(leaf_size)
     o.eta, o.aca_eps = float(eta), float(aca_eps)
     o.recompress = int(bool(recompress))
+    o.aca_hits = int(aca_hits)
     o.precision = PRECISIONS.get(precision, precision) if isinstance(precision, str) else int(precision)
     return o
 

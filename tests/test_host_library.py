@@ -122,6 +122,8 @@ def test_mesh_validation(kw, frag):
     (dict(aca_eps=0.0), "aca_eps"),
     (dict(precision=7), "precision"),
     (dict(kind=5), "kind"),
+    (dict(aca_hits=3), "aca_hits"),
+    (dict(recompress=True, aca_hits=-1), "aca_hits"),
 ])
 def test_plan_validation(kw, frag):
     mesh = rte.rte_mesh_create((4, 4, 4))
