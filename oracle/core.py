@@ -53,6 +53,7 @@ class _Problem(C.Structure):
         ("R", C.c_double * 6),
         ("emit_faces", C.c_uint32),
         ("hole_lo", C.c_int32 * 3), ("hole_hi", C.c_int32 * 3), ("hole_emit", C.c_uint32),
+        ("emission", C.c_uint32),
         ("near_cheb", C.c_int32),
         ("nq_tet_far", C.c_int32), ("nq_tet_near", C.c_int32),
         ("nq_tri_far", C.c_int32), ("nq_tri_near", C.c_int32),
@@ -147,7 +148,11 @@ class Problem:
     A non-convex domain (Remark rem1): `hole` = ((i0, j0, k0), (i1, j1, k1)), the
     grid cells [i0, i1) x [j0, j1) x [k0, k1) removed from the box (kappa =
     +infinity there); bit f of `hole_emit` makes the hole's face on side f % 2
-    of axis f // 2 emit into the domain."""
+    of axis f // 2 emit into the domain.
+
+    `emission` = 1 takes the cosine-weighted wall source of Section "Example"
+    (Q = [omega.n]_- Q0: kernel cos^2 / r^2 at the wall) instead of the
+    isotropic one (eq. SE1, the default 0)."""
     grid: Grid
     kappa: np.ndarray
     emit_faces: int = 1
@@ -160,6 +165,7 @@ class Problem:
     walls: list = None
     hole: tuple = None
     hole_emit: int = 0
+    emission: int = 0
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -186,6 +192,8 @@ class Problem:
         for w, (a, sd, r) in enumerate(self.walls):
             s.wall_axis[w], s.wall_side[w], s.R[w] = int(a), int(sd), float(r)
         s.emit_faces, s.near_cheb = self.emit_faces, self.near_cheb
+        assert self.emission in (0, 1)
+        s.emission = self.emission
         if self.hole is not None:
             lo, hi = self.hole
             n = self.grid.n

@@ -72,6 +72,8 @@ typedef struct {
     int32_t hole_lo[3];    /* non-convex domain: the box minus the cells [hole_lo, hole_hi), where */
     int32_t hole_hi[3];    /* kappa is +infinity (no hole when hole_lo[0] >= hole_hi[0]) */
     uint32_t hole_emit;    /* bit f: the hole's face on side f%2 of axis f/2 emits into the domain */
+    uint32_t emission;     /* 0: isotropic wall, kernel [(x-y).n]_+ / |x-y|^3 (eq. SE1); 1: the Example's
+                              Q = [omega.n]_- Q0, kernel ([(x-y).n]_+)^2 / |x-y|^4 */
     int32_t near_cheb;
     int32_t nq_tet_far, nq_tet_near, nq_tri_far, nq_tri_near;
     const double *tet_far_p, *tet_far_w;     /* [nq][4], [nq] */
@@ -459,7 +461,11 @@ static int emitting_square(const og_problem_t *P, const og_rect_t *R, const int 
  * emitting squares of w~^l(y) [(x-y).n_R]_+ / |x-y|^3 (a rectangle seen from
  * behind adds nothing); on the diagonal, when the point lies in the plane of
  * R, the planar angle theta of R's emitting squares at the point over 4pi
- * (pi/2 per square). */
+ * (pi/2 per square).  With the Example's cosine-weighted source (section
+ * "Example": Q = [omega.n]_- Q0) the integrand is w~^l(y) ([(x-y).n_R]_+)^2 /
+ * |x-y|^4 and the in-plane limit half as large: a quarter plane gives
+ * int_0^inf d^2 rho / (d^2 + rho^2)^2 drho * pi/2 = pi/4 whatever d, so pi/4
+ * per square over 4pi. */
 static double surface_quad(const og_problem_t *P, const double x[3], const int xidx[3],
                            const int l[3], int near)
 {
@@ -480,7 +486,7 @@ static double surface_quad(const og_problem_t *P, const double x[3], const int x
             if (xidx[0] == l[0] && xidx[1] == l[1] && xidx[2] == l[2])
                 for (int o = 0; o < 4; ++o) {
                     int sq[2] = {l[b] - (o & 1), l[c] - ((o >> 1) & 1)};
-                    if (emitting_square(P, R, sq)) sum += 0.5 * OG_PI / (4.0 * OG_PI);
+                    if (emitting_square(P, R, sq)) sum += (P->emission ? 0.25 : 0.5) * OG_PI / (4.0 * OG_PI);
                 }
             continue;
         }
@@ -521,7 +527,8 @@ static double surface_quad(const og_problem_t *P, const double x[3], const int x
                         for (int k = 0; k < 3; ++k) y[k] += bb[m] * pos[m][k];
                     double r2 = 0.0;
                     for (int k = 0; k < 3; ++k) r2 += (x[k] - y[k]) * (x[k] - y[k]);
-                    sum += area * bw[qi] * bb[loc] * d / (r2 * sqrt(r2)) / (4.0 * OG_PI);
+                    const double k = P->emission ? d * d / (r2 * r2) : d / (r2 * sqrt(r2));
+                    sum += area * bw[qi] * bb[loc] * k / (4.0 * OG_PI);
                 }
             }
         }

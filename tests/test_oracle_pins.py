@@ -581,6 +581,45 @@ def test_surface_source_kappa0_equals_solid_angle():
     assert abs(P.surface_block([wall], P.emitting).sum() - 0.5) < 1e-15
 
 
+def _rect_view_factor(x, y, z):
+    """View factor from a differential area parallel to the plane X = 0, at (x, y, z),
+    x > 0, to [0,1]^2 in that plane: sum over the four corner sub-rectangles of
+    (1/2 pi) [A/sqrt(1+A^2) atan(B/sqrt(1+A^2)) + B/sqrt(1+B^2) atan(A/sqrt(1+B^2))],
+    A = a/d, B = b/d, the textbook formula for a parallel rectangle."""
+    d = x
+    tot = 0.0
+    for a in (y, 1 - y):
+        for b in (z, 1 - z):
+            A, B = a / d, b / d
+            tot += (A / np.sqrt(1 + A * A) * np.arctan(B / np.sqrt(1 + A * A))
+                    + B / np.sqrt(1 + B * B) * np.arctan(A / np.sqrt(1 + B * B))) / (2 * np.pi)
+    return tot
+
+
+def test_cosine_weighted_source_kappa0_equals_view_factor():
+    """kappa -> 0 with the Example's source Q = [omega.n]_- Q0: S^E = (Q0 / 4 pi) int
+    cos^2 / r^2 = Q0 F(x) / 4, F the view factor of the emitting face from a
+    parallel differential area at x (the isotropic law gives the solid angle instead,
+    which is not proportional to it); a vertex inside the face gets a quarter."""
+    errs = []
+    for n in (5, 9, 17):
+        P = _grid_problem((n, n, n), kappa=np.zeros(n ** 3), emit_faces=1, emission=1)
+        g = P.grid
+        pts = [(n // 2, n // 2, n // 2), (n - 1, 0, n // 4), (n // 4, n // 2, n - 1)]
+        ids = g.vid(np.array(pts))
+        SE = P.surface_block(ids, P.emitting).sum(axis=1)
+        ref = np.array([_rect_view_factor(*g.positions()[i]) / 4 for i in ids])
+        errs.append(np.max(np.abs(SE - ref) / ref))
+    assert errs[2] < errs[0] and errs[2] < 1e-5, errs
+    P = _grid_problem((5, 5, 5), kappa=np.zeros(125), emit_faces=1, emission=1)
+    wall = int(P.grid.vid([0, 2, 2]))
+    assert abs(P.surface_block([wall], P.emitting).sum() - 0.25) < 1e-15
+    # the volume operator does not depend on the wall law
+    Q = _grid_problem((5, 5, 5), kappa=np.full(125, 0.7), emit_faces=1, emission=1)
+    Q0 = _grid_problem((5, 5, 5), kappa=np.full(125, 0.7), emit_faces=1)
+    assert np.array_equal(Q.dense_G(), Q0.dense_G())
+
+
 # ---------------------------------------------------------------- Planck, bands, temperature
 
 def test_band_sum_of_planck_recovers_stefan_boltzmann():
