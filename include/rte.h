@@ -96,6 +96,10 @@ typedef struct {
     int32_t hole_lo[3];
     int32_t hole_hi[3];
     uint32_t hole_emit;
+    uint32_t emission;   /* 0: isotropic black wall, Q = B_nu(T_wall) and the kernel [(x-y).n]_+ / |x-y|^3
+                            of eq. SE1 (the default); 1: the cosine-weighted source of Section "Example",
+                            Q = [omega.n]_- Q0, kernel ([(x-y).n]_+)^2 / |x-y|^4 (in the face's plane on the
+                            diagonal theta_F / (8 pi)); the same for every emitting face */
 } rte_mesh_desc_t;
 
 rte_status_t rte_mesh_create(const rte_mesh_desc_t *desc, rte_mesh_t *out);

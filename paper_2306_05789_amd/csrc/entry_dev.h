@@ -654,7 +654,16 @@ __device__ __forceinline__ void volume_entry_pair(const EntryCtx<T> &c, int64_t 
 }
 
 // ---------------------------------------------------------------- surface quadrature
-template <typename T, int NQ, int t>
+// The wall kernel without its normal-distance factor: 1 / r^3 for the
+// isotropic source (eq. SE1, times |d|), 1 / r^4 for the cosine-weighted one
+// of Section "Example" (C2, times d^2).
+template <typename T, bool C2>
+__device__ __forceinline__ T wall_kernel(T r2) {
+    if constexpr (C2) return recip(r2 * r2);
+    else return recip(r2 * sqrt(r2));
+}
+
+template <typename T, int NQ, bool C2, int t>
 __device__ __forceinline__ void tri_term(const T *__restrict__ tab, const int lb, const int lc, const int nb,
                                          const int nc, const T db, const T dc, const T da2, const T hb2,
                                          const T hc2, T &acc) {
@@ -667,16 +676,16 @@ __device__ __forceinline__ void tri_term(const T *__restrict__ tab, const int lb
     for (int q = 0; q < NQ; ++q) {
         const T eb = db - e[4 * q + 0], ec = dc - e[4 * q + 1];
         const T r2 = da2 + hb2 * eb * eb + hc2 * ec * ec;
-        s += e[4 * q + 2] * recip(r2 * sqrt(r2));
+        s += e[4 * q + 2] * wall_kernel<T, C2>(r2);
     }
     acc += s;
 }
 
-template <typename T, int NQ, int... ts>
+template <typename T, int NQ, bool C2, int... ts>
 __device__ __forceinline__ T tri_all(std::integer_sequence<int, ts...>, const T *__restrict__ tab, int lb, int lc,
                                      int nb, int nc, T db, T dc, T da2, T hb2, T hc2) {
     T acc = (T)0;
-    (tri_term<T, NQ, ts>(tab, lb, lc, nb, nc, db, dc, da2, hb2, hc2, acc), ...);
+    (tri_term<T, NQ, C2, ts>(tab, lb, lc, nb, nc, db, dc, da2, hb2, hc2, acc), ...);
     return acc;
 }
 
@@ -695,7 +704,8 @@ __device__ T surf_quad(const EntryCtx<T> &c, const int xi[3], const int ll[3], b
         const int b = (a == 0) ? 1 : 0;
         const int cc = (a == 2) ? 1 : 2;
         if (xi[a] == pf) {
-            // coplanar limit: theta_F(x)/(4 pi) on the diagonal
+            // coplanar limit: theta_F(x)/(4 pi) on the diagonal (isotropic), half
+            // that for the cosine-weighted source
             if (xi[0] == ll[0] && xi[1] == ll[1] && xi[2] == ll[2]) {
                 T frac = (T)1;
                 const int axes[2] = {b, cc};
@@ -705,7 +715,7 @@ __device__ T surf_quad(const EntryCtx<T> &c, const int xi[3], const int ll[3], b
                     if (p < 0 || p > g.n[axes[k]] - 1) frac = (T)0;
                     else if (p == 0 || p == g.n[axes[k]] - 1) frac *= (T)0.5;
                 }
-                acc += (T)0.5 * frac;
+                acc += (g.emission ? (T)0.25 : (T)0.5) * frac;
             }
             continue;
         }
@@ -713,14 +723,18 @@ __device__ T surf_quad(const EntryCtx<T> &c, const int xi[3], const int ll[3], b
         const T da2 = da * da;
         const T hb2 = (T)(g.h[b] * g.h[b]), hc2 = (T)(g.h[cc] * g.h[cc]);
         const T db = (T)(xi[b] - ll[b]), dc = (T)(xi[cc] - ll[cc]);
+        constexpr auto seq = std::make_integer_sequence<int, kTris>{};
         T s;
-        if (near)
-            s = tri_all<T, 7>(std::make_integer_sequence<int, kTris>{}, c.st.tri_near, ll[b], ll[cc], g.n[b],
-                              g.n[cc], db, dc, da2, hb2, hc2);
-        else
-            s = tri_all<T, 3>(std::make_integer_sequence<int, kTris>{}, c.st.tri_far, ll[b], ll[cc], g.n[b],
-                              g.n[cc], db, dc, da2, hb2, hc2);
-        acc += s * fabs(da) * (T)g.area_scale[a];
+        if (g.emission) {
+            s = near ? tri_all<T, 7, true>(seq, c.st.tri_near, ll[b], ll[cc], g.n[b], g.n[cc], db, dc, da2, hb2, hc2)
+                     : tri_all<T, 3, true>(seq, c.st.tri_far, ll[b], ll[cc], g.n[b], g.n[cc], db, dc, da2, hb2, hc2);
+            s *= da2;
+        } else {
+            s = near ? tri_all<T, 7, false>(seq, c.st.tri_near, ll[b], ll[cc], g.n[b], g.n[cc], db, dc, da2, hb2, hc2)
+                     : tri_all<T, 3, false>(seq, c.st.tri_far, ll[b], ll[cc], g.n[b], g.n[cc], db, dc, da2, hb2, hc2);
+            s *= fabs(da);
+        }
+        acc += s * (T)g.area_scale[a];
     }
     return acc;
 }
@@ -732,7 +746,7 @@ __device__ T surf_quad(const EntryCtx<T> &c, const int xi[3], const int ll[3], b
 // rectangle seen from behind adds nothing; on the diagonal in the rectangle's
 // plane the planar angle of the emitting squares, pi/2 each, over 4 pi.  For
 // the box faces of a mesh without a hole this is surf_quad, term for term.
-template <typename T, int NQ, int t>
+template <typename T, int NQ, bool C2, int t>
 __device__ __forceinline__ void tri_term_m(const T *__restrict__ tab, int sqmask, const T db, const T dc, const T da2,
                                            const T hb2, const T hc2, T &acc) {
     constexpr TriInfo ti = kStar.tri[t];
@@ -743,16 +757,16 @@ __device__ __forceinline__ void tri_term_m(const T *__restrict__ tab, int sqmask
     for (int q = 0; q < NQ; ++q) {
         const T eb = db - e[4 * q + 0], ec = dc - e[4 * q + 1];
         const T r2 = da2 + hb2 * eb * eb + hc2 * ec * ec;
-        s += e[4 * q + 2] * recip(r2 * sqrt(r2));
+        s += e[4 * q + 2] * wall_kernel<T, C2>(r2);
     }
     acc += s;
 }
 
-template <typename T, int NQ, int... ts>
+template <typename T, int NQ, bool C2, int... ts>
 __device__ __forceinline__ T tri_all_m(std::integer_sequence<int, ts...>, const T *__restrict__ tab, int sqmask, T db,
                                        T dc, T da2, T hb2, T hc2) {
     T acc = (T)0;
-    (tri_term_m<T, NQ, ts>(tab, sqmask, db, dc, da2, hb2, hc2, acc), ...);
+    (tri_term_m<T, NQ, C2, ts>(tab, sqmask, db, dc, da2, hb2, hc2, acc), ...);
     return acc;
 }
 
@@ -796,7 +810,9 @@ __device__ T surf_quad_rects(const EntryCtx<T> &c, const int xi[3], const int ll
         }
         if (xi[a] == pf) {
             // coplanar limit: theta(x)/(4 pi) on the diagonal, pi/2 per emitting square
-            if (xi[0] == ll[0] && xi[1] == ll[1] && xi[2] == ll[2]) acc += (T)0.125 * (T)__builtin_popcount(sqmask);
+            // (isotropic), half that for the cosine-weighted source
+            if (xi[0] == ll[0] && xi[1] == ll[1] && xi[2] == ll[2])
+                acc += (g.emission ? (T)0.0625 : (T)0.125) * (T)__builtin_popcount(sqmask);
             continue;
         }
         const int d = (xi[a] - pf) * sign;
@@ -811,12 +827,18 @@ __device__ T surf_quad_rects(const EntryCtx<T> &c, const int xi[3], const int ll
         const T da = (T)d * ha;
         const T da2 = da * da;
         const T db = (T)(xi[b] - ll[b]), dc = (T)(xi[cc] - ll[cc]);
+        constexpr auto seq = std::make_integer_sequence<int, kTris>{};
         T s;
-        if (near)
-            s = tri_all_m<T, 7>(std::make_integer_sequence<int, kTris>{}, c.st.tri_near, sqmask, db, dc, da2, hb2, hc2);
-        else
-            s = tri_all_m<T, 3>(std::make_integer_sequence<int, kTris>{}, c.st.tri_far, sqmask, db, dc, da2, hb2, hc2);
-        acc += s * da * as;
+        if (g.emission) {
+            s = near ? tri_all_m<T, 7, true>(seq, c.st.tri_near, sqmask, db, dc, da2, hb2, hc2)
+                     : tri_all_m<T, 3, true>(seq, c.st.tri_far, sqmask, db, dc, da2, hb2, hc2);
+            s *= da2;
+        } else {
+            s = near ? tri_all_m<T, 7, false>(seq, c.st.tri_near, sqmask, db, dc, da2, hb2, hc2)
+                     : tri_all_m<T, 3, false>(seq, c.st.tri_far, sqmask, db, dc, da2, hb2, hc2);
+            s *= da;
+        }
+        acc += s * as;
     }
     return acc;
 }

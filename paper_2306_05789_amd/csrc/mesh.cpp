@@ -299,6 +299,7 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
         }
     for (auto &w : walls)
         RTE_REQUIRE(!((d.emit_faces >> w.first) & 1u), "mesh: a reflective face cannot also emit");
+    RTE_REQUIRE(d.emission <= 1u, "mesh: emission must be 0 (isotropic) or 1 (cosine-weighted)");
     // the removed box of cells (all-zero fields: none)
     const bool hole = d.hole_lo[0] < d.hole_hi[0] || d.hole_lo[1] < d.hole_hi[1] || d.hole_lo[2] < d.hole_hi[2];
     if (hole) {
@@ -388,6 +389,7 @@ void mesh_init(Mesh &M, const rte_mesh_desc_t &d) {
         if (hole && d.hole_hi[a] == d.n[a] - 1) g.hole_open |= 1u << (2 * a + 1);
     }
     g.hole_emit = hole ? d.hole_emit : 0u;
+    g.emission = d.emission;
     const double four_pi = 4.0 * M_PI;
     g.vol_scale = M.h[0] * M.h[1] * M.h[2] / 6.0 / four_pi;
     g.area_scale[0] = 0.5 * M.h[1] * M.h[2] / four_pi;

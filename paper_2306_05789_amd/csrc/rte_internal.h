@@ -66,6 +66,7 @@ struct GridDev {
     int hole_lo[3], hole_hi[3];
     unsigned hole_open;     // bit 2a (2a+1): the hole reaches the box face at the low (high) end of axis a
     unsigned hole_emit;     // bit f: the hole's face on side f%2 of axis f/2 emits
+    unsigned emission;      // 0: isotropic wall source (eq. SE1); 1: cosine-weighted (Section "Example")
     double vol_scale;       // |tet| / (4 pi)
     double area_scale[3];   // |triangle| / (4 pi) for faces normal to axis a
 };

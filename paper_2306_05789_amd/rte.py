@@ -29,7 +29,8 @@ class MeshDesc(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("reflect_axis", C.c_int32), ("reflect_side", C.c_int32), ("R", C.c_double),
                 ("emit_faces", C.c_uint32), ("reflect_faces", C.c_uint32), ("R_faces", C.c_double * 6),
-                ("hole_lo", C.c_int32 * 3), ("hole_hi", C.c_int32 * 3), ("hole_emit", C.c_uint32)]
+                ("hole_lo", C.c_int32 * 3), ("hole_hi", C.c_int32 * 3), ("hole_emit", C.c_uint32),
+                ("emission", C.c_uint32)]
 
 
 class HmatOpts(C.Structure):
@@ -224,10 +225,11 @@ class Mesh:
 
 
 def mesh_desc(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), reflect_axis=-1, reflect_side=0, R=0.0,
-              emit_faces=1, walls=None, hole=None, hole_emit=0) -> MeshDesc:
+              emit_faces=1, walls=None, hole=None, hole_emit=0, emission=0) -> MeshDesc:
     """walls: further reflective faces as (axis, side, R) triples.  hole: the removed
     box of cells ((i0, j0, k0), (i1, j1, k1)), cells [i0, i1) x [j0, j1) x [k0, k1);
-    hole_emit: its emitting faces (bit 2a + side)."""
+    hole_emit: its emitting faces (bit 2a + side).  emission: 0 for the isotropic
+    wall source, 1 for the cosine-weighted one."""
     d = MeshDesc()
     d.n[:] = [int(v) for v in n]
     d.lo[:] = [float(v) for v in lo]
@@ -242,12 +244,13 @@ def mesh_desc(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), reflect_axis=-1, reflec
         d.hole_lo[:] = [int(v) for v in hole[0]]
         d.hole_hi[:] = [int(v) for v in hole[1]]
     d.hole_emit = int(hole_emit)
+    d.emission = int(emission)
     return d
 
 
 def rte_mesh_create(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), reflect_axis=-1, reflect_side=0, R=0.0,
-                    emit_faces=1, walls=None, hole=None, hole_emit=0) -> Mesh:
-    d = mesh_desc(n, lo, hi, reflect_axis, reflect_side, R, emit_faces, walls, hole, hole_emit)
+                    emit_faces=1, walls=None, hole=None, hole_emit=0, emission=0) -> Mesh:
+    d = mesh_desc(n, lo, hi, reflect_axis, reflect_side, R, emit_faces, walls, hole, hole_emit, emission)
     h = C.c_void_p()
     _check(load().rte_mesh_create(C.byref(d), C.byref(h)))
     N, L = C.c_int64(), C.c_int64()

@@ -108,6 +108,7 @@ def test_emitting_ids_with_a_hole_match_oracle(emit, hole, hole_emit):
     (dict(n=(4, 4, 4), reflect_axis=2, R=1.5), "R must"),
     (dict(n=(4, 4, 4), reflect_axis=0, reflect_side=0, R=0.5, emit_faces=1), "cannot also emit"),
     (dict(n=(4, 4, 4), emit_faces=64), "6 bits"),
+    (dict(n=(4, 4, 4), emission=2), "emission"),
     (dict(n=(1024, 1024, 256)), "2^28 vertices"),
 ])
 def test_mesh_validation(kw, frag):
