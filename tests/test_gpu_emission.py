@@ -1,8 +1,9 @@
 """GPU: the cosine-weighted wall source of Section "Example" (Q = [omega.n]_- Q0,
 kernel ([(x-y).n]_+)^2 / |x-y|^4, half the isotropic in-plane limit) against
 the FP64 oracle with the same option: surface entries one by one on the
-single-wall, one-wall, several-wall and hole code paths, and a dense solve
-element by element."""
+single-wall, one-wall, several-wall and hole code paths, a dense solve
+element by element, and compressed solves against the oracle's fixed point
+of the read-back operators."""
 import numpy as np
 import pytest
 import torch
@@ -110,3 +111,29 @@ def test_cosine_weighted_dense_solve_matches_oracle():
     Jg, Tg = J.cpu().numpy()[0, 0], T.cpu().numpy()[0]
     assert np.max(np.abs(Jg - ref.J[0])) / np.max(ref.J[0]) < 1e-10
     assert np.max(np.abs(Tg - ref.T) / np.maximum(ref.T, 1e-300)) < 1e-10
+
+
+@pytest.mark.parametrize("precision,gpu_tol,tol", [(rte.RTE_FP64, 1e-14, 1e-10), (rte.RTE_MIXED_BF16, 1e-9, 1e-6)])
+def test_cosine_weighted_hmatrix_solve_matches_oracle(precision, gpu_tol, tol):
+    """Compressed operators with the cosine-weighted source: the stored surface
+    operator against the oracle's dense one within the ACA bound, and the solve
+    against the oracle's fixed point of the read-back operators."""
+    import readback
+    g = Grid((13, 13, 13))
+    kap = inputs.smooth_kappa(g.positions())
+    P = Problem(g, kap, emit_faces=1 | 8, emission=1)
+    mesh = rte.rte_mesh_create(g.n, emit_faces=1 | 8, emission=1)
+    kt = torch.tensor(kap[None, :], device=DEV)
+    opts = lambda kind: rte.hmat_opts(kind=kind, leaf_size=32, eta=2.0, aca_eps=1e-5, precision=precision)
+    oG, oS = opts(rte.RTE_VOLUME), opts(rte.RTE_SURFACE)
+    Gh, Sh = rte.rte_hmat_assemble(mesh, kt, oG), rte.rte_hmat_assemble(mesh, kt, oS)
+    HG, HS = readback.gpu_operator(mesh, Gh, oG), readback.gpu_operator(mesh, Sh, oS)
+    x = np.random.default_rng(7).uniform(0.5, 2.0, mesh.L)
+    Sd = P.dense_S()
+    assert np.linalg.norm(HS @ x - Sd @ x) / np.linalg.norm(Sd @ x) < 1e-4
+    ref = osolve.fixed_point([HG], (HS @ np.full(mesh.L, osolve.SIGMA))[None], grey=True, tol=1e-14)
+    T = torch.empty((1, mesh.N), device=DEV, dtype=torch.float64)
+    st = rte.rte_fixed_point_solve(mesh, Gh, Sh, torch.ones((1, mesh.L), device=DEV, dtype=torch.float64), T,
+                                   grey=True, tol=gpu_tol, max_iter=500, precision=precision)
+    assert st["converged"]
+    assert np.max(np.abs(T.cpu().numpy()[0] - ref.T) / ref.T) < tol
