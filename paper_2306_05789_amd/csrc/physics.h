@@ -55,8 +55,10 @@ __device__ double solve_temperature(int nb, double Told, Band band) {
         f0 += c * j;
     });
     if (!(f0 > 0.0)) return 0.0;
-    // f and f' at t > 0: B = nu^3 r, dB/dT = B (1 + r) x / t with x = nu / t and
-    // r = 1 / (e^x - 1); one division per band
+    // f = f0 - sum c_b B_b(t) and f' at t > 0: B = nu^3 r, dB/dT = B (1 + r) x / t
+    // with x = nu / t and r = 1 / (e^x - 1); one division per band.  The J_b enter
+    // through f0 alone, so a caller holding the bands in registers keeps only c_b
+    // live through the iteration.
     auto f = [&](double t, double &df) {
         double s = 0.0, d = 0.0;
         const double it = 1.0 / t;
@@ -70,11 +72,11 @@ __device__ double solve_temperature(int nb, double Told, Band band) {
                 B = nu * nu * nu * r;
                 dB = B * (1.0 + r) * (x * it);
             }
-            s += c * (j - B);
+            s += c * B;
             d -= c * dB;
         });
         df = d;
-        return s;
+        return f0 - s;
     };
     double lo = 0.0, hi = INFINITY, d;
     double x = Told > 0.0 ? Told : 1.0;
