@@ -34,9 +34,10 @@ class Server:
             rte._lib.rte_server_destroy(self.handle)
             self.handle = None
 
-    def add_mesh(self, n, kappa, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), emit_faces=63) -> int:
-        """kappa: float64 device [N] base field, natural order."""
-        md = rte.mesh_desc(n, lo, hi, emit_faces=emit_faces)
+    def add_mesh(self, n, kappa, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), emit_faces=63, emission=0) -> int:
+        """kappa: float64 device [N] base field, natural order.  emission: 0 for the
+        isotropic wall source, 1 for the cosine-weighted one."""
+        md = rte.mesh_desc(n, lo, hi, emit_faces=emit_faces, emission=emission)
         mid = C.c_int32()
         rte._check(rte.load().rte_server_add_mesh(self.handle, C.byref(md), rte._ptr(kappa), C.byref(mid)))
         return mid.value

@@ -213,3 +213,31 @@ def test_invalid_requests_are_rejected():
         srv.submit(ids[0], [0], [1.0], -tw)                 # wall temperature <= 0
     with pytest.raises(rte.RteError):
         srv.poll(12345)
+
+
+def test_served_cosine_weighted_mesh_matches_single_solve():
+    """A mesh with the cosine-weighted wall source served like any other: the
+    request equals the library's single solve on the snapped levels' operators
+    of the same mesh, and differs from the isotropic source's result."""
+    n = 9
+    srv = Server(NU, leaf_size=LEAF, precision=rte.RTE_MIXED_BF16)
+    base = torch.tensor(base_kappa(n), device=DEV)
+    ids = [srv.add_mesh((n, n, n), base, emission=1), srv.add_mesh((n, n, n), base)]
+    bands = np.array([0, 2])
+    Tw = np.random.default_rng(11).uniform(0.5, 2.0, inputs.n_emitting((n, n, n), inputs.ALL_FACES))
+    reqs = [inputs.Request(0.0, 0, bands, 1.3, Tw), inputs.Request(0.0, 1, bands, 1.3, Tw)]
+    (T_c2, T_iso), (info, _) = serve_all(srv, ids, [n, n], reqs, tol=1e-8)
+    assert info["converged"]
+    mult = 10.0 ** (np.asarray(info["levels"]) / 8.0)
+    kt = torch.tensor(mult[:, None] * base_kappa(n)[None, :], device=DEV)
+    mesh = rte.rte_mesh_create((n, n, n), emit_faces=inputs.ALL_FACES, emission=1)
+    opts = lambda kind: rte.hmat_opts(kind=kind, leaf_size=LEAF, precision=rte.RTE_MIXED_BF16)
+    G, S = rte.rte_hmat_assemble(mesh, kt, opts(rte.RTE_VOLUME)), rte.rte_hmat_assemble(mesh, kt, opts(rte.RTE_SURFACE))
+    T = torch.empty((1, mesh.N), device=DEV, dtype=torch.float64)
+    st = rte.rte_fixed_point_solve(mesh, G, S, torch.tensor(Tw[None, :], device=DEV), T, grey=False, nu=NU[bands],
+                                   w=catalogue_weights(NU)[bands], tol=1e-8, max_iter=2000,
+                                   precision=rte.RTE_MIXED_BF16)
+    assert st["converged"]
+    T1 = T.cpu().numpy()[0]
+    assert np.max(np.abs(T_c2 - T1) / T1) < 1e-7
+    assert np.max(np.abs(T_c2 - T_iso) / T_iso) > 1e-3
