@@ -129,7 +129,8 @@ def _doubled(P: Problem, axis: int = 0):
         if (P.emit_faces >> f) & 1:
             assert f // 2 != axis, "the doubled check keeps emitting faces off the wall axis"
             emit |= 1 << f
-    Pd = Problem(gd, P.kappa[g.vid(src)], emit_faces=emit, flip_axis=axis, flip_cells=na - 1)
+    Pd = Problem(gd, P.kappa[g.vid(src)], emit_faces=emit, flip_axis=axis, flip_cells=na - 1,
+                 emission=P.emission)
     return Pd
 
 
@@ -148,15 +149,16 @@ def test_mirror_tau_equals_straight_tau_in_doubled_domain():
     assert np.max(np.abs(Pd.kappa_at(ym) - P.kappa_at(y))) < 1e-14
 
 
-@pytest.mark.parametrize("axis", [0, 2])
-def test_reflective_operator_equals_doubled_domain_for_R1(axis):
+@pytest.mark.parametrize("axis,emission", [(0, 0), (2, 0), (0, 1), (2, 1)])
+def test_reflective_operator_equals_doubled_domain_for_R1(axis, emission):
     """Section "Results" (Test-1): a planar reflection is the same as extending the
     domain by its mirror image.  With R = 1 the reflective G and S equal the
-    doubled-domain matrices folded onto the original vertices, entry by entry."""
+    doubled-domain matrices folded onto the original vertices, entry by entry;
+    for the isotropic and the cosine-weighted wall source alike."""
     rng = np.random.default_rng(5)
     emit = 4 | 32 if axis == 0 else 1 | 8
     P = _grid_problem((5, 4, 4), kappa=lambda X: rng.uniform(0.2, 1.5, len(X)),
-                      wall_axis=axis, wall_side=0, R=1.0, emit_faces=emit)
+                      wall_axis=axis, wall_side=0, R=1.0, emit_faces=emit, emission=emission)
     Pd = _doubled(P, axis)
     g, gd = P.grid, Pd.grid
     na = g.n[axis]
@@ -181,7 +183,7 @@ def test_reflective_operator_equals_doubled_domain_for_R1(axis):
     foldS = Sd[:, :len(em)] + np.where(eidx[:, axis] > 0, 1.0, 0.0)[None, :] * Sd[:, len(em):]
     assert np.max(np.abs(SR - foldS)) < 1e-13 * np.max(np.abs(SR))
     # R = 0 is a different operator (the check has teeth)
-    P0 = _grid_problem((5, 4, 4), kappa=P.kappa, emit_faces=emit)
+    P0 = _grid_problem((5, 4, 4), kappa=P.kappa, emit_faces=emit, emission=emission)
     assert np.max(np.abs(P0.dense_G() - fold)) > 1e-3 * np.max(np.abs(GR))
 
 
